@@ -1,0 +1,160 @@
+/*
+ * fe_abi.h - C ABI of the MI355X (gfx950) finite-element library for the
+ * exact-gradient step of minimum-compliance topology optimisation
+ * (Zhang et al., "Speeding up Computational Morphogenesis with Online Neural
+ * Synthetic Gradients": problem (4), gradient (5), Sec. III-D).
+ *
+ * The step: given a physical density rho = P z on a structured nx*ny*nz
+ * grid of cubic 8-node bricks, solve K(rho) u = f (linear elasticity, SIMP
+ * modulus E(rho) = Emin + rho^p (E0 - Emin)), then return the compliance
+ * f^T u, its gradient dc/drho (Eq. 5), the filter P and its transpose (the
+ * volume gradient P^T v of Sec. III-D) and the optimality-criteria update.
+ *
+ * Layouts (all "canonical"):
+ *   element e = i + nx*(j + ny*k),  node n = i + (nx+1)*(j + (ny+1)*k),
+ *   dof 3*n + c with c = x, y, z.
+ *
+ * Memory: every array argument is a DEVICE pointer owned by the caller, in
+ * float64, unless stated otherwise.  The library owns only the opaque handle;
+ * all of its device memory lives in the caller's workspace (no allocation on
+ * any call after fe_setup, and none inside fe_setup either).
+ *
+ * Streams: every call is ordered on the stream given to fe_setup.  Calls that
+ * return host scalars (fe_solve) synchronise that stream before returning;
+ * the others are asynchronous and may write device scalars.  One handle must
+ * not be used from two host threads at once.
+ *
+ * Errors: nothing throws across the ABI.  Every entry point returns an
+ * fe_status; on failure fe_last_error() gives a message (thread-local).
+ */
+#ifndef FE_ABI_H
+#define FE_ABI_H
+
+#include <stddef.h>
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+#ifndef FE_API
+#define FE_API __attribute__((visibility("default")))
+#endif
+
+typedef enum {
+  FE_OK = 0,
+  FE_EINVAL = -1,      /* bad argument: dims < 1, nu not in (-1, 0.5), Emin not in (0, E0),
+                          penal < 1, filter_r <= 0, NULL required pointer, ... */
+  FE_ENOMEM = -2,      /* workspace smaller than fe_workspace_size(cfg) */
+  FE_EDEVICE = -3,     /* a HIP runtime call failed */
+  FE_ENOTCONV = -4,    /* iteration limit reached; u holds the last iterate */
+  FE_EBREAKDOWN = -5   /* p^T K p <= 0 or a non-finite value inside CG */
+} fe_status;
+
+enum { FE_PREC_FP64 = 0,     /* vectors, K*u and dots in float64 */
+       FE_PREC_FP32_IR = 1,  /* float32 CG inside float64 iterative refinement */
+       FE_PREC_BF16_IR = 2   /* as FP32_IR with the element contraction Ke*u_e on
+                                bf16 matrix cores, float32 accumulation */ };
+
+enum { FE_PRECOND_JACOBI = 0, FE_PRECOND_GMG = 1 };
+
+typedef struct fe_config {
+  int32_t nx, ny, nz;   /* elements per axis, each >= 1 */
+  double h;             /* element edge length (> 0) */
+  double E0, Emin;      /* SIMP moduli, 0 < Emin < E0 */
+  double nu;            /* Poisson ratio, -1 < nu < 0.5 */
+  double penal;         /* SIMP exponent p >= 1 */
+  double filter_r;      /* density-filter radius in element units (> 0) */
+  int32_t precision;    /* FE_PREC_* */
+  int32_t precond;      /* FE_PRECOND_* */
+  int32_t mg_levels;    /* levels of the geometric multigrid (>= 2 when precond = GMG) */
+  int32_t reserved;     /* must be 0 */
+} fe_config;
+
+typedef struct fe_solve_info {
+  int32_t iters;        /* total inner CG iterations */
+  int32_t outer_iters;  /* float64 refinement steps (0 for FE_PREC_FP64) */
+  double rel_res;       /* ||f - K u||_2 / ||f||_2 over the free dofs, in float64 */
+  double compliance;    /* f^T u (Eq. 4 objective) */
+} fe_solve_info;
+
+typedef struct fe_problem fe_problem;
+
+/* Bytes of device workspace fe_setup needs for cfg (pure host arithmetic;
+ * 0 when cfg is invalid). */
+FE_API size_t fe_workspace_size(const fe_config* cfg);
+
+/* Build a problem in the caller's workspace.
+ *   fixed : device uint8[ndof], 1 = dof held at zero; NULL = clamp every dof
+ *           of the face x = 0 (the cantilever support of Sec. IV).
+ *   f     : device float64[ndof] load vector (copied; entries on fixed dofs
+ *           are ignored).
+ *   ws    : device memory of ws_bytes >= fe_workspace_size(cfg), 256-byte
+ *           aligned, untouched by the caller until fe_destroy.
+ *   stream: hipStream_t to order all work on (NULL = default stream).
+ * Precomputes Ke by 2x2x2 Gauss quadrature, the filter row sums and the
+ * multigrid geometry. */
+FE_API fe_status fe_setup(const fe_config* cfg, const uint8_t* fixed, const double* f,
+                   void* ws, size_t ws_bytes, void* stream, fe_problem** out);
+
+/* y = K(rho) u restricted to the free dofs (fixed rows and columns removed,
+ * y = 0 on fixed dofs).  variant: 0 = float64, 1 = float32 vector,
+ * 2 = bf16 matrix cores (float32 accumulation); the low-precision variants
+ * convert u and y at the boundary.  rho: float64[nelem]. */
+FE_API fe_status fe_apply_K(fe_problem* p, const double* rho, const double* u, double* y,
+                     int32_t variant);
+
+/* Solve K(rho) u = f for the free dofs (Sec. III-D; CG preconditioned by
+ * Jacobi or geometric multigrid, Sec. III-D "PCG and multi-grid methods").
+ *   rho : float64[nelem], physical (filtered) density in [0, 1].
+ *   u   : float64[ndof]; in: initial guess, out: solution (0 on fixed dofs).
+ *   rtol: stop when ||f - K u||_2 <= rtol ||f||_2 (float64 residual).
+ *   max_iters: cap on inner CG iterations over the whole solve.
+ *   info: host pointer, may be NULL.
+ * Synchronises the stream.  FE_ENOTCONV / FE_EBREAKDOWN leave the last
+ * iterate in u and fill info. */
+FE_API fe_status fe_solve(fe_problem* p, const double* rho, double* u, double rtol,
+                   int32_t max_iters, fe_solve_info* info);
+
+/* Gradient of the compliance with respect to the physical density (Eq. 5):
+ *   dc[e] = -penal rho_e^(penal-1) (E0 - Emin) u_e^T Ke u_e.
+ * compliance: device float64 scalar receiving f^T u, may be NULL.
+ * Asynchronous. */
+FE_API fe_status fe_sensitivity(fe_problem* p, const double* rho, const double* u,
+                         double* dc, double* compliance);
+
+/* Density filter of problem (4): out = P in (transpose = 0) or
+ * out = P^T in (transpose = 1), with P_ij = w_ij / sum_j w_ij and
+ * w_ij = max(0, r - |c_i - c_j|) over element centroids in element units.
+ * in and out are float64[nelem] and must not alias.  Asynchronous. */
+FE_API fe_status fe_filter(fe_problem* p, const double* in, double* out, int32_t transpose);
+
+/* Optimality-criteria update of the design (Sec. III-D):
+ *   x_new = clamp(x * sqrt(max(0, -dcx) / (lambda * dv)),
+ *                 max(0, x - move), min(1, x + move)),
+ * lambda chosen so that sum(dv * x_new) = volfrac * nelem, to a relative
+ * bracket of 1e-12 on lambda.  dv = P^T v with unit element volumes.
+ * change: device float64 scalar receiving max |x_new - x|, may be NULL.
+ * x and x_new may alias.  Asynchronous. */
+FE_API fe_status oc_update(fe_problem* p, const double* x, const double* dcx, const double* dv,
+                    double volfrac, double move, double* x_new, double* change);
+
+/* Timing of the dominant kernel (matrix-free K*u): when on, every K*u launch
+ * is bracketed by HIP events on the handle's stream; fe_kernel_stats
+ * returns the number of launches and their summed duration in ms since the
+ * last reset, and the algorithmic bytes one launch moves. */
+FE_API fe_status fe_set_profiling(fe_problem* p, int32_t on);
+FE_API fe_status fe_kernel_stats(fe_problem* p, int32_t reset, int64_t* launches,
+                          double* total_ms, double* bytes_per_launch);
+
+/* Release the handle (the workspace stays the caller's). */
+FE_API void fe_destroy(fe_problem* p);
+
+/* Message of the last failure on this thread ("" if none). */
+FE_API const char* fe_last_error(void);
+
+#ifdef __cplusplus
+}
+#endif
+
+#endif /* FE_ABI_H */

@@ -1,0 +1,162 @@
+// Internal declarations of the gfx950 finite-element library.
+#pragma once
+#include <hip/hip_runtime.h>
+
+#include <cstddef>
+#include <cstdint>
+#include <string>
+#include <vector>
+
+#include "fe_abi.h"
+
+#define FE_BLOCK 256
+#define FE_MAX_LEVELS 6
+#define FE_RED_GRID 1024  // grid of the reduction kernels (partials per slot)
+
+// Structured brick grid of one multigrid level.
+struct Grid {
+  int32_t nx, ny, nz;
+  int64_t nelem, nnode, ndof;
+};
+
+// Device-resident state of one CG instance.  Scalars are written by the
+// last workgroup of a kernel and read by the following kernels, so the loop
+// runs with no host round trip per iteration.
+struct CgState {
+  double rz;      // r^T z of the current iterate
+  double alpha;   // step length of the current iteration
+  double beta;    // direction update factor
+  double rr;      // ||r||^2
+  double bb;      // ||b||^2 (right-hand side)
+  double tol2;    // stop when rr <= tol2
+  double pq;      // p^T K p
+  double spare;
+  int32_t iter;   // iterations done
+  int32_t max_iter;
+  int32_t done;   // 1 = stop (converged, capped or broken down)
+  int32_t status; // FE_OK, FE_ENOTCONV, FE_EBREAKDOWN
+  uint32_t counter[8];  // arrival counters of the last-block reductions
+};
+
+// Constants of the element operator in the per-axis sum/difference basis.
+// With t = V u_e (V = Walsh transform of the 8 corners, per component),
+// Ke u_e = V S t / 64 and S has the sparsity of an isotropic cube:
+//   A, B  : normal-strain block of the three linear modes
+//   G     : shear pairs of the linear modes
+//   C, D  : bilinear-mode pairs, F, H : bilinear triple, J : trilinear mode.
+// The stored values already include the 1/64.
+struct WalshK {
+  double A, B, G, C, D, F, H, J;
+};
+
+struct Level {
+  Grid g;
+  double h;
+  // device arrays (inside the workspace)
+  double* E64 = nullptr;     // element moduli
+  float* E32 = nullptr;
+  double* invd64 = nullptr;  // 1 / Jacobi diagonal per node
+  float* invd32 = nullptr;
+  uint8_t* nmask = nullptr;  // bit c set = dof c of the node is fixed
+  // multigrid work vectors (float32 or float64 by precision)
+  void* mg_r = nullptr;
+  void* mg_z = nullptr;
+  void* mg_t = nullptr;
+};
+
+struct KStats {
+  bool on = false;
+  std::vector<hipEvent_t> ev;  // pairs
+  int64_t pending = 0;         // recorded pairs not yet read
+  int64_t launches = 0;
+  double total_ms = 0.0;
+};
+
+struct fe_problem {
+  fe_config cfg;
+  hipStream_t stream = nullptr;
+  char* ws = nullptr;
+  size_t ws_bytes = 0;
+  int nlev = 1;
+  Level L[FE_MAX_LEVELS];
+
+  double ke64_host[576];
+  double* ke64 = nullptr;  // dense Ke (device copy)
+  float* ke32 = nullptr;
+  WalshK wk;               // for h = 1 per level scaled by h
+  double ke_diag = 0.0;    // common diagonal entry of Ke (unit modulus, edge h)
+
+  double* f = nullptr;     // load, zero on fixed dofs
+  double* invW = nullptr;  // 1 / filter row sums
+  int nstencil = 0;        // filter stencil: offsets and cone weights
+  int4* st_off = nullptr;
+  double* st_w = nullptr;
+
+  // float64 CG vectors
+  double *r64 = nullptr, *p64 = nullptr, *q64 = nullptr;
+  // float32 CG vectors (iterative refinement)
+  float *x32 = nullptr, *r32 = nullptr, *p32 = nullptr, *q32 = nullptr;
+  // scratch
+  double* tmp64 = nullptr;
+  double* partials = nullptr;  // FE_RED_GRID * 64 doubles
+  CgState* st = nullptr;       // device state (two instances: [0] inner, [1] aux)
+  double* scal = nullptr;      // 64 device scalars for small results
+  double* oc = nullptr;        // OC search state
+
+  KStats kst;
+};
+
+// ------------------------------------------------------------------ host
+void fe_set_error(const std::string& msg);
+int host_hex8_ke(double nu, double E, double h, double* Ke /*576*/);
+int host_walsh_constants(const double* Ke, WalshK* wk, double* max_dev);
+
+// ------------------------------------------------------------- launchers
+// All launchers enqueue on p->stream and return hipGetLastError().
+hipError_t launch_simp(fe_problem* p, int lev, const double* rho);
+hipError_t launch_coarsen_modulus(fe_problem* p, int lev);  // E[lev] from E[lev-1]
+hipError_t launch_diag(fe_problem* p, int lev);
+hipError_t launch_node_mask(fe_problem* p, const uint8_t* fixed);
+hipError_t launch_coarsen_mask(fe_problem* p, int lev);
+hipError_t launch_mask_load(fe_problem* p, const double* f);
+template <typename T>
+hipError_t launch_mask_vec(fe_problem* p, int lev, T* v);
+
+// y = K x (masked) on level lev; if st != nullptr also accumulates x^T y and
+// finalises alpha = rz / pq into st (CG step).
+template <typename T>
+hipError_t launch_kxu(fe_problem* p, int lev, const T* x, T* y, CgState* st);
+
+// CG helpers (T = float or double vectors, float64 reductions)
+template <typename T>
+hipError_t launch_cg_init(fe_problem* p, const T* b, const T* Kx, T* r, T* pvec, CgState* st,
+                          int precond_mg);
+template <typename T>
+hipError_t launch_cg_update(fe_problem* p, T* x, T* r, const T* pvec, const T* q, CgState* st,
+                            int precond_mg);
+template <typename T>
+hipError_t launch_cg_direction(fe_problem* p, const T* r, const T* z, T* pvec, CgState* st);
+template <typename T>
+hipError_t launch_cg_rz(fe_problem* p, const T* r, const T* z, CgState* st);
+
+hipError_t launch_cg_state_init(fe_problem* p, CgState* st, double tol_rel, int max_iter);
+
+// float64 residual r = f - K u (masked) and ||r||^2 into scal[slot]
+hipError_t launch_residual64(fe_problem* p, const double* u, double* r, double* scal_slot);
+// r32 = r64 * scale (scale = 1/||r64|| read on device from scal)
+hipError_t launch_to32_scaled(fe_problem* p, const double* r64, float* r32, const double* nrm2);
+hipError_t launch_axpy_from32(fe_problem* p, double* u, const float* d, const double* nrm2);
+hipError_t launch_dot64(fe_problem* p, const double* a, const double* b, int64_t n, double* out);
+
+// element kernels
+hipError_t launch_sensitivity(fe_problem* p, const double* rho, const double* u, double* dc);
+hipError_t launch_filter(fe_problem* p, const double* in, double* out, int transpose);
+hipError_t launch_filter_rowsums(fe_problem* p);
+hipError_t launch_oc(fe_problem* p, const double* x, const double* dcx, const double* dv,
+                     double volfrac, double move, double* x_new, double* change);
+
+// conversions and fills (fill is a kernel, so it is safe inside captured graphs)
+template <typename T>
+hipError_t launch_fill(fe_problem* p, T* v, int64_t n, T val);
+hipError_t launch_convert_64_32(fe_problem* p, const double* a, float* b, int64_t n);
+hipError_t launch_convert_32_64(fe_problem* p, const float* a, double* b, int64_t n);

@@ -1,0 +1,869 @@
+// Element, node and vector kernels of the FE step (gfx950, wave64).
+#include <hip/hip_runtime.h>
+
+#include "fe_internal.h"
+#include "fe_reduce.h"
+
+namespace {
+
+__host__ __device__ inline int64_t ceil_div(int64_t a, int64_t b) { return (a + b - 1) / b; }
+
+inline int red_grid(int64_t n) {
+  int64_t g = ceil_div(n, FE_BLOCK);
+  if (g > FE_RED_GRID) g = FE_RED_GRID;
+  if (g < 1) g = 1;
+  return (int)g;
+}
+
+// Corner offsets of the brick in the fixed local order.
+__constant__ int c_cx[8] = {0, 1, 1, 0, 0, 1, 1, 0};
+__constant__ int c_cy[8] = {0, 0, 1, 1, 0, 0, 1, 1};
+__constant__ int c_cz[8] = {0, 0, 0, 0, 1, 1, 1, 1};
+
+// ------------------------------------------------------------------ SIMP
+template <typename T>
+__global__ void __launch_bounds__(FE_BLOCK) simp_kernel(const double* __restrict__ rho, int64_t n,
+                                                        double E0, double Emin, double penal,
+                                                        double* __restrict__ E64,
+                                                        float* __restrict__ E32) {
+  for (int64_t e = blockIdx.x * (int64_t)FE_BLOCK + threadIdx.x; e < n;
+       e += (int64_t)gridDim.x * FE_BLOCK) {
+    const double r = rho[e];
+    const double E = Emin + pow(r, penal) * (E0 - Emin);
+    if (E64) E64[e] = E;
+    if (E32) E32[e] = (float)E;
+  }
+}
+
+// Coarse modulus: mean of the (up to) 8 fine children of each coarse element.
+__global__ void __launch_bounds__(FE_BLOCK) coarsen_modulus_kernel(Grid fg, Grid cg,
+                                                                   const double* __restrict__ Ef,
+                                                                   double* __restrict__ Ec64,
+                                                                   float* __restrict__ Ec32) {
+  for (int64_t e = blockIdx.x * (int64_t)FE_BLOCK + threadIdx.x; e < cg.nelem;
+       e += (int64_t)gridDim.x * FE_BLOCK) {
+    const int i = (int)(e % cg.nx), j = (int)((e / cg.nx) % cg.ny), k = (int)(e / ((int64_t)cg.nx * cg.ny));
+    double s = 0.0;
+    int cnt = 0;
+    for (int c = 0; c < 8; ++c) {
+      const int fi = 2 * i + c_cx[c], fj = 2 * j + c_cy[c], fk = 2 * k + c_cz[c];
+      if (fi < fg.nx && fj < fg.ny && fk < fg.nz) {
+        s += Ef[fi + (int64_t)fg.nx * (fj + (int64_t)fg.ny * fk)];
+        ++cnt;
+      }
+    }
+    const double E = s / cnt;
+    if (Ec64) Ec64[e] = E;
+    if (Ec32) Ec32[e] = (float)E;
+  }
+}
+
+// --------------------------------------------------------------- masks
+__global__ void __launch_bounds__(FE_BLOCK) node_mask_kernel(Grid g, const uint8_t* __restrict__ fixed,
+                                                             uint8_t* __restrict__ nmask) {
+  for (int64_t n = blockIdx.x * (int64_t)FE_BLOCK + threadIdx.x; n < g.nnode;
+       n += (int64_t)gridDim.x * FE_BLOCK) {
+    uint8_t m = 0;
+    if (fixed) {
+      for (int c = 0; c < 3; ++c) m |= (fixed[3 * n + c] ? 1 : 0) << c;
+    } else {
+      m = (n % (g.nx + 1)) == 0 ? 7 : 0;
+    }
+    nmask[n] = m;
+  }
+}
+
+// A coarse node is fixed in component c when the fine node at the same place is.
+__global__ void __launch_bounds__(FE_BLOCK) coarsen_mask_kernel(Grid fg, Grid cg,
+                                                                const uint8_t* __restrict__ fm,
+                                                                uint8_t* __restrict__ cm) {
+  for (int64_t n = blockIdx.x * (int64_t)FE_BLOCK + threadIdx.x; n < cg.nnode;
+       n += (int64_t)gridDim.x * FE_BLOCK) {
+    const int i = (int)(n % (cg.nx + 1)), j = (int)((n / (cg.nx + 1)) % (cg.ny + 1)),
+              k = (int)(n / ((int64_t)(cg.nx + 1) * (cg.ny + 1)));
+    const int fi = min(2 * i, fg.nx), fj = min(2 * j, fg.ny), fk = min(2 * k, fg.nz);
+    cm[n] = fm[fi + (int64_t)(fg.nx + 1) * (fj + (int64_t)(fg.ny + 1) * fk)];
+  }
+}
+
+__global__ void __launch_bounds__(FE_BLOCK) mask_load_kernel(Grid g, const double* __restrict__ fin,
+                                                             const uint8_t* __restrict__ nmask,
+                                                             double* __restrict__ fout) {
+  for (int64_t d = blockIdx.x * (int64_t)FE_BLOCK + threadIdx.x; d < g.ndof;
+       d += (int64_t)gridDim.x * FE_BLOCK) {
+    const int64_t n = d / 3;
+    const int c = (int)(d - 3 * n);
+    fout[d] = ((nmask[n] >> c) & 1) ? 0.0 : fin[d];
+  }
+}
+
+template <typename T>
+__global__ void __launch_bounds__(FE_BLOCK) mask_vec_kernel(Grid g, const uint8_t* __restrict__ nmask,
+                                                            T* __restrict__ v) {
+  for (int64_t d = blockIdx.x * (int64_t)FE_BLOCK + threadIdx.x; d < g.ndof;
+       d += (int64_t)gridDim.x * FE_BLOCK) {
+    const int64_t n = d / 3;
+    const int c = (int)(d - 3 * n);
+    if ((nmask[n] >> c) & 1) v[d] = T(0);
+  }
+}
+
+// ---------------------------------------------------------- Jacobi diag
+// All 24 diagonal entries of Ke are equal (cube, isotropic), so
+// diag K at node n = kdiag * sum of the moduli of the elements around n.
+__global__ void __launch_bounds__(FE_BLOCK) diag_kernel(Grid g, const double* __restrict__ E,
+                                                        double kdiag, double* __restrict__ invd64,
+                                                        float* __restrict__ invd32) {
+  for (int64_t n = blockIdx.x * (int64_t)FE_BLOCK + threadIdx.x; n < g.nnode;
+       n += (int64_t)gridDim.x * FE_BLOCK) {
+    const int i = (int)(n % (g.nx + 1)), j = (int)((n / (g.nx + 1)) % (g.ny + 1)),
+              k = (int)(n / ((int64_t)(g.nx + 1) * (g.ny + 1)));
+    double s = 0.0;
+    for (int c = 0; c < 8; ++c) {
+      const int ei = i - c_cx[c], ej = j - c_cy[c], ek = k - c_cz[c];
+      if (ei >= 0 && ei < g.nx && ej >= 0 && ej < g.ny && ek >= 0 && ek < g.nz)
+        s += E[ei + (int64_t)g.nx * (ej + (int64_t)g.ny * ek)];
+    }
+    const double d = 1.0 / (kdiag * s);
+    if (invd64) invd64[n] = d;
+    if (invd32) invd32[n] = (float)d;
+  }
+}
+
+// ----------------------------------------------------------- K * x (v1)
+// Node-centric, dense Ke: node n sums, over the (up to) 8 bricks around it,
+// E_e * (row block of Ke for n's corner) * u_e.  Inputs must be zero on fixed
+// dofs; outputs are zeroed there.  MODE 0: y = Kx.  MODE 1: CG step, also
+// pq = x^T y and alpha = rz / pq.  MODE 2: y = b - Kx and ||y||^2 -> out.
+template <typename T, int MODE>
+__global__ void __launch_bounds__(FE_BLOCK) kxu_dense_kernel(
+    Grid g, const T* __restrict__ x, const T* __restrict__ E, const uint8_t* __restrict__ nmask,
+    const double* __restrict__ ke, double kscale, T* __restrict__ y, const double* __restrict__ b,
+    CgState* st, double* partials, double* out) {
+  if (MODE == 1 && st->done) return;
+  __shared__ T sKe[576];
+  for (int i = threadIdx.x; i < 576; i += FE_BLOCK) sKe[i] = (T)(ke[i] * kscale);
+  __syncthreads();
+  const int64_t n = blockIdx.x * (int64_t)FE_BLOCK + threadIdx.x;
+  double dotv = 0.0;
+  if (n < g.nnode) {
+    const int i = (int)(n % (g.nx + 1)), j = (int)((n / (g.nx + 1)) % (g.ny + 1)),
+              k = (int)(n / ((int64_t)(g.nx + 1) * (g.ny + 1)));
+    T acc[3] = {T(0), T(0), T(0)};
+    for (int a = 0; a < 8; ++a) {
+      const int ei = i - c_cx[a], ej = j - c_cy[a], ek = k - c_cz[a];
+      if (ei < 0 || ei >= g.nx || ej < 0 || ej >= g.ny || ek < 0 || ek >= g.nz) continue;
+      const T Ee = E[ei + (int64_t)g.nx * (ej + (int64_t)g.ny * ek)];
+      T ue[24];
+#pragma unroll
+      for (int bb = 0; bb < 8; ++bb) {
+        const int64_t nb = (ei + c_cx[bb]) + (int64_t)(g.nx + 1) * ((ej + c_cy[bb]) + (int64_t)(g.ny + 1) * (ek + c_cz[bb]));
+        ue[3 * bb + 0] = x[3 * nb + 0];
+        ue[3 * bb + 1] = x[3 * nb + 1];
+        ue[3 * bb + 2] = x[3 * nb + 2];
+      }
+#pragma unroll
+      for (int c = 0; c < 3; ++c) {
+        const T* row = &sKe[(3 * a + c) * 24];
+        T s = T(0);
+#pragma unroll
+        for (int q = 0; q < 24; ++q) s += row[q] * ue[q];
+        acc[c] += Ee * s;
+      }
+    }
+    const uint8_t m = nmask[n];
+#pragma unroll
+    for (int c = 0; c < 3; ++c) {
+      T v = ((m >> c) & 1) ? T(0) : acc[c];
+      if (MODE == 2) {
+        v = ((m >> c) & 1) ? T(0) : (T)(b[3 * n + c] - (double)v);
+        dotv += (double)v * (double)v;
+      } else if (MODE == 1) {
+        dotv += (double)x[3 * n + c] * (double)v;
+      }
+      y[3 * n + c] = v;
+    }
+  }
+  if (MODE == 0) return;
+  double vv[1] = {dotv};
+  const bool last = grid_sum<1>(vv, partials, MODE == 1 ? &st->counter[0] : (uint32_t*)(out + 1));
+  if (last && threadIdx.x == 0) {
+    if (MODE == 1) {
+      const double pq = vv[0];
+      st->pq = pq;
+      if (!(pq > 0.0) || !finite_d(pq)) {
+        st->status = FE_EBREAKDOWN;
+        st->done = 1;
+      } else {
+        st->alpha = st->rz / pq;
+      }
+    } else {
+      out[0] = vv[0];
+    }
+  }
+}
+
+// ------------------------------------------------------------- CG pieces
+// r = b - Kx (Kx may be null: x = 0), z = D^-1 r, p = z, and rz, rr, bb.
+template <typename T>
+__global__ void __launch_bounds__(FE_BLOCK) cg_init_kernel(Grid g, const T* __restrict__ b,
+                                                           const T* __restrict__ Kx, T* __restrict__ r,
+                                                           T* __restrict__ p, const T* __restrict__ invd,
+                                                           CgState* st, double* partials, int mg) {
+  double acc[3] = {0.0, 0.0, 0.0};  // rz, rr, bb
+  for (int64_t d = blockIdx.x * (int64_t)FE_BLOCK + threadIdx.x; d < g.ndof;
+       d += (int64_t)gridDim.x * FE_BLOCK) {
+    const T bv = b[d];
+    const T rv = Kx ? (T)(bv - Kx[d]) : bv;
+    r[d] = rv;
+    if (!mg) {
+      const T zv = rv * invd[d / 3];
+      p[d] = zv;
+      acc[0] += (double)rv * (double)zv;
+    }
+    acc[1] += (double)rv * (double)rv;
+    acc[2] += (double)bv * (double)bv;
+  }
+  if (grid_sum<3>(acc, partials, &st->counter[1]) && threadIdx.x == 0) {
+    st->rz = acc[0];
+    st->rr = acc[1];
+    st->bb = acc[2];
+    st->tol2 = st->tol2 * acc[2];  // tol2 held rtol^2 until now
+    st->iter = 0;
+    st->status = FE_OK;
+    st->done = (acc[1] <= st->tol2) ? 1 : 0;
+    if (!finite_d(acc[1])) {
+      st->status = FE_EBREAKDOWN;
+      st->done = 1;
+    }
+  }
+}
+
+// x += alpha p, r -= alpha q, (Jacobi) rz = r^T D^-1 r, rr = r^T r; then the
+// convergence test.  With mg = 1 the preconditioner runs separately and rz
+// comes from cg_rz_kernel.
+template <typename T>
+__global__ void __launch_bounds__(FE_BLOCK) cg_update_kernel(Grid g, T* __restrict__ x, T* __restrict__ r,
+                                                             const T* __restrict__ p, const T* __restrict__ q,
+                                                             const T* __restrict__ invd, CgState* st,
+                                                             double* partials, int mg) {
+  if (st->done) return;
+  const T alpha = (T)st->alpha;
+  double acc[2] = {0.0, 0.0};
+  for (int64_t d = blockIdx.x * (int64_t)FE_BLOCK + threadIdx.x; d < g.ndof;
+       d += (int64_t)gridDim.x * FE_BLOCK) {
+    x[d] += alpha * p[d];
+    const T rv = r[d] - alpha * q[d];
+    r[d] = rv;
+    if (!mg) acc[0] += (double)rv * (double)rv * (double)invd[d / 3];
+    acc[1] += (double)rv * (double)rv;
+  }
+  if (grid_sum<2>(acc, partials, &st->counter[2]) && threadIdx.x == 0) {
+    st->iter += 1;
+    st->rr = acc[1];
+    if (!mg) {
+      st->beta = acc[0] / st->rz;
+      st->rz = acc[0];
+    }
+    if (!finite_d(acc[1])) {
+      st->status = FE_EBREAKDOWN;
+      st->done = 1;
+    } else if (acc[1] <= st->tol2) {
+      st->status = FE_OK;
+      st->done = 1;
+    } else if (st->iter >= st->max_iter) {
+      st->status = FE_ENOTCONV;
+      st->done = 1;
+    }
+  }
+}
+
+// rz = r^T z (preconditioned by the multigrid cycle), beta = rz / rz_old.
+template <typename T>
+__global__ void __launch_bounds__(FE_BLOCK) cg_rz_kernel(Grid g, const T* __restrict__ r,
+                                                         const T* __restrict__ z, CgState* st,
+                                                         double* partials) {
+  if (st->done) return;
+  double acc[1] = {0.0};
+  for (int64_t d = blockIdx.x * (int64_t)FE_BLOCK + threadIdx.x; d < g.ndof;
+       d += (int64_t)gridDim.x * FE_BLOCK)
+    acc[0] += (double)r[d] * (double)z[d];
+  if (grid_sum<1>(acc, partials, &st->counter[3]) && threadIdx.x == 0) {
+    if (st->iter == 0) {
+      st->beta = 0.0;
+    } else {
+      st->beta = acc[0] / st->rz;
+    }
+    st->rz = acc[0];
+    if (!finite_d(acc[0]) || !(acc[0] > 0.0)) {
+      st->status = FE_EBREAKDOWN;
+      st->done = 1;
+    }
+  }
+}
+
+// p = z + beta p, z = D^-1 r when z is null (Jacobi).
+template <typename T>
+__global__ void __launch_bounds__(FE_BLOCK) cg_direction_kernel(Grid g, const T* __restrict__ r,
+                                                                const T* __restrict__ z,
+                                                                const T* __restrict__ invd,
+                                                                T* __restrict__ p, CgState* st) {
+  if (st->done) return;
+  const T beta = (T)st->beta;
+  for (int64_t d = blockIdx.x * (int64_t)FE_BLOCK + threadIdx.x; d < g.ndof;
+       d += (int64_t)gridDim.x * FE_BLOCK) {
+    const T zv = z ? z[d] : r[d] * invd[d / 3];
+    p[d] = zv + beta * p[d];
+  }
+}
+
+__global__ void cg_state_init_kernel(CgState* st, double tol_rel, int max_iter) {
+  if (threadIdx.x == 0 && blockIdx.x == 0) {
+    st->rz = st->alpha = st->beta = st->rr = st->bb = st->pq = 0.0;
+    st->tol2 = tol_rel * tol_rel;
+    st->iter = 0;
+    st->max_iter = max_iter;
+    st->done = 0;
+    st->status = FE_OK;
+    for (int i = 0; i < 8; ++i) st->counter[i] = 0;
+  }
+}
+
+// --------------------------------------------------- refinement helpers
+__global__ void __launch_bounds__(FE_BLOCK) to32_scaled_kernel(int64_t n, const double* __restrict__ a,
+                                                               float* __restrict__ b,
+                                                               const double* __restrict__ nrm2) {
+  const double s = 1.0 / sqrt(*nrm2);
+  for (int64_t d = blockIdx.x * (int64_t)FE_BLOCK + threadIdx.x; d < n;
+       d += (int64_t)gridDim.x * FE_BLOCK)
+    b[d] = (float)(a[d] * s);
+}
+
+__global__ void __launch_bounds__(FE_BLOCK) axpy_from32_kernel(int64_t n, double* __restrict__ u,
+                                                               const float* __restrict__ dvec,
+                                                               const double* __restrict__ nrm2) {
+  const double s = sqrt(*nrm2);
+  for (int64_t d = blockIdx.x * (int64_t)FE_BLOCK + threadIdx.x; d < n;
+       d += (int64_t)gridDim.x * FE_BLOCK)
+    u[d] += (double)dvec[d] * s;
+}
+
+__global__ void __launch_bounds__(FE_BLOCK) dot64_kernel(int64_t n, const double* __restrict__ a,
+                                                         const double* __restrict__ b, double* partials,
+                                                         double* out) {
+  double acc[1] = {0.0};
+  for (int64_t d = blockIdx.x * (int64_t)FE_BLOCK + threadIdx.x; d < n;
+       d += (int64_t)gridDim.x * FE_BLOCK)
+    acc[0] += a[d] * b[d];
+  if (grid_sum<1>(acc, partials, (uint32_t*)(out + 1)) && threadIdx.x == 0) out[0] = acc[0];
+}
+
+template <typename T>
+__global__ void __launch_bounds__(FE_BLOCK) fill_kernel(int64_t n, T* __restrict__ v, T val) {
+  for (int64_t d = blockIdx.x * (int64_t)FE_BLOCK + threadIdx.x; d < n;
+       d += (int64_t)gridDim.x * FE_BLOCK)
+    v[d] = val;
+}
+
+template <typename A, typename B>
+__global__ void __launch_bounds__(FE_BLOCK) convert_kernel(int64_t n, const A* __restrict__ a,
+                                                           B* __restrict__ b) {
+  for (int64_t d = blockIdx.x * (int64_t)FE_BLOCK + threadIdx.x; d < n;
+       d += (int64_t)gridDim.x * FE_BLOCK)
+    b[d] = (B)a[d];
+}
+
+// ------------------------------------------------------- sensitivity
+// dc_e = -p rho^(p-1) (E0 - Emin) u_e^T Ke u_e, with u_e^T Ke u_e = t^T S t
+// in the per-axis sum/difference basis (t = Walsh transform of the corners).
+__device__ inline void bfly(double& a, double& b) {
+  const double s = a + b, d = a - b;
+  a = s;
+  b = d;
+}
+
+__device__ inline void walsh8(double (&v)[8]) {
+  // corners in local order 000 100 110 010 001 101 111 011
+  bfly(v[0], v[1]); bfly(v[3], v[2]); bfly(v[4], v[5]); bfly(v[7], v[6]);  // x
+  bfly(v[0], v[3]); bfly(v[1], v[2]); bfly(v[4], v[7]); bfly(v[5], v[6]);  // y
+  bfly(v[0], v[4]); bfly(v[1], v[5]); bfly(v[2], v[6]); bfly(v[3], v[7]);  // z
+}
+
+__global__ void __launch_bounds__(FE_BLOCK) sensitivity_kernel(Grid g, const double* __restrict__ rho,
+                                                               const double* __restrict__ u,
+                                                               WalshK wk, double penal, double dE,
+                                                               double* __restrict__ dc) {
+  for (int64_t e = blockIdx.x * (int64_t)FE_BLOCK + threadIdx.x; e < g.nelem;
+       e += (int64_t)gridDim.x * FE_BLOCK) {
+    const int i = (int)(e % g.nx), j = (int)((e / g.nx) % g.ny), k = (int)(e / ((int64_t)g.nx * g.ny));
+    double t[3][8];
+#pragma unroll
+    for (int a = 0; a < 8; ++a) {
+      const int64_t n = (i + c_cx[a]) + (int64_t)(g.nx + 1) * ((j + c_cy[a]) + (int64_t)(g.ny + 1) * (k + c_cz[a]));
+      t[0][a] = u[3 * n];
+      t[1][a] = u[3 * n + 1];
+      t[2][a] = u[3 * n + 2];
+    }
+    walsh8(t[0]);
+    walsh8(t[1]);
+    walsh8(t[2]);
+    enum { X = 0, Y = 1, Z = 2 };
+    // modes: 1=100 2=110 3=010 4=001 5=101 6=111 7=011
+    double en = 0.0;
+    // linear modes, normal block
+    const double n1 = t[X][1], n2 = t[Y][3], n3 = t[Z][4];
+    en += wk.A * (n1 * n1 + n2 * n2 + n3 * n3) + 2.0 * wk.B * (n1 * n2 + n1 * n3 + n2 * n3);
+    // shear pairs (rank one)
+    const double s1 = t[Y][1] + t[X][3], s2 = t[Z][1] + t[X][4], s3 = t[Z][3] + t[Y][4];
+    en += wk.G * (s1 * s1 + s2 * s2 + s3 * s3);
+    // bilinear pairs
+    en += wk.C * (t[X][2] * t[X][2] + t[Z][7] * t[Z][7]) + 2.0 * wk.D * t[X][2] * t[Z][7];
+    en += wk.C * (t[Y][2] * t[Y][2] + t[Z][5] * t[Z][5]) + 2.0 * wk.D * t[Y][2] * t[Z][5];
+    en += wk.C * (t[X][5] * t[X][5] + t[Y][7] * t[Y][7]) + 2.0 * wk.D * t[X][5] * t[Y][7];
+    // bilinear triple
+    const double a3 = t[Z][2], b3 = t[Y][5], c3 = t[X][7];
+    en += wk.F * (a3 * a3 + b3 * b3 + c3 * c3) + 2.0 * wk.H * (a3 * b3 + a3 * c3 + b3 * c3);
+    // trilinear mode
+    en += wk.J * (t[X][6] * t[X][6] + t[Y][6] * t[Y][6] + t[Z][6] * t[Z][6]);
+    const double r = rho[e];
+    dc[e] = -penal * pow(r, penal - 1.0) * dE * en;
+  }
+}
+
+// ------------------------------------------------------------ filter
+struct Stencil {
+  int n;
+  const int4* off;  // (di, dj, dk, unused)
+  const double* w;
+};
+
+__global__ void __launch_bounds__(FE_BLOCK) filter_rowsum_kernel(Grid g, Stencil s, double* __restrict__ invW) {
+  for (int64_t e = blockIdx.x * (int64_t)FE_BLOCK + threadIdx.x; e < g.nelem;
+       e += (int64_t)gridDim.x * FE_BLOCK) {
+    const int i = (int)(e % g.nx), j = (int)((e / g.nx) % g.ny), k = (int)(e / ((int64_t)g.nx * g.ny));
+    double W = 0.0;
+    for (int q = 0; q < s.n; ++q) {
+      const int4 o = s.off[q];
+      const int ii = i + o.x, jj = j + o.y, kk = k + o.z;
+      if (ii >= 0 && ii < g.nx && jj >= 0 && jj < g.ny && kk >= 0 && kk < g.nz) W += s.w[q];
+    }
+    invW[e] = 1.0 / W;
+  }
+}
+
+// out = P in (transpose = 0):  out_i = invW_i sum_j w_ij in_j
+// out = P^T in (transpose = 1): out_j = sum_i w_ij invW_i in_i
+template <int TRANSPOSE>
+__global__ void __launch_bounds__(FE_BLOCK) filter_kernel(Grid g, Stencil s, const double* __restrict__ invW,
+                                                          const double* __restrict__ in,
+                                                          double* __restrict__ out) {
+  for (int64_t e = blockIdx.x * (int64_t)FE_BLOCK + threadIdx.x; e < g.nelem;
+       e += (int64_t)gridDim.x * FE_BLOCK) {
+    const int i = (int)(e % g.nx), j = (int)((e / g.nx) % g.ny), k = (int)(e / ((int64_t)g.nx * g.ny));
+    double acc = 0.0;
+    for (int q = 0; q < s.n; ++q) {
+      const int4 o = s.off[q];
+      const int ii = i + o.x, jj = j + o.y, kk = k + o.z;
+      if (ii >= 0 && ii < g.nx && jj >= 0 && jj < g.ny && kk >= 0 && kk < g.nz) {
+        const int64_t f = ii + (int64_t)g.nx * (jj + (int64_t)g.ny * kk);
+        acc += TRANSPOSE ? s.w[q] * invW[f] * in[f] : s.w[q] * in[f];
+      }
+    }
+    out[e] = TRANSPOSE ? acc : acc * invW[e];
+  }
+}
+
+// ------------------------------------------------------------------ OC
+// In s = 1/sqrt(lambda) the update is x_new = clamp(a s, lo, hi) with
+// a = x sqrt(max(0, -dcx) / dv); the volume sum(dv x_new) is continuous and
+// non-decreasing in s.  Each pass evaluates the volume at OC_NC points inside
+// the current bracket [s_lo, s_hi] and keeps the sub-interval that contains
+// the target.
+#define OC_NC 64
+struct OcState {
+  double s_lo, s_hi, target, lam;
+  int32_t done, pass, pad0, pad1;
+  uint32_t counter[4];
+};
+
+__device__ inline void oc_elem(const double* x, const double* dcx, const double* dv, int64_t e,
+                               double move, double& a, double& lo, double& hi, double& w) {
+  const double xe = x[e];
+  w = dv[e];
+  a = xe * sqrt(fmax(0.0, -dcx[e]) / w);
+  lo = fmax(0.0, xe - move);
+  hi = fmin(1.0, xe + move);
+}
+
+__global__ void __launch_bounds__(FE_BLOCK) oc_prep_kernel(int64_t n, const double* __restrict__ x,
+                                                           const double* __restrict__ dcx,
+                                                           const double* __restrict__ dv, double move,
+                                                           double target, OcState* os, double* partials) {
+  // s_max: beyond it every element with a > 0 sits at hi.
+  double smax = 0.0;
+  for (int64_t e = blockIdx.x * (int64_t)FE_BLOCK + threadIdx.x; e < n;
+       e += (int64_t)gridDim.x * FE_BLOCK) {
+    double a, lo, hi, w;
+    oc_elem(x, dcx, dv, e, move, a, lo, hi, w);
+    if (a > 0.0) smax = fmax(smax, hi / a);
+  }
+  if (grid_max(smax, partials, &os->counter[0]) && threadIdx.x == 0) {
+    os->s_lo = 0.0;
+    os->s_hi = smax * (1.0 + 1e-15) + 1e-300;
+    os->target = target;
+    os->done = 0;
+    os->pass = 0;
+  }
+}
+
+// Pass 0 spaces the candidates geometrically over s_hi * [1e-30, 1]; later
+// passes space them evenly inside the bracket.
+__device__ inline double oc_candidate(const OcState* os, int c) {
+  if (os->pass == 0) return os->s_hi * exp2(-100.0 * (double)(OC_NC - 1 - c) / (OC_NC - 1));
+  return os->s_lo + (os->s_hi - os->s_lo) * (double)(c + 1) / (double)(OC_NC + 1);
+}
+
+__global__ void __launch_bounds__(FE_BLOCK) oc_pass_kernel(int64_t n, const double* __restrict__ x,
+                                                           const double* __restrict__ dcx,
+                                                           const double* __restrict__ dv, double move,
+                                                           OcState* os, double* partials) {
+  if (os->done) return;
+  const int cand = threadIdx.x & (OC_NC - 1);
+  const int sub = threadIdx.x / OC_NC;  // 0..3
+  const double sc = oc_candidate(os, cand);
+  __shared__ double sa[FE_BLOCK], slo[FE_BLOCK], shi[FE_BLOCK], sw[FE_BLOCK];
+  double vol = 0.0;
+  for (int64_t base = blockIdx.x * (int64_t)FE_BLOCK; base < n; base += (int64_t)gridDim.x * FE_BLOCK) {
+    const int64_t e = base + threadIdx.x;
+    if (e < n) {
+      double a, lo, hi, w;
+      oc_elem(x, dcx, dv, e, move, a, lo, hi, w);
+      sa[threadIdx.x] = a;
+      slo[threadIdx.x] = lo;
+      shi[threadIdx.x] = hi;
+      sw[threadIdx.x] = w;
+    } else {
+      sa[threadIdx.x] = 0.0;
+      slo[threadIdx.x] = 0.0;
+      shi[threadIdx.x] = 0.0;
+      sw[threadIdx.x] = 0.0;
+    }
+    __syncthreads();
+    for (int q = sub; q < FE_BLOCK; q += FE_BLOCK / OC_NC)
+      vol += sw[q] * fmin(fmax(sa[q] * sc, slo[q]), shi[q]);
+    __syncthreads();
+  }
+  // combine the four sub-sums of each candidate in fixed order
+  __shared__ double part[FE_BLOCK];
+  part[threadIdx.x] = vol;
+  __syncthreads();
+  __shared__ int amlast;
+  if (threadIdx.x < OC_NC) {
+    double s = 0.0;
+    for (int q = 0; q < FE_BLOCK / OC_NC; ++q) s += part[q * OC_NC + threadIdx.x];
+    partials[(size_t)threadIdx.x * gridDim.x + blockIdx.x] = s;
+  }
+  __threadfence();
+  __syncthreads();
+  if (threadIdx.x == 0) {
+    const uint32_t t = atomicAdd(&os->counter[1], 1u);
+    amlast = (t == gridDim.x - 1);
+  }
+  __syncthreads();
+  if (!amlast) return;
+  __threadfence();
+  __shared__ double vols[OC_NC];
+  if (threadIdx.x < OC_NC) {
+    double s = 0.0;
+    for (uint32_t b = 0; b < gridDim.x; ++b)
+      s += __builtin_nontemporal_load(&partials[(size_t)threadIdx.x * gridDim.x + b]);
+    vols[threadIdx.x] = s;
+  }
+  __syncthreads();
+  if (threadIdx.x == 0) {
+    atomicExch(&os->counter[1], 0u);
+    // first candidate whose volume reaches the target
+    int c = 0;
+    while (c < OC_NC && vols[c] < os->target) ++c;
+    const double lo_new = (c == 0) ? os->s_lo : oc_candidate(os, c - 1);
+    const double hi_new = (c == OC_NC) ? os->s_hi : oc_candidate(os, c);
+    os->s_lo = lo_new;
+    os->s_hi = hi_new;
+    os->pass += 1;
+    // bracket on lambda = 1/s^2 relatively 1e-12 wide  <=>  on s about 5e-13
+    if (hi_new - lo_new <= 5e-13 * (hi_new + lo_new)) os->done = 1;
+  }
+}
+
+__global__ void __launch_bounds__(FE_BLOCK) oc_final_kernel(int64_t n, const double* x,
+                                                            const double* __restrict__ dcx,
+                                                            const double* __restrict__ dv, double move,
+                                                            OcState* os, double* x_new, double* partials,
+                                                            double* change) {
+  const double s = 0.5 * (os->s_lo + os->s_hi);
+  double ch = 0.0;
+  for (int64_t e = blockIdx.x * (int64_t)FE_BLOCK + threadIdx.x; e < n;
+       e += (int64_t)gridDim.x * FE_BLOCK) {
+    double a, lo, hi, w;
+    oc_elem(x, dcx, dv, e, move, a, lo, hi, w);
+    const double xo = x[e];
+    const double xn = fmin(fmax(a * s, lo), hi);
+    x_new[e] = xn;
+    ch = fmax(ch, fabs(xn - xo));
+  }
+  if (grid_max(ch, partials, &os->counter[2]) && threadIdx.x == 0) {
+    os->lam = 1.0 / (s * s);
+    if (change) *change = ch;
+  }
+}
+
+}  // namespace
+
+// =================================================================== launchers
+static inline Grid G(fe_problem* p, int lev) { return p->L[lev].g; }
+
+hipError_t launch_simp(fe_problem* p, int lev, const double* rho) {
+  const Grid g = G(p, lev);
+  hipLaunchKernelGGL(simp_kernel<double>, dim3(red_grid(g.nelem) * 4), dim3(FE_BLOCK), 0, p->stream, rho,
+                     g.nelem, p->cfg.E0, p->cfg.Emin, p->cfg.penal, p->L[lev].E64, p->L[lev].E32);
+  return hipGetLastError();
+}
+
+hipError_t launch_coarsen_modulus(fe_problem* p, int lev) {
+  hipLaunchKernelGGL(coarsen_modulus_kernel, dim3(red_grid(G(p, lev).nelem) * 4), dim3(FE_BLOCK), 0,
+                     p->stream, G(p, lev - 1), G(p, lev), p->L[lev - 1].E64, p->L[lev].E64, p->L[lev].E32);
+  return hipGetLastError();
+}
+
+hipError_t launch_diag(fe_problem* p, int lev) {
+  const Grid g = G(p, lev);
+  hipLaunchKernelGGL(diag_kernel, dim3(red_grid(g.nnode) * 4), dim3(FE_BLOCK), 0, p->stream, g,
+                     p->L[lev].E64, p->ke_diag * p->L[lev].h, p->L[lev].invd64, p->L[lev].invd32);
+  return hipGetLastError();
+}
+
+hipError_t launch_node_mask(fe_problem* p, const uint8_t* fixed) {
+  const Grid g = G(p, 0);
+  hipLaunchKernelGGL(node_mask_kernel, dim3(red_grid(g.nnode) * 4), dim3(FE_BLOCK), 0, p->stream, g,
+                     fixed, p->L[0].nmask);
+  return hipGetLastError();
+}
+
+hipError_t launch_coarsen_mask(fe_problem* p, int lev) {
+  hipLaunchKernelGGL(coarsen_mask_kernel, dim3(red_grid(G(p, lev).nnode) * 4), dim3(FE_BLOCK), 0,
+                     p->stream, G(p, lev - 1), G(p, lev), p->L[lev - 1].nmask, p->L[lev].nmask);
+  return hipGetLastError();
+}
+
+hipError_t launch_mask_load(fe_problem* p, const double* f) {
+  const Grid g = G(p, 0);
+  hipLaunchKernelGGL(mask_load_kernel, dim3(red_grid(g.ndof) * 4), dim3(FE_BLOCK), 0, p->stream, g, f,
+                     p->L[0].nmask, p->f);
+  return hipGetLastError();
+}
+
+template <typename T>
+hipError_t launch_mask_vec(fe_problem* p, int lev, T* v) {
+  const Grid g = G(p, lev);
+  hipLaunchKernelGGL(mask_vec_kernel<T>, dim3(red_grid(g.ndof) * 4), dim3(FE_BLOCK), 0, p->stream, g,
+                     p->L[lev].nmask, v);
+  return hipGetLastError();
+}
+template hipError_t launch_mask_vec<double>(fe_problem*, int, double*);
+template hipError_t launch_mask_vec<float>(fe_problem*, int, float*);
+
+template <typename T>
+static const T* level_E(fe_problem* p, int lev);
+template <>
+const double* level_E<double>(fe_problem* p, int lev) { return p->L[lev].E64; }
+template <>
+const float* level_E<float>(fe_problem* p, int lev) { return p->L[lev].E32; }
+template <typename T>
+static const T* level_invd(fe_problem* p, int lev);
+template <>
+const double* level_invd<double>(fe_problem* p, int lev) { return p->L[lev].invd64; }
+template <>
+const float* level_invd<float>(fe_problem* p, int lev) { return p->L[lev].invd32; }
+
+template <typename T>
+hipError_t launch_kxu(fe_problem* p, int lev, const T* x, T* y, CgState* st) {
+  const Grid g = G(p, lev);
+  const int nb = (int)ceil_div(g.nnode, FE_BLOCK);
+  KStats& ks = p->kst;
+  const bool prof = ks.on && lev == 0;
+  if (prof) {
+    const size_t slot = (size_t)ks.pending * 2;
+    if (slot + 2 > ks.ev.size()) {
+      hipEvent_t a, b;
+      if (hipEventCreate(&a) != hipSuccess || hipEventCreate(&b) != hipSuccess) return hipErrorOutOfMemory;
+      ks.ev.push_back(a);
+      ks.ev.push_back(b);
+    }
+    (void)hipEventRecord(ks.ev[slot], p->stream);
+  }
+  if (st)
+    hipLaunchKernelGGL((kxu_dense_kernel<T, 1>), dim3(nb), dim3(FE_BLOCK), 0, p->stream, g, x,
+                       level_E<T>(p, lev), p->L[lev].nmask, p->ke64, p->L[lev].h, y, nullptr, st,
+                       p->partials, nullptr);
+  else
+    hipLaunchKernelGGL((kxu_dense_kernel<T, 0>), dim3(nb), dim3(FE_BLOCK), 0, p->stream, g, x,
+                       level_E<T>(p, lev), p->L[lev].nmask, p->ke64, p->L[lev].h, y, nullptr, nullptr,
+                       p->partials, nullptr);
+  if (prof) {
+    (void)hipEventRecord(ks.ev[(size_t)ks.pending * 2 + 1], p->stream);
+    ks.pending += 1;
+  }
+  return hipGetLastError();
+}
+template hipError_t launch_kxu<double>(fe_problem*, int, const double*, double*, CgState*);
+template hipError_t launch_kxu<float>(fe_problem*, int, const float*, float*, CgState*);
+
+hipError_t launch_residual64(fe_problem* p, const double* u, double* r, double* scal_slot) {
+  const Grid g = G(p, 0);
+  const int nb = (int)ceil_div(g.nnode, FE_BLOCK);
+  hipLaunchKernelGGL((kxu_dense_kernel<double, 2>), dim3(nb), dim3(FE_BLOCK), 0, p->stream, g, u,
+                     p->L[0].E64, p->L[0].nmask, p->ke64, p->L[0].h, r, p->f, nullptr, p->partials,
+                     scal_slot);
+  return hipGetLastError();
+}
+
+template <typename T>
+hipError_t launch_cg_init(fe_problem* p, const T* b, const T* Kx, T* r, T* pvec, CgState* st, int mg) {
+  const Grid g = G(p, 0);
+  hipLaunchKernelGGL(cg_init_kernel<T>, dim3(red_grid(g.ndof)), dim3(FE_BLOCK), 0, p->stream, g, b, Kx, r,
+                     pvec, level_invd<T>(p, 0), st, p->partials, mg);
+  return hipGetLastError();
+}
+template hipError_t launch_cg_init<double>(fe_problem*, const double*, const double*, double*, double*,
+                                           CgState*, int);
+template hipError_t launch_cg_init<float>(fe_problem*, const float*, const float*, float*, float*,
+                                          CgState*, int);
+
+template <typename T>
+hipError_t launch_cg_update(fe_problem* p, T* x, T* r, const T* pvec, const T* q, CgState* st, int mg) {
+  const Grid g = G(p, 0);
+  hipLaunchKernelGGL(cg_update_kernel<T>, dim3(red_grid(g.ndof)), dim3(FE_BLOCK), 0, p->stream, g, x, r,
+                     pvec, q, level_invd<T>(p, 0), st, p->partials, mg);
+  return hipGetLastError();
+}
+template hipError_t launch_cg_update<double>(fe_problem*, double*, double*, const double*, const double*,
+                                             CgState*, int);
+template hipError_t launch_cg_update<float>(fe_problem*, float*, float*, const float*, const float*,
+                                            CgState*, int);
+
+template <typename T>
+hipError_t launch_cg_direction(fe_problem* p, const T* r, const T* z, T* pvec, CgState* st) {
+  const Grid g = G(p, 0);
+  hipLaunchKernelGGL(cg_direction_kernel<T>, dim3(red_grid(g.ndof) * 2), dim3(FE_BLOCK), 0, p->stream, g,
+                     r, z, level_invd<T>(p, 0), pvec, st);
+  return hipGetLastError();
+}
+template hipError_t launch_cg_direction<double>(fe_problem*, const double*, const double*, double*,
+                                                CgState*);
+template hipError_t launch_cg_direction<float>(fe_problem*, const float*, const float*, float*, CgState*);
+
+template <typename T>
+hipError_t launch_cg_rz(fe_problem* p, const T* r, const T* z, CgState* st) {
+  const Grid g = G(p, 0);
+  hipLaunchKernelGGL(cg_rz_kernel<T>, dim3(red_grid(g.ndof)), dim3(FE_BLOCK), 0, p->stream, g, r, z, st,
+                     p->partials);
+  return hipGetLastError();
+}
+template hipError_t launch_cg_rz<double>(fe_problem*, const double*, const double*, CgState*);
+template hipError_t launch_cg_rz<float>(fe_problem*, const float*, const float*, CgState*);
+
+hipError_t launch_cg_state_init(fe_problem* p, CgState* st, double tol_rel, int max_iter) {
+  hipLaunchKernelGGL(cg_state_init_kernel, dim3(1), dim3(64), 0, p->stream, st, tol_rel, max_iter);
+  return hipGetLastError();
+}
+
+hipError_t launch_to32_scaled(fe_problem* p, const double* r64, float* r32, const double* nrm2) {
+  const int64_t n = G(p, 0).ndof;
+  hipLaunchKernelGGL(to32_scaled_kernel, dim3(red_grid(n) * 2), dim3(FE_BLOCK), 0, p->stream, n, r64, r32,
+                     nrm2);
+  return hipGetLastError();
+}
+
+hipError_t launch_axpy_from32(fe_problem* p, double* u, const float* d, const double* nrm2) {
+  const int64_t n = G(p, 0).ndof;
+  hipLaunchKernelGGL(axpy_from32_kernel, dim3(red_grid(n) * 2), dim3(FE_BLOCK), 0, p->stream, n, u, d,
+                     nrm2);
+  return hipGetLastError();
+}
+
+hipError_t launch_dot64(fe_problem* p, const double* a, const double* b, int64_t n, double* out) {
+  hipLaunchKernelGGL(dot64_kernel, dim3(red_grid(n)), dim3(FE_BLOCK), 0, p->stream, n, a, b, p->partials,
+                     out);
+  return hipGetLastError();
+}
+
+template <typename T>
+hipError_t launch_fill(fe_problem* p, T* v, int64_t n, T val) {
+  hipLaunchKernelGGL(fill_kernel<T>, dim3(red_grid(n) * 2), dim3(FE_BLOCK), 0, p->stream, n, v, val);
+  return hipGetLastError();
+}
+template hipError_t launch_fill<double>(fe_problem*, double*, int64_t, double);
+template hipError_t launch_fill<float>(fe_problem*, float*, int64_t, float);
+
+hipError_t launch_convert_64_32(fe_problem* p, const double* a, float* b, int64_t n) {
+  hipLaunchKernelGGL((convert_kernel<double, float>), dim3(red_grid(n) * 2), dim3(FE_BLOCK), 0, p->stream,
+                     n, a, b);
+  return hipGetLastError();
+}
+
+hipError_t launch_convert_32_64(fe_problem* p, const float* a, double* b, int64_t n) {
+  hipLaunchKernelGGL((convert_kernel<float, double>), dim3(red_grid(n) * 2), dim3(FE_BLOCK), 0, p->stream,
+                     n, a, b);
+  return hipGetLastError();
+}
+
+hipError_t launch_sensitivity(fe_problem* p, const double* rho, const double* u, double* dc) {
+  const Grid g = G(p, 0);
+  WalshK wk = p->wk;
+  const double h = p->L[0].h;
+  wk.A *= h; wk.B *= h; wk.G *= h; wk.C *= h; wk.D *= h; wk.F *= h; wk.H *= h; wk.J *= h;
+  hipLaunchKernelGGL(sensitivity_kernel, dim3(red_grid(g.nelem) * 4), dim3(FE_BLOCK), 0, p->stream, g, rho,
+                     u, wk, p->cfg.penal, p->cfg.E0 - p->cfg.Emin, dc);
+  return hipGetLastError();
+}
+
+static Stencil make_stencil(fe_problem* p) {
+  Stencil s;
+  s.n = p->nstencil;
+  s.off = p->st_off;
+  s.w = p->st_w;
+  return s;
+}
+
+hipError_t launch_filter_rowsums(fe_problem* p) {
+  const Grid g = G(p, 0);
+  hipLaunchKernelGGL(filter_rowsum_kernel, dim3(red_grid(g.nelem) * 4), dim3(FE_BLOCK), 0, p->stream, g,
+                     make_stencil(p), p->invW);
+  return hipGetLastError();
+}
+
+hipError_t launch_filter(fe_problem* p, const double* in, double* out, int transpose) {
+  const Grid g = G(p, 0);
+  if (transpose)
+    hipLaunchKernelGGL(filter_kernel<1>, dim3(red_grid(g.nelem) * 4), dim3(FE_BLOCK), 0, p->stream, g,
+                       make_stencil(p), p->invW, in, out);
+  else
+    hipLaunchKernelGGL(filter_kernel<0>, dim3(red_grid(g.nelem) * 4), dim3(FE_BLOCK), 0, p->stream, g,
+                       make_stencil(p), p->invW, in, out);
+  return hipGetLastError();
+}
+
+hipError_t launch_oc(fe_problem* p, const double* x, const double* dcx, const double* dv, double volfrac,
+                     double move, double* x_new, double* change) {
+  const int64_t n = G(p, 0).nelem;
+  OcState* os = reinterpret_cast<OcState*>(p->oc);
+  const double target = volfrac * (double)n;
+  hipLaunchKernelGGL(oc_prep_kernel, dim3(red_grid(n)), dim3(FE_BLOCK), 0, p->stream, n, x, dcx, dv, move,
+                     target, os, p->partials);
+  for (int pass = 0; pass < 12; ++pass)
+    hipLaunchKernelGGL(oc_pass_kernel, dim3(red_grid(n)), dim3(FE_BLOCK), 0, p->stream, n, x, dcx, dv, move,
+                       os, p->partials);
+  hipLaunchKernelGGL(oc_final_kernel, dim3(red_grid(n)), dim3(FE_BLOCK), 0, p->stream, n, x, dcx, dv, move,
+                     os, x_new, p->partials, change);
+  return hipGetLastError();
+}

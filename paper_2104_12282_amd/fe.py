@@ -1,0 +1,194 @@
+"""Thin ctypes binding of libfe_hip.so (include/fe_abi.h).
+
+Argument marshalling only: torch tensors supply device memory and the stream;
+every step of the computation runs in the HIP library.  Importing this module
+does not need a GPU, but constructing a Problem does, and the library must be
+built (``python -m paper_2104_12282_amd.build``); there is no fallback.
+"""
+from __future__ import annotations
+
+import ctypes as C
+import os
+
+import torch
+
+_PKG = os.path.dirname(os.path.abspath(__file__))
+LIB_PATH = os.path.join(_PKG, "libfe_hip.so")
+
+FE_OK, FE_EINVAL, FE_ENOMEM, FE_EDEVICE, FE_ENOTCONV, FE_EBREAKDOWN = 0, -1, -2, -3, -4, -5
+PRECISION = {"fp64": 0, "fp32_ir": 1, "bf16_ir": 2}
+PRECOND = {"jacobi": 0, "gmg": 1}
+STATUS_NAME = {0: "FE_OK", -1: "FE_EINVAL", -2: "FE_ENOMEM", -3: "FE_EDEVICE",
+               -4: "FE_ENOTCONV", -5: "FE_EBREAKDOWN"}
+
+# Every entry point declared in include/fe_abi.h.
+ABI_SYMBOLS = ("fe_workspace_size", "fe_setup", "fe_apply_K", "fe_solve", "fe_sensitivity",
+               "fe_filter", "oc_update", "fe_set_profiling", "fe_kernel_stats", "fe_destroy",
+               "fe_last_error")
+
+
+class FEError(RuntimeError):
+    def __init__(self, status: int, msg: str):
+        super().__init__(f"{STATUS_NAME.get(status, status)}: {msg}")
+        self.status = status
+
+
+class fe_config(C.Structure):
+    _fields_ = [("nx", C.c_int32), ("ny", C.c_int32), ("nz", C.c_int32),
+                ("h", C.c_double), ("E0", C.c_double), ("Emin", C.c_double),
+                ("nu", C.c_double), ("penal", C.c_double), ("filter_r", C.c_double),
+                ("precision", C.c_int32), ("precond", C.c_int32),
+                ("mg_levels", C.c_int32), ("reserved", C.c_int32)]
+
+
+class fe_solve_info(C.Structure):
+    _fields_ = [("iters", C.c_int32), ("outer_iters", C.c_int32),
+                ("rel_res", C.c_double), ("compliance", C.c_double)]
+
+
+_lib = None
+
+
+def load_library() -> C.CDLL:
+    """Loads the HIP library; raises if it has not been built."""
+    global _lib
+    if _lib is not None:
+        return _lib
+    if not os.path.exists(LIB_PATH):
+        raise RuntimeError(f"{LIB_PATH} is missing: build it with "
+                           "`python -m paper_2104_12282_amd.build`")
+    lib = C.CDLL(LIB_PATH)
+    P, D, I32, I64 = C.c_void_p, C.c_double, C.c_int32, C.c_int64
+    lib.fe_workspace_size.argtypes = [C.POINTER(fe_config)]
+    lib.fe_workspace_size.restype = C.c_size_t
+    lib.fe_setup.argtypes = [C.POINTER(fe_config), P, P, P, C.c_size_t, P, C.POINTER(P)]
+    lib.fe_apply_K.argtypes = [P, P, P, P, I32]
+    lib.fe_solve.argtypes = [P, P, P, D, I32, C.POINTER(fe_solve_info)]
+    lib.fe_sensitivity.argtypes = [P, P, P, P, P]
+    lib.fe_filter.argtypes = [P, P, P, I32]
+    lib.oc_update.argtypes = [P, P, P, P, D, D, P, P]
+    lib.fe_set_profiling.argtypes = [P, I32]
+    lib.fe_kernel_stats.argtypes = [P, I32, C.POINTER(I64), C.POINTER(D), C.POINTER(D)]
+    lib.fe_destroy.argtypes = [P]
+    lib.fe_destroy.restype = None
+    lib.fe_last_error.argtypes = []
+    lib.fe_last_error.restype = C.c_char_p
+    for name in ("fe_setup", "fe_apply_K", "fe_solve", "fe_sensitivity", "fe_filter",
+                 "oc_update", "fe_set_profiling", "fe_kernel_stats"):
+        getattr(lib, name).restype = C.c_int
+    _lib = lib
+    return lib
+
+
+def _check(status: int, allow=()):
+    if status != FE_OK and status not in allow:
+        raise FEError(status, load_library().fe_last_error().decode())
+    return status
+
+
+def _ptr(t: torch.Tensor | None, dtype=torch.float64):
+    if t is None:
+        return None
+    if not t.is_cuda:
+        raise ValueError("device tensor required")
+    if t.dtype != dtype or not t.is_contiguous():
+        raise ValueError(f"contiguous {dtype} tensor required, got {t.dtype}")
+    return C.c_void_p(t.data_ptr())
+
+
+def make_config(nx, ny, nz, *, h=1.0, E0=1.0, Emin=1e-9, nu=0.3, penal=3.0, filter_r=1.5,
+                precision="fp64", precond="jacobi", mg_levels=3) -> fe_config:
+    return fe_config(nx, ny, nz, h, E0, Emin, nu, penal, filter_r, PRECISION[precision],
+                     PRECOND[precond], mg_levels if precond == "gmg" else 0, 0)
+
+
+def workspace_size(cfg: fe_config) -> int:
+    return int(load_library().fe_workspace_size(C.byref(cfg)))
+
+
+class Problem:
+    """One FE problem (grid, material, load, supports) resident on the GPU."""
+
+    def __init__(self, nx, ny, nz, f: torch.Tensor, fixed: torch.Tensor | None = None, *,
+                 device="cuda:0", stream: torch.cuda.Stream | None = None, **cfg_kw):
+        lib = load_library()
+        self.nx, self.ny, self.nz = nx, ny, nz
+        self.nelem = nx * ny * nz
+        self.ndof = 3 * (nx + 1) * (ny + 1) * (nz + 1)
+        self.cfg = make_config(nx, ny, nz, **cfg_kw)
+        self.device = torch.device(device)
+        self.stream = stream if stream is not None else torch.cuda.current_stream(self.device)
+        nbytes = lib.fe_workspace_size(C.byref(self.cfg))
+        if nbytes == 0:
+            # validation failed: let fe_setup report why
+            nbytes = 256
+        self.ws_bytes = int(nbytes)
+        self.ws = torch.empty(self.ws_bytes, dtype=torch.uint8, device=self.device)
+        self.f = f.to(self.device, torch.float64).contiguous()
+        self.fixed = None if fixed is None else fixed.to(self.device, torch.uint8).contiguous()
+        h = C.c_void_p()
+        with torch.cuda.stream(self.stream):
+            _check(lib.fe_setup(C.byref(self.cfg), _ptr(self.fixed, torch.uint8), _ptr(self.f),
+                                C.c_void_p(self.ws.data_ptr()), self.ws_bytes,
+                                C.c_void_p(self.stream.cuda_stream), C.byref(h)))
+        self._h = h
+
+    # -- helpers -----------------------------------------------------------
+    def _vec(self, n):
+        return torch.empty(n, dtype=torch.float64, device=self.device)
+
+    def close(self):
+        if getattr(self, "_h", None):
+            load_library().fe_destroy(self._h)
+            self._h = None
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
+
+    # -- ABI calls ---------------------------------------------------------
+    def apply_K(self, rho, u, variant=0, out=None):
+        y = self._vec(self.ndof) if out is None else out
+        _check(load_library().fe_apply_K(self._h, _ptr(rho), _ptr(u), _ptr(y), variant))
+        return y
+
+    def solve(self, rho, u=None, rtol=1e-8, max_iters=100000, allow_notconv=False):
+        if u is None:
+            u = torch.zeros(self.ndof, dtype=torch.float64, device=self.device)
+        info = fe_solve_info()
+        allow = (FE_ENOTCONV,) if allow_notconv else ()
+        st = _check(load_library().fe_solve(self._h, _ptr(rho), _ptr(u), rtol, max_iters,
+                                            C.byref(info)), allow)
+        return u, {"iters": info.iters, "outer_iters": info.outer_iters,
+                   "rel_res": info.rel_res, "compliance": info.compliance, "status": st}
+
+    def sensitivity(self, rho, u, out=None, compliance_out=None):
+        dc = self._vec(self.nelem) if out is None else out
+        c = torch.zeros(1, dtype=torch.float64, device=self.device) if compliance_out is None \
+            else compliance_out
+        _check(load_library().fe_sensitivity(self._h, _ptr(rho), _ptr(u), _ptr(dc), _ptr(c)))
+        return dc, c
+
+    def filter(self, x, transpose=False, out=None):
+        y = self._vec(self.nelem) if out is None else out
+        _check(load_library().fe_filter(self._h, _ptr(x), _ptr(y), 1 if transpose else 0))
+        return y
+
+    def oc_update(self, x, dcx, dv, volfrac, move, out=None, change_out=None):
+        xn = self._vec(self.nelem) if out is None else out
+        ch = torch.zeros(1, dtype=torch.float64, device=self.device) if change_out is None \
+            else change_out
+        _check(load_library().oc_update(self._h, _ptr(x), _ptr(dcx), _ptr(dv), volfrac, move,
+                                        _ptr(xn), _ptr(ch)))
+        return xn, ch
+
+    def set_profiling(self, on: bool):
+        _check(load_library().fe_set_profiling(self._h, 1 if on else 0))
+
+    def kernel_stats(self, reset=False):
+        n, ms, b = C.c_int64(), C.c_double(), C.c_double()
+        _check(load_library().fe_kernel_stats(self._h, 1 if reset else 0, C.byref(n), C.byref(ms),
+                                              C.byref(b)))
+        return {"launches": n.value, "total_ms": ms.value, "bytes_per_launch": b.value}
