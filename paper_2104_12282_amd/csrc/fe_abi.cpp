@@ -94,7 +94,8 @@ size_t layout(const fe_config* c, fe_problem* p, char* base) {
       L.mg_t = take(g.ndof * vbytes);
     }
     if (p) p->L[l] = L;
-    const int64_t nb = (g.nnode + FE_BLOCK - 1) / FE_BLOCK;
+    int64_t nb = (g.nnode + FE_BLOCK - 1) / FE_BLOCK;
+    if (kxu_tile_blocks(g) > nb) nb = kxu_tile_blocks(g);
     if (nb > max_blocks) max_blocks = nb;
     nx /= 2;
     ny /= 2;
@@ -406,6 +407,12 @@ extern "C" fe_status fe_apply_K(fe_problem* p, const double* rho, const double* 
     HIP_TRY(launch_mask_vec<float>(p, 0, p->x32));
     HIP_TRY(launch_kxu<float>(p, 0, p->x32, p->q32, nullptr));
     HIP_TRY(launch_convert_32_64(p, p->q32, y, ndof));
+    return FE_OK;
+  }
+  if (variant == 3) {  // dense-Ke node-centric reference kernel, float64
+    HIP_TRY(hipMemcpyAsync(p->tmp64, u, ndof * sizeof(double), hipMemcpyDeviceToDevice, p->stream));
+    HIP_TRY(launch_mask_vec<double>(p, 0, p->tmp64));
+    HIP_TRY(launch_kxu_dense64(p, p->tmp64, y));
     return FE_OK;
   }
   fe_set_error("unknown K*u variant");

@@ -127,6 +127,15 @@ hipError_t launch_mask_vec(fe_problem* p, int lev, T* v);
 template <typename T>
 hipError_t launch_kxu(fe_problem* p, int lev, const T* x, T* y, CgState* st);
 
+// The tiled kernel behind launch_kxu: mode 0 y = Kx, 1 CG step (st), 2 y = b - Kx
+// with ||y||^2 -> out[0] (float64 only).
+template <typename T>
+hipError_t launch_kxu_tile(fe_problem* p, int lev, const T* x, const T* E, T* y, CgState* st, int mode,
+                           const double* b, double* out);
+int64_t kxu_tile_blocks(const Grid& g);
+// Node-centric dense-Ke reference kernel (float64), kept as a second implementation.
+hipError_t launch_kxu_dense64(fe_problem* p, const double* x, double* y);
+
 // CG helpers (T = float or double vectors, float64 reductions)
 template <typename T>
 hipError_t launch_cg_init(fe_problem* p, const T* b, const T* Kx, T* r, T* pvec, CgState* st,

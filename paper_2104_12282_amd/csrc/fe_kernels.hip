@@ -701,14 +701,8 @@ hipError_t launch_kxu(fe_problem* p, int lev, const T* x, T* y, CgState* st) {
     }
     (void)hipEventRecord(ks.ev[slot], p->stream);
   }
-  if (st)
-    hipLaunchKernelGGL((kxu_dense_kernel<T, 1>), dim3(nb), dim3(FE_BLOCK), 0, p->stream, g, x,
-                       level_E<T>(p, lev), p->L[lev].nmask, p->ke64, p->L[lev].h, y, nullptr, st,
-                       p->partials, nullptr);
-  else
-    hipLaunchKernelGGL((kxu_dense_kernel<T, 0>), dim3(nb), dim3(FE_BLOCK), 0, p->stream, g, x,
-                       level_E<T>(p, lev), p->L[lev].nmask, p->ke64, p->L[lev].h, y, nullptr, nullptr,
-                       p->partials, nullptr);
+  hipError_t err = launch_kxu_tile<T>(p, lev, x, level_E<T>(p, lev), y, st, st ? 1 : 0, nullptr, nullptr);
+  if (err != hipSuccess) return err;
   if (prof) {
     (void)hipEventRecord(ks.ev[(size_t)ks.pending * 2 + 1], p->stream);
     ks.pending += 1;
@@ -719,11 +713,15 @@ template hipError_t launch_kxu<double>(fe_problem*, int, const double*, double*,
 template hipError_t launch_kxu<float>(fe_problem*, int, const float*, float*, CgState*);
 
 hipError_t launch_residual64(fe_problem* p, const double* u, double* r, double* scal_slot) {
+  return launch_kxu_tile<double>(p, 0, u, p->L[0].E64, r, nullptr, 2, p->f, scal_slot);
+}
+
+hipError_t launch_kxu_dense64(fe_problem* p, const double* x, double* y) {
   const Grid g = G(p, 0);
   const int nb = (int)ceil_div(g.nnode, FE_BLOCK);
-  hipLaunchKernelGGL((kxu_dense_kernel<double, 2>), dim3(nb), dim3(FE_BLOCK), 0, p->stream, g, u,
-                     p->L[0].E64, p->L[0].nmask, p->ke64, p->L[0].h, r, p->f, nullptr, p->partials,
-                     scal_slot);
+  hipLaunchKernelGGL((kxu_dense_kernel<double, 0>), dim3(nb), dim3(FE_BLOCK), 0, p->stream, g, x,
+                     p->L[0].E64, p->L[0].nmask, p->ke64, p->L[0].h, y, nullptr, nullptr, p->partials,
+                     nullptr);
   return hipGetLastError();
 }
 

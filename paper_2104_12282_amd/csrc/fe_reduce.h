@@ -1,7 +1,7 @@
 // Deterministic block and grid reductions for float64 sums.
 //
 // Every workgroup reduces its values in a fixed order (wave64 butterfly, then
-// the waves in index order), writes them to partials[v * gridDim.x + block]
+// the waves in index order), writes them to partials[v * blocks + block]
 // and bumps an arrival counter; the workgroup that arrives last sums the
 // partials in block order and runs the finaliser.  The result is independent
 // of scheduling, so a solve is bitwise reproducible.
@@ -21,6 +21,12 @@ __device__ inline double wave_max(double v) {
   for (int o = 32; o > 0; o >>= 1) v = fmax(v, __shfl_xor(v, o, 64));
   return v;
 }
+
+// Linear index and count of the workgroups of a (possibly 3-D) grid.
+__device__ inline uint32_t block_id() {
+  return blockIdx.x + gridDim.x * (blockIdx.y + gridDim.y * blockIdx.z);
+}
+__device__ inline uint32_t block_count() { return gridDim.x * gridDim.y * gridDim.z; }
 
 // Sum of v[0..NV) over the workgroup; the totals are valid in thread 0.
 // Needs a barrier-free entry (all threads of the block call it).
@@ -67,10 +73,10 @@ __device__ inline bool grid_sum(double (&v)[NV], double* partials, uint32_t* cou
   block_sum<NV>(v);
   if (threadIdx.x == 0) {
 #pragma unroll
-    for (int i = 0; i < NV; ++i) partials[(size_t)i * gridDim.x + blockIdx.x] = v[i];
+    for (int i = 0; i < NV; ++i) partials[(size_t)i * block_count() + block_id()] = v[i];
     __threadfence();
     const uint32_t t = atomicAdd(counter, 1u);
-    amlast = (t == gridDim.x - 1);
+    amlast = (t == block_count() - 1);
   }
   __syncthreads();
   if (!amlast) return false;
@@ -78,8 +84,8 @@ __device__ inline bool grid_sum(double (&v)[NV], double* partials, uint32_t* cou
 #pragma unroll
   for (int i = 0; i < NV; ++i) {
     double s = 0.0;
-    for (uint32_t b = threadIdx.x; b < gridDim.x; b += FE_BLOCK)
-      s += __builtin_nontemporal_load(&partials[(size_t)i * gridDim.x + b]);
+    for (uint32_t b = threadIdx.x; b < block_count(); b += FE_BLOCK)
+      s += __builtin_nontemporal_load(&partials[(size_t)i * block_count() + b]);
     v[i] = s;
   }
   block_sum<NV>(v);
@@ -91,16 +97,16 @@ __device__ inline bool grid_max(double& v, double* partials, uint32_t* counter) 
   __shared__ int amlast;
   v = block_max(v);
   if (threadIdx.x == 0) {
-    partials[blockIdx.x] = v;
+    partials[block_id()] = v;
     __threadfence();
     const uint32_t t = atomicAdd(counter, 1u);
-    amlast = (t == gridDim.x - 1);
+    amlast = (t == block_count() - 1);
   }
   __syncthreads();
   if (!amlast) return false;
   __threadfence();
   double s = 0.0;
-  for (uint32_t b = threadIdx.x; b < gridDim.x; b += FE_BLOCK)
+  for (uint32_t b = threadIdx.x; b < block_count(); b += FE_BLOCK)
     s = fmax(s, __builtin_nontemporal_load(&partials[b]));
   v = block_max(s);
   if (threadIdx.x == 0) atomicExch(counter, 0u);
