@@ -34,28 +34,32 @@ def source_digest() -> str:
     return h.hexdigest()[:16]
 
 
-def _compile(src: str) -> str:
-    obj = os.path.join(OUT, os.path.splitext(src)[0] + ".o")
-    cmd = [HIPCC, *FLAGS, "-x", "hip", "-c", os.path.join(CSRC, src), "-o", obj]
+def _compile(src: str, out_dir: str = OUT, defines=()) -> str:
+    obj = os.path.join(out_dir, os.path.splitext(src)[0] + ".o")
+    cmd = [HIPCC, *FLAGS, *[f"-D{d}" for d in defines], "-x", "hip", "-c",
+           os.path.join(CSRC, src), "-o", obj]
     r = subprocess.run(cmd, capture_output=True, text=True)
     if r.returncode != 0:
         raise RuntimeError(f"hipcc failed for {src}:\n{r.stderr}")
     return obj
 
 
-def build(verbose: bool = False) -> str:
-    os.makedirs(OUT, exist_ok=True)
+def build(verbose: bool = False, out_lib: str = LIB, defines=()) -> str:
+    """Compiles every source and links out_lib; `defines` are extra -D macros
+    (tuning constants), empty for the library the package loads."""
+    out_dir = OUT if out_lib == LIB else os.path.splitext(out_lib)[0] + "_obj"
+    os.makedirs(out_dir, exist_ok=True)
     with cf.ThreadPoolExecutor(max_workers=min(8, len(SOURCES))) as ex:
-        objs = list(ex.map(_compile, SOURCES))
-    tmp = LIB + ".tmp"
+        objs = list(ex.map(lambda s: _compile(s, out_dir, defines), SOURCES))
+    tmp = out_lib + ".tmp"
     cmd = [HIPCC, "--offload-arch=gfx950", "-shared", "-fPIC", *objs, "-o", tmp]
     r = subprocess.run(cmd, capture_output=True, text=True)
     if r.returncode != 0:
         raise RuntimeError(f"link failed:\n{r.stderr}")
-    os.replace(tmp, LIB)
+    os.replace(tmp, out_lib)
     if verbose:
-        print(f"built {LIB}")
-    return LIB
+        print(f"built {out_lib}")
+    return out_lib
 
 
 if __name__ == "__main__":

@@ -106,50 +106,59 @@ __global__ void __launch_bounds__(TX* TY) kxu_tile_kernel(Grid g, int kc, const 
   auto node_ok = [&](int i, int j, int k) {
     return i >= 0 && i <= g.nx && j >= 0 && j <= g.ny && k >= 0 && k <= g.nz;
   };
-  // Loads node level k into su: own column plus the +1 ring.  Returns the own values.
-  auto load_level = [&](int k, T (&own)[3]) {
-    if (node_ok(ni, nj, k)) {
-      const int64_t n = ni + sx * nj + sxy * k;
-      own[0] = x[3 * n];
-      own[1] = x[3 * n + 1];
-      own[2] = x[3 * n + 2];
+  // Node values of one level held in registers: this thread's column and, for
+  // threads on the high edges of the tile, the extra column/row/corner that
+  // closes the 17 x 17 ring of the tile.
+  struct LevelRegs {
+    T own[3];
+    T ext[3][3];
+  };
+  const bool ex0 = tx == TX - 1, ex1 = ty == TY - 1, ex2 = ex0 && ex1;
+  auto fetch = [&](int i, int j, int k, T (&v)[3]) {
+    if (node_ok(i, j, k)) {
+      const int64_t n = i + sx * j + sxy * k;
+      v[0] = x[3 * n];
+      v[1] = x[3 * n + 1];
+      v[2] = x[3 * n + 2];
     } else {
-      own[0] = own[1] = own[2] = T(0);
+      v[0] = v[1] = v[2] = T(0);
     }
+  };
+  auto load_regs = [&](int k, LevelRegs& L) {
+    fetch(ni, nj, k, L.own);
+    if (ex0) fetch(I0 + TX, nj, k, L.ext[0]);
+    if (ex1) fetch(ni, J0 + TY, k, L.ext[1]);
+    if (ex2) fetch(I0 + TX, J0 + TY, k, L.ext[2]);
+  };
+  auto store_lds = [&](const LevelRegs& L) {
 #pragma unroll
-    for (int c = 0; c < 3; ++c) su[c][ty][tx] = own[c];
-    if (tx == TX - 1 || ty == TY - 1) {
-#pragma unroll
-      for (int e = 0; e < 3; ++e) {
-        // e = 0: column TX (right), e = 1: row TY (top), e = 2: the corner
-        const int ex = (e == 1) ? tx : TX, ey = (e == 0) ? ty : TY;
-        const bool want = (e == 0 && tx == TX - 1) || (e == 1 && ty == TY - 1) ||
-                          (e == 2 && tx == TX - 1 && ty == TY - 1);
-        if (want) {
-          const int i = I0 + ex, j = J0 + ey;
-          T v0 = T(0), v1 = T(0), v2 = T(0);
-          if (node_ok(i, j, k)) {
-            const int64_t n = i + sx * j + sxy * k;
-            v0 = x[3 * n];
-            v1 = x[3 * n + 1];
-            v2 = x[3 * n + 2];
-          }
-          su[0][ey][ex] = v0;
-          su[1][ey][ex] = v1;
-          su[2][ey][ex] = v2;
-        }
-      }
-    }
+    for (int c = 0; c < 3; ++c) su[c][ty][tx] = L.own[c];
+    if (ex0)
+      for (int c = 0; c < 3; ++c) su[c][ty][TX] = L.ext[0][c];
+    if (ex1)
+      for (int c = 0; c < 3; ++c) su[c][TY][tx] = L.ext[1][c];
+    if (ex2)
+      for (int c = 0; c < 3; ++c) su[c][TY][TX] = L.ext[2][c];
+  };
+  auto modulus = [&](int ek) -> T {
+    return (ecol && ek >= 0 && ek < g.nz) ? E[ni + (int64_t)g.nx * (nj + (int64_t)g.ny * ek)] : T(0);
   };
 
   T lo[4][3];      // corners (0,0) (1,0) (1,1) (0,1) of the brick's lower level
   T carry[4][3];   // contributions of the brick below to those corners
   T own_prev[3];   // this thread's node at the lower level
+  LevelRegs nxt;
+  T Enxt;
   {
-    load_level(K0 - 1, own_prev);
+    LevelRegs L0;
+    load_regs(K0 - 1, L0);
+    load_regs(K0, nxt);  // in flight during the prologue
+    Enxt = modulus(K0 - 1);
+    store_lds(L0);
     __syncthreads();
 #pragma unroll
     for (int c = 0; c < 3; ++c) {
+      own_prev[c] = L0.own[c];
       lo[0][c] = su[c][ty][tx];
       lo[1][c] = su[c][ty][tx + 1];
       lo[2][c] = su[c][ty + 1][tx + 1];
@@ -163,10 +172,13 @@ __global__ void __launch_bounds__(TX* TY) kxu_tile_kernel(Grid g, int kc, const 
   for (int s = 0; s <= kc; ++s) {
     const int ek = K0 - 1 + s;  // brick layer between node levels ek and ek + 1
     if (ek >= g.nz + 1) break;  // uniform over the workgroup
-    T own[3];
-    load_level(ek + 1, own);
-    T Ee = T(0);
-    if (ecol && ek >= 0 && ek < g.nz) Ee = E[ni + (int64_t)g.nx * (nj + (int64_t)g.ny * ek)];
+    const LevelRegs cur = nxt;
+    const T Ee = Enxt;
+    store_lds(cur);
+    if (s < kc) {  // prefetch the next level while this one is computed
+      load_regs(ek + 2, nxt);
+      Enxt = modulus(ek + 1);
+    }
     __syncthreads();
 
     T v[3][8];
@@ -176,7 +188,7 @@ __global__ void __launch_bounds__(TX* TY) kxu_tile_kernel(Grid g, int kc, const 
       v[c][1] = lo[1][c];
       v[c][2] = lo[2][c];
       v[c][3] = lo[3][c];
-      v[c][4] = own[c];
+      v[c][4] = cur.own[c];
       v[c][5] = su[c][ty][tx + 1];
       v[c][6] = su[c][ty + 1][tx + 1];
       v[c][7] = su[c][ty + 1][tx];
@@ -226,7 +238,7 @@ __global__ void __launch_bounds__(TX* TY) kxu_tile_kernel(Grid g, int kc, const 
       }
     }
 #pragma unroll
-    for (int c = 0; c < 3; ++c) own_prev[c] = own[c];
+    for (int c = 0; c < 3; ++c) own_prev[c] = cur.own[c];
   }
   if (MODE == 0) return;
   double vv[1] = {dot};
@@ -257,7 +269,10 @@ WK<T> scaled_wk(const WalshK& w, double h) {
 
 }  // namespace
 
-static int kxu_levels_per_block() { return 8; }
+#ifndef FE_KXU_KC
+#define FE_KXU_KC 8  // node levels one workgroup marches through
+#endif
+static int kxu_levels_per_block() { return FE_KXU_KC; }
 
 static dim3 kxu_grid(const Grid& g, int kc) {
   return dim3((unsigned)((g.nx + 1 + OWN - 1) / OWN), (unsigned)((g.ny + 1 + OWN - 1) / OWN),

@@ -13,7 +13,7 @@ import os
 import torch
 
 _PKG = os.path.dirname(os.path.abspath(__file__))
-LIB_PATH = os.path.join(_PKG, "libfe_hip.so")
+LIB_PATH = os.environ.get("FE_HIP_LIB") or os.path.join(_PKG, "libfe_hip.so")
 
 FE_OK, FE_EINVAL, FE_ENOMEM, FE_EDEVICE, FE_ENOTCONV, FE_EBREAKDOWN = 0, -1, -2, -3, -4, -5
 PRECISION = {"fp64": 0, "fp32_ir": 1, "bf16_ir": 2}
