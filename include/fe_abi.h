@@ -139,6 +139,13 @@ FE_API fe_status fe_filter(fe_problem* p, const double* in, double* out, int32_t
 FE_API fe_status oc_update(fe_problem* p, const double* x, const double* dcx, const double* dv,
                     double volfrac, double move, double* x_new, double* change);
 
+/* Multigrid smoothing parameters (used when precond = FE_PRECOND_GMG):
+ * nu damped-Jacobi sweeps before and after each coarse correction (1..8),
+ * coarse_sweeps sweeps on the coarsest level (1..10000), damping omega in
+ * (0, 1).  Defaults: 1, 30, 0.6.  The V-cycle stays symmetric and linear, so
+ * plain CG applies. */
+FE_API fe_status fe_set_mg_params(fe_problem* p, int32_t nu, int32_t coarse_sweeps, double omega);
+
 /* Timing of the dominant kernel (matrix-free K*u): when on, every K*u launch
  * is bracketed by HIP events on the handle's stream; fe_kernel_stats
  * returns the number of launches and their summed duration in ms since the

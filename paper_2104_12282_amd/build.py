@@ -14,7 +14,7 @@ OUT = os.path.join(PKG, "_build")
 LIB = os.path.join(PKG, "libfe_hip.so")
 HIPCC = os.environ.get("HIPCC", "/opt/rocm/bin/hipcc")
 
-SOURCES = ["fe_host.cpp", "fe_abi.cpp", "fe_kernels.hip", "fe_kxu.hip"]
+SOURCES = ["fe_host.cpp", "fe_abi.cpp", "fe_kernels.hip", "fe_kxu.hip", "fe_mg.hip"]
 # Packed-FP32 instructions are switched off for every device pass.
 FLAGS = ["-O3", "-std=c++17", "--offload-arch=gfx950", "-fPIC", "-Wall",
          "-Wno-unused-function", "-fvisibility=hidden", "-Xclang", "-target-feature", "-Xclang", "-packed-fp32-ops",

@@ -189,17 +189,25 @@ fe_status prepare_operator(fe_problem* p, const double* rho) {
   return FE_OK;
 }
 
-constexpr int kChunk = 24;  // CG iterations enqueued between host checks
+constexpr int kChunk = 24;    // Jacobi-PCG iterations enqueued between host checks
+constexpr int kChunkMG = 4;   // multigrid-PCG iterations enqueued between host checks
 
-// Preconditioned CG on level 0 with vectors of type T: solves K x = b from the
-// state prepared by cg_init (r, p set).  Returns the CgState at exit.
+// Preconditioned CG on level 0 with vectors of type T, from the state set by
+// cg_start.  Returns the CgState at exit.
 template <typename T>
 fe_status cg_loop(fe_problem* p, T* x, T* r, T* pv, T* q, CgState* out) {
+  const bool mg = p->nlev > 1;
+  T* z = mg ? static_cast<T*>(p->L[0].mg_z) : nullptr;
+  const int chunk = mg ? kChunkMG : kChunk;
   for (;;) {
-    for (int it = 0; it < kChunk; ++it) {
+    for (int it = 0; it < chunk; ++it) {
       HIP_TRY(launch_kxu<T>(p, 0, pv, q, p->st));
-      HIP_TRY(launch_cg_update<T>(p, x, r, pv, q, p->st, 0));
-      HIP_TRY(launch_cg_direction<T>(p, r, nullptr, pv, p->st));
+      HIP_TRY(launch_cg_update<T>(p, x, r, pv, q, p->st, mg ? 1 : 0));
+      if (mg) {
+        HIP_TRY(launch_vcycle<T>(p, 0, r, z));
+        HIP_TRY(launch_cg_rz<T>(p, r, z, p->st));
+      }
+      HIP_TRY(launch_cg_direction<T>(p, r, z, pv, p->st));
     }
     fe_status s = read_state(p, out);
     if (s != FE_OK) return s;
@@ -207,12 +215,27 @@ fe_status cg_loop(fe_problem* p, T* x, T* r, T* pv, T* q, CgState* out) {
   }
 }
 
+// r = b - Kx (Kx null: x = 0), first preconditioned direction, convergence
+// test of the start point.
+template <typename T>
+fe_status cg_start(fe_problem* p, const T* b, const T* Kx, T* r, T* pv, CgState* hs) {
+  const bool mg = p->nlev > 1;
+  HIP_TRY(launch_cg_init<T>(p, b, Kx, r, pv, p->st, mg ? 1 : 0));
+  if (mg) {
+    T* z = static_cast<T*>(p->L[0].mg_z);
+    HIP_TRY(launch_fill<T>(p, pv, p->L[0].g.ndof, T(0)));
+    HIP_TRY(launch_vcycle<T>(p, 0, r, z));
+    HIP_TRY(launch_cg_rz<T>(p, r, z, p->st));
+    HIP_TRY(launch_cg_direction<T>(p, r, z, pv, p->st));
+  }
+  return read_state(p, hs);
+}
+
 fe_status solve_fp64(fe_problem* p, double* u, double rtol, int max_iters, fe_solve_info* info) {
   HIP_TRY(launch_kxu<double>(p, 0, u, p->q64, nullptr));
   HIP_TRY(launch_cg_state_init(p, p->st, rtol, max_iters));
-  HIP_TRY(launch_cg_init<double>(p, p->f, p->q64, p->r64, p->p64, p->st, 0));
   CgState hs;
-  fe_status s = read_state(p, &hs);
+  fe_status s = cg_start<double>(p, p->f, p->q64, p->r64, p->p64, &hs);
   if (s != FE_OK) return s;
   if (!hs.done) {
     s = cg_loop<double>(p, u, p->r64, p->p64, p->q64, &hs);
@@ -256,9 +279,8 @@ fe_status solve_ir(fe_problem* p, double* u, double rtol, int max_iters, fe_solv
     HIP_TRY(launch_to32_scaled(p, p->r64, p->r32, p->scal + 2 * SLOT_RR));
     HIP_TRY(launch_fill<float>(p, p->x32, p->L[0].g.ndof, 0.0f));
     HIP_TRY(launch_cg_state_init(p, p->st, itol, max_iters - total));
-    HIP_TRY(launch_cg_init<float>(p, p->r32, nullptr, p->r32, p->p32, p->st, 0));
     CgState hs;
-    s = read_state(p, &hs);
+    s = cg_start<float>(p, p->r32, nullptr, p->r32, p->p32, &hs);
     if (s != FE_OK) return s;
     if (!hs.done) {
       s = cg_loop<float>(p, p->x32, p->r32, p->p32, p->q32, &hs);
@@ -505,6 +527,18 @@ extern "C" fe_status oc_update(fe_problem* p, const double* x, const double* dcx
     return FE_EINVAL;
   }
   HIP_TRY(launch_oc(p, x, dcx, dv, volfrac, move, x_new, change));
+  return FE_OK;
+}
+
+extern "C" fe_status fe_set_mg_params(fe_problem* p, int32_t nu, int32_t coarse_sweeps, double omega) {
+  CHECK_HANDLE(p);
+  if (nu < 1 || nu > 8 || coarse_sweeps < 1 || coarse_sweeps > 10000 || !(omega > 0.0 && omega < 1.0)) {
+    fe_set_error("need 1 <= nu <= 8, 1 <= coarse_sweeps <= 10000, 0 < omega < 1");
+    return FE_EINVAL;
+  }
+  p->mg_nu = nu;
+  p->mg_coarse_sweeps = coarse_sweeps;
+  p->mg_omega = omega;
   return FE_OK;
 }
 

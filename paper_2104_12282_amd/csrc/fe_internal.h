@@ -103,6 +103,11 @@ struct fe_problem {
   double* scal = nullptr;      // 64 device scalars for small results
   double* oc = nullptr;        // OC search state
 
+  // geometric multigrid parameters
+  int mg_nu = 1;               // damped Jacobi sweeps before and after the coarse correction
+  int mg_coarse_sweeps = 30;   // sweeps on the coarsest level
+  double mg_omega = 0.6;       // Jacobi damping
+
   KStats kst;
 };
 
@@ -127,14 +132,20 @@ hipError_t launch_mask_vec(fe_problem* p, int lev, T* v);
 template <typename T>
 hipError_t launch_kxu(fe_problem* p, int lev, const T* x, T* y, CgState* st);
 
-// The tiled kernel behind launch_kxu: mode 0 y = Kx, 1 CG step (st), 2 y = b - Kx
-// with ||y||^2 -> out[0] (float64 only).
+// The tiled kernel behind launch_kxu: mode 0 y = Kx, 1 CG step (st), 2 y = b64 - Kx
+// with ||y||^2 -> out[0] (float64 only), 3 damped Jacobi y = x + omega D^-1 (bT - Kx),
+// 4 y = bT - Kx.
 template <typename T>
 hipError_t launch_kxu_tile(fe_problem* p, int lev, const T* x, const T* E, T* y, CgState* st, int mode,
-                           const double* b, double* out);
+                           const double* b64, double* out, const T* bT = nullptr,
+                           const T* invd = nullptr, double omega = 0.0);
 int64_t kxu_tile_blocks(const Grid& g);
 // Node-centric dense-Ke reference kernel (float64), kept as a second implementation.
 hipError_t launch_kxu_dense64(fe_problem* p, const double* x, double* y);
+
+// z = V(r): one symmetric multigrid V-cycle from level l down.
+template <typename T>
+hipError_t launch_vcycle(fe_problem* p, int l, const T* r, T* z);
 
 // CG helpers (T = float or double vectors, float64 reductions)
 template <typename T>

@@ -83,14 +83,26 @@ __device__ inline void apply_S(const WK<T>& k, const T (&t)[3][8], T (&s)[3][8])
   s[Z][6] = k.J * t[Z][6];
 }
 
+// Epilogue operands of the modes below.
+template <typename T>
+struct Epi {
+  const double* b64;  // MODE 2
+  const T* bT;        // MODES 3, 4
+  const T* invd;      // MODE 3: inverse Jacobi diagonal per node
+  T omega;            // MODE 3: damping
+};
+
 // MODE 0: y = Kx.  MODE 1: CG step, pq = x^T y, alpha = rz / pq.
 // MODE 2: y = b - Kx (float64 only), ||y||^2 -> out[0].
+// MODE 3: damped Jacobi sweep y = x + omega D^-1 (b - Kx).
+// MODE 4: y = b - Kx.
+// y must not alias x (other workgroups read x around their tiles).
 template <typename T, int MODE>
 __global__ void __launch_bounds__(TX* TY) kxu_tile_kernel(Grid g, int kc, const T* __restrict__ x,
                                                          const T* __restrict__ E,
                                                          const uint8_t* __restrict__ nmask, WK<T> wk,
-                                                         T* __restrict__ y, const double* __restrict__ b,
-                                                         CgState* st, double* partials, double* out) {
+                                                         T* __restrict__ y, Epi<T> ep, CgState* st,
+                                                         double* partials, double* out) {
   if (MODE == 1 && st->done) return;
   __shared__ T su[3][TY + 1][TX + 1];  // node values of the current upper level
   __shared__ T sy[9][TY][TX];          // level partials of corners (1,0), (1,1), (0,1)
@@ -227,12 +239,17 @@ __global__ void __launch_bounds__(TX* TY) kxu_tile_kernel(Grid g, int kc, const 
 #pragma unroll
       for (int c = 0; c < 3; ++c) {
         T v2 = p0[c] + sy[0 + c][ty][tx - 1] + sy[3 + c][ty - 1][tx - 1] + sy[6 + c][ty - 1][tx];
-        if ((m >> c) & 1) v2 = T(0);
+        const bool fx = (m >> c) & 1;
+        if (fx) v2 = T(0);
         if (MODE == 2) {
-          v2 = ((m >> c) & 1) ? T(0) : (T)(b[3 * n + c] - (double)v2);
+          v2 = fx ? T(0) : (T)(ep.b64[3 * n + c] - (double)v2);
           dot += (double)v2 * (double)v2;
         } else if (MODE == 1) {
           dot += (double)own_prev[c] * (double)v2;
+        } else if (MODE == 3) {
+          v2 = fx ? T(0) : own_prev[c] + ep.omega * ep.invd[n] * (ep.bT[3 * n + c] - v2);
+        } else if (MODE == 4) {
+          v2 = fx ? T(0) : ep.bT[3 * n + c] - v2;
         }
         y[3 * n + c] = v2;
       }
@@ -240,7 +257,7 @@ __global__ void __launch_bounds__(TX* TY) kxu_tile_kernel(Grid g, int kc, const 
 #pragma unroll
     for (int c = 0; c < 3; ++c) own_prev[c] = cur.own[c];
   }
-  if (MODE == 0) return;
+  if (MODE == 0 || MODE >= 3) return;
   double vv[1] = {dot};
   const bool last = grid_sum<1>(vv, partials, MODE == 1 ? &st->counter[0] : (uint32_t*)(out + 1));
   if (last && threadIdx.x == 0) {
@@ -286,24 +303,43 @@ int64_t kxu_tile_blocks(const Grid& g) {
 
 template <typename T>
 hipError_t launch_kxu_tile(fe_problem* p, int lev, const T* x, const T* E, T* y, CgState* st, int mode,
-                           const double* b, double* out) {
+                           const double* b64, double* out, const T* bT, const T* invd, double omega) {
   const Grid g = p->L[lev].g;
   const int kc = kxu_levels_per_block();
   const dim3 grid = kxu_grid(g, kc);
   const WK<T> wk = scaled_wk<T>(p->wk, p->L[lev].h);
-  if (mode == 1)
-    hipLaunchKernelGGL((kxu_tile_kernel<T, 1>), grid, dim3(TX * TY), 0, p->stream, g, kc, x, E,
-                       p->L[lev].nmask, wk, y, b, st, p->partials, out);
-  else if (mode == 2)
-    hipLaunchKernelGGL((kxu_tile_kernel<T, 2>), grid, dim3(TX * TY), 0, p->stream, g, kc, x, E,
-                       p->L[lev].nmask, wk, y, b, st, p->partials, out);
-  else
-    hipLaunchKernelGGL((kxu_tile_kernel<T, 0>), grid, dim3(TX * TY), 0, p->stream, g, kc, x, E,
-                       p->L[lev].nmask, wk, y, b, st, p->partials, out);
+  Epi<T> ep;
+  ep.b64 = b64;
+  ep.bT = bT;
+  ep.invd = invd;
+  ep.omega = (T)omega;
+  const uint8_t* nm = p->L[lev].nmask;
+  switch (mode) {
+    case 1:
+      hipLaunchKernelGGL((kxu_tile_kernel<T, 1>), grid, dim3(TX * TY), 0, p->stream, g, kc, x, E, nm, wk,
+                         y, ep, st, p->partials, out);
+      break;
+    case 2:
+      hipLaunchKernelGGL((kxu_tile_kernel<T, 2>), grid, dim3(TX * TY), 0, p->stream, g, kc, x, E, nm, wk,
+                         y, ep, st, p->partials, out);
+      break;
+    case 3:
+      hipLaunchKernelGGL((kxu_tile_kernel<T, 3>), grid, dim3(TX * TY), 0, p->stream, g, kc, x, E, nm, wk,
+                         y, ep, st, p->partials, out);
+      break;
+    case 4:
+      hipLaunchKernelGGL((kxu_tile_kernel<T, 4>), grid, dim3(TX * TY), 0, p->stream, g, kc, x, E, nm, wk,
+                         y, ep, st, p->partials, out);
+      break;
+    default:
+      hipLaunchKernelGGL((kxu_tile_kernel<T, 0>), grid, dim3(TX * TY), 0, p->stream, g, kc, x, E, nm, wk,
+                         y, ep, st, p->partials, out);
+  }
   return hipGetLastError();
 }
 
 template hipError_t launch_kxu_tile<double>(fe_problem*, int, const double*, const double*, double*,
-                                            CgState*, int, const double*, double*);
+                                            CgState*, int, const double*, double*, const double*,
+                                            const double*, double);
 template hipError_t launch_kxu_tile<float>(fe_problem*, int, const float*, const float*, float*, CgState*,
-                                           int, const double*, double*);
+                                           int, const double*, double*, const float*, const float*, double);

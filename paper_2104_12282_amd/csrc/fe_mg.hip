@@ -1,0 +1,166 @@
+// Geometric multigrid pieces: grid transfers and the first Jacobi sweep.
+//
+// Level l+1 halves every grid dimension of level l (element edge doubles).
+// Prolongation P is trilinear interpolation from coarse to fine nodes, with
+// the rows and columns of fixed dofs removed; restriction is its transpose,
+// which keeps the V-cycle symmetric so it can precondition CG.
+#include <hip/hip_runtime.h>
+
+#include "fe_internal.h"
+
+namespace {
+
+inline int nblocks(int64_t n) {
+  int64_t g = (n + FE_BLOCK - 1) / FE_BLOCK;
+  return (int)(g < 1 ? 1 : g);
+}
+
+// z = omega D^-1 r (the first sweep from z = 0; fixed dofs have r = 0).
+template <typename T>
+__global__ void __launch_bounds__(FE_BLOCK) jacobi0_kernel(int64_t ndof, const T* __restrict__ r,
+                                                           const T* __restrict__ invd, T omega,
+                                                           T* __restrict__ z) {
+  const int64_t d = blockIdx.x * (int64_t)FE_BLOCK + threadIdx.x;
+  if (d < ndof) z[d] = omega * invd[d / 3] * r[d];
+}
+
+// r_c = P^T t_f: coarse node (I,J,K) collects the fine nodes 2I+a, 2J+b, 2K+c
+// (a, b, c in {-1, 0, 1}) with weight prod (a == 0 ? 1 : 1/2).
+template <typename T>
+__global__ void __launch_bounds__(FE_BLOCK) restrict_kernel(Grid fg, Grid cg, const T* __restrict__ tf,
+                                                            const uint8_t* __restrict__ cmask,
+                                                            T* __restrict__ rc) {
+  const int64_t n = blockIdx.x * (int64_t)FE_BLOCK + threadIdx.x;
+  if (n >= cg.nnode) return;
+  const int I = (int)(n % (cg.nx + 1)), J = (int)((n / (cg.nx + 1)) % (cg.ny + 1)),
+            K = (int)(n / ((int64_t)(cg.nx + 1) * (cg.ny + 1)));
+  const int64_t fsx = fg.nx + 1, fsxy = (int64_t)(fg.nx + 1) * (fg.ny + 1);
+  T acc[3] = {T(0), T(0), T(0)};
+  for (int c = -1; c <= 1; ++c) {
+    const int k = 2 * K + c;
+    if (k < 0 || k > fg.nz) continue;
+    const T wc = c ? T(0.5) : T(1);
+    for (int b = -1; b <= 1; ++b) {
+      const int j = 2 * J + b;
+      if (j < 0 || j > fg.ny) continue;
+      const T wb = wc * (b ? T(0.5) : T(1));
+      for (int a = -1; a <= 1; ++a) {
+        const int i = 2 * I + a;
+        if (i < 0 || i > fg.nx) continue;
+        const T w = wb * (a ? T(0.5) : T(1));
+        const int64_t f = i + fsx * j + fsxy * k;
+        acc[0] += w * tf[3 * f];
+        acc[1] += w * tf[3 * f + 1];
+        acc[2] += w * tf[3 * f + 2];
+      }
+    }
+  }
+  const uint8_t m = cmask[n];
+#pragma unroll
+  for (int q = 0; q < 3; ++q) rc[3 * n + q] = ((m >> q) & 1) ? T(0) : acc[q];
+}
+
+// out_f = z_f + P z_c (out may alias z: each thread touches only its own node).
+template <typename T>
+__global__ void __launch_bounds__(FE_BLOCK) prolong_add_kernel(Grid fg, Grid cg, const T* zf,
+                                                               const T* __restrict__ zc,
+                                                               const uint8_t* __restrict__ fmask, T* out) {
+  const int64_t n = blockIdx.x * (int64_t)FE_BLOCK + threadIdx.x;
+  if (n >= fg.nnode) return;
+  const int i = (int)(n % (fg.nx + 1)), j = (int)((n / (fg.nx + 1)) % (fg.ny + 1)),
+            k = (int)(n / ((int64_t)(fg.nx + 1) * (fg.ny + 1)));
+  // coarse neighbours along each axis: one (even index) or two (odd index)
+  const int i0 = i >> 1, i1 = (i + 1) >> 1, j0 = j >> 1, j1 = (j + 1) >> 1, k0 = k >> 1, k1 = (k + 1) >> 1;
+  const T wi = (i & 1) ? T(0.5) : T(1), wj = (j & 1) ? T(0.5) : T(1), wk = (k & 1) ? T(0.5) : T(1);
+  const int64_t csx = cg.nx + 1, csxy = (int64_t)(cg.nx + 1) * (cg.ny + 1);
+  T acc[3] = {T(0), T(0), T(0)};
+  const int ii[2] = {i0, i1}, jj[2] = {j0, j1}, kk[2] = {k0, k1};
+  const int ni = (i & 1) ? 2 : 1, nj = (j & 1) ? 2 : 1, nk = (k & 1) ? 2 : 1;
+  for (int c = 0; c < nk; ++c)
+    for (int b = 0; b < nj; ++b)
+      for (int a = 0; a < ni; ++a) {
+        const int64_t q = ii[a] + csx * jj[b] + csxy * kk[c];
+        const T w = wi * wj * wk;
+        acc[0] += w * zc[3 * q];
+        acc[1] += w * zc[3 * q + 1];
+        acc[2] += w * zc[3 * q + 2];
+      }
+  const uint8_t m = fmask[n];
+#pragma unroll
+  for (int q = 0; q < 3; ++q) out[3 * n + q] = ((m >> q) & 1) ? T(0) : zf[3 * n + q] + acc[q];
+}
+
+template <typename T>
+const T* lev_invd(const Level& L);
+template <>
+const double* lev_invd<double>(const Level& L) { return L.invd64; }
+template <>
+const float* lev_invd<float>(const Level& L) { return L.invd32; }
+template <typename T>
+const T* lev_E(const Level& L);
+template <>
+const double* lev_E<double>(const Level& L) { return L.E64; }
+template <>
+const float* lev_E<float>(const Level& L) { return L.E32; }
+
+// n damped Jacobi sweeps from z = 0 on level l, result in z (t is scratch).
+template <typename T>
+hipError_t jacobi_sweeps(fe_problem* p, int l, const T* r, T* z, T* t, int n) {
+  const Level& L = p->L[l];
+  const double om = p->mg_omega;
+  T* a = (n % 2) ? z : t;  // first target chosen so the last sweep lands in z
+  T* b = (n % 2) ? t : z;
+  hipLaunchKernelGGL(jacobi0_kernel<T>, dim3(nblocks(L.g.ndof)), dim3(FE_BLOCK), 0, p->stream, L.g.ndof, r,
+                     lev_invd<T>(L), (T)om, a);
+  hipError_t e = hipGetLastError();
+  for (int s = 1; s < n && e == hipSuccess; ++s) {
+    e = launch_kxu_tile<T>(p, l, a, lev_E<T>(L), b, nullptr, 3, nullptr, nullptr, r, lev_invd<T>(L), om);
+    T* tmp = a;
+    a = b;
+    b = tmp;
+  }
+  return e;
+}
+
+}  // namespace
+
+// z = V(r): one symmetric V-cycle on levels l .. nlev-1 (pre- and
+// post-smoothing with mg_nu damped Jacobi sweeps, mg_coarse sweeps on the
+// coarsest level).
+template <typename T>
+hipError_t launch_vcycle(fe_problem* p, int l, const T* r, T* z) {
+  const Level& L = p->L[l];
+  T* t = static_cast<T*>(L.mg_t);
+  if (l == p->nlev - 1) return jacobi_sweeps<T>(p, l, r, z, t, p->mg_coarse_sweeps);
+  hipError_t e = jacobi_sweeps<T>(p, l, r, z, t, p->mg_nu);
+  if (e != hipSuccess) return e;
+  // t = r - K z, restricted to the next level's right-hand side
+  e = launch_kxu_tile<T>(p, l, z, lev_E<T>(L), t, nullptr, 4, nullptr, nullptr, r, nullptr, 0.0);
+  if (e != hipSuccess) return e;
+  const Level& C = p->L[l + 1];
+  T* rc = static_cast<T*>(C.mg_r);
+  T* zc = static_cast<T*>(C.mg_z);
+  hipLaunchKernelGGL(restrict_kernel<T>, dim3(nblocks(C.g.nnode)), dim3(FE_BLOCK), 0, p->stream, L.g, C.g, t,
+                     C.nmask, rc);
+  if ((e = hipGetLastError()) != hipSuccess) return e;
+  if ((e = launch_vcycle<T>(p, l + 1, rc, zc)) != hipSuccess) return e;
+  // post-smoothing, arranged so the last sweep writes z
+  const int nu = p->mg_nu;
+  T* a = (nu % 2) ? t : z;
+  hipLaunchKernelGGL(prolong_add_kernel<T>, dim3(nblocks(L.g.nnode)), dim3(FE_BLOCK), 0, p->stream, L.g, C.g,
+                     z, zc, L.nmask, a);
+  if ((e = hipGetLastError()) != hipSuccess) return e;
+  T* b = (a == t) ? z : t;
+  for (int s = 0; s < nu; ++s) {
+    e = launch_kxu_tile<T>(p, l, a, lev_E<T>(L), b, nullptr, 3, nullptr, nullptr, r, lev_invd<T>(L),
+                           p->mg_omega);
+    if (e != hipSuccess) return e;
+    T* tmp = a;
+    a = b;
+    b = tmp;
+  }
+  return hipSuccess;
+}
+
+template hipError_t launch_vcycle<double>(fe_problem*, int, const double*, double*);
+template hipError_t launch_vcycle<float>(fe_problem*, int, const float*, float*);

@@ -23,8 +23,8 @@ STATUS_NAME = {0: "FE_OK", -1: "FE_EINVAL", -2: "FE_ENOMEM", -3: "FE_EDEVICE",
 
 # Every entry point declared in include/fe_abi.h.
 ABI_SYMBOLS = ("fe_workspace_size", "fe_setup", "fe_apply_K", "fe_solve", "fe_sensitivity",
-               "fe_filter", "oc_update", "fe_set_profiling", "fe_kernel_stats", "fe_destroy",
-               "fe_last_error")
+               "fe_filter", "oc_update", "fe_set_mg_params", "fe_set_profiling", "fe_kernel_stats",
+               "fe_destroy", "fe_last_error")
 
 
 class FEError(RuntimeError):
@@ -67,6 +67,7 @@ def load_library() -> C.CDLL:
     lib.fe_sensitivity.argtypes = [P, P, P, P, P]
     lib.fe_filter.argtypes = [P, P, P, I32]
     lib.oc_update.argtypes = [P, P, P, P, D, D, P, P]
+    lib.fe_set_mg_params.argtypes = [P, I32, I32, D]
     lib.fe_set_profiling.argtypes = [P, I32]
     lib.fe_kernel_stats.argtypes = [P, I32, C.POINTER(I64), C.POINTER(D), C.POINTER(D)]
     lib.fe_destroy.argtypes = [P]
@@ -74,7 +75,7 @@ def load_library() -> C.CDLL:
     lib.fe_last_error.argtypes = []
     lib.fe_last_error.restype = C.c_char_p
     for name in ("fe_setup", "fe_apply_K", "fe_solve", "fe_sensitivity", "fe_filter",
-                 "oc_update", "fe_set_profiling", "fe_kernel_stats"):
+                 "oc_update", "fe_set_mg_params", "fe_set_profiling", "fe_kernel_stats"):
         getattr(lib, name).restype = C.c_int
     _lib = lib
     return lib
@@ -183,6 +184,9 @@ class Problem:
         _check(load_library().oc_update(self._h, _ptr(x), _ptr(dcx), _ptr(dv), volfrac, move,
                                         _ptr(xn), _ptr(ch)))
         return xn, ch
+
+    def set_mg_params(self, nu=1, coarse_sweeps=30, omega=0.6):
+        _check(load_library().fe_set_mg_params(self._h, nu, coarse_sweeps, omega))
 
     def set_profiling(self, on: bool):
         _check(load_library().fe_set_profiling(self._h, 1 if on else 0))

@@ -198,3 +198,34 @@ def test_breakdown_on_nan_density():
     with pytest.raises(fe.FEError) as ei:
         prob.solve(T(rho), rtol=1e-8, max_iters=100)
     assert ei.value.status == fe.FE_EBREAKDOWN
+
+
+@pytest.mark.parametrize("precision", ["fp64", "fp32_ir"])
+@pytest.mark.parametrize("grid,levels", [((24, 12, 12), 3), ((16, 8, 8), 2), ((32, 16, 8), 4)])
+def test_gmg_solve_parity(Ke, grid, levels, precision):
+    nx, ny, nz = grid
+    rho = synth.density_around(nx, ny, nz, 3)
+    f = synth.cantilever_edge_load(nx, ny, nz)
+    u_ref = O.solve_direct(nx, ny, nz, O.simp_modulus(rho), Ke, f, O.clamp_x0_fixed(nx, ny, nz))
+    c_ref = O.compliance(f, u_ref)
+    dc_ref = O.sensitivity(nx, ny, nz, Ke, rho, u_ref)
+    prob = _problem(nx, ny, nz, precision=precision, precond="gmg", mg_levels=levels)
+    u, info = prob.solve(T(rho), rtol=1e-10)
+    dc, c = prob.sensitivity(T(rho), u)
+    assert info["rel_res"] <= 1e-10
+    assert abs(float(N(c)[0]) - c_ref) / c_ref <= 1e-6
+    assert np.abs(N(dc) - dc_ref).max() / np.abs(dc_ref).max() <= 1e-5
+    # the multigrid preconditioner must beat Jacobi on the same system
+    jac = _problem(nx, ny, nz, precision=precision)
+    _, info_j = jac.solve(T(rho), rtol=1e-10)
+    assert info["iters"] < info_j["iters"]
+
+
+def test_gmg_params_validation():
+    prob = _problem(16, 8, 8, precond="gmg", mg_levels=3)
+    with pytest.raises(fe.FEError):
+        prob.set_mg_params(nu=0)
+    prob.set_mg_params(nu=2, coarse_sweeps=10, omega=0.5)
+    rho = synth.density_around(16, 8, 8, 1)
+    _, info = prob.solve(T(rho), rtol=1e-9)
+    assert info["rel_res"] <= 1e-9
