@@ -142,8 +142,10 @@ FE_API fe_status oc_update(fe_problem* p, const double* x, const double* dcx, co
 /* Multigrid smoothing parameters (used when precond = FE_PRECOND_GMG):
  * nu damped-Jacobi sweeps before and after each coarse correction (1..8),
  * coarse_sweeps sweeps on the coarsest level (1..10000), damping omega in
- * (0, 1).  Defaults: 1, 30, 0.6.  The V-cycle stays symmetric and linear, so
- * plain CG applies. */
+ * (0, 1).  Defaults: 1, 30, 0.35.  The V-cycle is symmetric and linear, so
+ * plain CG applies; it is also positive definite while omega stays below
+ * 2 / 5.32 (5.32 = largest eigenvalue of diag(Ke)^-1 Ke for nu = 0.3, which
+ * bounds that of D^-1 K for any density field). */
 FE_API fe_status fe_set_mg_params(fe_problem* p, int32_t nu, int32_t coarse_sweeps, double omega);
 
 /* Timing of the dominant kernel (matrix-free K*u): when on, every K*u launch

@@ -106,7 +106,7 @@ struct fe_problem {
   // geometric multigrid parameters
   int mg_nu = 1;               // damped Jacobi sweeps before and after the coarse correction
   int mg_coarse_sweeps = 30;   // sweeps on the coarsest level
-  double mg_omega = 0.6;       // Jacobi damping
+  double mg_omega = 0.35;      // Jacobi damping: below 2 / lambda_max(D^-1 Ke) = 2 / 5.32
 
   KStats kst;
 };
