@@ -190,7 +190,7 @@ fe_status prepare_operator(fe_problem* p, const double* rho) {
 }
 
 constexpr int kChunk = 24;    // Jacobi-PCG iterations enqueued between host checks
-constexpr int kChunkMG = 4;   // multigrid-PCG iterations enqueued between host checks
+constexpr int kChunkMG = 8;   // multigrid-PCG iterations enqueued between host checks
 
 // Preconditioned CG on level 0 with vectors of type T, from the state set by
 // cg_start.  Returns the CgState at exit.
@@ -203,10 +203,7 @@ fe_status cg_loop(fe_problem* p, T* x, T* r, T* pv, T* q, CgState* out) {
     for (int it = 0; it < chunk; ++it) {
       HIP_TRY(launch_kxu<T>(p, 0, pv, q, p->st));
       HIP_TRY(launch_cg_update<T>(p, x, r, pv, q, p->st, mg ? 1 : 0));
-      if (mg) {
-        HIP_TRY(launch_vcycle<T>(p, 0, r, z));
-        HIP_TRY(launch_cg_rz<T>(p, r, z, p->st));
-      }
+      if (mg) HIP_TRY(launch_vcycle<T>(p, 0, r, z, p->st, true));
       HIP_TRY(launch_cg_direction<T>(p, r, z, pv, p->st));
     }
     fe_status s = read_state(p, out);
@@ -224,8 +221,7 @@ fe_status cg_start(fe_problem* p, const T* b, const T* Kx, T* r, T* pv, CgState*
   if (mg) {
     T* z = static_cast<T*>(p->L[0].mg_z);
     HIP_TRY(launch_fill<T>(p, pv, p->L[0].g.ndof, T(0)));
-    HIP_TRY(launch_vcycle<T>(p, 0, r, z));
-    HIP_TRY(launch_cg_rz<T>(p, r, z, p->st));
+    HIP_TRY(launch_vcycle<T>(p, 0, r, z, p->st, true));
     HIP_TRY(launch_cg_direction<T>(p, r, z, pv, p->st));
   }
   return read_state(p, hs);

@@ -11,7 +11,7 @@
 
 #define FE_BLOCK 256
 #define FE_MAX_LEVELS 6
-#define FE_RED_GRID 1024  // grid of the reduction kernels (partials per slot)
+#define FE_RED_GRID 4096  // grid of the reduction kernels (partials per slot)
 
 // Structured brick grid of one multigrid level.
 struct Grid {
@@ -143,9 +143,11 @@ int64_t kxu_tile_blocks(const Grid& g);
 // Node-centric dense-Ke reference kernel (float64), kept as a second implementation.
 hipError_t launch_kxu_dense64(fe_problem* p, const double* x, double* y);
 
-// z = V(r): one symmetric multigrid V-cycle from level l down.
+// z = V(r): one symmetric multigrid V-cycle from level l down.  st (may be
+// null) skips the launches once CG stopped; fuse_rz makes the last level-0
+// sweep also compute rz = r^T z and beta into st.
 template <typename T>
-hipError_t launch_vcycle(fe_problem* p, int l, const T* r, T* z);
+hipError_t launch_vcycle(fe_problem* p, int l, const T* r, T* z, CgState* st, bool fuse_rz);
 
 // CG helpers (T = float or double vectors, float64 reductions)
 template <typename T>

@@ -96,14 +96,17 @@ struct Epi {
 // MODE 2: y = b - Kx (float64 only), ||y||^2 -> out[0].
 // MODE 3: damped Jacobi sweep y = x + omega D^-1 (b - Kx).
 // MODE 4: y = b - Kx.
-// y must not alias x (other workgroups read x around their tiles).
+// MODE 5: MODE 3 and rz = b^T y, beta = rz / rz_old into st (the last sweep of
+//         a multigrid V-cycle that preconditions CG).
+// For modes 3 and 4 a non-null st only guards: the launch is skipped once CG
+// has stopped.  y must not alias x (other workgroups read x around their tiles).
 template <typename T, int MODE>
 __global__ void __launch_bounds__(TX* TY) kxu_tile_kernel(Grid g, int kc, const T* __restrict__ x,
                                                          const T* __restrict__ E,
                                                          const uint8_t* __restrict__ nmask, WK<T> wk,
                                                          T* __restrict__ y, Epi<T> ep, CgState* st,
                                                          double* partials, double* out) {
-  if (MODE == 1 && st->done) return;
+  if ((MODE == 1 || MODE == 5 || st) && st->done) return;
   __shared__ T su[3][TY + 1][TX + 1];  // node values of the current upper level
   __shared__ T sy[9][TY][TX];          // level partials of corners (1,0), (1,1), (0,1)
 
@@ -246,8 +249,10 @@ __global__ void __launch_bounds__(TX* TY) kxu_tile_kernel(Grid g, int kc, const 
           dot += (double)v2 * (double)v2;
         } else if (MODE == 1) {
           dot += (double)own_prev[c] * (double)v2;
-        } else if (MODE == 3) {
-          v2 = fx ? T(0) : own_prev[c] + ep.omega * ep.invd[n] * (ep.bT[3 * n + c] - v2);
+        } else if (MODE == 3 || MODE == 5) {
+          const T bv = ep.bT[3 * n + c];
+          v2 = fx ? T(0) : own_prev[c] + ep.omega * ep.invd[n] * (bv - v2);
+          if (MODE == 5) dot += (double)bv * (double)v2;
         } else if (MODE == 4) {
           v2 = fx ? T(0) : ep.bT[3 * n + c] - v2;
         }
@@ -257,11 +262,20 @@ __global__ void __launch_bounds__(TX* TY) kxu_tile_kernel(Grid g, int kc, const 
 #pragma unroll
     for (int c = 0; c < 3; ++c) own_prev[c] = cur.own[c];
   }
-  if (MODE == 0 || MODE >= 3) return;
+  if (MODE == 0 || MODE == 3 || MODE == 4) return;
   double vv[1] = {dot};
-  const bool last = grid_sum<1>(vv, partials, MODE == 1 ? &st->counter[0] : (uint32_t*)(out + 1));
+  uint32_t* ctr = MODE == 1 ? &st->counter[0] : MODE == 5 ? &st->counter[3] : (uint32_t*)(out + 1);
+  const bool last = grid_sum<1>(vv, partials, ctr);
   if (last && threadIdx.x == 0) {
-    if (MODE == 1) {
+    if (MODE == 5) {
+      const double rz = vv[0];
+      st->beta = st->iter == 0 ? 0.0 : rz / st->rz;
+      st->rz = rz;
+      if (!finite_d(rz) || !(rz > 0.0)) {
+        st->status = FE_EBREAKDOWN;
+        st->done = 1;
+      }
+    } else if (MODE == 1) {
       const double pq = vv[0];
       st->pq = pq;
       if (!(pq > 0.0) || !finite_d(pq)) {
@@ -287,9 +301,21 @@ WK<T> scaled_wk(const WalshK& w, double h) {
 }  // namespace
 
 #ifndef FE_KXU_KC
-#define FE_KXU_KC 8  // node levels one workgroup marches through
+#define FE_KXU_KC 8  // most node levels one workgroup marches through
 #endif
-static int kxu_levels_per_block() { return FE_KXU_KC; }
+#ifndef FE_KXU_TARGET_BLOCKS
+#define FE_KXU_TARGET_BLOCKS 1024  // aim: four workgroups per compute unit
+#endif
+
+// Levels per workgroup: long marches amortise the tile halo, but small grids
+// need short ones to give every compute unit work.
+static int kxu_levels_per_block(const Grid& g) {
+  const int64_t cols = (int64_t)((g.nx + 1 + OWN - 1) / OWN) * ((g.ny + 1 + OWN - 1) / OWN);
+  int64_t kc = ((int64_t)(g.nz + 1) * cols + FE_KXU_TARGET_BLOCKS - 1) / FE_KXU_TARGET_BLOCKS;
+  if (kc < 1) kc = 1;
+  if (kc > FE_KXU_KC) kc = FE_KXU_KC;
+  return (int)kc;
+}
 
 static dim3 kxu_grid(const Grid& g, int kc) {
   return dim3((unsigned)((g.nx + 1 + OWN - 1) / OWN), (unsigned)((g.ny + 1 + OWN - 1) / OWN),
@@ -297,7 +323,7 @@ static dim3 kxu_grid(const Grid& g, int kc) {
 }
 
 int64_t kxu_tile_blocks(const Grid& g) {
-  const dim3 d = kxu_grid(g, kxu_levels_per_block());
+  const dim3 d = kxu_grid(g, kxu_levels_per_block(g));
   return (int64_t)d.x * d.y * d.z;
 }
 
@@ -305,7 +331,7 @@ template <typename T>
 hipError_t launch_kxu_tile(fe_problem* p, int lev, const T* x, const T* E, T* y, CgState* st, int mode,
                            const double* b64, double* out, const T* bT, const T* invd, double omega) {
   const Grid g = p->L[lev].g;
-  const int kc = kxu_levels_per_block();
+  const int kc = kxu_levels_per_block(g);
   const dim3 grid = kxu_grid(g, kc);
   const WK<T> wk = scaled_wk<T>(p->wk, p->L[lev].h);
   Epi<T> ep;
@@ -329,6 +355,10 @@ hipError_t launch_kxu_tile(fe_problem* p, int lev, const T* x, const T* E, T* y,
       break;
     case 4:
       hipLaunchKernelGGL((kxu_tile_kernel<T, 4>), grid, dim3(TX * TY), 0, p->stream, g, kc, x, E, nm, wk,
+                         y, ep, st, p->partials, out);
+      break;
+    case 5:
+      hipLaunchKernelGGL((kxu_tile_kernel<T, 5>), grid, dim3(TX * TY), 0, p->stream, g, kc, x, E, nm, wk,
                          y, ep, st, p->partials, out);
       break;
     default:

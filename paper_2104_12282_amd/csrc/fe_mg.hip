@@ -16,10 +16,12 @@ inline int nblocks(int64_t n) {
 }
 
 // z = omega D^-1 r (the first sweep from z = 0; fixed dofs have r = 0).
+// A non-null st guards every kernel of the cycle: nothing runs once CG stopped.
 template <typename T>
 __global__ void __launch_bounds__(FE_BLOCK) jacobi0_kernel(int64_t ndof, const T* __restrict__ r,
                                                            const T* __restrict__ invd, T omega,
-                                                           T* __restrict__ z) {
+                                                           T* __restrict__ z, const CgState* st) {
+  if (st && st->done) return;
   const int64_t d = blockIdx.x * (int64_t)FE_BLOCK + threadIdx.x;
   if (d < ndof) z[d] = omega * invd[d / 3] * r[d];
 }
@@ -29,7 +31,8 @@ __global__ void __launch_bounds__(FE_BLOCK) jacobi0_kernel(int64_t ndof, const T
 template <typename T>
 __global__ void __launch_bounds__(FE_BLOCK) restrict_kernel(Grid fg, Grid cg, const T* __restrict__ tf,
                                                             const uint8_t* __restrict__ cmask,
-                                                            T* __restrict__ rc) {
+                                                            T* __restrict__ rc, const CgState* st) {
+  if (st && st->done) return;
   const int64_t n = blockIdx.x * (int64_t)FE_BLOCK + threadIdx.x;
   if (n >= cg.nnode) return;
   const int I = (int)(n % (cg.nx + 1)), J = (int)((n / (cg.nx + 1)) % (cg.ny + 1)),
@@ -64,7 +67,9 @@ __global__ void __launch_bounds__(FE_BLOCK) restrict_kernel(Grid fg, Grid cg, co
 template <typename T>
 __global__ void __launch_bounds__(FE_BLOCK) prolong_add_kernel(Grid fg, Grid cg, const T* zf,
                                                                const T* __restrict__ zc,
-                                                               const uint8_t* __restrict__ fmask, T* out) {
+                                                               const uint8_t* __restrict__ fmask, T* out,
+                                                               const CgState* st) {
+  if (st && st->done) return;
   const int64_t n = blockIdx.x * (int64_t)FE_BLOCK + threadIdx.x;
   if (n >= fg.nnode) return;
   const int i = (int)(n % (fg.nx + 1)), j = (int)((n / (fg.nx + 1)) % (fg.ny + 1)),
@@ -105,16 +110,16 @@ const float* lev_E<float>(const Level& L) { return L.E32; }
 
 // n damped Jacobi sweeps from z = 0 on level l, result in z (t is scratch).
 template <typename T>
-hipError_t jacobi_sweeps(fe_problem* p, int l, const T* r, T* z, T* t, int n) {
+hipError_t jacobi_sweeps(fe_problem* p, int l, const T* r, T* z, T* t, int n, CgState* st) {
   const Level& L = p->L[l];
   const double om = p->mg_omega;
   T* a = (n % 2) ? z : t;  // first target chosen so the last sweep lands in z
   T* b = (n % 2) ? t : z;
   hipLaunchKernelGGL(jacobi0_kernel<T>, dim3(nblocks(L.g.ndof)), dim3(FE_BLOCK), 0, p->stream, L.g.ndof, r,
-                     lev_invd<T>(L), (T)om, a);
+                     lev_invd<T>(L), (T)om, a, st);
   hipError_t e = hipGetLastError();
   for (int s = 1; s < n && e == hipSuccess; ++s) {
-    e = launch_kxu_tile<T>(p, l, a, lev_E<T>(L), b, nullptr, 3, nullptr, nullptr, r, lev_invd<T>(L), om);
+    e = launch_kxu_tile<T>(p, l, a, lev_E<T>(L), b, st, 3, nullptr, nullptr, r, lev_invd<T>(L), om);
     T* tmp = a;
     a = b;
     b = tmp;
@@ -126,33 +131,35 @@ hipError_t jacobi_sweeps(fe_problem* p, int l, const T* r, T* z, T* t, int n) {
 
 // z = V(r): one symmetric V-cycle on levels l .. nlev-1 (pre- and
 // post-smoothing with mg_nu damped Jacobi sweeps, mg_coarse sweeps on the
-// coarsest level).
+// coarsest level).  st (may be null) guards the launches; with fuse_rz the
+// last sweep on level 0 also forms r^T z and the CG direction factor.
 template <typename T>
-hipError_t launch_vcycle(fe_problem* p, int l, const T* r, T* z) {
+hipError_t launch_vcycle(fe_problem* p, int l, const T* r, T* z, CgState* st, bool fuse_rz) {
   const Level& L = p->L[l];
   T* t = static_cast<T*>(L.mg_t);
-  if (l == p->nlev - 1) return jacobi_sweeps<T>(p, l, r, z, t, p->mg_coarse_sweeps);
-  hipError_t e = jacobi_sweeps<T>(p, l, r, z, t, p->mg_nu);
+  if (l == p->nlev - 1) return jacobi_sweeps<T>(p, l, r, z, t, p->mg_coarse_sweeps, st);
+  hipError_t e = jacobi_sweeps<T>(p, l, r, z, t, p->mg_nu, st);
   if (e != hipSuccess) return e;
   // t = r - K z, restricted to the next level's right-hand side
-  e = launch_kxu_tile<T>(p, l, z, lev_E<T>(L), t, nullptr, 4, nullptr, nullptr, r, nullptr, 0.0);
+  e = launch_kxu_tile<T>(p, l, z, lev_E<T>(L), t, st, 4, nullptr, nullptr, r, nullptr, 0.0);
   if (e != hipSuccess) return e;
   const Level& C = p->L[l + 1];
   T* rc = static_cast<T*>(C.mg_r);
   T* zc = static_cast<T*>(C.mg_z);
   hipLaunchKernelGGL(restrict_kernel<T>, dim3(nblocks(C.g.nnode)), dim3(FE_BLOCK), 0, p->stream, L.g, C.g, t,
-                     C.nmask, rc);
+                     C.nmask, rc, st);
   if ((e = hipGetLastError()) != hipSuccess) return e;
-  if ((e = launch_vcycle<T>(p, l + 1, rc, zc)) != hipSuccess) return e;
+  if ((e = launch_vcycle<T>(p, l + 1, rc, zc, st, false)) != hipSuccess) return e;
   // post-smoothing, arranged so the last sweep writes z
   const int nu = p->mg_nu;
   T* a = (nu % 2) ? t : z;
   hipLaunchKernelGGL(prolong_add_kernel<T>, dim3(nblocks(L.g.nnode)), dim3(FE_BLOCK), 0, p->stream, L.g, C.g,
-                     z, zc, L.nmask, a);
+                     z, zc, L.nmask, a, st);
   if ((e = hipGetLastError()) != hipSuccess) return e;
   T* b = (a == t) ? z : t;
   for (int s = 0; s < nu; ++s) {
-    e = launch_kxu_tile<T>(p, l, a, lev_E<T>(L), b, nullptr, 3, nullptr, nullptr, r, lev_invd<T>(L),
+    const int mode = (fuse_rz && l == 0 && s == nu - 1) ? 5 : 3;
+    e = launch_kxu_tile<T>(p, l, a, lev_E<T>(L), b, st, mode, nullptr, nullptr, r, lev_invd<T>(L),
                            p->mg_omega);
     if (e != hipSuccess) return e;
     T* tmp = a;
@@ -162,5 +169,5 @@ hipError_t launch_vcycle(fe_problem* p, int l, const T* r, T* z) {
   return hipSuccess;
 }
 
-template hipError_t launch_vcycle<double>(fe_problem*, int, const double*, double*);
-template hipError_t launch_vcycle<float>(fe_problem*, int, const float*, float*);
+template hipError_t launch_vcycle<double>(fe_problem*, int, const double*, double*, CgState*, bool);
+template hipError_t launch_vcycle<float>(fe_problem*, int, const float*, float*, CgState*, bool);
