@@ -148,10 +148,12 @@ FE_API fe_status oc_update(fe_problem* p, const double* x, const double* dcx, co
  * bounds that of D^-1 K for any density field). */
 FE_API fe_status fe_set_mg_params(fe_problem* p, int32_t nu, int32_t coarse_sweeps, double omega);
 
-/* Timing of the dominant kernel (matrix-free K*u): when on, every K*u launch
- * is bracketed by HIP events on the handle's stream; fe_kernel_stats
+/* Timing of the dominant kernel (matrix-free K*u on the finest grid, in all
+ * its forms: CG product, residual, smoothing sweep): when on, every such
+ * launch is bracketed by HIP events on the handle's stream.  fe_kernel_stats
  * returns the number of launches and their summed duration in ms since the
- * last reset, and the algorithmic bytes one launch moves. */
+ * last reset, and the mean algorithmic bytes of one launch (each array the
+ * kernel reads or writes counted once). */
 FE_API fe_status fe_set_profiling(fe_problem* p, int32_t on);
 FE_API fe_status fe_kernel_stats(fe_problem* p, int32_t reset, int64_t* launches,
                           double* total_ms, double* bytes_per_launch);

@@ -554,21 +554,18 @@ extern "C" fe_status fe_kernel_stats(fe_problem* p, int32_t reset, int64_t* laun
       float ms = 0.0f;
       HIP_TRY(hipEventElapsedTime(&ms, ks.ev[2 * i], ks.ev[2 * i + 1]));
       ks.total_ms += ms;
+      ks.total_bytes += ks.bytes[i];
     }
     ks.launches += ks.pending;
     ks.pending = 0;
   }
   if (launches) *launches = ks.launches;
   if (total_ms) *total_ms = ks.total_ms;
-  if (bytes_per_launch) {
-    // read x and E, write y, in the vector precision of the solve
-    const Grid& g = p->L[0].g;
-    const double vb = p->cfg.precision == FE_PREC_FP64 ? 8.0 : 4.0;
-    *bytes_per_launch = vb * (2.0 * (double)g.ndof + (double)g.nelem);
-  }
+  if (bytes_per_launch) *bytes_per_launch = ks.launches ? ks.total_bytes / (double)ks.launches : 0.0;
   if (reset) {
     ks.launches = 0;
     ks.total_ms = 0.0;
+    ks.total_bytes = 0.0;
   }
   return FE_OK;
 }

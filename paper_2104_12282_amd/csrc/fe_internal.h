@@ -67,10 +67,17 @@ struct Level {
 struct KStats {
   bool on = false;
   std::vector<hipEvent_t> ev;  // pairs
+  std::vector<double> bytes;   // algorithmic bytes of each recorded launch
   int64_t pending = 0;         // recorded pairs not yet read
   int64_t launches = 0;
   double total_ms = 0.0;
+  double total_bytes = 0.0;
 };
+
+// Brackets the next launch on p->stream with a pair of events when profiling
+// is on (returns the slot, or -1).
+int kstats_begin(fe_problem* p, double bytes);
+void kstats_end(fe_problem* p, int slot);
 
 struct fe_problem {
   fe_config cfg;
@@ -162,6 +169,11 @@ template <typename T>
 hipError_t launch_cg_rz(fe_problem* p, const T* r, const T* z, CgState* st);
 
 hipError_t launch_cg_state_init(fe_problem* p, CgState* st, double tol_rel, int max_iter);
+// One-workgroup scalar update after a kernel that left nb partials:
+// op 0 alpha = rz / pq, 1 CG start, 2 CG update and convergence test,
+// 3 rz and beta, 4 out[0] = the sum.
+enum { FIN_ALPHA = 0, FIN_INIT = 1, FIN_UPDATE = 2, FIN_RZ = 3, FIN_SCALAR = 4 };
+hipError_t launch_cg_finalize(fe_problem* p, int op, int nb, int mg, CgState* st, double* out);
 
 // float64 residual r = f - K u (masked) and ||r||^2 into scal[slot]
 hipError_t launch_residual64(fe_problem* p, const double* u, double* r, double* scal_slot);

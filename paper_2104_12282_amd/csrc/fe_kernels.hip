@@ -130,77 +130,48 @@ __global__ void __launch_bounds__(FE_BLOCK) diag_kernel(Grid g, const double* __
   }
 }
 
-// ----------------------------------------------------------- K * x (v1)
+// ------------------------------------------------ K * x, dense reference
 // Node-centric, dense Ke: node n sums, over the (up to) 8 bricks around it,
-// E_e * (row block of Ke for n's corner) * u_e.  Inputs must be zero on fixed
-// dofs; outputs are zeroed there.  MODE 0: y = Kx.  MODE 1: CG step, also
-// pq = x^T y and alpha = rz / pq.  MODE 2: y = b - Kx and ||y||^2 -> out.
-template <typename T, int MODE>
-__global__ void __launch_bounds__(FE_BLOCK) kxu_dense_kernel(
-    Grid g, const T* __restrict__ x, const T* __restrict__ E, const uint8_t* __restrict__ nmask,
-    const double* __restrict__ ke, double kscale, T* __restrict__ y, const double* __restrict__ b,
-    CgState* st, double* partials, double* out) {
-  if (MODE == 1 && st->done) return;
-  __shared__ T sKe[576];
-  for (int i = threadIdx.x; i < 576; i += FE_BLOCK) sKe[i] = (T)(ke[i] * kscale);
+// E_e * (row block of Ke for n's corner) * u_e.  Kept as a second, plainly
+// written implementation of the operator (float64).  Inputs must be zero on
+// fixed dofs; outputs are zeroed there.
+__global__ void __launch_bounds__(FE_BLOCK) kxu_dense_kernel(Grid g, const double* __restrict__ x,
+                                                             const double* __restrict__ E,
+                                                             const uint8_t* __restrict__ nmask,
+                                                             const double* __restrict__ ke, double kscale,
+                                                             double* __restrict__ y) {
+  __shared__ double sKe[576];
+  for (int i = threadIdx.x; i < 576; i += FE_BLOCK) sKe[i] = ke[i] * kscale;
   __syncthreads();
   const int64_t n = blockIdx.x * (int64_t)FE_BLOCK + threadIdx.x;
-  double dotv = 0.0;
-  if (n < g.nnode) {
-    const int i = (int)(n % (g.nx + 1)), j = (int)((n / (g.nx + 1)) % (g.ny + 1)),
-              k = (int)(n / ((int64_t)(g.nx + 1) * (g.ny + 1)));
-    T acc[3] = {T(0), T(0), T(0)};
-    for (int a = 0; a < 8; ++a) {
-      const int ei = i - c_cx[a], ej = j - c_cy[a], ek = k - c_cz[a];
-      if (ei < 0 || ei >= g.nx || ej < 0 || ej >= g.ny || ek < 0 || ek >= g.nz) continue;
-      const T Ee = E[ei + (int64_t)g.nx * (ej + (int64_t)g.ny * ek)];
-      T ue[24];
+  if (n >= g.nnode) return;
+  const int i = (int)(n % (g.nx + 1)), j = (int)((n / (g.nx + 1)) % (g.ny + 1)),
+            k = (int)(n / ((int64_t)(g.nx + 1) * (g.ny + 1)));
+  double acc[3] = {0.0, 0.0, 0.0};
+  for (int a = 0; a < 8; ++a) {
+    const int ei = i - c_cx[a], ej = j - c_cy[a], ek = k - c_cz[a];
+    if (ei < 0 || ei >= g.nx || ej < 0 || ej >= g.ny || ek < 0 || ek >= g.nz) continue;
+    const double Ee = E[ei + (int64_t)g.nx * (ej + (int64_t)g.ny * ek)];
+    double ue[24];
 #pragma unroll
-      for (int bb = 0; bb < 8; ++bb) {
-        const int64_t nb = (ei + c_cx[bb]) + (int64_t)(g.nx + 1) * ((ej + c_cy[bb]) + (int64_t)(g.ny + 1) * (ek + c_cz[bb]));
-        ue[3 * bb + 0] = x[3 * nb + 0];
-        ue[3 * bb + 1] = x[3 * nb + 1];
-        ue[3 * bb + 2] = x[3 * nb + 2];
-      }
-#pragma unroll
-      for (int c = 0; c < 3; ++c) {
-        const T* row = &sKe[(3 * a + c) * 24];
-        T s = T(0);
-#pragma unroll
-        for (int q = 0; q < 24; ++q) s += row[q] * ue[q];
-        acc[c] += Ee * s;
-      }
+    for (int bb = 0; bb < 8; ++bb) {
+      const int64_t nb = (ei + c_cx[bb]) + (int64_t)(g.nx + 1) * ((ej + c_cy[bb]) + (int64_t)(g.ny + 1) * (ek + c_cz[bb]));
+      ue[3 * bb + 0] = x[3 * nb + 0];
+      ue[3 * bb + 1] = x[3 * nb + 1];
+      ue[3 * bb + 2] = x[3 * nb + 2];
     }
-    const uint8_t m = nmask[n];
 #pragma unroll
     for (int c = 0; c < 3; ++c) {
-      T v = ((m >> c) & 1) ? T(0) : acc[c];
-      if (MODE == 2) {
-        v = ((m >> c) & 1) ? T(0) : (T)(b[3 * n + c] - (double)v);
-        dotv += (double)v * (double)v;
-      } else if (MODE == 1) {
-        dotv += (double)x[3 * n + c] * (double)v;
-      }
-      y[3 * n + c] = v;
+      const double* row = &sKe[(3 * a + c) * 24];
+      double s = 0.0;
+#pragma unroll
+      for (int q = 0; q < 24; ++q) s += row[q] * ue[q];
+      acc[c] += Ee * s;
     }
   }
-  if (MODE == 0) return;
-  double vv[1] = {dotv};
-  const bool last = grid_sum<1>(vv, partials, MODE == 1 ? &st->counter[0] : (uint32_t*)(out + 1));
-  if (last && threadIdx.x == 0) {
-    if (MODE == 1) {
-      const double pq = vv[0];
-      st->pq = pq;
-      if (!(pq > 0.0) || !finite_d(pq)) {
-        st->status = FE_EBREAKDOWN;
-        st->done = 1;
-      } else {
-        st->alpha = st->rz / pq;
-      }
-    } else {
-      out[0] = vv[0];
-    }
-  }
+  const uint8_t m = nmask[n];
+#pragma unroll
+  for (int c = 0; c < 3; ++c) y[3 * n + c] = ((m >> c) & 1) ? 0.0 : acc[c];
 }
 
 // ------------------------------------------------------------- CG pieces
@@ -209,7 +180,7 @@ template <typename T>
 __global__ void __launch_bounds__(FE_BLOCK) cg_init_kernel(Grid g, const T* __restrict__ b,
                                                            const T* __restrict__ Kx, T* __restrict__ r,
                                                            T* __restrict__ p, const T* __restrict__ invd,
-                                                           CgState* st, double* partials, int mg) {
+                                                           double* partials, int mg) {
   double acc[3] = {0.0, 0.0, 0.0};  // rz, rr, bb
   for (int64_t d = blockIdx.x * (int64_t)FE_BLOCK + threadIdx.x; d < g.ndof;
        d += (int64_t)gridDim.x * FE_BLOCK) {
@@ -224,19 +195,7 @@ __global__ void __launch_bounds__(FE_BLOCK) cg_init_kernel(Grid g, const T* __re
     acc[1] += (double)rv * (double)rv;
     acc[2] += (double)bv * (double)bv;
   }
-  if (grid_sum<3>(acc, partials, &st->counter[1]) && threadIdx.x == 0) {
-    st->rz = acc[0];
-    st->rr = acc[1];
-    st->bb = acc[2];
-    st->tol2 = st->tol2 * acc[2];  // tol2 held rtol^2 until now
-    st->iter = 0;
-    st->status = FE_OK;
-    st->done = (acc[1] <= st->tol2) ? 1 : 0;
-    if (!finite_d(acc[1])) {
-      st->status = FE_EBREAKDOWN;
-      st->done = 1;
-    }
-  }
+  block_partials<3>(acc, partials);
 }
 
 // x += alpha p, r -= alpha q, (Jacobi) rz = r^T D^-1 r, rr = r^T r; then the
@@ -258,24 +217,7 @@ __global__ void __launch_bounds__(FE_BLOCK) cg_update_kernel(Grid g, T* __restri
     if (!mg) acc[0] += (double)rv * (double)rv * (double)invd[d / 3];
     acc[1] += (double)rv * (double)rv;
   }
-  if (grid_sum<2>(acc, partials, &st->counter[2]) && threadIdx.x == 0) {
-    st->iter += 1;
-    st->rr = acc[1];
-    if (!mg) {
-      st->beta = acc[0] / st->rz;
-      st->rz = acc[0];
-    }
-    if (!finite_d(acc[1])) {
-      st->status = FE_EBREAKDOWN;
-      st->done = 1;
-    } else if (acc[1] <= st->tol2) {
-      st->status = FE_OK;
-      st->done = 1;
-    } else if (st->iter >= st->max_iter) {
-      st->status = FE_ENOTCONV;
-      st->done = 1;
-    }
-  }
+  block_partials<2>(acc, partials);
 }
 
 // rz = r^T z (preconditioned by the multigrid cycle), beta = rz / rz_old.
@@ -288,16 +230,75 @@ __global__ void __launch_bounds__(FE_BLOCK) cg_rz_kernel(Grid g, const T* __rest
   for (int64_t d = blockIdx.x * (int64_t)FE_BLOCK + threadIdx.x; d < g.ndof;
        d += (int64_t)gridDim.x * FE_BLOCK)
     acc[0] += (double)r[d] * (double)z[d];
-  if (grid_sum<1>(acc, partials, &st->counter[3]) && threadIdx.x == 0) {
-    if (st->iter == 0) {
-      st->beta = 0.0;
-    } else {
-      st->beta = acc[0] / st->rz;
+  block_partials<1>(acc, partials);
+}
+
+// Scalar updates of CG, one workgroup, after the kernel that left nb partials.
+
+__global__ void __launch_bounds__(FE_BLOCK) cg_finalize_kernel(int op, int nb, int mg,
+                                                               const double* __restrict__ partials,
+                                                               CgState* st, double* out) {
+  if (op != FIN_SCALAR && op != FIN_INIT && st->done) return;
+  if (op == FIN_INIT) {
+    double acc[3];
+    reduce_partials<3>(acc, partials, nb);
+    if (threadIdx.x == 0) {
+      st->rz = acc[0];
+      st->rr = acc[1];
+      st->bb = acc[2];
+      st->tol2 = st->tol2 * acc[2];  // tol2 held rtol^2 until now
+      st->iter = 0;
+      st->status = FE_OK;
+      st->done = (acc[1] <= st->tol2) ? 1 : 0;
+      if (!finite_d(acc[1])) {
+        st->status = FE_EBREAKDOWN;
+        st->done = 1;
+      }
     }
-    st->rz = acc[0];
-    if (!finite_d(acc[0]) || !(acc[0] > 0.0)) {
-      st->status = FE_EBREAKDOWN;
-      st->done = 1;
+  } else if (op == FIN_UPDATE) {
+    double acc[2];
+    reduce_partials<2>(acc, partials, nb);
+    if (threadIdx.x == 0) {
+      st->iter += 1;
+      st->rr = acc[1];
+      if (!mg) {
+        st->beta = acc[0] / st->rz;
+        st->rz = acc[0];
+      }
+      if (!finite_d(acc[1])) {
+        st->status = FE_EBREAKDOWN;
+        st->done = 1;
+      } else if (acc[1] <= st->tol2) {
+        st->status = FE_OK;
+        st->done = 1;
+      } else if (st->iter >= st->max_iter) {
+        st->status = FE_ENOTCONV;
+        st->done = 1;
+      }
+    }
+  } else {
+    double acc[1];
+    reduce_partials<1>(acc, partials, nb);
+    if (threadIdx.x == 0) {
+      const double v = acc[0];
+      if (op == FIN_ALPHA) {
+        st->pq = v;
+        if (!(v > 0.0) || !finite_d(v)) {
+          st->status = FE_EBREAKDOWN;
+          st->done = 1;
+        } else {
+          st->alpha = st->rz / v;
+        }
+      } else if (op == FIN_RZ) {
+        st->beta = st->iter == 0 ? 0.0 : v / st->rz;
+        st->rz = v;
+        if (!finite_d(v) || !(v > 0.0)) {
+          st->status = FE_EBREAKDOWN;
+          st->done = 1;
+        }
+      } else {
+        out[0] = v;
+      }
     }
   }
 }
@@ -355,7 +356,7 @@ __global__ void __launch_bounds__(FE_BLOCK) dot64_kernel(int64_t n, const double
   for (int64_t d = blockIdx.x * (int64_t)FE_BLOCK + threadIdx.x; d < n;
        d += (int64_t)gridDim.x * FE_BLOCK)
     acc[0] += a[d] * b[d];
-  if (grid_sum<1>(acc, partials, (uint32_t*)(out + 1)) && threadIdx.x == 0) out[0] = acc[0];
+  block_partials<1>(acc, partials);
 }
 
 template <typename T>
@@ -483,7 +484,6 @@ __global__ void __launch_bounds__(FE_BLOCK) filter_kernel(Grid g, Stencil s, con
 struct OcState {
   double s_lo, s_hi, target, lam;
   int32_t done, pass, pad0, pad1;
-  uint32_t counter[4];
 };
 
 __device__ inline void oc_elem(const double* x, const double* dcx, const double* dv, int64_t e,
@@ -498,7 +498,7 @@ __device__ inline void oc_elem(const double* x, const double* dcx, const double*
 __global__ void __launch_bounds__(FE_BLOCK) oc_prep_kernel(int64_t n, const double* __restrict__ x,
                                                            const double* __restrict__ dcx,
                                                            const double* __restrict__ dv, double move,
-                                                           double target, OcState* os, double* partials) {
+                                                           double* partials) {
   // s_max: beyond it every element with a > 0 sits at hi.
   double smax = 0.0;
   for (int64_t e = blockIdx.x * (int64_t)FE_BLOCK + threadIdx.x; e < n;
@@ -507,7 +507,13 @@ __global__ void __launch_bounds__(FE_BLOCK) oc_prep_kernel(int64_t n, const doub
     oc_elem(x, dcx, dv, e, move, a, lo, hi, w);
     if (a > 0.0) smax = fmax(smax, hi / a);
   }
-  if (grid_max(smax, partials, &os->counter[0]) && threadIdx.x == 0) {
+  block_partial_max(smax, partials);
+}
+
+__global__ void __launch_bounds__(FE_BLOCK) oc_prep_finalize(int nb, const double* __restrict__ partials,
+                                                             double target, OcState* os) {
+  const double smax = reduce_partials_max(partials, nb);
+  if (threadIdx.x == 0) {
     os->s_lo = 0.0;
     os->s_hi = smax * (1.0 + 1e-15) + 1e-300;
     os->target = target;
@@ -516,7 +522,7 @@ __global__ void __launch_bounds__(FE_BLOCK) oc_prep_kernel(int64_t n, const doub
   }
 }
 
-// Pass 0 spaces the candidates geometrically over s_hi * [1e-30, 1]; later
+// Pass 0 spaces the candidates geometrically over s_hi * [2^-100, 1]; later
 // passes space them evenly inside the bracket.
 __device__ inline double oc_candidate(const OcState* os, int c) {
   if (os->pass == 0) return os->s_hi * exp2(-100.0 * (double)(OC_NC - 1 - c) / (OC_NC - 1));
@@ -526,7 +532,7 @@ __device__ inline double oc_candidate(const OcState* os, int c) {
 __global__ void __launch_bounds__(FE_BLOCK) oc_pass_kernel(int64_t n, const double* __restrict__ x,
                                                            const double* __restrict__ dcx,
                                                            const double* __restrict__ dv, double move,
-                                                           OcState* os, double* partials) {
+                                                           const OcState* os, double* partials) {
   if (os->done) return;
   const int cand = threadIdx.x & (OC_NC - 1);
   const int sub = threadIdx.x / OC_NC;  // 0..3
@@ -557,31 +563,24 @@ __global__ void __launch_bounds__(FE_BLOCK) oc_pass_kernel(int64_t n, const doub
   __shared__ double part[FE_BLOCK];
   part[threadIdx.x] = vol;
   __syncthreads();
-  __shared__ int amlast;
   if (threadIdx.x < OC_NC) {
     double s = 0.0;
     for (int q = 0; q < FE_BLOCK / OC_NC; ++q) s += part[q * OC_NC + threadIdx.x];
     partials[(size_t)threadIdx.x * gridDim.x + blockIdx.x] = s;
   }
-  __threadfence();
-  __syncthreads();
-  if (threadIdx.x == 0) {
-    const uint32_t t = atomicAdd(&os->counter[1], 1u);
-    amlast = (t == gridDim.x - 1);
-  }
-  __syncthreads();
-  if (!amlast) return;
-  __threadfence();
+}
+
+__global__ void __launch_bounds__(FE_BLOCK) oc_pass_finalize(int nb, const double* __restrict__ partials,
+                                                             OcState* os) {
+  if (os->done) return;
   __shared__ double vols[OC_NC];
   if (threadIdx.x < OC_NC) {
     double s = 0.0;
-    for (uint32_t b = 0; b < gridDim.x; ++b)
-      s += __builtin_nontemporal_load(&partials[(size_t)threadIdx.x * gridDim.x + b]);
+    for (int b = 0; b < nb; ++b) s += partials[(size_t)threadIdx.x * nb + b];
     vols[threadIdx.x] = s;
   }
   __syncthreads();
   if (threadIdx.x == 0) {
-    atomicExch(&os->counter[1], 0u);
     // first candidate whose volume reaches the target
     int c = 0;
     while (c < OC_NC && vols[c] < os->target) ++c;
@@ -598,8 +597,8 @@ __global__ void __launch_bounds__(FE_BLOCK) oc_pass_kernel(int64_t n, const doub
 __global__ void __launch_bounds__(FE_BLOCK) oc_final_kernel(int64_t n, const double* x,
                                                             const double* __restrict__ dcx,
                                                             const double* __restrict__ dv, double move,
-                                                            OcState* os, double* x_new, double* partials,
-                                                            double* change) {
+                                                            const OcState* os, double* x_new,
+                                                            double* partials) {
   const double s = 0.5 * (os->s_lo + os->s_hi);
   double ch = 0.0;
   for (int64_t e = blockIdx.x * (int64_t)FE_BLOCK + threadIdx.x; e < n;
@@ -611,7 +610,14 @@ __global__ void __launch_bounds__(FE_BLOCK) oc_final_kernel(int64_t n, const dou
     x_new[e] = xn;
     ch = fmax(ch, fabs(xn - xo));
   }
-  if (grid_max(ch, partials, &os->counter[2]) && threadIdx.x == 0) {
+  block_partial_max(ch, partials);
+}
+
+__global__ void __launch_bounds__(FE_BLOCK) oc_final_finalize(int nb, const double* __restrict__ partials,
+                                                              OcState* os, double* change) {
+  const double ch = reduce_partials_max(partials, nb);
+  if (threadIdx.x == 0) {
+    const double s = 0.5 * (os->s_lo + os->s_hi);
     os->lam = 1.0 / (s * s);
     if (change) *change = ch;
   }
@@ -685,29 +691,35 @@ const double* level_invd<double>(fe_problem* p, int lev) { return p->L[lev].invd
 template <>
 const float* level_invd<float>(fe_problem* p, int lev) { return p->L[lev].invd32; }
 
+int kstats_begin(fe_problem* p, double bytes) {
+  KStats& ks = p->kst;
+  if (!ks.on) return -1;
+  const size_t slot = (size_t)ks.pending;
+  if (2 * slot + 2 > ks.ev.size()) {
+    hipEvent_t a, b;
+    if (hipEventCreate(&a) != hipSuccess) return -1;
+    if (hipEventCreate(&b) != hipSuccess) {
+      (void)hipEventDestroy(a);
+      return -1;
+    }
+    ks.ev.push_back(a);
+    ks.ev.push_back(b);
+  }
+  if (slot + 1 > ks.bytes.size()) ks.bytes.resize(slot + 1);
+  ks.bytes[slot] = bytes;
+  (void)hipEventRecord(ks.ev[2 * slot], p->stream);
+  return (int)slot;
+}
+
+void kstats_end(fe_problem* p, int slot) {
+  if (slot < 0) return;
+  (void)hipEventRecord(p->kst.ev[2 * (size_t)slot + 1], p->stream);
+  p->kst.pending += 1;
+}
+
 template <typename T>
 hipError_t launch_kxu(fe_problem* p, int lev, const T* x, T* y, CgState* st) {
-  const Grid g = G(p, lev);
-  const int nb = (int)ceil_div(g.nnode, FE_BLOCK);
-  KStats& ks = p->kst;
-  const bool prof = ks.on && lev == 0;
-  if (prof) {
-    const size_t slot = (size_t)ks.pending * 2;
-    if (slot + 2 > ks.ev.size()) {
-      hipEvent_t a, b;
-      if (hipEventCreate(&a) != hipSuccess || hipEventCreate(&b) != hipSuccess) return hipErrorOutOfMemory;
-      ks.ev.push_back(a);
-      ks.ev.push_back(b);
-    }
-    (void)hipEventRecord(ks.ev[slot], p->stream);
-  }
-  hipError_t err = launch_kxu_tile<T>(p, lev, x, level_E<T>(p, lev), y, st, st ? 1 : 0, nullptr, nullptr);
-  if (err != hipSuccess) return err;
-  if (prof) {
-    (void)hipEventRecord(ks.ev[(size_t)ks.pending * 2 + 1], p->stream);
-    ks.pending += 1;
-  }
-  return hipGetLastError();
+  return launch_kxu_tile<T>(p, lev, x, level_E<T>(p, lev), y, st, st ? 1 : 0, nullptr, nullptr);
 }
 template hipError_t launch_kxu<double>(fe_problem*, int, const double*, double*, CgState*);
 template hipError_t launch_kxu<float>(fe_problem*, int, const float*, float*, CgState*);
@@ -719,18 +731,26 @@ hipError_t launch_residual64(fe_problem* p, const double* u, double* r, double* 
 hipError_t launch_kxu_dense64(fe_problem* p, const double* x, double* y) {
   const Grid g = G(p, 0);
   const int nb = (int)ceil_div(g.nnode, FE_BLOCK);
-  hipLaunchKernelGGL((kxu_dense_kernel<double, 0>), dim3(nb), dim3(FE_BLOCK), 0, p->stream, g, x,
-                     p->L[0].E64, p->L[0].nmask, p->ke64, p->L[0].h, y, nullptr, nullptr, p->partials,
-                     nullptr);
+  hipLaunchKernelGGL(kxu_dense_kernel, dim3(nb), dim3(FE_BLOCK), 0, p->stream, g, x, p->L[0].E64,
+                     p->L[0].nmask, p->ke64, p->L[0].h, y);
+  return hipGetLastError();
+}
+
+hipError_t launch_cg_finalize(fe_problem* p, int op, int nb, int mg, CgState* st, double* out) {
+  hipLaunchKernelGGL(cg_finalize_kernel, dim3(1), dim3(FE_BLOCK), 0, p->stream, op, nb, mg, p->partials, st,
+                     out);
   return hipGetLastError();
 }
 
 template <typename T>
 hipError_t launch_cg_init(fe_problem* p, const T* b, const T* Kx, T* r, T* pvec, CgState* st, int mg) {
   const Grid g = G(p, 0);
-  hipLaunchKernelGGL(cg_init_kernel<T>, dim3(red_grid(g.ndof)), dim3(FE_BLOCK), 0, p->stream, g, b, Kx, r,
-                     pvec, level_invd<T>(p, 0), st, p->partials, mg);
-  return hipGetLastError();
+  const int nb = red_grid(g.ndof);
+  hipLaunchKernelGGL(cg_init_kernel<T>, dim3(nb), dim3(FE_BLOCK), 0, p->stream, g, b, Kx, r, pvec,
+                     level_invd<T>(p, 0), p->partials, mg);
+  hipError_t e = hipGetLastError();
+  if (e != hipSuccess) return e;
+  return launch_cg_finalize(p, FIN_INIT, nb, mg, st, nullptr);
 }
 template hipError_t launch_cg_init<double>(fe_problem*, const double*, const double*, double*, double*,
                                            CgState*, int);
@@ -740,9 +760,12 @@ template hipError_t launch_cg_init<float>(fe_problem*, const float*, const float
 template <typename T>
 hipError_t launch_cg_update(fe_problem* p, T* x, T* r, const T* pvec, const T* q, CgState* st, int mg) {
   const Grid g = G(p, 0);
-  hipLaunchKernelGGL(cg_update_kernel<T>, dim3(red_grid(g.ndof)), dim3(FE_BLOCK), 0, p->stream, g, x, r,
-                     pvec, q, level_invd<T>(p, 0), st, p->partials, mg);
-  return hipGetLastError();
+  const int nb = red_grid(g.ndof);
+  hipLaunchKernelGGL(cg_update_kernel<T>, dim3(nb), dim3(FE_BLOCK), 0, p->stream, g, x, r, pvec, q,
+                     level_invd<T>(p, 0), st, p->partials, mg);
+  hipError_t e = hipGetLastError();
+  if (e != hipSuccess) return e;
+  return launch_cg_finalize(p, FIN_UPDATE, nb, mg, st, nullptr);
 }
 template hipError_t launch_cg_update<double>(fe_problem*, double*, double*, const double*, const double*,
                                              CgState*, int);
@@ -763,9 +786,11 @@ template hipError_t launch_cg_direction<float>(fe_problem*, const float*, const 
 template <typename T>
 hipError_t launch_cg_rz(fe_problem* p, const T* r, const T* z, CgState* st) {
   const Grid g = G(p, 0);
-  hipLaunchKernelGGL(cg_rz_kernel<T>, dim3(red_grid(g.ndof)), dim3(FE_BLOCK), 0, p->stream, g, r, z, st,
-                     p->partials);
-  return hipGetLastError();
+  const int nb = red_grid(g.ndof);
+  hipLaunchKernelGGL(cg_rz_kernel<T>, dim3(nb), dim3(FE_BLOCK), 0, p->stream, g, r, z, st, p->partials);
+  hipError_t e = hipGetLastError();
+  if (e != hipSuccess) return e;
+  return launch_cg_finalize(p, FIN_RZ, nb, 1, st, nullptr);
 }
 template hipError_t launch_cg_rz<double>(fe_problem*, const double*, const double*, CgState*);
 template hipError_t launch_cg_rz<float>(fe_problem*, const float*, const float*, CgState*);
@@ -790,9 +815,11 @@ hipError_t launch_axpy_from32(fe_problem* p, double* u, const float* d, const do
 }
 
 hipError_t launch_dot64(fe_problem* p, const double* a, const double* b, int64_t n, double* out) {
-  hipLaunchKernelGGL(dot64_kernel, dim3(red_grid(n)), dim3(FE_BLOCK), 0, p->stream, n, a, b, p->partials,
-                     out);
-  return hipGetLastError();
+  const int nb = red_grid(n);
+  hipLaunchKernelGGL(dot64_kernel, dim3(nb), dim3(FE_BLOCK), 0, p->stream, n, a, b, p->partials, out);
+  hipError_t e = hipGetLastError();
+  if (e != hipSuccess) return e;
+  return launch_cg_finalize(p, FIN_SCALAR, nb, 0, nullptr, out);
 }
 
 template <typename T>
@@ -856,12 +883,16 @@ hipError_t launch_oc(fe_problem* p, const double* x, const double* dcx, const do
   const int64_t n = G(p, 0).nelem;
   OcState* os = reinterpret_cast<OcState*>(p->oc);
   const double target = volfrac * (double)n;
-  hipLaunchKernelGGL(oc_prep_kernel, dim3(red_grid(n)), dim3(FE_BLOCK), 0, p->stream, n, x, dcx, dv, move,
-                     target, os, p->partials);
-  for (int pass = 0; pass < 12; ++pass)
-    hipLaunchKernelGGL(oc_pass_kernel, dim3(red_grid(n)), dim3(FE_BLOCK), 0, p->stream, n, x, dcx, dv, move,
-                       os, p->partials);
-  hipLaunchKernelGGL(oc_final_kernel, dim3(red_grid(n)), dim3(FE_BLOCK), 0, p->stream, n, x, dcx, dv, move,
-                     os, x_new, p->partials, change);
+  const int nb = red_grid(n);
+  hipLaunchKernelGGL(oc_prep_kernel, dim3(nb), dim3(FE_BLOCK), 0, p->stream, n, x, dcx, dv, move, p->partials);
+  hipLaunchKernelGGL(oc_prep_finalize, dim3(1), dim3(FE_BLOCK), 0, p->stream, nb, p->partials, target, os);
+  for (int pass = 0; pass < 12; ++pass) {
+    hipLaunchKernelGGL(oc_pass_kernel, dim3(nb), dim3(FE_BLOCK), 0, p->stream, n, x, dcx, dv, move, os,
+                       p->partials);
+    hipLaunchKernelGGL(oc_pass_finalize, dim3(1), dim3(FE_BLOCK), 0, p->stream, nb, p->partials, os);
+  }
+  hipLaunchKernelGGL(oc_final_kernel, dim3(nb), dim3(FE_BLOCK), 0, p->stream, n, x, dcx, dv, move, os, x_new,
+                     p->partials);
+  hipLaunchKernelGGL(oc_final_finalize, dim3(1), dim3(FE_BLOCK), 0, p->stream, nb, p->partials, os, change);
   return hipGetLastError();
 }

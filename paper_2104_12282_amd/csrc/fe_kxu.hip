@@ -264,30 +264,7 @@ __global__ void __launch_bounds__(TX* TY) kxu_tile_kernel(Grid g, int kc, const 
   }
   if (MODE == 0 || MODE == 3 || MODE == 4) return;
   double vv[1] = {dot};
-  uint32_t* ctr = MODE == 1 ? &st->counter[0] : MODE == 5 ? &st->counter[3] : (uint32_t*)(out + 1);
-  const bool last = grid_sum<1>(vv, partials, ctr);
-  if (last && threadIdx.x == 0) {
-    if (MODE == 5) {
-      const double rz = vv[0];
-      st->beta = st->iter == 0 ? 0.0 : rz / st->rz;
-      st->rz = rz;
-      if (!finite_d(rz) || !(rz > 0.0)) {
-        st->status = FE_EBREAKDOWN;
-        st->done = 1;
-      }
-    } else if (MODE == 1) {
-      const double pq = vv[0];
-      st->pq = pq;
-      if (!(pq > 0.0) || !finite_d(pq)) {
-        st->status = FE_EBREAKDOWN;
-        st->done = 1;
-      } else {
-        st->alpha = st->rz / pq;
-      }
-    } else {
-      out[0] = vv[0];
-    }
-  }
+  block_partials<1>(vv, partials);
 }
 
 template <typename T>
@@ -340,6 +317,17 @@ hipError_t launch_kxu_tile(fe_problem* p, int lev, const T* x, const T* E, T* y,
   ep.invd = invd;
   ep.omega = (T)omega;
   const uint8_t* nm = p->L[lev].nmask;
+  // algorithmic bytes: read x and E, write y, plus b (modes 2-5) and the
+  // Jacobi diagonal (modes 3, 5); each array touched once
+  int slot = -1;
+  if (lev == 0 && p->kst.on) {
+    const double vb = sizeof(T);
+    double bytes = vb * (2.0 * (double)g.ndof + (double)g.nelem);
+    if (mode == 2) bytes += 8.0 * (double)g.ndof;
+    if (mode >= 3) bytes += vb * (double)g.ndof;
+    if (mode == 3 || mode == 5) bytes += vb * (double)g.nnode;
+    slot = kstats_begin(p, bytes);
+  }
   switch (mode) {
     case 1:
       hipLaunchKernelGGL((kxu_tile_kernel<T, 1>), grid, dim3(TX * TY), 0, p->stream, g, kc, x, E, nm, wk,
@@ -365,7 +353,14 @@ hipError_t launch_kxu_tile(fe_problem* p, int lev, const T* x, const T* E, T* y,
       hipLaunchKernelGGL((kxu_tile_kernel<T, 0>), grid, dim3(TX * TY), 0, p->stream, g, kc, x, E, nm, wk,
                          y, ep, st, p->partials, out);
   }
-  return hipGetLastError();
+  hipError_t e = hipGetLastError();
+  kstats_end(p, slot);
+  if (e != hipSuccess) return e;
+  const int nb = (int)((int64_t)grid.x * grid.y * grid.z);
+  if (mode == 1) return launch_cg_finalize(p, FIN_ALPHA, nb, 0, st, nullptr);
+  if (mode == 2) return launch_cg_finalize(p, FIN_SCALAR, nb, 0, nullptr, out);
+  if (mode == 5) return launch_cg_finalize(p, FIN_RZ, nb, 1, st, nullptr);
+  return hipSuccess;
 }
 
 template hipError_t launch_kxu_tile<double>(fe_problem*, int, const double*, const double*, double*,

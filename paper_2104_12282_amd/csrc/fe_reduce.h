@@ -1,10 +1,13 @@
-// Deterministic block and grid reductions for float64 sums.
+// Deterministic float64 reductions in two launches.
 //
-// Every workgroup reduces its values in a fixed order (wave64 butterfly, then
-// the waves in index order), writes them to partials[v * blocks + block]
-// and bumps an arrival counter; the workgroup that arrives last sums the
-// partials in block order and runs the finaliser.  The result is independent
-// of scheduling, so a solve is bitwise reproducible.
+// A producing kernel reduces its values inside each workgroup in a fixed
+// order (wave64 butterfly, then the four waves in index order) and stores
+// one partial per workgroup: partials[slot * blocks + block].  A one-
+// workgroup finalize kernel, launched right after on the same stream, sums
+// the partials in block order and applies the scalar update.  The kernel
+// boundary orders the two, so no workgroup ever fences the L2 (a device-scope
+// fence per workgroup writes back and invalidates the L2 of its XCD, which
+// costs more than the data pass itself).  Results are bitwise reproducible.
 #pragma once
 #include <hip/hip_runtime.h>
 
@@ -28,8 +31,8 @@ __device__ inline uint32_t block_id() {
 }
 __device__ inline uint32_t block_count() { return gridDim.x * gridDim.y * gridDim.z; }
 
-// Sum of v[0..NV) over the workgroup; the totals are valid in thread 0.
-// Needs a barrier-free entry (all threads of the block call it).
+// Sum of v[0..NV) over the workgroup (FE_BLOCK threads); totals valid in
+// thread 0.  Every thread of the workgroup must call it.
 template <int NV>
 __device__ inline void block_sum(double (&v)[NV]) {
   __shared__ double sh[NV][FE_BLOCK / 64];
@@ -65,52 +68,38 @@ __device__ inline double block_max(double v) {
   return v;
 }
 
-// Publishes the block sums and tells whether this block arrived last.  When it
-// returns true, thread 0 holds in v[] the grid totals (fixed summation order).
+// Producer side: one partial per workgroup and slot.
 template <int NV>
-__device__ inline bool grid_sum(double (&v)[NV], double* partials, uint32_t* counter) {
-  __shared__ int amlast;
+__device__ inline void block_partials(double (&v)[NV], double* partials) {
   block_sum<NV>(v);
   if (threadIdx.x == 0) {
 #pragma unroll
     for (int i = 0; i < NV; ++i) partials[(size_t)i * block_count() + block_id()] = v[i];
-    __threadfence();
-    const uint32_t t = atomicAdd(counter, 1u);
-    amlast = (t == block_count() - 1);
   }
-  __syncthreads();
-  if (!amlast) return false;
-  __threadfence();
+}
+
+__device__ inline void block_partial_max(double v, double* partials) {
+  v = block_max(v);
+  if (threadIdx.x == 0) partials[block_id()] = v;
+}
+
+// Finalize side (one workgroup): totals of the nb partials of each slot, in
+// thread 0.
+template <int NV>
+__device__ inline void reduce_partials(double (&v)[NV], const double* partials, int nb) {
 #pragma unroll
   for (int i = 0; i < NV; ++i) {
     double s = 0.0;
-    for (uint32_t b = threadIdx.x; b < block_count(); b += FE_BLOCK)
-      s += __builtin_nontemporal_load(&partials[(size_t)i * block_count() + b]);
+    for (int b = threadIdx.x; b < nb; b += FE_BLOCK) s += partials[(size_t)i * nb + b];
     v[i] = s;
   }
   block_sum<NV>(v);
-  if (threadIdx.x == 0) atomicExch(counter, 0u);
-  return true;
 }
 
-__device__ inline bool grid_max(double& v, double* partials, uint32_t* counter) {
-  __shared__ int amlast;
-  v = block_max(v);
-  if (threadIdx.x == 0) {
-    partials[block_id()] = v;
-    __threadfence();
-    const uint32_t t = atomicAdd(counter, 1u);
-    amlast = (t == block_count() - 1);
-  }
-  __syncthreads();
-  if (!amlast) return false;
-  __threadfence();
+__device__ inline double reduce_partials_max(const double* partials, int nb) {
   double s = 0.0;
-  for (uint32_t b = threadIdx.x; b < block_count(); b += FE_BLOCK)
-    s = fmax(s, __builtin_nontemporal_load(&partials[b]));
-  v = block_max(s);
-  if (threadIdx.x == 0) atomicExch(counter, 0u);
-  return true;
+  for (int b = threadIdx.x; b < nb; b += FE_BLOCK) s = fmax(s, partials[b]);
+  return block_max(s);
 }
 
 __device__ inline bool finite_d(double x) { return x - x == 0.0; }
