@@ -139,13 +139,15 @@ FE_API fe_status fe_filter(fe_problem* p, const double* in, double* out, int32_t
 FE_API fe_status oc_update(fe_problem* p, const double* x, const double* dcx, const double* dv,
                     double volfrac, double move, double* x_new, double* change);
 
-/* Multigrid smoothing parameters (used when precond = FE_PRECOND_GMG):
- * nu damped-Jacobi sweeps before and after each coarse correction (1..8),
- * coarse_sweeps sweeps on the coarsest level (1..10000), damping omega in
- * (0, 1).  Defaults: 1, 30, 0.35.  The V-cycle is symmetric and linear, so
- * plain CG applies; it is also positive definite while omega stays below
- * 2 / 5.32 (5.32 = largest eigenvalue of diag(Ke)^-1 Ke for nu = 0.3, which
- * bounds that of D^-1 K for any density field). */
+/* Multigrid parameters (used when precond = FE_PRECOND_GMG): nu damped
+ * Jacobi sweeps (damping omega) before and after each coarse correction
+ * (1..8), and the degree (1..10000) of the Jacobi-preconditioned Chebyshev
+ * iteration that solves the coarsest level, on the interval
+ * [lambda_max / 100, lambda_max] with lambda_max = largest eigenvalue of
+ * diag(Ke)^-1 Ke (5.32 for nu = 0.3), which bounds that of D^-1 K for any
+ * density field.  Defaults: nu = 1, degree 20, omega = 0.35.  The V-cycle is
+ * linear and symmetric, and positive definite while omega * lambda_max < 2
+ * (checked: FE_EINVAL otherwise), so plain CG applies. */
 FE_API fe_status fe_set_mg_params(fe_problem* p, int32_t nu, int32_t coarse_sweeps, double omega);
 
 /* Timing of the dominant kernel (matrix-free K*u on the finest grid, in all

@@ -92,6 +92,7 @@ size_t layout(const fe_config* c, fe_problem* p, char* base) {
       L.mg_r = take(g.ndof * vbytes);
       L.mg_z = take(g.ndof * vbytes);
       L.mg_t = take(g.ndof * vbytes);
+      L.mg_w = take(g.ndof * vbytes);
     }
     if (p) p->L[l] = L;
     int64_t nb = (g.nnode + FE_BLOCK - 1) / FE_BLOCK;
@@ -349,6 +350,30 @@ extern "C" fe_status fe_setup(const fe_config* cfg, const uint8_t* fixed, const 
     return FE_EINVAL;
   }
   p->ke_diag = p->ke64_host[0];
+  {
+    // lambda_max(Ke) / Ke_dd by power iteration (Ke is symmetric positive
+    // semi-definite); it bounds lambda_max(D^-1 K) for any modulus field
+    double v[24], w[24], lam = 0.0;
+    for (int i = 0; i < 24; ++i) v[i] = 1.0 + 0.01 * i * ((i & 1) ? -1.0 : 1.0);
+    for (int it = 0; it < 5000; ++it) {
+      double nrm = 0.0;
+      for (int i = 0; i < 24; ++i) {
+        double s2 = 0.0;
+        for (int j = 0; j < 24; ++j) s2 += p->ke64_host[i * 24 + j] * v[j];
+        w[i] = s2;
+        nrm += s2 * s2;
+      }
+      nrm = std::sqrt(nrm);
+      double num = 0.0, den = 0.0;
+      for (int i = 0; i < 24; ++i) {
+        num += v[i] * w[i];
+        den += v[i] * v[i];
+      }
+      lam = num / den;
+      for (int i = 0; i < 24; ++i) v[i] = w[i] / nrm;
+    }
+    p->lam_max = lam / p->ke_diag;
+  }
   float ke32h[576];
   for (int i = 0; i < 576; ++i) ke32h[i] = (float)p->ke64_host[i];
 
@@ -530,6 +555,11 @@ extern "C" fe_status fe_set_mg_params(fe_problem* p, int32_t nu, int32_t coarse_
   CHECK_HANDLE(p);
   if (nu < 1 || nu > 8 || coarse_sweeps < 1 || coarse_sweeps > 10000 || !(omega > 0.0 && omega < 1.0)) {
     fe_set_error("need 1 <= nu <= 8, 1 <= coarse_sweeps <= 10000, 0 < omega < 1");
+    return FE_EINVAL;
+  }
+  if (omega * p->lam_max >= 2.0) {
+    fe_set_error("omega must stay below 2 / lambda_max(diag(Ke)^-1 Ke) = " + std::to_string(2.0 / p->lam_max) +
+                 " for the smoother to be convergent");
     return FE_EINVAL;
   }
   p->mg_nu = nu;

@@ -62,6 +62,7 @@ struct Level {
   void* mg_r = nullptr;
   void* mg_z = nullptr;
   void* mg_t = nullptr;
+  void* mg_w = nullptr;
 };
 
 struct KStats {
@@ -112,8 +113,10 @@ struct fe_problem {
 
   // geometric multigrid parameters
   int mg_nu = 1;               // damped Jacobi sweeps before and after the coarse correction
-  int mg_coarse_sweeps = 30;   // sweeps on the coarsest level
+  int mg_coarse_sweeps = 20;   // Chebyshev degree on the coarsest level
   double mg_omega = 0.35;      // Jacobi damping: below 2 / lambda_max(D^-1 Ke) = 2 / 5.32
+  double lam_max = 0.0;        // lambda_max(diag(Ke)^-1 Ke): bounds that of D^-1 K on every level
+  double cheb_ratio = 100.0;   // coarse Chebyshev interval [lam_max / ratio, lam_max]
 
   KStats kst;
 };
@@ -139,13 +142,23 @@ hipError_t launch_mask_vec(fe_problem* p, int lev, T* v);
 template <typename T>
 hipError_t launch_kxu(fe_problem* p, int lev, const T* x, T* y, CgState* st);
 
+// Operands of one Chebyshev step (mode 6 of the tiled kernel).
+template <typename T>
+struct ChebStep {
+  T* res;      // residual, updated in place
+  T* acc;      // iterate, updated in place
+  double c1, c2;
+  int first;   // iterate starts at zero
+};
+
 // The tiled kernel behind launch_kxu: mode 0 y = Kx, 1 CG step (st), 2 y = b64 - Kx
 // with ||y||^2 -> out[0] (float64 only), 3 damped Jacobi y = x + omega D^-1 (bT - Kx),
-// 4 y = bT - Kx.
+// 4 y = bT - Kx, 5 mode 3 plus r^T z for CG, 6 Chebyshev step with direction x.
 template <typename T>
 hipError_t launch_kxu_tile(fe_problem* p, int lev, const T* x, const T* E, T* y, CgState* st, int mode,
                            const double* b64, double* out, const T* bT = nullptr,
-                           const T* invd = nullptr, double omega = 0.0);
+                           const T* invd = nullptr, double omega = 0.0,
+                           const ChebStep<T>* cs = nullptr);
 int64_t kxu_tile_blocks(const Grid& g);
 // Node-centric dense-Ke reference kernel (float64), kept as a second implementation.
 hipError_t launch_kxu_dense64(fe_problem* p, const double* x, double* y);

@@ -87,9 +87,13 @@ __device__ inline void apply_S(const WK<T>& k, const T (&t)[3][8], T (&s)[3][8])
 template <typename T>
 struct Epi {
   const double* b64;  // MODE 2
-  const T* bT;        // MODES 3, 4
-  const T* invd;      // MODE 3: inverse Jacobi diagonal per node
-  T omega;            // MODE 3: damping
+  const T* bT;        // MODES 3, 4, 5
+  const T* invd;      // MODES 3, 5, 6: inverse Jacobi diagonal per node
+  T omega;            // MODES 3, 5: damping
+  T* res;             // MODE 6: residual, updated in place
+  T* acc;             // MODE 6: iterate, updated in place
+  T c1, c2;           // MODE 6: direction recurrence
+  int first;          // MODE 6: the iterate starts at zero
 };
 
 // MODE 0: y = Kx.  MODE 1: CG step, pq = x^T y, alpha = rz / pq.
@@ -98,8 +102,11 @@ struct Epi {
 // MODE 4: y = b - Kx.
 // MODE 5: MODE 3 and rz = b^T y, beta = rz / rz_old into st (the last sweep of
 //         a multigrid V-cycle that preconditions CG).
-// For modes 3 and 4 a non-null st only guards: the launch is skipped once CG
-// has stopped.  y must not alias x (other workgroups read x around their tiles).
+// MODE 6: one step of Jacobi-preconditioned Chebyshev iteration with
+//         direction d = x: acc += d, res -= K d, y = c1 d + c2 D^-1 res.
+// For modes 3, 4 and 6 a non-null st only guards: the launch is skipped once
+// CG has stopped.  y must not alias x (other workgroups read x around their
+// tiles).
 template <typename T, int MODE>
 __global__ void __launch_bounds__(TX* TY) kxu_tile_kernel(Grid g, int kc, const T* __restrict__ x,
                                                          const T* __restrict__ E,
@@ -255,6 +262,12 @@ __global__ void __launch_bounds__(TX* TY) kxu_tile_kernel(Grid g, int kc, const 
           if (MODE == 5) dot += (double)bv * (double)v2;
         } else if (MODE == 4) {
           v2 = fx ? T(0) : ep.bT[3 * n + c] - v2;
+        } else if (MODE == 6) {
+          const T dv = own_prev[c];
+          const T rn = fx ? T(0) : ep.res[3 * n + c] - v2;
+          ep.res[3 * n + c] = rn;
+          ep.acc[3 * n + c] = ep.first ? dv : ep.acc[3 * n + c] + dv;
+          v2 = fx ? T(0) : ep.c1 * dv + ep.c2 * ep.invd[n] * rn;
         }
         y[3 * n + c] = v2;
       }
@@ -262,7 +275,7 @@ __global__ void __launch_bounds__(TX* TY) kxu_tile_kernel(Grid g, int kc, const 
 #pragma unroll
     for (int c = 0; c < 3; ++c) own_prev[c] = cur.own[c];
   }
-  if (MODE == 0 || MODE == 3 || MODE == 4) return;
+  if (MODE == 0 || MODE == 3 || MODE == 4 || MODE == 6) return;
   double vv[1] = {dot};
   block_partials<1>(vv, partials);
 }
@@ -306,7 +319,8 @@ int64_t kxu_tile_blocks(const Grid& g) {
 
 template <typename T>
 hipError_t launch_kxu_tile(fe_problem* p, int lev, const T* x, const T* E, T* y, CgState* st, int mode,
-                           const double* b64, double* out, const T* bT, const T* invd, double omega) {
+                           const double* b64, double* out, const T* bT, const T* invd, double omega,
+                           const ChebStep<T>* cs) {
   const Grid g = p->L[lev].g;
   const int kc = kxu_levels_per_block(g);
   const dim3 grid = kxu_grid(g, kc);
@@ -316,6 +330,11 @@ hipError_t launch_kxu_tile(fe_problem* p, int lev, const T* x, const T* E, T* y,
   ep.bT = bT;
   ep.invd = invd;
   ep.omega = (T)omega;
+  ep.res = cs ? cs->res : nullptr;
+  ep.acc = cs ? cs->acc : nullptr;
+  ep.c1 = cs ? (T)cs->c1 : T(0);
+  ep.c2 = cs ? (T)cs->c2 : T(0);
+  ep.first = cs ? cs->first : 0;
   const uint8_t* nm = p->L[lev].nmask;
   // algorithmic bytes: read x and E, write y, plus b (modes 2-5) and the
   // Jacobi diagonal (modes 3, 5); each array touched once
@@ -325,7 +344,8 @@ hipError_t launch_kxu_tile(fe_problem* p, int lev, const T* x, const T* E, T* y,
     double bytes = vb * (2.0 * (double)g.ndof + (double)g.nelem);
     if (mode == 2) bytes += 8.0 * (double)g.ndof;
     if (mode >= 3) bytes += vb * (double)g.ndof;
-    if (mode == 3 || mode == 5) bytes += vb * (double)g.nnode;
+    if (mode == 3 || mode == 5 || mode == 6) bytes += vb * (double)g.nnode;
+    if (mode == 6) bytes += vb * 3.0 * (double)g.ndof;  // res in/out, acc in/out (res read counted above)
     slot = kstats_begin(p, bytes);
   }
   switch (mode) {
@@ -349,6 +369,10 @@ hipError_t launch_kxu_tile(fe_problem* p, int lev, const T* x, const T* E, T* y,
       hipLaunchKernelGGL((kxu_tile_kernel<T, 5>), grid, dim3(TX * TY), 0, p->stream, g, kc, x, E, nm, wk,
                          y, ep, st, p->partials, out);
       break;
+    case 6:
+      hipLaunchKernelGGL((kxu_tile_kernel<T, 6>), grid, dim3(TX * TY), 0, p->stream, g, kc, x, E, nm, wk,
+                         y, ep, st, p->partials, out);
+      break;
     default:
       hipLaunchKernelGGL((kxu_tile_kernel<T, 0>), grid, dim3(TX * TY), 0, p->stream, g, kc, x, E, nm, wk,
                          y, ep, st, p->partials, out);
@@ -365,6 +389,7 @@ hipError_t launch_kxu_tile(fe_problem* p, int lev, const T* x, const T* E, T* y,
 
 template hipError_t launch_kxu_tile<double>(fe_problem*, int, const double*, const double*, double*,
                                             CgState*, int, const double*, double*, const double*,
-                                            const double*, double);
+                                            const double*, double, const ChebStep<double>*);
 template hipError_t launch_kxu_tile<float>(fe_problem*, int, const float*, const float*, float*, CgState*,
-                                           int, const double*, double*, const float*, const float*, double);
+                                           int, const double*, double*, const float*, const float*, double,
+                                           const ChebStep<float>*);

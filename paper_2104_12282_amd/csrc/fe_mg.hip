@@ -127,17 +127,52 @@ hipError_t jacobi_sweeps(fe_problem* p, int l, const T* r, T* z, T* t, int n, Cg
   return e;
 }
 
+// Coarsest-level solve: `deg` steps of Jacobi-preconditioned Chebyshev
+// iteration from z = 0 on the interval [lam_max / ratio, lam_max], where
+// lam_max bounds the spectrum of D^-1 K from above.  The result is a fixed
+// polynomial in D^-1 K applied to D^-1 r: linear, symmetric and (since the
+// Chebyshev residual polynomial stays inside (0, 1) below the interval and
+// below 1 in magnitude on it) positive definite.  r is overwritten by the
+// final residual.
+template <typename T>
+hipError_t chebyshev_solve(fe_problem* p, int l, T* r, T* z, T* d0, T* d1, int deg, CgState* st) {
+  const Level& L = p->L[l];
+  const double b = 1.02 * p->lam_max, a = b / p->cheb_ratio;
+  const double theta = 0.5 * (b + a), delta = 0.5 * (b - a), sigma = theta / delta;
+  double rho = 1.0 / sigma;
+  // d0 = D^-1 r / theta
+  hipLaunchKernelGGL(jacobi0_kernel<T>, dim3(nblocks(L.g.ndof)), dim3(FE_BLOCK), 0, p->stream, L.g.ndof, r,
+                     lev_invd<T>(L), (T)(1.0 / theta), d0, st);
+  hipError_t e = hipGetLastError();
+  for (int k = 0; k < deg && e == hipSuccess; ++k) {
+    const double rho_new = 1.0 / (2.0 * sigma - rho);
+    ChebStep<T> cs;
+    cs.res = r;
+    cs.acc = z;
+    cs.c1 = rho_new * rho;
+    cs.c2 = 2.0 * rho_new / delta;
+    cs.first = k == 0;
+    e = launch_kxu_tile<T>(p, l, d0, lev_E<T>(L), d1, st, 6, nullptr, nullptr, nullptr, lev_invd<T>(L), 0.0, &cs);
+    rho = rho_new;
+    T* tmp = d0;
+    d0 = d1;
+    d1 = tmp;
+  }
+  return e;
+}
+
 }  // namespace
 
 // z = V(r): one symmetric V-cycle on levels l .. nlev-1 (pre- and
-// post-smoothing with mg_nu damped Jacobi sweeps, mg_coarse sweeps on the
-// coarsest level).  st (may be null) guards the launches; with fuse_rz the
+// post-smoothing with mg_nu damped Jacobi sweeps, a Chebyshev solve of
+// degree mg_coarse_sweeps on the coarsest level).  st (may be null) guards the launches; with fuse_rz the
 // last sweep on level 0 also forms r^T z and the CG direction factor.
 template <typename T>
 hipError_t launch_vcycle(fe_problem* p, int l, const T* r, T* z, CgState* st, bool fuse_rz) {
   const Level& L = p->L[l];
   T* t = static_cast<T*>(L.mg_t);
-  if (l == p->nlev - 1) return jacobi_sweeps<T>(p, l, r, z, t, p->mg_coarse_sweeps, st);
+  if (l == p->nlev - 1)  // r is this level's own restricted residual: free to overwrite
+    return chebyshev_solve<T>(p, l, const_cast<T*>(r), z, t, static_cast<T*>(L.mg_w), p->mg_coarse_sweeps, st);
   hipError_t e = jacobi_sweeps<T>(p, l, r, z, t, p->mg_nu, st);
   if (e != hipSuccess) return e;
   // t = r - K z, restricted to the next level's right-hand side

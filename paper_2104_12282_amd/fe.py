@@ -185,7 +185,7 @@ class Problem:
                                         _ptr(xn), _ptr(ch)))
         return xn, ch
 
-    def set_mg_params(self, nu=1, coarse_sweeps=30, omega=0.35):
+    def set_mg_params(self, nu=1, coarse_sweeps=20, omega=0.35):
         _check(load_library().fe_set_mg_params(self._h, nu, coarse_sweeps, omega))
 
     def set_profiling(self, on: bool):

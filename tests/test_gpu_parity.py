@@ -225,6 +225,8 @@ def test_gmg_params_validation():
     prob = _problem(16, 8, 8, precond="gmg", mg_levels=3)
     with pytest.raises(fe.FEError):
         prob.set_mg_params(nu=0)
+    with pytest.raises(fe.FEError):  # unstable smoother: omega * 5.32 >= 2
+        prob.set_mg_params(omega=0.6)
     prob.set_mg_params(nu=2, coarse_sweeps=10, omega=0.3)
     rho = synth.density_around(16, 8, 8, 1)
     _, info = prob.solve(T(rho), rtol=1e-9)
