@@ -2,10 +2,13 @@
 
 A step is one iteration of the density-based optimisation loop on the
 paper-scale cantilever (224 x 112 x 56 bricks, 1,404,928 design variables):
-  rho = P x;  u = K(rho)^-1 f (warm-started CG to 1e-6);  dc = dc/drho;
-  dcx = P^T dc;  x = OC(x, dcx, dv)   (volume fraction 0.12, move 0.2).
-Warm-up steps run first; the timed steps continue the same trajectory.
-Prints one JSON line.
+  rho = P x;  u = K(rho)^-1 f (CG with a 3-level geometric multigrid
+  preconditioner, warm-started, to 1e-6);  dc = dc/drho;  dcx = P^T dc;
+  x = OC(x, dcx, dv)   (volume fraction 0.12, move limit 0.2).
+Warm-up steps run first; the design is then reset to the uniform start and
+the timed steps are the first `--steps` iterations of the loop (50 by
+default: the whole loop).  The same loop is then run untimed-for-roofline in
+the alternative precision and reported under "alt".  Prints one JSON line.
 """
 from __future__ import annotations
 
@@ -27,32 +30,45 @@ HBM_PEAK_GBS = 8000.0  # MI355X HBM3E, AMD published figure
 def parse():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
-    ap.add_argument("--steps", type=int, default=5)
+    ap.add_argument("--steps", type=int, default=50)
     ap.add_argument("--warmup", type=int, default=2)
     ap.add_argument("--grid", type=str, default="224x112x56")
-    ap.add_argument("--precision", default="fp32_ir", choices=["fp64", "fp32_ir", "bf16_ir"])
-    ap.add_argument("--precond", default="jacobi", choices=["jacobi", "gmg"])
+    ap.add_argument("--precision", default="fp64", choices=["fp64", "fp32_ir", "bf16_ir"])
+    ap.add_argument("--alt-precision", default="fp32_ir", choices=["none", "fp64", "fp32_ir", "bf16_ir"])
+    ap.add_argument("--precond", default="gmg", choices=["jacobi", "gmg"])
     ap.add_argument("--mg-levels", type=int, default=3)
+    ap.add_argument("--mg-nu", type=int, default=1)
+    ap.add_argument("--mg-coarse", type=int, default=20)
     ap.add_argument("--rtol", type=float, default=1e-6)
+    ap.add_argument("--volfrac", type=float, default=0.12)
+    ap.add_argument("--move", type=float, default=0.2)
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--cpu-grid", type=str, default="80x40x20")
+    ap.add_argument("--copy-probe", action="store_true",
+                    help="also run one device-to-device copy of 512 MiB (reference for counters)")
     return ap.parse_args()
 
 
-def traffic_from_profiles(kernel_key: str):
-    """HBM bytes per launch measured by rocprofv3 counters, when the stored
-    figure was taken on the current kernel source; else None."""
-    path = os.path.join(ROOT, "profiles", "kxu_traffic.json")
+def traffic_from_profiles(precision: str, grid: str):
+    """HBM bytes (fetched + written) of one CG-product launch of the tiled K*u
+    kernel on this grid, from rocprofv3 FETCH_SIZE / WRITE_SIZE counters scaled
+    by a copy of known size, when the stored figure was taken on the current
+    kernel source; else None."""
+    path = os.path.join(ROOT, "profiles", f"kxu_tile_{grid}_traffic.json")
     if not os.path.exists(path):
         return None
     try:
         rec = json.load(open(path))
         from paper_2104_12282_amd.build import source_digest
-        if rec.get("source_digest") != source_digest() or kernel_key not in rec.get("kernels", {}):
+        if rec.get("source_digest") != source_digest():
             return None
-        return rec["kernels"][kernel_key]["bytes_per_launch"]
+        want = f"kxu_tile_kernel<{'double' if precision == 'fp64' else 'float'}, 1>"
+        for name, k in rec["kernels"].items():
+            if want in name:
+                return k["fetch_bytes"] + k["write_bytes"]
     except Exception:
         return None
+    return None
 
 
 def cpu_baseline(grid, rtol):
@@ -87,6 +103,67 @@ def cpu_baseline(grid, rtol):
             "seconds": dt}
 
 
+def run_loop(fe, synth, torch, nx, ny, nz, precision, args, steps, warmup, profile):
+    """Warm-up steps, then `steps` timed optimisation steps from the start
+    design (the timed steps are iterations 0 .. steps-1 of the loop)."""
+    ne = nx * ny * nz
+    dev = "cuda:0"
+    T = lambda a: torch.as_tensor(a, dtype=torch.float64, device=dev)
+    f = synth.cantilever_edge_load(nx, ny, nz)
+    prob = fe.Problem(nx, ny, nz, T(f), device=dev, precision=precision, precond=args.precond,
+                      mg_levels=args.mg_levels)
+    if args.precond == "gmg":
+        prob.set_mg_params(nu=args.mg_nu, coarse_sweeps=args.mg_coarse)
+    x = torch.empty(ne, dtype=torch.float64, device=dev)
+    u = torch.empty(prob.ndof, dtype=torch.float64, device=dev)
+    rho = torch.empty_like(x)
+    dc = torch.empty_like(x)
+    dcx = torch.empty_like(x)
+    dv = prob.filter(torch.ones_like(x), transpose=True)
+    comp = torch.zeros(1, dtype=torch.float64, device=dev)
+    change = torch.zeros(1, dtype=torch.float64, device=dev)
+    rec = {"iters": [], "compliance": []}
+
+    def reset():
+        x.fill_(args.volfrac)
+        u.zero_()
+
+    def step():
+        prob.filter(x, out=rho)
+        _, info = prob.solve(rho, u=u, rtol=args.rtol)
+        prob.sensitivity(rho, u, out=dc, compliance_out=comp)
+        prob.filter(dc, transpose=True, out=dcx)
+        prob.oc_update(x, dcx, dv, args.volfrac, args.move, out=x, change_out=change)
+        rec["iters"].append(info["iters"])
+        rec["compliance"].append(info["compliance"])
+        return info
+
+    reset()
+    for i in range(warmup):
+        info = step()
+        print(f"bench[{precision}]: warmup {i} iters {info['iters']} c {info['compliance']:.6g}",
+              file=sys.stderr, flush=True)
+    reset()
+    rec["iters"].clear()
+    rec["compliance"].clear()
+    torch.cuda.synchronize()
+    prob.kernel_stats(reset=True)
+    prob.set_profiling(profile)
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    for i in range(steps):
+        info = step()
+        if i % 10 == 0 or i == steps - 1:
+            print(f"bench[{precision}]: step {i} iters {info['iters']} outer {info['outer_iters']} "
+                  f"rel_res {info['rel_res']:.2e} c {info['compliance']:.6g}", file=sys.stderr, flush=True)
+    torch.cuda.synchronize()
+    dt = time.perf_counter() - t0
+    prob.set_profiling(False)
+    ks = prob.kernel_stats(reset=True)
+    prob.close()
+    return dt, rec, ks, prob.ndof
+
+
 def main():
     args = parse()
     if args.gpus != 1:
@@ -98,55 +175,22 @@ def main():
 
     nx, ny, nz = (int(v) for v in args.grid.split("x"))
     ne = nx * ny * nz
-    dev = "cuda:0"
     torch.cuda.set_device(0)
-    T = lambda a: torch.as_tensor(a, dtype=torch.float64, device=dev)
-    f = synth.cantilever_edge_load(nx, ny, nz)
-    prob = fe.Problem(nx, ny, nz, T(f), device=dev, precision=args.precision,
-                      precond=args.precond, mg_levels=args.mg_levels)
-    x = torch.full((ne,), 0.12, dtype=torch.float64, device=dev)
-    u = torch.zeros(prob.ndof, dtype=torch.float64, device=dev)
-    rho = torch.empty_like(x)
-    dc = torch.empty_like(x)
-    dcx = torch.empty_like(x)
-    dv = prob.filter(torch.ones_like(x), transpose=True)
-    comp = torch.zeros(1, dtype=torch.float64, device=dev)
-    change = torch.zeros(1, dtype=torch.float64, device=dev)
-    iters = []
-
-    def step():
-        prob.filter(x, out=rho)
-        _, info = prob.solve(rho, u=u, rtol=args.rtol)
-        prob.sensitivity(rho, u, out=dc, compliance_out=comp)
-        prob.filter(dc, transpose=True, out=dcx)
-        prob.oc_update(x, dcx, dv, 0.12, 0.2, out=x, change_out=change)
-        iters.append(info["iters"])
-        return info
-
+    probe = None
+    if args.copy_probe:
+        nbytes = 512 << 20
+        src = torch.ones(nbytes // 8, dtype=torch.float64, device="cuda:0")
+        dst = torch.empty_like(src)
+        dst.copy_(src)
+        torch.cuda.synchronize()
+        del src, dst
+        probe = {"bytes": nbytes}
     print(f"bench: grid {nx}x{ny}x{nz} precision {args.precision} precond {args.precond}",
           file=sys.stderr, flush=True)
-    for i in range(args.warmup):
-        info = step()
-        print(f"bench: warmup {i} iters {info['iters']} c {info['compliance']:.6g}",
-              file=sys.stderr, flush=True)
-    torch.cuda.synchronize()
-    prob.kernel_stats(reset=True)
-    prob.set_profiling(True)
-    iters.clear()
-    torch.cuda.synchronize()
-    t0 = time.perf_counter()
-    for i in range(args.steps):
-        info = step()
-        print(f"bench: step {i} iters {info['iters']} outer {info['outer_iters']} "
-              f"rel_res {info['rel_res']:.2e} c {info['compliance']:.6g}", file=sys.stderr, flush=True)
-    torch.cuda.synchronize()
-    dt = time.perf_counter() - t0
-    prob.set_profiling(False)
-    ks = prob.kernel_stats(reset=True)
-
+    dt, rec, ks, ndof = run_loop(fe, synth, torch, nx, ny, nz, args.precision, args, args.steps,
+                                 args.warmup, profile=True)
     avg_ms = ks["total_ms"] / max(1, ks["launches"])
     achieved = ks["bytes_per_launch"] / (avg_ms * 1e-3) / 1e9 if ks["launches"] else 0.0
-    kkey = f"kxu_{'f64' if args.precision == 'fp64' else 'f32'}_{nx}x{ny}x{nz}"
     out = {
         "metric": "FE solves/s at 1.4M elements (one optimisation step = one solve)",
         "value": args.steps / dt,
@@ -160,18 +204,33 @@ def main():
         "vs_baseline": None,
         "dtype": "f64" if args.precision == "fp64" else "f32 (f64 refinement and dots)",
         "data": "synthetic (seeded cantilever, uniform start density 0.12)",
-        "config": {"workload": f"cantilever {nx}x{ny}x{nz} optimisation step",
-                   "grid": [nx, ny, nz], "elements": ne, "dofs": prob.ndof,
+        "config": {"workload": f"cantilever {nx}x{ny}x{nz} optimisation loop, first {args.steps} "
+                               f"iterations",
+                   "grid": [nx, ny, nz], "elements": ne, "dofs": ndof,
                    "precision": args.precision, "precond": args.precond,
                    "mg_levels": args.mg_levels if args.precond == "gmg" else None,
-                   "rtol": args.rtol, "volfrac": 0.12, "filter_r": 1.5, "move": 0.2,
-                   "cg_iters_per_solve": float(np.mean(iters)) if iters else None},
+                   "rtol": args.rtol, "volfrac": args.volfrac, "filter_r": 1.5, "move": args.move,
+                   "cg_iters_per_solve": float(np.mean(rec["iters"])),
+                   "cg_iters_max": int(np.max(rec["iters"])),
+                   "compliance_first": rec["compliance"][0], "compliance_last": rec["compliance"][-1]},
         "roofline": {"bound": "hbm", "achieved": achieved, "peak": HBM_PEAK_GBS, "unit": "GB/s",
-                     "frac": achieved / HBM_PEAK_GBS, "traffic": traffic_from_profiles(kkey),
-                     "kernel": "matrix-free K*u", "launches": ks["launches"],
-                     "avg_launch_us": avg_ms * 1e3,
+                     "frac": achieved / HBM_PEAK_GBS,
+                     "traffic": traffic_from_profiles(args.precision, f"{nx}x{ny}x{nz}"),
+                     "traffic_of": "one CG-product launch (rocprofv3 counters, copy-scaled)",
+                     "kernel": "matrix-free K*u (tiled, finest grid, all epilogues)",
+                     "launches": ks["launches"], "avg_launch_us": avg_ms * 1e3,
                      "algorithmic_bytes_per_launch": ks["bytes_per_launch"]},
     }
+    if probe:
+        out["copy_probe"] = probe
+    if args.alt_precision != "none":
+        dt2, rec2, _, _ = run_loop(fe, synth, torch, nx, ny, nz, args.alt_precision, args, args.steps,
+                                   0, profile=False)
+        c1, c2 = np.array(rec["compliance"]), np.array(rec2["compliance"])
+        out["alt"] = {"precision": args.alt_precision, "value": args.steps / dt2,
+                      "ms_per_step": 1e3 * dt2 / args.steps,
+                      "cg_iters_per_solve": float(np.mean(rec2["iters"])),
+                      "compliance_max_rel_diff": float(np.max(np.abs(c2 - c1) / np.abs(c1)))}
     if not args.no_cpu_baseline:
         cg = tuple(int(v) for v in args.cpu_grid.split("x"))
         out["cpu_baseline"] = cpu_baseline(cg, args.rtol)

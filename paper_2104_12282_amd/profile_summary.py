@@ -1,0 +1,95 @@
+"""Turns rocprofv3 CSV output into the short text summaries kept under
+profiles/.
+
+  python -m paper_2104_12282_amd.profile_summary stats <kernel_stats.csv> <out.md> "<command>"
+  python -m paper_2104_12282_amd.profile_summary traffic <fetch_dir> <write_dir> <bench.json> <out.json> "<commands>"
+
+`traffic` reads two counter runs (FETCH_SIZE, then WRITE_SIZE, in KiB per
+dispatch), scales each by what the same counter reads for the plain copy of
+known size that bench.py --copy-probe performs (hipMemcpy device-to-device,
+kernel __amd_rocclr_copyBuffer), and stores the bytes per launch of the tiled
+K*u kernel next to the digest of the sources it was measured on.
+"""
+from __future__ import annotations
+
+import csv
+import glob
+import json
+import os
+import sys
+
+
+def _rows(path):
+    with open(path, newline="") as fh:
+        return list(csv.DictReader(fh))
+
+
+def stats(csv_path, out_path, command):
+    rows = _rows(csv_path)
+    rows.sort(key=lambda r: -float(r["TotalDurationNs"]))
+    total = sum(float(r["TotalDurationNs"]) for r in rows)
+    lines = ["# rocprofv3 kernel statistics", "", f"Command: `{command}`", "",
+             "| kernel | calls | total ms | avg us | min us | max us | % |",
+             "|---|---:|---:|---:|---:|---:|---:|"]
+    for r in rows[:20]:
+        name = r["Name"]
+        if len(name) > 90:
+            name = name[:90] + "..."
+        lines.append(f"| `{name}` | {r['Calls']} | {float(r['TotalDurationNs']) / 1e6:.3f} | "
+                     f"{float(r['AverageNs']) / 1e3:.2f} | {float(r['MinNs']) / 1e3:.2f} | "
+                     f"{float(r['MaxNs']) / 1e3:.2f} | {100 * float(r['TotalDurationNs']) / total:.1f} |")
+    with open(out_path, "w") as fh:
+        fh.write("\n".join(lines) + "\n")
+
+
+def _counter_by_kernel(run_dir, counter):
+    files = glob.glob(os.path.join(run_dir, "**", "*counter_collection.csv"), recursive=True)
+    if not files:
+        raise SystemExit(f"no counter_collection.csv under {run_dir}")
+    out = {}
+    for r in _rows(files[0]):
+        if r.get("Counter_Name") != counter:
+            continue
+        out.setdefault(r["Kernel_Name"], []).append(float(r["Counter_Value"]))
+    return out
+
+
+def traffic(fetch_dir, write_dir, bench_json, out_path, command):
+    sys.path.insert(0, os.path.dirname(os.path.dirname(os.path.abspath(__file__))))
+    from paper_2104_12282_amd.build import source_digest
+    probe = json.load(open(bench_json))["copy_probe"]
+    fetch = _counter_by_kernel(fetch_dir, "FETCH_SIZE")
+    write = _counter_by_kernel(write_dir, "WRITE_SIZE")
+
+    def pick(d, key):
+        vals = [v for k, vs in d.items() if key in k for v in vs]
+        return vals
+
+    copy_f = max(pick(fetch, "copyBuffer"))  # the probe is the largest copy
+    copy_w = max(pick(write, "copyBuffer"))
+    f_scale = probe["bytes"] / (copy_f * 1024.0)
+    w_scale = probe["bytes"] / (copy_w * 1024.0)
+    rec = {"source_digest": source_digest(), "command": command,
+           "copy_probe_bytes": probe["bytes"], "copy_fetch_kib": copy_f, "copy_write_kib": copy_w,
+           "fetch_scale": f_scale, "write_scale": w_scale, "kernels": {}}
+    for mode_key in sorted({k for k in fetch if "kxu_tile_kernel" in k}):
+        fk = fetch[mode_key]
+        wk = write.get(mode_key, [])
+        if not wk:
+            continue
+        # the finest grid's launches are the largest of each kernel variant
+        fmax, wmax = max(fk), max(wk)
+        rec["kernels"][mode_key] = {"fetch_bytes": fmax * 1024 * f_scale,
+                                    "write_bytes": wmax * 1024 * w_scale,
+                                    "launches_seen": len(fk)}
+    with open(out_path, "w") as fh:
+        json.dump(rec, fh, indent=1)
+
+
+if __name__ == "__main__":
+    if sys.argv[1] == "stats":
+        stats(sys.argv[2], sys.argv[3], sys.argv[4])
+    elif sys.argv[1] == "traffic":
+        traffic(sys.argv[2], sys.argv[3], sys.argv[4], sys.argv[5], sys.argv[6])
+    else:
+        raise SystemExit(__doc__)
