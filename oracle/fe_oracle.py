@@ -340,7 +340,7 @@ def oc_update(x, dcx, dv, volfrac, move, rel_tol=1e-12):
         return np.clip(x * np.sqrt(B / lam), lo, hi)
 
     l1, l2 = 0.0, 1e9
-    while np.sum(dv * x_of(l2)) > target:     # widen until the bracket holds
+    while np.sum(dv * x_of(l2)) > target and l2 < 1e300:   # widen until the bracket holds
         l2 *= 10.0
     while (l2 - l1) > rel_tol * (l1 + l2):
         lmid = 0.5 * (l1 + l2)

@@ -479,7 +479,9 @@ __global__ void __launch_bounds__(FE_BLOCK) filter_kernel(Grid g, Stencil s, con
 // a = x sqrt(max(0, -dcx) / dv); the volume sum(dv x_new) is continuous and
 // non-decreasing in s.  Each pass evaluates the volume at OC_NC points inside
 // the current bracket [s_lo, s_hi] and keeps the sub-interval that contains
-// the target.
+// the target, until the bracket on lambda is relatively 1e-12 wide (the
+// oracle's bisection tolerance).  A target above the largest reachable
+// volume leaves s = s_hi (every element with a > 0 at its upper bound).
 #define OC_NC 64
 struct OcState {
   double s_lo, s_hi, target, lam;
@@ -515,18 +517,24 @@ __global__ void __launch_bounds__(FE_BLOCK) oc_prep_finalize(int nb, const doubl
   const double smax = reduce_partials_max(partials, nb);
   if (threadIdx.x == 0) {
     os->s_lo = 0.0;
-    os->s_hi = smax * (1.0 + 1e-15) + 1e-300;
+    os->s_hi = smax * (1.0 + 1e-15);
     os->target = target;
-    os->done = 0;
     os->pass = 0;
+    // no element with a > 0: every element sits at its lower bound for any s
+    os->done = smax > 0.0 ? 0 : 1;
   }
 }
 
-// Pass 0 spaces the candidates geometrically over s_hi * [2^-100, 1]; later
-// passes space them evenly inside the bracket.
+// Candidate c of the current bracket [s_lo, s_hi].  While s_lo = 0 they step
+// down from s_hi by factors of 2^16 (the volume is flat below the smallest
+// a-scale, which can be 1e-300 for void elements, so the multiplier may lie
+// many decades below s_hi); while s_hi / s_lo is large they are spaced
+// geometrically, and once the bracket is narrow, evenly.
 __device__ inline double oc_candidate(const OcState* os, int c) {
-  if (os->pass == 0) return os->s_hi * exp2(-100.0 * (double)(OC_NC - 1 - c) / (OC_NC - 1));
-  return os->s_lo + (os->s_hi - os->s_lo) * (double)(c + 1) / (double)(OC_NC + 1);
+  const double lo = os->s_lo, hi = os->s_hi;
+  if (lo == 0.0) return hi * exp2(-16.0 * (double)(OC_NC - c));
+  if (hi > 1.5 * lo) return lo * exp2(log2(hi / lo) * (double)(c + 1) / (double)(OC_NC + 1));
+  return lo + (hi - lo) * (double)(c + 1) / (double)(OC_NC + 1);
 }
 
 __global__ void __launch_bounds__(FE_BLOCK) oc_pass_kernel(int64_t n, const double* __restrict__ x,
@@ -886,7 +894,7 @@ hipError_t launch_oc(fe_problem* p, const double* x, const double* dcx, const do
   const int nb = red_grid(n);
   hipLaunchKernelGGL(oc_prep_kernel, dim3(nb), dim3(FE_BLOCK), 0, p->stream, n, x, dcx, dv, move, p->partials);
   hipLaunchKernelGGL(oc_prep_finalize, dim3(1), dim3(FE_BLOCK), 0, p->stream, nb, p->partials, target, os);
-  for (int pass = 0; pass < 12; ++pass) {
+  for (int pass = 0; pass < 24; ++pass) {  // passes after convergence return at once
     hipLaunchKernelGGL(oc_pass_kernel, dim3(nb), dim3(FE_BLOCK), 0, p->stream, n, x, dcx, dv, move, os,
                        p->partials);
     hipLaunchKernelGGL(oc_pass_finalize, dim3(1), dim3(FE_BLOCK), 0, p->stream, nb, p->partials, os);

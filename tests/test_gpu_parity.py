@@ -231,3 +231,56 @@ def test_gmg_params_validation():
     rho = synth.density_around(16, 8, 8, 1)
     _, info = prob.solve(T(rho), rtol=1e-9)
     assert info["rel_res"] <= 1e-9
+
+
+def test_oc_extreme_dynamic_range():
+    """Late designs have void elements with x ~ 1e-50 and dc ~ 1e-80: the
+    multiplier then lies hundreds of decades below the largest a-scale."""
+    nx, ny, nz = 20, 10, 6
+    n = nx * ny * nz
+    rng = np.random.default_rng(21)
+    x = np.where(rng.random(n) < 0.7, 10.0 ** rng.uniform(-60, -20, n), rng.uniform(0.2, 1.0, n))
+    dcx = -np.where(x < 1e-10, 10.0 ** rng.uniform(-90, -40, n), rng.uniform(1e-3, 1.0, n))
+    dv = O.filter_matrix(nx, ny, nz, 1.5).T @ np.ones(n)
+    volfrac, move = 0.12, 0.2
+    xn_ref, lam_ref, ch_ref = O.oc_update(x, dcx, dv, volfrac, move)
+    prob = _problem(nx, ny, nz)
+    xn, ch = prob.oc_update(T(x), T(dcx), T(dv), volfrac, move)
+    xn = N(xn)
+    assert abs(np.sum(dv * xn) - volfrac * n) <= 1e-10 * volfrac * n
+    assert np.abs(xn - xn_ref).max() <= 1e-9
+
+
+@pytest.mark.parametrize("precond", ["jacobi", "gmg"])
+def test_optimisation_trajectory(Ke, precond):
+    """Twelve iterations of the whole loop (filter, solve, sensitivity,
+    transpose filter, OC) from the uniform start: the GPU's compliance history
+    follows the oracle's."""
+    nx, ny, nz = 32, 16, 8
+    ne = nx * ny * nz
+    f = synth.cantilever_edge_load(nx, ny, nz)
+    fixed = O.clamp_x0_fixed(nx, ny, nz)
+    P = O.filter_matrix(nx, ny, nz, 1.5)
+    dv_ref = P.T @ np.ones(ne)
+    x_ref = np.full(ne, 0.12)
+    c_ref = []
+    for _ in range(12):
+        rho = P @ x_ref
+        u = O.solve_direct(nx, ny, nz, O.simp_modulus(rho), Ke, f, fixed)
+        c_ref.append(O.compliance(f, u))
+        dc = O.sensitivity(nx, ny, nz, Ke, rho, u)
+        x_ref, _, _ = O.oc_update(x_ref, P.T @ dc, dv_ref, 0.12, 0.2)
+    prob = _problem(nx, ny, nz, precond=precond, mg_levels=3)
+    x = T(np.full(ne, 0.12))
+    u = torch.zeros(prob.ndof, dtype=torch.float64, device=DEV)
+    dv = prob.filter(torch.ones_like(x), transpose=True)
+    c_gpu = []
+    for _ in range(12):
+        rho = prob.filter(x)
+        _, info = prob.solve(rho, u=u, rtol=1e-10)
+        c_gpu.append(info["compliance"])
+        dc, _ = prob.sensitivity(rho, u)
+        x, _ = prob.oc_update(x, prob.filter(dc, transpose=True), dv, 0.12, 0.2)
+    rel = np.abs(np.array(c_gpu) - np.array(c_ref)) / np.array(c_ref)
+    assert rel.max() <= 1e-6, rel
+    assert np.abs(N(x) - x_ref).max() <= 1e-6
