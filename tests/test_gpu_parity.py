@@ -242,13 +242,20 @@ def test_oc_extreme_dynamic_range():
     x = np.where(rng.random(n) < 0.7, 10.0 ** rng.uniform(-60, -20, n), rng.uniform(0.2, 1.0, n))
     dcx = -np.where(x < 1e-10, 10.0 ** rng.uniform(-90, -40, n), rng.uniform(1e-3, 1.0, n))
     dv = O.filter_matrix(nx, ny, nz, 1.5).T @ np.ones(n)
-    volfrac, move = 0.12, 0.2
-    xn_ref, lam_ref, ch_ref = O.oc_update(x, dcx, dv, volfrac, move)
+    move = 0.2
     prob = _problem(nx, ny, nz)
+    # reachable target (between the all-lower and all-upper volumes 0.128, 0.383)
+    volfrac = 0.2
+    xn_ref, lam_ref, ch_ref = O.oc_update(x, dcx, dv, volfrac, move)
     xn, ch = prob.oc_update(T(x), T(dcx), T(dv), volfrac, move)
     xn = N(xn)
     assert abs(np.sum(dv * xn) - volfrac * n) <= 1e-10 * volfrac * n
     assert np.abs(xn - xn_ref).max() <= 1e-9
+    # unreachable target below the all-lower volume: every element at its lower bound
+    xn2, _ = prob.oc_update(T(x), T(dcx), T(dv), 0.12, move)
+    assert np.array_equal(N(xn2), np.maximum(0.0, x - move))
+    xn2_ref, _, _ = O.oc_update(x, dcx, dv, 0.12, move)
+    assert np.abs(xn2_ref - np.maximum(0.0, x - move)).max() <= 1e-300
 
 
 @pytest.mark.parametrize("precond", ["jacobi", "gmg"])
