@@ -507,7 +507,9 @@ __global__ void __launch_bounds__(FE_BLOCK) oc_prep_kernel(int64_t n, const doub
        e += (int64_t)gridDim.x * FE_BLOCK) {
     double a, lo, hi, w;
     oc_elem(x, dcx, dv, e, move, a, lo, hi, w);
-    if (a > 0.0) smax = fmax(smax, hi / a);
+    // a can be subnormal for long-void elements: keep the bound finite (such
+    // elements reach their upper bound only beyond s = 1e300)
+    if (a > 0.0) smax = fmax(smax, fmin(hi / a, 1e300));
   }
   block_partial_max(smax, partials);
 }

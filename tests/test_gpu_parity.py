@@ -241,6 +241,9 @@ def test_oc_extreme_dynamic_range():
     rng = np.random.default_rng(21)
     x = np.where(rng.random(n) < 0.7, 10.0 ** rng.uniform(-60, -20, n), rng.uniform(0.2, 1.0, n))
     dcx = -np.where(x < 1e-10, 10.0 ** rng.uniform(-90, -40, n), rng.uniform(1e-3, 1.0, n))
+    x[:40] = 0.0            # elements driven to zero
+    x[40:80] = 1e-310       # subnormal densities
+    dcx[80:90] = 0.0        # no descent information
     dv = O.filter_matrix(nx, ny, nz, 1.5).T @ np.ones(n)
     move = 0.2
     prob = _problem(nx, ny, nz)
