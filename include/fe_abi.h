@@ -116,6 +116,21 @@ FE_API fe_status fe_apply_K(fe_problem* p, const double* rho, const double* u, d
 FE_API fe_status fe_solve(fe_problem* p, const double* rho, double* u, double rtol,
                    int32_t max_iters, fe_solve_info* info);
 
+/* The same solve without blocking, for callers that keep several problems in
+ * flight on different streams (continuous batching):
+ *   fe_solve_begin enqueues the start of the solve and returns;
+ *   fe_solve_step advances it by at most one stage if the previous stage
+ *     has completed on the device (never waits), *done = 1 once finished;
+ *   fe_solve_end returns the status and info of a finished solve.
+ * The arithmetic is exactly that of fe_solve (which is begin, step until
+ * done, end), so a design's result does not depend on what else runs.
+ * u and rho must stay valid until the solve is finished; one solve per
+ * problem at a time (FE_EINVAL otherwise). */
+FE_API fe_status fe_solve_begin(fe_problem* p, const double* rho, double* u, double rtol,
+                                int32_t max_iters);
+FE_API fe_status fe_solve_step(fe_problem* p, int32_t* done);
+FE_API fe_status fe_solve_end(fe_problem* p, fe_solve_info* info);
+
 /* Gradient of the compliance with respect to the physical density (Eq. 5):
  *   dc[e] = -penal rho_e^(penal-1) (E0 - Emin) u_e^T Ke u_e.
  * compliance: device float64 scalar receiving f^T u, may be NULL.

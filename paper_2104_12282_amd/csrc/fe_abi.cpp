@@ -5,8 +5,11 @@
 #include <cmath>
 #include <cstdio>
 #include <cstring>
+#include <mutex>
 #include <new>
 #include <string>
+#include <utility>
+#include <vector>
 
 #include "fe_internal.h"
 
@@ -111,6 +114,7 @@ size_t layout(const fe_config* c, fe_problem* p, char* base) {
   double* p64 = (double*)take(g0.ndof * sizeof(double));
   double* q64 = (double*)take(g0.ndof * sizeof(double));
   double* tmp64 = (double*)take(g0.ndof * sizeof(double));
+  double* x64 = (double*)take(g0.ndof * sizeof(double));
   float *x32 = nullptr, *r32 = nullptr, *p32 = nullptr, *q32 = nullptr;
   if (f32) {
     x32 = (float*)take(g0.ndof * sizeof(float));
@@ -136,6 +140,7 @@ size_t layout(const fe_config* c, fe_problem* p, char* base) {
     p->p64 = p64;
     p->q64 = q64;
     p->tmp64 = tmp64;
+    p->x64 = x64;
     p->x32 = x32;
     p->r32 = r32;
     p->p32 = p32;
@@ -190,110 +195,341 @@ fe_status prepare_operator(fe_problem* p, const double* rho) {
   return FE_OK;
 }
 
-constexpr int kChunk = 24;    // Jacobi-PCG iterations enqueued between host checks
-constexpr int kChunkMG = 8;   // multigrid-PCG iterations enqueued between host checks
+constexpr int kChunk = 24;    // Jacobi-PCG iterations per enqueued chunk
+constexpr int kChunkMG = 8;   // multigrid-PCG iterations per enqueued chunk
+constexpr int kMaxOuter = 40; // float64 refinement steps
 
-// Preconditioned CG on level 0 with vectors of type T, from the state set by
-// cg_start.  Returns the CgState at exit.
+enum { ST_DONE = 0, ST_CG64 = 1, ST_IR_RESID = 2, ST_IR_CG = 3, ST_FINISH = 4 };
+
+// One CG iteration: q = K p (alpha), x/r update and convergence test, the
+// preconditioner (multigrid V-cycle with r^T z fused, or Jacobi inside the
+// direction kernel), p = z + beta p.  Every kernel is guarded by st->done.
 template <typename T>
-fe_status cg_loop(fe_problem* p, T* x, T* r, T* pv, T* q, CgState* out) {
+hipError_t cg_iteration(fe_problem* p, T* x, T* r, T* pv, T* q) {
   const bool mg = p->nlev > 1;
   T* z = mg ? static_cast<T*>(p->L[0].mg_z) : nullptr;
-  const int chunk = mg ? kChunkMG : kChunk;
-  for (;;) {
-    for (int it = 0; it < chunk; ++it) {
-      HIP_TRY(launch_kxu<T>(p, 0, pv, q, p->st));
-      HIP_TRY(launch_cg_update<T>(p, x, r, pv, q, p->st, mg ? 1 : 0));
-      if (mg) HIP_TRY(launch_vcycle<T>(p, 0, r, z, p->st, true));
-      HIP_TRY(launch_cg_direction<T>(p, r, z, pv, p->st));
-    }
-    fe_status s = read_state(p, out);
-    if (s != FE_OK) return s;
-    if (out->done) return FE_OK;
-  }
+  hipError_t e;
+  if ((e = launch_kxu<T>(p, 0, pv, q, p->st)) != hipSuccess) return e;
+  if ((e = launch_cg_update<T>(p, x, r, pv, q, p->st, mg ? 1 : 0)) != hipSuccess) return e;
+  if (mg && (e = launch_vcycle<T>(p, 0, r, z, p->st, true)) != hipSuccess) return e;
+  return launch_cg_direction<T>(p, r, z, pv, p->st);
 }
 
-// r = b - Kx (Kx null: x = 0), first preconditioned direction, convergence
-// test of the start point.
 template <typename T>
-fe_status cg_start(fe_problem* p, const T* b, const T* Kx, T* r, T* pv, CgState* hs) {
+GraphChunk& chunk_of(fe_problem* p);
+template <>
+GraphChunk& chunk_of<double>(fe_problem* p) { return p->chunk64; }
+template <>
+GraphChunk& chunk_of<float>(fe_problem* p) { return p->chunk32; }
+
+void drop_graph(GraphChunk& gc) {
+  if (gc.exec) (void)hipGraphExecDestroy(gc.exec);
+  gc.exec = nullptr;
+  for (hipEvent_t e : gc.ev) (void)hipEventDestroy(e);
+  gc.ev.clear();
+  gc.bytes.clear();
+}
+
+// Enqueues a chunk of CG iterations on p->stream.  The chunk is captured once
+// per problem and vector type as a HIP graph (on a private stream, then
+// replayed on p->stream); with profiling on, the graph carries its own event
+// pairs around each fine-grid K*u launch.
+template <typename T>
+hipError_t enqueue_chunk(fe_problem* p, T* x, T* r, T* pv, T* q) {
+  const int n = p->nlev > 1 ? kChunkMG : kChunk;
+  GraphChunk& gc = chunk_of<T>(p);
+  const bool prof = p->kst.on;
+  if (p->use_graphs && p->cap_stream) {
+    if (!gc.exec || gc.prof != prof) {
+      drop_graph(gc);
+      hipStream_t saved = p->stream;
+      p->stream = p->cap_stream;
+      if (prof) {
+        p->kst.cap_ev = &gc.ev;
+        p->kst.cap_bytes = &gc.bytes;
+      }
+      hipError_t e = hipStreamBeginCapture(p->cap_stream, hipStreamCaptureModeRelaxed);
+      for (int it = 0; it < n && e == hipSuccess; ++it) e = cg_iteration<T>(p, x, r, pv, q);
+      hipGraph_t graph = nullptr;
+      hipError_t e2 = hipStreamEndCapture(p->cap_stream, &graph);
+      p->stream = saved;
+      p->kst.cap_ev = nullptr;
+      p->kst.cap_bytes = nullptr;
+      if (e == hipSuccess && e2 == hipSuccess && graph)
+        e = hipGraphInstantiate(&gc.exec, graph, nullptr, nullptr, 0);
+      else
+        e = (e != hipSuccess) ? e : e2;
+      if (graph) (void)hipGraphDestroy(graph);
+      if (e != hipSuccess || !gc.exec) {
+        (void)hipGetLastError();
+        drop_graph(gc);
+        p->use_graphs = false;  // fall back to direct launches from now on
+      } else {
+        gc.prof = prof;
+      }
+    }
+    if (gc.exec) {
+      if (gc.prof) p->last_replay = &gc;
+      return hipGraphLaunch(gc.exec, p->stream);
+    }
+  }
+  hipError_t e = hipSuccess;
+  for (int it = 0; it < n && e == hipSuccess; ++it) e = cg_iteration<T>(p, x, r, pv, q);
+  return e;
+}
+
+// Adds the kernel times the last profiled graph replay recorded (the replay
+// has completed: its stage event fired).
+fe_status harvest_graph_events(fe_problem* p) {
+  GraphChunk* gc = p->last_replay;
+  p->last_replay = nullptr;
+  if (!gc || !gc->exec || !gc->prof) return FE_OK;
+  for (size_t i = 0; i < gc->bytes.size(); ++i) {
+    float ms = 0.0f;
+    HIP_TRY(hipEventElapsedTime(&ms, gc->ev[2 * i], gc->ev[2 * i + 1]));
+    p->kst.total_ms += ms;
+    p->kst.total_bytes += gc->bytes[i];
+    p->kst.launches += 1;
+  }
+  return FE_OK;
+}
+
+// r = b - Kx (Kx null: x = 0) and the first preconditioned direction.
+template <typename T>
+hipError_t enqueue_start(fe_problem* p, const T* b, const T* Kx, T* r, T* pv) {
   const bool mg = p->nlev > 1;
-  HIP_TRY(launch_cg_init<T>(p, b, Kx, r, pv, p->st, mg ? 1 : 0));
-  if (mg) {
-    T* z = static_cast<T*>(p->L[0].mg_z);
-    HIP_TRY(launch_fill<T>(p, pv, p->L[0].g.ndof, T(0)));
-    HIP_TRY(launch_vcycle<T>(p, 0, r, z, p->st, true));
-    HIP_TRY(launch_cg_direction<T>(p, r, z, pv, p->st));
-  }
-  return read_state(p, hs);
+  hipError_t e = launch_cg_init<T>(p, b, Kx, r, pv, p->st, mg ? 1 : 0);
+  if (e != hipSuccess || !mg) return e;
+  T* z = static_cast<T*>(p->L[0].mg_z);
+  if ((e = launch_fill<T>(p, pv, p->L[0].g.ndof, T(0))) != hipSuccess) return e;
+  if ((e = launch_vcycle<T>(p, 0, r, z, p->st, true)) != hipSuccess) return e;
+  return launch_cg_direction<T>(p, r, z, pv, p->st);
 }
 
-fe_status solve_fp64(fe_problem* p, double* u, double rtol, int max_iters, fe_solve_info* info) {
-  HIP_TRY(launch_kxu<double>(p, 0, u, p->q64, nullptr));
-  HIP_TRY(launch_cg_state_init(p, p->st, rtol, max_iters));
-  CgState hs;
-  fe_status s = cg_start<double>(p, p->f, p->q64, p->r64, p->p64, &hs);
+fe_status copy_state(fe_problem* p) {
+  HIP_TRY(hipMemcpyAsync(p->h_st, p->st, sizeof(CgState), hipMemcpyDeviceToHost, p->stream));
+  HIP_TRY(hipEventRecord(p->done_ev, p->stream));
+  return FE_OK;
+}
+
+fe_status copy_scal(fe_problem* p, int slot, int dst) {
+  HIP_TRY(hipMemcpyAsync(p->h_scal + dst, p->scal + 2 * slot, sizeof(double), hipMemcpyDeviceToHost,
+                         p->stream));
+  return FE_OK;
+}
+
+// Final float64 residual and compliance of the returned u.
+fe_status enqueue_finish(fe_problem* p, bool need_residual) {
+  SolveCtx& sc = p->sc;
+  if (need_residual) {
+    HIP_TRY(launch_residual64(p, sc.u, p->tmp64, p->scal + 2 * SLOT_RR));
+    fe_status s = copy_scal(p, SLOT_RR, 0);
+    if (s != FE_OK) return s;
+  }
+  HIP_TRY(launch_dot64(p, p->f, sc.u, p->L[0].g.ndof, p->scal + 2 * SLOT_C));
+  fe_status s = copy_scal(p, SLOT_C, 1);
   if (s != FE_OK) return s;
-  if (!hs.done) {
-    s = cg_loop<double>(p, u, p->r64, p->p64, p->q64, &hs);
-    if (s != FE_OK) return s;
-  }
-  info->iters = hs.iter;
-  info->outer_iters = 0;
-  return (fe_status)hs.status;
+  HIP_TRY(hipEventRecord(p->done_ev, p->stream));
+  sc.stage = ST_FINISH;
+  return FE_OK;
 }
 
-// float32 PCG on K d = r / ||r|| inside float64 refinement u += ||r|| d.
-fe_status solve_ir(fe_problem* p, double* u, double rtol, int max_iters, fe_solve_info* info,
-                   double ff) {
-  int total = 0, outer = 0;
-  fe_status result = FE_ENOTCONV;
-  const int max_outer = 40;
-  double prev_rel = 1e300;
-  for (;;) {
-    HIP_TRY(launch_residual64(p, u, p->r64, p->scal + 2 * SLOT_RR));
-    double rr;
-    fe_status s = read_scal(p, SLOT_RR, &rr);
-    if (s != FE_OK) return s;
-    const double rel = std::sqrt(rr / ff);
-    if (!std::isfinite(rel)) {
-      result = FE_EBREAKDOWN;
-      break;
+fe_status enqueue_ir_residual(fe_problem* p) {
+  HIP_TRY(launch_residual64(p, p->sc.u, p->r64, p->scal + 2 * SLOT_RR));
+  fe_status s = copy_scal(p, SLOT_RR, 0);
+  if (s != FE_OK) return s;
+  HIP_TRY(hipEventRecord(p->done_ev, p->stream));
+  p->sc.stage = ST_IR_RESID;
+  return FE_OK;
+}
+
+// Advances the solve by one stage; the previous stage's event has completed.
+fe_status advance(fe_problem* p) {
+  SolveCtx& sc = p->sc;
+  fe_status hs0 = harvest_graph_events(p);
+  if (hs0 != FE_OK) return hs0;
+  switch (sc.stage) {
+    case ST_CG64: {
+      const CgState hs = *p->h_st;
+      if (!hs.done) {
+        HIP_TRY(enqueue_chunk<double>(p, p->x64, p->r64, p->p64, p->q64));
+        return copy_state(p);
+      }
+      sc.info.iters = hs.iter;
+      sc.result = (fe_status)hs.status;
+      HIP_TRY(hipMemcpyAsync(sc.u, p->x64, p->L[0].g.ndof * sizeof(double), hipMemcpyDeviceToDevice,
+                             p->stream));
+      return enqueue_finish(p, true);
     }
-    if (rel <= rtol) {
-      result = FE_OK;
-      break;
+    case ST_IR_RESID: {
+      const double rr = p->h_scal[0];
+      const double rel = std::sqrt(rr / p->ff);
+      sc.info.iters = sc.total;
+      sc.info.outer_iters = sc.outer;
+      if (!std::isfinite(rel)) {
+        sc.result = FE_EBREAKDOWN;
+        return enqueue_finish(p, false);
+      }
+      if (rel <= sc.rtol) {
+        sc.result = FE_OK;
+        return enqueue_finish(p, false);
+      }
+      if (sc.outer >= kMaxOuter || sc.total >= sc.max_iters || rel > 0.99 * sc.prev_rel) {
+        sc.result = FE_ENOTCONV;
+        return enqueue_finish(p, false);
+      }
+      sc.prev_rel = rel;
+      // inner tolerance: aim a little past the target, within float32 reach
+      double itol = 0.3 * sc.rtol / rel;
+      if (itol < 1e-5) itol = 1e-5;
+      if (itol > 1e-1) itol = 1e-1;
+      HIP_TRY(launch_to32_scaled(p, p->r64, p->r32, p->scal + 2 * SLOT_RR));
+      HIP_TRY(launch_fill<float>(p, p->x32, p->L[0].g.ndof, 0.0f));
+      HIP_TRY(launch_cg_state_init(p, p->st, itol, sc.max_iters - sc.total));
+      HIP_TRY(enqueue_start<float>(p, p->r32, nullptr, p->r32, p->p32));
+      sc.stage = ST_IR_CG;
+      return copy_state(p);
     }
-    if (outer >= max_outer || total >= max_iters || rel > 0.99 * prev_rel) {
-      result = FE_ENOTCONV;
-      break;
+    case ST_IR_CG: {
+      const CgState hs = *p->h_st;
+      if (!hs.done) {
+        HIP_TRY(enqueue_chunk<float>(p, p->x32, p->r32, p->p32, p->q32));
+        return copy_state(p);
+      }
+      sc.total += hs.iter;
+      sc.outer += 1;
+      sc.info.iters = sc.total;
+      sc.info.outer_iters = sc.outer;
+      if (hs.iter > 0) HIP_TRY(launch_axpy_from32(p, sc.u, p->x32, p->scal + 2 * SLOT_RR));
+      if (hs.status == FE_EBREAKDOWN && hs.iter == 0) {
+        sc.result = FE_EBREAKDOWN;
+        return enqueue_finish(p, false);
+      }
+      return enqueue_ir_residual(p);
     }
-    prev_rel = rel;
-    // inner tolerance: aim a little past the target, within float32 reach
-    double itol = 0.3 * rtol / rel;
-    if (itol < 1e-5) itol = 1e-5;
-    if (itol > 1e-1) itol = 1e-1;
-    HIP_TRY(launch_to32_scaled(p, p->r64, p->r32, p->scal + 2 * SLOT_RR));
-    HIP_TRY(launch_fill<float>(p, p->x32, p->L[0].g.ndof, 0.0f));
-    HIP_TRY(launch_cg_state_init(p, p->st, itol, max_iters - total));
-    CgState hs;
-    s = cg_start<float>(p, p->r32, nullptr, p->r32, p->p32, &hs);
-    if (s != FE_OK) return s;
-    if (!hs.done) {
-      s = cg_loop<float>(p, p->x32, p->r32, p->p32, p->q32, &hs);
-      if (s != FE_OK) return s;
+    case ST_FINISH: {
+      sc.info.rel_res = std::sqrt(p->h_scal[0] / p->ff);
+      sc.info.compliance = p->h_scal[1];
+      sc.stage = ST_DONE;
+      return FE_OK;
     }
-    total += hs.iter;
-    ++outer;
-    if (hs.iter > 0) HIP_TRY(launch_axpy_from32(p, u, p->x32, p->scal + 2 * SLOT_RR));
-    if (hs.status == FE_EBREAKDOWN && hs.iter == 0) {
-      result = FE_EBREAKDOWN;
-      break;
-    }
+    default:
+      return FE_OK;
   }
-  info->iters = total;
-  info->outer_iters = outer;
-  return result;
+}
+
+fe_status solve_begin(fe_problem* p, const double* rho, double* u, double rtol, int max_iters) {
+  if (!rho || !u) {
+    fe_set_error("rho and u must not be NULL");
+    return FE_EINVAL;
+  }
+  if (!(rtol > 0.0) || max_iters < 1) {
+    fe_set_error("rtol must be > 0 and max_iters >= 1");
+    return FE_EINVAL;
+  }
+  if (p->sc.stage != ST_DONE) {
+    fe_set_error("a solve is still in progress on this problem");
+    return FE_EINVAL;
+  }
+  SolveCtx& sc = p->sc;
+  sc = SolveCtx();
+  sc.rtol = rtol;
+  sc.max_iters = max_iters;
+  sc.u = u;
+  fe_status s = prepare_operator(p, rho);
+  if (s != FE_OK) return s;
+  HIP_TRY(launch_mask_vec<double>(p, 0, u));
+  if (!(p->ff > 0.0)) {  // no load: u = 0 is exact
+    HIP_TRY(launch_fill<double>(p, u, p->L[0].g.ndof, 0.0));
+    HIP_TRY(hipEventRecord(p->done_ev, p->stream));
+    sc.stage = ST_DONE;
+    return FE_OK;
+  }
+  if (p->cfg.precision == FE_PREC_FP64) {
+    const int64_t nd = p->L[0].g.ndof;
+    HIP_TRY(hipMemcpyAsync(p->x64, u, nd * sizeof(double), hipMemcpyDeviceToDevice, p->stream));
+    HIP_TRY(launch_kxu<double>(p, 0, p->x64, p->q64, nullptr));
+    HIP_TRY(launch_cg_state_init(p, p->st, rtol, max_iters));
+    HIP_TRY(enqueue_start<double>(p, p->f, p->q64, p->r64, p->p64));
+    sc.stage = ST_CG64;
+    return copy_state(p);
+  }
+  return enqueue_ir_residual(p);
+}
+
+fe_status solve_step(fe_problem* p, int wait, int* done) {
+  *done = 0;
+  while (p->sc.stage != ST_DONE) {
+    if (wait) {
+      HIP_TRY(hipEventSynchronize(p->done_ev));
+    } else {
+      const hipError_t q = hipEventQuery(p->done_ev);
+      if (q == hipErrorNotReady) return FE_OK;
+      if (q != hipSuccess) {
+        fe_set_error(std::string("hipEventQuery: ") + hipGetErrorString(q));
+        return FE_EDEVICE;
+      }
+    }
+    fe_status s = advance(p);
+    if (s != FE_OK) {
+      p->sc.stage = ST_DONE;
+      return s;
+    }
+    if (!wait) break;  // one stage per call when polling
+  }
+  *done = p->sc.stage == ST_DONE;
+  return FE_OK;
+}
+
+fe_status solve_end(fe_problem* p, fe_solve_info* info) {
+  SolveCtx& sc = p->sc;
+  if (sc.stage != ST_DONE) {
+    fe_set_error("the solve has not finished");
+    return FE_EINVAL;
+  }
+  if (info) *info = sc.info;
+  if (sc.result == FE_ENOTCONV)
+    fe_set_error("iteration limit reached (relative residual " + std::to_string(sc.info.rel_res) + ")");
+  if (sc.result == FE_EBREAKDOWN) fe_set_error("CG breakdown (p^T K p <= 0 or non-finite value)");
+  return sc.result;
+}
+
+struct KeTables {
+  double ke[576];
+  WalshK wk;
+  double lam_max;
+};
+
+// Ke by Gauss quadrature, its sum/difference-basis constants (checked against
+// the full transformed matrix) and lambda_max(Ke) / Ke_dd by power iteration
+// (Ke is symmetric positive semi-definite); that ratio bounds
+// lambda_max(D^-1 K) for any modulus field.
+bool make_ke_tables(double nu, KeTables* t) {
+  host_hex8_ke(nu, 1.0, 1.0, t->ke);
+  double dev = 0.0;
+  host_walsh_constants(t->ke, &t->wk, &dev);
+  if (dev > 1e-12) return false;
+  double v[24], w[24], lam = 0.0;
+  for (int i = 0; i < 24; ++i) v[i] = 1.0 + 0.01 * i * ((i & 1) ? -1.0 : 1.0);
+  for (int it = 0; it < 5000; ++it) {
+    double nrm = 0.0;
+    for (int i = 0; i < 24; ++i) {
+      double s2 = 0.0;
+      for (int j = 0; j < 24; ++j) s2 += t->ke[i * 24 + j] * v[j];
+      w[i] = s2;
+      nrm += s2 * s2;
+    }
+    nrm = std::sqrt(nrm);
+    double num = 0.0, den = 0.0;
+    for (int i = 0; i < 24; ++i) {
+      num += v[i] * w[i];
+      den += v[i] * v[i];
+    }
+    lam = num / den;
+    for (int i = 0; i < 24; ++i) v[i] = w[i] / nrm;
+  }
+  t->lam_max = lam / t->ke[0];
+  return true;
 }
 
 }  // namespace
@@ -340,40 +576,30 @@ extern "C" fe_status fe_setup(const fe_config* cfg, const uint8_t* fixed, const 
   p->ws_bytes = ws_bytes;
   layout(cfg, p, (char*)ws);
 
-  // Ke and its sum/difference-basis constants (unit modulus, unit edge)
-  host_hex8_ke(cfg->nu, 1.0, 1.0, p->ke64_host);
-  double dev = 0.0;
-  host_walsh_constants(p->ke64_host, &p->wk, &dev);
-  if (dev > 1e-12) {
-    delete p;
-    fe_set_error("element stiffness lacks the cube symmetry the kernels rely on");
-    return FE_EINVAL;
+  // Ke, its sum/difference-basis constants and lambda_max(diag(Ke)^-1 Ke)
+  // (unit modulus, unit edge) depend on nu only: computed once per nu.
+  {
+    static std::mutex mu;
+    static std::vector<std::pair<double, KeTables>> cache;
+    std::lock_guard<std::mutex> lock(mu);
+    const KeTables* hit = nullptr;
+    for (auto& kv : cache)
+      if (kv.first == cfg->nu) hit = &kv.second;
+    if (!hit) {
+      KeTables t;
+      if (!make_ke_tables(cfg->nu, &t)) {
+        delete p;
+        fe_set_error("element stiffness lacks the cube symmetry the kernels rely on");
+        return FE_EINVAL;
+      }
+      cache.emplace_back(cfg->nu, t);
+      hit = &cache.back().second;
+    }
+    std::memcpy(p->ke64_host, hit->ke, sizeof(p->ke64_host));
+    p->wk = hit->wk;
+    p->lam_max = hit->lam_max;
   }
   p->ke_diag = p->ke64_host[0];
-  {
-    // lambda_max(Ke) / Ke_dd by power iteration (Ke is symmetric positive
-    // semi-definite); it bounds lambda_max(D^-1 K) for any modulus field
-    double v[24], w[24], lam = 0.0;
-    for (int i = 0; i < 24; ++i) v[i] = 1.0 + 0.01 * i * ((i & 1) ? -1.0 : 1.0);
-    for (int it = 0; it < 5000; ++it) {
-      double nrm = 0.0;
-      for (int i = 0; i < 24; ++i) {
-        double s2 = 0.0;
-        for (int j = 0; j < 24; ++j) s2 += p->ke64_host[i * 24 + j] * v[j];
-        w[i] = s2;
-        nrm += s2 * s2;
-      }
-      nrm = std::sqrt(nrm);
-      double num = 0.0, den = 0.0;
-      for (int i = 0; i < 24; ++i) {
-        num += v[i] * w[i];
-        den += v[i] * v[i];
-      }
-      lam = num / den;
-      for (int i = 0; i < 24; ++i) v[i] = w[i] / nrm;
-    }
-    p->lam_max = lam / p->ke_diag;
-  }
   float ke32h[576];
   for (int i = 0; i < 576; ++i) ke32h[i] = (float)p->ke64_host[i];
 
@@ -397,7 +623,7 @@ extern "C" fe_status fe_setup(const fe_config* cfg, const uint8_t* fixed, const 
 
   auto fail = [&](hipError_t e, const char* what) {
     fe_set_error(std::string(what) + ": " + hipGetErrorString(e));
-    delete p;
+    fe_destroy(p);
     return FE_EDEVICE;
   };
   hipError_t e;
@@ -419,8 +645,16 @@ extern "C" fe_status fe_setup(const fe_config* cfg, const uint8_t* fixed, const 
   if ((e = launch_mask_load(p, f))) return fail(e, "load");
   if ((e = launch_filter_rowsums(p))) return fail(e, "filter row sums");
   if ((e = launch_dot64(p, p->f, p->f, p->L[0].g.ndof, p->scal + 2 * SLOT_FF))) return fail(e, "||f||");
+  if ((e = hipHostMalloc((void**)&p->h_st, sizeof(CgState), hipHostMallocDefault))) return fail(e, "pinned state");
+  if ((e = hipHostMalloc((void**)&p->h_scal, 4 * sizeof(double), hipHostMallocDefault)))
+    return fail(e, "pinned scalars");
+  if ((e = hipEventCreateWithFlags(&p->done_ev, hipEventDisableTiming))) return fail(e, "event");
+  if ((e = hipStreamCreateWithFlags(&p->cap_stream, hipStreamNonBlocking))) return fail(e, "capture stream");
+  if ((e = hipMemcpyAsync(p->h_scal, p->scal + 2 * SLOT_FF, sizeof(double), hipMemcpyDeviceToHost, p->stream)))
+    return fail(e, "read ||f||");
   // host copies above read stack arrays: finish them before returning
   if ((e = hipStreamSynchronize(p->stream))) return fail(e, "setup sync");
+  p->ff = p->h_scal[0];
   *out = p;
   return FE_OK;
 }
@@ -465,48 +699,36 @@ extern "C" fe_status fe_apply_K(fe_problem* p, const double* rho, const double* 
 extern "C" fe_status fe_solve(fe_problem* p, const double* rho, double* u, double rtol, int32_t max_iters,
                               fe_solve_info* info) {
   CHECK_HANDLE(p);
-  if (!rho || !u) {
-    fe_set_error("rho and u must not be NULL");
+  if (info) std::memset(info, 0, sizeof(*info));
+  fe_status s = solve_begin(p, rho, u, rtol, max_iters);
+  if (s != FE_OK) return s;
+  int done = 0;
+  s = solve_step(p, 1, &done);
+  if (s != FE_OK) return s;
+  return solve_end(p, info);
+}
+
+extern "C" fe_status fe_solve_begin(fe_problem* p, const double* rho, double* u, double rtol,
+                                    int32_t max_iters) {
+  CHECK_HANDLE(p);
+  return solve_begin(p, rho, u, rtol, max_iters);
+}
+
+extern "C" fe_status fe_solve_step(fe_problem* p, int32_t* done) {
+  CHECK_HANDLE(p);
+  if (!done) {
+    fe_set_error("done must not be NULL");
     return FE_EINVAL;
   }
-  if (!(rtol > 0.0) || max_iters < 1) {
-    fe_set_error("rtol must be > 0 and max_iters >= 1");
-    return FE_EINVAL;
-  }
-  fe_solve_info local;
-  if (!info) info = &local;
-  std::memset(info, 0, sizeof(*info));
-  fe_status s = prepare_operator(p, rho);
-  if (s != FE_OK) return s;
-  HIP_TRY(launch_mask_vec<double>(p, 0, u));
-  double ff;
-  s = read_scal(p, SLOT_FF, &ff);
-  if (s != FE_OK) return s;
-  if (!(ff > 0.0)) {  // no load: u = 0 is exact
-    HIP_TRY(launch_fill<double>(p, u, p->L[0].g.ndof, 0.0));
-    HIP_TRY(hipStreamSynchronize(p->stream));
-    return FE_OK;
-  }
-  fe_status res;
-  if (p->cfg.precision == FE_PREC_FP64)
-    res = solve_fp64(p, u, rtol, max_iters, info);
-  else
-    res = solve_ir(p, u, rtol, max_iters, info, ff);
-  if (res == FE_EDEVICE || res == FE_EINVAL) return res;
-  // true float64 residual and compliance of the returned u
-  HIP_TRY(launch_residual64(p, u, p->tmp64, p->scal + 2 * SLOT_RR));
-  HIP_TRY(launch_dot64(p, p->f, u, p->L[0].g.ndof, p->scal + 2 * SLOT_C));
-  double rr, c;
-  s = read_scal(p, SLOT_RR, &rr);
-  if (s != FE_OK) return s;
-  s = read_scal(p, SLOT_C, &c);
-  if (s != FE_OK) return s;
-  info->rel_res = std::sqrt(rr / ff);
-  info->compliance = c;
-  if (res == FE_ENOTCONV)
-    fe_set_error("iteration limit reached (relative residual " + std::to_string(info->rel_res) + ")");
-  if (res == FE_EBREAKDOWN) fe_set_error("CG breakdown (p^T K p <= 0 or non-finite value)");
-  return res;
+  int d = 0;
+  fe_status s = solve_step(p, 0, &d);
+  *done = d;
+  return s;
+}
+
+extern "C" fe_status fe_solve_end(fe_problem* p, fe_solve_info* info) {
+  CHECK_HANDLE(p);
+  return solve_end(p, info);
 }
 
 extern "C" fe_status fe_sensitivity(fe_problem* p, const double* rho, const double* u, double* dc,
@@ -565,6 +787,8 @@ extern "C" fe_status fe_set_mg_params(fe_problem* p, int32_t nu, int32_t coarse_
   p->mg_nu = nu;
   p->mg_coarse_sweeps = coarse_sweeps;
   p->mg_omega = omega;
+  drop_graph(p->chunk64);  // the captured chunks bake these in
+  drop_graph(p->chunk32);
   return FE_OK;
 }
 
@@ -602,7 +826,13 @@ extern "C" fe_status fe_kernel_stats(fe_problem* p, int32_t reset, int64_t* laun
 
 extern "C" void fe_destroy(fe_problem* p) {
   if (!p) return;
-  if (p->stream) hipStreamSynchronize(p->stream);
-  for (hipEvent_t e : p->kst.ev) hipEventDestroy(e);
+  if (p->stream) (void)hipStreamSynchronize(p->stream);
+  drop_graph(p->chunk64);
+  drop_graph(p->chunk32);
+  for (hipEvent_t e : p->kst.ev) (void)hipEventDestroy(e);
+  if (p->done_ev) (void)hipEventDestroy(p->done_ev);
+  if (p->cap_stream) (void)hipStreamDestroy(p->cap_stream);
+  if (p->h_st) (void)hipHostFree(p->h_st);
+  if (p->h_scal) (void)hipHostFree(p->h_scal);
   delete p;
 }

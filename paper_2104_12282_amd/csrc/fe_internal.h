@@ -73,6 +73,32 @@ struct KStats {
   int64_t launches = 0;
   double total_ms = 0.0;
   double total_bytes = 0.0;
+  // while a graph is being captured, event pairs go to the graph's own lists
+  std::vector<hipEvent_t>* cap_ev = nullptr;
+  std::vector<double>* cap_bytes = nullptr;
+};
+
+// One captured chunk of CG iterations (per vector type).
+struct GraphChunk {
+  hipGraphExec_t exec = nullptr;
+  bool prof = false;            // captured with profiling events
+  std::vector<hipEvent_t> ev;   // event pairs recorded by each replay
+  std::vector<double> bytes;
+};
+
+// Non-blocking solve: a host state machine advanced by fe_solve_step; every
+// stage ends with a copy of the few scalars it needs into pinned host memory
+// and an event.
+struct SolveCtx {
+  int stage = 0;
+  double rtol = 0.0;
+  int max_iters = 0;
+  double* u = nullptr;
+  int total = 0, outer = 0;
+  double prev_rel = 1e300;
+  int fresh_inner = 0;          // the inner CG state was just initialised
+  fe_status result = FE_OK;
+  fe_solve_info info{};
 };
 
 // Brackets the next launch on p->stream with a pair of events when profiling
@@ -110,6 +136,18 @@ struct fe_problem {
   CgState* st = nullptr;       // device state (two instances: [0] inner, [1] aux)
   double* scal = nullptr;      // 64 device scalars for small results
   double* oc = nullptr;        // OC search state
+
+  // solve state machine, pinned host mirrors, captured CG chunks
+  SolveCtx sc;
+  CgState* h_st = nullptr;      // pinned
+  double* h_scal = nullptr;     // pinned, 4 values
+  hipEvent_t done_ev = nullptr;
+  hipStream_t cap_stream = nullptr;
+  GraphChunk chunk64, chunk32;
+  GraphChunk* last_replay = nullptr;  // profiled graph replayed since the last harvest
+  bool use_graphs = true;
+  double* x64 = nullptr;        // float64 iterate of the solve (graphs need fixed pointers)
+  double ff = 0.0;              // ||f||^2
 
   // geometric multigrid parameters
   int mg_nu = 1;               // damped Jacobi sweeps before and after the coarse correction

@@ -583,19 +583,27 @@ __global__ void __launch_bounds__(FE_BLOCK) oc_pass_kernel(int64_t n, const doub
 __global__ void __launch_bounds__(FE_BLOCK) oc_pass_finalize(int nb, const double* __restrict__ partials,
                                                              OcState* os) {
   if (os->done) return;
+  // thread (c, q): candidate c, every (FE_BLOCK / OC_NC)-th block from q;
+  // the quarter sums are then added in q order (fixed)
+  const int c = threadIdx.x % OC_NC, q = threadIdx.x / OC_NC;
+  double s = 0.0;
+  for (int b = q; b < nb; b += FE_BLOCK / OC_NC) s += partials[(size_t)c * nb + b];
+  __shared__ double part[FE_BLOCK];
   __shared__ double vols[OC_NC];
+  part[threadIdx.x] = s;
+  __syncthreads();
   if (threadIdx.x < OC_NC) {
-    double s = 0.0;
-    for (int b = 0; b < nb; ++b) s += partials[(size_t)threadIdx.x * nb + b];
-    vols[threadIdx.x] = s;
+    double v = 0.0;
+    for (int k = 0; k < FE_BLOCK / OC_NC; ++k) v += part[k * OC_NC + threadIdx.x];
+    vols[threadIdx.x] = v;
   }
   __syncthreads();
   if (threadIdx.x == 0) {
     // first candidate whose volume reaches the target
-    int c = 0;
-    while (c < OC_NC && vols[c] < os->target) ++c;
-    const double lo_new = (c == 0) ? os->s_lo : oc_candidate(os, c - 1);
-    const double hi_new = (c == OC_NC) ? os->s_hi : oc_candidate(os, c);
+    int k = 0;
+    while (k < OC_NC && vols[k] < os->target) ++k;
+    const double lo_new = (k == 0) ? os->s_lo : oc_candidate(os, k - 1);
+    const double hi_new = (k == OC_NC) ? os->s_hi : oc_candidate(os, k);
     os->s_lo = lo_new;
     os->s_hi = hi_new;
     os->pass += 1;
@@ -704,6 +712,19 @@ const float* level_invd<float>(fe_problem* p, int lev) { return p->L[lev].invd32
 int kstats_begin(fe_problem* p, double bytes) {
   KStats& ks = p->kst;
   if (!ks.on) return -1;
+  if (ks.cap_ev) {  // inside a graph capture: the graph owns the pair
+    hipEvent_t a, b;
+    if (hipEventCreate(&a) != hipSuccess) return -1;
+    if (hipEventCreate(&b) != hipSuccess) {
+      (void)hipEventDestroy(a);
+      return -1;
+    }
+    ks.cap_ev->push_back(a);
+    ks.cap_ev->push_back(b);
+    ks.cap_bytes->push_back(bytes);
+    (void)hipEventRecord(a, p->stream);
+    return (int)ks.cap_bytes->size() - 1;
+  }
   const size_t slot = (size_t)ks.pending;
   if (2 * slot + 2 > ks.ev.size()) {
     hipEvent_t a, b;
@@ -723,8 +744,13 @@ int kstats_begin(fe_problem* p, double bytes) {
 
 void kstats_end(fe_problem* p, int slot) {
   if (slot < 0) return;
-  (void)hipEventRecord(p->kst.ev[2 * (size_t)slot + 1], p->stream);
-  p->kst.pending += 1;
+  KStats& ks = p->kst;
+  if (ks.cap_ev) {
+    (void)hipEventRecord((*ks.cap_ev)[2 * (size_t)slot + 1], p->stream);
+    return;
+  }
+  (void)hipEventRecord(ks.ev[2 * (size_t)slot + 1], p->stream);
+  ks.pending += 1;
 }
 
 template <typename T>
@@ -894,12 +920,14 @@ hipError_t launch_oc(fe_problem* p, const double* x, const double* dcx, const do
   OcState* os = reinterpret_cast<OcState*>(p->oc);
   const double target = volfrac * (double)n;
   const int nb = red_grid(n);
+  // the candidate passes keep 64 partials per workgroup: fewer, fuller workgroups
+  const int nbp = nb < 512 ? nb : 512;
   hipLaunchKernelGGL(oc_prep_kernel, dim3(nb), dim3(FE_BLOCK), 0, p->stream, n, x, dcx, dv, move, p->partials);
   hipLaunchKernelGGL(oc_prep_finalize, dim3(1), dim3(FE_BLOCK), 0, p->stream, nb, p->partials, target, os);
   for (int pass = 0; pass < 24; ++pass) {  // passes after convergence return at once
-    hipLaunchKernelGGL(oc_pass_kernel, dim3(nb), dim3(FE_BLOCK), 0, p->stream, n, x, dcx, dv, move, os,
+    hipLaunchKernelGGL(oc_pass_kernel, dim3(nbp), dim3(FE_BLOCK), 0, p->stream, n, x, dcx, dv, move, os,
                        p->partials);
-    hipLaunchKernelGGL(oc_pass_finalize, dim3(1), dim3(FE_BLOCK), 0, p->stream, nb, p->partials, os);
+    hipLaunchKernelGGL(oc_pass_finalize, dim3(1), dim3(FE_BLOCK), 0, p->stream, nbp, p->partials, os);
   }
   hipLaunchKernelGGL(oc_final_kernel, dim3(nb), dim3(FE_BLOCK), 0, p->stream, n, x, dcx, dv, move, os, x_new,
                      p->partials);

@@ -22,7 +22,8 @@ STATUS_NAME = {0: "FE_OK", -1: "FE_EINVAL", -2: "FE_ENOMEM", -3: "FE_EDEVICE",
                -4: "FE_ENOTCONV", -5: "FE_EBREAKDOWN"}
 
 # Every entry point declared in include/fe_abi.h.
-ABI_SYMBOLS = ("fe_workspace_size", "fe_setup", "fe_apply_K", "fe_solve", "fe_sensitivity",
+ABI_SYMBOLS = ("fe_workspace_size", "fe_setup", "fe_apply_K", "fe_solve", "fe_solve_begin",
+               "fe_solve_step", "fe_solve_end", "fe_sensitivity",
                "fe_filter", "oc_update", "fe_set_mg_params", "fe_set_profiling", "fe_kernel_stats",
                "fe_destroy", "fe_last_error")
 
@@ -64,6 +65,9 @@ def load_library() -> C.CDLL:
     lib.fe_setup.argtypes = [C.POINTER(fe_config), P, P, P, C.c_size_t, P, C.POINTER(P)]
     lib.fe_apply_K.argtypes = [P, P, P, P, I32]
     lib.fe_solve.argtypes = [P, P, P, D, I32, C.POINTER(fe_solve_info)]
+    lib.fe_solve_begin.argtypes = [P, P, P, D, I32]
+    lib.fe_solve_step.argtypes = [P, C.POINTER(I32)]
+    lib.fe_solve_end.argtypes = [P, C.POINTER(fe_solve_info)]
     lib.fe_sensitivity.argtypes = [P, P, P, P, P]
     lib.fe_filter.argtypes = [P, P, P, I32]
     lib.oc_update.argtypes = [P, P, P, P, D, D, P, P]
@@ -74,7 +78,8 @@ def load_library() -> C.CDLL:
     lib.fe_destroy.restype = None
     lib.fe_last_error.argtypes = []
     lib.fe_last_error.restype = C.c_char_p
-    for name in ("fe_setup", "fe_apply_K", "fe_solve", "fe_sensitivity", "fe_filter",
+    for name in ("fe_setup", "fe_apply_K", "fe_solve", "fe_solve_begin", "fe_solve_step",
+                 "fe_solve_end", "fe_sensitivity", "fe_filter",
                  "oc_update", "fe_set_mg_params", "fe_set_profiling", "fe_kernel_stats"):
         getattr(lib, name).restype = C.c_int
     _lib = lib
@@ -164,6 +169,24 @@ class Problem:
                                             C.byref(info)), allow)
         return u, {"iters": info.iters, "outer_iters": info.outer_iters,
                    "rel_res": info.rel_res, "compliance": info.compliance, "status": st}
+
+    # non-blocking form (continuous batching): begin, poll step() until True, end()
+    def solve_begin(self, rho, u, rtol=1e-8, max_iters=100000):
+        self._pending = (rho, u)  # keep the arrays alive while the solve runs
+        _check(load_library().fe_solve_begin(self._h, _ptr(rho), _ptr(u), rtol, max_iters))
+
+    def solve_step(self) -> bool:
+        done = C.c_int32(0)
+        _check(load_library().fe_solve_step(self._h, C.byref(done)))
+        return bool(done.value)
+
+    def solve_end(self, allow_notconv=False):
+        info = fe_solve_info()
+        allow = (FE_ENOTCONV,) if allow_notconv else ()
+        st = _check(load_library().fe_solve_end(self._h, C.byref(info)), allow)
+        self._pending = None
+        return {"iters": info.iters, "outer_iters": info.outer_iters, "rel_res": info.rel_res,
+                "compliance": info.compliance, "status": st}
 
     def sensitivity(self, rho, u, out=None, compliance_out=None):
         dc = self._vec(self.nelem) if out is None else out

@@ -1,0 +1,191 @@
+"""Continuous batching of design solves on one GPU.
+
+Requests (grid, load, density seed) arrive over time.  The engine admits
+them in arrival order whenever a slot is free and the sum of the admitted
+designs' device footprints (workspace + arrays, from fe_workspace_size) stays
+within the HBM budget.  Every admitted design keeps its u, rho and multigrid
+hierarchy resident in its own workspace and advances through the
+non-blocking ABI (fe_solve_begin / fe_solve_step / fe_solve_end): each call
+to step() enqueues at most one stage (a captured graph of CG iterations, a
+residual, ...) on the design's stream and returns at once, so the kernels of
+all admitted designs overlap on the device while new requests are admitted
+as slots free up.  A design's arithmetic is exactly that of a lone
+fe_solve, so its result does not depend on the mix.
+
+Per request the engine records arrival, admission and completion times
+(completion = sensitivity finished on the device, observed by the host); it
+reports designs/s and p50/p99 latency.
+"""
+from __future__ import annotations
+
+import collections
+import time
+
+import numpy as np
+import torch
+
+from . import fe, synth
+
+
+def request_footprint(nx, ny, nz, **cfg_kw) -> int:
+    """Device bytes one design holds while admitted: its workspace plus load,
+    density (two buffers), displacement and sensitivity arrays."""
+    cfg = fe.make_config(nx, ny, nz, **cfg_kw)
+    ne, nd = nx * ny * nz, 3 * (nx + 1) * (ny + 1) * (nz + 1)
+    return fe.workspace_size(cfg) + 8 * (2 * nd + 3 * ne)
+
+
+class _Slot:
+    def __init__(self, req, prob, stream, rho, u, dc, comp, admit_t, footprint):
+        self.req, self.prob, self.stream = req, prob, stream
+        self.rho, self.u, self.dc, self.comp = rho, u, dc, comp
+        self.admit_t, self.footprint = admit_t, footprint
+        self.info = None
+        self.event = None  # sensitivity completion
+
+
+def prepare_inputs(req, device):
+    """Host-side seeded inputs of one request (load, raw density)."""
+    nx, ny, nz = req["grid"]
+    f = synth.point_load(nx, ny, nz, req["seed"])
+    rho0 = synth.density_uniform(nx, ny, nz, req["seed"])
+    return f, rho0
+
+
+def _start(req, stream, device, cfg_kw, rtol, filter_passes):
+    nx, ny, nz = req["grid"]
+    f, rho0 = prepare_inputs(req, device)
+    with torch.cuda.stream(stream):
+        prob = fe.Problem(nx, ny, nz, torch.as_tensor(f, device=device), device=device,
+                          stream=stream, **cfg_kw)
+        a = torch.as_tensor(rho0, device=device)
+        b = torch.empty_like(a)
+        for _ in range(filter_passes):  # smoothed density, on the device
+            prob.filter(a, out=b)
+            a, b = b, a
+        u = torch.zeros(prob.ndof, dtype=torch.float64, device=device)
+        dc = torch.empty_like(a)
+        comp = torch.zeros(1, dtype=torch.float64, device=device)
+        prob.solve_begin(a, u, rtol=rtol)
+    return prob, a, u, dc, comp
+
+
+def run_engine(requests, arrivals=None, *, device="cuda:0", max_active=16, n_streams=4,
+               hbm_budget=64 << 30, rtol=1e-8, filter_passes=3, keep_outputs=False,
+               cfg_kw=None, log=None):
+    """Serves `requests` (dicts with id, grid, seed) arriving at `arrivals`
+    (seconds after the start; None = all at once).  Returns (results, stats)."""
+    cfg_kw = dict(cfg_kw or {"precision": "fp32_ir", "precond": "gmg", "mg_levels": 3})
+    if arrivals is None:
+        arrivals = np.zeros(len(requests))
+    order = np.argsort(arrivals, kind="stable")
+    pending = collections.deque((float(arrivals[i]), requests[i]) for i in order)
+    queue = collections.deque()
+    streams = [torch.cuda.Stream(device=device) for _ in range(n_streams)]
+    active: list[_Slot] = []
+    used = 0
+    results = {}
+    max_q = max_act = 0
+    t0 = time.perf_counter()
+    rr = 0
+    while pending or queue or active:
+        now = time.perf_counter() - t0
+        while pending and pending[0][0] <= now:
+            t_arr, req = pending.popleft()
+            queue.append((t_arr, req))
+        # admission: FIFO, slot and memory permitting
+        while queue and len(active) < max_active:
+            t_arr, req = queue[0]
+            fp = request_footprint(*req["grid"], **cfg_kw)
+            if used + fp > hbm_budget and active:
+                break
+            queue.popleft()
+            stream = streams[rr % n_streams]
+            rr += 1
+            prob, rho, u, dc, comp = _start(req, stream, device, cfg_kw, rtol, filter_passes)
+            s = _Slot(req, prob, stream, rho, u, dc, comp, time.perf_counter() - t0, fp)
+            s.arrival = t_arr
+            active.append(s)
+            used += fp
+        max_q = max(max_q, len(queue))
+        max_act = max(max_act, len(active))
+        # advance every admitted design by at most one stage
+        still = []
+        for s in active:
+            if s.info is None:
+                if s.prob.solve_step():
+                    s.info = s.prob.solve_end()
+                    with torch.cuda.stream(s.stream):
+                        s.prob.sensitivity(s.rho, s.u, out=s.dc, compliance_out=s.comp)
+                        s.event = torch.cuda.Event()
+                        s.event.record(s.stream)
+                still.append(s)
+            elif s.event.query():
+                t_done = time.perf_counter() - t0
+                rec = {"id": s.req["id"], "grid": s.req["grid"], "arrival": s.arrival,
+                       "admit": s.admit_t, "finish": t_done, "latency": t_done - s.arrival,
+                       "iters": s.info["iters"], "outer_iters": s.info["outer_iters"],
+                       "rel_res": s.info["rel_res"], "compliance": float(s.comp.item())}
+                if keep_outputs:
+                    rec["u"] = s.u.cpu().numpy()
+                    rec["dc"] = s.dc.cpu().numpy()
+                results[s.req["id"]] = rec
+                used -= s.footprint
+                s.prob.close()
+                if log:
+                    log(rec)
+            else:
+                still.append(s)
+        active = still
+        if not active and queue == collections.deque() and pending:
+            # idle until the next arrival
+            wait = pending[0][0] - (time.perf_counter() - t0)
+            if wait > 0:
+                time.sleep(min(wait, 0.01))
+    torch.cuda.synchronize(device)
+    wall = time.perf_counter() - t0
+    lat = np.array([r["latency"] for r in results.values()])
+    stats = {"requests": len(results), "wall_s": wall, "designs_per_s": len(results) / wall,
+             "p50_latency_s": float(np.percentile(lat, 50)), "p99_latency_s": float(np.percentile(lat, 99)),
+             "max_queue": max_q, "max_active": max_act}
+    return results, stats
+
+
+def run_sequential(requests, *, device="cuda:0", rtol=1e-8, filter_passes=3, keep_outputs=False,
+                   cfg_kw=None):
+    """The same requests one at a time with the blocking fe_solve (no
+    overlap, no admission), for comparison."""
+    cfg_kw = dict(cfg_kw or {"precision": "fp32_ir", "precond": "gmg", "mg_levels": 3})
+    stream = torch.cuda.current_stream(device)
+    results = {}
+    t0 = time.perf_counter()
+    for req in requests:
+        ts = time.perf_counter() - t0
+        prob, rho, u, dc, comp = None, None, None, None, None
+        nx, ny, nz = req["grid"]
+        f, rho0 = prepare_inputs(req, device)
+        prob = fe.Problem(nx, ny, nz, torch.as_tensor(f, device=device), device=device,
+                          stream=stream, **cfg_kw)
+        a = torch.as_tensor(rho0, device=device)
+        b = torch.empty_like(a)
+        for _ in range(filter_passes):
+            prob.filter(a, out=b)
+            a, b = b, a
+        u = torch.zeros(prob.ndof, dtype=torch.float64, device=device)
+        _, info = prob.solve(a, u=u, rtol=rtol)
+        dc, comp = prob.sensitivity(a, u)
+        torch.cuda.synchronize(device)
+        t_done = time.perf_counter() - t0
+        rec = {"id": req["id"], "grid": req["grid"], "start": ts, "finish": t_done,
+               "latency": t_done - ts, "iters": info["iters"], "rel_res": info["rel_res"],
+               "compliance": float(comp.item())}
+        if keep_outputs:
+            rec["u"] = u.cpu().numpy()
+            rec["dc"] = dc.cpu().numpy()
+        results[req["id"]] = rec
+        prob.close()
+    wall = time.perf_counter() - t0
+    lat = np.array([r["latency"] for r in results.values()])
+    return results, {"requests": len(results), "wall_s": wall, "designs_per_s": len(results) / wall,
+                     "p50_latency_s": float(np.percentile(lat, 50)),
+                     "p99_latency_s": float(np.percentile(lat, 99))}

@@ -71,3 +71,11 @@ def test_calls_on_null_handle_fail_cleanly():
     assert lib.oc_update(None, x, x, x, 0.1, 0.2, x, None) == fe.FE_EINVAL
     assert lib.fe_apply_K(None, x, x, x, 0) == fe.FE_EINVAL
     lib.fe_destroy(None)
+
+
+def test_serving_footprint_grows_with_grid():
+    from paper_2104_12282_amd import serve, synth
+    sizes = [serve.request_footprint(*g, precision="fp32_ir", precond="gmg", mg_levels=3)
+             for g in synth.SERVING_GRIDS]
+    assert all(a < b for a, b in zip(sizes, sizes[1:]))
+    assert sizes[-1] < 1 << 30  # the largest request fits easily in HBM

@@ -1,0 +1,60 @@
+"""Continuous batching: every design's result is the same alone and in the
+mix, admission respects the HBM budget, and one result matches the oracle."""
+import numpy as np
+import pytest
+import torch
+
+from oracle import fe_oracle as O
+from paper_2104_12282_amd import serve, synth
+
+pytestmark = pytest.mark.gpu
+DEV = "cuda:0"
+
+
+def _requests(n, seed=0):
+    grids = ((32, 16, 16), (48, 24, 24), (16, 8, 8))
+    return synth.serving_requests(n, seed=seed, grids=grids)
+
+
+def test_results_same_alone_and_in_the_mix():
+    reqs = _requests(10)
+    arrivals = np.linspace(0.0, 0.02, len(reqs))  # arrive while others are on the GPU
+    mix, st = serve.run_engine(reqs, arrivals, device=DEV, max_active=6, keep_outputs=True)
+    alone, _ = serve.run_sequential(reqs, device=DEV, keep_outputs=True)
+    assert st["requests"] == len(reqs) and st["max_active"] > 1
+    for r in reqs:
+        a, b = mix[r["id"]], alone[r["id"]]
+        assert a["iters"] == b["iters"]
+        assert np.array_equal(a["u"], b["u"])      # same arithmetic, bitwise
+        assert np.array_equal(a["dc"], b["dc"])
+        assert a["rel_res"] <= 1e-8
+
+
+def test_admission_by_footprint():
+    reqs = _requests(5, seed=3)
+    fps = [serve.request_footprint(*r["grid"], precision="fp32_ir", precond="gmg", mg_levels=3)
+           for r in reqs]
+    budget = max(fps) + 1  # room for one design at a time
+    res, st = serve.run_engine(reqs, None, device=DEV, max_active=8, hbm_budget=budget)
+    assert st["requests"] == len(reqs)
+    assert st["max_active"] == 1
+    # admissions never overlap: each admits after the previous finished
+    seq = sorted(res.values(), key=lambda r: r["admit"])
+    for prev, nxt in zip(seq, seq[1:]):
+        assert nxt["admit"] >= prev["finish"] - 1e-3
+
+
+def test_served_design_matches_oracle():
+    req = {"id": 0, "grid": (16, 8, 8), "seed": 1234}
+    res, _ = serve.run_engine([req], None, device=DEV, keep_outputs=True)
+    nx, ny, nz = req["grid"]
+    f, rho0 = serve.prepare_inputs(req, DEV)
+    P = O.filter_matrix(nx, ny, nz, 1.5)
+    rho = P @ (P @ (P @ rho0))
+    Ke = O.hex8_ke(0.3)
+    u = O.solve_direct(nx, ny, nz, O.simp_modulus(rho), Ke, f, O.clamp_x0_fixed(nx, ny, nz))
+    c_ref = O.compliance(f, u)
+    dc_ref = O.sensitivity(nx, ny, nz, Ke, rho, u)
+    r = res[0]
+    assert abs(r["compliance"] - c_ref) / c_ref <= 1e-6
+    assert np.abs(r["dc"] - dc_ref).max() / np.abs(dc_ref).max() <= 1e-5
