@@ -44,6 +44,8 @@ def parse():
     ap.add_argument("--move", type=float, default=0.2)
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--cpu-grid", type=str, default="80x40x20")
+    ap.add_argument("--serving", type=int, default=256,
+                    help="requests of the serving stream to run (0: skip)")
     ap.add_argument("--copy-probe", action="store_true",
                     help="also run one device-to-device copy of 512 MiB (reference for counters)")
     return ap.parse_args()
@@ -101,6 +103,36 @@ def cpu_baseline(grid, rtol):
                        f"sensitivity, filter, OC) on the {nx}x{ny}x{nz} cantilever, "
                        f"{dt:.2f} s; the 224x112x56 step needs ~675 GB for the banded factor"),
             "seconds": dt}
+
+
+def serving_bench(n, torch):
+    """Serving stream of n seeded requests over the five grid sizes: the same
+    requests one at a time (blocking solves), then through the continuous-
+    batching engine all at once (throughput) and as Poisson arrivals at 0.5x
+    and 2x the sequential rate (latency under load)."""
+    from paper_2104_12282_amd import serve, synth
+    reqs = synth.serving_requests(n, seed=0)
+    serve.run_engine(reqs[:8], None)  # warm-up: kernels, graphs, allocator
+    _, seq = serve.run_sequential(reqs)
+    print(f"bench[serving]: sequential {seq['designs_per_s']:.1f} designs/s", file=sys.stderr, flush=True)
+    _, sat = serve.run_engine(reqs, None)
+    print(f"bench[serving]: engine {sat['designs_per_s']:.1f} designs/s", file=sys.stderr, flush=True)
+    out = {"requests": n, "grids": [list(g) for g in synth.SERVING_GRIDS],
+           "per_request": "load at a random node of x = nx (random direction), density U(0.01,1) "
+                          "through 3 filter passes, float32 CG with 3-level multigrid inside float64 "
+                          "refinement to 1e-8, then sensitivity",
+           "sequential": seq, "engine_all_at_once": sat, "poisson": {}}
+    for mult in (0.5, 2.0):
+        rate = mult * seq["designs_per_s"]
+        arr = synth.poisson_arrivals(n, rate, seed=1)
+        _, st = serve.run_engine(reqs, arr)
+        st["arrival_rate_per_s"] = rate
+        out["poisson"][f"{mult}x_sequential_rate"] = st
+        print(f"bench[serving]: poisson {mult}x: {st['designs_per_s']:.1f} designs/s p50 "
+              f"{st['p50_latency_s']*1e3:.1f} ms p99 {st['p99_latency_s']*1e3:.1f} ms", file=sys.stderr,
+              flush=True)
+    out["speedup_vs_sequential"] = sat["designs_per_s"] / seq["designs_per_s"]
+    return out
 
 
 def run_loop(fe, synth, torch, nx, ny, nz, precision, args, steps, warmup, profile):
@@ -231,6 +263,8 @@ def main():
                       "ms_per_step": 1e3 * dt2 / args.steps,
                       "cg_iters_per_solve": float(np.mean(rec2["iters"])),
                       "compliance_max_rel_diff": float(np.max(np.abs(c2 - c1) / np.abs(c1)))}
+    if args.serving > 0:
+        out["serving"] = serving_bench(args.serving, torch)
     if not args.no_cpu_baseline:
         cg = tuple(int(v) for v in args.cpu_grid.split("x"))
         out["cpu_baseline"] = cpu_baseline(cg, args.rtol)
