@@ -722,7 +722,8 @@ int kstats_begin(fe_problem* p, double bytes) {
     ks.cap_ev->push_back(a);
     ks.cap_ev->push_back(b);
     ks.cap_bytes->push_back(bytes);
-    (void)hipEventRecord(a, p->stream);
+    // external: captured as an event-record node that records on every replay
+    (void)hipEventRecordWithFlags(a, p->stream, hipEventRecordExternal);
     return (int)ks.cap_bytes->size() - 1;
   }
   const size_t slot = (size_t)ks.pending;
@@ -746,7 +747,7 @@ void kstats_end(fe_problem* p, int slot) {
   if (slot < 0) return;
   KStats& ks = p->kst;
   if (ks.cap_ev) {
-    (void)hipEventRecord((*ks.cap_ev)[2 * (size_t)slot + 1], p->stream);
+    (void)hipEventRecordWithFlags((*ks.cap_ev)[2 * (size_t)slot + 1], p->stream, hipEventRecordExternal);
     return;
   }
   (void)hipEventRecord(ks.ev[2 * (size_t)slot + 1], p->stream);
