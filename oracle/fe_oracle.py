@@ -188,6 +188,32 @@ def assemble_K(nx, ny, nz, E_elem, Ke) -> sp.csr_matrix:
     return K
 
 
+def apply_K_rows(nx, ny, nz, E_elem, Ke, fixed, u, nodes):
+    """Rows of y = K_ff u_f at the given nodes, one node at a time from the
+    (up to) eight bricks around it: y_n = sum_e E_e (Ke u_e)[local(n, e)].
+    Returns an (len(nodes), 3) array (zero on fixed dofs)."""
+    uf = np.where(fixed, 0.0, u)
+    out = np.zeros((len(nodes), 3))
+    for r, n in enumerate(nodes):
+        i = n % (nx + 1)
+        j = (n // (nx + 1)) % (ny + 1)
+        k = n // ((nx + 1) * (ny + 1))
+        for a, (di, dj, dk) in enumerate(LOCAL_NODES):
+            ei, ej, ek = i - di, j - dj, k - dk
+            if not (0 <= ei < nx and 0 <= ej < ny and 0 <= ek < nz):
+                continue
+            dofs = []
+            for b, (bi, bj, bk) in enumerate(LOCAL_NODES):
+                m = node_index(nx, ny, nz, ei + bi, ej + bj, ek + bk)
+                dofs.extend((3 * m, 3 * m + 1, 3 * m + 2))
+            e = ei + nx * (ej + ny * ek)
+            out[r] += E_elem[e] * (Ke[3 * a:3 * a + 3, :] @ uf[dofs])
+        for c in range(3):
+            if fixed[3 * n + c]:
+                out[r, c] = 0.0
+    return out
+
+
 def apply_K_free(K: sp.csr_matrix, fixed: np.ndarray, u: np.ndarray) -> np.ndarray:
     """y = K_ff u_f on free dofs, 0 on fixed dofs (fixed entries of u are
     ignored)."""
@@ -279,6 +305,14 @@ def element_energies(nx, ny, nz, Ke, u) -> np.ndarray:
     """u_e^T Ke u_e of every element (unit modulus)."""
     Ue = u[element_dofs(nx, ny, nz)]
     return np.einsum("ei,ij,ej->e", Ue, Ke, Ue)
+
+
+def sensitivity_elements(nx, ny, nz, Ke, rho, u, elems, E0=1.0, Emin=1e-9, penal=3.0):
+    """Eq. (5) for the given elements only (same formula as sensitivity)."""
+    edof = element_dofs(nx, ny, nz)[elems]
+    Ue = u[edof]
+    ee = np.einsum("ei,ij,ej->e", Ue, Ke, Ue)
+    return -penal * np.asarray(rho)[elems] ** (penal - 1.0) * (E0 - Emin) * ee
 
 
 def sensitivity(nx, ny, nz, Ke, rho, u, E0=1.0, Emin=1e-9, penal=3.0):

@@ -364,3 +364,18 @@ def test_pins_catch_planted_mistakes(monkeypatch):
     Ke_bad = O.hex8_ke(NU)
     R = O.rigid_body_modes(O.LOCAL_NODES.astype(float))
     assert np.abs(Ke_bad @ R).max() > 1e-3
+
+
+def test_row_and_element_samplers_agree_with_full_forms(Ke):
+    nx, ny, nz = 5, 4, 3
+    rng = np.random.default_rng(3)
+    E = rng.uniform(0.1, 1.0, nx * ny * nz)
+    u = rng.standard_normal(3 * (nx + 1) * (ny + 1) * (nz + 1))
+    fixed = O.clamp_x0_fixed(nx, ny, nz)
+    y = O.apply_K_free(O.assemble_K(nx, ny, nz, E, Ke), fixed, u).reshape(-1, 3)
+    nodes = np.arange(y.shape[0])
+    assert np.abs(O.apply_K_rows(nx, ny, nz, E, Ke, fixed, u, nodes) - y).max() < 1e-13
+    rho = rng.uniform(0.1, 1.0, nx * ny * nz)
+    el = np.array([0, 7, 33, 59])
+    assert np.abs(O.sensitivity_elements(nx, ny, nz, Ke, rho, u, el)
+                  - O.sensitivity(nx, ny, nz, Ke, rho, u)[el]).max() < 1e-13
