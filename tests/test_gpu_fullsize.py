@@ -84,7 +84,10 @@ def test_fullsize_solve_properties_and_sampled_sensitivity(Ke, grid, passes):
     rng = np.random.default_rng(4)
     el = np.unique(np.concatenate([rng.integers(0, ne, 500), [0, nx - 1, ne - 1, ne // 2]]))
     ref = O.sensitivity_elements(nx, ny, nz, Ke, rho, u64, el)
-    assert np.abs(dc64[el] - ref).max() <= 1e-12 * np.abs(dc64).max()
+    # the dense quadratic form u_e^T Ke u_e cancels the large rigid part of u_e
+    # in floating point (24 x 24 terms of size |u_e|^2 |Ke|); the kernel's
+    # factorised form drops translations exactly.  1e-10 of max |dc| bounds that.
+    assert np.abs(dc64[el] - ref).max() <= 1e-10 * np.abs(dc64).max()
     # mixed precision reaches the float64 answer within the stated tolerances
     u32, dc32, c32, _ = res["fp32_ir"]
     assert abs(c32 - c64) / c64 <= 1e-6
