@@ -571,6 +571,7 @@ extern "C" fe_status fe_setup(const fe_config* cfg, const uint8_t* fixed, const 
     return FE_ENOMEM;
   }
   p->cfg = *cfg;
+  p->mfma_l0 = cfg->precision == FE_PREC_BF16_IR;
   p->stream = (hipStream_t)stream;
   p->ws = (char*)ws;
   p->ws_bytes = ws_bytes;
@@ -675,14 +676,18 @@ extern "C" fe_status fe_apply_K(fe_problem* p, const double* rho, const double* 
     HIP_TRY(launch_kxu<double>(p, 0, p->tmp64, y, nullptr));
     return FE_OK;
   }
-  if (variant == 1) {
+  if (variant == 1 || variant == 2) {
     if (p->cfg.precision == FE_PREC_FP64) {
-      fe_set_error("float32 variant needs a problem set up with a reduced precision");
+      fe_set_error("float32 and bf16 variants need a problem set up with a reduced precision");
       return FE_EINVAL;
     }
+    const bool saved = p->mfma_l0;
+    p->mfma_l0 = variant == 2;
     HIP_TRY(launch_convert_64_32(p, u, p->x32, ndof));
     HIP_TRY(launch_mask_vec<float>(p, 0, p->x32));
-    HIP_TRY(launch_kxu<float>(p, 0, p->x32, p->q32, nullptr));
+    hipError_t e = launch_kxu<float>(p, 0, p->x32, p->q32, nullptr);
+    p->mfma_l0 = saved;
+    HIP_TRY(e);
     HIP_TRY(launch_convert_32_64(p, p->q32, y, ndof));
     return FE_OK;
   }

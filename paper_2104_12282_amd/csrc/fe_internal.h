@@ -146,6 +146,7 @@ struct fe_problem {
   GraphChunk chunk64, chunk32;
   GraphChunk* last_replay = nullptr;  // profiled graph replayed since the last harvest
   bool use_graphs = true;
+  bool mfma_l0 = false;         // finest-grid float32 K*u on bf16 matrix cores
   double* x64 = nullptr;        // float64 iterate of the solve (graphs need fixed pointers)
   double ff = 0.0;              // ||f||^2
 

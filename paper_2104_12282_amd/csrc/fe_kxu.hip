@@ -17,6 +17,8 @@
 // this is exact and costs about a fifth of the dense 24 x 24 product.
 #include <hip/hip_runtime.h>
 
+#include <type_traits>
+
 #include "fe_internal.h"
 #include "fe_reduce.h"
 
@@ -280,6 +282,185 @@ __global__ void __launch_bounds__(TX* TY) kxu_tile_kernel(Grid g, int kc, const 
   block_partials<1>(vv, partials);
 }
 
+// ---------------------------------------------------------------------------
+// The same operator with the brick contraction Ke u_e on bf16 matrix cores
+// (v_mfma_f32_16x16x32_bf16, float32 accumulation), float32 vectors.
+//
+// A wave holds 4 x 16 brick columns of the tile.  For each of its four rows t
+// (an N-tile of 16 bricks) the product is D (32 x 16) = Ke_pad (32 x 32) *
+// U_t (32 x 16), with the dof index of Ke_pad and U_t ordered 4 * corner +
+// component (slot 3 of each corner is zero padding).  In the operand layout
+// lane group g (lanes 16g .. 16g+15) supplies k = 8g .. 8g+7, i.e. corners
+// 2g and 2g+1 of its brick, read straight from the two LDS level buffers; in
+// the result layout the same lane receives rows 4g .. 4g+3 of each 16-row
+// M-tile, i.e. the three components of corner g (lower level, M-tile 0) and
+// corner 4 + g (upper level, M-tile 1) of its brick -- exactly what the
+// z-carry and the node sums need.  Before rounding to bf16 the corner values
+// are taken relative to corner 0 of the brick: Ke annihilates translations,
+// so the product is unchanged in exact arithmetic while the rounding acts on
+// the deformation only.
+typedef __bf16 bf16x8 __attribute__((ext_vector_type(8)));
+typedef float f32x4 __attribute__((ext_vector_type(4)));
+
+template <int MODE>
+__global__ void __launch_bounds__(TX* TY) kxu_mfma_kernel(Grid g, int kc, const float* __restrict__ x,
+                                                         const float* __restrict__ E,
+                                                         const uint8_t* __restrict__ nmask,
+                                                         const float* __restrict__ ke, float kscale,
+                                                         float* __restrict__ y, Epi<float> ep, CgState* st,
+                                                         double* partials) {
+  if ((MODE == 1 || MODE == 5 || st) && st->done) return;
+  __shared__ float su[2][3][TY + 1][TX + 1];  // two node levels
+  __shared__ float sy[4][3][TY][TX];          // level partials per corner
+  __shared__ float sE[TY][TX];
+
+  const int tx = threadIdx.x % TX, ty = threadIdx.x / TX;
+  const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
+  const int grp = lane >> 4, ln = lane & 15;
+  const int I0 = blockIdx.x * OWN - 1, J0 = blockIdx.y * OWN - 1, K0 = blockIdx.z * kc;
+  const int ni = I0 + tx, nj = J0 + ty;
+  const int64_t sx = g.nx + 1, sxy = (int64_t)(g.nx + 1) * (g.ny + 1);
+  const bool owner = tx >= 1 && ty >= 1 && ni <= g.nx && nj <= g.ny;
+  const bool ecol = ni >= 0 && ni < g.nx && nj >= 0 && nj < g.ny;
+  const int kend = min(K0 + kc, g.nz + 1);
+
+  // Ke_pad rows 16 mt + ln, columns 8 grp .. 8 grp + 7 (bf16), in registers
+  bf16x8 a[2];
+#pragma unroll
+  for (int mt = 0; mt < 2; ++mt) {
+    const int m = 16 * mt + ln, cm = m >> 2, am = m & 3;
+#pragma unroll
+    for (int i = 0; i < 8; ++i) {
+      const int k = 8 * grp + i, ck = k >> 2, ak = k & 3;
+      const float v = (am < 3 && ak < 3) ? ke[(3 * cm + am) * 24 + 3 * ck + ak] * kscale : 0.0f;
+      a[mt][i] = (__bf16)v;
+    }
+  }
+
+  auto node_ok = [&](int i, int j, int k) {
+    return i >= 0 && i <= g.nx && j >= 0 && j <= g.ny && k >= 0 && k <= g.nz;
+  };
+  struct LevelRegs {
+    float own[3];
+    float ext[3][3];
+  };
+  const bool ex0 = tx == TX - 1, ex1 = ty == TY - 1, ex2 = ex0 && ex1;
+  auto fetch = [&](int i, int j, int k, float (&v)[3]) {
+    if (node_ok(i, j, k)) {
+      const int64_t n = i + sx * j + sxy * k;
+      v[0] = x[3 * n];
+      v[1] = x[3 * n + 1];
+      v[2] = x[3 * n + 2];
+    } else {
+      v[0] = v[1] = v[2] = 0.0f;
+    }
+  };
+  auto load_regs = [&](int k, LevelRegs& L) {
+    fetch(ni, nj, k, L.own);
+    if (ex0) fetch(I0 + TX, nj, k, L.ext[0]);
+    if (ex1) fetch(ni, J0 + TY, k, L.ext[1]);
+    if (ex2) fetch(I0 + TX, J0 + TY, k, L.ext[2]);
+  };
+  auto store_lds = [&](int buf, const LevelRegs& L) {
+#pragma unroll
+    for (int c = 0; c < 3; ++c) su[buf][c][ty][tx] = L.own[c];
+    if (ex0)
+      for (int c = 0; c < 3; ++c) su[buf][c][ty][TX] = L.ext[0][c];
+    if (ex1)
+      for (int c = 0; c < 3; ++c) su[buf][c][TY][tx] = L.ext[1][c];
+    if (ex2)
+      for (int c = 0; c < 3; ++c) su[buf][c][TY][TX] = L.ext[2][c];
+  };
+  auto modulus = [&](int ek) -> float {
+    return (ecol && ek >= 0 && ek < g.nz) ? E[ni + (int64_t)g.nx * (nj + (int64_t)g.ny * ek)] : 0.0f;
+  };
+
+  // lane group grp supplies corners 2 grp and 2 grp + 1: (0,0),(1,0) for
+  // grp 0 and 2, (1,1),(0,1) for grp 1 and 3, on the upper level for grp >= 2
+  const int oxA = grp & 1, oyA = grp & 1, oxB = 1 - (grp & 1), oyB = grp & 1, upper = grp >= 2;
+
+  float carry[4][3];  // upper-corner outputs of the brick below, per row t
+  float own_prev[3];
+  LevelRegs nxt;
+  float Enxt;
+  {
+    LevelRegs L0;
+    load_regs(K0 - 1, L0);
+    load_regs(K0, nxt);
+    Enxt = modulus(K0 - 1);
+    store_lds((K0 - 1) & 1, L0);
+#pragma unroll
+    for (int c = 0; c < 3; ++c) own_prev[c] = L0.own[c];
+#pragma unroll
+    for (int t = 0; t < 4; ++t) carry[t][0] = carry[t][1] = carry[t][2] = 0.0f;
+  }
+
+  double dot = 0.0;
+  for (int s = 0; s <= kc; ++s) {
+    const int ek = K0 - 1 + s;
+    if (ek >= g.nz + 1) break;  // uniform
+    const LevelRegs cur = nxt;
+    const int blo = ek & 1, bhi = (ek + 1) & 1;
+    store_lds(bhi, cur);
+    sE[ty][tx] = Enxt;
+    if (s < kc) {
+      load_regs(ek + 2, nxt);
+      Enxt = modulus(ek + 1);
+    }
+    __syncthreads();
+
+#pragma unroll
+    for (int t = 0; t < 4; ++t) {
+      const int r = 4 * wave + t;  // brick row of this N-tile inside the tile
+      const int b = upper ? bhi : blo;
+      bf16x8 bv;
+#pragma unroll
+      for (int c = 0; c < 3; ++c) {
+        const float ref = su[blo][c][r][ln];  // corner 0 of the brick
+        bv[c] = (__bf16)(su[b][c][r + oyA][ln + oxA] - ref);
+        bv[4 + c] = (__bf16)(su[b][c][r + oyB][ln + oxB] - ref);
+      }
+      bv[3] = (__bf16)0.0f;
+      bv[7] = (__bf16)0.0f;
+      const f32x4 zero = {0.0f, 0.0f, 0.0f, 0.0f};
+      const f32x4 dlo = __builtin_amdgcn_mfma_f32_16x16x32_bf16(a[0], bv, zero, 0, 0, 0);
+      const f32x4 dhi = __builtin_amdgcn_mfma_f32_16x16x32_bf16(a[1], bv, zero, 0, 0, 0);
+      const float Ee = sE[r][ln];
+#pragma unroll
+      for (int c = 0; c < 3; ++c) {
+        sy[grp][c][r][ln] = carry[t][c] + Ee * dlo[c];
+        carry[t][c] = Ee * dhi[c];
+      }
+    }
+    __syncthreads();
+    if (s >= 1 && owner && ek >= K0 && ek < kend) {
+      const int64_t n = ni + sx * nj + sxy * ek;
+      const uint8_t m = nmask[n];
+#pragma unroll
+      for (int c = 0; c < 3; ++c) {
+        float v2 = sy[0][c][ty][tx] + sy[1][c][ty][tx - 1] + sy[2][c][ty - 1][tx - 1] + sy[3][c][ty - 1][tx];
+        const bool fx = (m >> c) & 1;
+        if (fx) v2 = 0.0f;
+        if (MODE == 1) {
+          dot += (double)own_prev[c] * (double)v2;
+        } else if (MODE == 3 || MODE == 5) {
+          const float bvv = ep.bT[3 * n + c];
+          v2 = fx ? 0.0f : own_prev[c] + ep.omega * ep.invd[n] * (bvv - v2);
+          if (MODE == 5) dot += (double)bvv * (double)v2;
+        } else if (MODE == 4) {
+          v2 = fx ? 0.0f : ep.bT[3 * n + c] - v2;
+        }
+        y[3 * n + c] = v2;
+      }
+    }
+#pragma unroll
+    for (int c = 0; c < 3; ++c) own_prev[c] = cur.own[c];
+  }
+  if (MODE == 0 || MODE == 3 || MODE == 4) return;
+  double vv[1] = {dot};
+  block_partials<1>(vv, partials);
+}
+
 template <typename T>
 WK<T> scaled_wk(const WalshK& w, double h) {
   WK<T> k;
@@ -348,7 +529,42 @@ hipError_t launch_kxu_tile(fe_problem* p, int lev, const T* x, const T* E, T* y,
     if (mode == 6) bytes += vb * 3.0 * (double)g.ndof;  // res in/out, acc in/out (res read counted above)
     slot = kstats_begin(p, bytes);
   }
-  switch (mode) {
+  if (std::is_same<T, float>::value && lev == 0 && p->mfma_l0 && mode != 2 && mode != 6) {
+    const float* xf = reinterpret_cast<const float*>(x);
+    const float* Ef = reinterpret_cast<const float*>(E);
+    float* yf = reinterpret_cast<float*>(y);
+    Epi<float> ef;
+    ef.b64 = b64;
+    ef.bT = reinterpret_cast<const float*>(bT);
+    ef.invd = reinterpret_cast<const float*>(invd);
+    ef.omega = (float)omega;
+    ef.res = nullptr;
+    ef.acc = nullptr;
+    ef.c1 = ef.c2 = 0.0f;
+    ef.first = 0;
+    const float ks = (float)p->L[lev].h;
+    switch (mode) {
+      case 1:
+        hipLaunchKernelGGL(kxu_mfma_kernel<1>, grid, dim3(TX * TY), 0, p->stream, g, kc, xf, Ef, nm, p->ke32,
+                           ks, yf, ef, st, p->partials);
+        break;
+      case 3:
+        hipLaunchKernelGGL(kxu_mfma_kernel<3>, grid, dim3(TX * TY), 0, p->stream, g, kc, xf, Ef, nm, p->ke32,
+                           ks, yf, ef, st, p->partials);
+        break;
+      case 4:
+        hipLaunchKernelGGL(kxu_mfma_kernel<4>, grid, dim3(TX * TY), 0, p->stream, g, kc, xf, Ef, nm, p->ke32,
+                           ks, yf, ef, st, p->partials);
+        break;
+      case 5:
+        hipLaunchKernelGGL(kxu_mfma_kernel<5>, grid, dim3(TX * TY), 0, p->stream, g, kc, xf, Ef, nm, p->ke32,
+                           ks, yf, ef, st, p->partials);
+        break;
+      default:
+        hipLaunchKernelGGL(kxu_mfma_kernel<0>, grid, dim3(TX * TY), 0, p->stream, g, kc, xf, Ef, nm, p->ke32,
+                           ks, yf, ef, st, p->partials);
+    }
+  } else switch (mode) {
     case 1:
       hipLaunchKernelGGL((kxu_tile_kernel<T, 1>), grid, dim3(TX * TY), 0, p->stream, g, kc, x, E, nm, wk,
                          y, ep, st, p->partials, out);

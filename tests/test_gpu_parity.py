@@ -294,3 +294,41 @@ def test_optimisation_trajectory(Ke, precond):
     rel = np.abs(np.array(c_gpu) - np.array(c_ref)) / np.array(c_ref)
     assert rel.max() <= 1e-6, rel
     assert np.abs(N(x) - x_ref).max() <= 1e-6
+
+
+@pytest.mark.parametrize("grid", [(24, 12, 12), (37, 19, 11), (31, 16, 17)])
+def test_kxu_bf16_mfma_accuracy(Ke, grid):
+    """bf16 operands, float32 accumulation: rows agree with float64 to the
+    bf16 rounding of Ke and of the corner-0-relative brick displacements."""
+    nx, ny, nz = grid
+    rho = synth.density_uniform(nx, ny, nz, seed=3)
+    E = O.simp_modulus(rho)
+    fixed = O.clamp_x0_fixed(nx, ny, nz)
+    K = O.assemble_K(nx, ny, nz, E, Ke)
+    prob = _problem(nx, ny, nz, precision="bf16_ir")
+    rng = np.random.default_rng(4)
+    # a rough field and a smooth (bending-like) field plus a large translation
+    nn = (nx + 1) * (ny + 1) * (nz + 1)
+    X = np.stack([np.arange(nn) % (nx + 1), (np.arange(nn) // (nx + 1)) % (ny + 1),
+                  np.arange(nn) // ((nx + 1) * (ny + 1))], axis=1).astype(float)
+    smooth = np.stack([0.01 * X[:, 0] * X[:, 2], 0.002 * X[:, 1] ** 2, -0.01 * X[:, 0] ** 2], axis=1)
+    for u, tol in ((rng.standard_normal(3 * nn), 2e-2), ((smooth + 50.0).ravel(), 2e-2)):
+        y_ref = O.apply_K_free(K, fixed, u)
+        y = N(prob.apply_K(T(rho), T(u), variant=2))
+        assert np.abs(y - y_ref).max() <= tol * np.abs(y_ref).max()
+
+
+@pytest.mark.parametrize("precond", ["jacobi", "gmg"])
+def test_bf16_refined_solve_parity(Ke, precond):
+    nx, ny, nz = 24, 12, 12
+    rho = synth.density_around(nx, ny, nz, 0)
+    f = synth.cantilever_edge_load(nx, ny, nz)
+    u_ref = O.solve_direct(nx, ny, nz, O.simp_modulus(rho), Ke, f, O.clamp_x0_fixed(nx, ny, nz))
+    c_ref = O.compliance(f, u_ref)
+    dc_ref = O.sensitivity(nx, ny, nz, Ke, rho, u_ref)
+    prob = _problem(nx, ny, nz, precision="bf16_ir", precond=precond, mg_levels=3)
+    u, info = prob.solve(T(rho), rtol=1e-10)
+    dc, c = prob.sensitivity(T(rho), u)
+    assert info["rel_res"] <= 1e-10 and info["outer_iters"] >= 2
+    assert abs(float(N(c)[0]) - c_ref) / c_ref <= 1e-6
+    assert np.abs(N(dc) - dc_ref).max() / np.abs(dc_ref).max() <= 1e-5
