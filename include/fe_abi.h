@@ -53,8 +53,12 @@ typedef enum {
 
 enum { FE_PREC_FP64 = 0,     /* vectors, K*u and dots in float64 */
        FE_PREC_FP32_IR = 1,  /* float32 CG inside float64 iterative refinement */
-       FE_PREC_BF16_IR = 2   /* as FP32_IR with the element contraction Ke*u_e on
-                                bf16 matrix cores, float32 accumulation */ };
+       FE_PREC_BF16_IR = 2,  /* as FP32_IR with the element contraction Ke*u_e of
+                                the finest-grid K*u on bf16 matrix cores (rigid
+                                motion of each brick removed before rounding),
+                                float32 accumulation */
+       FE_PREC_BF16X3_IR = 3 /* as BF16_IR with Ke and u_e each split into a
+                                hi + lo pair of bf16 numbers (three products) */ };
 
 enum { FE_PRECOND_JACOBI = 0, FE_PRECOND_GMG = 1 };
 
@@ -99,8 +103,10 @@ FE_API fe_status fe_setup(const fe_config* cfg, const uint8_t* fixed, const doub
 
 /* y = K(rho) u restricted to the free dofs (fixed rows and columns removed,
  * y = 0 on fixed dofs).  variant: 0 = float64, 1 = float32 vector,
- * 2 = bf16 matrix cores (float32 accumulation); the low-precision variants
- * convert u and y at the boundary.  rho: float64[nelem]. */
+ * 2 = bf16 matrix cores (float32 accumulation), 3 = float64 dense-Ke
+ * reference kernel, 4 = split-bf16 matrix cores; variants 1, 2 and 4 need a
+ * problem set up with a reduced precision and convert u and y at the
+ * boundary.  rho: float64[nelem]. */
 FE_API fe_status fe_apply_K(fe_problem* p, const double* rho, const double* u, double* y,
                      int32_t variant);
 

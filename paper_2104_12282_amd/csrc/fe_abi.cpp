@@ -45,7 +45,7 @@ std::string validate(const fe_config* c) {
   if (!(c->Emin > 0.0 && c->Emin < c->E0)) return "Emin must lie in (0, E0)";
   if (!(c->penal >= 1.0) || !std::isfinite(c->penal)) return "penal must be >= 1";
   if (!(c->filter_r > 0.0) || c->filter_r > 7.0) return "filter_r must lie in (0, 7]";
-  if (c->precision < FE_PREC_FP64 || c->precision > FE_PREC_BF16_IR) return "unknown precision";
+  if (c->precision < FE_PREC_FP64 || c->precision > FE_PREC_BF16X3_IR) return "unknown precision";
   if (c->precond != FE_PRECOND_JACOBI && c->precond != FE_PRECOND_GMG) return "unknown preconditioner";
   if (c->reserved != 0) return "reserved must be 0";
   if (c->precond == FE_PRECOND_GMG) {
@@ -130,6 +130,7 @@ size_t layout(const fe_config* c, fe_problem* p, char* base) {
   double* oc = (double*)take(64 * sizeof(double));
   double* ke64 = (double*)take(576 * sizeof(double));
   float* ke32 = (float*)take(576 * sizeof(float));
+  double* zpad = (double*)take(8 * sizeof(double));
   if (p) {
     p->nlev = nl;
     p->f = f;
@@ -151,6 +152,7 @@ size_t layout(const fe_config* c, fe_problem* p, char* base) {
     p->oc = oc;
     p->ke64 = ke64;
     p->ke32 = ke32;
+    p->zpad = zpad;
   }
   return align_up(off);
 }
@@ -571,7 +573,7 @@ extern "C" fe_status fe_setup(const fe_config* cfg, const uint8_t* fixed, const 
     return FE_ENOMEM;
   }
   p->cfg = *cfg;
-  p->mfma_l0 = cfg->precision == FE_PREC_BF16_IR;
+  p->mfma_l0 = cfg->precision == FE_PREC_BF16_IR ? 1 : cfg->precision == FE_PREC_BF16X3_IR ? 2 : 0;
   p->stream = (hipStream_t)stream;
   p->ws = (char*)ws;
   p->ws_bytes = ws_bytes;
@@ -637,6 +639,7 @@ extern "C" fe_status fe_setup(const fe_config* cfg, const uint8_t* fixed, const 
   if ((e = hipMemcpyAsync(p->st_w, w, n * sizeof(double), hipMemcpyHostToDevice, p->stream)))
     return fail(e, "copy stencil weights");
   if ((e = launch_fill<double>(p, p->scal, NSCAL, 0.0))) return fail(e, "clear scalars");
+  if ((e = launch_fill<double>(p, p->zpad, 8, 0.0))) return fail(e, "clear zero pad");
   if ((e = launch_fill<double>(p, (double*)p->st, 2 * sizeof(CgState) / sizeof(double), 0.0)))
     return fail(e, "clear state");
   if ((e = launch_fill<double>(p, p->oc, 64, 0.0))) return fail(e, "clear oc state");
@@ -676,13 +679,13 @@ extern "C" fe_status fe_apply_K(fe_problem* p, const double* rho, const double* 
     HIP_TRY(launch_kxu<double>(p, 0, p->tmp64, y, nullptr));
     return FE_OK;
   }
-  if (variant == 1 || variant == 2) {
+  if (variant == 1 || variant == 2 || variant == 4) {
     if (p->cfg.precision == FE_PREC_FP64) {
       fe_set_error("float32 and bf16 variants need a problem set up with a reduced precision");
       return FE_EINVAL;
     }
-    const bool saved = p->mfma_l0;
-    p->mfma_l0 = variant == 2;
+    const int saved = p->mfma_l0;
+    p->mfma_l0 = variant == 2 ? 1 : variant == 4 ? 2 : 0;
     HIP_TRY(launch_convert_64_32(p, u, p->x32, ndof));
     HIP_TRY(launch_mask_vec<float>(p, 0, p->x32));
     hipError_t e = launch_kxu<float>(p, 0, p->x32, p->q32, nullptr);

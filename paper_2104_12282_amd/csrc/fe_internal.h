@@ -122,6 +122,7 @@ struct fe_problem {
 
   double* f = nullptr;     // load, zero on fixed dofs
   double* invW = nullptr;  // 1 / filter row sums
+  double* zpad = nullptr;  // 64 zero bytes: the source of loads outside the mesh
   int nstencil = 0;        // filter stencil: offsets and cone weights
   int4* st_off = nullptr;
   double* st_w = nullptr;
@@ -146,7 +147,7 @@ struct fe_problem {
   GraphChunk chunk64, chunk32;
   GraphChunk* last_replay = nullptr;  // profiled graph replayed since the last harvest
   bool use_graphs = true;
-  bool mfma_l0 = false;         // finest-grid float32 K*u on bf16 matrix cores
+  int mfma_l0 = 0;  // finest-grid float32 K*u: 0 vector ALUs, 1 bf16, 2 split-bf16 matrix cores
   double* x64 = nullptr;        // float64 iterate of the solve (graphs need fixed pointers)
   double ff = 0.0;              // ||f||^2
 

@@ -17,7 +17,11 @@
 // this is exact and costs about a fifth of the dense 24 x 24 product.
 #include <hip/hip_runtime.h>
 
+#include <algorithm>
+#include <map>
+#include <mutex>
 #include <type_traits>
+#include <utility>
 
 #include "fe_internal.h"
 #include "fe_reduce.h"
@@ -98,6 +102,35 @@ struct Epi {
   int first;          // MODE 6: the iterate starts at zero
 };
 
+// Workgroup -> tile.  The grid is one-dimensional; consecutive workgroups
+// are dispatched to the eight XCDs in turn, so workgroup b runs on XCD b % 8.
+// Each XCD is given one contiguous run of tiles (x fastest, then y, then the
+// z chunk): neighbouring tiles share their halo nodes through that XCD's L2.
+struct TileMap {
+  int gx, gy, nzc, kc, nblk;
+};
+
+__device__ inline void tile_of_block(const TileMap& tm, int& cx, int& cy, int& cz) {
+  const int b = blockIdx.x, xcd = b & 7, m = b >> 3;
+  const int q = tm.nblk >> 3, r = tm.nblk & 7;
+  const int lid = xcd * q + min(xcd, r) + m;
+  cx = lid % tm.gx;
+  const int rest = lid / tm.gx;
+  cy = rest % tm.gy;
+  cz = rest / tm.gy;
+}
+
+// x and y butterflies of one face (corners 00 10 11 01 of a node level):
+// the part of the brick transform that the brick below and the brick above
+// a face have in common.
+template <typename T>
+__device__ inline void face4(T (&v)[4]) {
+  bf(v[0], v[1]);
+  bf(v[3], v[2]);
+  bf(v[0], v[3]);
+  bf(v[1], v[2]);
+}
+
 // MODE 0: y = Kx.  MODE 1: CG step, pq = x^T y, alpha = rz / pq.
 // MODE 2: y = b - Kx (float64 only), ||y||^2 -> out[0].
 // MODE 3: damped Jacobi sweep y = x + omega D^-1 (b - Kx).
@@ -109,174 +142,237 @@ struct Epi {
 // For modes 3, 4 and 6 a non-null st only guards: the launch is skipped once
 // CG has stopped.  y must not alias x (other workgroups read x around their
 // tiles).
+//
+// Pipeline of one level step (brick layer ek between node levels ek and
+// ek + 1), with one barrier:
+//   1. the upper level (loaded one step ahead) goes to LDS buffer (ek+1)&1;
+//   2. loads are issued for the level after it and for the epilogue operands
+//      of level ek;
+//   3. barrier;
+//   4. the node sums of level ek - 1 (complete since the previous step) are
+//      read from partial buffer (ek-1)&1 and written out;
+//   5. the brick is computed: upper face from LDS, lower face (already in
+//      the x-y transformed form) from registers, z butterflies, S, inverse z
+//      butterflies; the upper half stays in registers as the carry to the
+//      next brick, the lower half plus the carry from the brick below is
+//      transformed back and goes to partial buffer ek&1.
+// Double buffering of both LDS arrays makes the single barrier sufficient:
+// a buffer is rewritten only after every thread has passed the barrier that
+// follows its last read.
 template <typename T, int MODE>
-__global__ void __launch_bounds__(TX* TY) kxu_tile_kernel(Grid g, int kc, const T* __restrict__ x,
+__global__ void __launch_bounds__(TX* TY) kxu_tile_kernel(Grid g, TileMap tm, const T* __restrict__ x,
                                                          const T* __restrict__ E,
                                                          const uint8_t* __restrict__ nmask, WK<T> wk,
                                                          T* __restrict__ y, Epi<T> ep, CgState* st,
-                                                         double* partials, double* out) {
+                                                         double* partials, double* out,
+                                                         const T* __restrict__ zpad) {
   if ((MODE == 1 || MODE == 5 || st) && st->done) return;
-  __shared__ T su[3][TY + 1][TX + 1];  // node values of the current upper level
-  __shared__ T sy[9][TY][TX];          // level partials of corners (1,0), (1,1), (0,1)
+  __shared__ T su[2][3][TY + 1][TX + 1];  // node values of a level (17 x 17 ring)
+  __shared__ T sy[2][9][TY][TX];          // lower-level partials of corners (1,0), (1,1), (0,1)
 
+  int cx, cy, cz;
+  tile_of_block(tm, cx, cy, cz);
+  const int kc = tm.kc;
   const int tx = threadIdx.x % TX, ty = threadIdx.x / TX;
-  const int I0 = blockIdx.x * OWN - 1, J0 = blockIdx.y * OWN - 1, K0 = blockIdx.z * kc;
+  const int I0 = cx * OWN - 1, J0 = cy * OWN - 1, K0 = cz * kc;
   const int ni = I0 + tx, nj = J0 + ty;
   const int64_t sx = g.nx + 1, sxy = (int64_t)(g.nx + 1) * (g.ny + 1);
   const bool owner = tx >= 1 && ty >= 1 && ni <= g.nx && nj <= g.ny;
   const bool ecol = ni >= 0 && ni < g.nx && nj >= 0 && nj < g.ny;
   const int kend = min(K0 + kc, g.nz + 1);  // owned levels: [K0, kend)
+  // halo slot: threads 0..16 load column TX (rows 0..16), 17..32 row TY
+  const int h = threadIdx.x;
+  const bool hslot = h < TX + TY + 1;
+  const int hx = h <= TY ? TX : h - (TY + 1), hy = h <= TY ? h : TY;
+  const int hi = I0 + hx, hj = J0 + hy;
 
   auto node_ok = [&](int i, int j, int k) {
     return i >= 0 && i <= g.nx && j >= 0 && j <= g.ny && k >= 0 && k <= g.nz;
   };
-  // Node values of one level held in registers: this thread's column and, for
-  // threads on the high edges of the tile, the extra column/row/corner that
-  // closes the 17 x 17 ring of the tile.
-  struct LevelRegs {
+  // Loads outside the mesh read a zero pad instead, so no instruction has to
+  // touch a load's registers before the data is used (a select after the
+  // load would make the wave wait for it at once).
+  struct LevelIn {
     T own[3];
-    T ext[3][3];
+    T halo[3];
+    T Ee;  // modulus of the brick layer below this level
   };
-  const bool ex0 = tx == TX - 1, ex1 = ty == TY - 1, ex2 = ex0 && ex1;
   auto fetch = [&](int i, int j, int k, T (&v)[3]) {
-    if (node_ok(i, j, k)) {
-      const int64_t n = i + sx * j + sxy * k;
-      v[0] = x[3 * n];
-      v[1] = x[3 * n + 1];
-      v[2] = x[3 * n + 2];
-    } else {
-      v[0] = v[1] = v[2] = T(0);
-    }
+    const T* src = node_ok(i, j, k) ? x + 3 * (i + sx * j + sxy * k) : zpad;
+    v[0] = src[0];
+    v[1] = src[1];
+    v[2] = src[2];
   };
-  auto load_regs = [&](int k, LevelRegs& L) {
+  auto load_level = [&](int k, LevelIn& L) {
     fetch(ni, nj, k, L.own);
-    if (ex0) fetch(I0 + TX, nj, k, L.ext[0]);
-    if (ex1) fetch(ni, J0 + TY, k, L.ext[1]);
-    if (ex2) fetch(I0 + TX, J0 + TY, k, L.ext[2]);
+    if (threadIdx.x < 64) fetch(hslot ? hi : ni, hslot ? hj : nj, k, L.halo);  // wave-uniform
+    const int ek = k - 1;
+    const bool ok = ecol && ek >= 0 && ek < g.nz;
+    L.Ee = *(ok ? E + (ni + (int64_t)g.nx * (nj + (int64_t)g.ny * ek)) : zpad);
   };
-  auto store_lds = [&](const LevelRegs& L) {
-#pragma unroll
-    for (int c = 0; c < 3; ++c) su[c][ty][tx] = L.own[c];
-    if (ex0)
-      for (int c = 0; c < 3; ++c) su[c][ty][TX] = L.ext[0][c];
-    if (ex1)
-      for (int c = 0; c < 3; ++c) su[c][TY][tx] = L.ext[1][c];
-    if (ex2)
-      for (int c = 0; c < 3; ++c) su[c][TY][TX] = L.ext[2][c];
-  };
-  auto modulus = [&](int ek) -> T {
-    return (ecol && ek >= 0 && ek < g.nz) ? E[ni + (int64_t)g.nx * (nj + (int64_t)g.ny * ek)] : T(0);
-  };
-
-  T lo[4][3];      // corners (0,0) (1,0) (1,1) (0,1) of the brick's lower level
-  T carry[4][3];   // contributions of the brick below to those corners
-  T own_prev[3];   // this thread's node at the lower level
-  LevelRegs nxt;
-  T Enxt;
-  {
-    LevelRegs L0;
-    load_regs(K0 - 1, L0);
-    load_regs(K0, nxt);  // in flight during the prologue
-    Enxt = modulus(K0 - 1);
-    store_lds(L0);
-    __syncthreads();
+  // stores the level into LDS and returns this thread's own values
+  auto store_level = [&](int buf, const LevelIn& L, T (&own)[3]) {
 #pragma unroll
     for (int c = 0; c < 3; ++c) {
-      own_prev[c] = L0.own[c];
-      lo[0][c] = su[c][ty][tx];
-      lo[1][c] = su[c][ty][tx + 1];
-      lo[2][c] = su[c][ty + 1][tx + 1];
-      lo[3][c] = su[c][ty + 1][tx];
-      carry[0][c] = carry[1][c] = carry[2][c] = carry[3][c] = T(0);
+      own[c] = L.own[c];
+      su[buf][c][ty][tx] = own[c];
     }
-    __syncthreads();
-  }
+    if (hslot)
+      for (int c = 0; c < 3; ++c) su[buf][c][hy][hx] = L.halo[c];
+  };
+  // epilogue operands of this thread's node at one level (read only by owners)
+  struct EpiIn {
+    uint8_t m;
+    T b[3];
+    T d;
+    T a[3];
+    double b2[3];
+  };
+  auto load_epi = [&](int k, EpiIn& P) {
+    const bool ok = owner && k >= K0 && k < kend;
+    const int64_t n = ok ? ni + sx * nj + sxy * k : 0;
+    P.m = nmask[n];
+#pragma unroll
+    for (int c = 0; c < 3; ++c) {
+      if (MODE == 2) P.b2[c] = ep.b64[3 * n + c];
+      if (MODE == 3 || MODE == 4 || MODE == 5) P.b[c] = ep.bT[3 * n + c];
+      if (MODE == 6) {
+        P.b[c] = ep.res[3 * n + c];
+        if (!ep.first) P.a[c] = ep.acc[3 * n + c];
+      }
+    }
+    if (MODE == 3 || MODE == 5 || MODE == 6) P.d = ep.invd[n];
+  };
 
   double dot = 0.0;
-  for (int s = 0; s <= kc; ++s) {
-    const int ek = K0 - 1 + s;  // brick layer between node levels ek and ek + 1
-    if (ek >= g.nz + 1) break;  // uniform over the workgroup
-    const LevelRegs cur = nxt;
-    const T Ee = Enxt;
-    store_lds(cur);
-    if (s < kc) {  // prefetch the next level while this one is computed
-      load_regs(ek + 2, nxt);
-      Enxt = modulus(ek + 1);
-    }
-    __syncthreads();
-
-    T v[3][8];
+  // node sums of level k: own corner p0 plus the partials of the three
+  // neighbouring brick columns, then the mode's epilogue
+  auto finish_level = [&](int k, const T (&p0)[3], const T (&own)[3], const EpiIn& P) {
+    if (!(owner && k >= K0 && k < kend)) return;
+    const int buf = k & 1;
+    const int64_t n = ni + sx * nj + sxy * k;
 #pragma unroll
     for (int c = 0; c < 3; ++c) {
-      v[c][0] = lo[0][c];
-      v[c][1] = lo[1][c];
-      v[c][2] = lo[2][c];
-      v[c][3] = lo[3][c];
-      v[c][4] = cur.own[c];
-      v[c][5] = su[c][ty][tx + 1];
-      v[c][6] = su[c][ty + 1][tx + 1];
-      v[c][7] = su[c][ty + 1][tx];
-      lo[0][c] = v[c][4];
-      lo[1][c] = v[c][5];
-      lo[2][c] = v[c][6];
-      lo[3][c] = v[c][7];
+      T v2 = p0[c] + sy[buf][0 + c][ty][tx - 1] + sy[buf][3 + c][ty - 1][tx - 1] + sy[buf][6 + c][ty - 1][tx];
+      const bool fx = (P.m >> c) & 1;
+      if (fx) v2 = T(0);
+      if (MODE == 2) {
+        v2 = fx ? T(0) : (T)(P.b2[c] - (double)v2);
+        dot += (double)v2 * (double)v2;
+      } else if (MODE == 1) {
+        dot += (double)own[c] * (double)v2;
+      } else if (MODE == 3 || MODE == 5) {
+        v2 = fx ? T(0) : own[c] + ep.omega * P.d * (P.b[c] - v2);
+        if (MODE == 5) dot += (double)P.b[c] * (double)v2;
+      } else if (MODE == 4) {
+        v2 = fx ? T(0) : P.b[c] - v2;
+      } else if (MODE == 6) {
+        const T dv = own[c];
+        const T rn = fx ? T(0) : P.b[c] - v2;
+        ep.res[3 * n + c] = rn;
+        ep.acc[3 * n + c] = ep.first ? dv : P.a[c] + dv;
+        v2 = fx ? T(0) : ep.c1 * dv + ep.c2 * P.d * rn;
+      }
+      y[3 * n + c] = v2;
     }
-    walsh8(v[0]);
-    walsh8(v[1]);
-    walsh8(v[2]);
+  };
+
+  T fl[3][4];      // lower face of the current brick, x-y transformed
+  T carry[3][4];   // upper half of the brick below (z-transformed), to this level
+  T own_lo[3];     // this thread's node on the lower level of the current brick
+  T own_ll[3];     // ... and on the level below it (its sums finish one step late)
+  T p0[3];         // own-corner sum of the level below
+  // ping-pong buffers: A/B hold the next upper level, PA/PB epilogue operands
+  LevelIn A, B;
+  EpiIn PA, PB;
+  {
+    LevelIn L0;
+    load_level(K0 - 1, L0);
+    load_level(K0, A);
+    const int b0 = (K0 - 1) & 1;
+    store_level(b0, L0, own_lo);
+    __syncthreads();
+#pragma unroll
+    for (int c = 0; c < 3; ++c) {
+      fl[c][0] = own_lo[c];
+      fl[c][1] = su[b0][c][ty][tx + 1];
+      fl[c][2] = su[b0][c][ty + 1][tx + 1];
+      fl[c][3] = su[b0][c][ty + 1][tx];
+      face4(fl[c]);
+      own_ll[c] = T(0);
+      p0[c] = T(0);
+      carry[c][0] = carry[c][1] = carry[c][2] = carry[c][3] = T(0);
+    }
+    PB.m = 0;
+  }
+
+  // one brick layer ek: `use` holds level ek + 1 (loaded one step ago),
+  // `fill` receives level ek + 2; Pu holds the operands of level ek - 1,
+  // Pf receives those of level ek
+  auto step = [&](int ek, const LevelIn& use, LevelIn& fill, const EpiIn& Pu, EpiIn& Pf) {
+    const int bu = (ek + 1) & 1;
+    T own_up[3];
+    store_level(bu, use, own_up);
+    if (ek + 2 <= kend) load_level(ek + 2, fill);  // uniform
+    load_epi(ek, Pf);
+    __syncthreads();
+
+    finish_level(ek - 1, p0, own_ll, Pu);
+
+    T t[3][8];
+#pragma unroll
+    for (int c = 0; c < 3; ++c) {
+      T fu[4];
+      fu[0] = own_up[c];
+      fu[1] = su[bu][c][ty][tx + 1];
+      fu[2] = su[bu][c][ty + 1][tx + 1];
+      fu[3] = su[bu][c][ty + 1][tx];
+      face4(fu);
+#pragma unroll
+      for (int i = 0; i < 4; ++i) {
+        t[c][i] = fl[c][i] + fu[i];
+        t[c][i + 4] = fl[c][i] - fu[i];
+        fl[c][i] = fu[i];
+      }
+    }
+    const T Ee = use.Ee;
     WK<T> k = wk;
     k.A *= Ee; k.B *= Ee; k.G *= Ee; k.C *= Ee; k.D *= Ee; k.F *= Ee; k.H *= Ee; k.J *= Ee;
     T w[3][8];
-    apply_S(k, v, w);
-    walsh8(w[0]);
-    walsh8(w[1]);
-    walsh8(w[2]);
-    // level-ek sums of this brick column's four corners
-    T p0[3];
+    apply_S(k, t, w);
+    const int bl = ek & 1;
 #pragma unroll
     for (int c = 0; c < 3; ++c) {
-      p0[c] = carry[0][c] + w[c][0];
-      sy[0 + c][ty][tx] = carry[1][c] + w[c][1];
-      sy[3 + c][ty][tx] = carry[2][c] + w[c][2];
-      sy[6 + c][ty][tx] = carry[3][c] + w[c][3];
-      carry[0][c] = w[c][4];
-      carry[1][c] = w[c][5];
-      carry[2][c] = w[c][6];
-      carry[3][c] = w[c][7];
-    }
-    __syncthreads();
-    if (s >= 1 && owner && ek >= K0 && ek < kend) {
-      const int64_t n = ni + sx * nj + sxy * ek;
-      const uint8_t m = nmask[n];
+      T lo[4];
 #pragma unroll
-      for (int c = 0; c < 3; ++c) {
-        T v2 = p0[c] + sy[0 + c][ty][tx - 1] + sy[3 + c][ty - 1][tx - 1] + sy[6 + c][ty - 1][tx];
-        const bool fx = (m >> c) & 1;
-        if (fx) v2 = T(0);
-        if (MODE == 2) {
-          v2 = fx ? T(0) : (T)(ep.b64[3 * n + c] - (double)v2);
-          dot += (double)v2 * (double)v2;
-        } else if (MODE == 1) {
-          dot += (double)own_prev[c] * (double)v2;
-        } else if (MODE == 3 || MODE == 5) {
-          const T bv = ep.bT[3 * n + c];
-          v2 = fx ? T(0) : own_prev[c] + ep.omega * ep.invd[n] * (bv - v2);
-          if (MODE == 5) dot += (double)bv * (double)v2;
-        } else if (MODE == 4) {
-          v2 = fx ? T(0) : ep.bT[3 * n + c] - v2;
-        } else if (MODE == 6) {
-          const T dv = own_prev[c];
-          const T rn = fx ? T(0) : ep.res[3 * n + c] - v2;
-          ep.res[3 * n + c] = rn;
-          ep.acc[3 * n + c] = ep.first ? dv : ep.acc[3 * n + c] + dv;
-          v2 = fx ? T(0) : ep.c1 * dv + ep.c2 * ep.invd[n] * rn;
-        }
-        y[3 * n + c] = v2;
+      for (int i = 0; i < 4; ++i) {
+        lo[i] = (w[c][i] + w[c][i + 4]) + carry[c][i];
+        carry[c][i] = w[c][i] - w[c][i + 4];
       }
+      face4(lo);
+      p0[c] = lo[0];
+      sy[bl][0 + c][ty][tx] = lo[1];
+      sy[bl][3 + c][ty][tx] = lo[2];
+      sy[bl][6 + c][ty][tx] = lo[3];
+      own_ll[c] = own_lo[c];
+      own_lo[c] = own_up[c];
     }
-#pragma unroll
-    for (int c = 0; c < 3; ++c) own_prev[c] = cur.own[c];
+  };
+
+  int ek = K0 - 1;
+  for (; ek + 1 < kend; ek += 2) {
+    step(ek, A, B, PB, PA);
+    step(ek + 1, B, A, PA, PB);
   }
+  if (ek < kend) {
+    step(ek, A, B, PB, PA);
+    __syncthreads();
+    finish_level(kend - 1, p0, own_ll, PA);
+  } else {
+    __syncthreads();
+    finish_level(kend - 1, p0, own_ll, PB);
+  }
+
   if (MODE == 0 || MODE == 3 || MODE == 4 || MODE == 6) return;
   double vv[1] = {dot};
   block_partials<1>(vv, partials);
@@ -295,15 +391,27 @@ __global__ void __launch_bounds__(TX* TY) kxu_tile_kernel(Grid g, int kc, const 
 // the result layout the same lane receives rows 4g .. 4g+3 of each 16-row
 // M-tile, i.e. the three components of corner g (lower level, M-tile 0) and
 // corner 4 + g (upper level, M-tile 1) of its brick -- exactly what the
-// z-carry and the node sums need.  Before rounding to bf16 the corner values
-// are taken relative to corner 0 of the brick: Ke annihilates translations,
-// so the product is unchanged in exact arithmetic while the rounding acts on
-// the deformation only.
+// z-carry and the node sums need.
+//
+// Rigid motion is removed before rounding.  Ke annihilates the six rigid
+// modes, so subtracting any translation plus infinitesimal rotation w x p
+// from all eight corners leaves the exact product unchanged.  The kernel
+// subtracts corner 0 and the rotation estimated from the three edges at
+// corner 0 (every lane of a brick reads the same six values, so the whole
+// brick sees one rigid field).  Rounding then acts on the deformation of the
+// brick alone, and the bf16 error of Ke along the rigid modes -- which the
+// rotations of a bending structure would otherwise amplify far beyond the
+// strain energy -- never enters.
+//
+// SPLIT: both operands as a pair of bf16 numbers (hi + lo, about 16
+// significant bits each); the product keeps hi*hi + lo*hi + hi*lo (three
+// matrix-core passes), i.e. the split-bf16 product of Henry, Tang and
+// Heinecke (2019) with one cross term fewer than their six-term form.
 typedef __bf16 bf16x8 __attribute__((ext_vector_type(8)));
 typedef float f32x4 __attribute__((ext_vector_type(4)));
 
-template <int MODE>
-__global__ void __launch_bounds__(TX* TY) kxu_mfma_kernel(Grid g, int kc, const float* __restrict__ x,
+template <int MODE, bool SPLIT>
+__global__ void __launch_bounds__(TX* TY) kxu_mfma_kernel(Grid g, TileMap tm, const float* __restrict__ x,
                                                          const float* __restrict__ E,
                                                          const uint8_t* __restrict__ nmask,
                                                          const float* __restrict__ ke, float kscale,
@@ -314,10 +422,13 @@ __global__ void __launch_bounds__(TX* TY) kxu_mfma_kernel(Grid g, int kc, const 
   __shared__ float sy[4][3][TY][TX];          // level partials per corner
   __shared__ float sE[TY][TX];
 
+  int cx, cy, cz;
+  tile_of_block(tm, cx, cy, cz);
+  const int kc = tm.kc;
   const int tx = threadIdx.x % TX, ty = threadIdx.x / TX;
   const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
   const int grp = lane >> 4, ln = lane & 15;
-  const int I0 = blockIdx.x * OWN - 1, J0 = blockIdx.y * OWN - 1, K0 = blockIdx.z * kc;
+  const int I0 = cx * OWN - 1, J0 = cy * OWN - 1, K0 = cz * kc;
   const int ni = I0 + tx, nj = J0 + ty;
   const int64_t sx = g.nx + 1, sxy = (int64_t)(g.nx + 1) * (g.ny + 1);
   const bool owner = tx >= 1 && ty >= 1 && ni <= g.nx && nj <= g.ny;
@@ -325,7 +436,7 @@ __global__ void __launch_bounds__(TX* TY) kxu_mfma_kernel(Grid g, int kc, const 
   const int kend = min(K0 + kc, g.nz + 1);
 
   // Ke_pad rows 16 mt + ln, columns 8 grp .. 8 grp + 7 (bf16), in registers
-  bf16x8 a[2];
+  bf16x8 a[2], alo[2];
 #pragma unroll
   for (int mt = 0; mt < 2; ++mt) {
     const int m = 16 * mt + ln, cm = m >> 2, am = m & 3;
@@ -334,6 +445,7 @@ __global__ void __launch_bounds__(TX* TY) kxu_mfma_kernel(Grid g, int kc, const 
       const int k = 8 * grp + i, ck = k >> 2, ak = k & 3;
       const float v = (am < 3 && ak < 3) ? ke[(3 * cm + am) * 24 + 3 * ck + ak] * kscale : 0.0f;
       a[mt][i] = (__bf16)v;
+      alo[mt][i] = (__bf16)(v - (float)a[mt][i]);
     }
   }
 
@@ -413,18 +525,44 @@ __global__ void __launch_bounds__(TX* TY) kxu_mfma_kernel(Grid g, int kc, const 
     for (int t = 0; t < 4; ++t) {
       const int r = 4 * wave + t;  // brick row of this N-tile inside the tile
       const int b = upper ? bhi : blo;
-      bf16x8 bv;
+      // rigid field of the brick: corner 0 and the edge-estimated rotation w
+      float ref[3];
+#pragma unroll
+      for (int c = 0; c < 3; ++c) ref[c] = su[blo][c][r][ln];
+      const float wz = 0.5f * ((su[blo][1][r][ln + 1] - ref[1]) - (su[blo][0][r + 1][ln] - ref[0]));
+      const float wy = 0.5f * ((su[bhi][0][r][ln] - ref[0]) - (su[blo][2][r][ln + 1] - ref[2]));
+      const float wx = 0.5f * ((su[blo][2][r + 1][ln] - ref[2]) - (su[bhi][1][r][ln] - ref[1]));
+      const float pz = upper ? 1.0f : 0.0f;
+      float dA[3], dB[3];  // w x p at the two corners
+      dA[0] = wy * pz - wz * oyA;
+      dA[1] = wz * oxA - wx * pz;
+      dA[2] = wx * oyA - wy * oxA;
+      dB[0] = wy * pz - wz * oyB;
+      dB[1] = wz * oxB - wx * pz;
+      dB[2] = wx * oyB - wy * oxB;
+      bf16x8 bv, bl;
 #pragma unroll
       for (int c = 0; c < 3; ++c) {
-        const float ref = su[blo][c][r][ln];  // corner 0 of the brick
-        bv[c] = (__bf16)(su[b][c][r + oyA][ln + oxA] - ref);
-        bv[4 + c] = (__bf16)(su[b][c][r + oyB][ln + oxB] - ref);
+        const float vA = su[b][c][r + oyA][ln + oxA] - ref[c] - dA[c];
+        const float vB = su[b][c][r + oyB][ln + oxB] - ref[c] - dB[c];
+        bv[c] = (__bf16)vA;
+        bv[4 + c] = (__bf16)vB;
+        if (SPLIT) {
+          bl[c] = (__bf16)(vA - (float)bv[c]);
+          bl[4 + c] = (__bf16)(vB - (float)bv[4 + c]);
+        }
       }
-      bv[3] = (__bf16)0.0f;
-      bv[7] = (__bf16)0.0f;
+      bv[3] = bv[7] = (__bf16)0.0f;
       const f32x4 zero = {0.0f, 0.0f, 0.0f, 0.0f};
-      const f32x4 dlo = __builtin_amdgcn_mfma_f32_16x16x32_bf16(a[0], bv, zero, 0, 0, 0);
-      const f32x4 dhi = __builtin_amdgcn_mfma_f32_16x16x32_bf16(a[1], bv, zero, 0, 0, 0);
+      f32x4 dlo = __builtin_amdgcn_mfma_f32_16x16x32_bf16(a[0], bv, zero, 0, 0, 0);
+      f32x4 dhi = __builtin_amdgcn_mfma_f32_16x16x32_bf16(a[1], bv, zero, 0, 0, 0);
+      if (SPLIT) {
+        bl[3] = bl[7] = (__bf16)0.0f;
+        dlo = __builtin_amdgcn_mfma_f32_16x16x32_bf16(alo[0], bv, dlo, 0, 0, 0);
+        dhi = __builtin_amdgcn_mfma_f32_16x16x32_bf16(alo[1], bv, dhi, 0, 0, 0);
+        dlo = __builtin_amdgcn_mfma_f32_16x16x32_bf16(a[0], bl, dlo, 0, 0, 0);
+        dhi = __builtin_amdgcn_mfma_f32_16x16x32_bf16(a[1], bl, dhi, 0, 0, 0);
+      }
       const float Ee = sE[r][ln];
 #pragma unroll
       for (int c = 0; c < 3; ++c) {
@@ -471,31 +609,86 @@ WK<T> scaled_wk(const WalshK& w, double h) {
 
 }  // namespace
 
-#ifndef FE_KXU_KC
-#define FE_KXU_KC 8  // most node levels one workgroup marches through
-#endif
-#ifndef FE_KXU_TARGET_BLOCKS
-#define FE_KXU_TARGET_BLOCKS 1024  // aim: four workgroups per compute unit
+#ifndef FE_KXU_KCMAX
+#define FE_KXU_KCMAX 16  // most node levels one workgroup marches through
 #endif
 
-// Levels per workgroup: long marches amortise the tile halo, but small grids
-// need short ones to give every compute unit work.
-static int kxu_levels_per_block(const Grid& g) {
-  const int64_t cols = (int64_t)((g.nx + 1 + OWN - 1) / OWN) * ((g.ny + 1 + OWN - 1) / OWN);
-  int64_t kc = ((int64_t)(g.nz + 1) * cols + FE_KXU_TARGET_BLOCKS - 1) / FE_KXU_TARGET_BLOCKS;
-  if (kc < 1) kc = 1;
-  if (kc > FE_KXU_KC) kc = FE_KXU_KC;
-  return (int)kc;
+// Resident workgroups per compute unit of a kernel on the current device
+// (cached per device and kernel).
+static int kxu_slots(const void* kernel) {
+  static std::mutex mu;
+  static std::map<std::pair<int, const void*>, int> cache;
+  int dev = 0;
+  if (hipGetDevice(&dev) != hipSuccess) dev = 0;
+  std::lock_guard<std::mutex> lk(mu);
+  auto it = cache.find({dev, kernel});
+  if (it != cache.end()) return it->second;
+  int per_cu = 0, cus = 0;
+  if (hipOccupancyMaxActiveBlocksPerMultiprocessor(&per_cu, kernel, TX * TY, 0) != hipSuccess || per_cu < 1)
+    per_cu = 1;
+  if (hipDeviceGetAttribute(&cus, hipDeviceAttributeMultiprocessorCount, dev) != hipSuccess || cus < 1)
+    cus = 1;
+  (void)hipGetLastError();
+  const int slots = per_cu * cus;
+  cache[{dev, kernel}] = slots;
+  return slots;
 }
 
-static dim3 kxu_grid(const Grid& g, int kc) {
-  return dim3((unsigned)((g.nx + 1 + OWN - 1) / OWN), (unsigned)((g.ny + 1 + OWN - 1) / OWN),
-              (unsigned)((g.nz + 1 + kc - 1) / kc));
+// Tiles of 15 x 15 node columns, split in z into chunks of kc levels so that
+// the workgroups fill whole rounds of the resident slots (no lone tail
+// round) with at most FE_KXU_KCMAX levels each.
+static TileMap kxu_tile_map(const Grid& g, int slots) {
+  TileMap tm;
+  tm.gx = (g.nx + 1 + OWN - 1) / OWN;
+  tm.gy = (g.ny + 1 + OWN - 1) / OWN;
+  const int64_t cols = (int64_t)tm.gx * tm.gy, L = g.nz + 1;
+  const int64_t rounds = std::max<int64_t>(1, (cols * L + (int64_t)slots * FE_KXU_KCMAX - 1) /
+                                                  ((int64_t)slots * FE_KXU_KCMAX));
+  int64_t nzc = std::max<int64_t>(1, std::min<int64_t>(L, rounds * slots / cols));
+  tm.kc = (int)((L + nzc - 1) / nzc);
+  tm.nzc = (int)((L + tm.kc - 1) / tm.kc);
+  tm.nblk = (int)(cols * tm.nzc);
+  return tm;
 }
 
+// Upper bound of the workgroup count of any tile map of g (partials sizing).
 int64_t kxu_tile_blocks(const Grid& g) {
-  const dim3 d = kxu_grid(g, kxu_levels_per_block(g));
-  return (int64_t)d.x * d.y * d.z;
+  return (int64_t)((g.nx + 1 + OWN - 1) / OWN) * ((g.ny + 1 + OWN - 1) / OWN) * (g.nz + 1);
+}
+
+template <typename T, int MODE>
+static int launch_tile(hipStream_t stream, const Grid& g, const T* x, const T* E, const uint8_t* nm,
+                       const WK<T>& wk, T* y, const Epi<T>& ep, CgState* st, double* partials, double* out,
+                       const T* zpad) {
+  const void* k = reinterpret_cast<const void*>(&kxu_tile_kernel<T, MODE>);
+  const TileMap tm = kxu_tile_map(g, kxu_slots(k));
+  hipLaunchKernelGGL((kxu_tile_kernel<T, MODE>), dim3(tm.nblk), dim3(TX * TY), 0, stream, g, tm, x, E, nm, wk,
+                     y, ep, st, partials, out, zpad);
+  return tm.nblk;
+}
+
+template <int MODE, bool SPLIT>
+static int launch_mfma_mode(hipStream_t stream, const Grid& g, const float* x, const float* E,
+                            const uint8_t* nm, const float* ke, float ks, float* y, const Epi<float>& ef,
+                            CgState* st, double* partials) {
+  const void* k = reinterpret_cast<const void*>(&kxu_mfma_kernel<MODE, SPLIT>);
+  const TileMap tm = kxu_tile_map(g, kxu_slots(k));
+  hipLaunchKernelGGL((kxu_mfma_kernel<MODE, SPLIT>), dim3(tm.nblk), dim3(TX * TY), 0, stream, g, tm, x, E, nm,
+                     ke, ks, y, ef, st, partials);
+  return tm.nblk;
+}
+
+template <bool SPLIT>
+static int launch_mfma(int mode, hipStream_t stream, const Grid& g, const float* x, const float* E,
+                       const uint8_t* nm, const float* ke, float ks, float* y, const Epi<float>& ef, CgState* st,
+                       double* partials) {
+  switch (mode) {
+    case 1: return launch_mfma_mode<1, SPLIT>(stream, g, x, E, nm, ke, ks, y, ef, st, partials);
+    case 3: return launch_mfma_mode<3, SPLIT>(stream, g, x, E, nm, ke, ks, y, ef, st, partials);
+    case 4: return launch_mfma_mode<4, SPLIT>(stream, g, x, E, nm, ke, ks, y, ef, st, partials);
+    case 5: return launch_mfma_mode<5, SPLIT>(stream, g, x, E, nm, ke, ks, y, ef, st, partials);
+    default: return launch_mfma_mode<0, SPLIT>(stream, g, x, E, nm, ke, ks, y, ef, st, partials);
+  }
 }
 
 template <typename T>
@@ -503,8 +696,6 @@ hipError_t launch_kxu_tile(fe_problem* p, int lev, const T* x, const T* E, T* y,
                            const double* b64, double* out, const T* bT, const T* invd, double omega,
                            const ChebStep<T>* cs) {
   const Grid g = p->L[lev].g;
-  const int kc = kxu_levels_per_block(g);
-  const dim3 grid = kxu_grid(g, kc);
   const WK<T> wk = scaled_wk<T>(p->wk, p->L[lev].h);
   Epi<T> ep;
   ep.b64 = b64;
@@ -529,10 +720,8 @@ hipError_t launch_kxu_tile(fe_problem* p, int lev, const T* x, const T* E, T* y,
     if (mode == 6) bytes += vb * 3.0 * (double)g.ndof;  // res in/out, acc in/out (res read counted above)
     slot = kstats_begin(p, bytes);
   }
+  int nb = 0;
   if (std::is_same<T, float>::value && lev == 0 && p->mfma_l0 && mode != 2 && mode != 6) {
-    const float* xf = reinterpret_cast<const float*>(x);
-    const float* Ef = reinterpret_cast<const float*>(E);
-    float* yf = reinterpret_cast<float*>(y);
     Epi<float> ef;
     ef.b64 = b64;
     ef.bT = reinterpret_cast<const float*>(bT);
@@ -542,61 +731,27 @@ hipError_t launch_kxu_tile(fe_problem* p, int lev, const T* x, const T* E, T* y,
     ef.acc = nullptr;
     ef.c1 = ef.c2 = 0.0f;
     ef.first = 0;
+    const float* xf = reinterpret_cast<const float*>(x);
+    const float* Ef = reinterpret_cast<const float*>(E);
+    float* yf = reinterpret_cast<float*>(y);
     const float ks = (float)p->L[lev].h;
+    nb = p->mfma_l0 == 2 ? launch_mfma<true>(mode, p->stream, g, xf, Ef, nm, p->ke32, ks, yf, ef, st, p->partials)
+                         : launch_mfma<false>(mode, p->stream, g, xf, Ef, nm, p->ke32, ks, yf, ef, st, p->partials);
+  } else {
+    const T* zp = reinterpret_cast<const T*>(p->zpad);
     switch (mode) {
-      case 1:
-        hipLaunchKernelGGL(kxu_mfma_kernel<1>, grid, dim3(TX * TY), 0, p->stream, g, kc, xf, Ef, nm, p->ke32,
-                           ks, yf, ef, st, p->partials);
-        break;
-      case 3:
-        hipLaunchKernelGGL(kxu_mfma_kernel<3>, grid, dim3(TX * TY), 0, p->stream, g, kc, xf, Ef, nm, p->ke32,
-                           ks, yf, ef, st, p->partials);
-        break;
-      case 4:
-        hipLaunchKernelGGL(kxu_mfma_kernel<4>, grid, dim3(TX * TY), 0, p->stream, g, kc, xf, Ef, nm, p->ke32,
-                           ks, yf, ef, st, p->partials);
-        break;
-      case 5:
-        hipLaunchKernelGGL(kxu_mfma_kernel<5>, grid, dim3(TX * TY), 0, p->stream, g, kc, xf, Ef, nm, p->ke32,
-                           ks, yf, ef, st, p->partials);
-        break;
-      default:
-        hipLaunchKernelGGL(kxu_mfma_kernel<0>, grid, dim3(TX * TY), 0, p->stream, g, kc, xf, Ef, nm, p->ke32,
-                           ks, yf, ef, st, p->partials);
+      case 1: nb = launch_tile<T, 1>(p->stream, g, x, E, nm, wk, y, ep, st, p->partials, out, zp); break;
+      case 2: nb = launch_tile<T, 2>(p->stream, g, x, E, nm, wk, y, ep, st, p->partials, out, zp); break;
+      case 3: nb = launch_tile<T, 3>(p->stream, g, x, E, nm, wk, y, ep, st, p->partials, out, zp); break;
+      case 4: nb = launch_tile<T, 4>(p->stream, g, x, E, nm, wk, y, ep, st, p->partials, out, zp); break;
+      case 5: nb = launch_tile<T, 5>(p->stream, g, x, E, nm, wk, y, ep, st, p->partials, out, zp); break;
+      case 6: nb = launch_tile<T, 6>(p->stream, g, x, E, nm, wk, y, ep, st, p->partials, out, zp); break;
+      default: nb = launch_tile<T, 0>(p->stream, g, x, E, nm, wk, y, ep, st, p->partials, out, zp);
     }
-  } else switch (mode) {
-    case 1:
-      hipLaunchKernelGGL((kxu_tile_kernel<T, 1>), grid, dim3(TX * TY), 0, p->stream, g, kc, x, E, nm, wk,
-                         y, ep, st, p->partials, out);
-      break;
-    case 2:
-      hipLaunchKernelGGL((kxu_tile_kernel<T, 2>), grid, dim3(TX * TY), 0, p->stream, g, kc, x, E, nm, wk,
-                         y, ep, st, p->partials, out);
-      break;
-    case 3:
-      hipLaunchKernelGGL((kxu_tile_kernel<T, 3>), grid, dim3(TX * TY), 0, p->stream, g, kc, x, E, nm, wk,
-                         y, ep, st, p->partials, out);
-      break;
-    case 4:
-      hipLaunchKernelGGL((kxu_tile_kernel<T, 4>), grid, dim3(TX * TY), 0, p->stream, g, kc, x, E, nm, wk,
-                         y, ep, st, p->partials, out);
-      break;
-    case 5:
-      hipLaunchKernelGGL((kxu_tile_kernel<T, 5>), grid, dim3(TX * TY), 0, p->stream, g, kc, x, E, nm, wk,
-                         y, ep, st, p->partials, out);
-      break;
-    case 6:
-      hipLaunchKernelGGL((kxu_tile_kernel<T, 6>), grid, dim3(TX * TY), 0, p->stream, g, kc, x, E, nm, wk,
-                         y, ep, st, p->partials, out);
-      break;
-    default:
-      hipLaunchKernelGGL((kxu_tile_kernel<T, 0>), grid, dim3(TX * TY), 0, p->stream, g, kc, x, E, nm, wk,
-                         y, ep, st, p->partials, out);
   }
   hipError_t e = hipGetLastError();
   kstats_end(p, slot);
   if (e != hipSuccess) return e;
-  const int nb = (int)((int64_t)grid.x * grid.y * grid.z);
   if (mode == 1) return launch_cg_finalize(p, FIN_ALPHA, nb, 0, st, nullptr);
   if (mode == 2) return launch_cg_finalize(p, FIN_SCALAR, nb, 0, nullptr, out);
   if (mode == 5) return launch_cg_finalize(p, FIN_RZ, nb, 1, st, nullptr);

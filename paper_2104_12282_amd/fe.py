@@ -16,7 +16,7 @@ _PKG = os.path.dirname(os.path.abspath(__file__))
 LIB_PATH = os.environ.get("FE_HIP_LIB") or os.path.join(_PKG, "libfe_hip.so")
 
 FE_OK, FE_EINVAL, FE_ENOMEM, FE_EDEVICE, FE_ENOTCONV, FE_EBREAKDOWN = 0, -1, -2, -3, -4, -5
-PRECISION = {"fp64": 0, "fp32_ir": 1, "bf16_ir": 2}
+PRECISION = {"fp64": 0, "fp32_ir": 1, "bf16_ir": 2, "bf16x3_ir": 3}
 PRECOND = {"jacobi": 0, "gmg": 1}
 STATUS_NAME = {0: "FE_OK", -1: "FE_EINVAL", -2: "FE_ENOMEM", -3: "FE_EDEVICE",
                -4: "FE_ENOTCONV", -5: "FE_EBREAKDOWN"}
