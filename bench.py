@@ -33,8 +33,8 @@ def parse():
     ap.add_argument("--steps", type=int, default=50)
     ap.add_argument("--warmup", type=int, default=2)
     ap.add_argument("--grid", type=str, default="224x112x56")
-    ap.add_argument("--precision", default="fp64", choices=["fp64", "fp32_ir", "bf16_ir"])
-    ap.add_argument("--alt-precision", default="fp32_ir", choices=["none", "fp64", "fp32_ir", "bf16_ir"])
+    ap.add_argument("--precision", default="fp64", choices=["fp64", "fp32_ir", "bf16_ir", "bf16x3_ir"])
+    ap.add_argument("--alt-precision", default="fp32_ir", choices=["none", "fp64", "fp32_ir", "bf16_ir", "bf16x3_ir"])
     ap.add_argument("--precond", default="gmg", choices=["jacobi", "gmg"])
     ap.add_argument("--mg-levels", type=int, default=3)
     ap.add_argument("--mg-nu", type=int, default=1)

@@ -30,6 +30,10 @@ namespace {
 
 constexpr int TX = 16, TY = 16, OWN = 15;
 
+#ifndef FE_KXU_MIN_WAVES
+#define FE_KXU_MIN_WAVES 1  // no occupancy floor beyond what the registers give
+#endif
+
 template <typename T>
 struct WK {
   T A, B, G, C, D, F, H, J;
@@ -145,9 +149,9 @@ __device__ inline void face4(T (&v)[4]) {
 //
 // Pipeline of one level step (brick layer ek between node levels ek and
 // ek + 1), with one barrier:
-//   1. the upper level (loaded one step ahead) goes to LDS buffer (ek+1)&1;
-//   2. loads are issued for the level after it and for the epilogue operands
-//      of level ek;
+//   1. the upper level (loaded two steps ahead) goes to LDS buffer (ek+1)&1;
+//   2. loads are issued for level ek + 3 and for the epilogue operands of
+//      level ek + 1;
 //   3. barrier;
 //   4. the node sums of level ek - 1 (complete since the previous step) are
 //      read from partial buffer (ek-1)&1 and written out;
@@ -160,7 +164,7 @@ __device__ inline void face4(T (&v)[4]) {
 // a buffer is rewritten only after every thread has passed the barrier that
 // follows its last read.
 template <typename T, int MODE>
-__global__ void __launch_bounds__(TX* TY) kxu_tile_kernel(Grid g, TileMap tm, const T* __restrict__ x,
+__global__ void __launch_bounds__(TX* TY, FE_KXU_MIN_WAVES) kxu_tile_kernel(Grid g, TileMap tm, const T* __restrict__ x,
                                                          const T* __restrict__ E,
                                                          const uint8_t* __restrict__ nmask, WK<T> wk,
                                                          T* __restrict__ y, Epi<T> ep, CgState* st,
@@ -197,26 +201,30 @@ __global__ void __launch_bounds__(TX* TY) kxu_tile_kernel(Grid g, TileMap tm, co
     T halo[3];
     T Ee;  // modulus of the brick layer below this level
   };
-  auto fetch = [&](int i, int j, int k, T (&v)[3]) {
-    const T* src = node_ok(i, j, k) ? x + 3 * (i + sx * j + sxy * k) : zpad;
+  // Every thread issues the same loads on every step (the halo slot of a
+  // thread without one, and levels past the chunk, read the pad): with no
+  // load behind a branch the compiler can count outstanding loads exactly
+  // and wait only for the ones a step really needs.
+  auto fetch = [&](bool ok, int i, int j, int k, T (&v)[3]) {
+    const T* src = ok ? x + 3 * (i + sx * j + sxy * k) : zpad;
     v[0] = src[0];
     v[1] = src[1];
     v[2] = src[2];
   };
   auto load_level = [&](int k, LevelIn& L) {
-    fetch(ni, nj, k, L.own);
-    if (threadIdx.x < 64) fetch(hslot ? hi : ni, hslot ? hj : nj, k, L.halo);  // wave-uniform
+    const bool need = k <= kend;
+    fetch(need && node_ok(ni, nj, k), ni, nj, k, L.own);
+    fetch(need && hslot && node_ok(hi, hj, k), hi, hj, k, L.halo);
     const int ek = k - 1;
-    const bool ok = ecol && ek >= 0 && ek < g.nz;
+    const bool ok = need && ecol && ek >= 0 && ek < g.nz;
     L.Ee = *(ok ? E + (ni + (int64_t)g.nx * (nj + (int64_t)g.ny * ek)) : zpad);
   };
-  // stores the level into LDS and returns this thread's own values
-  auto store_level = [&](int buf, const LevelIn& L, T (&own)[3]) {
+  // stores a level into LDS; the loaded registers die here (this thread's
+  // own values are read back from LDS after the barrier), so the register
+  // ring rotates in place and no copy waits for a load still in flight
+  auto store_level = [&](int buf, const LevelIn& L) {
 #pragma unroll
-    for (int c = 0; c < 3; ++c) {
-      own[c] = L.own[c];
-      su[buf][c][ty][tx] = own[c];
-    }
+    for (int c = 0; c < 3; ++c) su[buf][c][ty][tx] = L.own[c];
     if (hslot)
       for (int c = 0; c < 3; ++c) su[buf][c][hy][hx] = L.halo[c];
   };
@@ -282,18 +290,24 @@ __global__ void __launch_bounds__(TX* TY) kxu_tile_kernel(Grid g, TileMap tm, co
   T own_lo[3];     // this thread's node on the lower level of the current brick
   T own_ll[3];     // ... and on the level below it (its sums finish one step late)
   T p0[3];         // own-corner sum of the level below
-  // ping-pong buffers: A/B hold the next upper level, PA/PB epilogue operands
-  LevelIn A, B;
-  EpiIn PA, PB;
+  // Register rings, two steps deep: R0..R2 hold node levels, Q0..Q2 epilogue
+  // operands.  Step s (brick layer ek = K0 - 1 + s) uses level ek + 1 from
+  // ring slot s % 3 and loads level ek + 3 into slot (s + 2) % 3 -- the slot
+  // step s - 1 used -- and likewise the operands of level ek + 1, which
+  // step s + 2 needs.  Loads thus have two steps to arrive.
+  LevelIn R0, R1, R2;
+  EpiIn Q0, Q1, Q2;
   {
     LevelIn L0;
     load_level(K0 - 1, L0);
-    load_level(K0, A);
+    load_level(K0, R0);
+    load_level(K0 + 1, R1);  // kend >= K0 + 1
     const int b0 = (K0 - 1) & 1;
-    store_level(b0, L0, own_lo);
+    store_level(b0, L0);
     __syncthreads();
 #pragma unroll
     for (int c = 0; c < 3; ++c) {
+      own_lo[c] = su[b0][c][ty][tx];
       fl[c][0] = own_lo[c];
       fl[c][1] = su[b0][c][ty][tx + 1];
       fl[c][2] = su[b0][c][ty + 1][tx + 1];
@@ -303,19 +317,17 @@ __global__ void __launch_bounds__(TX* TY) kxu_tile_kernel(Grid g, TileMap tm, co
       p0[c] = T(0);
       carry[c][0] = carry[c][1] = carry[c][2] = carry[c][3] = T(0);
     }
-    PB.m = 0;
   }
 
-  // one brick layer ek: `use` holds level ek + 1 (loaded one step ago),
-  // `fill` receives level ek + 2; Pu holds the operands of level ek - 1,
-  // Pf receives those of level ek
   auto step = [&](int ek, const LevelIn& use, LevelIn& fill, const EpiIn& Pu, EpiIn& Pf) {
     const int bu = (ek + 1) & 1;
-    T own_up[3];
-    store_level(bu, use, own_up);
-    if (ek + 2 <= kend) load_level(ek + 2, fill);  // uniform
-    load_epi(ek, Pf);
+    store_level(bu, use);
+    load_level(ek + 3, fill);
+    load_epi(ek + 1, Pf);
     __syncthreads();
+    T own_up[3];
+#pragma unroll
+    for (int c = 0; c < 3; ++c) own_up[c] = su[bu][c][ty][tx];
 
     finish_level(ek - 1, p0, own_ll, Pu);
 
@@ -359,19 +371,21 @@ __global__ void __launch_bounds__(TX* TY) kxu_tile_kernel(Grid g, TileMap tm, co
     }
   };
 
-  int ek = K0 - 1;
-  for (; ek + 1 < kend; ek += 2) {
-    step(ek, A, B, PB, PA);
-    step(ek + 1, B, A, PA, PB);
+  // the operands of level ek + 1 sit in slot (s + 2) % 3; the first step's
+  // finish (level K0 - 2) and the second's (K0 - 1) are not owned
+  const int n = kend - K0 + 1;  // steps: layers K0 - 1 .. kend - 1
+  int s = 0;
+  for (; s + 3 <= n; s += 3) {
+    step(K0 - 1 + s, R0, R2, Q0, Q2);
+    step(K0 + s, R1, R0, Q1, Q0);
+    step(K0 + 1 + s, R2, R1, Q2, Q1);
   }
-  if (ek < kend) {
-    step(ek, A, B, PB, PA);
-    __syncthreads();
-    finish_level(kend - 1, p0, own_ll, PA);
-  } else {
-    __syncthreads();
-    finish_level(kend - 1, p0, own_ll, PB);
-  }
+  if (s < n) step(K0 - 1 + s, R0, R2, Q0, Q2);
+  if (s + 1 < n) step(K0 + s, R1, R0, Q1, Q0);
+  __syncthreads();
+  // level kend - 1 = K0 + n - 2: its operands went to slot n % 3
+  const int last = n % 3;
+  finish_level(kend - 1, p0, own_ll, last == 0 ? Q0 : last == 1 ? Q1 : Q2);
 
   if (MODE == 0 || MODE == 3 || MODE == 4 || MODE == 6) return;
   double vv[1] = {dot};
