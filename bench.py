@@ -38,11 +38,15 @@ def parse():
     ap.add_argument("--precond", default="gmg", choices=["jacobi", "gmg"])
     ap.add_argument("--mg-levels", type=int, default=3)
     ap.add_argument("--mg-nu", type=int, default=1)
-    ap.add_argument("--mg-coarse", type=int, default=20)
+    ap.add_argument("--mg-coarse", type=int, default=30)
     ap.add_argument("--rtol", type=float, default=1e-6)
     ap.add_argument("--volfrac", type=float, default=0.12)
     ap.add_argument("--move", type=float, default=0.2)
     ap.add_argument("--no-cpu-baseline", action="store_true")
+    ap.add_argument("--precision-seeds", type=int, default=4,
+                    help="seeded smoothed densities of the precision study (0 = skip it)")
+    ap.add_argument("--mg4", type=int, default=1,
+                    help="also run the float64 loop with a 4-level hierarchy (context line)")
     ap.add_argument("--cpu-grid", type=str, default="80x40x20")
     ap.add_argument("--serving", type=int, default=256,
                     help="requests of the serving stream to run (0: skip)")
@@ -103,6 +107,83 @@ def cpu_baseline(grid, rtol):
                        f"sensitivity, filter, OC) on the {nx}x{ny}x{nz} cantilever, "
                        f"{dt:.2f} s; the 224x112x56 step needs ~675 GB for the banded factor"),
             "seconds": dt}
+
+
+PREC_VARIANTS = (("fp32_ir", 1), ("bf16_ir", 2), ("bf16x3_ir", 4))
+
+
+def kxu_rate(prob, rho, u, variant, reps=20):
+    """Average finest-grid K*u kernel time (HIP events around each launch on
+    the problem's stream) and algorithmic GB/s of one fe_apply_K variant."""
+    y = prob.apply_K(rho, u, variant=variant)
+    prob.kernel_stats(reset=True)
+    prob.set_profiling(True)
+    for _ in range(reps):
+        prob.apply_K(rho, u, variant=variant, out=y)
+    prob.set_profiling(False)
+    ks = prob.kernel_stats(reset=True)
+    us = ks["total_ms"] / max(1, ks["launches"]) * 1e3
+    return us, ks["bytes_per_launch"] / (us * 1e-6) / 1e9
+
+
+def precision_study(fe, synth, torch, nx, ny, nz, seeds, args):
+    """Smoothed random densities (U(0.01,1) through 5 filter passes): the
+    float64 solve to 1e-8 is the reference; float32, bf16 and split-bf16
+    element contractions, each inside float64 iterative refinement to 1e-8,
+    are compared with it (relative compliance error, max sensitivity error
+    relative to max |dc|), with the K*u kernel rate of each variant."""
+    dev = "cuda:0"
+    T = lambda a: torch.as_tensor(a, dtype=torch.float64, device=dev)
+    f = T(synth.cantilever_edge_load(nx, ny, nz))
+    kw = dict(device=dev, precond=args.precond, mg_levels=args.mg_levels)
+    probs = {p: fe.Problem(nx, ny, nz, f, precision=p, **kw) for p in ("fp64",) + tuple(v for v, _ in PREC_VARIANTS)}
+    if args.precond == "gmg":
+        for pr in probs.values():
+            pr.set_mg_params(nu=args.mg_nu, coarse_sweeps=args.mg_coarse)
+    res = {p: {"c_rel_err": [], "dc_rel_err": [], "iters": [], "outer_iters": [], "rel_res": [], "ms": []}
+           for p in probs}
+    for seed in range(seeds):
+        a = T(synth.density_uniform(nx, ny, nz, seed))
+        b = torch.empty_like(a)
+        for _ in range(5):
+            probs["fp64"].filter(a, out=b)
+            a, b = b, a
+        ref = None
+        for p, pr in probs.items():
+            torch.cuda.synchronize()
+            t0 = time.perf_counter()
+            u, info = pr.solve(a, rtol=1e-8, allow_notconv=True)
+            dc, c = pr.sensitivity(a, u)
+            torch.cuda.synchronize()
+            ms = 1e3 * (time.perf_counter() - t0)
+            dcn, cv = dc.cpu().numpy(), float(c.item())
+            if p == "fp64":
+                ref = (dcn, cv)
+            r = res[p]
+            r["c_rel_err"].append(abs(cv - ref[1]) / abs(ref[1]))
+            r["dc_rel_err"].append(float(np.abs(dcn - ref[0]).max() / np.abs(ref[0]).max()))
+            r["iters"].append(info["iters"])
+            r["outer_iters"].append(info["outer_iters"])
+            r["rel_res"].append(info["rel_res"])
+            r["ms"].append(ms)
+            print(f"bench[precision]: seed {seed} {p} iters {info['iters']} outer {info['outer_iters']} "
+                  f"rel_res {info['rel_res']:.2e} c_err {r['c_rel_err'][-1]:.2e} dc_err {r['dc_rel_err'][-1]:.2e}",
+                  file=sys.stderr, flush=True)
+    uu = T(np.random.default_rng(7).standard_normal(probs["fp64"].ndof))
+    out = {"grid": [nx, ny, nz], "seeds": seeds, "density": "U(0.01,1) seeded, 5 filter passes (r=1.5)",
+           "rtol": 1e-8, "reference": "fp64 solve to 1e-8 on the GPU", "variants": {}}
+    for p, pr in probs.items():
+        variant = 0 if p == "fp64" else dict(PREC_VARIANTS)[p]
+        us, gbs = kxu_rate(pr, a, uu, variant)
+        r = res[p]
+        out["variants"][p] = {
+            "kxu_variant": variant, "kxu_us": us, "kxu_gbs": gbs, "kxu_frac_of_hbm_peak": gbs / HBM_PEAK_GBS,
+            "c_rel_err_max": max(r["c_rel_err"]), "dc_rel_err_max": max(r["dc_rel_err"]),
+            "iters_mean": float(np.mean(r["iters"])), "outer_iters_mean": float(np.mean(r["outer_iters"])),
+            "rel_res_max": max(r["rel_res"]), "solve_ms_mean": float(np.mean(r["ms"]))}
+        pr.close()
+    return out
+
 
 
 def serving_bench(n, torch):
@@ -241,6 +322,8 @@ def main():
                    "grid": [nx, ny, nz], "elements": ne, "dofs": ndof,
                    "precision": args.precision, "precond": args.precond,
                    "mg_levels": args.mg_levels if args.precond == "gmg" else None,
+                   "mg_smoothing_sweeps": args.mg_nu if args.precond == "gmg" else None,
+                   "mg_coarse_chebyshev_degree": args.mg_coarse if args.precond == "gmg" else None,
                    "rtol": args.rtol, "volfrac": args.volfrac, "filter_r": 1.5, "move": args.move,
                    "cg_iters_per_solve": float(np.mean(rec["iters"])),
                    "cg_iters_max": int(np.max(rec["iters"])),
@@ -263,6 +346,16 @@ def main():
                       "ms_per_step": 1e3 * dt2 / args.steps,
                       "cg_iters_per_solve": float(np.mean(rec2["iters"])),
                       "compliance_max_rel_diff": float(np.max(np.abs(c2 - c1) / np.abs(c1)))}
+    if args.mg4 and args.precond == "gmg" and args.mg_levels != 4 and nx % 8 == 0 and ny % 8 == 0 \
+            and nz % 8 == 0:
+        a4 = argparse.Namespace(**{**vars(args), "mg_levels": 4})
+        dt4, rec4, _, _ = run_loop(fe, synth, torch, nx, ny, nz, args.precision, a4, args.steps, 1,
+                                   profile=False)
+        out["gmg4_context"] = {"precision": args.precision, "mg_levels": 4, "value": args.steps / dt4,
+                               "ms_per_step": 1e3 * dt4 / args.steps,
+                               "cg_iters_per_solve": float(np.mean(rec4["iters"]))}
+    if args.precision_seeds > 0:
+        out["precision_study"] = precision_study(fe, synth, torch, nx, ny, nz, args.precision_seeds, args)
     if args.serving > 0:
         out["serving"] = serving_bench(args.serving, torch)
     if not args.no_cpu_baseline:

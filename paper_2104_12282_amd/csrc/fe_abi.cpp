@@ -2,6 +2,7 @@
 // drivers (float64 PCG and float32 PCG inside float64 iterative refinement).
 #include <hip/hip_runtime.h>
 
+#include <algorithm>
 #include <cmath>
 #include <cstdio>
 #include <cstring>
@@ -112,19 +113,26 @@ size_t layout(const fe_config* c, fe_problem* p, char* base) {
   double* st_w = (double*)take(512 * sizeof(double));
   double* r64 = (double*)take(g0.ndof * sizeof(double));
   double* p64 = (double*)take(g0.ndof * sizeof(double));
+  double* p64b = (double*)take(g0.ndof * sizeof(double));
   double* q64 = (double*)take(g0.ndof * sizeof(double));
   double* tmp64 = (double*)take(g0.ndof * sizeof(double));
   double* x64 = (double*)take(g0.ndof * sizeof(double));
-  float *x32 = nullptr, *r32 = nullptr, *p32 = nullptr, *q32 = nullptr;
+  float *x32 = nullptr, *r32 = nullptr, *p32 = nullptr, *q32 = nullptr, *p32b = nullptr;
   if (f32) {
     x32 = (float*)take(g0.ndof * sizeof(float));
     r32 = (float*)take(g0.ndof * sizeof(float));
     p32 = (float*)take(g0.ndof * sizeof(float));
+    p32b = (float*)take(g0.ndof * sizeof(float));
     q32 = (float*)take(g0.ndof * sizeof(float));
   }
-  size_t npart = (size_t)FE_RED_GRID * 64;
-  if ((size_t)max_blocks * 2 > npart) npart = (size_t)max_blocks * 2;
-  double* partials = (double*)take(npart * sizeof(double));
+  // the general region also holds the 64 per-workgroup partials of the OC
+  // passes; the CG regions hold up to 3 partials per workgroup of any
+  // reducing launch
+  int64_t gen = std::max<int64_t>((int64_t)FE_RED_GRID * 64, max_blocks * 3);
+  int64_t stride = std::max<int64_t>((int64_t)FE_RED_GRID, max_blocks) * 3;
+  gen = (gen + 63) / 64 * 64;
+  stride = (stride + 63) / 64 * 64;
+  double* partials = (double*)take((size_t)(gen + stride * (PART_REGIONS - 1)) * sizeof(double));
   CgState* st = (CgState*)take(2 * sizeof(CgState));
   double* scal = (double*)take(NSCAL * sizeof(double));
   double* oc = (double*)take(64 * sizeof(double));
@@ -139,14 +147,18 @@ size_t layout(const fe_config* c, fe_problem* p, char* base) {
     p->st_w = st_w;
     p->r64 = r64;
     p->p64 = p64;
+    p->p64b = p64b;
     p->q64 = q64;
     p->tmp64 = tmp64;
     p->x64 = x64;
     p->x32 = x32;
     p->r32 = r32;
     p->p32 = p32;
+    p->p32b = p32b;
     p->q32 = q32;
     p->partials = partials;
+    p->part_stride = stride;
+    p->part_gen = gen;
     p->st = st;
     p->scal = scal;
     p->oc = oc;
@@ -198,22 +210,68 @@ fe_status prepare_operator(fe_problem* p, const double* rho) {
 }
 
 constexpr int kChunk = 24;    // Jacobi-PCG iterations per enqueued chunk
-constexpr int kChunkMG = 8;   // multigrid-PCG iterations per enqueued chunk
+constexpr int kChunkMG = 8;   // multigrid-PCG iterations per enqueued chunk (even: the folded
+                              // iteration alternates two direction buffers)
 constexpr int kMaxOuter = 40; // float64 refinement steps
 
 enum { ST_DONE = 0, ST_CG64 = 1, ST_IR_RESID = 2, ST_IR_CG = 3, ST_FINISH = 4 };
 
-// One CG iteration: q = K p (alpha), x/r update and convergence test, the
-// preconditioner (multigrid V-cycle with r^T z fused, or Jacobi inside the
-// direction kernel), p = z + beta p.  Every kernel is guarded by st->done.
 template <typename T>
-hipError_t cg_iteration(fe_problem* p, T* x, T* r, T* pv, T* q) {
+T* second_direction(fe_problem* p);
+template <>
+double* second_direction<double>(fe_problem* p) { return p->p64b; }
+template <>
+float* second_direction<float>(fe_problem* p) { return p->p32b; }
+template <typename T>
+const T* fine_E(fe_problem* p);
+template <>
+const double* fine_E<double>(fe_problem* p) { return p->L[0].E64; }
+template <>
+const float* fine_E<float>(fe_problem* p) { return p->L[0].E32; }
+
+// Multigrid CG with its reductions folded into the kernels that consume
+// them: three launch groups per iteration instead of seven.
+//   1. direction + product: p = z + beta p_old (beta from the r^T z partials
+//      of the last V-cycle), q = K p, p^T q partials;
+//   2. update: alpha, x += alpha p, r -= alpha q, r^T r partials;
+//   3. V-cycle z = M r whose first kernel takes the convergence decision and
+//      whose last sweep leaves r^T z partials.
+// The direction alternates between two buffers (other workgroups still read
+// the old one around their tiles while a workgroup writes the new one).
+bool folded_mg(const fe_problem* p) { return p->nlev > 1 && !p->mfma_l0; }
+
+// One CG iteration (iteration `it` of its chunk): q = K p (alpha), x/r update
+// and convergence test, the preconditioner (multigrid V-cycle with r^T z
+// fused, or Jacobi inside the direction kernel), p = z + beta p.  Every
+// kernel is guarded by st->done.
+template <typename T>
+hipError_t cg_iteration(fe_problem* p, T* x, T* r, T* pv, T* q, int it) {
   const bool mg = p->nlev > 1;
   T* z = mg ? static_cast<T*>(p->L[0].mg_z) : nullptr;
   hipError_t e;
+  if (folded_mg(p)) {
+    T* pb = second_direction<T>(p);
+    T* pold = (it & 1) ? pb : pv;
+    T* pnew = (it & 1) ? pv : pb;
+    int npq = 0, nrr = 0;
+    TileFuse<T> fz;
+    fz.xin = 2;
+    fz.pold = pold;
+    fz.xout = pnew;
+    fz.fold = part_region(p, PART_RZ);
+    fz.nfold = p->nrz;
+    fz.part = part_region(p, PART_PQ);
+    fz.no_finalize = true;
+    fz.nblocks = &npq;
+    if ((e = launch_kxu_tile<T>(p, 0, z, fine_E<T>(p), q, p->st, 1, nullptr, nullptr, nullptr, nullptr, 0.0,
+                                nullptr, &fz)) != hipSuccess)
+      return e;
+    if ((e = launch_cg_update_mg<T>(p, x, r, pnew, q, p->st, npq, &nrr)) != hipSuccess) return e;
+    return launch_vcycle<T>(p, 0, r, z, p->st, RZ_PARTIALS, nrr);
+  }
   if ((e = launch_kxu<T>(p, 0, pv, q, p->st)) != hipSuccess) return e;
   if ((e = launch_cg_update<T>(p, x, r, pv, q, p->st, mg ? 1 : 0)) != hipSuccess) return e;
-  if (mg && (e = launch_vcycle<T>(p, 0, r, z, p->st, true)) != hipSuccess) return e;
+  if (mg && (e = launch_vcycle<T>(p, 0, r, z, p->st, RZ_FINISH)) != hipSuccess) return e;
   return launch_cg_direction<T>(p, r, z, pv, p->st);
 }
 
@@ -251,7 +309,7 @@ hipError_t enqueue_chunk(fe_problem* p, T* x, T* r, T* pv, T* q) {
         p->kst.cap_bytes = &gc.bytes;
       }
       hipError_t e = hipStreamBeginCapture(p->cap_stream, hipStreamCaptureModeRelaxed);
-      for (int it = 0; it < n && e == hipSuccess; ++it) e = cg_iteration<T>(p, x, r, pv, q);
+      for (int it = 0; it < n && e == hipSuccess; ++it) e = cg_iteration<T>(p, x, r, pv, q, it);
       hipGraph_t graph = nullptr;
       hipError_t e2 = hipStreamEndCapture(p->cap_stream, &graph);
       p->stream = saved;
@@ -276,7 +334,7 @@ hipError_t enqueue_chunk(fe_problem* p, T* x, T* r, T* pv, T* q) {
     }
   }
   hipError_t e = hipSuccess;
-  for (int it = 0; it < n && e == hipSuccess; ++it) e = cg_iteration<T>(p, x, r, pv, q);
+  for (int it = 0; it < n && e == hipSuccess; ++it) e = cg_iteration<T>(p, x, r, pv, q, it);
   return e;
 }
 
@@ -303,8 +361,10 @@ hipError_t enqueue_start(fe_problem* p, const T* b, const T* Kx, T* r, T* pv) {
   hipError_t e = launch_cg_init<T>(p, b, Kx, r, pv, p->st, mg ? 1 : 0);
   if (e != hipSuccess || !mg) return e;
   T* z = static_cast<T*>(p->L[0].mg_z);
+  // folded: the first direction kernel forms p = z from the r^T z partials
+  if (folded_mg(p)) return launch_vcycle<T>(p, 0, r, z, p->st, RZ_PARTIALS, 0);
   if ((e = launch_fill<T>(p, pv, p->L[0].g.ndof, T(0))) != hipSuccess) return e;
-  if ((e = launch_vcycle<T>(p, 0, r, z, p->st, true)) != hipSuccess) return e;
+  if ((e = launch_vcycle<T>(p, 0, r, z, p->st, RZ_FINISH)) != hipSuccess) return e;
   return launch_cg_direction<T>(p, r, z, pv, p->st);
 }
 

@@ -31,10 +31,12 @@ struct CgState {
   double tol2;    // stop when rr <= tol2
   double pq;      // p^T K p
   double spare;
+  double rz_new;  // r^T z of the new preconditioned residual (multigrid CG, not yet committed)
   int32_t iter;   // iterations done
   int32_t max_iter;
   int32_t done;   // 1 = stop (converged, capped or broken down)
   int32_t status; // FE_OK, FE_ENOTCONV, FE_EBREAKDOWN
+  int32_t iter_next;  // iteration count after the update in flight (multigrid CG)
   uint32_t counter[8];  // arrival counters of the last-block reductions
 };
 
@@ -129,11 +131,16 @@ struct fe_problem {
 
   // float64 CG vectors
   double *r64 = nullptr, *p64 = nullptr, *q64 = nullptr;
+  double* p64b = nullptr;  // second direction buffer (multigrid CG alternates the two)
   // float32 CG vectors (iterative refinement)
   float *x32 = nullptr, *r32 = nullptr, *p32 = nullptr, *q32 = nullptr;
+  float* p32b = nullptr;
   // scratch
   double* tmp64 = nullptr;
-  double* partials = nullptr;  // FE_RED_GRID * 64 doubles
+  double* partials = nullptr;  // 4 regions of part_stride doubles (see part_region)
+  int64_t part_stride = 0;     // doubles per CG region
+  int64_t part_gen = 0;        // doubles of the general region
+  int nrz = 0;                 // partials the last level-0 post-smoothing sweep left
   CgState* st = nullptr;       // device state (two instances: [0] inner, [1] aux)
   double* scal = nullptr;      // 64 device scalars for small results
   double* oc = nullptr;        // OC search state
@@ -160,6 +167,15 @@ struct fe_problem {
 
   KStats kst;
 };
+
+// Partial-sum regions.  Multigrid CG hands each reduction to the next kernel
+// (which sums the partials itself), so producer and consumer must not share
+// a region: GEN is for one-shot reductions finished by cg_finalize, PQ for
+// p^T K p, RR for r^T r, RZ for r^T z.
+enum { PART_GEN = 0, PART_PQ = 1, PART_RR = 2, PART_RZ = 3, PART_REGIONS = 4 };
+inline double* part_region(const fe_problem* p, int k) {
+  return k == PART_GEN ? p->partials : p->partials + p->part_gen + (k - 1) * p->part_stride;
+}
 
 // ------------------------------------------------------------------ host
 void fe_set_error(const std::string& msg);
@@ -194,20 +210,50 @@ struct ChebStep {
 // The tiled kernel behind launch_kxu: mode 0 y = Kx, 1 CG step (st), 2 y = b64 - Kx
 // with ||y||^2 -> out[0] (float64 only), 3 damped Jacobi y = x + omega D^-1 (bT - Kx),
 // 4 y = bT - Kx, 5 mode 3 plus r^T z for CG, 6 Chebyshev step with direction x.
+// Optional fused input and reduction of a tiled launch.
+//   xin 1: the operand is x = s * D^-1 a, formed on the fly (a first Jacobi
+//          sweep from zero); owners store it to xout when xout is non-null.
+//   xin 2: the operand is the CG direction x = z + beta * pold (z on the
+//          first iteration), beta = rz / rz_old with rz summed from the
+//          nfold partials at fold; owners store it to xout.
+//   fold_rr: before its work every workgroup sums the nfold r^T r partials at
+//          fold and takes the convergence decision of the CG update.
+//   part: partials region of modes 1 and 5; no_finalize: leave them for the
+//          next kernel instead of a one-workgroup finalize.
+template <typename T>
+struct TileFuse {
+  int xin = 0;
+  const T* invd = nullptr;  // xin 1
+  double s = 0.0;           // xin 1
+  const T* pold = nullptr;  // xin 2
+  T* xout = nullptr;
+  const double* fold = nullptr;
+  int nfold = 0;
+  bool fold_rr = false;
+  double* part = nullptr;
+  bool no_finalize = false;
+  int* nblocks = nullptr;   // out: workgroups launched
+};
+
 template <typename T>
 hipError_t launch_kxu_tile(fe_problem* p, int lev, const T* x, const T* E, T* y, CgState* st, int mode,
                            const double* b64, double* out, const T* bT = nullptr,
                            const T* invd = nullptr, double omega = 0.0,
-                           const ChebStep<T>* cs = nullptr);
+                           const ChebStep<T>* cs = nullptr, const TileFuse<T>* fz = nullptr);
 int64_t kxu_tile_blocks(const Grid& g);
 // Node-centric dense-Ke reference kernel (float64), kept as a second implementation.
 hipError_t launch_kxu_dense64(fe_problem* p, const double* x, double* y);
 
 // z = V(r): one symmetric multigrid V-cycle from level l down.  st (may be
-// null) skips the launches once CG stopped; fuse_rz makes the last level-0
-// sweep also compute rz = r^T z and beta into st.
+// null) skips the launches once CG stopped.
+// rz: what the last level-0 sweep does with r^T z -- RZ_NONE nothing,
+// RZ_FINISH rz and beta into st (one-workgroup finalize), RZ_PARTIALS leave
+// the partials in PART_RZ (count in p->nrz) for the next direction kernel.
+// With fold_rr > 0 the first level-0 kernel also takes the convergence
+// decision of the CG update from the fold_rr r^T r partials in PART_RR.
+enum { RZ_NONE = 0, RZ_FINISH = 1, RZ_PARTIALS = 2 };
 template <typename T>
-hipError_t launch_vcycle(fe_problem* p, int l, const T* r, T* z, CgState* st, bool fuse_rz);
+hipError_t launch_vcycle(fe_problem* p, int l, const T* r, T* z, CgState* st, int rz, int fold_rr = 0);
 
 // CG helpers (T = float or double vectors, float64 reductions)
 template <typename T>
@@ -218,6 +264,12 @@ hipError_t launch_cg_update(fe_problem* p, T* x, T* r, const T* pvec, const T* q
                             int precond_mg);
 template <typename T>
 hipError_t launch_cg_direction(fe_problem* p, const T* r, const T* z, T* pvec, CgState* st);
+// Multigrid CG update: alpha = rz_new / p^T q from the npq partials in PART_PQ
+// (summed by every workgroup), x += alpha p, r -= alpha q, r^T r partials to
+// PART_RR; returns their count in *nrr.
+template <typename T>
+hipError_t launch_cg_update_mg(fe_problem* p, T* x, T* r, const T* pvec, const T* q, CgState* st, int npq,
+                               int* nrr);
 template <typename T>
 hipError_t launch_cg_rz(fe_problem* p, const T* r, const T* z, CgState* st);
 

@@ -220,6 +220,56 @@ __global__ void __launch_bounds__(FE_BLOCK) cg_update_kernel(Grid g, T* __restri
   block_partials<2>(acc, partials);
 }
 
+// Multigrid CG update.  Every workgroup sums the p^T q partials the direction
+// kernel left (same order, same value), alpha = rz_new / p^T q; workgroup 0
+// commits rz and the step.  Then x += alpha p, r -= alpha q and r^T r
+// partials for the convergence test the next kernel takes.
+template <typename T>
+__global__ void __launch_bounds__(FE_BLOCK) cg_update_mg_kernel(Grid g, T* __restrict__ x, T* __restrict__ r,
+                                                                const T* __restrict__ p,
+                                                                const T* __restrict__ q, CgState* st,
+                                                                const double* __restrict__ pq_part, int npq,
+                                                                double* partials) {
+  if (st->done) return;
+  __shared__ double sh[FE_BLOCK / 64];
+  __shared__ double tot;
+  double v = 0.0;
+  for (int i = threadIdx.x; i < npq; i += FE_BLOCK) v += pq_part[i];
+  v = wave_sum(v);
+  if ((threadIdx.x & 63) == 0) sh[threadIdx.x >> 6] = v;
+  __syncthreads();
+  if (threadIdx.x == 0) {
+    double t = 0.0;
+    for (int w = 0; w < FE_BLOCK / 64; ++w) t += sh[w];
+    tot = t;
+  }
+  __syncthreads();
+  const double pq = tot, rz = st->rz_new;
+  const bool bad = !(pq > 0.0) || !finite_d(pq);
+  if (blockIdx.x == 0 && threadIdx.x == 0) {
+    st->pq = pq;
+    if (bad) {
+      st->status = FE_EBREAKDOWN;
+      st->done = 1;
+    } else {
+      st->alpha = rz / pq;
+      st->rz = rz;
+      st->iter_next = st->iter + 1;
+    }
+  }
+  if (bad) return;
+  const T alpha = (T)(rz / pq);
+  double acc[1] = {0.0};
+  for (int64_t d = blockIdx.x * (int64_t)FE_BLOCK + threadIdx.x; d < g.ndof;
+       d += (int64_t)gridDim.x * FE_BLOCK) {
+    x[d] += alpha * p[d];
+    const T rv = r[d] - alpha * q[d];
+    r[d] = rv;
+    acc[0] += (double)rv * (double)rv;
+  }
+  block_partials<1>(acc, partials);
+}
+
 // rz = r^T z (preconditioned by the multigrid cycle), beta = rz / rz_old.
 template <typename T>
 __global__ void __launch_bounds__(FE_BLOCK) cg_rz_kernel(Grid g, const T* __restrict__ r,
@@ -808,6 +858,25 @@ template hipError_t launch_cg_update<double>(fe_problem*, double*, double*, cons
                                              CgState*, int);
 template hipError_t launch_cg_update<float>(fe_problem*, float*, float*, const float*, const float*,
                                             CgState*, int);
+
+// few workgroups: the next kernel's every workgroup sums these partials
+constexpr int kUpdateMgGrid = 1024;
+
+template <typename T>
+hipError_t launch_cg_update_mg(fe_problem* p, T* x, T* r, const T* pvec, const T* q, CgState* st, int npq,
+                               int* nrr) {
+  const Grid g = G(p, 0);
+  int nb = red_grid(g.ndof);
+  if (nb > kUpdateMgGrid) nb = kUpdateMgGrid;
+  hipLaunchKernelGGL(cg_update_mg_kernel<T>, dim3(nb), dim3(FE_BLOCK), 0, p->stream, g, x, r, pvec, q, st,
+                     part_region(p, PART_PQ), npq, part_region(p, PART_RR));
+  *nrr = nb;
+  return hipGetLastError();
+}
+template hipError_t launch_cg_update_mg<double>(fe_problem*, double*, double*, const double*, const double*,
+                                                CgState*, int, int*);
+template hipError_t launch_cg_update_mg<float>(fe_problem*, float*, float*, const float*, const float*,
+                                               CgState*, int, int*);
 
 template <typename T>
 hipError_t launch_cg_direction(fe_problem* p, const T* r, const T* z, T* pvec, CgState* st) {

@@ -135,6 +135,42 @@ __device__ inline void face4(T (&v)[4]) {
   bf(v[1], v[2]);
 }
 
+// Fused operand of a launch (see TileFuse): XIN 1 forms x = s D^-1 a, XIN 2
+// the CG direction x = z + beta p; owners store the x they used to xout.
+template <typename T>
+struct XinK {
+  const T* invd;  // XIN 1
+  T s;            // XIN 1
+  const T* pold;  // XIN 2
+  T* xout;        // may be null
+};
+// Reduction folded into a launch: `what` 1 = r^T z partials (direction
+// factor beta), 2 = r^T r partials (convergence test of the CG update).
+struct FoldK {
+  const double* part;
+  int n;
+  int what;
+};
+
+// Sum of part[0..n) in a fixed order, returned to every thread of the
+// workgroup (each workgroup of a launch computes the same value).
+__device__ inline double block_sum_all(const double* __restrict__ part, int n) {
+  __shared__ double sh[TX * TY / 64];
+  __shared__ double tot;
+  double v = 0.0;
+  for (int i = threadIdx.x; i < n; i += TX * TY) v += part[i];
+  v = wave_sum(v);
+  if ((threadIdx.x & 63) == 0) sh[threadIdx.x >> 6] = v;
+  __syncthreads();
+  if (threadIdx.x == 0) {
+    double t = 0.0;
+    for (int w = 0; w < TX * TY / 64; ++w) t += sh[w];
+    tot = t;
+  }
+  __syncthreads();
+  return tot;
+}
+
 // MODE 0: y = Kx.  MODE 1: CG step, pq = x^T y, alpha = rz / pq.
 // MODE 2: y = b - Kx (float64 only), ||y||^2 -> out[0].
 // MODE 3: damped Jacobi sweep y = x + omega D^-1 (b - Kx).
@@ -163,14 +199,58 @@ __device__ inline void face4(T (&v)[4]) {
 // Double buffering of both LDS arrays makes the single barrier sufficient:
 // a buffer is rewritten only after every thread has passed the barrier that
 // follows its last read.
-template <typename T, int MODE>
+template <typename T, int MODE, int XIN>
 __global__ void __launch_bounds__(TX* TY, FE_KXU_MIN_WAVES) kxu_tile_kernel(Grid g, TileMap tm, const T* __restrict__ x,
                                                          const T* __restrict__ E,
                                                          const uint8_t* __restrict__ nmask, WK<T> wk,
                                                          T* __restrict__ y, Epi<T> ep, CgState* st,
                                                          double* partials, double* out,
-                                                         const T* __restrict__ zpad) {
+                                                         const T* __restrict__ zpad, XinK<T> xi, FoldK fo) {
   if ((MODE == 1 || MODE == 5 || st) && st->done) return;
+  // folded reductions: every workgroup sums the same partials in the same
+  // order, so all take the same decision; workgroup 0 records it in st
+  T beta = T(0);
+  bool first_dir = false;
+  if (fo.what == 1) {
+    const double v = block_sum_all(fo.part, fo.n);
+    const int it = st->iter;
+    const bool bad = !(v > 0.0) || !finite_d(v);
+    if (blockIdx.x == 0 && threadIdx.x == 0) {
+      if (bad) {
+        st->status = FE_EBREAKDOWN;
+        st->done = 1;
+      } else {
+        st->rz_new = v;
+        st->beta = it == 0 ? 0.0 : v / st->rz;
+      }
+    }
+    if (bad) return;
+    first_dir = it == 0;
+    beta = first_dir ? T(0) : (T)(v / st->rz);
+  } else if (fo.what == 2) {
+    const double v = block_sum_all(fo.part, fo.n);
+    const int it = st->iter_next;
+    int status = FE_OK;
+    bool stop = false;
+    if (!finite_d(v)) {
+      stop = true;
+      status = FE_EBREAKDOWN;
+    } else if (v <= st->tol2) {
+      stop = true;
+    } else if (it >= st->max_iter) {
+      stop = true;
+      status = FE_ENOTCONV;
+    }
+    if (blockIdx.x == 0 && threadIdx.x == 0) {
+      st->iter = it;
+      st->rr = v;
+      if (stop) {
+        st->status = status;
+        st->done = 1;
+      }
+    }
+    if (stop) return;
+  }
   __shared__ T su[2][3][TY + 1][TX + 1];  // node values of a level (17 x 17 ring)
   __shared__ T sy[2][9][TY][TX];          // lower-level partials of corners (1,0), (1,1), (0,1)
 
@@ -200,33 +280,47 @@ __global__ void __launch_bounds__(TX* TY, FE_KXU_MIN_WAVES) kxu_tile_kernel(Grid
     T own[3];
     T halo[3];
     T Ee;  // modulus of the brick layer below this level
+    T d_own, d_halo;       // XIN 1: inverse diagonal
+    T p_own[3], p_halo[3];  // XIN 2: previous direction
   };
-  // Every thread issues the same loads on every step (the halo slot of a
-  // thread without one, and levels past the chunk, read the pad): with no
-  // load behind a branch the compiler can count outstanding loads exactly
-  // and wait only for the ones a step really needs.
   auto fetch = [&](bool ok, int i, int j, int k, T (&v)[3]) {
     const T* src = ok ? x + 3 * (i + sx * j + sxy * k) : zpad;
     v[0] = src[0];
     v[1] = src[1];
     v[2] = src[2];
   };
+  auto node_in = [&](bool ok, int i, int j, int k, T (&v)[3], T& d, T (&pv)[3]) {
+    fetch(ok, i, j, k, v);
+    if (XIN == 1) d = *(ok ? xi.invd + (i + sx * j + sxy * k) : zpad);
+    if (XIN == 2) {
+      const T* src = (ok && !first_dir) ? xi.pold + 3 * (i + sx * j + sxy * k) : zpad;
+      pv[0] = src[0];
+      pv[1] = src[1];
+      pv[2] = src[2];
+    }
+  };
   auto load_level = [&](int k, LevelIn& L) {
     const bool need = k <= kend;
-    fetch(need && node_ok(ni, nj, k), ni, nj, k, L.own);
-    fetch(need && hslot && node_ok(hi, hj, k), hi, hj, k, L.halo);
+    node_in(need && node_ok(ni, nj, k), ni, nj, k, L.own, L.d_own, L.p_own);
+    node_in(need && hslot && node_ok(hi, hj, k), hi, hj, k, L.halo, L.d_halo, L.p_halo);
     const int ek = k - 1;
     const bool ok = need && ecol && ek >= 0 && ek < g.nz;
     L.Ee = *(ok ? E + (ni + (int64_t)g.nx * (nj + (int64_t)g.ny * ek)) : zpad);
+  };
+  // the operand value of a node from what was loaded for it
+  auto operand = [&](const T (&v)[3], T d, const T (&pv)[3], int c) -> T {
+    if (XIN == 1) return xi.s * d * v[c];
+    if (XIN == 2) return v[c] + beta * pv[c];
+    return v[c];
   };
   // stores a level into LDS; the loaded registers die here (this thread's
   // own values are read back from LDS after the barrier), so the register
   // ring rotates in place and no copy waits for a load still in flight
   auto store_level = [&](int buf, const LevelIn& L) {
 #pragma unroll
-    for (int c = 0; c < 3; ++c) su[buf][c][ty][tx] = L.own[c];
+    for (int c = 0; c < 3; ++c) su[buf][c][ty][tx] = operand(L.own, L.d_own, L.p_own, c);
     if (hslot)
-      for (int c = 0; c < 3; ++c) su[buf][c][hy][hx] = L.halo[c];
+      for (int c = 0; c < 3; ++c) su[buf][c][hy][hx] = operand(L.halo, L.d_halo, L.p_halo, c);
   };
   // epilogue operands of this thread's node at one level (read only by owners)
   struct EpiIn {
@@ -282,6 +376,7 @@ __global__ void __launch_bounds__(TX* TY, FE_KXU_MIN_WAVES) kxu_tile_kernel(Grid
         v2 = fx ? T(0) : ep.c1 * dv + ep.c2 * P.d * rn;
       }
       y[3 * n + c] = v2;
+      if (XIN && xi.xout) xi.xout[3 * n + c] = own[c];
     }
   };
 
@@ -670,14 +765,14 @@ int64_t kxu_tile_blocks(const Grid& g) {
   return (int64_t)((g.nx + 1 + OWN - 1) / OWN) * ((g.ny + 1 + OWN - 1) / OWN) * (g.nz + 1);
 }
 
-template <typename T, int MODE>
+template <typename T, int MODE, int XIN>
 static int launch_tile(hipStream_t stream, const Grid& g, const T* x, const T* E, const uint8_t* nm,
                        const WK<T>& wk, T* y, const Epi<T>& ep, CgState* st, double* partials, double* out,
-                       const T* zpad) {
-  const void* k = reinterpret_cast<const void*>(&kxu_tile_kernel<T, MODE>);
+                       const T* zpad, const XinK<T>& xi, const FoldK& fo) {
+  const void* k = reinterpret_cast<const void*>(&kxu_tile_kernel<T, MODE, XIN>);
   const TileMap tm = kxu_tile_map(g, kxu_slots(k));
-  hipLaunchKernelGGL((kxu_tile_kernel<T, MODE>), dim3(tm.nblk), dim3(TX * TY), 0, stream, g, tm, x, E, nm, wk,
-                     y, ep, st, partials, out, zpad);
+  hipLaunchKernelGGL((kxu_tile_kernel<T, MODE, XIN>), dim3(tm.nblk), dim3(TX * TY), 0, stream, g, tm, x, E, nm,
+                     wk, y, ep, st, partials, out, zpad, xi, fo);
   return tm.nblk;
 }
 
@@ -708,7 +803,7 @@ static int launch_mfma(int mode, hipStream_t stream, const Grid& g, const float*
 template <typename T>
 hipError_t launch_kxu_tile(fe_problem* p, int lev, const T* x, const T* E, T* y, CgState* st, int mode,
                            const double* b64, double* out, const T* bT, const T* invd, double omega,
-                           const ChebStep<T>* cs) {
+                           const ChebStep<T>* cs, const TileFuse<T>* fz) {
   const Grid g = p->L[lev].g;
   const WK<T> wk = scaled_wk<T>(p->wk, p->L[lev].h);
   Epi<T> ep;
@@ -735,7 +830,9 @@ hipError_t launch_kxu_tile(fe_problem* p, int lev, const T* x, const T* E, T* y,
     slot = kstats_begin(p, bytes);
   }
   int nb = 0;
-  if (std::is_same<T, float>::value && lev == 0 && p->mfma_l0 && mode != 2 && mode != 6) {
+  double* pt = (fz && fz->part) ? fz->part : p->partials;
+  const bool fused = fz && (fz->xin != 0 || fz->fold);  // the matrix-core kernel has no fused operand
+  if (std::is_same<T, float>::value && lev == 0 && p->mfma_l0 && mode != 2 && mode != 6 && !fused) {
     Epi<float> ef;
     ef.b64 = b64;
     ef.bT = reinterpret_cast<const float*>(bT);
@@ -749,23 +846,41 @@ hipError_t launch_kxu_tile(fe_problem* p, int lev, const T* x, const T* E, T* y,
     const float* Ef = reinterpret_cast<const float*>(E);
     float* yf = reinterpret_cast<float*>(y);
     const float ks = (float)p->L[lev].h;
-    nb = p->mfma_l0 == 2 ? launch_mfma<true>(mode, p->stream, g, xf, Ef, nm, p->ke32, ks, yf, ef, st, p->partials)
-                         : launch_mfma<false>(mode, p->stream, g, xf, Ef, nm, p->ke32, ks, yf, ef, st, p->partials);
+    nb = p->mfma_l0 == 2 ? launch_mfma<true>(mode, p->stream, g, xf, Ef, nm, p->ke32, ks, yf, ef, st, pt)
+                         : launch_mfma<false>(mode, p->stream, g, xf, Ef, nm, p->ke32, ks, yf, ef, st, pt);
   } else {
     const T* zp = reinterpret_cast<const T*>(p->zpad);
-    switch (mode) {
-      case 1: nb = launch_tile<T, 1>(p->stream, g, x, E, nm, wk, y, ep, st, p->partials, out, zp); break;
-      case 2: nb = launch_tile<T, 2>(p->stream, g, x, E, nm, wk, y, ep, st, p->partials, out, zp); break;
-      case 3: nb = launch_tile<T, 3>(p->stream, g, x, E, nm, wk, y, ep, st, p->partials, out, zp); break;
-      case 4: nb = launch_tile<T, 4>(p->stream, g, x, E, nm, wk, y, ep, st, p->partials, out, zp); break;
-      case 5: nb = launch_tile<T, 5>(p->stream, g, x, E, nm, wk, y, ep, st, p->partials, out, zp); break;
-      case 6: nb = launch_tile<T, 6>(p->stream, g, x, E, nm, wk, y, ep, st, p->partials, out, zp); break;
-      default: nb = launch_tile<T, 0>(p->stream, g, x, E, nm, wk, y, ep, st, p->partials, out, zp);
+    XinK<T> xi;
+    xi.invd = fz ? fz->invd : nullptr;
+    xi.s = fz ? (T)fz->s : T(0);
+    xi.pold = fz ? fz->pold : nullptr;
+    xi.xout = fz ? fz->xout : nullptr;
+    FoldK fo;
+    fo.part = fz ? fz->fold : nullptr;
+    fo.n = fz ? fz->nfold : 0;
+    fo.what = (fz && fz->fold) ? (fz->fold_rr ? 2 : 1) : 0;
+    const int xin = fz ? fz->xin : 0;
+#define FE_TILE(M, X) launch_tile<T, M, X>(p->stream, g, x, E, nm, wk, y, ep, st, pt, out, zp, xi, fo)
+    switch (mode * 4 + xin) {
+      case 1 * 4: nb = FE_TILE(1, 0); break;
+      case 1 * 4 + 2: nb = FE_TILE(1, 2); break;
+      case 2 * 4: nb = FE_TILE(2, 0); break;
+      case 3 * 4: nb = FE_TILE(3, 0); break;
+      case 3 * 4 + 1: nb = FE_TILE(3, 1); break;
+      case 4 * 4: nb = FE_TILE(4, 0); break;
+      case 4 * 4 + 1: nb = FE_TILE(4, 1); break;
+      case 5 * 4: nb = FE_TILE(5, 0); break;
+      case 6 * 4: nb = FE_TILE(6, 0); break;
+      case 0: nb = FE_TILE(0, 0); break;
+      default: return hipErrorInvalidValue;
     }
+#undef FE_TILE
   }
   hipError_t e = hipGetLastError();
   kstats_end(p, slot);
   if (e != hipSuccess) return e;
+  if (fz && fz->nblocks) *fz->nblocks = nb;
+  if (fz && fz->no_finalize) return hipSuccess;
   if (mode == 1) return launch_cg_finalize(p, FIN_ALPHA, nb, 0, st, nullptr);
   if (mode == 2) return launch_cg_finalize(p, FIN_SCALAR, nb, 0, nullptr, out);
   if (mode == 5) return launch_cg_finalize(p, FIN_RZ, nb, 1, st, nullptr);
@@ -774,7 +889,8 @@ hipError_t launch_kxu_tile(fe_problem* p, int lev, const T* x, const T* E, T* y,
 
 template hipError_t launch_kxu_tile<double>(fe_problem*, int, const double*, const double*, double*,
                                             CgState*, int, const double*, double*, const double*,
-                                            const double*, double, const ChebStep<double>*);
+                                            const double*, double, const ChebStep<double>*,
+                                            const TileFuse<double>*);
 template hipError_t launch_kxu_tile<float>(fe_problem*, int, const float*, const float*, float*, CgState*,
                                            int, const double*, double*, const float*, const float*, double,
-                                           const ChebStep<float>*);
+                                           const ChebStep<float>*, const TileFuse<float>*);

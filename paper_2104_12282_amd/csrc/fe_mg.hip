@@ -108,23 +108,57 @@ const double* lev_E<double>(const Level& L) { return L.E64; }
 template <>
 const float* lev_E<float>(const Level& L) { return L.E32; }
 
-// n damped Jacobi sweeps from z = 0 on level l, result in z (t is scratch).
+// Pre-smoothing on level l: n damped Jacobi sweeps from z = 0, then the
+// residual t = r - K z.  The first sweep (z = omega D^-1 r, pointwise) is
+// formed inside the next tiled launch instead of a launch of its own: for
+// n = 1 inside the residual launch (which also stores z), otherwise inside
+// the second sweep.  With fold_rr > 0 that first launch also takes the CG
+// convergence decision.  Level 0 of a matrix-core problem keeps the
+// separate first sweep, so that its tiled launches stay on matrix cores.
 template <typename T>
-hipError_t jacobi_sweeps(fe_problem* p, int l, const T* r, T* z, T* t, int n, CgState* st) {
+hipError_t presmooth(fe_problem* p, int l, const T* r, T* z, T* t, int n, CgState* st, int fold_rr) {
   const Level& L = p->L[l];
   const double om = p->mg_omega;
-  T* a = (n % 2) ? z : t;  // first target chosen so the last sweep lands in z
-  T* b = (n % 2) ? t : z;
-  hipLaunchKernelGGL(jacobi0_kernel<T>, dim3(nblocks(L.g.ndof)), dim3(FE_BLOCK), 0, p->stream, L.g.ndof, r,
-                     lev_invd<T>(L), (T)om, a, st);
-  hipError_t e = hipGetLastError();
-  for (int s = 1; s < n && e == hipSuccess; ++s) {
+  TileFuse<T> fz;
+  fz.fold = fold_rr > 0 ? part_region(p, PART_RR) : nullptr;
+  fz.nfold = fold_rr;
+  fz.fold_rr = fold_rr > 0;
+  const bool fuse = !(l == 0 && p->mfma_l0) || fold_rr > 0;
+  hipError_t e = hipSuccess;
+  if (!fuse) {
+    T* a = (n % 2) ? z : t;  // first target chosen so the last sweep lands in z
+    T* b = (n % 2) ? t : z;
+    hipLaunchKernelGGL(jacobi0_kernel<T>, dim3(nblocks(L.g.ndof)), dim3(FE_BLOCK), 0, p->stream, L.g.ndof, r,
+                       lev_invd<T>(L), (T)om, a, st);
+    e = hipGetLastError();
+    for (int s = 1; s < n && e == hipSuccess; ++s) {
+      e = launch_kxu_tile<T>(p, l, a, lev_E<T>(L), b, st, 3, nullptr, nullptr, r, lev_invd<T>(L), om);
+      T* tmp = a;
+      a = b;
+      b = tmp;
+    }
+    if (e != hipSuccess) return e;
+    return launch_kxu_tile<T>(p, l, z, lev_E<T>(L), t, st, 4, nullptr, nullptr, r, nullptr, 0.0);
+  }
+  fz.xin = 1;
+  fz.invd = lev_invd<T>(L);
+  fz.s = om;
+  if (n == 1) {
+    fz.xout = z;  // z = omega D^-1 r, t = r - K z
+    return launch_kxu_tile<T>(p, l, r, lev_E<T>(L), t, st, 4, nullptr, nullptr, r, nullptr, 0.0, nullptr, &fz);
+  }
+  // sweeps 2 .. n ping-pong between t and z so that the last lands in z
+  T* a = (n % 2) ? t : z;
+  T* b = (n % 2) ? z : t;
+  e = launch_kxu_tile<T>(p, l, r, lev_E<T>(L), a, st, 3, nullptr, nullptr, r, lev_invd<T>(L), om, nullptr, &fz);
+  for (int s = 2; s < n && e == hipSuccess; ++s) {
     e = launch_kxu_tile<T>(p, l, a, lev_E<T>(L), b, st, 3, nullptr, nullptr, r, lev_invd<T>(L), om);
     T* tmp = a;
     a = b;
     b = tmp;
   }
-  return e;
+  if (e != hipSuccess) return e;
+  return launch_kxu_tile<T>(p, l, z, lev_E<T>(L), t, st, 4, nullptr, nullptr, r, nullptr, 0.0);
 }
 
 // Coarsest-level solve: `deg` steps of Jacobi-preconditioned Chebyshev
@@ -165,18 +199,16 @@ hipError_t chebyshev_solve(fe_problem* p, int l, T* r, T* z, T* d0, T* d1, int d
 
 // z = V(r): one symmetric V-cycle on levels l .. nlev-1 (pre- and
 // post-smoothing with mg_nu damped Jacobi sweeps, a Chebyshev solve of
-// degree mg_coarse_sweeps on the coarsest level).  st (may be null) guards the launches; with fuse_rz the
-// last sweep on level 0 also forms r^T z and the CG direction factor.
+// degree mg_coarse_sweeps on the coarsest level).  st (may be null) guards
+// the launches; rz and fold_rr as declared in the internal header.
 template <typename T>
-hipError_t launch_vcycle(fe_problem* p, int l, const T* r, T* z, CgState* st, bool fuse_rz) {
+hipError_t launch_vcycle(fe_problem* p, int l, const T* r, T* z, CgState* st, int rz, int fold_rr) {
   const Level& L = p->L[l];
   T* t = static_cast<T*>(L.mg_t);
   if (l == p->nlev - 1)  // r is this level's own restricted residual: free to overwrite
     return chebyshev_solve<T>(p, l, const_cast<T*>(r), z, t, static_cast<T*>(L.mg_w), p->mg_coarse_sweeps, st);
-  hipError_t e = jacobi_sweeps<T>(p, l, r, z, t, p->mg_nu, st);
-  if (e != hipSuccess) return e;
-  // t = r - K z, restricted to the next level's right-hand side
-  e = launch_kxu_tile<T>(p, l, z, lev_E<T>(L), t, st, 4, nullptr, nullptr, r, nullptr, 0.0);
+  // z from the pre-smoothing sweeps, t = r - K z restricted to the next level
+  hipError_t e = presmooth<T>(p, l, r, z, t, p->mg_nu, st, l == 0 ? fold_rr : 0);
   if (e != hipSuccess) return e;
   const Level& C = p->L[l + 1];
   T* rc = static_cast<T*>(C.mg_r);
@@ -184,7 +216,7 @@ hipError_t launch_vcycle(fe_problem* p, int l, const T* r, T* z, CgState* st, bo
   hipLaunchKernelGGL(restrict_kernel<T>, dim3(nblocks(C.g.nnode)), dim3(FE_BLOCK), 0, p->stream, L.g, C.g, t,
                      C.nmask, rc, st);
   if ((e = hipGetLastError()) != hipSuccess) return e;
-  if ((e = launch_vcycle<T>(p, l + 1, rc, zc, st, false)) != hipSuccess) return e;
+  if ((e = launch_vcycle<T>(p, l + 1, rc, zc, st, RZ_NONE, 0)) != hipSuccess) return e;
   // post-smoothing, arranged so the last sweep writes z
   const int nu = p->mg_nu;
   T* a = (nu % 2) ? t : z;
@@ -193,9 +225,15 @@ hipError_t launch_vcycle(fe_problem* p, int l, const T* r, T* z, CgState* st, bo
   if ((e = hipGetLastError()) != hipSuccess) return e;
   T* b = (a == t) ? z : t;
   for (int s = 0; s < nu; ++s) {
-    const int mode = (fuse_rz && l == 0 && s == nu - 1) ? 5 : 3;
-    e = launch_kxu_tile<T>(p, l, a, lev_E<T>(L), b, st, mode, nullptr, nullptr, r, lev_invd<T>(L),
-                           p->mg_omega);
+    const bool last = rz != RZ_NONE && l == 0 && s == nu - 1;
+    TileFuse<T> fz;
+    if (last && rz == RZ_PARTIALS) {
+      fz.part = part_region(p, PART_RZ);
+      fz.no_finalize = true;
+      fz.nblocks = &p->nrz;
+    }
+    e = launch_kxu_tile<T>(p, l, a, lev_E<T>(L), b, st, last ? 5 : 3, nullptr, nullptr, r, lev_invd<T>(L),
+                           p->mg_omega, nullptr, (last && rz == RZ_PARTIALS) ? &fz : nullptr);
     if (e != hipSuccess) return e;
     T* tmp = a;
     a = b;
@@ -204,5 +242,5 @@ hipError_t launch_vcycle(fe_problem* p, int l, const T* r, T* z, CgState* st, bo
   return hipSuccess;
 }
 
-template hipError_t launch_vcycle<double>(fe_problem*, int, const double*, double*, CgState*, bool);
-template hipError_t launch_vcycle<float>(fe_problem*, int, const float*, float*, CgState*, bool);
+template hipError_t launch_vcycle<double>(fe_problem*, int, const double*, double*, CgState*, int, int);
+template hipError_t launch_vcycle<float>(fe_problem*, int, const float*, float*, CgState*, int, int);
