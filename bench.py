@@ -68,7 +68,7 @@ def traffic_from_profiles(precision: str, grid: str):
         from paper_2104_12282_amd.build import source_digest
         if rec.get("source_digest") != source_digest():
             return None
-        want = f"kxu_tile_kernel<{'double' if precision == 'fp64' else 'float'}, 1>"
+        want = f"kxu_tile_kernel<{'double' if precision == 'fp64' else 'float'}, 1, 2>"
         for name, k in rec["kernels"].items():
             if want in name:
                 return k["fetch_bytes"] + k["write_bytes"]
@@ -261,7 +261,7 @@ def run_loop(fe, synth, torch, nx, ny, nz, precision, args, steps, warmup, profi
     rec["compliance"].clear()
     torch.cuda.synchronize()
     prob.kernel_stats(reset=True)
-    prob.set_profiling(profile)
+    prob.set_profiling(profile, mode=1)  # the CG product: direction + K*u launch
     torch.cuda.synchronize()
     t0 = time.perf_counter()
     for i in range(steps):
@@ -332,7 +332,9 @@ def main():
                      "frac": achieved / HBM_PEAK_GBS,
                      "traffic": traffic_from_profiles(args.precision, f"{nx}x{ny}x{nz}"),
                      "traffic_of": "one CG-product launch (rocprofv3 counters, copy-scaled)",
-                     "kernel": "matrix-free K*u (tiled, finest grid, all epilogues)",
+                     "kernel": "kxu_tile_kernel<" + ("double" if args.precision == "fp64" else "float")
+                               + ", 1, 2>: CG product on the finest grid (direction p = z + beta p fused "
+                               "into the matrix-free K*u, p^T K p partials)",
                      "launches": ks["launches"], "avg_launch_us": avg_ms * 1e3,
                      "algorithmic_bytes_per_launch": ks["bytes_per_launch"]},
     }

@@ -171,12 +171,15 @@ FE_API fe_status oc_update(fe_problem* p, const double* x, const double* dcx, co
  * (checked: FE_EINVAL otherwise), so plain CG applies. */
 FE_API fe_status fe_set_mg_params(fe_problem* p, int32_t nu, int32_t coarse_sweeps, double omega);
 
-/* Timing of the dominant kernel (matrix-free K*u on the finest grid, in all
- * its forms: CG product, residual, smoothing sweep): when on, every such
- * launch is bracketed by HIP events on the handle's stream.  fe_kernel_stats
- * returns the number of launches and their summed duration in ms since the
- * last reset, and the mean algorithmic bytes of one launch (each array the
- * kernel reads or writes counted once). */
+/* Timing of the dominant kernel (matrix-free K*u on the finest grid): with
+ * on = 1 every such launch, in all its forms (CG product, residual, smoothing
+ * sweep), is bracketed by HIP events on the handle's stream; with on = 2 + m
+ * only the launches of form m (1 = CG product, 3 = smoothing sweep,
+ * 4 = residual, 5 = last smoothing sweep with r^T z, 6 = Chebyshev step,
+ * 0 = plain product); on = 0 switches it off, other values are FE_EINVAL.
+ * fe_kernel_stats returns the number of launches and their summed duration
+ * in ms since the last reset, and the mean algorithmic bytes of one launch
+ * (each array the kernel reads or writes counted once). */
 FE_API fe_status fe_set_profiling(fe_problem* p, int32_t on);
 FE_API fe_status fe_kernel_stats(fe_problem* p, int32_t reset, int64_t* launches,
                           double* total_ms, double* bytes_per_launch);

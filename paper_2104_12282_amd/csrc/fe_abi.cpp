@@ -862,7 +862,12 @@ extern "C" fe_status fe_set_mg_params(fe_problem* p, int32_t nu, int32_t coarse_
 
 extern "C" fe_status fe_set_profiling(fe_problem* p, int32_t on) {
   CHECK_HANDLE(p);
+  if (on < 0 || on > 8) {
+    fe_set_error("profiling selector must be 0, 1 or 2 + form (form 0..6)");
+    return FE_EINVAL;
+  }
   p->kst.on = on != 0;
+  p->kst.mode = on >= 2 ? on - 2 : -1;
   return FE_OK;
 }
 

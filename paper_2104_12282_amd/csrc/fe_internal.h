@@ -69,6 +69,7 @@ struct Level {
 
 struct KStats {
   bool on = false;
+  int mode = -1;               // only launches of this form (-1: all)
   std::vector<hipEvent_t> ev;  // pairs
   std::vector<double> bytes;   // algorithmic bytes of each recorded launch
   int64_t pending = 0;         // recorded pairs not yet read

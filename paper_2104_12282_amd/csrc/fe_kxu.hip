@@ -818,15 +818,19 @@ hipError_t launch_kxu_tile(fe_problem* p, int lev, const T* x, const T* E, T* y,
   ep.first = cs ? cs->first : 0;
   const uint8_t* nm = p->L[lev].nmask;
   // algorithmic bytes: read x and E, write y, plus b (modes 2-5) and the
-  // Jacobi diagonal (modes 3, 5); each array touched once
+  // Jacobi diagonal (modes 3, 5, 6) and the fused operand's extra arrays;
+  // each array touched once
   int slot = -1;
-  if (lev == 0 && p->kst.on) {
+  if (lev == 0 && p->kst.on && (p->kst.mode < 0 || p->kst.mode == mode)) {
     const double vb = sizeof(T);
     double bytes = vb * (2.0 * (double)g.ndof + (double)g.nelem);
     if (mode == 2) bytes += 8.0 * (double)g.ndof;
     if (mode >= 3) bytes += vb * (double)g.ndof;
     if (mode == 3 || mode == 5 || mode == 6) bytes += vb * (double)g.nnode;
     if (mode == 6) bytes += vb * 3.0 * (double)g.ndof;  // res in/out, acc in/out (res read counted above)
+    if (fz && fz->xin == 1) bytes += vb * (double)g.nnode;  // inverse diagonal of the fused first sweep
+    if (fz && fz->xin == 2) bytes += vb * (double)g.ndof;   // previous direction
+    if (fz && fz->xin && fz->xout) bytes += vb * (double)g.ndof;  // the operand, stored
     slot = kstats_begin(p, bytes);
   }
   int nb = 0;

@@ -211,8 +211,10 @@ class Problem:
     def set_mg_params(self, nu=1, coarse_sweeps=20, omega=0.35):
         _check(load_library().fe_set_mg_params(self._h, nu, coarse_sweeps, omega))
 
-    def set_profiling(self, on: bool):
-        _check(load_library().fe_set_profiling(self._h, 1 if on else 0))
+    def set_profiling(self, on, mode=None):
+        """Times finest-grid K*u launches: all forms, or only form `mode`."""
+        sel = 0 if not on else (1 if mode is None else 2 + int(mode))
+        _check(load_library().fe_set_profiling(self._h, sel))
 
     def kernel_stats(self, reset=False):
         n, ms, b = C.c_int64(), C.c_double(), C.c_double()

@@ -332,3 +332,44 @@ def test_bf16_refined_solve_parity(Ke, precond):
     assert info["rel_res"] <= 1e-10 and info["outer_iters"] >= 2
     assert abs(float(N(c)[0]) - c_ref) / c_ref <= 1e-6
     assert np.abs(N(dc) - dc_ref).max() / np.abs(dc_ref).max() <= 1e-5
+
+
+@pytest.mark.parametrize("nu", [2, 3])
+@pytest.mark.parametrize("precision", ["fp64", "fp32_ir"])
+def test_gmg_smoothing_sweeps_parity(Ke, nu, precision):
+    """More than one smoothing sweep takes the fused first sweep through a
+    smoothing launch (and, for nu = 3, the ping-pong of the later sweeps)."""
+    nx, ny, nz = 24, 12, 12
+    rho = synth.density_around(nx, ny, nz, 0)
+    f = synth.cantilever_edge_load(nx, ny, nz)
+    u_ref = O.solve_direct(nx, ny, nz, O.simp_modulus(rho), Ke, f, O.clamp_x0_fixed(nx, ny, nz))
+    c_ref = O.compliance(f, u_ref)
+    dc_ref = O.sensitivity(nx, ny, nz, Ke, rho, u_ref)
+    prob = _problem(nx, ny, nz, precision=precision, precond="gmg", mg_levels=3)
+    prob.set_mg_params(nu=nu, coarse_sweeps=12)
+    u, info = prob.solve(T(rho), rtol=1e-10)
+    dc, c = prob.sensitivity(T(rho), u)
+    assert info["rel_res"] <= 1e-10
+    assert abs(float(N(c)[0]) - c_ref) / c_ref <= 1e-6
+    assert np.abs(N(dc) - dc_ref).max() / np.abs(dc_ref).max() <= 1e-5
+
+
+def test_profiling_selector():
+    nx, ny, nz = 32, 16, 16
+    prob = _problem(nx, ny, nz, precond="gmg", mg_levels=3)
+    rho = T(synth.density_around(nx, ny, nz, 0))
+    with pytest.raises(fe.FEError):
+        fe._check(fe.load_library().fe_set_profiling(prob._h, 9))
+    prob.set_profiling(True, mode=1)
+    _, info = prob.solve(rho, rtol=1e-8)
+    prob.set_profiling(False)
+    ks = prob.kernel_stats(reset=True)
+    # one CG-product launch per iteration, plus the unused tail of the last chunk
+    assert info["iters"] <= ks["launches"] <= info["iters"] + 8
+    nd, ne = prob.ndof, nx * ny * nz
+    # z and the previous direction read, q and the new direction written, E read
+    assert ks["bytes_per_launch"] == pytest.approx(8.0 * (4 * nd + ne), rel=1e-12)
+    prob.set_profiling(True)
+    prob.solve(rho, rtol=1e-8)
+    prob.set_profiling(False)
+    assert prob.kernel_stats()["launches"] > ks["launches"]
