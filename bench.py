@@ -55,11 +55,12 @@ def parse():
     return ap.parse_args()
 
 
-def traffic_from_profiles(precision: str, grid: str):
+def traffic_from_profiles(precision: str, grid: str, field: str = "bytes"):
     """HBM bytes (fetched + written) of one CG-product launch of the tiled K*u
     kernel on this grid, from rocprofv3 FETCH_SIZE / WRITE_SIZE counters scaled
-    by a copy of known size, when the stored figure was taken on the current
-    kernel source; else None."""
+    by a copy of known size (field "bytes"), or rocprofv3's average kernel
+    duration of that launch in us (field "trace_avg_us"), when the stored
+    figures were taken on the current kernel source; else None."""
     path = os.path.join(ROOT, "profiles", f"kxu_tile_{grid}_traffic.json")
     if not os.path.exists(path):
         return None
@@ -71,7 +72,7 @@ def traffic_from_profiles(precision: str, grid: str):
         want = f"kxu_tile_kernel<{'double' if precision == 'fp64' else 'float'}, 1, 2>"
         for name, k in rec["kernels"].items():
             if want in name:
-                return k["fetch_bytes"] + k["write_bytes"]
+                return k["fetch_bytes"] + k["write_bytes"] if field == "bytes" else k.get(field)
     except Exception:
         return None
     return None
@@ -336,6 +337,12 @@ def main():
                                + ", 1, 2>: CG product on the finest grid (direction p = z + beta p fused "
                                "into the matrix-free K*u, p^T K p partials)",
                      "launches": ks["launches"], "avg_launch_us": avg_ms * 1e3,
+                     "rocprofv3_avg_kernel_us": traffic_from_profiles(args.precision, f"{nx}x{ny}x{nz}",
+                                                                      "trace_avg_us"),
+                     "timing_note": "avg_launch_us brackets each launch with HIP event nodes inside the "
+                                    "captured CG graph (includes the nodes' own dispatch time); "
+                                    "rocprofv3_avg_kernel_us is the kernel-trace average of the same "
+                                    "kernel in the profiled run of this command",
                      "algorithmic_bytes_per_launch": ks["bytes_per_launch"]},
     }
     if probe:

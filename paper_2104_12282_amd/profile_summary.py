@@ -2,13 +2,15 @@
 profiles/.
 
   python -m paper_2104_12282_amd.profile_summary stats <kernel_stats.csv> <out.md> "<command>"
-  python -m paper_2104_12282_amd.profile_summary traffic <fetch_dir> <write_dir> <bench.json> <out.json> "<commands>"
+  python -m paper_2104_12282_amd.profile_summary traffic <fetch_dir> <write_dir> <bench.json> <out.json> "<commands>" [<kernel_stats.csv>]
 
 `traffic` reads two counter runs (FETCH_SIZE, then WRITE_SIZE, in KiB per
 dispatch), scales each by what the same counter reads for the plain copy of
 known size that bench.py --copy-probe performs (hipMemcpy device-to-device,
 kernel __amd_rocclr_copyBuffer), and stores the bytes per launch of the tiled
-K*u kernel next to the digest of the sources it was measured on.
+K*u kernel next to the digest of the sources it was measured on; given the
+kernel statistics of a --kernel-trace run of the same sources, it also
+stores each kernel's average duration there.
 """
 from __future__ import annotations
 
@@ -54,7 +56,7 @@ def _counter_by_kernel(run_dir, counter):
     return out
 
 
-def traffic(fetch_dir, write_dir, bench_json, out_path, command):
+def traffic(fetch_dir, write_dir, bench_json, out_path, command, stats_csv=None):
     sys.path.insert(0, os.path.dirname(os.path.dirname(os.path.abspath(__file__))))
     from paper_2104_12282_amd.build import source_digest
     probe = json.load(open(bench_json))["copy_probe"]
@@ -82,6 +84,11 @@ def traffic(fetch_dir, write_dir, bench_json, out_path, command):
         rec["kernels"][mode_key] = {"fetch_bytes": fmax * 1024 * f_scale,
                                     "write_bytes": wmax * 1024 * w_scale,
                                     "launches_seen": len(fk)}
+    if stats_csv:
+        for r in _rows(stats_csv):
+            if r["Name"] in rec["kernels"]:
+                rec["kernels"][r["Name"]]["trace_avg_us"] = float(r["AverageNs"]) / 1e3
+                rec["kernels"][r["Name"]]["trace_max_us"] = float(r["MaxNs"]) / 1e3
     with open(out_path, "w") as fh:
         json.dump(rec, fh, indent=1)
 
@@ -90,6 +97,7 @@ if __name__ == "__main__":
     if sys.argv[1] == "stats":
         stats(sys.argv[2], sys.argv[3], sys.argv[4])
     elif sys.argv[1] == "traffic":
-        traffic(sys.argv[2], sys.argv[3], sys.argv[4], sys.argv[5], sys.argv[6])
+        traffic(sys.argv[2], sys.argv[3], sys.argv[4], sys.argv[5], sys.argv[6],
+                sys.argv[7] if len(sys.argv) > 7 else None)
     else:
         raise SystemExit(__doc__)
