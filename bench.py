@@ -38,7 +38,8 @@ def parse():
     ap.add_argument("--precond", default="gmg", choices=["jacobi", "gmg"])
     ap.add_argument("--mg-levels", type=int, default=3)
     ap.add_argument("--mg-nu", type=int, default=1)
-    ap.add_argument("--mg-coarse", type=int, default=30)
+    ap.add_argument("--mg-coarse", type=int, default=40)
+    ap.add_argument("--mg-coarse-ratio", type=float, default=5000.0)
     ap.add_argument("--rtol", type=float, default=1e-6)
     ap.add_argument("--volfrac", type=float, default=0.12)
     ap.add_argument("--move", type=float, default=0.2)
@@ -140,7 +141,7 @@ def precision_study(fe, synth, torch, nx, ny, nz, seeds, args):
     probs = {p: fe.Problem(nx, ny, nz, f, precision=p, **kw) for p in ("fp64",) + tuple(v for v, _ in PREC_VARIANTS)}
     if args.precond == "gmg":
         for pr in probs.values():
-            pr.set_mg_params(nu=args.mg_nu, coarse_sweeps=args.mg_coarse)
+            pr.set_mg_params(nu=args.mg_nu, coarse_sweeps=args.mg_coarse, coarse_ratio=args.mg_coarse_ratio)
     res = {p: {"c_rel_err": [], "dc_rel_err": [], "iters": [], "outer_iters": [], "rel_res": [], "ms": []}
            for p in probs}
     for seed in range(seeds):
@@ -227,7 +228,7 @@ def run_loop(fe, synth, torch, nx, ny, nz, precision, args, steps, warmup, profi
     prob = fe.Problem(nx, ny, nz, T(f), device=dev, precision=precision, precond=args.precond,
                       mg_levels=args.mg_levels)
     if args.precond == "gmg":
-        prob.set_mg_params(nu=args.mg_nu, coarse_sweeps=args.mg_coarse)
+        prob.set_mg_params(nu=args.mg_nu, coarse_sweeps=args.mg_coarse, coarse_ratio=args.mg_coarse_ratio)
     x = torch.empty(ne, dtype=torch.float64, device=dev)
     u = torch.empty(prob.ndof, dtype=torch.float64, device=dev)
     rho = torch.empty_like(x)
@@ -325,6 +326,7 @@ def main():
                    "mg_levels": args.mg_levels if args.precond == "gmg" else None,
                    "mg_smoothing_sweeps": args.mg_nu if args.precond == "gmg" else None,
                    "mg_coarse_chebyshev_degree": args.mg_coarse if args.precond == "gmg" else None,
+                   "mg_coarse_chebyshev_ratio": args.mg_coarse_ratio if args.precond == "gmg" else None,
                    "rtol": args.rtol, "volfrac": args.volfrac, "filter_r": 1.5, "move": args.move,
                    "cg_iters_per_solve": float(np.mean(rec["iters"])),
                    "cg_iters_max": int(np.max(rec["iters"])),

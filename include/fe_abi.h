@@ -164,12 +164,15 @@ FE_API fe_status oc_update(fe_problem* p, const double* x, const double* dcx, co
  * Jacobi sweeps (damping omega) before and after each coarse correction
  * (1..8), and the degree (1..10000) of the Jacobi-preconditioned Chebyshev
  * iteration that solves the coarsest level, on the interval
- * [lambda_max / 100, lambda_max] with lambda_max = largest eigenvalue of
- * diag(Ke)^-1 Ke (5.32 for nu = 0.3), which bounds that of D^-1 K for any
- * density field.  Defaults: nu = 1, degree 20, omega = 0.35.  The V-cycle is
- * linear and symmetric, and positive definite while omega * lambda_max < 2
- * (checked: FE_EINVAL otherwise), so plain CG applies. */
-FE_API fe_status fe_set_mg_params(fe_problem* p, int32_t nu, int32_t coarse_sweeps, double omega);
+ * [lambda_max / coarse_ratio, lambda_max] (2 <= coarse_ratio <= 1e12) with
+ * lambda_max = largest eigenvalue of diag(Ke)^-1 Ke (5.32 for nu = 0.3),
+ * which bounds that of D^-1 K for any density field.  Defaults: nu = 1,
+ * degree 40, omega = 0.35, coarse_ratio 5000.  The V-cycle is linear and
+ * symmetric, and positive definite while omega * lambda_max < 2 (checked:
+ * FE_EINVAL otherwise; the Chebyshev residual polynomial stays in (0, 1)
+ * below the interval for any ratio), so plain CG applies. */
+FE_API fe_status fe_set_mg_params(fe_problem* p, int32_t nu, int32_t coarse_sweeps, double omega,
+                           double coarse_ratio);
 
 /* Timing of the dominant kernel (matrix-free K*u on the finest grid): with
  * on = 1 every such launch, in all its forms (CG product, residual, smoothing

@@ -841,10 +841,12 @@ extern "C" fe_status oc_update(fe_problem* p, const double* x, const double* dcx
   return FE_OK;
 }
 
-extern "C" fe_status fe_set_mg_params(fe_problem* p, int32_t nu, int32_t coarse_sweeps, double omega) {
+extern "C" fe_status fe_set_mg_params(fe_problem* p, int32_t nu, int32_t coarse_sweeps, double omega,
+                                      double coarse_ratio) {
   CHECK_HANDLE(p);
-  if (nu < 1 || nu > 8 || coarse_sweeps < 1 || coarse_sweeps > 10000 || !(omega > 0.0 && omega < 1.0)) {
-    fe_set_error("need 1 <= nu <= 8, 1 <= coarse_sweeps <= 10000, 0 < omega < 1");
+  if (nu < 1 || nu > 8 || coarse_sweeps < 1 || coarse_sweeps > 10000 || !(omega > 0.0 && omega < 1.0) ||
+      !(coarse_ratio >= 2.0 && coarse_ratio <= 1e12)) {
+    fe_set_error("need 1 <= nu <= 8, 1 <= coarse_sweeps <= 10000, 0 < omega < 1, 2 <= coarse_ratio <= 1e12");
     return FE_EINVAL;
   }
   if (omega * p->lam_max >= 2.0) {
@@ -855,6 +857,7 @@ extern "C" fe_status fe_set_mg_params(fe_problem* p, int32_t nu, int32_t coarse_
   p->mg_nu = nu;
   p->mg_coarse_sweeps = coarse_sweeps;
   p->mg_omega = omega;
+  p->cheb_ratio = coarse_ratio;
   drop_graph(p->chunk64);  // the captured chunks bake these in
   drop_graph(p->chunk32);
   return FE_OK;

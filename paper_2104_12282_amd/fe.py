@@ -71,7 +71,7 @@ def load_library() -> C.CDLL:
     lib.fe_sensitivity.argtypes = [P, P, P, P, P]
     lib.fe_filter.argtypes = [P, P, P, I32]
     lib.oc_update.argtypes = [P, P, P, P, D, D, P, P]
-    lib.fe_set_mg_params.argtypes = [P, I32, I32, D]
+    lib.fe_set_mg_params.argtypes = [P, I32, I32, D, D]
     lib.fe_set_profiling.argtypes = [P, I32]
     lib.fe_kernel_stats.argtypes = [P, I32, C.POINTER(I64), C.POINTER(D), C.POINTER(D)]
     lib.fe_destroy.argtypes = [P]
@@ -208,8 +208,8 @@ class Problem:
                                         _ptr(xn), _ptr(ch)))
         return xn, ch
 
-    def set_mg_params(self, nu=1, coarse_sweeps=20, omega=0.35):
-        _check(load_library().fe_set_mg_params(self._h, nu, coarse_sweeps, omega))
+    def set_mg_params(self, nu=1, coarse_sweeps=40, omega=0.35, coarse_ratio=5000.0):
+        _check(load_library().fe_set_mg_params(self._h, nu, coarse_sweeps, omega, coarse_ratio))
 
     def set_profiling(self, on, mode=None):
         """Times finest-grid K*u launches: all forms, or only form `mode`."""

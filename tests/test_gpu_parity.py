@@ -227,8 +227,15 @@ def test_gmg_params_validation():
         prob.set_mg_params(nu=0)
     with pytest.raises(fe.FEError):  # unstable smoother: omega * 5.32 >= 2
         prob.set_mg_params(omega=0.6)
+    with pytest.raises(fe.FEError):  # empty Chebyshev interval
+        prob.set_mg_params(coarse_ratio=1.0)
     prob.set_mg_params(nu=2, coarse_sweeps=10, omega=0.3)
     rho = synth.density_around(16, 8, 8, 1)
+    _, info = prob.solve(T(rho), rtol=1e-9)
+    assert info["rel_res"] <= 1e-9
+    # a wide interval (the residual polynomial stays in (0, 1) below it):
+    # still a symmetric positive definite preconditioner
+    prob.set_mg_params(coarse_sweeps=30, coarse_ratio=1e8)
     _, info = prob.solve(T(rho), rtol=1e-9)
     assert info["rel_res"] <= 1e-9
 
