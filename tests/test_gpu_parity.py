@@ -380,3 +380,24 @@ def test_profiling_selector():
     prob.solve(rho, rtol=1e-8)
     prob.set_profiling(False)
     assert prob.kernel_stats()["launches"] > ks["launches"]
+
+
+@pytest.mark.parametrize("deg", [1, 2, 3, 8])
+@pytest.mark.parametrize("precision", ["fp64", "fp32_ir"])
+def test_coarse_chebyshev_degrees_parity(Ke, deg, precision):
+    """Low coarse Chebyshev degrees (a poor coarse solve, the first step from
+    zero alone for degree 1) still give a symmetric positive definite
+    V-cycle: CG reaches the oracle's answer."""
+    nx, ny, nz = 32, 16, 16
+    rho = synth.density_around(nx, ny, nz, 2)
+    f = synth.cantilever_edge_load(nx, ny, nz)
+    u_ref = O.solve_direct(nx, ny, nz, O.simp_modulus(rho), Ke, f, O.clamp_x0_fixed(nx, ny, nz))
+    c_ref = O.compliance(f, u_ref)
+    dc_ref = O.sensitivity(nx, ny, nz, Ke, rho, u_ref)
+    prob = _problem(nx, ny, nz, precision=precision, precond="gmg", mg_levels=3)
+    prob.set_mg_params(coarse_sweeps=deg)
+    u, info = prob.solve(T(rho), rtol=1e-10)
+    dc, c = prob.sensitivity(T(rho), u)
+    assert info["rel_res"] <= 1e-10
+    assert abs(float(N(c)[0]) - c_ref) / c_ref <= 1e-6
+    assert np.abs(N(dc) - dc_ref).max() / np.abs(dc_ref).max() <= 1e-5
