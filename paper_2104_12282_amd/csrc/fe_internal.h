@@ -271,8 +271,6 @@ hipError_t launch_cg_direction(fe_problem* p, const T* r, const T* z, T* pvec, C
 template <typename T>
 hipError_t launch_cg_update_mg(fe_problem* p, T* x, T* r, const T* pvec, const T* q, CgState* st, int npq,
                                int* nrr);
-template <typename T>
-hipError_t launch_cg_rz(fe_problem* p, const T* r, const T* z, CgState* st);
 
 hipError_t launch_cg_state_init(fe_problem* p, CgState* st, double tol_rel, int max_iter);
 // One-workgroup scalar update after a kernel that left nb partials:

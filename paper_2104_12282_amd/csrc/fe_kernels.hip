@@ -199,8 +199,8 @@ __global__ void __launch_bounds__(FE_BLOCK) cg_init_kernel(Grid g, const T* __re
 }
 
 // x += alpha p, r -= alpha q, (Jacobi) rz = r^T D^-1 r, rr = r^T r; then the
-// convergence test.  With mg = 1 the preconditioner runs separately and rz
-// comes from cg_rz_kernel.
+// convergence test.  With mg = 1 (the unfolded multigrid CG, which the
+// matrix-core problems use) the V-cycle's last sweep forms rz.
 template <typename T>
 __global__ void __launch_bounds__(FE_BLOCK) cg_update_kernel(Grid g, T* __restrict__ x, T* __restrict__ r,
                                                              const T* __restrict__ p, const T* __restrict__ q,
@@ -267,19 +267,6 @@ __global__ void __launch_bounds__(FE_BLOCK) cg_update_mg_kernel(Grid g, T* __res
     r[d] = rv;
     acc[0] += (double)rv * (double)rv;
   }
-  block_partials<1>(acc, partials);
-}
-
-// rz = r^T z (preconditioned by the multigrid cycle), beta = rz / rz_old.
-template <typename T>
-__global__ void __launch_bounds__(FE_BLOCK) cg_rz_kernel(Grid g, const T* __restrict__ r,
-                                                         const T* __restrict__ z, CgState* st,
-                                                         double* partials) {
-  if (st->done) return;
-  double acc[1] = {0.0};
-  for (int64_t d = blockIdx.x * (int64_t)FE_BLOCK + threadIdx.x; d < g.ndof;
-       d += (int64_t)gridDim.x * FE_BLOCK)
-    acc[0] += (double)r[d] * (double)z[d];
   block_partials<1>(acc, partials);
 }
 
@@ -888,18 +875,6 @@ hipError_t launch_cg_direction(fe_problem* p, const T* r, const T* z, T* pvec, C
 template hipError_t launch_cg_direction<double>(fe_problem*, const double*, const double*, double*,
                                                 CgState*);
 template hipError_t launch_cg_direction<float>(fe_problem*, const float*, const float*, float*, CgState*);
-
-template <typename T>
-hipError_t launch_cg_rz(fe_problem* p, const T* r, const T* z, CgState* st) {
-  const Grid g = G(p, 0);
-  const int nb = red_grid(g.ndof);
-  hipLaunchKernelGGL(cg_rz_kernel<T>, dim3(nb), dim3(FE_BLOCK), 0, p->stream, g, r, z, st, p->partials);
-  hipError_t e = hipGetLastError();
-  if (e != hipSuccess) return e;
-  return launch_cg_finalize(p, FIN_RZ, nb, 1, st, nullptr);
-}
-template hipError_t launch_cg_rz<double>(fe_problem*, const double*, const double*, CgState*);
-template hipError_t launch_cg_rz<float>(fe_problem*, const float*, const float*, CgState*);
 
 hipError_t launch_cg_state_init(fe_problem* p, CgState* st, double tol_rel, int max_iter) {
   hipLaunchKernelGGL(cg_state_init_kernel, dim3(1), dim3(64), 0, p->stream, st, tol_rel, max_iter);

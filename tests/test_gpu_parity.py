@@ -401,3 +401,28 @@ def test_coarse_chebyshev_degrees_parity(Ke, deg, precision):
     assert info["rel_res"] <= 1e-10
     assert abs(float(N(c)[0]) - c_ref) / c_ref <= 1e-6
     assert np.abs(N(dc) - dc_ref).max() / np.abs(dc_ref).max() <= 1e-5
+
+
+@pytest.mark.parametrize("grid,precond,levels", [((1, 1, 1), "jacobi", 1), ((5, 1, 1), "jacobi", 1),
+                                                 ((2, 9, 3), "jacobi", 1), ((2, 2, 2), "gmg", 2),
+                                                 ((4, 2, 2), "gmg", 2), ((8, 4, 4), "gmg", 3)])
+@pytest.mark.parametrize("precision", ["fp64", "fp32_ir"])
+def test_solve_degenerate_grids(Ke, grid, precond, levels, precision):
+    """One-element-thick grids and multigrid hierarchies whose coarsest
+    level is a single element layer."""
+    nx, ny, nz = grid
+    rho = synth.density_around(nx, ny, nz, 3)
+    f = synth.cantilever_edge_load(nx, ny, nz)
+    fixed = O.clamp_x0_fixed(nx, ny, nz)
+    u_ref = O.solve_direct(nx, ny, nz, O.simp_modulus(rho), Ke, f, fixed)
+    c_ref = O.compliance(f, u_ref)
+    dc_ref = O.sensitivity(nx, ny, nz, Ke, rho, u_ref)
+    kw = {"precond": precond}
+    if precond == "gmg":
+        kw["mg_levels"] = levels
+    prob = _problem(nx, ny, nz, precision=precision, **kw)
+    u, info = prob.solve(T(rho), rtol=1e-10)
+    dc, c = prob.sensitivity(T(rho), u)
+    assert info["rel_res"] <= 1e-10
+    assert abs(float(N(c)[0]) - c_ref) / c_ref <= 1e-6
+    assert np.abs(N(dc) - dc_ref).max() / np.abs(dc_ref).max() <= 1e-5
