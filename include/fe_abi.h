@@ -190,6 +190,52 @@ FE_API fe_status fe_kernel_stats(fe_problem* p, int32_t reset, int64_t* launches
 /* Release the handle (the workspace stays the caller's). */
 FE_API void fe_destroy(fe_problem* p);
 
+/* ---- Batches: many designs of one configuration in shared launches ----
+ * The serving form of the step (continuous batching of design solves).  A
+ * batch holds nslots problems of one configuration (multigrid; FE_PREC_FP64
+ * or FE_PREC_FP32_IR) in one caller workspace.  Their CG iterations run as
+ * one captured HIP graph whose every launch covers all slots (one slot per
+ * grid y index); a slot whose CG is stopped (empty, finished, or between
+ * refinement steps) costs an early exit, so designs join and leave a batch
+ * between replays while the others keep iterating.  Everything else of a
+ * slot (setup, solve start, float64 residuals, sensitivity, filter, OC) runs
+ * per slot on the batch's stream through the usual calls on its handle. */
+typedef struct fe_batch fe_batch;
+
+/* Bytes of device workspace for a batch of nslots (0 if cfg or nslots is
+ * invalid for a batch: 1 <= nslots <= 1024). */
+FE_API size_t fe_batch_workspace_size(const fe_config* cfg, int32_t nslots);
+
+/* Creates the batch on ws (device, 256-byte aligned, >= the size above; the
+ * caller keeps it alive until fe_batch_destroy) with every slot idle.  All
+ * work of the batch and its slots is ordered on `stream`.  Errors:
+ * FE_EINVAL, FE_ENOMEM (workspace too small), FE_EDEVICE. */
+FE_API fe_status fe_batch_create(const fe_config* cfg, int32_t nslots, void* ws, size_t ws_bytes,
+                          void* stream, fe_batch** out);
+
+/* (Re)initialises slot `slot` for a new design (supports `fixed`, load `f`,
+ * as for fe_setup; f = NULL: no load) and returns its handle, owned by the
+ * batch: valid until the slot is set up again or the batch is destroyed,
+ * never passed to fe_destroy.  Start its solve with fe_solve_begin; the
+ * batch's rounds advance it; fe_solve_step reports (without advancing)
+ * whether it finished; then fe_solve_end.  fe_solve and fe_set_mg_params are
+ * FE_EINVAL on a slot (the multigrid parameters are the library defaults).
+ * FE_EINVAL if the slot's previous solve is still running or a round is
+ * open. */
+FE_API fe_status fe_batch_setup_slot(fe_batch* b, int32_t slot, const uint8_t* fixed, const double* f,
+                              fe_problem** out);
+
+/* One round, in two halves so that several batches (on different streams)
+ * overlap: begin enqueues one replay of the batched CG chunk and the state
+ * copies; end waits for them and advances every running slot by one stage,
+ * returning the number of slots still running.  A slot that fails stops
+ * with its status in fe_solve_end; the first such status is also returned. */
+FE_API fe_status fe_batch_round_begin(fe_batch* b);
+FE_API fe_status fe_batch_round_end(fe_batch* b, int32_t* running);
+
+/* Releases the batch and its slots' handles (the workspace stays the caller's). */
+FE_API void fe_batch_destroy(fe_batch* b);
+
 /* Message of the last failure on this thread ("" if none). */
 FE_API const char* fe_last_error(void);
 

@@ -9,6 +9,7 @@
 #include <mutex>
 #include <new>
 #include <string>
+#include <type_traits>
 #include <utility>
 #include <vector>
 
@@ -259,7 +260,7 @@ hipError_t cg_iteration(fe_problem* p, T* x, T* r, T* pv, T* q, int it) {
     fz.pold = pold;
     fz.xout = pnew;
     fz.fold = part_region(p, PART_RZ);
-    fz.nfold = p->nrz;
+    fz.nfold = kxu_rz_partials<T>(p, 0);
     fz.part = part_region(p, PART_PQ);
     fz.no_finalize = true;
     fz.nblocks = &npq;
@@ -414,6 +415,7 @@ fe_status advance(fe_problem* p) {
     case ST_CG64: {
       const CgState hs = *p->h_st;
       if (!hs.done) {
+        if (p->in_batch) return FE_OK;  // the batch's next replay runs the chunk
         HIP_TRY(enqueue_chunk<double>(p, p->x64, p->r64, p->p64, p->q64));
         return copy_state(p);
       }
@@ -455,6 +457,7 @@ fe_status advance(fe_problem* p) {
     case ST_IR_CG: {
       const CgState hs = *p->h_st;
       if (!hs.done) {
+        if (p->in_batch) return FE_OK;  // the batch's next replay runs the chunk
         HIP_TRY(enqueue_chunk<float>(p, p->x32, p->r32, p->p32, p->q32));
         return copy_state(p);
       }
@@ -767,6 +770,10 @@ extern "C" fe_status fe_apply_K(fe_problem* p, const double* rho, const double* 
 extern "C" fe_status fe_solve(fe_problem* p, const double* rho, double* u, double rtol, int32_t max_iters,
                               fe_solve_info* info) {
   CHECK_HANDLE(p);
+  if (p->in_batch) {
+    fe_set_error("a batch slot solves through fe_solve_begin and the batch's rounds");
+    return FE_EINVAL;
+  }
   if (info) std::memset(info, 0, sizeof(*info));
   fe_status s = solve_begin(p, rho, u, rtol, max_iters);
   if (s != FE_OK) return s;
@@ -787,6 +794,10 @@ extern "C" fe_status fe_solve_step(fe_problem* p, int32_t* done) {
   if (!done) {
     fe_set_error("done must not be NULL");
     return FE_EINVAL;
+  }
+  if (p->in_batch) {  // the batch's rounds advance it
+    *done = p->sc.stage == ST_DONE;
+    return FE_OK;
   }
   int d = 0;
   fe_status s = solve_step(p, 0, &d);
@@ -844,6 +855,10 @@ extern "C" fe_status oc_update(fe_problem* p, const double* x, const double* dcx
 extern "C" fe_status fe_set_mg_params(fe_problem* p, int32_t nu, int32_t coarse_sweeps, double omega,
                                       double coarse_ratio) {
   CHECK_HANDLE(p);
+  if (p->in_batch) {
+    fe_set_error("batch slots share the batch's multigrid parameters (the library defaults)");
+    return FE_EINVAL;
+  }
   if (nu < 1 || nu > 8 || coarse_sweeps < 1 || coarse_sweeps > 10000 || !(omega > 0.0 && omega < 1.0) ||
       !(coarse_ratio >= 2.0 && coarse_ratio <= 1e12)) {
     fe_set_error("need 1 <= nu <= 8, 1 <= coarse_sweeps <= 10000, 0 < omega < 1, 2 <= coarse_ratio <= 1e12");
@@ -911,4 +926,259 @@ extern "C" void fe_destroy(fe_problem* p) {
   if (p->h_st) (void)hipHostFree(p->h_st);
   if (p->h_scal) (void)hipHostFree(p->h_scal);
   delete p;
+}
+
+// ------------------------------------------------------------------ batches
+// A batch holds nslots problems of one configuration in one workspace, slot
+// s at byte s * stride; their CG chunks run as one captured graph whose
+// kernels take one problem per grid y index (pointers moved by the stride).
+// A slot whose CG is stopped (idle, finished, or in another stage) turns
+// every workgroup of its y index into an early exit, so problems join and
+// leave between replays.
+struct fe_batch {
+  fe_config cfg;
+  int nslots = 0;
+  size_t stride = 0;
+  char* ws = nullptr;
+  double* zero_f = nullptr;  // zero load of the idle slots
+  size_t st_off = 0;         // offset of the CG state inside a slot
+  hipStream_t stream = nullptr;
+  std::vector<fe_problem*> slot;
+  hipGraphExec_t chunk = nullptr;
+  hipEvent_t ev = nullptr;
+  bool open = false;  // a round was begun and not yet ended
+};
+
+namespace {
+
+std::string batch_validate(const fe_config* cfg, int nslots) {
+  const std::string why = validate(cfg);
+  if (!why.empty()) return why;
+  if (nslots < 1 || nslots > 1024) return "nslots must lie in [1, 1024]";
+  if (cfg->precond != FE_PRECOND_GMG) return "batches need the multigrid preconditioner";
+  if (cfg->precision != FE_PREC_FP64 && cfg->precision != FE_PREC_FP32_IR)
+    return "batches run FE_PREC_FP64 or FE_PREC_FP32_IR";
+  return "";
+}
+
+size_t batch_stride(const fe_config* cfg) { return align_up(layout(cfg, nullptr, nullptr)); }
+
+size_t batch_zero_bytes(const fe_config* cfg) {
+  return align_up((size_t)3 * (cfg->nx + 1) * (cfg->ny + 1) * (cfg->nz + 1) * sizeof(double));
+}
+
+// Stops the CG state at slot s (its workgroups exit at once in a replay).
+fe_status batch_stop_slot(fe_batch* b, int s) {
+  CgState cs;
+  std::memset(&cs, 0, sizeof(cs));
+  cs.done = 1;
+  cs.status = FE_OK;
+  HIP_TRY(hipMemcpyAsync(b->ws + (size_t)s * b->stride + b->st_off, &cs, sizeof(cs), hipMemcpyHostToDevice,
+                         b->stream));
+  HIP_TRY(hipStreamSynchronize(b->stream));  // the source is on this stack
+  return FE_OK;
+}
+
+template <typename T>
+fe_status batch_capture(fe_batch* b) {
+  fe_problem* t = b->slot[0];
+  T *x, *r, *pv, *q;
+  if (std::is_same<T, double>::value) {
+    x = reinterpret_cast<T*>(t->x64);
+    r = reinterpret_cast<T*>(t->r64);
+    pv = reinterpret_cast<T*>(t->p64);
+    q = reinterpret_cast<T*>(t->q64);
+  } else {
+    x = reinterpret_cast<T*>(t->x32);
+    r = reinterpret_cast<T*>(t->r32);
+    pv = reinterpret_cast<T*>(t->p32);
+    q = reinterpret_cast<T*>(t->q32);
+  }
+  const bool prof = t->kst.on;
+  t->kst.on = false;
+  t->bcount = b->nslots;
+  t->bstride = (int64_t)b->stride;
+  hipStream_t saved = t->stream;
+  t->stream = t->cap_stream;
+  hipError_t e = hipStreamBeginCapture(t->cap_stream, hipStreamCaptureModeRelaxed);
+  for (int it = 0; it < kChunkMG && e == hipSuccess; ++it) e = cg_iteration<T>(t, x, r, pv, q, it);
+  hipGraph_t graph = nullptr;
+  const hipError_t e2 = hipStreamEndCapture(t->cap_stream, &graph);
+  t->stream = saved;
+  t->bcount = 1;
+  t->bstride = 0;
+  t->kst.on = prof;
+  if (e == hipSuccess && e2 == hipSuccess && graph) e = hipGraphInstantiate(&b->chunk, graph, nullptr, nullptr, 0);
+  else if (e == hipSuccess) e = e2;
+  if (graph) (void)hipGraphDestroy(graph);
+  if (e != hipSuccess || !b->chunk) {
+    (void)hipGetLastError();
+    b->chunk = nullptr;
+    fe_set_error(std::string("batch chunk capture: ") + hipGetErrorString(e));
+    return FE_EDEVICE;
+  }
+  return FE_OK;
+}
+
+bool in_cg_stage(const fe_problem* h) { return h && (h->sc.stage == ST_CG64 || h->sc.stage == ST_IR_CG); }
+
+}  // namespace
+
+extern "C" size_t fe_batch_workspace_size(const fe_config* cfg, int32_t nslots) {
+  if (!batch_validate(cfg, nslots).empty()) return 0;
+  return (size_t)nslots * batch_stride(cfg) + batch_zero_bytes(cfg);
+}
+
+extern "C" fe_status fe_batch_create(const fe_config* cfg, int32_t nslots, void* ws, size_t ws_bytes,
+                                     void* stream, fe_batch** out) {
+  if (!out) {
+    fe_set_error("out is NULL");
+    return FE_EINVAL;
+  }
+  *out = nullptr;
+  const std::string why = batch_validate(cfg, nslots);
+  if (!why.empty()) {
+    fe_set_error(why);
+    return FE_EINVAL;
+  }
+  if (!ws || ((uintptr_t)ws) % kAlign) {
+    fe_set_error("ws must be a 256-byte aligned device pointer");
+    return FE_EINVAL;
+  }
+  const size_t need = fe_batch_workspace_size(cfg, nslots);
+  if (ws_bytes < need) {
+    fe_set_error("batch workspace too small: need " + std::to_string(need) + " bytes");
+    return FE_ENOMEM;
+  }
+  fe_batch* b = new (std::nothrow) fe_batch();
+  if (!b) {
+    fe_set_error("out of host memory");
+    return FE_ENOMEM;
+  }
+  b->cfg = *cfg;
+  b->nslots = nslots;
+  b->stride = batch_stride(cfg);
+  b->ws = static_cast<char*>(ws);
+  b->zero_f = reinterpret_cast<double*>(b->ws + (size_t)nslots * b->stride);
+  b->stream = (hipStream_t)stream;
+  b->slot.assign(nslots, nullptr);
+  auto fail = [&](fe_status st) {
+    fe_batch_destroy(b);
+    return st;
+  };
+  hipError_t e = hipMemsetAsync(b->zero_f, 0, batch_zero_bytes(cfg), b->stream);
+  if (e == hipSuccess) e = hipEventCreateWithFlags(&b->ev, hipEventDisableTiming);
+  if (e != hipSuccess) {
+    fe_set_error(std::string("batch setup: ") + hipGetErrorString(e));
+    return fail(FE_EDEVICE);
+  }
+  for (int s = 0; s < nslots; ++s) {
+    fe_problem* h = nullptr;
+    const fe_status st = fe_setup(cfg, nullptr, b->zero_f, b->ws + (size_t)s * b->stride, b->stride, stream, &h);
+    if (st != FE_OK) return fail(st);
+    h->in_batch = true;
+    b->slot[s] = h;
+    if (s == 0) b->st_off = (size_t)(reinterpret_cast<char*>(h->st) - b->ws);
+    const fe_status ss = batch_stop_slot(b, s);
+    if (ss != FE_OK) return fail(ss);
+  }
+  *out = b;
+  return FE_OK;
+}
+
+extern "C" fe_status fe_batch_setup_slot(fe_batch* b, int32_t slot, const uint8_t* fixed, const double* f,
+                                         fe_problem** out) {
+  if (!b || !out || slot < 0 || slot >= b->nslots) {
+    fe_set_error("invalid batch, slot or out");
+    return FE_EINVAL;
+  }
+  *out = nullptr;
+  if (b->open) {
+    fe_set_error("end the open round before setting up a slot");
+    return FE_EINVAL;
+  }
+  fe_problem* old = b->slot[slot];
+  if (old && old->sc.stage != ST_DONE) {
+    fe_set_error("the slot's solve is still running");
+    return FE_EINVAL;
+  }
+  if (old) fe_destroy(old);
+  b->slot[slot] = nullptr;
+  fe_problem* h = nullptr;
+  fe_status st = fe_setup(&b->cfg, fixed, f ? f : b->zero_f, b->ws + (size_t)slot * b->stride, b->stride,
+                          b->stream, &h);
+  if (st != FE_OK) {
+    (void)batch_stop_slot(b, slot);  // the region keeps a stopped state for the replays
+    return st;
+  }
+  h->in_batch = true;
+  b->slot[slot] = h;
+  st = batch_stop_slot(b, slot);  // until its solve begins
+  if (st != FE_OK) return st;
+  *out = h;
+  return FE_OK;
+}
+
+extern "C" fe_status fe_batch_round_begin(fe_batch* b) {
+  if (!b) {
+    fe_set_error("batch is NULL");
+    return FE_EINVAL;
+  }
+  if (b->open) {
+    fe_set_error("a round is already open");
+    return FE_EINVAL;
+  }
+  bool any = false;
+  for (fe_problem* h : b->slot) any = any || in_cg_stage(h);
+  if (any) {
+    if (!b->slot[0]) {
+      fe_set_error("slot 0 has no problem");
+      return FE_EINVAL;
+    }
+    if (!b->chunk) {
+      const fe_status st = b->cfg.precision == FE_PREC_FP64 ? batch_capture<double>(b) : batch_capture<float>(b);
+      if (st != FE_OK) return st;
+    }
+    HIP_TRY(hipGraphLaunch(b->chunk, b->stream));
+    for (fe_problem* h : b->slot)
+      if (in_cg_stage(h))
+        HIP_TRY(hipMemcpyAsync(h->h_st, h->st, sizeof(CgState), hipMemcpyDeviceToHost, b->stream));
+  }
+  HIP_TRY(hipEventRecord(b->ev, b->stream));
+  b->open = true;
+  return FE_OK;
+}
+
+extern "C" fe_status fe_batch_round_end(fe_batch* b, int32_t* running) {
+  if (!b || !b->open) {
+    fe_set_error("no open round");
+    return FE_EINVAL;
+  }
+  b->open = false;
+  HIP_TRY(hipEventSynchronize(b->ev));
+  fe_status first_err = FE_OK;
+  int n = 0;
+  for (fe_problem* h : b->slot) {
+    if (!h || h->sc.stage == ST_DONE) continue;
+    const fe_status st = advance(h);
+    if (st != FE_OK) {
+      h->sc.stage = ST_DONE;
+      h->sc.result = st;
+      if (first_err == FE_OK) first_err = st;
+      continue;
+    }
+    if (h->sc.stage != ST_DONE) ++n;
+  }
+  if (running) *running = n;
+  return first_err;
+}
+
+extern "C" void fe_batch_destroy(fe_batch* b) {
+  if (!b) return;
+  if (b->stream) (void)hipStreamSynchronize(b->stream);
+  for (fe_problem* h : b->slot)
+    if (h) fe_destroy(h);
+  if (b->chunk) (void)hipGraphExecDestroy(b->chunk);
+  if (b->ev) (void)hipEventDestroy(b->ev);
+  delete b;
 }

@@ -141,7 +141,7 @@ struct fe_problem {
   double* partials = nullptr;  // 4 regions of part_stride doubles (see part_region)
   int64_t part_stride = 0;     // doubles per CG region
   int64_t part_gen = 0;        // doubles of the general region
-  int nrz = 0;                 // partials the last level-0 post-smoothing sweep left
+
   CgState* st = nullptr;       // device state (two instances: [0] inner, [1] aux)
   double* scal = nullptr;      // 64 device scalars for small results
   double* oc = nullptr;        // OC search state
@@ -155,6 +155,7 @@ struct fe_problem {
   GraphChunk chunk64, chunk32;
   GraphChunk* last_replay = nullptr;  // profiled graph replayed since the last harvest
   bool use_graphs = true;
+  bool in_batch = false;  // a slot of an fe_batch: its CG chunks run in the batch's replays
   int mfma_l0 = 0;  // finest-grid float32 K*u: 0 vector ALUs, 1 bf16, 2 split-bf16 matrix cores
   double* x64 = nullptr;        // float64 iterate of the solve (graphs need fixed pointers)
   double ff = 0.0;              // ||f||^2
@@ -167,7 +168,21 @@ struct fe_problem {
   double cheb_ratio = 5000.0;  // coarse Chebyshev interval [lam_max / ratio, lam_max]
 
   KStats kst;
+
+  // batched launches: while bcount > 1 (a batch's captured CG chunk) every
+  // kernel of the chunk runs bcount problems, one per grid y index, whose
+  // workspaces lie bstride bytes apart (this problem's is the first)
+  int bcount = 1;
+  int64_t bstride = 0;
 };
+
+// Byte offset of this workgroup's problem in a batched launch, and a pointer
+// moved by it (null stays null).
+__device__ inline int64_t batch_offset(int64_t wsh) { return (int64_t)blockIdx.y * wsh; }
+template <typename P>
+__device__ inline P* wshift(P* ptr, int64_t off) {
+  return ptr ? reinterpret_cast<P*>(reinterpret_cast<uintptr_t>(ptr) + off) : ptr;
+}
 
 // Partial-sum regions.  Multigrid CG hands each reduction to the next kernel
 // (which sums the partials itself), so producer and consumer must not share
@@ -242,6 +257,9 @@ hipError_t launch_kxu_tile(fe_problem* p, int lev, const T* x, const T* E, T* y,
                            const T* invd = nullptr, double omega = 0.0,
                            const ChebStep<T>* cs = nullptr, const TileFuse<T>* fz = nullptr);
 int64_t kxu_tile_blocks(const Grid& g);
+// Number of r^T z partials the level's last smoothing sweep (mode 5) leaves.
+template <typename T>
+int kxu_rz_partials(const fe_problem* p, int lev);
 // Node-centric dense-Ke reference kernel (float64), kept as a second implementation.
 hipError_t launch_kxu_dense64(fe_problem* p, const double* x, double* y);
 
@@ -249,7 +267,8 @@ hipError_t launch_kxu_dense64(fe_problem* p, const double* x, double* y);
 // null) skips the launches once CG stopped.
 // rz: what the last level-0 sweep does with r^T z -- RZ_NONE nothing,
 // RZ_FINISH rz and beta into st (one-workgroup finalize), RZ_PARTIALS leave
-// the partials in PART_RZ (count in p->nrz) for the next direction kernel.
+// the partials in PART_RZ (kxu_rz_partials of them) for the next direction
+// kernel.
 // With fold_rr > 0 the first level-0 kernel also takes the convergence
 // decision of the CG update from the fold_rr r^T r partials in PART_RR.
 enum { RZ_NONE = 0, RZ_FINISH = 1, RZ_PARTIALS = 2 };

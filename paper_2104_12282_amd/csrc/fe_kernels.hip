@@ -229,7 +229,17 @@ __global__ void __launch_bounds__(FE_BLOCK) cg_update_mg_kernel(Grid g, T* __res
                                                                 const T* __restrict__ p,
                                                                 const T* __restrict__ q, CgState* st,
                                                                 const double* __restrict__ pq_part, int npq,
-                                                                double* partials) {
+                                                                double* partials, int64_t wsh) {
+  if (wsh) {  // batched launch: this workgroup's problem
+    const int64_t o = batch_offset(wsh);
+    x = wshift(x, o);
+    r = wshift(r, o);
+    p = wshift(p, o);
+    q = wshift(q, o);
+    st = wshift(st, o);
+    pq_part = wshift(pq_part, o);
+    partials = wshift(partials, o);
+  }
   if (st->done) return;
   __shared__ double sh[FE_BLOCK / 64];
   __shared__ double tot;
@@ -855,8 +865,9 @@ hipError_t launch_cg_update_mg(fe_problem* p, T* x, T* r, const T* pvec, const T
   const Grid g = G(p, 0);
   int nb = red_grid(g.ndof);
   if (nb > kUpdateMgGrid) nb = kUpdateMgGrid;
-  hipLaunchKernelGGL(cg_update_mg_kernel<T>, dim3(nb), dim3(FE_BLOCK), 0, p->stream, g, x, r, pvec, q, st,
-                     part_region(p, PART_PQ), npq, part_region(p, PART_RR));
+  hipLaunchKernelGGL(cg_update_mg_kernel<T>, dim3(nb, p->bcount), dim3(FE_BLOCK), 0, p->stream, g, x, r, pvec, q,
+                     st, part_region(p, PART_PQ), npq, part_region(p, PART_RR),
+                     p->bcount > 1 ? p->bstride : (int64_t)0);
   *nrr = nb;
   return hipGetLastError();
 }

@@ -205,7 +205,28 @@ __global__ void __launch_bounds__(TX* TY, FE_KXU_MIN_WAVES) kxu_tile_kernel(Grid
                                                          const uint8_t* __restrict__ nmask, WK<T> wk,
                                                          T* __restrict__ y, Epi<T> ep, CgState* st,
                                                          double* partials, double* out,
-                                                         const T* __restrict__ zpad, XinK<T> xi, FoldK fo) {
+                                                         const T* __restrict__ zpad, XinK<T> xi, FoldK fo,
+                                                         int64_t wsh) {
+  if (wsh) {  // batched launch: this workgroup's problem
+    const int64_t o = batch_offset(wsh);
+    x = wshift(x, o);
+    E = wshift(E, o);
+    nmask = wshift(nmask, o);
+    y = wshift(y, o);
+    ep.b64 = wshift(ep.b64, o);
+    ep.bT = wshift(ep.bT, o);
+    ep.invd = wshift(ep.invd, o);
+    ep.res = wshift(ep.res, o);
+    ep.acc = wshift(ep.acc, o);
+    st = wshift(st, o);
+    partials = wshift(partials, o);
+    out = wshift(out, o);
+    zpad = wshift(zpad, o);
+    xi.invd = wshift(xi.invd, o);
+    xi.pold = wshift(xi.pold, o);
+    xi.xout = wshift(xi.xout, o);
+    fo.part = wshift(fo.part, o);
+  }
   if ((MODE == 1 || MODE == 5 || st) && st->done) return;
   // folded reductions: every workgroup sums the same partials in the same
   // order, so all take the same decision; workgroup 0 records it in st
@@ -768,11 +789,11 @@ int64_t kxu_tile_blocks(const Grid& g) {
 template <typename T, int MODE, int XIN>
 static int launch_tile(hipStream_t stream, const Grid& g, const T* x, const T* E, const uint8_t* nm,
                        const WK<T>& wk, T* y, const Epi<T>& ep, CgState* st, double* partials, double* out,
-                       const T* zpad, const XinK<T>& xi, const FoldK& fo) {
+                       const T* zpad, const XinK<T>& xi, const FoldK& fo, int bcount, int64_t bstride) {
   const void* k = reinterpret_cast<const void*>(&kxu_tile_kernel<T, MODE, XIN>);
   const TileMap tm = kxu_tile_map(g, kxu_slots(k));
-  hipLaunchKernelGGL((kxu_tile_kernel<T, MODE, XIN>), dim3(tm.nblk), dim3(TX * TY), 0, stream, g, tm, x, E, nm,
-                     wk, y, ep, st, partials, out, zpad, xi, fo);
+  hipLaunchKernelGGL((kxu_tile_kernel<T, MODE, XIN>), dim3(tm.nblk, bcount), dim3(TX * TY), 0, stream, g, tm, x,
+                     E, nm, wk, y, ep, st, partials, out, zpad, xi, fo, bcount > 1 ? bstride : (int64_t)0);
   return tm.nblk;
 }
 
@@ -799,6 +820,16 @@ static int launch_mfma(int mode, hipStream_t stream, const Grid& g, const float*
     default: return launch_mfma_mode<0, SPLIT>(stream, g, x, E, nm, ke, ks, y, ef, st, partials);
   }
 }
+
+// Workgroups of the level-`lev` launch of the last smoothing sweep with
+// r^T z (mode 5, plain operand): the count of r^T z partials it leaves.
+template <typename T>
+int kxu_rz_partials(const fe_problem* p, int lev) {
+  const void* k = reinterpret_cast<const void*>(&kxu_tile_kernel<T, 5, 0>);
+  return kxu_tile_map(p->L[lev].g, kxu_slots(k)).nblk;
+}
+template int kxu_rz_partials<double>(const fe_problem*, int);
+template int kxu_rz_partials<float>(const fe_problem*, int);
 
 template <typename T>
 hipError_t launch_kxu_tile(fe_problem* p, int lev, const T* x, const T* E, T* y, CgState* st, int mode,
@@ -836,6 +867,7 @@ hipError_t launch_kxu_tile(fe_problem* p, int lev, const T* x, const T* E, T* y,
   int nb = 0;
   double* pt = (fz && fz->part) ? fz->part : p->partials;
   const bool fused = fz && (fz->xin != 0 || fz->fold);  // the matrix-core kernel has no fused operand
+  if (p->bcount > 1 && (p->mfma_l0 || (lev == 0 && p->kst.on))) return hipErrorInvalidValue;  // not batched
   if (std::is_same<T, float>::value && lev == 0 && p->mfma_l0 && mode != 2 && mode != 6 && !fused) {
     Epi<float> ef;
     ef.b64 = b64;
@@ -864,7 +896,8 @@ hipError_t launch_kxu_tile(fe_problem* p, int lev, const T* x, const T* E, T* y,
     fo.n = fz ? fz->nfold : 0;
     fo.what = (fz && fz->fold) ? (fz->fold_rr ? 2 : 1) : 0;
     const int xin = fz ? fz->xin : 0;
-#define FE_TILE(M, X) launch_tile<T, M, X>(p->stream, g, x, E, nm, wk, y, ep, st, pt, out, zp, xi, fo)
+#define FE_TILE(M, X) \
+  launch_tile<T, M, X>(p->stream, g, x, E, nm, wk, y, ep, st, pt, out, zp, xi, fo, p->bcount, p->bstride)
     switch (mode * 4 + xin) {
       case 1 * 4: nb = FE_TILE(1, 0); break;
       case 1 * 4 + 2: nb = FE_TILE(1, 2); break;

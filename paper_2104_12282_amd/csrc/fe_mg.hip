@@ -10,6 +10,8 @@
 
 namespace {
 
+inline int64_t wsh_of(const fe_problem* p) { return p->bcount > 1 ? p->bstride : 0; }
+
 inline int nblocks(int64_t n) {
   int64_t g = (n + FE_BLOCK - 1) / FE_BLOCK;
   return (int)(g < 1 ? 1 : g);
@@ -20,7 +22,14 @@ inline int nblocks(int64_t n) {
 template <typename T>
 __global__ void __launch_bounds__(FE_BLOCK) jacobi0_kernel(int64_t ndof, const T* __restrict__ r,
                                                            const T* __restrict__ invd, T omega,
-                                                           T* __restrict__ z, const CgState* st) {
+                                                           T* __restrict__ z, const CgState* st, int64_t wsh) {
+  if (wsh) {  // batched launch: this workgroup's problem
+    const int64_t o = batch_offset(wsh);
+    r = wshift(r, o);
+    invd = wshift(invd, o);
+    z = wshift(z, o);
+    st = wshift(st, o);
+  }
   if (st && st->done) return;
   const int64_t d = blockIdx.x * (int64_t)FE_BLOCK + threadIdx.x;
   if (d < ndof) z[d] = omega * invd[d / 3] * r[d];
@@ -31,7 +40,14 @@ __global__ void __launch_bounds__(FE_BLOCK) jacobi0_kernel(int64_t ndof, const T
 template <typename T>
 __global__ void __launch_bounds__(FE_BLOCK) restrict_kernel(Grid fg, Grid cg, const T* __restrict__ tf,
                                                             const uint8_t* __restrict__ cmask,
-                                                            T* __restrict__ rc, const CgState* st) {
+                                                            T* __restrict__ rc, const CgState* st, int64_t wsh) {
+  if (wsh) {  // batched launch: this workgroup's problem
+    const int64_t o = batch_offset(wsh);
+    tf = wshift(tf, o);
+    cmask = wshift(cmask, o);
+    rc = wshift(rc, o);
+    st = wshift(st, o);
+  }
   if (st && st->done) return;
   const int64_t n = blockIdx.x * (int64_t)FE_BLOCK + threadIdx.x;
   if (n >= cg.nnode) return;
@@ -68,7 +84,15 @@ template <typename T>
 __global__ void __launch_bounds__(FE_BLOCK) prolong_add_kernel(Grid fg, Grid cg, const T* zf,
                                                                const T* __restrict__ zc,
                                                                const uint8_t* __restrict__ fmask, T* out,
-                                                               const CgState* st) {
+                                                               const CgState* st, int64_t wsh) {
+  if (wsh) {  // batched launch: this workgroup's problem
+    const int64_t o = batch_offset(wsh);
+    zf = wshift(zf, o);
+    zc = wshift(zc, o);
+    fmask = wshift(fmask, o);
+    out = wshift(out, o);
+    st = wshift(st, o);
+  }
   if (st && st->done) return;
   const int64_t n = blockIdx.x * (int64_t)FE_BLOCK + threadIdx.x;
   if (n >= fg.nnode) return;
@@ -128,8 +152,8 @@ hipError_t presmooth(fe_problem* p, int l, const T* r, T* z, T* t, int n, CgStat
   if (!fuse) {
     T* a = (n % 2) ? z : t;  // first target chosen so the last sweep lands in z
     T* b = (n % 2) ? t : z;
-    hipLaunchKernelGGL(jacobi0_kernel<T>, dim3(nblocks(L.g.ndof)), dim3(FE_BLOCK), 0, p->stream, L.g.ndof, r,
-                       lev_invd<T>(L), (T)om, a, st);
+    hipLaunchKernelGGL(jacobi0_kernel<T>, dim3(nblocks(L.g.ndof), p->bcount), dim3(FE_BLOCK), 0, p->stream,
+                       L.g.ndof, r, lev_invd<T>(L), (T)om, a, st, wsh_of(p));
     e = hipGetLastError();
     for (int s = 1; s < n && e == hipSuccess; ++s) {
       e = launch_kxu_tile<T>(p, l, a, lev_E<T>(L), b, st, 3, nullptr, nullptr, r, lev_invd<T>(L), om);
@@ -175,8 +199,8 @@ hipError_t chebyshev_solve(fe_problem* p, int l, T* r, T* z, T* d0, T* d1, int d
   const double theta = 0.5 * (b + a), delta = 0.5 * (b - a), sigma = theta / delta;
   double rho = 1.0 / sigma;
   // d0 = D^-1 r / theta
-  hipLaunchKernelGGL(jacobi0_kernel<T>, dim3(nblocks(L.g.ndof)), dim3(FE_BLOCK), 0, p->stream, L.g.ndof, r,
-                     lev_invd<T>(L), (T)(1.0 / theta), d0, st);
+  hipLaunchKernelGGL(jacobi0_kernel<T>, dim3(nblocks(L.g.ndof), p->bcount), dim3(FE_BLOCK), 0, p->stream,
+                     L.g.ndof, r, lev_invd<T>(L), (T)(1.0 / theta), d0, st, wsh_of(p));
   hipError_t e = hipGetLastError();
   for (int k = 0; k < deg && e == hipSuccess; ++k) {
     const double rho_new = 1.0 / (2.0 * sigma - rho);
@@ -213,15 +237,15 @@ hipError_t launch_vcycle(fe_problem* p, int l, const T* r, T* z, CgState* st, in
   const Level& C = p->L[l + 1];
   T* rc = static_cast<T*>(C.mg_r);
   T* zc = static_cast<T*>(C.mg_z);
-  hipLaunchKernelGGL(restrict_kernel<T>, dim3(nblocks(C.g.nnode)), dim3(FE_BLOCK), 0, p->stream, L.g, C.g, t,
-                     C.nmask, rc, st);
+  hipLaunchKernelGGL(restrict_kernel<T>, dim3(nblocks(C.g.nnode), p->bcount), dim3(FE_BLOCK), 0, p->stream, L.g,
+                     C.g, t, C.nmask, rc, st, wsh_of(p));
   if ((e = hipGetLastError()) != hipSuccess) return e;
   if ((e = launch_vcycle<T>(p, l + 1, rc, zc, st, RZ_NONE, 0)) != hipSuccess) return e;
   // post-smoothing, arranged so the last sweep writes z
   const int nu = p->mg_nu;
   T* a = (nu % 2) ? t : z;
-  hipLaunchKernelGGL(prolong_add_kernel<T>, dim3(nblocks(L.g.nnode)), dim3(FE_BLOCK), 0, p->stream, L.g, C.g,
-                     z, zc, L.nmask, a, st);
+  hipLaunchKernelGGL(prolong_add_kernel<T>, dim3(nblocks(L.g.nnode), p->bcount), dim3(FE_BLOCK), 0, p->stream,
+                     L.g, C.g, z, zc, L.nmask, a, st, wsh_of(p));
   if ((e = hipGetLastError()) != hipSuccess) return e;
   T* b = (a == t) ? z : t;
   for (int s = 0; s < nu; ++s) {
@@ -230,7 +254,6 @@ hipError_t launch_vcycle(fe_problem* p, int l, const T* r, T* z, CgState* st, in
     if (last && rz == RZ_PARTIALS) {
       fz.part = part_region(p, PART_RZ);
       fz.no_finalize = true;
-      fz.nblocks = &p->nrz;
     }
     e = launch_kxu_tile<T>(p, l, a, lev_E<T>(L), b, st, last ? 5 : 3, nullptr, nullptr, r, lev_invd<T>(L),
                            p->mg_omega, nullptr, (last && rz == RZ_PARTIALS) ? &fz : nullptr);

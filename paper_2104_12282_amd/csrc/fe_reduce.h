@@ -25,11 +25,11 @@ __device__ inline double wave_max(double v) {
   return v;
 }
 
-// Linear index and count of the workgroups of a (possibly 3-D) grid.
-__device__ inline uint32_t block_id() {
-  return blockIdx.x + gridDim.x * (blockIdx.y + gridDim.y * blockIdx.z);
-}
-__device__ inline uint32_t block_count() { return gridDim.x * gridDim.y * gridDim.z; }
+// Index and count of the workgroups of one problem: the x dimension of the
+// grid (a batched launch runs one problem per y index, each with its own
+// partials).
+__device__ inline uint32_t block_id() { return blockIdx.x; }
+__device__ inline uint32_t block_count() { return gridDim.x; }
 
 // Sum of v[0..NV) over the workgroup (FE_BLOCK threads); totals valid in
 // thread 0.  Every thread of the workgroup must call it.

@@ -25,7 +25,8 @@ STATUS_NAME = {0: "FE_OK", -1: "FE_EINVAL", -2: "FE_ENOMEM", -3: "FE_EDEVICE",
 ABI_SYMBOLS = ("fe_workspace_size", "fe_setup", "fe_apply_K", "fe_solve", "fe_solve_begin",
                "fe_solve_step", "fe_solve_end", "fe_sensitivity",
                "fe_filter", "oc_update", "fe_set_mg_params", "fe_set_profiling", "fe_kernel_stats",
-               "fe_destroy", "fe_last_error")
+               "fe_destroy", "fe_batch_workspace_size", "fe_batch_create", "fe_batch_setup_slot",
+               "fe_batch_round_begin", "fe_batch_round_end", "fe_batch_destroy", "fe_last_error")
 
 
 class FEError(RuntimeError):
@@ -76,11 +77,20 @@ def load_library() -> C.CDLL:
     lib.fe_kernel_stats.argtypes = [P, I32, C.POINTER(I64), C.POINTER(D), C.POINTER(D)]
     lib.fe_destroy.argtypes = [P]
     lib.fe_destroy.restype = None
+    lib.fe_batch_workspace_size.argtypes = [C.POINTER(fe_config), I32]
+    lib.fe_batch_workspace_size.restype = C.c_size_t
+    lib.fe_batch_create.argtypes = [C.POINTER(fe_config), I32, P, C.c_size_t, P, C.POINTER(P)]
+    lib.fe_batch_setup_slot.argtypes = [P, I32, P, P, C.POINTER(P)]
+    lib.fe_batch_round_begin.argtypes = [P]
+    lib.fe_batch_round_end.argtypes = [P, C.POINTER(I32)]
+    lib.fe_batch_destroy.argtypes = [P]
+    lib.fe_batch_destroy.restype = None
     lib.fe_last_error.argtypes = []
     lib.fe_last_error.restype = C.c_char_p
     for name in ("fe_setup", "fe_apply_K", "fe_solve", "fe_solve_begin", "fe_solve_step",
                  "fe_solve_end", "fe_sensitivity", "fe_filter",
-                 "oc_update", "fe_set_mg_params", "fe_set_profiling", "fe_kernel_stats"):
+                 "oc_update", "fe_set_mg_params", "fe_set_profiling", "fe_kernel_stats",
+                 "fe_batch_create", "fe_batch_setup_slot", "fe_batch_round_begin", "fe_batch_round_end"):
         getattr(lib, name).restype = C.c_int
     _lib = lib
     return lib
@@ -138,6 +148,21 @@ class Problem:
                                 C.c_void_p(self.ws.data_ptr()), self.ws_bytes,
                                 C.c_void_p(self.stream.cuda_stream), C.byref(h)))
         self._h = h
+        self._owned = True
+
+    @classmethod
+    def _slot(cls, batch, handle, f, fixed):
+        """A batch slot's problem: the handle belongs to the batch."""
+        self = cls.__new__(cls)
+        self.nx, self.ny, self.nz = batch.nx, batch.ny, batch.nz
+        self.nelem = batch.nx * batch.ny * batch.nz
+        self.ndof = 3 * (batch.nx + 1) * (batch.ny + 1) * (batch.nz + 1)
+        self.cfg, self.device, self.stream = batch.cfg, batch.device, batch.stream
+        self.ws, self.ws_bytes = batch.ws, batch.ws_bytes
+        self.f, self.fixed = f, fixed
+        self._h = handle
+        self._owned = False
+        return self
 
     # -- helpers -----------------------------------------------------------
     def _vec(self, n):
@@ -145,7 +170,8 @@ class Problem:
 
     def close(self):
         if getattr(self, "_h", None):
-            load_library().fe_destroy(self._h)
+            if getattr(self, "_owned", True):
+                load_library().fe_destroy(self._h)
             self._h = None
 
     def __del__(self):
@@ -221,3 +247,68 @@ class Problem:
         _check(load_library().fe_kernel_stats(self._h, 1 if reset else 0, C.byref(n), C.byref(ms),
                                               C.byref(b)))
         return {"launches": n.value, "total_ms": ms.value, "bytes_per_launch": b.value}
+
+
+class Batch:
+    """nslots designs of one configuration whose CG iterations share launches
+    (include/fe_abi.h, fe_batch_*): slots are set up for new designs, their
+    solves started with Problem.solve_begin, and advanced by rounds."""
+
+    def __init__(self, nx, ny, nz, nslots, *, device="cuda:0", stream: torch.cuda.Stream | None = None,
+                 **cfg_kw):
+        lib = load_library()
+        self.nx, self.ny, self.nz, self.nslots = nx, ny, nz, nslots
+        cfg_kw.setdefault("precond", "gmg")
+        self.cfg = make_config(nx, ny, nz, **cfg_kw)
+        self.device = torch.device(device)
+        self.stream = stream if stream is not None else torch.cuda.current_stream(self.device)
+        self.ws_bytes = int(lib.fe_batch_workspace_size(C.byref(self.cfg), nslots)) or 256
+        self.ws = torch.empty(self.ws_bytes, dtype=torch.uint8, device=self.device)
+        h = C.c_void_p()
+        with torch.cuda.stream(self.stream):
+            _check(lib.fe_batch_create(C.byref(self.cfg), nslots, C.c_void_p(self.ws.data_ptr()), self.ws_bytes,
+                                       C.c_void_p(self.stream.cuda_stream), C.byref(h)))
+        self._b = h
+        self.slots = [None] * nslots
+
+    @staticmethod
+    def workspace_bytes(nx, ny, nz, nslots, **cfg_kw) -> int:
+        cfg_kw.setdefault("precond", "gmg")
+        cfg = make_config(nx, ny, nz, **cfg_kw)
+        return int(load_library().fe_batch_workspace_size(C.byref(cfg), nslots))
+
+    def setup_slot(self, slot, f: torch.Tensor | None, fixed: torch.Tensor | None = None) -> Problem:
+        f = None if f is None else f.to(self.device, torch.float64).contiguous()
+        fixed = None if fixed is None else fixed.to(self.device, torch.uint8).contiguous()
+        h = C.c_void_p()
+        with torch.cuda.stream(self.stream):
+            _check(load_library().fe_batch_setup_slot(self._b, slot, _ptr(fixed, torch.uint8), _ptr(f),
+                                                      C.byref(h)))
+        if self.slots[slot] is not None:
+            self.slots[slot]._h = None  # the batch released the old handle
+        self.slots[slot] = Problem._slot(self, h, f, fixed)
+        return self.slots[slot]
+
+    def round_begin(self):
+        _check(load_library().fe_batch_round_begin(self._b))
+
+    def round_end(self) -> int:
+        n = C.c_int32()
+        st = load_library().fe_batch_round_end(self._b, C.byref(n))
+        if st != FE_OK:
+            raise FEError(st, load_library().fe_last_error().decode())
+        return n.value
+
+    def close(self):
+        if getattr(self, "_b", None):
+            for s in self.slots:
+                if s is not None:
+                    s._h = None
+            load_library().fe_batch_destroy(self._b)
+            self._b = None
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass

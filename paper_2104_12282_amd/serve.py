@@ -1,20 +1,23 @@
 """Continuous batching of design solves on one GPU.
 
-Requests (grid, load, density seed) arrive over time.  The engine admits
-them in arrival order whenever a slot is free and the sum of the admitted
-designs' device footprints (workspace + arrays, from fe_workspace_size) stays
-within the HBM budget.  Every admitted design keeps its u, rho and multigrid
-hierarchy resident in its own workspace and advances through the
-non-blocking ABI (fe_solve_begin / fe_solve_step / fe_solve_end): each call
-to step() enqueues at most one stage (a captured graph of CG iterations, a
-residual, ...) on the design's stream and returns at once, so the kernels of
-all admitted designs overlap on the device while new requests are admitted
-as slots free up.  A design's arithmetic is exactly that of a lone
-fe_solve, so its result does not depend on the mix.
+Requests (grid, load, density seed) arrive over time and are admitted in
+arrival order whenever a slot is free and the device footprint of what is
+admitted stays within the HBM budget.  Every admitted design keeps its u,
+rho and multigrid hierarchy resident in its own workspace.  Two engines:
 
-Per request the engine records arrival, admission and completion times
-(completion = sensitivity finished on the device, observed by the host); it
-reports designs/s and p50/p99 latency.
+* run_engine_batched: designs of one grid size share an fe_batch (one
+  workspace, nslots slots); their CG iterations run as one captured graph
+  whose every launch covers all slots, and designs join a batch (free slot)
+  and leave it (finished) between replays -- the batches of the different
+  sizes advance in overlapping rounds on their own streams;
+* run_engine: every design on its own, advancing through the non-blocking
+  ABI (fe_solve_begin / fe_solve_step / fe_solve_end) on a few streams so
+  that the designs' launches overlap.
+
+A design's arithmetic is exactly that of a lone fe_solve in both, so its
+result does not depend on the mix.  Per request the engines record arrival,
+admission and completion times (completion = sensitivity finished on the
+device, observed by the host); they report designs/s and p50/p99 latency.
 """
 from __future__ import annotations
 
@@ -189,3 +192,120 @@ def run_sequential(requests, *, device="cuda:0", rtol=1e-8, filter_passes=3, kee
     return results, {"requests": len(results), "wall_s": wall, "designs_per_s": len(results) / wall,
                      "p50_latency_s": float(np.percentile(lat, 50)),
                      "p99_latency_s": float(np.percentile(lat, 99))}
+
+
+def run_engine_batched(requests, arrivals=None, *, device="cuda:0", nslots=16, n_streams=4,
+                       hbm_budget=64 << 30, rtol=1e-8, filter_passes=3, keep_outputs=False, cfg_kw=None,
+                       log=None):
+    """Serves `requests` with one fe_batch per grid size (nslots slots each,
+    created when the first request of that size is admitted)."""
+    cfg_kw = dict(cfg_kw or {"precision": "fp32_ir", "precond": "gmg", "mg_levels": 3})
+    if arrivals is None:
+        arrivals = np.zeros(len(requests))
+    order = np.argsort(arrivals, kind="stable")
+    pending = collections.deque((float(arrivals[i]), requests[i]) for i in order)
+    queue = []
+    streams = [torch.cuda.Stream(device=device) for _ in range(n_streams)]
+    classes = {}  # grid -> {"batch", "free", "live"}
+    used = 0
+    results = {}
+    finishing = []  # (slot record, event)
+    max_q = max_act = 0
+    t0 = time.perf_counter()
+
+    def per_request_bytes(grid):
+        nx, ny, nz = grid
+        ne, nd = nx * ny * nz, 3 * (nx + 1) * (ny + 1) * (nz + 1)
+        return 8 * (2 * nd + 3 * ne)
+
+    while pending or queue or finishing or any(c["live"] for c in classes.values()):
+        now = time.perf_counter() - t0
+        while pending and pending[0][0] <= now:
+            queue.append(pending.popleft())
+        # admission in arrival order: a request whose size has a free slot (or
+        # whose size's batch fits the budget) is admitted
+        rest = []
+        for t_arr, req in queue:
+            g = tuple(req["grid"])
+            c = classes.get(g)
+            if c is None:
+                nbytes = fe.Batch.workspace_bytes(*g, nslots, **cfg_kw)
+                if used + nbytes + per_request_bytes(g) > hbm_budget and (classes or finishing):
+                    rest.append((t_arr, req))
+                    continue
+                stream = streams[len(classes) % n_streams]
+                with torch.cuda.stream(stream):
+                    b = fe.Batch(*g, nslots, device=device, stream=stream, **cfg_kw)
+                c = classes[g] = {"batch": b, "free": list(range(nslots - 1, -1, -1)), "live": {}}
+                used += nbytes
+            if not c["free"] or used + per_request_bytes(g) > hbm_budget:
+                rest.append((t_arr, req))
+                continue
+            slot = c["free"].pop()
+            b = c["batch"]
+            f, rho0 = prepare_inputs(req, device)
+            with torch.cuda.stream(b.stream):
+                prob = b.setup_slot(slot, torch.as_tensor(f, device=device))
+                a = torch.as_tensor(rho0, device=device)
+                tmp = torch.empty_like(a)
+                for _ in range(filter_passes):
+                    prob.filter(a, out=tmp)
+                    a, tmp = tmp, a
+                u = torch.zeros(prob.ndof, dtype=torch.float64, device=device)
+                prob.solve_begin(a, u, rtol=rtol)
+            c["live"][slot] = {"req": req, "arrival": t_arr, "admit": time.perf_counter() - t0, "prob": prob,
+                               "rho": a, "u": u, "slot": slot, "cls": g}
+            used += per_request_bytes(g)
+        queue = rest
+        max_q = max(max_q, len(queue))
+        max_act = max(max_act, sum(len(c["live"]) for c in classes.values()))
+        # one round of every batch with running designs, overlapping
+        active = [c for c in classes.values() if c["live"]]
+        for c in active:
+            c["batch"].round_begin()
+        for c in active:
+            c["batch"].round_end()
+            for slot, rec in list(c["live"].items()):
+                if not rec["prob"].solve_step():
+                    continue
+                prob = rec["prob"]
+                rec["info"] = prob.solve_end()
+                with torch.cuda.stream(c["batch"].stream):
+                    rec["dc"], rec["comp"] = prob.sensitivity(rec["rho"], rec["u"])
+                    ev = torch.cuda.Event()
+                    ev.record(c["batch"].stream)
+                finishing.append((rec, ev))
+                del c["live"][slot]
+                c["free"].append(slot)  # stream order: the next design's setup follows the sensitivity
+        still = []
+        for rec, ev in finishing:
+            if not ev.query():
+                still.append((rec, ev))
+                continue
+            t_done = time.perf_counter() - t0
+            info = rec["info"]
+            out = {"id": rec["req"]["id"], "grid": rec["req"]["grid"], "arrival": rec["arrival"],
+                   "admit": rec["admit"], "finish": t_done, "latency": t_done - rec["arrival"],
+                   "iters": info["iters"], "outer_iters": info["outer_iters"], "rel_res": info["rel_res"],
+                   "compliance": float(rec["comp"].item()), "slot": rec["slot"]}
+            if keep_outputs:
+                out["u"] = rec["u"].cpu().numpy()
+                out["dc"] = rec["dc"].cpu().numpy()
+            results[rec["req"]["id"]] = out
+            used -= per_request_bytes(rec["cls"])
+            if log:
+                log(out)
+        finishing = still
+        if not active and not finishing and not queue and pending:
+            wait = pending[0][0] - (time.perf_counter() - t0)
+            if wait > 0:
+                time.sleep(min(wait, 0.01))
+    torch.cuda.synchronize(device)
+    wall = time.perf_counter() - t0
+    for c in classes.values():
+        c["batch"].close()
+    lat = np.array([r["latency"] for r in results.values()])
+    return results, {"requests": len(results), "wall_s": wall, "designs_per_s": len(results) / wall,
+                     "p50_latency_s": float(np.percentile(lat, 50)),
+                     "p99_latency_s": float(np.percentile(lat, 99)), "max_queue": max_q,
+                     "max_active": max_act, "slots_per_size": nslots, "sizes": len(classes)}

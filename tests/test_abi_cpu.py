@@ -79,3 +79,28 @@ def test_serving_footprint_grows_with_grid():
              for g in synth.SERVING_GRIDS]
     assert all(a < b for a, b in zip(sizes, sizes[1:]))
     assert sizes[-1] < 1 << 30  # the largest request fits easily in HBM
+
+
+def test_batch_workspace_and_argument_validation_without_gpu():
+    lib = fe.load_library()
+    cfg = fe.make_config(16, 8, 8, precision="fp32_ir", precond="gmg", mg_levels=3)
+    one = lib.fe_workspace_size(C.byref(cfg))
+    n4 = lib.fe_batch_workspace_size(C.byref(cfg), 4)
+    # four slots, each at least a lone problem's workspace, plus the idle slots' zero load
+    assert n4 >= 4 * one and n4 % 256 == 0
+    assert lib.fe_batch_workspace_size(C.byref(cfg), 8) > n4
+    assert lib.fe_batch_workspace_size(C.byref(cfg), 0) == 0
+    assert lib.fe_batch_workspace_size(C.byref(cfg), 2000) == 0
+    jac = fe.make_config(16, 8, 8, precision="fp32_ir", precond="jacobi")
+    assert lib.fe_batch_workspace_size(C.byref(jac), 4) == 0   # batches are multigrid only
+    bf = fe.make_config(16, 8, 8, precision="bf16_ir", precond="gmg", mg_levels=3)
+    assert lib.fe_batch_workspace_size(C.byref(bf), 4) == 0    # not on matrix cores
+    out = C.c_void_p()
+    fake = C.c_void_p(256)
+    assert lib.fe_batch_create(C.byref(cfg), 4, fake, 16, None, C.byref(out)) == fe.FE_ENOMEM
+    assert lib.fe_batch_create(C.byref(jac), 4, fake, 1 << 30, None, C.byref(out)) == fe.FE_EINVAL
+    assert lib.fe_batch_create(C.byref(cfg), 4, C.c_void_p(257), 1 << 30, None, C.byref(out)) == fe.FE_EINVAL
+    assert lib.fe_batch_round_begin(None) == fe.FE_EINVAL
+    assert lib.fe_batch_round_end(None, None) == fe.FE_EINVAL
+    assert lib.fe_batch_setup_slot(None, 0, None, None, C.byref(out)) == fe.FE_EINVAL
+    lib.fe_batch_destroy(None)

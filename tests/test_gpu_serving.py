@@ -58,3 +58,63 @@ def test_served_design_matches_oracle():
     r = res[0]
     assert abs(r["compliance"] - c_ref) / c_ref <= 1e-6
     assert np.abs(r["dc"] - dc_ref).max() / np.abs(dc_ref).max() <= 1e-5
+
+
+@pytest.mark.parametrize("precision", ["fp32_ir", "fp64"])
+def test_batch_slots_match_lone_solves(precision):
+    """Designs sharing a batch's launches (one slot idle, slots reused)
+    give bitwise the result of the same design solved alone."""
+    from paper_2104_12282_amd import fe
+    nx, ny, nz = 16, 8, 8
+    T = lambda a: torch.as_tensor(a, dtype=torch.float64, device=DEV)
+    designs = [(synth.point_load(nx, ny, nz, s), synth.density_uniform(nx, ny, nz, s)) for s in (11, 12, 13, 14)]
+    alone = []
+    for f, rho in designs:
+        p = fe.Problem(nx, ny, nz, T(f), device=DEV, precision=precision, precond="gmg", mg_levels=3)
+        u, info = p.solve(T(rho), rtol=1e-8)
+        alone.append((u.cpu().numpy(), info))
+        p.close()
+    b = fe.Batch(nx, ny, nz, 3, device=DEV, precision=precision, mg_levels=3)
+    got = {}
+    todo = list(range(len(designs)))
+    live = {}
+    free = [0, 1]  # slot 2 stays idle
+    rounds = 0
+    while todo or live:
+        while todo and free:
+            d, s = todo.pop(0), free.pop(0)
+            f, rho = designs[d]
+            prob = b.setup_slot(s, T(f))
+            u = torch.zeros(prob.ndof, dtype=torch.float64, device=DEV)
+            prob.solve_begin(T(rho), u, rtol=1e-8)
+            live[s] = (d, prob, u)
+        b.round_begin()
+        b.round_end()
+        rounds += 1
+        assert rounds < 5000
+        for s, (d, prob, u) in list(live.items()):
+            if prob.solve_step():
+                got[d] = (u.cpu().numpy(), prob.solve_end())
+                del live[s]
+                free.append(s)
+    b.close()
+    for d in range(len(designs)):
+        ua, ia = alone[d]
+        ub, ib = got[d]
+        assert ia["iters"] == ib["iters"] and ia["outer_iters"] == ib["outer_iters"]
+        assert np.array_equal(ua, ub)
+        assert ib["rel_res"] <= 1e-8
+
+
+def test_batched_engine_matches_sequential():
+    reqs = _requests(12, seed=5)
+    arrivals = np.linspace(0.0, 0.03, len(reqs))
+    mix, st = serve.run_engine_batched(reqs, arrivals, device=DEV, nslots=3, keep_outputs=True)
+    alone, _ = serve.run_sequential(reqs, device=DEV, keep_outputs=True)
+    assert st["requests"] == len(reqs) and st["max_active"] > 1
+    for r in reqs:
+        a, b = mix[r["id"]], alone[r["id"]]
+        assert a["iters"] == b["iters"]
+        assert np.array_equal(a["u"], b["u"])
+        assert np.array_equal(a["dc"], b["dc"])
+        assert a["rel_res"] <= 1e-8
