@@ -951,6 +951,21 @@ struct fe_batch {
 
 namespace {
 
+// New supports and load on a problem of the same configuration (the parts
+// of fe_setup that depend on the design, not on the configuration).
+fe_status reinit_design(fe_problem* p, const uint8_t* fixed, const double* f) {
+  HIP_TRY(launch_fill<double>(p, (double*)p->st, 2 * sizeof(CgState) / sizeof(double), 0.0));
+  HIP_TRY(launch_node_mask(p, fixed));
+  for (int l = 1; l < p->nlev; ++l) HIP_TRY(launch_coarsen_mask(p, l));
+  HIP_TRY(launch_mask_load(p, f));
+  HIP_TRY(launch_dot64(p, p->f, p->f, p->L[0].g.ndof, p->scal + 2 * SLOT_FF));
+  HIP_TRY(hipMemcpyAsync(p->h_scal, p->scal + 2 * SLOT_FF, sizeof(double), hipMemcpyDeviceToHost, p->stream));
+  HIP_TRY(hipStreamSynchronize(p->stream));
+  p->ff = p->h_scal[0];
+  p->sc = SolveCtx();
+  return FE_OK;
+}
+
 std::string batch_validate(const fe_config* cfg, int nslots) {
   const std::string why = validate(cfg);
   if (!why.empty()) return why;
@@ -1102,7 +1117,18 @@ extern "C" fe_status fe_batch_setup_slot(fe_batch* b, int32_t slot, const uint8_
     fe_set_error("the slot's solve is still running");
     return FE_EINVAL;
   }
-  if (old) fe_destroy(old);
+  if (old) {
+    // same configuration: keep the handle, its Ke, filter and multigrid
+    // tables and its host resources; reset only the design's own data
+    const fe_status st = reinit_design(old, fixed, f ? f : b->zero_f);
+    if (st == FE_OK) {
+      const fe_status ss = batch_stop_slot(b, slot);
+      if (ss != FE_OK) return ss;
+      *out = old;
+      return FE_OK;
+    }
+    fe_destroy(old);
+  }
   b->slot[slot] = nullptr;
   fe_problem* h = nullptr;
   fe_status st = fe_setup(&b->cfg, fixed, f ? f : b->zero_f, b->ws + (size_t)slot * b->stride, b->stride,

@@ -5,6 +5,7 @@
 #include <cstddef>
 #include <cstdint>
 #include <string>
+#include <type_traits>
 #include <vector>
 
 #include "fe_abi.h"
@@ -179,9 +180,13 @@ struct fe_problem {
 // Byte offset of this workgroup's problem in a batched launch, and a pointer
 // moved by it (null stays null).
 __device__ inline int64_t batch_offset(int64_t wsh) { return (int64_t)blockIdx.y * wsh; }
+// Byte arithmetic on a char pointer (not on an integer) keeps the pointer's
+// address space visible to the compiler, so shifted pointers still load with
+// global (not flat) instructions.
 template <typename P>
 __device__ inline P* wshift(P* ptr, int64_t off) {
-  return ptr ? reinterpret_cast<P*>(reinterpret_cast<uintptr_t>(ptr) + off) : ptr;
+  using B = std::conditional_t<std::is_const<P>::value, const char, char>;
+  return ptr ? reinterpret_cast<P*>(reinterpret_cast<B*>(ptr) + off) : ptr;
 }
 
 // Partial-sum regions.  Multigrid CG hands each reduction to the next kernel

@@ -227,51 +227,9 @@ __global__ void __launch_bounds__(TX* TY, FE_KXU_MIN_WAVES) kxu_tile_kernel(Grid
     xi.xout = wshift(xi.xout, o);
     fo.part = wshift(fo.part, o);
   }
-  if ((MODE == 1 || MODE == 5 || st) && st->done) return;
-  // folded reductions: every workgroup sums the same partials in the same
-  // order, so all take the same decision; workgroup 0 records it in st
+  // the operand of the folded CG direction (set by the gate below)
   T beta = T(0);
   bool first_dir = false;
-  if (fo.what == 1) {
-    const double v = block_sum_all(fo.part, fo.n);
-    const int it = st->iter;
-    const bool bad = !(v > 0.0) || !finite_d(v);
-    if (blockIdx.x == 0 && threadIdx.x == 0) {
-      if (bad) {
-        st->status = FE_EBREAKDOWN;
-        st->done = 1;
-      } else {
-        st->rz_new = v;
-        st->beta = it == 0 ? 0.0 : v / st->rz;
-      }
-    }
-    if (bad) return;
-    first_dir = it == 0;
-    beta = first_dir ? T(0) : (T)(v / st->rz);
-  } else if (fo.what == 2) {
-    const double v = block_sum_all(fo.part, fo.n);
-    const int it = st->iter_next;
-    int status = FE_OK;
-    bool stop = false;
-    if (!finite_d(v)) {
-      stop = true;
-      status = FE_EBREAKDOWN;
-    } else if (v <= st->tol2) {
-      stop = true;
-    } else if (it >= st->max_iter) {
-      stop = true;
-      status = FE_ENOTCONV;
-    }
-    if (blockIdx.x == 0 && threadIdx.x == 0) {
-      st->iter = it;
-      st->rr = v;
-      if (stop) {
-        st->status = status;
-        st->done = 1;
-      }
-    }
-    if (stop) return;
-  }
   __shared__ T su[2][3][TY + 1][TX + 1];  // node values of a level (17 x 17 ring)
   __shared__ T sy[2][9][TY][TX];          // lower-level partials of corners (1,0), (1,1), (0,1)
 
@@ -313,8 +271,8 @@ __global__ void __launch_bounds__(TX* TY, FE_KXU_MIN_WAVES) kxu_tile_kernel(Grid
   auto node_in = [&](bool ok, int i, int j, int k, T (&v)[3], T& d, T (&pv)[3]) {
     fetch(ok, i, j, k, v);
     if (XIN == 1) d = *(ok ? xi.invd + (i + sx * j + sxy * k) : zpad);
-    if (XIN == 2) {
-      const T* src = (ok && !first_dir) ? xi.pold + 3 * (i + sx * j + sxy * k) : zpad;
+    if (XIN == 2) {  // loaded also on the first iteration (then unused: see operand)
+      const T* src = ok ? xi.pold + 3 * (i + sx * j + sxy * k) : zpad;
       pv[0] = src[0];
       pv[1] = src[1];
       pv[2] = src[2];
@@ -331,7 +289,7 @@ __global__ void __launch_bounds__(TX* TY, FE_KXU_MIN_WAVES) kxu_tile_kernel(Grid
   // the operand value of a node from what was loaded for it
   auto operand = [&](const T (&v)[3], T d, const T (&pv)[3], int c) -> T {
     if (XIN == 1) return xi.s * d * v[c];
-    if (XIN == 2) return v[c] + beta * pv[c];
+    if (XIN == 2) return first_dir ? v[c] : v[c] + beta * pv[c];  // p_old is not set before the first
     return v[c];
   };
   // stores a level into LDS; the loaded registers die here (this thread's
@@ -418,6 +376,53 @@ __global__ void __launch_bounds__(TX* TY, FE_KXU_MIN_WAVES) kxu_tile_kernel(Grid
     load_level(K0 - 1, L0);
     load_level(K0, R0);
     load_level(K0 + 1, R1);  // kend >= K0 + 1
+    // The stop flag and the folded reductions are read only now, with the
+    // first levels' loads already in flight (a read before them would put a
+    // whole memory round trip in front of every launch); nothing has been
+    // stored yet.  Folded reductions: every workgroup sums the same partials
+    // in the same order, so all take the same decision; workgroup 0 records
+    // it in st.
+    if ((MODE == 1 || MODE == 5 || st) && st->done) return;
+    if (fo.what == 1) {
+      const double v = block_sum_all(fo.part, fo.n);
+      const int it = st->iter;
+      const bool bad = !(v > 0.0) || !finite_d(v);
+      if (blockIdx.x == 0 && threadIdx.x == 0) {
+        if (bad) {
+          st->status = FE_EBREAKDOWN;
+          st->done = 1;
+        } else {
+          st->rz_new = v;
+          st->beta = it == 0 ? 0.0 : v / st->rz;
+        }
+      }
+      if (bad) return;
+      first_dir = it == 0;
+      beta = first_dir ? T(0) : (T)(v / st->rz);
+    } else if (fo.what == 2) {
+      const double v = block_sum_all(fo.part, fo.n);
+      const int it = st->iter_next;
+      int status = FE_OK;
+      bool stop = false;
+      if (!finite_d(v)) {
+        stop = true;
+        status = FE_EBREAKDOWN;
+      } else if (v <= st->tol2) {
+        stop = true;
+      } else if (it >= st->max_iter) {
+        stop = true;
+        status = FE_ENOTCONV;
+      }
+      if (blockIdx.x == 0 && threadIdx.x == 0) {
+        st->iter = it;
+        st->rr = v;
+        if (stop) {
+          st->status = status;
+          st->done = 1;
+        }
+      }
+      if (stop) return;
+    }
     const int b0 = (K0 - 1) & 1;
     store_level(b0, L0);
     __syncthreads();

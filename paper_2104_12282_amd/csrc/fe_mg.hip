@@ -18,7 +18,8 @@ inline int nblocks(int64_t n) {
 }
 
 // z = omega D^-1 r (the first sweep from z = 0; fixed dofs have r = 0).
-// A non-null st guards every kernel of the cycle: nothing runs once CG stopped.
+// A non-null st guards every kernel of the cycle: nothing is stored once CG
+// stopped.
 template <typename T>
 __global__ void __launch_bounds__(FE_BLOCK) jacobi0_kernel(int64_t ndof, const T* __restrict__ r,
                                                            const T* __restrict__ invd, T omega,
@@ -30,9 +31,11 @@ __global__ void __launch_bounds__(FE_BLOCK) jacobi0_kernel(int64_t ndof, const T
     z = wshift(z, o);
     st = wshift(st, o);
   }
-  if (st && st->done) return;
   const int64_t d = blockIdx.x * (int64_t)FE_BLOCK + threadIdx.x;
-  if (d < ndof) z[d] = omega * invd[d / 3] * r[d];
+  if (d >= ndof) return;
+  const T v = omega * invd[d / 3] * r[d];
+  if (st && st->done) return;  // read after the loads: no round trip in front of them
+  z[d] = v;
 }
 
 // r_c = P^T t_f: coarse node (I,J,K) collects the fine nodes 2I+a, 2J+b, 2K+c
@@ -48,7 +51,6 @@ __global__ void __launch_bounds__(FE_BLOCK) restrict_kernel(Grid fg, Grid cg, co
     rc = wshift(rc, o);
     st = wshift(st, o);
   }
-  if (st && st->done) return;
   const int64_t n = blockIdx.x * (int64_t)FE_BLOCK + threadIdx.x;
   if (n >= cg.nnode) return;
   const int I = (int)(n % (cg.nx + 1)), J = (int)((n / (cg.nx + 1)) % (cg.ny + 1)),
@@ -75,6 +77,7 @@ __global__ void __launch_bounds__(FE_BLOCK) restrict_kernel(Grid fg, Grid cg, co
     }
   }
   const uint8_t m = cmask[n];
+  if (st && st->done) return;  // read after the loads: no round trip in front of them
 #pragma unroll
   for (int q = 0; q < 3; ++q) rc[3 * n + q] = ((m >> q) & 1) ? T(0) : acc[q];
 }
@@ -93,7 +96,6 @@ __global__ void __launch_bounds__(FE_BLOCK) prolong_add_kernel(Grid fg, Grid cg,
     out = wshift(out, o);
     st = wshift(st, o);
   }
-  if (st && st->done) return;
   const int64_t n = blockIdx.x * (int64_t)FE_BLOCK + threadIdx.x;
   if (n >= fg.nnode) return;
   const int i = (int)(n % (fg.nx + 1)), j = (int)((n / (fg.nx + 1)) % (fg.ny + 1)),
@@ -115,8 +117,12 @@ __global__ void __launch_bounds__(FE_BLOCK) prolong_add_kernel(Grid fg, Grid cg,
         acc[2] += w * zc[3 * q + 2];
       }
   const uint8_t m = fmask[n];
+  T zv[3];
 #pragma unroll
-  for (int q = 0; q < 3; ++q) out[3 * n + q] = ((m >> q) & 1) ? T(0) : zf[3 * n + q] + acc[q];
+  for (int q = 0; q < 3; ++q) zv[q] = zf[3 * n + q];
+  if (st && st->done) return;  // read after the loads: no round trip in front of them
+#pragma unroll
+  for (int q = 0; q < 3; ++q) out[3 * n + q] = ((m >> q) & 1) ? T(0) : zv[q] + acc[q];
 }
 
 template <typename T>
