@@ -93,6 +93,27 @@ __device__ inline void apply_S(const WK<T>& k, const T (&t)[3][8], T (&s)[3][8])
   s[Z][6] = k.J * t[Z][6];
 }
 
+// Stores through a raw buffer resource.  The hardware drops a store whose
+// byte offset lies outside [0, bytes), so a lane with nothing to store is
+// given an offset past the end instead of a branch around its store: a
+// divergent branch around stores makes the compiler count those stores as
+// possibly missing at the join, and every later wait for an older load then
+// also waits for loads issued after it (the prefetched levels).
+constexpr uint32_t kStoreDrop = 0x80000000u;  // beyond any range below 2^31 bytes
+
+__device__ inline __amdgpu_buffer_rsrc_t store_range(void* base, uint32_t bytes) {
+  // word 3 of a gfx9 buffer descriptor: 32-bit data format, no swizzle
+  return __builtin_amdgcn_make_buffer_rsrc(base, (short)0, (int)bytes, 0x00020000);
+}
+
+__device__ inline void store_at(__amdgpu_buffer_rsrc_t r, uint32_t off, double v) {
+  typedef int i32x2 __attribute__((ext_vector_type(2)));
+  __builtin_amdgcn_raw_buffer_store_b64(__builtin_bit_cast(i32x2, v), r, (int)off, 0, 0);
+}
+__device__ inline void store_at(__amdgpu_buffer_rsrc_t r, uint32_t off, float v) {
+  __builtin_amdgcn_raw_buffer_store_b32(__builtin_bit_cast(int, v), r, (int)off, 0, 0);
+}
+
 // Epilogue operands of the modes below.
 template <typename T>
 struct Epi {
@@ -319,43 +340,58 @@ __global__ void __launch_bounds__(TX* TY, FE_KXU_MIN_WAVES) kxu_tile_kernel(Grid
       if (MODE == 3 || MODE == 4 || MODE == 5) P.b[c] = ep.bT[3 * n + c];
       if (MODE == 6) {
         P.b[c] = ep.res[3 * n + c];
-        if (!ep.first) P.a[c] = ep.acc[3 * n + c];
+        P.a[c] = ep.acc[3 * n + c];  // unused on the first step (no branch in the march)
       }
     }
     if (MODE == 3 || MODE == 5 || MODE == 6) P.d = ep.invd[n];
   };
 
   double dot = 0.0;
+  // Stores of the owned levels [K0, kend) go through ranges that start at
+  // level K0 (byte offsets below 2^31: the tile map bounds the chunk).
+  const int64_t lev0 = 3 * sxy * K0;
+  const uint32_t chunk_bytes = (uint32_t)(3 * sxy * (kend - K0) * (int64_t)sizeof(T));
+  const __amdgpu_buffer_rsrc_t ry = store_range(y + lev0, chunk_bytes);
+  const __amdgpu_buffer_rsrc_t rres = store_range(MODE == 6 ? ep.res + lev0 : y, MODE == 6 ? chunk_bytes : 0u);
+  const __amdgpu_buffer_rsrc_t racc = store_range(MODE == 6 ? ep.acc + lev0 : y, MODE == 6 ? chunk_bytes : 0u);
+  const __amdgpu_buffer_rsrc_t rxo =
+      store_range(XIN && xi.xout ? xi.xout + lev0 : y, XIN && xi.xout ? chunk_bytes : 0u);
+  // LDS reads of lanes that own no node stay inside the arrays
+  const int txl = tx > 0 ? tx - 1 : 0, tyl = ty > 0 ? ty - 1 : 0;
   // node sums of level k: own corner p0 plus the partials of the three
-  // neighbouring brick columns, then the mode's epilogue
+  // neighbouring brick columns, then the mode's epilogue.  Every lane runs
+  // it (no branch: see store_range); lanes without an owned node at level
+  // k store at kStoreDrop and add nothing to the dot product.
   auto finish_level = [&](int k, const T (&p0)[3], const T (&own)[3], const EpiIn& P) {
-    if (!(owner && k >= K0 && k < kend)) return;
+    const bool mine = owner && k >= K0 && k < kend;
     const int buf = k & 1;
-    const int64_t n = ni + sx * nj + sxy * k;
+    const uint32_t at =
+        mine ? (uint32_t)((ni + sx * nj + sxy * (k - K0)) * 3 * (int64_t)sizeof(T)) : kStoreDrop;
 #pragma unroll
     for (int c = 0; c < 3; ++c) {
-      T v2 = p0[c] + sy[buf][0 + c][ty][tx - 1] + sy[buf][3 + c][ty - 1][tx - 1] + sy[buf][6 + c][ty - 1][tx];
+      const uint32_t o = at + c * (uint32_t)sizeof(T);
+      T v2 = p0[c] + sy[buf][0 + c][ty][txl] + sy[buf][3 + c][tyl][txl] + sy[buf][6 + c][tyl][tx];
       const bool fx = (P.m >> c) & 1;
       if (fx) v2 = T(0);
       if (MODE == 2) {
         v2 = fx ? T(0) : (T)(P.b2[c] - (double)v2);
-        dot += (double)v2 * (double)v2;
+        dot += mine ? (double)v2 * (double)v2 : 0.0;
       } else if (MODE == 1) {
-        dot += (double)own[c] * (double)v2;
+        dot += mine ? (double)own[c] * (double)v2 : 0.0;
       } else if (MODE == 3 || MODE == 5) {
         v2 = fx ? T(0) : own[c] + ep.omega * P.d * (P.b[c] - v2);
-        if (MODE == 5) dot += (double)P.b[c] * (double)v2;
+        if (MODE == 5) dot += mine ? (double)P.b[c] * (double)v2 : 0.0;
       } else if (MODE == 4) {
         v2 = fx ? T(0) : P.b[c] - v2;
       } else if (MODE == 6) {
         const T dv = own[c];
         const T rn = fx ? T(0) : P.b[c] - v2;
-        ep.res[3 * n + c] = rn;
-        ep.acc[3 * n + c] = ep.first ? dv : P.a[c] + dv;
+        store_at(rres, o, rn);
+        store_at(racc, o, ep.first ? dv : P.a[c] + dv);
         v2 = fx ? T(0) : ep.c1 * dv + ep.c2 * P.d * rn;
       }
-      y[3 * n + c] = v2;
-      if (XIN && xi.xout) xi.xout[3 * n + c] = own[c];
+      store_at(ry, o, v2);
+      if (XIN) store_at(rxo, o, own[c]);
     }
   };
 
@@ -440,7 +476,9 @@ __global__ void __launch_bounds__(TX* TY, FE_KXU_MIN_WAVES) kxu_tile_kernel(Grid
     }
   }
 
-  auto step = [&](int ek, const LevelIn& use, LevelIn& fill, const EpiIn& Pu, EpiIn& Pf) {
+  // fin: whether the step finishes level ek - 1 (the first two steps would
+  // finish levels K0 - 2 and K0 - 1, which this workgroup does not own)
+  auto step = [&](auto fin, int ek, const LevelIn& use, LevelIn& fill, const EpiIn& Pu, EpiIn& Pf) {
     const int bu = (ek + 1) & 1;
     store_level(bu, use);
     load_level(ek + 3, fill);
@@ -450,7 +488,7 @@ __global__ void __launch_bounds__(TX* TY, FE_KXU_MIN_WAVES) kxu_tile_kernel(Grid
 #pragma unroll
     for (int c = 0; c < 3; ++c) own_up[c] = su[bu][c][ty][tx];
 
-    finish_level(ek - 1, p0, own_ll, Pu);
+    if constexpr (decltype(fin)::value) finish_level(ek - 1, p0, own_ll, Pu);
 
     T t[3][8];
 #pragma unroll
@@ -492,17 +530,23 @@ __global__ void __launch_bounds__(TX* TY, FE_KXU_MIN_WAVES) kxu_tile_kernel(Grid
     }
   };
 
-  // the operands of level ek + 1 sit in slot (s + 2) % 3; the first step's
-  // finish (level K0 - 2) and the second's (K0 - 1) are not owned
-  const int n = kend - K0 + 1;  // steps: layers K0 - 1 .. kend - 1
-  int s = 0;
+  // Step s (layer K0 - 1 + s) uses ring slot s % 3 and fills (s + 2) % 3;
+  // the operands of level ek + 1 sit in slot (s + 2) % 3.  The first two
+  // steps, which finish no owned level, are peeled off, so every step of
+  // the loop stores.
+  const std::false_type skip{};
+  const std::true_type fin{};
+  const int n = kend - K0 + 1;  // steps: layers K0 - 1 .. kend - 1 (n >= 2)
+  step(skip, K0 - 1, R0, R2, Q0, Q2);
+  step(skip, K0, R1, R0, Q1, Q0);
+  int s = 2;
   for (; s + 3 <= n; s += 3) {
-    step(K0 - 1 + s, R0, R2, Q0, Q2);
-    step(K0 + s, R1, R0, Q1, Q0);
-    step(K0 + 1 + s, R2, R1, Q2, Q1);
+    step(fin, K0 - 1 + s, R2, R1, Q2, Q1);
+    step(fin, K0 + s, R0, R2, Q0, Q2);
+    step(fin, K0 + 1 + s, R1, R0, Q1, Q0);
   }
-  if (s < n) step(K0 - 1 + s, R0, R2, Q0, Q2);
-  if (s + 1 < n) step(K0 + s, R1, R0, Q1, Q0);
+  if (s < n) step(fin, K0 - 1 + s, R2, R1, Q2, Q1);
+  if (s + 1 < n) step(fin, K0 + s, R0, R2, Q0, Q2);
   __syncthreads();
   // level kend - 1 = K0 + n - 2: its operands went to slot n % 3
   const int last = n % 3;
@@ -780,7 +824,9 @@ static TileMap kxu_tile_map(const Grid& g, int slots) {
   const int64_t rounds = std::max<int64_t>(1, (cols * L + (int64_t)slots * FE_KXU_KCMAX - 1) /
                                                   ((int64_t)slots * FE_KXU_KCMAX));
   int64_t nzc = std::max<int64_t>(1, std::min<int64_t>(L, rounds * slots / cols));
-  tm.kc = (int)((L + nzc - 1) / nzc);
+  // the stores address a chunk's levels with 31-bit byte offsets
+  const int64_t kc_fit = std::max<int64_t>(1, ((int64_t)1 << 31) / (24 * (int64_t)(g.nx + 1) * (g.ny + 1)));
+  tm.kc = (int)std::min<int64_t>((L + nzc - 1) / nzc, kc_fit);
   tm.nzc = (int)((L + tm.kc - 1) / tm.kc);
   tm.nblk = (int)(cols * tm.nzc);
   return tm;
@@ -797,6 +843,7 @@ static int launch_tile(hipStream_t stream, const Grid& g, const T* x, const T* E
                        const T* zpad, const XinK<T>& xi, const FoldK& fo, int bcount, int64_t bstride) {
   const void* k = reinterpret_cast<const void*>(&kxu_tile_kernel<T, MODE, XIN>);
   const TileMap tm = kxu_tile_map(g, kxu_slots(k));
+  if (3 * (int64_t)(g.nx + 1) * (g.ny + 1) * tm.kc * (int64_t)sizeof(T) >= ((int64_t)1 << 31)) return -1;
   hipLaunchKernelGGL((kxu_tile_kernel<T, MODE, XIN>), dim3(tm.nblk, bcount), dim3(TX * TY), 0, stream, g, tm, x,
                      E, nm, wk, y, ep, st, partials, out, zpad, xi, fo, bcount > 1 ? bstride : (int64_t)0);
   return tm.nblk;
@@ -917,6 +964,10 @@ hipError_t launch_kxu_tile(fe_problem* p, int lev, const T* x, const T* E, T* y,
       default: return hipErrorInvalidValue;
     }
 #undef FE_TILE
+    if (nb < 0) {  // a chunk too large for the stores' 31-bit offsets (about 89M nodes per level)
+      kstats_end(p, slot);
+      return hipErrorInvalidValue;
+    }
   }
   hipError_t e = hipGetLastError();
   kstats_end(p, slot);
