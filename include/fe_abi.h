@@ -174,6 +174,14 @@ FE_API fe_status oc_update(fe_problem* p, const double* x, const double* dcx, co
 FE_API fe_status fe_set_mg_params(fe_problem* p, int32_t nu, int32_t coarse_sweeps, double omega,
                            double coarse_ratio);
 
+/* Launches of the coarsest-level Chebyshev solve: steps_per_launch = 2
+ * (default) runs pairs of steps in one launch, each workgroup recomputing
+ * the ring of first-step values its second step needs (the solve on the
+ * small coarse grid is bound by launch latency, not by arithmetic); 1 runs
+ * one launch per step.  Both give bitwise the same result.  FE_EINVAL for
+ * other values and for batch slots. */
+FE_API fe_status fe_set_coarse_fusion(fe_problem* p, int32_t steps_per_launch);
+
 /* Timing of the dominant kernel (matrix-free K*u on the finest grid): with
  * on = 1 every such launch, in all its forms (CG product, residual, smoothing
  * sweep), is bracketed by HIP events on the handle's stream; with on = 2 + m

@@ -98,6 +98,7 @@ size_t layout(const fe_config* c, fe_problem* p, char* base) {
       L.mg_z = take(g.ndof * vbytes);
       L.mg_t = take(g.ndof * vbytes);
       L.mg_w = take(g.ndof * vbytes);
+      if (l == nl - 1) L.mg_q = take(g.ndof * vbytes);
     }
     if (p) p->L[l] = L;
     int64_t nb = (g.nnode + FE_BLOCK - 1) / FE_BLOCK;
@@ -874,6 +875,22 @@ extern "C" fe_status fe_set_mg_params(fe_problem* p, int32_t nu, int32_t coarse_
   p->mg_omega = omega;
   p->cheb_ratio = coarse_ratio;
   drop_graph(p->chunk64);  // the captured chunks bake these in
+  drop_graph(p->chunk32);
+  return FE_OK;
+}
+
+extern "C" fe_status fe_set_coarse_fusion(fe_problem* p, int32_t steps_per_launch) {
+  CHECK_HANDLE(p);
+  if (p->in_batch) {
+    fe_set_error("batch slots share the batch's multigrid parameters (the library defaults)");
+    return FE_EINVAL;
+  }
+  if (steps_per_launch != 1 && steps_per_launch != 2) {
+    fe_set_error("steps_per_launch must be 1 or 2");
+    return FE_EINVAL;
+  }
+  p->cheb_per_launch = steps_per_launch;
+  drop_graph(p->chunk64);
   drop_graph(p->chunk32);
   return FE_OK;
 }

@@ -66,6 +66,7 @@ struct Level {
   void* mg_z = nullptr;
   void* mg_t = nullptr;
   void* mg_w = nullptr;
+  void* mg_q = nullptr;  // coarsest level only: second residual of the fused Chebyshev steps
 };
 
 struct KStats {
@@ -167,6 +168,7 @@ struct fe_problem {
   double mg_omega = 0.35;      // Jacobi damping: below 2 / lambda_max(D^-1 Ke) = 2 / 5.32
   double lam_max = 0.0;        // lambda_max(diag(Ke)^-1 Ke): bounds that of D^-1 K on every level
   double cheb_ratio = 5000.0;  // coarse Chebyshev interval [lam_max / ratio, lam_max]
+  int cheb_per_launch = 2;     // coarse Chebyshev steps per launch (2: pairs fused, 1: one each)
 
   KStats kst;
 
@@ -262,6 +264,14 @@ hipError_t launch_kxu_tile(fe_problem* p, int lev, const T* x, const T* E, T* y,
                            const T* invd = nullptr, double omega = 0.0,
                            const ChebStep<T>* cs = nullptr, const TileFuse<T>* fz = nullptr);
 int64_t kxu_tile_blocks(const Grid& g);
+// Two Chebyshev steps (mode 6 twice) on level lev in one launch: from the
+// direction dk, residual rin and iterate acc (in place) to the direction
+// y = d_{k+2} and residual rout (rin and rout must differ); c = c1, c2 of
+// step k, then of step k + 1; first: step k starts the iterate.  The result
+// is bitwise that of two mode-6 launches.
+template <typename T>
+hipError_t launch_cheb2(fe_problem* p, int lev, const T* dk, T* y, const T* E, const T* invd, const T* rin,
+                        T* rout, T* acc, const double (&c)[4], int first, CgState* st);
 // Number of r^T z partials the level's last smoothing sweep (mode 5) leaves.
 template <typename T>
 int kxu_rz_partials(const fe_problem* p, int lev);

@@ -26,6 +26,11 @@
 #include "fe_internal.h"
 #include "fe_reduce.h"
 
+// No multiply-add is fused unless written as fma(): every kernel here then
+// rounds the brick arithmetic alike, whatever the surrounding code (the
+// fused Chebyshev launch relies on matching the single-step one bitwise).
+#pragma clang fp contract(off)
+
 namespace {
 
 constexpr int TX = 16, TY = 16, OWN = 15;
@@ -62,9 +67,9 @@ __device__ inline void apply_S(const WK<T>& k, const T (&t)[3][8], T (&s)[3][8])
   s[X][0] = s[Y][0] = s[Z][0] = T(0);
   // linear modes: normal block
   const T n1 = t[X][1], n2 = t[Y][3], n3 = t[Z][4];
-  s[X][1] = k.A * n1 + k.B * (n2 + n3);
-  s[Y][3] = k.A * n2 + k.B * (n1 + n3);
-  s[Z][4] = k.A * n3 + k.B * (n1 + n2);
+  s[X][1] = fma(k.A, n1, k.B * (n2 + n3));
+  s[Y][3] = fma(k.A, n2, k.B * (n1 + n3));
+  s[Z][4] = fma(k.A, n3, k.B * (n1 + n2));
   // linear modes: shear pairs
   T g = k.G * (t[Y][1] + t[X][3]);
   s[Y][1] = g;
@@ -76,17 +81,17 @@ __device__ inline void apply_S(const WK<T>& k, const T (&t)[3][8], T (&s)[3][8])
   s[Z][3] = g;
   s[Y][4] = g;
   // bilinear pairs
-  s[X][2] = k.C * t[X][2] + k.D * t[Z][7];
-  s[Z][7] = k.D * t[X][2] + k.C * t[Z][7];
-  s[Y][2] = k.C * t[Y][2] + k.D * t[Z][5];
-  s[Z][5] = k.D * t[Y][2] + k.C * t[Z][5];
-  s[X][5] = k.C * t[X][5] + k.D * t[Y][7];
-  s[Y][7] = k.D * t[X][5] + k.C * t[Y][7];
+  s[X][2] = fma(k.C, t[X][2], k.D * t[Z][7]);
+  s[Z][7] = fma(k.D, t[X][2], k.C * t[Z][7]);
+  s[Y][2] = fma(k.C, t[Y][2], k.D * t[Z][5]);
+  s[Z][5] = fma(k.D, t[Y][2], k.C * t[Z][5]);
+  s[X][5] = fma(k.C, t[X][5], k.D * t[Y][7]);
+  s[Y][7] = fma(k.D, t[X][5], k.C * t[Y][7]);
   // bilinear triple
   const T a = t[Z][2], b = t[Y][5], c = t[X][7];
-  s[Z][2] = k.F * a + k.H * (b + c);
-  s[Y][5] = k.F * b + k.H * (a + c);
-  s[X][7] = k.F * c + k.H * (a + b);
+  s[Z][2] = fma(k.F, a, k.H * (b + c));
+  s[Y][5] = fma(k.F, b, k.H * (a + c));
+  s[X][7] = fma(k.F, c, k.H * (a + b));
   // trilinear mode
   s[X][6] = k.J * t[X][6];
   s[Y][6] = k.J * t[Y][6];
@@ -154,6 +159,58 @@ __device__ inline void face4(T (&v)[4]) {
   bf(v[3], v[2]);
   bf(v[0], v[3]);
   bf(v[1], v[2]);
+}
+
+// One brick layer of a march up through node levels, for the brick whose
+// lower-left corner is this thread's node column.  fl: the lower face,
+// already x-y transformed (face4); on return the upper face, which is the
+// next brick's lower face.  fu: the upper face's corner values 00 10 11 01
+// (transformed here).  carry: the upper-corner contributions of the brick
+// below (on return: this brick's, in the face domain).  lo: this brick's
+// contributions to its lower corners 00 10 11 01 with the carry added, back
+// in corner values.  Ee scales the constants (the brick's modulus).
+template <typename T>
+__device__ inline void brick_layer(T (&fl)[3][4], T (&fu)[3][4], T (&carry)[3][4], T Ee, const WK<T>& wk,
+                                   T (&lo)[3][4]) {
+  T t[3][8];
+#pragma unroll
+  for (int c = 0; c < 3; ++c) {
+    face4(fu[c]);
+#pragma unroll
+    for (int i = 0; i < 4; ++i) {
+      t[c][i] = fl[c][i] + fu[c][i];
+      t[c][i + 4] = fl[c][i] - fu[c][i];
+      fl[c][i] = fu[c][i];
+    }
+  }
+  WK<T> k = wk;
+  k.A *= Ee; k.B *= Ee; k.G *= Ee; k.C *= Ee; k.D *= Ee; k.F *= Ee; k.H *= Ee; k.J *= Ee;
+  T w[3][8];
+  apply_S(k, t, w);
+#pragma unroll
+  for (int c = 0; c < 3; ++c) {
+#pragma unroll
+    for (int i = 0; i < 4; ++i) {
+      lo[c][i] = (w[c][i] + w[c][i + 4]) + carry[c][i];
+      carry[c][i] = w[c][i] - w[c][i + 4];
+    }
+    face4(lo[c]);
+  }
+}
+
+// Node sum of component c at a node whose own brick gave p0: the partials
+// of the bricks at (x-1, y), (x-1, y-1) and (x, y-1), in this fixed order.
+template <typename T>
+__device__ inline T node_sum(T p0, const T (&syb)[9][TY][TX], int c, int ty, int tx, int tyl, int txl) {
+  return p0 + syb[0 + c][ty][txl] + syb[3 + c][tyl][txl] + syb[6 + c][tyl][tx];
+}
+
+// Chebyshev step at one dof: residual r - (K d)_i and direction
+// c1 d_i + c2 D^-1_i (new residual); both zero at a fixed dof.
+template <typename T>
+__device__ inline void cheb_dof(bool fx, T r, T Kd, T d, T invd, T c1, T c2, T& rn, T& dn) {
+  rn = fx ? T(0) : r - Kd;
+  dn = fx ? T(0) : fma(c1, d, (c2 * invd) * rn);
 }
 
 // Fused operand of a launch (see TileFuse): XIN 1 forms x = s D^-1 a, XIN 2
@@ -370,7 +427,7 @@ __global__ void __launch_bounds__(TX* TY, FE_KXU_MIN_WAVES) kxu_tile_kernel(Grid
 #pragma unroll
     for (int c = 0; c < 3; ++c) {
       const uint32_t o = at + c * (uint32_t)sizeof(T);
-      T v2 = p0[c] + sy[buf][0 + c][ty][txl] + sy[buf][3 + c][tyl][txl] + sy[buf][6 + c][tyl][tx];
+      T v2 = node_sum(p0[c], sy[buf], c, ty, tx, tyl, txl);
       const bool fx = (P.m >> c) & 1;
       if (fx) v2 = T(0);
       if (MODE == 2) {
@@ -385,10 +442,10 @@ __global__ void __launch_bounds__(TX* TY, FE_KXU_MIN_WAVES) kxu_tile_kernel(Grid
         v2 = fx ? T(0) : P.b[c] - v2;
       } else if (MODE == 6) {
         const T dv = own[c];
-        const T rn = fx ? T(0) : P.b[c] - v2;
+        T rn;
+        cheb_dof(fx, P.b[c], v2, dv, P.d, ep.c1, ep.c2, rn, v2);
         store_at(rres, o, rn);
         store_at(racc, o, ep.first ? dv : P.a[c] + dv);
-        v2 = fx ? T(0) : ep.c1 * dv + ep.c2 * P.d * rn;
       }
       store_at(ry, o, v2);
       if (XIN) store_at(rxo, o, own[c]);
@@ -490,41 +547,22 @@ __global__ void __launch_bounds__(TX* TY, FE_KXU_MIN_WAVES) kxu_tile_kernel(Grid
 
     if constexpr (decltype(fin)::value) finish_level(ek - 1, p0, own_ll, Pu);
 
-    T t[3][8];
+    T fu[3][4], lo[3][4];
 #pragma unroll
     for (int c = 0; c < 3; ++c) {
-      T fu[4];
-      fu[0] = own_up[c];
-      fu[1] = su[bu][c][ty][tx + 1];
-      fu[2] = su[bu][c][ty + 1][tx + 1];
-      fu[3] = su[bu][c][ty + 1][tx];
-      face4(fu);
-#pragma unroll
-      for (int i = 0; i < 4; ++i) {
-        t[c][i] = fl[c][i] + fu[i];
-        t[c][i + 4] = fl[c][i] - fu[i];
-        fl[c][i] = fu[i];
-      }
+      fu[c][0] = own_up[c];
+      fu[c][1] = su[bu][c][ty][tx + 1];
+      fu[c][2] = su[bu][c][ty + 1][tx + 1];
+      fu[c][3] = su[bu][c][ty + 1][tx];
     }
-    const T Ee = use.Ee;
-    WK<T> k = wk;
-    k.A *= Ee; k.B *= Ee; k.G *= Ee; k.C *= Ee; k.D *= Ee; k.F *= Ee; k.H *= Ee; k.J *= Ee;
-    T w[3][8];
-    apply_S(k, t, w);
+    brick_layer(fl, fu, carry, use.Ee, wk, lo);
     const int bl = ek & 1;
 #pragma unroll
     for (int c = 0; c < 3; ++c) {
-      T lo[4];
-#pragma unroll
-      for (int i = 0; i < 4; ++i) {
-        lo[i] = (w[c][i] + w[c][i + 4]) + carry[c][i];
-        carry[c][i] = w[c][i] - w[c][i + 4];
-      }
-      face4(lo);
-      p0[c] = lo[0];
-      sy[bl][0 + c][ty][tx] = lo[1];
-      sy[bl][3 + c][ty][tx] = lo[2];
-      sy[bl][6 + c][ty][tx] = lo[3];
+      p0[c] = lo[c][0];
+      sy[bl][0 + c][ty][tx] = lo[c][1];
+      sy[bl][3 + c][ty][tx] = lo[c][2];
+      sy[bl][6 + c][ty][tx] = lo[c][3];
       own_ll[c] = own_lo[c];
       own_lo[c] = own_up[c];
     }
@@ -555,6 +593,348 @@ __global__ void __launch_bounds__(TX* TY, FE_KXU_MIN_WAVES) kxu_tile_kernel(Grid
   if (MODE == 0 || MODE == 3 || MODE == 4 || MODE == 6) return;
   double vv[1] = {dot};
   block_partials<1>(vv, partials);
+}
+
+// ---------------------------------------------------------------------------
+// Two steps of the coarsest-level Chebyshev iteration in one launch.
+//
+// On a small grid a launch costs mostly latency (loading what the previous
+// launch wrote, a few march steps, the stores draining), so the coarse solve
+// is bound by its number of launches.  A workgroup here runs two marches of
+// 16 x 16 threads.  Group A marches step k (the tile kernel's march with the
+// Chebyshev epilogue) over a 17 x 17 node ring and finishes the 15 x 15 node
+// columns and the kc + 2 levels that step k + 1 needs around the 13 x 13
+// columns and kc levels the workgroup owns; it hands r_{k+1} and d_{k+1} to
+// group B through LDS, level by level.  Group B marches step k + 1 on those
+// values three levels behind and writes the results.  The ring of step-k
+// values is recomputed by the neighbouring workgroups as well (the price of
+// the saved launch), and every node sum is formed in the tile kernel's order
+// with the same per-dof update, so the result is bitwise that of two
+// single-step launches.
+//
+// Both groups pass the same number of barriers (kend - K0 + 7).  A finishes
+// level l after the barrier of iteration l - K0 + 4 and B reads it after the
+// next barrier; A's next write of the same buffer (level l + 2) follows one
+// barrier after B's read.  The residual is read on the ring, so it cannot be
+// updated in place (rin -> rout); the iterate acc is read and written at
+// owned nodes only (in place).
+template <typename T>
+struct Cheb2 {
+  T c1a, c2a;  // step k: d_{k+1} = c1a d_k + c2a D^-1 r_{k+1}
+  T c1b, c2b;  // step k + 1
+  int first;   // step k is the first (the iterate starts at zero)
+};
+
+constexpr int OWN2 = 13;  // node columns per direction a fused workgroup finishes
+
+template <typename T>
+__global__ void __launch_bounds__(2 * TX * TY) cheb2_kernel(Grid g, TileMap tm, const T* __restrict__ dk,
+                                                       const T* __restrict__ E,
+                                                       const uint8_t* __restrict__ nmask, WK<T> wk,
+                                                       const T* __restrict__ invd, const T* __restrict__ rin,
+                                                       T* __restrict__ rout, T* __restrict__ acc,
+                                                       T* __restrict__ y, Cheb2<T> cf, CgState* st,
+                                                       const T* __restrict__ zpad, int64_t wsh) {
+  if (wsh) {  // batched launch: this workgroup's problem
+    const int64_t o = batch_offset(wsh);
+    dk = wshift(dk, o);
+    E = wshift(E, o);
+    nmask = wshift(nmask, o);
+    invd = wshift(invd, o);
+    rin = wshift(rin, o);
+    rout = wshift(rout, o);
+    acc = wshift(acc, o);
+    y = wshift(y, o);
+    st = wshift(st, o);
+    zpad = wshift(zpad, o);
+  }
+  __shared__ T suA[2][3][TY + 1][TX + 1];  // step-k direction by level (group A's ring)
+  __shared__ T syA[2][9][TY][TX];
+  __shared__ T suB[2][3][TY + 1][TX + 1];  // d_{k+1} by level, group B's frame
+  __shared__ T srB[2][3][TY][TX];          // r_{k+1} by level, group B's frame
+  __shared__ T syB[2][9][TY][TX];
+
+  int cx, cy, cz;
+  tile_of_block(tm, cx, cy, cz);
+  const int K0 = cz * tm.kc, kend = min(K0 + tm.kc, g.nz + 1);  // owned levels: [K0, kend)
+  const int64_t sx = g.nx + 1, sxy = (int64_t)(g.nx + 1) * (g.ny + 1);
+  const int q = threadIdx.x % (TX * TY);
+  const int tx = q % TX, ty = q / TX;
+  const int nbar = kend - K0 + 7;
+  const int txl = tx > 0 ? tx - 1 : 0, tyl = ty > 0 ? ty - 1 : 0;
+  const std::false_type skip{};
+  const std::true_type fin{};
+  // 256 threads are four whole waves: the group is uniform in a wave
+  const int grp = __builtin_amdgcn_readfirstlane((int)(threadIdx.x / (TX * TY)));
+
+  if (grp == 0) {
+    // ---- group A: step k on node columns I0 .. I0 + 16, levels ka0 - 1 .. kaend
+    const int I0 = cx * OWN2 - 2, J0 = cy * OWN2 - 2;
+    const int ni = I0 + tx, nj = J0 + ty;
+    const int ka0 = K0 - 1, kaend = min(kend + 1, g.nz + 1);  // finished levels: [ka0, kaend)
+    const bool owner = tx >= 1 && ty >= 1 && ni >= 0 && nj >= 0 && ni <= g.nx && nj <= g.ny;
+    const bool ecol = ni >= 0 && ni < g.nx && nj >= 0 && nj < g.ny;
+    const bool hslot = q < TX + TY + 1;
+    const int hx = q <= TY ? TX : q - (TY + 1), hy = q <= TY ? q : TY;
+    const int hi = I0 + hx, hj = J0 + hy;
+    auto node_ok = [&](int i, int j, int k) {
+      return i >= 0 && i <= g.nx && j >= 0 && j <= g.ny && k >= 0 && k <= g.nz;
+    };
+    struct LevelIn {
+      T own[3];
+      T halo[3];
+      T Ee;  // modulus of the brick layer below this level
+    };
+    auto fetch = [&](bool ok, int i, int j, int k, T (&v)[3]) {
+      const T* src = ok ? dk + 3 * (i + sx * j + sxy * k) : zpad;
+      v[0] = src[0];
+      v[1] = src[1];
+      v[2] = src[2];
+    };
+    auto load_level = [&](int k, LevelIn& L) {
+      const bool need = k <= kaend;
+      fetch(need && node_ok(ni, nj, k), ni, nj, k, L.own);
+      fetch(need && hslot && node_ok(hi, hj, k), hi, hj, k, L.halo);
+      const int ek = k - 1;
+      const bool ok = need && ecol && ek >= 0 && ek < g.nz;
+      L.Ee = *(ok ? E + (ni + (int64_t)g.nx * (nj + (int64_t)g.ny * ek)) : zpad);
+    };
+    auto store_level = [&](int buf, const LevelIn& L) {
+#pragma unroll
+      for (int c = 0; c < 3; ++c) suA[buf][c][ty][tx] = L.own[c];
+      if (hslot)
+        for (int c = 0; c < 3; ++c) suA[buf][c][hy][hx] = L.halo[c];
+    };
+    struct EpiIn {
+      uint8_t m;
+      T r[3];
+      T d;
+    };
+    auto load_epi = [&](int k, EpiIn& P) {
+      const bool ok = owner && k >= 0 && k >= ka0 && k < kaend;
+      const int64_t n = ok ? ni + sx * nj + sxy * k : 0;
+      P.m = nmask[n];
+#pragma unroll
+      for (int c = 0; c < 3; ++c) P.r[c] = rin[3 * n + c];
+      P.d = invd[n];
+    };
+    // level k of step k: r_{k+1} and d_{k+1} (zero off the mesh) to group B
+    auto finish = [&](int k, const T (&p0)[3], const T (&own)[3], const EpiIn& P) {
+      const bool mine = owner && k >= 0;
+      const int buf = k & 1;
+#pragma unroll
+      for (int c = 0; c < 3; ++c) {
+        T v = node_sum(p0[c], syA[buf], c, ty, tx, tyl, txl);
+        const bool fx = (P.m >> c) & 1;
+        if (fx) v = T(0);
+        T rn, dn;
+        cheb_dof(fx, P.r[c], v, own[c], P.d, cf.c1a, cf.c2a, rn, dn);
+        if (tx >= 1 && ty >= 1) {
+          suB[buf][c][ty - 1][tx - 1] = mine ? dn : T(0);
+          srB[buf][c][ty - 1][tx - 1] = rn;
+        }
+      }
+    };
+
+    T fl[3][4], carry[3][4], own_lo[3], own_ll[3], p0[3];
+    LevelIn R0, R1, R2;
+    EpiIn Q0, Q1, Q2;
+    {
+      LevelIn L0;
+      load_level(ka0 - 1, L0);
+      load_level(ka0, R0);
+      load_level(ka0 + 1, R1);  // kaend >= ka0 + 2
+      if (st && st->done) return;  // group B leaves on the same flag
+      const int b0 = (ka0 - 1) & 1;
+      store_level(b0, L0);
+      __syncthreads();
+#pragma unroll
+      for (int c = 0; c < 3; ++c) {
+        own_lo[c] = suA[b0][c][ty][tx];
+        fl[c][0] = own_lo[c];
+        fl[c][1] = suA[b0][c][ty][tx + 1];
+        fl[c][2] = suA[b0][c][ty + 1][tx + 1];
+        fl[c][3] = suA[b0][c][ty + 1][tx];
+        face4(fl[c]);
+        own_ll[c] = T(0);
+        p0[c] = T(0);
+        carry[c][0] = carry[c][1] = carry[c][2] = carry[c][3] = T(0);
+      }
+    }
+    auto step = [&](auto fn, int ek, const LevelIn& use, LevelIn& fill, const EpiIn& Pu, EpiIn& Pf) {
+      const int bu = (ek + 1) & 1;
+      store_level(bu, use);
+      load_level(ek + 3, fill);
+      load_epi(ek + 1, Pf);
+      __syncthreads();
+      T fu[3][4], lo[3][4];
+#pragma unroll
+      for (int c = 0; c < 3; ++c) {
+        fu[c][0] = suA[bu][c][ty][tx];
+        fu[c][1] = suA[bu][c][ty][tx + 1];
+        fu[c][2] = suA[bu][c][ty + 1][tx + 1];
+        fu[c][3] = suA[bu][c][ty + 1][tx];
+      }
+      if constexpr (decltype(fn)::value) finish(ek - 1, p0, own_ll, Pu);
+      T own_up[3];
+#pragma unroll
+      for (int c = 0; c < 3; ++c) own_up[c] = fu[c][0];
+      brick_layer(fl, fu, carry, use.Ee, wk, lo);
+      const int bl = ek & 1;
+#pragma unroll
+      for (int c = 0; c < 3; ++c) {
+        p0[c] = lo[c][0];
+        syA[bl][0 + c][ty][tx] = lo[c][1];
+        syA[bl][3 + c][ty][tx] = lo[c][2];
+        syA[bl][6 + c][ty][tx] = lo[c][3];
+        own_ll[c] = own_lo[c];
+        own_lo[c] = own_up[c];
+      }
+    };
+    const int n = kaend - ka0 + 1;  // steps: layers ka0 - 1 .. kaend - 1
+    step(skip, ka0 - 1, R0, R2, Q0, Q2);
+    step(skip, ka0, R1, R0, Q1, Q0);
+    int s = 2;
+    for (; s + 3 <= n; s += 3) {
+      step(fin, ka0 - 1 + s, R2, R1, Q2, Q1);
+      step(fin, ka0 + s, R0, R2, Q0, Q2);
+      step(fin, ka0 + 1 + s, R1, R0, Q1, Q0);
+    }
+    if (s < n) step(fin, ka0 - 1 + s, R2, R1, Q2, Q1);
+    if (s + 1 < n) step(fin, ka0 + s, R0, R2, Q0, Q2);
+    __syncthreads();
+    const int last = n % 3;
+    finish(kaend - 1, p0, own_ll, last == 0 ? Q0 : last == 1 ? Q1 : Q2);
+    for (int b = n + 2; b < nbar; ++b) __syncthreads();  // group B is still marching
+  } else {
+    // ---- group B: step k + 1 on node columns I0 .. I0 + 15 (positions 0 .. 14
+    // come from group A, 15 and 16 stay zero), owned 1 .. 13
+    const int I0 = cx * OWN2 - 1, J0 = cy * OWN2 - 1;
+    const int ni = I0 + tx, nj = J0 + ty;
+    const bool owner = tx >= 1 && ty >= 1 && tx <= OWN2 && ty <= OWN2 && ni <= g.nx && nj <= g.ny;
+    const bool ecol = ni >= 0 && ni < g.nx && nj >= 0 && nj < g.ny;
+    for (int e = q; e < 2 * 3 * (TY + 1) * (TX + 1); e += TX * TY) {
+      const int col = e % (TX + 1), row = (e / (TX + 1)) % (TY + 1);
+      if (row > OWN2 + 1 || col > OWN2 + 1) (&suB[0][0][0][0])[e] = T(0);
+    }
+    auto load_E = [&](int ek) -> T {
+      const bool ok = ecol && ek >= 0 && ek < g.nz;
+      return *(ok ? E + (ni + (int64_t)g.nx * (nj + (int64_t)g.ny * ek)) : zpad);
+    };
+    struct EpiIn {
+      uint8_t m;
+      T d;
+      T a[3];  // iterate before step k
+      T v[3];  // d_k
+    };
+    auto load_epi = [&](int k, EpiIn& P) {
+      const bool ok = owner && k >= K0 && k < kend;
+      const int64_t n = ok ? ni + sx * nj + sxy * k : 0;
+      P.m = nmask[n];
+      P.d = invd[n];
+#pragma unroll
+      for (int c = 0; c < 3; ++c) {
+        P.a[c] = acc[3 * n + c];  // unused on the first step (no branch in the march)
+        P.v[c] = dk[3 * n + c];
+      }
+    };
+    const int64_t lev0 = 3 * sxy * K0;
+    const uint32_t chunk_bytes = (uint32_t)(3 * sxy * (kend - K0) * (int64_t)sizeof(T));
+    const __amdgpu_buffer_rsrc_t rr = store_range(rout + lev0, chunk_bytes);
+    const __amdgpu_buffer_rsrc_t ra = store_range(acc + lev0, chunk_bytes);
+    const __amdgpu_buffer_rsrc_t ry = store_range(y + lev0, chunk_bytes);
+    auto finish = [&](int k, const T (&p0)[3], const T (&own)[3], const T (&r1)[3], const EpiIn& P) {
+      const bool mine = owner && k >= K0 && k < kend;
+      const int buf = k & 1;
+      const uint32_t at =
+          mine ? (uint32_t)((ni + sx * nj + sxy * (k - K0)) * 3 * (int64_t)sizeof(T)) : kStoreDrop;
+#pragma unroll
+      for (int c = 0; c < 3; ++c) {
+        const uint32_t o = at + c * (uint32_t)sizeof(T);
+        T v = node_sum(p0[c], syB[buf], c, ty, tx, tyl, txl);
+        const bool fx = (P.m >> c) & 1;
+        if (fx) v = T(0);
+        T rn, dn;
+        cheb_dof(fx, r1[c], v, own[c], P.d, cf.c1b, cf.c2b, rn, dn);
+        store_at(rr, o, rn);
+        store_at(ra, o, (cf.first ? P.v[c] : P.a[c] + P.v[c]) + own[c]);
+        store_at(ry, o, dn);
+      }
+    };
+    // level k of d_{k+1} (zero off the mesh) and this node's r_{k+1}
+    auto read_level = [&](int k, T (&fu)[3][4], T (&r1)[3]) {
+      const bool in = k >= 0 && k <= g.nz;
+      const int b = k & 1;
+#pragma unroll
+      for (int c = 0; c < 3; ++c) {
+        fu[c][0] = in ? suB[b][c][ty][tx] : T(0);
+        fu[c][1] = in ? suB[b][c][ty][tx + 1] : T(0);
+        fu[c][2] = in ? suB[b][c][ty + 1][tx + 1] : T(0);
+        fu[c][3] = in ? suB[b][c][ty + 1][tx] : T(0);
+        r1[c] = srB[b][c][ty][tx];
+      }
+    };
+
+    T fl[3][4], carry[3][4], own_lo[3], own_ll[3], p0[3], r1_lo[3], r1_ll[3];
+    T E0 = load_E(K0 - 1), E1 = load_E(K0), E2;  // layer K0 - 1 + s in slot s % 3
+    EpiIn Q0, Q1, Q2;
+    if (st && st->done) return;  // group A leaves on the same flag
+    for (int b = 0; b < 4; ++b) __syncthreads();  // group A's first levels
+    __syncthreads();                                // level K0 - 1 of d_{k+1} is ready
+    {
+      T fu[3][4], r1[3];
+      read_level(K0 - 1, fu, r1);
+#pragma unroll
+      for (int c = 0; c < 3; ++c) {
+        own_lo[c] = fu[c][0];
+#pragma unroll
+        for (int i = 0; i < 4; ++i) fl[c][i] = fu[c][i];
+        face4(fl[c]);
+        own_ll[c] = T(0);
+        p0[c] = T(0);
+        r1_lo[c] = r1[c];
+        r1_ll[c] = T(0);
+        carry[c][0] = carry[c][1] = carry[c][2] = carry[c][3] = T(0);
+      }
+    }
+    auto step = [&](auto fn, int ek, T Ee, T& Efill, const EpiIn& Pu, EpiIn& Pf) {
+      Efill = load_E(ek + 2);
+      load_epi(ek + 1, Pf);
+      __syncthreads();
+      T fu[3][4], r1_up[3], own_up[3], lo[3][4];
+      read_level(ek + 1, fu, r1_up);
+#pragma unroll
+      for (int c = 0; c < 3; ++c) own_up[c] = fu[c][0];
+      if constexpr (decltype(fn)::value) finish(ek - 1, p0, own_ll, r1_ll, Pu);
+      brick_layer(fl, fu, carry, Ee, wk, lo);
+      const int bl = ek & 1;
+#pragma unroll
+      for (int c = 0; c < 3; ++c) {
+        p0[c] = lo[c][0];
+        syB[bl][0 + c][ty][tx] = lo[c][1];
+        syB[bl][3 + c][ty][tx] = lo[c][2];
+        syB[bl][6 + c][ty][tx] = lo[c][3];
+        own_ll[c] = own_lo[c];
+        own_lo[c] = own_up[c];
+        r1_ll[c] = r1_lo[c];
+        r1_lo[c] = r1_up[c];
+      }
+    };
+    const int n = kend - K0 + 1;  // steps: layers K0 - 1 .. kend - 1
+    step(skip, K0 - 1, E0, E2, Q0, Q2);
+    step(skip, K0, E1, E0, Q1, Q0);
+    int s = 2;
+    for (; s + 3 <= n; s += 3) {
+      step(fin, K0 - 1 + s, E2, E1, Q2, Q1);
+      step(fin, K0 + s, E0, E2, Q0, Q2);
+      step(fin, K0 + 1 + s, E1, E0, Q1, Q0);
+    }
+    if (s < n) step(fin, K0 - 1 + s, E2, E1, Q2, Q1);
+    if (s + 1 < n) step(fin, K0 + s, E0, E2, Q0, Q2);
+    __syncthreads();
+    const int last = n % 3;
+    finish(kend - 1, p0, own_ll, r1_ll, last == 0 ? Q0 : last == 1 ? Q1 : Q2);
+  }
 }
 
 // ---------------------------------------------------------------------------
@@ -794,7 +1174,7 @@ WK<T> scaled_wk(const WalshK& w, double h) {
 
 // Resident workgroups per compute unit of a kernel on the current device
 // (cached per device and kernel).
-static int kxu_slots(const void* kernel) {
+static int kxu_slots(const void* kernel, int threads = TX * TY) {
   static std::mutex mu;
   static std::map<std::pair<int, const void*>, int> cache;
   int dev = 0;
@@ -803,7 +1183,7 @@ static int kxu_slots(const void* kernel) {
   auto it = cache.find({dev, kernel});
   if (it != cache.end()) return it->second;
   int per_cu = 0, cus = 0;
-  if (hipOccupancyMaxActiveBlocksPerMultiprocessor(&per_cu, kernel, TX * TY, 0) != hipSuccess || per_cu < 1)
+  if (hipOccupancyMaxActiveBlocksPerMultiprocessor(&per_cu, kernel, threads, 0) != hipSuccess || per_cu < 1)
     per_cu = 1;
   if (hipDeviceGetAttribute(&cus, hipDeviceAttributeMultiprocessorCount, dev) != hipSuccess || cus < 1)
     cus = 1;
@@ -816,10 +1196,10 @@ static int kxu_slots(const void* kernel) {
 // Tiles of 15 x 15 node columns, split in z into chunks of kc levels so that
 // the workgroups fill whole rounds of the resident slots (no lone tail
 // round) with at most FE_KXU_KCMAX levels each.
-static TileMap kxu_tile_map(const Grid& g, int slots) {
+static TileMap kxu_tile_map(const Grid& g, int slots, int own = OWN) {
   TileMap tm;
-  tm.gx = (g.nx + 1 + OWN - 1) / OWN;
-  tm.gy = (g.ny + 1 + OWN - 1) / OWN;
+  tm.gx = (g.nx + 1 + own - 1) / own;
+  tm.gy = (g.ny + 1 + own - 1) / own;
   const int64_t cols = (int64_t)tm.gx * tm.gy, L = g.nz + 1;
   const int64_t rounds = std::max<int64_t>(1, (cols * L + (int64_t)slots * FE_KXU_KCMAX - 1) /
                                                   ((int64_t)slots * FE_KXU_KCMAX));
@@ -882,6 +1262,30 @@ int kxu_rz_partials(const fe_problem* p, int lev) {
 }
 template int kxu_rz_partials<double>(const fe_problem*, int);
 template int kxu_rz_partials<float>(const fe_problem*, int);
+
+template <typename T>
+hipError_t launch_cheb2(fe_problem* p, int lev, const T* dk, T* y, const T* E, const T* invd, const T* rin,
+                        T* rout, T* acc, const double (&c)[4], int first, CgState* st) {
+  const Grid g = p->L[lev].g;
+  const void* k = reinterpret_cast<const void*>(&cheb2_kernel<T>);
+  const TileMap tm = kxu_tile_map(g, kxu_slots(k, 2 * TX * TY), OWN2);
+  if (3 * (int64_t)(g.nx + 1) * (g.ny + 1) * tm.kc * (int64_t)sizeof(T) >= ((int64_t)1 << 31))
+    return hipErrorInvalidValue;  // the stores' 31-bit offsets
+  Cheb2<T> cf;
+  cf.c1a = (T)c[0];
+  cf.c2a = (T)c[1];
+  cf.c1b = (T)c[2];
+  cf.c2b = (T)c[3];
+  cf.first = first;
+  hipLaunchKernelGGL(cheb2_kernel<T>, dim3(tm.nblk, p->bcount), dim3(2 * TX * TY), 0, p->stream, g, tm, dk, E,
+                     p->L[lev].nmask, scaled_wk<T>(p->wk, p->L[lev].h), invd, rin, rout, acc, y, cf, st,
+                     reinterpret_cast<const T*>(p->zpad), p->bcount > 1 ? p->bstride : (int64_t)0);
+  return hipGetLastError();
+}
+template hipError_t launch_cheb2<double>(fe_problem*, int, const double*, double*, const double*, const double*,
+                                         const double*, double*, double*, const double (&)[4], int, CgState*);
+template hipError_t launch_cheb2<float>(fe_problem*, int, const float*, float*, const float*, const float*,
+                                        const float*, float*, float*, const double (&)[4], int, CgState*);
 
 template <typename T>
 hipError_t launch_kxu_tile(fe_problem* p, int lev, const T* x, const T* E, T* y, CgState* st, int mode,

@@ -6,6 +6,8 @@
 // which keeps the V-cycle symmetric so it can precondition CG.
 #include <hip/hip_runtime.h>
 
+#include <utility>
+
 #include "fe_internal.h"
 
 namespace {
@@ -196,8 +198,8 @@ hipError_t presmooth(fe_problem* p, int l, const T* r, T* z, T* t, int n, CgStat
 // lam_max bounds the spectrum of D^-1 K from above.  The result is a fixed
 // polynomial in D^-1 K applied to D^-1 r: linear, symmetric and (since the
 // Chebyshev residual polynomial stays inside (0, 1) below the interval and
-// below 1 in magnitude on it) positive definite.  r is overwritten by the
-// final residual.
+// below 1 in magnitude on it) positive definite.  r and the level's mg_q
+// buffer are overwritten (the residual of the iteration).
 template <typename T>
 hipError_t chebyshev_solve(fe_problem* p, int l, T* r, T* z, T* d0, T* d1, int deg, CgState* st) {
   const Level& L = p->L[l];
@@ -208,19 +210,30 @@ hipError_t chebyshev_solve(fe_problem* p, int l, T* r, T* z, T* d0, T* d1, int d
   hipLaunchKernelGGL(jacobi0_kernel<T>, dim3(nblocks(L.g.ndof), p->bcount), dim3(FE_BLOCK), 0, p->stream,
                      L.g.ndof, r, lev_invd<T>(L), (T)(1.0 / theta), d0, st, wsh_of(p));
   hipError_t e = hipGetLastError();
-  for (int k = 0; k < deg && e == hipSuccess; ++k) {
-    const double rho_new = 1.0 / (2.0 * sigma - rho);
-    ChebStep<T> cs;
-    cs.res = r;
-    cs.acc = z;
-    cs.c1 = rho_new * rho;
-    cs.c2 = 2.0 * rho_new / delta;
-    cs.first = k == 0;
-    e = launch_kxu_tile<T>(p, l, d0, lev_E<T>(L), d1, st, 6, nullptr, nullptr, nullptr, lev_invd<T>(L), 0.0, &cs);
-    rho = rho_new;
-    T* tmp = d0;
-    d0 = d1;
-    d1 = tmp;
+  T* r_alt = static_cast<T*>(L.mg_q);
+  for (int k = 0; k < deg && e == hipSuccess;) {
+    const double rho1 = 1.0 / (2.0 * sigma - rho);
+    if (p->cheb_per_launch == 2 && k + 2 <= deg && r_alt) {
+      // steps k and k + 1 in one launch; the residual moves to the other buffer
+      const double rho2 = 1.0 / (2.0 * sigma - rho1);
+      const double c[4] = {rho1 * rho, 2.0 * rho1 / delta, rho2 * rho1, 2.0 * rho2 / delta};
+      e = launch_cheb2<T>(p, l, d0, d1, lev_E<T>(L), lev_invd<T>(L), r, r_alt, z, c, k == 0, st);
+      rho = rho2;
+      std::swap(r, r_alt);
+      k += 2;
+    } else {
+      ChebStep<T> cs;
+      cs.res = r;
+      cs.acc = z;
+      cs.c1 = rho1 * rho;
+      cs.c2 = 2.0 * rho1 / delta;
+      cs.first = k == 0;
+      e = launch_kxu_tile<T>(p, l, d0, lev_E<T>(L), d1, st, 6, nullptr, nullptr, nullptr, lev_invd<T>(L), 0.0,
+                             &cs);
+      rho = rho1;
+      k += 1;
+    }
+    std::swap(d0, d1);
   }
   return e;
 }

@@ -24,8 +24,8 @@ STATUS_NAME = {0: "FE_OK", -1: "FE_EINVAL", -2: "FE_ENOMEM", -3: "FE_EDEVICE",
 # Every entry point declared in include/fe_abi.h.
 ABI_SYMBOLS = ("fe_workspace_size", "fe_setup", "fe_apply_K", "fe_solve", "fe_solve_begin",
                "fe_solve_step", "fe_solve_end", "fe_sensitivity",
-               "fe_filter", "oc_update", "fe_set_mg_params", "fe_set_profiling", "fe_kernel_stats",
-               "fe_destroy", "fe_batch_workspace_size", "fe_batch_create", "fe_batch_setup_slot",
+               "fe_filter", "oc_update", "fe_set_mg_params", "fe_set_coarse_fusion", "fe_set_profiling",
+               "fe_kernel_stats", "fe_destroy", "fe_batch_workspace_size", "fe_batch_create", "fe_batch_setup_slot",
                "fe_batch_round_begin", "fe_batch_round_end", "fe_batch_destroy", "fe_last_error")
 
 
@@ -73,6 +73,7 @@ def load_library() -> C.CDLL:
     lib.fe_filter.argtypes = [P, P, P, I32]
     lib.oc_update.argtypes = [P, P, P, P, D, D, P, P]
     lib.fe_set_mg_params.argtypes = [P, I32, I32, D, D]
+    lib.fe_set_coarse_fusion.argtypes = [P, I32]
     lib.fe_set_profiling.argtypes = [P, I32]
     lib.fe_kernel_stats.argtypes = [P, I32, C.POINTER(I64), C.POINTER(D), C.POINTER(D)]
     lib.fe_destroy.argtypes = [P]
@@ -89,7 +90,7 @@ def load_library() -> C.CDLL:
     lib.fe_last_error.restype = C.c_char_p
     for name in ("fe_setup", "fe_apply_K", "fe_solve", "fe_solve_begin", "fe_solve_step",
                  "fe_solve_end", "fe_sensitivity", "fe_filter",
-                 "oc_update", "fe_set_mg_params", "fe_set_profiling", "fe_kernel_stats",
+                 "oc_update", "fe_set_mg_params", "fe_set_coarse_fusion", "fe_set_profiling", "fe_kernel_stats",
                  "fe_batch_create", "fe_batch_setup_slot", "fe_batch_round_begin", "fe_batch_round_end"):
         getattr(lib, name).restype = C.c_int
     _lib = lib
@@ -236,6 +237,10 @@ class Problem:
 
     def set_mg_params(self, nu=1, coarse_sweeps=40, omega=0.35, coarse_ratio=5000.0):
         _check(load_library().fe_set_mg_params(self._h, nu, coarse_sweeps, omega, coarse_ratio))
+
+    def set_coarse_fusion(self, steps_per_launch=2):
+        """Coarsest-level Chebyshev steps per launch (2: pairs fused, 1: one each)."""
+        _check(load_library().fe_set_coarse_fusion(self._h, steps_per_launch))
 
     def set_profiling(self, on, mode=None):
         """Times finest-grid K*u launches: all forms, or only form `mode`."""

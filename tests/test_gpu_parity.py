@@ -426,3 +426,32 @@ def test_solve_degenerate_grids(Ke, grid, precond, levels, precision):
     assert info["rel_res"] <= 1e-10
     assert abs(float(N(c)[0]) - c_ref) / c_ref <= 1e-6
     assert np.abs(N(dc) - dc_ref).max() / np.abs(dc_ref).max() <= 1e-5
+
+
+@pytest.mark.parametrize("grid,levels,deg", [((32, 16, 16), 3, 40), ((60, 32, 28), 3, 7), ((8, 4, 4), 3, 4),
+                                             ((26, 14, 2), 2, 5), ((80, 80, 40), 2, 6),
+                                             ((208, 208, 64), 2, 6)])
+@pytest.mark.parametrize("precision", ["fp64", "fp32_ir"])
+def test_coarse_fusion_bitwise(grid, levels, deg, precision):
+    """Pairs of coarse Chebyshev steps in one launch (each workgroup
+    recomputing the ring of first-step values its second step needs) give
+    bitwise the solve of one launch per step: coarse grids of one or several
+    13-column tiles, one-element-thick coarse grids, z chunks of one level
+    and of many, even and odd degrees."""
+    nx, ny, nz = grid
+    rho = T(synth.density_around(nx, ny, nz, 4))
+    out = []
+    for per_launch in (1, 2):
+        prob = _problem(nx, ny, nz, precision=precision, precond="gmg", mg_levels=levels)
+        prob.set_mg_params(coarse_sweeps=deg)
+        prob.set_coarse_fusion(per_launch)
+        u, info = prob.solve(rho, rtol=1e-6)
+        out.append((N(u), info))
+        if per_launch == 2:
+            with pytest.raises(fe.FEError):
+                prob.set_coarse_fusion(3)
+        prob.close()
+    (u1, i1), (u2, i2) = out
+    assert i1["rel_res"] <= 1e-6
+    assert i1["iters"] == i2["iters"] and i1["outer_iters"] == i2["outer_iters"]
+    assert np.array_equal(u1, u2)
