@@ -38,7 +38,7 @@ def parse():
     ap.add_argument("--precond", default="gmg", choices=["jacobi", "gmg"])
     ap.add_argument("--mg-levels", type=int, default=3)
     ap.add_argument("--mg-nu", type=int, default=1)
-    ap.add_argument("--mg-coarse", type=int, default=40)
+    ap.add_argument("--mg-coarse", type=int, default=48)
     ap.add_argument("--mg-coarse-ratio", type=float, default=5000.0)
     ap.add_argument("--rtol", type=float, default=1e-6)
     ap.add_argument("--volfrac", type=float, default=0.12)
@@ -79,6 +79,52 @@ def traffic_from_profiles(precision: str, grid: str, field: str = "bytes"):
     except Exception:
         return None
     return None
+
+
+def profile_record(grid: str):
+    """The stored rocprofv3 figures of this grid when they were taken on the
+    current kernel source, else None."""
+    path = os.path.join(ROOT, "profiles", f"kxu_tile_{grid}_traffic.json")
+    if not os.path.exists(path):
+        return None
+    try:
+        rec = json.load(open(path))
+        from paper_2104_12282_amd.build import source_digest
+        return rec if rec.get("source_digest") == source_digest() else None
+    except Exception:
+        return None
+
+
+def coarse_solve_record(nx, ny, nz, args):
+    """Roofline context of the coarsest-level Chebyshev launches (two steps
+    each), the largest share of GPU time in the multigrid solve: algorithmic
+    bytes per launch and rocprofv3's average duration from the stored
+    kernel-trace run of the same source."""
+    if args.precond != "gmg":
+        return None
+    s = 2 ** (args.mg_levels - 1)
+    cx, cy, cz = nx // s, ny // s, nz // s
+    nnode = (cx + 1) * (cy + 1) * (cz + 1)
+    vb = 8.0 if args.precision == "fp64" else 4.0
+    # d_k, r_k, acc read and r, acc, d_{k+2} written (3 dofs per node), moduli,
+    # inverse diagonal, fixed-dof mask: each array once
+    nbytes = vb * (6 * 3 * nnode + cx * cy * cz + nnode) + nnode
+    out = {"kernel": "cheb2_kernel<" + ("double" if args.precision == "fp64" else "float")
+                     + ">: two coarsest-level Chebyshev steps per launch",
+           "coarse_grid": [cx, cy, cz], "launches_per_vcycle": args.mg_coarse // 2,
+           "algorithmic_bytes_per_launch": nbytes, "bound": "latency",
+           "note": "about 4 MB per launch on a 22k-element grid: the launch is bound by its chain of "
+                   "dependent memory round trips and march steps, not by HBM bandwidth"}
+    rec = profile_record(f"{nx}x{ny}x{nz}")
+    if rec:
+        for t in rec.get("time_shares", []):
+            if "cheb2_kernel" in t["kernel"]:
+                out["rocprofv3_avg_kernel_us"] = t["avg_us"]
+                out["rocprofv3_share_of_gpu_time"] = t["share"]
+                out["achieved_GBs"] = nbytes / (t["avg_us"] * 1e-6) / 1e9
+                out["frac_of_hbm_peak"] = out["achieved_GBs"] / HBM_PEAK_GBS
+                break
+    return out
 
 
 def cpu_baseline(grid, rtol):
@@ -359,6 +405,14 @@ def main():
                                     "kernel in the profiled run of this command",
                      "algorithmic_bytes_per_launch": ks["bytes_per_launch"]},
     }
+    rec_prof = profile_record(f"{nx}x{ny}x{nz}")
+    if rec_prof and rec_prof.get("time_shares"):
+        out["roofline"]["rocprofv3_time_shares"] = [
+            {"kernel": t["kernel"], "share": round(t["share"], 4), "avg_us": round(t["avg_us"], 2)}
+            for t in rec_prof["time_shares"][:8]]
+    coarse = coarse_solve_record(nx, ny, nz, args)
+    if coarse:
+        out["roofline"]["coarse_solve"] = coarse
     if probe:
         out["copy_probe"] = probe
     if args.alt_precision != "none":

@@ -167,7 +167,7 @@ FE_API fe_status oc_update(fe_problem* p, const double* x, const double* dcx, co
  * [lambda_max / coarse_ratio, lambda_max] (2 <= coarse_ratio <= 1e12) with
  * lambda_max = largest eigenvalue of diag(Ke)^-1 Ke (5.32 for nu = 0.3),
  * which bounds that of D^-1 K for any density field.  Defaults: nu = 1,
- * degree 40, omega = 0.35, coarse_ratio 5000.  The V-cycle is linear and
+ * degree 48, omega = 0.35, coarse_ratio 5000.  The V-cycle is linear and
  * symmetric, and positive definite while omega * lambda_max < 2 (checked:
  * FE_EINVAL otherwise; the Chebyshev residual polynomial stays in (0, 1)
  * below the interval for any ratio), so plain CG applies. */

@@ -164,7 +164,7 @@ struct fe_problem {
 
   // geometric multigrid parameters
   int mg_nu = 1;               // damped Jacobi sweeps before and after the coarse correction
-  int mg_coarse_sweeps = 40;   // Chebyshev degree on the coarsest level
+  int mg_coarse_sweeps = 48;   // Chebyshev degree on the coarsest level
   double mg_omega = 0.35;      // Jacobi damping: below 2 / lambda_max(D^-1 Ke) = 2 / 5.32
   double lam_max = 0.0;        // lambda_max(diag(Ke)^-1 Ke): bounds that of D^-1 K on every level
   double cheb_ratio = 5000.0;  // coarse Chebyshev interval [lam_max / ratio, lam_max]

@@ -235,7 +235,7 @@ class Problem:
                                         _ptr(xn), _ptr(ch)))
         return xn, ch
 
-    def set_mg_params(self, nu=1, coarse_sweeps=40, omega=0.35, coarse_ratio=5000.0):
+    def set_mg_params(self, nu=1, coarse_sweeps=48, omega=0.35, coarse_ratio=5000.0):
         _check(load_library().fe_set_mg_params(self._h, nu, coarse_sweeps, omega, coarse_ratio))
 
     def set_coarse_fusion(self, steps_per_launch=2):

@@ -10,7 +10,8 @@ known size that bench.py --copy-probe performs (hipMemcpy device-to-device,
 kernel __amd_rocclr_copyBuffer), and stores the bytes per launch of the tiled
 K*u kernel next to the digest of the sources it was measured on; given the
 kernel statistics of a --kernel-trace run of the same sources, it also
-stores each kernel's average duration there.
+stores each kernel's average duration there, and every kernel's share of
+the traced GPU time.
 """
 from __future__ import annotations
 
@@ -85,7 +86,14 @@ def traffic(fetch_dir, write_dir, bench_json, out_path, command, stats_csv=None)
                                     "write_bytes": wmax * 1024 * w_scale,
                                     "launches_seen": len(fk)}
     if stats_csv:
-        for r in _rows(stats_csv):
+        rows = _rows(stats_csv)
+        total = sum(float(r["TotalDurationNs"]) for r in rows)
+        rec["time_shares"] = []  # every kernel of the kernel-trace run, largest total first
+        for r in sorted(rows, key=lambda r: -float(r["TotalDurationNs"])):
+            name = r["Name"].replace("void ", "").replace("(anonymous namespace)::", "").split("(")[0]
+            rec["time_shares"].append({"kernel": name, "calls": int(r["Calls"]),
+                                       "avg_us": float(r["AverageNs"]) / 1e3,
+                                       "share": float(r["TotalDurationNs"]) / total})
             if r["Name"] in rec["kernels"]:
                 rec["kernels"][r["Name"]]["trace_avg_us"] = float(r["AverageNs"]) / 1e3
                 rec["kernels"][r["Name"]]["trace_max_us"] = float(r["MaxNs"]) / 1e3
