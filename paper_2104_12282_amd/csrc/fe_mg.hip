@@ -58,25 +58,41 @@ __global__ void __launch_bounds__(FE_BLOCK) restrict_kernel(Grid fg, Grid cg, co
   const int I = (int)(n % (cg.nx + 1)), J = (int)((n / (cg.nx + 1)) % (cg.ny + 1)),
             K = (int)(n / ((int64_t)(cg.nx + 1) * (cg.ny + 1)));
   const int64_t fsx = fg.nx + 1, fsxy = (int64_t)(fg.nx + 1) * (fg.ny + 1);
-  T acc[3] = {T(0), T(0), T(0)};
+  // All 27 fine neighbours are loaded unconditionally (one off the mesh
+  // reads a clamped node and gets weight 0), so the loads issue back to back
+  // instead of one branch and one round trip each; a zero term leaves the
+  // sum unchanged.
+  T v[27][3], w[27];
+#pragma unroll
   for (int c = -1; c <= 1; ++c) {
     const int k = 2 * K + c;
-    if (k < 0 || k > fg.nz) continue;
-    const T wc = c ? T(0.5) : T(1);
+    const bool kin = k >= 0 && k <= fg.nz;
+    const int kc = min(max(k, 0), fg.nz);
+#pragma unroll
     for (int b = -1; b <= 1; ++b) {
       const int j = 2 * J + b;
-      if (j < 0 || j > fg.ny) continue;
-      const T wb = wc * (b ? T(0.5) : T(1));
+      const bool jin = j >= 0 && j <= fg.ny;
+      const int jc = min(max(j, 0), fg.ny);
+#pragma unroll
       for (int a = -1; a <= 1; ++a) {
         const int i = 2 * I + a;
-        if (i < 0 || i > fg.nx) continue;
-        const T w = wb * (a ? T(0.5) : T(1));
-        const int64_t f = i + fsx * j + fsxy * k;
-        acc[0] += w * tf[3 * f];
-        acc[1] += w * tf[3 * f + 1];
-        acc[2] += w * tf[3 * f + 2];
+        const bool in = kin && jin && i >= 0 && i <= fg.nx;
+        const int ic = min(max(i, 0), fg.nx);
+        const int q = 9 * (c + 1) + 3 * (b + 1) + (a + 1);
+        const int64_t f = ic + fsx * jc + fsxy * kc;
+        w[q] = in ? (c ? T(0.5) : T(1)) * (b ? T(0.5) : T(1)) * (a ? T(0.5) : T(1)) : T(0);
+        v[q][0] = tf[3 * f];
+        v[q][1] = tf[3 * f + 1];
+        v[q][2] = tf[3 * f + 2];
       }
     }
+  }
+  T acc[3] = {T(0), T(0), T(0)};
+#pragma unroll
+  for (int q = 0; q < 27; ++q) {
+    acc[0] += w[q] * v[q][0];
+    acc[1] += w[q] * v[q][1];
+    acc[2] += w[q] * v[q][2];
   }
   const uint8_t m = cmask[n];
   if (st && st->done) return;  // read after the loads: no round trip in front of them
@@ -106,18 +122,32 @@ __global__ void __launch_bounds__(FE_BLOCK) prolong_add_kernel(Grid fg, Grid cg,
   const int i0 = i >> 1, i1 = (i + 1) >> 1, j0 = j >> 1, j1 = (j + 1) >> 1, k0 = k >> 1, k1 = (k + 1) >> 1;
   const T wi = (i & 1) ? T(0.5) : T(1), wj = (j & 1) ? T(0.5) : T(1), wk = (k & 1) ? T(0.5) : T(1);
   const int64_t csx = cg.nx + 1, csxy = (int64_t)(cg.nx + 1) * (cg.ny + 1);
-  T acc[3] = {T(0), T(0), T(0)};
+  // the 8 corner loads are issued unconditionally: along an even axis the
+  // second neighbour is the first one again, with weight 0
   const int ii[2] = {i0, i1}, jj[2] = {j0, j1}, kk[2] = {k0, k1};
-  const int ni = (i & 1) ? 2 : 1, nj = (j & 1) ? 2 : 1, nk = (k & 1) ? 2 : 1;
-  for (int c = 0; c < nk; ++c)
-    for (int b = 0; b < nj; ++b)
-      for (int a = 0; a < ni; ++a) {
-        const int64_t q = ii[a] + csx * jj[b] + csxy * kk[c];
-        const T w = wi * wj * wk;
-        acc[0] += w * zc[3 * q];
-        acc[1] += w * zc[3 * q + 1];
-        acc[2] += w * zc[3 * q + 2];
+  const T w = wi * wj * wk;
+  T v[8][3], wq[8];
+#pragma unroll
+  for (int c = 0; c < 2; ++c)
+#pragma unroll
+    for (int b = 0; b < 2; ++b)
+#pragma unroll
+      for (int a = 0; a < 2; ++a) {
+        const int q = 4 * c + 2 * b + a;
+        const bool used = (c == 0 || (k & 1)) && (b == 0 || (j & 1)) && (a == 0 || (i & 1));
+        const int64_t cq = ii[a] + csx * jj[b] + csxy * kk[c];
+        wq[q] = used ? w : T(0);
+        v[q][0] = zc[3 * cq];
+        v[q][1] = zc[3 * cq + 1];
+        v[q][2] = zc[3 * cq + 2];
       }
+  T acc[3] = {T(0), T(0), T(0)};
+#pragma unroll
+  for (int q = 0; q < 8; ++q) {
+    acc[0] += wq[q] * v[q][0];
+    acc[1] += wq[q] * v[q][1];
+    acc[2] += wq[q] * v[q][2];
+  }
   const uint8_t m = fmask[n];
   T zv[3];
 #pragma unroll
