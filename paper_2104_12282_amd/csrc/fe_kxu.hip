@@ -606,18 +606,24 @@ __global__ void __launch_bounds__(TX* TY, FE_KXU_MIN_WAVES) kxu_tile_kernel(Grid
 // columns and the kc + 2 levels that step k + 1 needs around the 13 x 13
 // columns and kc levels the workgroup owns; it hands r_{k+1} and d_{k+1} to
 // group B through LDS, level by level.  Group B marches step k + 1 on those
-// values three levels behind and writes the results.  The ring of step-k
-// values is recomputed by the neighbouring workgroups as well (the price of
-// the saved launch), and every node sum is formed in the tile kernel's order
-// with the same per-dof update, so the result is bitwise that of two
-// single-step launches.
+// values behind it and writes the results.  The ring of step-k values is
+// recomputed by the neighbouring workgroups as well (the price of the saved
+// launch), and every node sum is formed in the tile kernel's order with the
+// same per-dof update, so the result is bitwise that of two single-step
+// launches.
 //
-// Both groups pass the same number of barriers (kend - K0 + 7).  A finishes
-// level l after the barrier of iteration l - K0 + 4 and B reads it after the
-// next barrier; A's next write of the same buffer (level l + 2) follows one
-// barrier after B's read.  The residual is read on the ring, so it cannot be
-// updated in place (rin -> rout); the iterate acc is read and written at
-// owned nodes only (in place).
+// Unlike the tile kernel, a march step here finishes the level of its own
+// brick layer, after a second barrier (bricks, then node sums), so a level
+// reaches group B one step earlier.  Barriers are numbered from 0 for the
+// whole workgroup: A's prologue passes barrier 0 and its step s barriers
+// 2s + 1 and 2s + 2, finishing level l = K0 - 2 + s after the latter, i.e.
+// after barrier 2(l - K0) + 6; B reads level l after barrier 2(l - K0) + 7
+// (its prologue, level K0 - 1, after barrier 5; its step s, level K0 + s,
+// after barrier 2s + 7), and A writes the same buffer again (level l + 2)
+// after barrier 2(l - K0) + 10.  Both groups pass 2(kend - K0) + 9 barriers.
+// The residual is read on the ring, so it cannot be updated in place
+// (rin -> rout); the iterate acc is read and written at owned nodes only (in
+// place).
 template <typename T>
 struct Cheb2 {
   T c1a, c2a;  // step k: d_{k+1} = c1a d_k + c2a D^-1 r_{k+1}
@@ -649,10 +655,10 @@ __global__ void __launch_bounds__(2 * TX * TY) cheb2_kernel(Grid g, TileMap tm, 
     zpad = wshift(zpad, o);
   }
   __shared__ T suA[2][3][TY + 1][TX + 1];  // step-k direction by level (group A's ring)
-  __shared__ T syA[2][9][TY][TX];
+  __shared__ T syA[9][TY][TX];
   __shared__ T suB[2][3][TY + 1][TX + 1];  // d_{k+1} by level, group B's frame
   __shared__ T srB[2][3][TY][TX];          // r_{k+1} by level, group B's frame
-  __shared__ T syB[2][9][TY][TX];
+  __shared__ T syB[9][TY][TX];
 
   int cx, cy, cz;
   tile_of_block(tm, cx, cy, cz);
@@ -660,7 +666,7 @@ __global__ void __launch_bounds__(2 * TX * TY) cheb2_kernel(Grid g, TileMap tm, 
   const int64_t sx = g.nx + 1, sxy = (int64_t)(g.nx + 1) * (g.ny + 1);
   const int q = threadIdx.x % (TX * TY);
   const int tx = q % TX, ty = q / TX;
-  const int nbar = kend - K0 + 7;
+  const int nbar = 2 * (kend - K0) + 9;
   const int txl = tx > 0 ? tx - 1 : 0, tyl = ty > 0 ? ty - 1 : 0;
   const std::false_type skip{};
   const std::true_type fin{};
@@ -720,11 +726,11 @@ __global__ void __launch_bounds__(2 * TX * TY) cheb2_kernel(Grid g, TileMap tm, 
     };
     // level k of step k: r_{k+1} and d_{k+1} (zero off the mesh) to group B
     auto finish = [&](int k, const T (&p0)[3], const T (&own)[3], const EpiIn& P) {
-      const bool mine = owner && k >= 0;
+      const bool mine = owner && k >= 0 && k < kaend;
       const int buf = k & 1;
 #pragma unroll
       for (int c = 0; c < 3; ++c) {
-        T v = node_sum(p0[c], syA[buf], c, ty, tx, tyl, txl);
+        T v = node_sum(p0[c], syA, c, ty, tx, tyl, txl);
         const bool fx = (P.m >> c) & 1;
         if (fx) v = T(0);
         T rn, dn;
@@ -736,7 +742,7 @@ __global__ void __launch_bounds__(2 * TX * TY) cheb2_kernel(Grid g, TileMap tm, 
       }
     };
 
-    T fl[3][4], carry[3][4], own_lo[3], own_ll[3], p0[3];
+    T fl[3][4], carry[3][4], own_lo[3], p0[3];
     LevelIn R0, R1, R2;
     EpiIn Q0, Q1, Q2;
     {
@@ -744,10 +750,11 @@ __global__ void __launch_bounds__(2 * TX * TY) cheb2_kernel(Grid g, TileMap tm, 
       load_level(ka0 - 1, L0);
       load_level(ka0, R0);
       load_level(ka0 + 1, R1);  // kaend >= ka0 + 2
+      load_epi(ka0, Q1);        // finished by step 1
       if (st && st->done) return;  // group B leaves on the same flag
       const int b0 = (ka0 - 1) & 1;
       store_level(b0, L0);
-      __syncthreads();
+      __syncthreads();  // barrier 0
 #pragma unroll
       for (int c = 0; c < 3; ++c) {
         own_lo[c] = suA[b0][c][ty][tx];
@@ -756,16 +763,16 @@ __global__ void __launch_bounds__(2 * TX * TY) cheb2_kernel(Grid g, TileMap tm, 
         fl[c][2] = suA[b0][c][ty + 1][tx + 1];
         fl[c][3] = suA[b0][c][ty + 1][tx];
         face4(fl[c]);
-        own_ll[c] = T(0);
-        p0[c] = T(0);
         carry[c][0] = carry[c][1] = carry[c][2] = carry[c][3] = T(0);
       }
     }
+    // step s: brick layer ek = ka0 - 1 + s, then the node sums of level ek
+    // (slot s % 3 of the rings is used, (s + 2) % 3 filled)
     auto step = [&](auto fn, int ek, const LevelIn& use, LevelIn& fill, const EpiIn& Pu, EpiIn& Pf) {
       const int bu = (ek + 1) & 1;
       store_level(bu, use);
       load_level(ek + 3, fill);
-      load_epi(ek + 1, Pf);
+      load_epi(ek + 2, Pf);
       __syncthreads();
       T fu[3][4], lo[3][4];
 #pragma unroll
@@ -775,25 +782,25 @@ __global__ void __launch_bounds__(2 * TX * TY) cheb2_kernel(Grid g, TileMap tm, 
         fu[c][2] = suA[bu][c][ty + 1][tx + 1];
         fu[c][3] = suA[bu][c][ty + 1][tx];
       }
-      if constexpr (decltype(fn)::value) finish(ek - 1, p0, own_ll, Pu);
       T own_up[3];
 #pragma unroll
       for (int c = 0; c < 3; ++c) own_up[c] = fu[c][0];
       brick_layer(fl, fu, carry, use.Ee, wk, lo);
-      const int bl = ek & 1;
 #pragma unroll
       for (int c = 0; c < 3; ++c) {
         p0[c] = lo[c][0];
-        syA[bl][0 + c][ty][tx] = lo[c][1];
-        syA[bl][3 + c][ty][tx] = lo[c][2];
-        syA[bl][6 + c][ty][tx] = lo[c][3];
-        own_ll[c] = own_lo[c];
-        own_lo[c] = own_up[c];
+        syA[0 + c][ty][tx] = lo[c][1];
+        syA[3 + c][ty][tx] = lo[c][2];
+        syA[6 + c][ty][tx] = lo[c][3];
       }
+      __syncthreads();
+      if constexpr (decltype(fn)::value) finish(ek, p0, own_lo, Pu);
+#pragma unroll
+      for (int c = 0; c < 3; ++c) own_lo[c] = own_up[c];
     };
-    const int n = kaend - ka0 + 1;  // steps: layers ka0 - 1 .. kaend - 1
+    const int n = kaend - ka0 + 1;  // steps: layers ka0 - 1 .. kaend - 1 (n >= 3)
     step(skip, ka0 - 1, R0, R2, Q0, Q2);
-    step(skip, ka0, R1, R0, Q1, Q0);
+    step(fin, ka0, R1, R0, Q1, Q0);
     int s = 2;
     for (; s + 3 <= n; s += 3) {
       step(fin, ka0 - 1 + s, R2, R1, Q2, Q1);
@@ -802,10 +809,7 @@ __global__ void __launch_bounds__(2 * TX * TY) cheb2_kernel(Grid g, TileMap tm, 
     }
     if (s < n) step(fin, ka0 - 1 + s, R2, R1, Q2, Q1);
     if (s + 1 < n) step(fin, ka0 + s, R0, R2, Q0, Q2);
-    __syncthreads();
-    const int last = n % 3;
-    finish(kaend - 1, p0, own_ll, last == 0 ? Q0 : last == 1 ? Q1 : Q2);
-    for (int b = n + 2; b < nbar; ++b) __syncthreads();  // group B is still marching
+    for (int b = 2 * n + 1; b < nbar; ++b) __syncthreads();  // group B is still marching
   } else {
     // ---- group B: step k + 1 on node columns I0 .. I0 + 15 (positions 0 .. 14
     // come from group A, 15 and 16 stay zero), owned 1 .. 13
@@ -845,13 +849,12 @@ __global__ void __launch_bounds__(2 * TX * TY) cheb2_kernel(Grid g, TileMap tm, 
     const __amdgpu_buffer_rsrc_t ry = store_range(y + lev0, chunk_bytes);
     auto finish = [&](int k, const T (&p0)[3], const T (&own)[3], const T (&r1)[3], const EpiIn& P) {
       const bool mine = owner && k >= K0 && k < kend;
-      const int buf = k & 1;
       const uint32_t at =
           mine ? (uint32_t)((ni + sx * nj + sxy * (k - K0)) * 3 * (int64_t)sizeof(T)) : kStoreDrop;
 #pragma unroll
       for (int c = 0; c < 3; ++c) {
         const uint32_t o = at + c * (uint32_t)sizeof(T);
-        T v = node_sum(p0[c], syB[buf], c, ty, tx, tyl, txl);
+        T v = node_sum(p0[c], syB, c, ty, tx, tyl, txl);
         const bool fx = (P.m >> c) & 1;
         if (fx) v = T(0);
         T rn, dn;
@@ -875,12 +878,13 @@ __global__ void __launch_bounds__(2 * TX * TY) cheb2_kernel(Grid g, TileMap tm, 
       }
     };
 
-    T fl[3][4], carry[3][4], own_lo[3], own_ll[3], p0[3], r1_lo[3], r1_ll[3];
+    T fl[3][4], carry[3][4], own_lo[3], p0[3], r1_lo[3];
     T E0 = load_E(K0 - 1), E1 = load_E(K0), E2;  // layer K0 - 1 + s in slot s % 3
     EpiIn Q0, Q1, Q2;
+    load_epi(K0, Q1);  // finished by step 1
     if (st && st->done) return;  // group A leaves on the same flag
-    for (int b = 0; b < 4; ++b) __syncthreads();  // group A's first levels
-    __syncthreads();                                // level K0 - 1 of d_{k+1} is ready
+    for (int b = 0; b < 5; ++b) __syncthreads();  // barriers 0 .. 4: group A's first levels
+    __syncthreads();                                // barrier 5: level K0 - 1 of d_{k+1} is ready
     {
       T fu[3][4], r1[3];
       read_level(K0 - 1, fu, r1);
@@ -890,39 +894,39 @@ __global__ void __launch_bounds__(2 * TX * TY) cheb2_kernel(Grid g, TileMap tm, 
 #pragma unroll
         for (int i = 0; i < 4; ++i) fl[c][i] = fu[c][i];
         face4(fl[c]);
-        own_ll[c] = T(0);
-        p0[c] = T(0);
         r1_lo[c] = r1[c];
-        r1_ll[c] = T(0);
         carry[c][0] = carry[c][1] = carry[c][2] = carry[c][3] = T(0);
       }
     }
+    __syncthreads();  // barrier 6
+    // step s: brick layer ek = K0 - 1 + s, then the node sums of level ek
     auto step = [&](auto fn, int ek, T Ee, T& Efill, const EpiIn& Pu, EpiIn& Pf) {
       Efill = load_E(ek + 2);
-      load_epi(ek + 1, Pf);
+      load_epi(ek + 2, Pf);
       __syncthreads();
       T fu[3][4], r1_up[3], own_up[3], lo[3][4];
       read_level(ek + 1, fu, r1_up);
 #pragma unroll
       for (int c = 0; c < 3; ++c) own_up[c] = fu[c][0];
-      if constexpr (decltype(fn)::value) finish(ek - 1, p0, own_ll, r1_ll, Pu);
       brick_layer(fl, fu, carry, Ee, wk, lo);
-      const int bl = ek & 1;
 #pragma unroll
       for (int c = 0; c < 3; ++c) {
         p0[c] = lo[c][0];
-        syB[bl][0 + c][ty][tx] = lo[c][1];
-        syB[bl][3 + c][ty][tx] = lo[c][2];
-        syB[bl][6 + c][ty][tx] = lo[c][3];
-        own_ll[c] = own_lo[c];
+        syB[0 + c][ty][tx] = lo[c][1];
+        syB[3 + c][ty][tx] = lo[c][2];
+        syB[6 + c][ty][tx] = lo[c][3];
+      }
+      __syncthreads();
+      if constexpr (decltype(fn)::value) finish(ek, p0, own_lo, r1_lo, Pu);
+#pragma unroll
+      for (int c = 0; c < 3; ++c) {
         own_lo[c] = own_up[c];
-        r1_ll[c] = r1_lo[c];
         r1_lo[c] = r1_up[c];
       }
     };
-    const int n = kend - K0 + 1;  // steps: layers K0 - 1 .. kend - 1
+    const int n = kend - K0 + 1;  // steps: layers K0 - 1 .. kend - 1 (n >= 2)
     step(skip, K0 - 1, E0, E2, Q0, Q2);
-    step(skip, K0, E1, E0, Q1, Q0);
+    step(fin, K0, E1, E0, Q1, Q0);
     int s = 2;
     for (; s + 3 <= n; s += 3) {
       step(fin, K0 - 1 + s, E2, E1, Q2, Q1);
@@ -931,9 +935,6 @@ __global__ void __launch_bounds__(2 * TX * TY) cheb2_kernel(Grid g, TileMap tm, 
     }
     if (s < n) step(fin, K0 - 1 + s, E2, E1, Q2, Q1);
     if (s + 1 < n) step(fin, K0 + s, E0, E2, Q0, Q2);
-    __syncthreads();
-    const int last = n % 3;
-    finish(kend - 1, p0, own_ll, r1_ll, last == 0 ? Q0 : last == 1 ? Q1 : Q2);
   }
 }
 
