@@ -119,6 +119,55 @@ __device__ inline void store_at(__amdgpu_buffer_rsrc_t r, uint32_t off, float v)
   __builtin_amdgcn_raw_buffer_store_b32(__builtin_bit_cast(int, v), r, (int)off, 0, 0);
 }
 
+// Loads through raw buffer ranges: a load at or past the end of its range
+// reads zero, which is the value of every node and brick off the mesh, so
+// no lane selects a pad address or branches around its load.  Offsets are
+// formed as (index in a level + index of the level) * unit, each part set to
+// kOffIndex when the lane's node or the level is out of range; a range holds
+// fewer than kOffIndex nodes or elements (bounded on the host), so any part
+// past it lands past the range's end without wrapping (2 kOffIndex * 24
+// bytes stays below 2^32).
+constexpr uint32_t kOffIndex = 1u << 26;
+
+__device__ inline __amdgpu_buffer_rsrc_t load_range(const void* base, int64_t bytes) {
+  return __builtin_amdgcn_make_buffer_rsrc(const_cast<void*>(base), (short)0, (int)bytes, 0x00020000);
+}
+__device__ inline double load1(__amdgpu_buffer_rsrc_t r, uint32_t off, double) {
+  typedef int i32x2 __attribute__((ext_vector_type(2)));
+  return __builtin_bit_cast(double, (i32x2)__builtin_amdgcn_raw_buffer_load_b64(r, (int)off, 0, 0));
+}
+__device__ inline float load1(__amdgpu_buffer_rsrc_t r, uint32_t off, float) {
+  return __builtin_bit_cast(float, (int)__builtin_amdgcn_raw_buffer_load_b32(r, (int)off, 0, 0));
+}
+__device__ inline void load3(__amdgpu_buffer_rsrc_t r, uint32_t off, double (&v)[3]) {
+  typedef int i32x2 __attribute__((ext_vector_type(2)));
+  typedef int i32x4 __attribute__((ext_vector_type(4)));
+  const i32x4 a = __builtin_amdgcn_raw_buffer_load_b128(r, (int)off, 0, 0);
+  const i32x2 b = __builtin_amdgcn_raw_buffer_load_b64(r, (int)(off + 16), 0, 0);
+  v[0] = __builtin_bit_cast(double, (i32x2){a[0], a[1]});
+  v[1] = __builtin_bit_cast(double, (i32x2){a[2], a[3]});
+  v[2] = __builtin_bit_cast(double, b);
+}
+__device__ inline void load3(__amdgpu_buffer_rsrc_t r, uint32_t off, float (&v)[3]) {
+  typedef int i32x3 __attribute__((ext_vector_type(3)));
+  const i32x3 a = __builtin_amdgcn_raw_buffer_load_b96(r, (int)off, 0, 0);
+  // the elements go through scalars: __builtin_bit_cast of a vector element
+  // reads the vector's first element on this toolchain
+  const int a0 = a[0], a1 = a[1], a2 = a[2];
+  v[0] = __builtin_bit_cast(float, a0);
+  v[1] = __builtin_bit_cast(float, a1);
+  v[2] = __builtin_bit_cast(float, a2);
+}
+__device__ inline uint8_t load_u8(__amdgpu_buffer_rsrc_t r, uint32_t off) {
+  return __builtin_amdgcn_raw_buffer_load_b8(r, (int)off, 0, 0);
+}
+// index part of a load offset: idx when in range, else kOffIndex
+__device__ inline uint32_t off_part(bool in, int64_t idx) { return in ? (uint32_t)idx : kOffIndex; }
+// level part: (k - lo) * stride for lo <= k < lo + n, else kOffIndex (one unsigned compare)
+__device__ inline uint32_t lev_part(int k, int lo, int n, int64_t stride) {
+  return (uint32_t)(k - lo) < (uint32_t)n ? (uint32_t)((int64_t)(k - lo) * stride) : kOffIndex;
+}
+
 // Epilogue operands of the modes below.
 template <typename T>
 struct Epi {
@@ -683,27 +732,31 @@ __global__ void __launch_bounds__(2 * TX * TY) cheb2_kernel(Grid g, TileMap tm, 
     const bool hslot = q < TX + TY + 1;
     const int hx = q <= TY ? TX : q - (TY + 1), hy = q <= TY ? q : TY;
     const int hi = I0 + hx, hj = J0 + hy;
-    auto node_ok = [&](int i, int j, int k) {
-      return i >= 0 && i <= g.nx && j >= 0 && j <= g.ny && k >= 0 && k <= g.nz;
-    };
+    // load ranges: node levels [nlo, nhi], brick layers [elo, ehi]
+    const int nlo = max(ka0 - 1, 0), nhi = min(kaend, g.nz);
+    const int elo = max(ka0 - 1, 0), ehi = min(kaend - 1, g.nz - 1);
+    const int64_t nel = (int64_t)g.nx * g.ny, nlev = nhi - nlo + 1;
+    const __amdgpu_buffer_rsrc_t rx = load_range(dk + 3 * sxy * nlo, 3 * sxy * nlev * (int64_t)sizeof(T));
+    const __amdgpu_buffer_rsrc_t rr = load_range(rin + 3 * sxy * nlo, 3 * sxy * nlev * (int64_t)sizeof(T));
+    const __amdgpu_buffer_rsrc_t rd = load_range(invd + sxy * nlo, sxy * nlev * (int64_t)sizeof(T));
+    const __amdgpu_buffer_rsrc_t rm = load_range(nmask + sxy * nlo, sxy * nlev);
+    const __amdgpu_buffer_rsrc_t re =
+        load_range(E + nel * elo, ehi >= elo ? nel * (ehi - elo + 1) * (int64_t)sizeof(T) : 0);
+    const uint32_t o_own = off_part(ni >= 0 && ni <= g.nx && nj >= 0 && nj <= g.ny, ni + sx * nj);
+    const uint32_t o_halo = off_part(hslot && hi >= 0 && hi <= g.nx && hj >= 0 && hj <= g.ny, hi + sx * hj);
+    const uint32_t o_epi = off_part(owner, ni + sx * nj);
+    const uint32_t o_el = off_part(ecol, ni + (int64_t)g.nx * nj);
     struct LevelIn {
       T own[3];
       T halo[3];
       T Ee;  // modulus of the brick layer below this level
     };
-    auto fetch = [&](bool ok, int i, int j, int k, T (&v)[3]) {
-      const T* src = ok ? dk + 3 * (i + sx * j + sxy * k) : zpad;
-      v[0] = src[0];
-      v[1] = src[1];
-      v[2] = src[2];
-    };
     auto load_level = [&](int k, LevelIn& L) {
-      const bool need = k <= kaend;
-      fetch(need && node_ok(ni, nj, k), ni, nj, k, L.own);
-      fetch(need && hslot && node_ok(hi, hj, k), hi, hj, k, L.halo);
+      const uint32_t lk = lev_part(k, nlo, (int)nlev, sxy);
+      load3(rx, (o_own + lk) * (uint32_t)(3 * sizeof(T)), L.own);
+      load3(rx, (o_halo + lk) * (uint32_t)(3 * sizeof(T)), L.halo);
       const int ek = k - 1;
-      const bool ok = need && ecol && ek >= 0 && ek < g.nz;
-      L.Ee = *(ok ? E + (ni + (int64_t)g.nx * (nj + (int64_t)g.ny * ek)) : zpad);
+      L.Ee = load1(re, (o_el + lev_part(ek, elo, ehi - elo + 1, nel)) * (uint32_t)sizeof(T), T());
     };
     auto store_level = [&](int buf, const LevelIn& L) {
 #pragma unroll
@@ -717,12 +770,11 @@ __global__ void __launch_bounds__(2 * TX * TY) cheb2_kernel(Grid g, TileMap tm, 
       T d;
     };
     auto load_epi = [&](int k, EpiIn& P) {
-      const bool ok = owner && k >= 0 && k >= ka0 && k < kaend;
-      const int64_t n = ok ? ni + sx * nj + sxy * k : 0;
-      P.m = nmask[n];
-#pragma unroll
-      for (int c = 0; c < 3; ++c) P.r[c] = rin[3 * n + c];
-      P.d = invd[n];
+      const int e0 = max(ka0, nlo);  // finished levels from here to kaend - 1
+      const uint32_t o = o_epi + lev_part(k, e0, kaend - e0, sxy) + (uint32_t)((e0 - nlo) * sxy);
+      P.m = load_u8(rm, o);
+      load3(rr, o * (uint32_t)(3 * sizeof(T)), P.r);
+      P.d = load1(rd, o * (uint32_t)sizeof(T), T());
     };
     // level k of step k: r_{k+1} and d_{k+1} (zero off the mesh) to group B
     auto finish = [&](int k, const T (&p0)[3], const T (&own)[3], const EpiIn& P) {
@@ -821,9 +873,19 @@ __global__ void __launch_bounds__(2 * TX * TY) cheb2_kernel(Grid g, TileMap tm, 
       const int col = e % (TX + 1), row = (e / (TX + 1)) % (TY + 1);
       if (row > OWN2 + 1 || col > OWN2 + 1) (&suB[0][0][0][0])[e] = T(0);
     }
+    // load ranges: owned node levels [K0, kend), brick layers [elo, ehi]
+    const int elo = max(K0 - 1, 0), ehi = min(kend - 1, g.nz - 1);
+    const int64_t nel = (int64_t)g.nx * g.ny, nlev = kend - K0;
+    const __amdgpu_buffer_rsrc_t re =
+        load_range(E + nel * elo, ehi >= elo ? nel * (ehi - elo + 1) * (int64_t)sizeof(T) : 0);
+    const __amdgpu_buffer_rsrc_t rm = load_range(nmask + sxy * K0, sxy * nlev);
+    const __amdgpu_buffer_rsrc_t rd = load_range(invd + sxy * K0, sxy * nlev * (int64_t)sizeof(T));
+    const __amdgpu_buffer_rsrc_t rac = load_range(acc + 3 * sxy * K0, 3 * sxy * nlev * (int64_t)sizeof(T));
+    const __amdgpu_buffer_rsrc_t rv = load_range(dk + 3 * sxy * K0, 3 * sxy * nlev * (int64_t)sizeof(T));
+    const uint32_t o_el = off_part(ecol, ni + (int64_t)g.nx * nj);
+    const uint32_t o_epi = off_part(owner, ni + sx * nj);
     auto load_E = [&](int ek) -> T {
-      const bool ok = ecol && ek >= 0 && ek < g.nz;
-      return *(ok ? E + (ni + (int64_t)g.nx * (nj + (int64_t)g.ny * ek)) : zpad);
+      return load1(re, (o_el + lev_part(ek, elo, ehi - elo + 1, nel)) * (uint32_t)sizeof(T), T());
     };
     struct EpiIn {
       uint8_t m;
@@ -832,15 +894,11 @@ __global__ void __launch_bounds__(2 * TX * TY) cheb2_kernel(Grid g, TileMap tm, 
       T v[3];  // d_k
     };
     auto load_epi = [&](int k, EpiIn& P) {
-      const bool ok = owner && k >= K0 && k < kend;
-      const int64_t n = ok ? ni + sx * nj + sxy * k : 0;
-      P.m = nmask[n];
-      P.d = invd[n];
-#pragma unroll
-      for (int c = 0; c < 3; ++c) {
-        P.a[c] = acc[3 * n + c];  // unused on the first step (no branch in the march)
-        P.v[c] = dk[3 * n + c];
-      }
+      const uint32_t o = o_epi + lev_part(k, K0, kend - K0, sxy);
+      P.m = load_u8(rm, o);
+      P.d = load1(rd, o * (uint32_t)sizeof(T), T());
+      load3(rac, o * (uint32_t)(3 * sizeof(T)), P.a);  // unused on the first step (no branch in the march)
+      load3(rv, o * (uint32_t)(3 * sizeof(T)), P.v);
     };
     const int64_t lev0 = 3 * sxy * K0;
     const uint32_t chunk_bytes = (uint32_t)(3 * sxy * (kend - K0) * (int64_t)sizeof(T));
@@ -1270,8 +1328,9 @@ hipError_t launch_cheb2(fe_problem* p, int lev, const T* dk, T* y, const T* E, c
   const Grid g = p->L[lev].g;
   const void* k = reinterpret_cast<const void*>(&cheb2_kernel<T>);
   const TileMap tm = kxu_tile_map(g, kxu_slots(k, 2 * TX * TY), OWN2);
-  if (3 * (int64_t)(g.nx + 1) * (g.ny + 1) * tm.kc * (int64_t)sizeof(T) >= ((int64_t)1 << 31))
-    return hipErrorInvalidValue;  // the stores' 31-bit offsets
+  if (3 * (int64_t)(g.nx + 1) * (g.ny + 1) * tm.kc * (int64_t)sizeof(T) >= ((int64_t)1 << 31) ||
+      (int64_t)(g.nx + 1) * (g.ny + 1) * (tm.kc + 4) >= (int64_t)kOffIndex)
+    return hipErrorInvalidValue;  // the stores' 31-bit offsets, the load ranges' index bound
   Cheb2<T> cf;
   cf.c1a = (T)c[0];
   cf.c2a = (T)c[1];
