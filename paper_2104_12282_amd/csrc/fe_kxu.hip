@@ -376,12 +376,23 @@ __global__ void __launch_bounds__(TX* TY, FE_KXU_MIN_WAVES) kxu_tile_kernel(Grid
   const int hx = h <= TY ? TX : h - (TY + 1), hy = h <= TY ? h : TY;
   const int hi = I0 + hx, hj = J0 + hy;
 
-  auto node_ok = [&](int i, int j, int k) {
-    return i >= 0 && i <= g.nx && j >= 0 && j <= g.ny && k >= 0 && k <= g.nz;
-  };
-  // Loads outside the mesh read a zero pad instead, so no instruction has to
-  // touch a load's registers before the data is used (a select after the
-  // load would make the wave wait for it at once).
+  // Loads go through raw buffer ranges (zero past the range: the nodes and
+  // bricks off the mesh), so no instruction has to touch a load's registers
+  // before the data is used and no lane branches around a load.  Node levels
+  // loaded: [nlo, nhi]; brick layers: [elo, ehi].
+  const int nlo = max(K0 - 1, 0), nhi = min(kend, g.nz), elo = max(K0 - 1, 0), ehi = min(kend - 1, g.nz - 1);
+  const int64_t nlev = nhi - nlo + 1, nel = (int64_t)g.nx * g.ny;
+  const int64_t vbytes = 3 * sxy * nlev * (int64_t)sizeof(T);
+  const __amdgpu_buffer_rsrc_t rx = load_range(x + 3 * sxy * nlo, vbytes);
+  const __amdgpu_buffer_rsrc_t rxd =
+      load_range(XIN == 1 ? (const void*)(xi.invd + sxy * nlo) : (const void*)x, XIN == 1 ? vbytes / 3 : 0);
+  const __amdgpu_buffer_rsrc_t rxp =
+      load_range(XIN == 2 ? (const void*)(xi.pold + 3 * sxy * nlo) : (const void*)x, XIN == 2 ? vbytes : 0);
+  const __amdgpu_buffer_rsrc_t re =
+      load_range(E + nel * elo, ehi >= elo ? nel * (ehi - elo + 1) * (int64_t)sizeof(T) : 0);
+  const uint32_t o_own = off_part(ni >= 0 && ni <= g.nx && nj >= 0 && nj <= g.ny, ni + sx * nj);
+  const uint32_t o_halo = off_part(hslot && hi >= 0 && hi <= g.nx && hj >= 0 && hj <= g.ny, hi + sx * hj);
+  const uint32_t o_el = off_part(ecol, ni + (int64_t)g.nx * nj);
   struct LevelIn {
     T own[3];
     T halo[3];
@@ -389,29 +400,16 @@ __global__ void __launch_bounds__(TX* TY, FE_KXU_MIN_WAVES) kxu_tile_kernel(Grid
     T d_own, d_halo;       // XIN 1: inverse diagonal
     T p_own[3], p_halo[3];  // XIN 2: previous direction
   };
-  auto fetch = [&](bool ok, int i, int j, int k, T (&v)[3]) {
-    const T* src = ok ? x + 3 * (i + sx * j + sxy * k) : zpad;
-    v[0] = src[0];
-    v[1] = src[1];
-    v[2] = src[2];
-  };
-  auto node_in = [&](bool ok, int i, int j, int k, T (&v)[3], T& d, T (&pv)[3]) {
-    fetch(ok, i, j, k, v);
-    if (XIN == 1) d = *(ok ? xi.invd + (i + sx * j + sxy * k) : zpad);
-    if (XIN == 2) {  // loaded also on the first iteration (then unused: see operand)
-      const T* src = ok ? xi.pold + 3 * (i + sx * j + sxy * k) : zpad;
-      pv[0] = src[0];
-      pv[1] = src[1];
-      pv[2] = src[2];
-    }
+  auto node_in = [&](uint32_t o, T (&v)[3], T& d, T (&pv)[3]) {
+    load3(rx, o * (uint32_t)(3 * sizeof(T)), v);
+    if (XIN == 1) d = load1(rxd, o * (uint32_t)sizeof(T), T());
+    if (XIN == 2) load3(rxp, o * (uint32_t)(3 * sizeof(T)), pv);  // also on the first iteration (then unused)
   };
   auto load_level = [&](int k, LevelIn& L) {
-    const bool need = k <= kend;
-    node_in(need && node_ok(ni, nj, k), ni, nj, k, L.own, L.d_own, L.p_own);
-    node_in(need && hslot && node_ok(hi, hj, k), hi, hj, k, L.halo, L.d_halo, L.p_halo);
-    const int ek = k - 1;
-    const bool ok = need && ecol && ek >= 0 && ek < g.nz;
-    L.Ee = *(ok ? E + (ni + (int64_t)g.nx * (nj + (int64_t)g.ny * ek)) : zpad);
+    const uint32_t lk = lev_part(k, nlo, (int)nlev, sxy);  // k <= kend: nhi bounds it
+    node_in(o_own + lk, L.own, L.d_own, L.p_own);
+    node_in(o_halo + lk, L.halo, L.d_halo, L.p_halo);
+    L.Ee = load1(re, (o_el + lev_part(k - 1, elo, ehi - elo + 1, nel)) * (uint32_t)sizeof(T), T());
   };
   // the operand value of a node from what was loaded for it
   auto operand = [&](const T (&v)[3], T d, const T (&pv)[3], int c) -> T {
@@ -436,20 +434,27 @@ __global__ void __launch_bounds__(TX* TY, FE_KXU_MIN_WAVES) kxu_tile_kernel(Grid
     T a[3];
     double b2[3];
   };
+  // epilogue ranges: the owned levels [K0, kend)
+  const int64_t elev = kend - K0;
+  const __amdgpu_buffer_rsrc_t rm = load_range(nmask + sxy * K0, sxy * elev);
+  const __amdgpu_buffer_rsrc_t rb2 =
+      load_range(MODE == 2 ? (const void*)(ep.b64 + 3 * sxy * K0) : (const void*)x, MODE == 2 ? 24 * sxy * elev : 0);
+  const bool has_b = MODE == 3 || MODE == 4 || MODE == 5, has_d = MODE == 3 || MODE == 5 || MODE == 6;
+  const __amdgpu_buffer_rsrc_t rb = load_range(
+      has_b ? (const void*)(ep.bT + 3 * sxy * K0) : MODE == 6 ? (const void*)(ep.res + 3 * sxy * K0) : (const void*)x,
+      has_b || MODE == 6 ? 3 * sxy * elev * (int64_t)sizeof(T) : 0);
+  const __amdgpu_buffer_rsrc_t ra = load_range(MODE == 6 ? (const void*)(ep.acc + 3 * sxy * K0) : (const void*)x,
+                                               MODE == 6 ? 3 * sxy * elev * (int64_t)sizeof(T) : 0);
+  const __amdgpu_buffer_rsrc_t rdi = load_range(has_d ? (const void*)(ep.invd + sxy * K0) : (const void*)x,
+                                                has_d ? sxy * elev * (int64_t)sizeof(T) : 0);
+  const uint32_t o_epi = off_part(owner, ni + sx * nj);
   auto load_epi = [&](int k, EpiIn& P) {
-    const bool ok = owner && k >= K0 && k < kend;
-    const int64_t n = ok ? ni + sx * nj + sxy * k : 0;
-    P.m = nmask[n];
-#pragma unroll
-    for (int c = 0; c < 3; ++c) {
-      if (MODE == 2) P.b2[c] = ep.b64[3 * n + c];
-      if (MODE == 3 || MODE == 4 || MODE == 5) P.b[c] = ep.bT[3 * n + c];
-      if (MODE == 6) {
-        P.b[c] = ep.res[3 * n + c];
-        P.a[c] = ep.acc[3 * n + c];  // unused on the first step (no branch in the march)
-      }
-    }
-    if (MODE == 3 || MODE == 5 || MODE == 6) P.d = ep.invd[n];
+    const uint32_t o = o_epi + lev_part(k, K0, (int)elev, sxy);
+    P.m = load_u8(rm, o);
+    if (MODE == 2) load3(rb2, o * 24u, P.b2);
+    if (has_b || MODE == 6) load3(rb, o * (uint32_t)(3 * sizeof(T)), P.b);
+    if (MODE == 6) load3(ra, o * (uint32_t)(3 * sizeof(T)), P.a);  // unused on the first step (no branch)
+    if (has_d) P.d = load1(rdi, o * (uint32_t)sizeof(T), T());
   };
 
   double dot = 0.0;
@@ -1263,8 +1268,11 @@ static TileMap kxu_tile_map(const Grid& g, int slots, int own = OWN) {
   const int64_t rounds = std::max<int64_t>(1, (cols * L + (int64_t)slots * FE_KXU_KCMAX - 1) /
                                                   ((int64_t)slots * FE_KXU_KCMAX));
   int64_t nzc = std::max<int64_t>(1, std::min<int64_t>(L, rounds * slots / cols));
-  // the stores address a chunk's levels with 31-bit byte offsets
-  const int64_t kc_fit = std::max<int64_t>(1, ((int64_t)1 << 31) / (24 * (int64_t)(g.nx + 1) * (g.ny + 1)));
+  // the stores address a chunk's levels with 31-bit byte offsets, the loads
+  // index fewer than kOffIndex nodes (kc + 2 levels)
+  const int64_t sxy = (int64_t)(g.nx + 1) * (g.ny + 1);
+  const int64_t kc_fit =
+      std::max<int64_t>(1, std::min<int64_t>(((int64_t)1 << 31) / (24 * sxy), (int64_t)kOffIndex / sxy - 4));
   tm.kc = (int)std::min<int64_t>((L + nzc - 1) / nzc, kc_fit);
   tm.nzc = (int)((L + tm.kc - 1) / tm.kc);
   tm.nblk = (int)(cols * tm.nzc);
@@ -1282,7 +1290,9 @@ static int launch_tile(hipStream_t stream, const Grid& g, const T* x, const T* E
                        const T* zpad, const XinK<T>& xi, const FoldK& fo, int bcount, int64_t bstride) {
   const void* k = reinterpret_cast<const void*>(&kxu_tile_kernel<T, MODE, XIN>);
   const TileMap tm = kxu_tile_map(g, kxu_slots(k));
-  if (3 * (int64_t)(g.nx + 1) * (g.ny + 1) * tm.kc * (int64_t)sizeof(T) >= ((int64_t)1 << 31)) return -1;
+  if (3 * (int64_t)(g.nx + 1) * (g.ny + 1) * tm.kc * (int64_t)sizeof(T) >= ((int64_t)1 << 31) ||
+      (int64_t)(g.nx + 1) * (g.ny + 1) * (tm.kc + 4) >= (int64_t)kOffIndex)
+    return -1;
   hipLaunchKernelGGL((kxu_tile_kernel<T, MODE, XIN>), dim3(tm.nblk, bcount), dim3(TX * TY), 0, stream, g, tm, x,
                      E, nm, wk, y, ep, st, partials, out, zpad, xi, fo, bcount > 1 ? bstride : (int64_t)0);
   return tm.nblk;
