@@ -10,8 +10,9 @@ known size that bench.py --copy-probe performs (hipMemcpy device-to-device,
 kernel __amd_rocclr_copyBuffer), and stores the bytes per launch of the tiled
 K*u kernel next to the digest of the sources it was measured on; given the
 kernel statistics of a --kernel-trace run of the same sources, it also
-stores each kernel's average duration there, and every kernel's share of
-the traced GPU time.
+stores each kernel's average duration there (all launches, and the launches
+that did their work: the kernel trace next to the statistics file gives the
+per-launch durations), and every kernel's share of the traced GPU time.
 """
 from __future__ import annotations
 
@@ -86,6 +87,20 @@ def traffic(fetch_dir, write_dir, bench_json, out_path, command, stats_csv=None)
                                     "write_bytes": wmax * 1024 * w_scale,
                                     "launches_seen": len(fk)}
     if stats_csv:
+        # per-launch durations from the kernel trace of the same run: the mean
+        # over launches that did their work (those that met the CG stop flag
+        # return at once; launches shorter than a quarter of the kernel's
+        # longest are left out)
+        work = {}
+        traces = glob.glob(os.path.join(os.path.dirname(stats_csv), "*kernel_trace.csv"))
+        if traces:
+            durs = {}
+            for r in _rows(traces[0]):
+                durs.setdefault(r["Kernel_Name"], []).append(
+                    (int(r["End_Timestamp"]) - int(r["Start_Timestamp"])) / 1e3)
+            for name, ds in durs.items():
+                kept = [d for d in ds if d >= 0.25 * max(ds)]
+                work[name] = sum(kept) / len(kept)
         rows = _rows(stats_csv)
         total = sum(float(r["TotalDurationNs"]) for r in rows)
         rec["time_shares"] = []  # every kernel of the kernel-trace run, largest total first
@@ -93,9 +108,11 @@ def traffic(fetch_dir, write_dir, bench_json, out_path, command, stats_csv=None)
             name = r["Name"].replace("void ", "").replace("(anonymous namespace)::", "").split("(")[0]
             rec["time_shares"].append({"kernel": name, "calls": int(r["Calls"]),
                                        "avg_us": float(r["AverageNs"]) / 1e3,
+                                       "work_avg_us": work.get(r["Name"]),
                                        "share": float(r["TotalDurationNs"]) / total})
             if r["Name"] in rec["kernels"]:
                 rec["kernels"][r["Name"]]["trace_avg_us"] = float(r["AverageNs"]) / 1e3
+                rec["kernels"][r["Name"]]["trace_work_avg_us"] = work.get(r["Name"])
                 rec["kernels"][r["Name"]]["trace_max_us"] = float(r["MaxNs"]) / 1e3
     with open(out_path, "w") as fh:
         json.dump(rec, fh, indent=1)
