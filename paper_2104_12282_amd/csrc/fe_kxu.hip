@@ -118,6 +118,21 @@ __device__ inline void store_at(__amdgpu_buffer_rsrc_t r, uint32_t off, double v
 __device__ inline void store_at(__amdgpu_buffer_rsrc_t r, uint32_t off, float v) {
   __builtin_amdgcn_raw_buffer_store_b32(__builtin_bit_cast(int, v), r, (int)off, 0, 0);
 }
+// a node's three values: one 16-byte and one 8-byte store (double), one
+// 12-byte store (float)
+__device__ inline void store3(__amdgpu_buffer_rsrc_t r, uint32_t off, const double (&v)[3]) {
+  typedef int i32x2 __attribute__((ext_vector_type(2)));
+  typedef int i32x4 __attribute__((ext_vector_type(4)));
+  const i32x2 a = __builtin_bit_cast(i32x2, v[0]), b = __builtin_bit_cast(i32x2, v[1]);
+  const i32x4 ab = {a.x, a.y, b.x, b.y};
+  __builtin_amdgcn_raw_buffer_store_b128(ab, r, (int)off, 0, 0);
+  __builtin_amdgcn_raw_buffer_store_b64(__builtin_bit_cast(i32x2, v[2]), r, (int)(off + 16), 0, 0);
+}
+__device__ inline void store3(__amdgpu_buffer_rsrc_t r, uint32_t off, const float (&v)[3]) {
+  typedef int i32x3 __attribute__((ext_vector_type(3)));
+  const i32x3 a = {__builtin_bit_cast(int, v[0]), __builtin_bit_cast(int, v[1]), __builtin_bit_cast(int, v[2])};
+  __builtin_amdgcn_raw_buffer_store_b96(a, r, (int)off, 0, 0);
+}
 
 // Loads through raw buffer ranges: a load at or past the end of its range
 // reads zero, which is the value of every node and brick off the mesh, so
@@ -478,9 +493,9 @@ __global__ void __launch_bounds__(TX* TY, FE_KXU_MIN_WAVES) kxu_tile_kernel(Grid
     const int buf = k & 1;
     const uint32_t at =
         mine ? (uint32_t)((ni + sx * nj + sxy * (k - K0)) * 3 * (int64_t)sizeof(T)) : kStoreDrop;
+    T yv[3], rv[3], av[3];
 #pragma unroll
     for (int c = 0; c < 3; ++c) {
-      const uint32_t o = at + c * (uint32_t)sizeof(T);
       T v2 = node_sum(p0[c], sy[buf], c, ty, tx, tyl, txl);
       const bool fx = (P.m >> c) & 1;
       if (fx) v2 = T(0);
@@ -496,14 +511,17 @@ __global__ void __launch_bounds__(TX* TY, FE_KXU_MIN_WAVES) kxu_tile_kernel(Grid
         v2 = fx ? T(0) : P.b[c] - v2;
       } else if (MODE == 6) {
         const T dv = own[c];
-        T rn;
-        cheb_dof(fx, P.b[c], v2, dv, P.d, ep.c1, ep.c2, rn, v2);
-        store_at(rres, o, rn);
-        store_at(racc, o, ep.first ? dv : P.a[c] + dv);
+        cheb_dof(fx, P.b[c], v2, dv, P.d, ep.c1, ep.c2, rv[c], v2);
+        av[c] = ep.first ? dv : P.a[c] + dv;
       }
-      store_at(ry, o, v2);
-      if (XIN) store_at(rxo, o, own[c]);
+      yv[c] = v2;
     }
+    if (MODE == 6) {
+      store3(rres, at, rv);
+      store3(racc, at, av);
+    }
+    store3(ry, at, yv);
+    if (XIN) store3(rxo, at, own);
   };
 
   T fl[3][4];      // lower face of the current brick, x-y transformed
@@ -914,18 +932,18 @@ __global__ void __launch_bounds__(2 * TX * TY) cheb2_kernel(Grid g, TileMap tm, 
       const bool mine = owner && k >= K0 && k < kend;
       const uint32_t at =
           mine ? (uint32_t)((ni + sx * nj + sxy * (k - K0)) * 3 * (int64_t)sizeof(T)) : kStoreDrop;
+      T rn[3], an[3], dn[3];
 #pragma unroll
       for (int c = 0; c < 3; ++c) {
-        const uint32_t o = at + c * (uint32_t)sizeof(T);
         T v = node_sum(p0[c], syB, c, ty, tx, tyl, txl);
         const bool fx = (P.m >> c) & 1;
         if (fx) v = T(0);
-        T rn, dn;
-        cheb_dof(fx, r1[c], v, own[c], P.d, cf.c1b, cf.c2b, rn, dn);
-        store_at(rr, o, rn);
-        store_at(ra, o, (cf.first ? P.v[c] : P.a[c] + P.v[c]) + own[c]);
-        store_at(ry, o, dn);
+        cheb_dof(fx, r1[c], v, own[c], P.d, cf.c1b, cf.c2b, rn[c], dn[c]);
+        an[c] = (cf.first ? P.v[c] : P.a[c] + P.v[c]) + own[c];
       }
+      store3(rr, at, rn);
+      store3(ra, at, an);
+      store3(ry, at, dn);
     };
     // level k of d_{k+1} (zero off the mesh) and this node's r_{k+1}
     auto read_level = [&](int k, T (&fu)[3][4], T (&r1)[3]) {
