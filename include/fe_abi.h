@@ -191,9 +191,8 @@ FE_API fe_status fe_set_coarse_fusion(fe_problem* p, int32_t steps_per_launch);
  * fe_kernel_stats returns the number of launches and their summed duration
  * in ms since the last reset, and the mean algorithmic bytes of one launch
  * (each array the kernel reads or writes counted once).  Launches that met
- * the CG stop flag (they return at once, after the solve converged inside a
- * chunk of iterations) are not counted: within each harvest of recorded
- * launches, those shorter than a quarter of the longest are left out. */
+ * the CG stop flag (the iterations of a captured chunk after the solve
+ * stopped inside it return at once) are not counted. */
 FE_API fe_status fe_set_profiling(fe_problem* p, int32_t on);
 FE_API fe_status fe_kernel_stats(fe_problem* p, int32_t reset, int64_t* launches,
                           double* total_ms, double* bytes_per_launch);

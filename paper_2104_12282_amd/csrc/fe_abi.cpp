@@ -331,7 +331,11 @@ hipError_t enqueue_chunk(fe_problem* p, T* x, T* r, T* pv, T* q) {
       }
     }
     if (gc.exec) {
-      if (gc.prof) p->last_replay = &gc;
+      if (gc.prof) {
+        p->last_replay = &gc;
+        gc.iters = n;
+        gc.iter0 = p->h_st->iter;  // the state copied after the previous stage
+      }
       return hipGraphLaunch(gc.exec, p->stream);
     }
   }
@@ -340,31 +344,25 @@ hipError_t enqueue_chunk(fe_problem* p, T* x, T* r, T* pv, T* q) {
   return e;
 }
 
-// Adds one harvest of recorded launches to the statistics.  A launch that
-// met the CG stop flag returns at once (a few us, no work): launches shorter
-// than a quarter of the longest one of the harvest are not counted, so the
-// mean is that of launches that did their work.
-void kstats_add(KStats& ks, const std::vector<float>& ms, const double* bytes) {
-  float top = 0.0f;
-  for (float m : ms) top = std::max(top, m);
-  for (size_t i = 0; i < ms.size(); ++i) {
-    if (ms[i] < 0.25f * top) continue;
-    ks.total_ms += ms[i];
-    ks.total_bytes += bytes[i];
-    ks.launches += 1;
-  }
-}
-
 // Adds the kernel times the last profiled graph replay recorded (the replay
-// has completed: its stage event fired).
+// has completed: its stage event fired, and the state copied after it is in
+// h_st).  Only the iterations that ran count: once CG has stopped inside a
+// chunk, the launches of its remaining iterations meet the stop flag and
+// return at once, without work.  The launches of one iteration are
+// recorded in order, the same number for every iteration.
 fe_status harvest_graph_events(fe_problem* p) {
   GraphChunk* gc = p->last_replay;
   p->last_replay = nullptr;
-  if (!gc || !gc->exec || !gc->prof) return FE_OK;
-  std::vector<float> ms(gc->bytes.size(), 0.0f);
-  for (size_t i = 0; i < gc->bytes.size(); ++i)
-    HIP_TRY(hipEventElapsedTime(&ms[i], gc->ev[2 * i], gc->ev[2 * i + 1]));
-  kstats_add(p->kst, ms, gc->bytes.data());
+  if (!gc || !gc->exec || !gc->prof || gc->iters < 1) return FE_OK;
+  const size_t per_iter = gc->bytes.size() / (size_t)gc->iters;
+  const int ran = std::min(gc->iters, std::max(1, p->h_st->iter - gc->iter0));
+  for (size_t i = 0; i < per_iter * (size_t)ran; ++i) {
+    float ms = 0.0f;
+    HIP_TRY(hipEventElapsedTime(&ms, gc->ev[2 * i], gc->ev[2 * i + 1]));
+    p->kst.total_ms += ms;
+    p->kst.total_bytes += gc->bytes[i];
+    p->kst.launches += 1;
+  }
   return FE_OK;
 }
 
@@ -924,9 +922,13 @@ extern "C" fe_status fe_kernel_stats(fe_problem* p, int32_t reset, int64_t* laun
   KStats& ks = p->kst;
   if (ks.pending) {
     HIP_TRY(hipStreamSynchronize(p->stream));
-    std::vector<float> ms((size_t)ks.pending, 0.0f);
-    for (int64_t i = 0; i < ks.pending; ++i) HIP_TRY(hipEventElapsedTime(&ms[i], ks.ev[2 * i], ks.ev[2 * i + 1]));
-    kstats_add(ks, ms, ks.bytes.data());
+    for (int64_t i = 0; i < ks.pending; ++i) {
+      float ms = 0.0f;
+      HIP_TRY(hipEventElapsedTime(&ms, ks.ev[2 * i], ks.ev[2 * i + 1]));
+      ks.total_ms += ms;
+      ks.total_bytes += ks.bytes[i];
+    }
+    ks.launches += ks.pending;
     ks.pending = 0;
   }
   if (launches) *launches = ks.launches;

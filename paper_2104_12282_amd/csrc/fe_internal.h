@@ -89,6 +89,8 @@ struct GraphChunk {
   bool prof = false;            // captured with profiling events
   std::vector<hipEvent_t> ev;   // event pairs recorded by each replay
   std::vector<double> bytes;
+  int iters = 0;                // CG iterations of the chunk
+  int iter0 = 0;                // completed CG iterations when the last replay was launched
 };
 
 // Non-blocking solve: a host state machine advanced by fe_solve_step; every

@@ -101,17 +101,23 @@ __global__ void __launch_bounds__(FE_BLOCK) restrict_kernel(Grid fg, Grid cg, co
 }
 
 // out_f = z_f + P z_c (out may alias z: each thread touches only its own node).
+// With rf given, z_f is the first Jacobi sweep from zero, formed here as
+// (omega D^-1) r_f exactly as the launch that used it formed it, instead of
+// being stored there and read back.
 template <typename T>
 __global__ void __launch_bounds__(FE_BLOCK) prolong_add_kernel(Grid fg, Grid cg, const T* zf,
                                                                const T* __restrict__ zc,
                                                                const uint8_t* __restrict__ fmask, T* out,
-                                                               const CgState* st, int64_t wsh) {
+                                                               const T* __restrict__ rf, const T* __restrict__ invd,
+                                                               T omega, const CgState* st, int64_t wsh) {
   if (wsh) {  // batched launch: this workgroup's problem
     const int64_t o = batch_offset(wsh);
     zf = wshift(zf, o);
     zc = wshift(zc, o);
     fmask = wshift(fmask, o);
     out = wshift(out, o);
+    rf = wshift(rf, o);
+    invd = wshift(invd, o);
     st = wshift(st, o);
   }
   const int64_t n = blockIdx.x * (int64_t)FE_BLOCK + threadIdx.x;
@@ -150,8 +156,14 @@ __global__ void __launch_bounds__(FE_BLOCK) prolong_add_kernel(Grid fg, Grid cg,
   }
   const uint8_t m = fmask[n];
   T zv[3];
+  if (rf) {
+    const T s = omega * invd[n];
 #pragma unroll
-  for (int q = 0; q < 3; ++q) zv[q] = zf[3 * n + q];
+    for (int q = 0; q < 3; ++q) zv[q] = s * rf[3 * n + q];
+  } else {
+#pragma unroll
+    for (int q = 0; q < 3; ++q) zv[q] = zf[3 * n + q];
+  }
   if (st && st->done) return;  // read after the loads: no round trip in front of them
 #pragma unroll
   for (int q = 0; q < 3; ++q) out[3 * n + q] = ((m >> q) & 1) ? T(0) : zv[q] + acc[q];
@@ -205,8 +217,7 @@ hipError_t presmooth(fe_problem* p, int l, const T* r, T* z, T* t, int n, CgStat
   fz.xin = 1;
   fz.invd = lev_invd<T>(L);
   fz.s = om;
-  if (n == 1) {
-    fz.xout = z;  // z = omega D^-1 r, t = r - K z
+  if (n == 1) {  // t = r - K z with z = omega D^-1 r (not stored: the prolongation forms it again)
     return launch_kxu_tile<T>(p, l, r, lev_E<T>(L), t, st, 4, nullptr, nullptr, r, nullptr, 0.0, nullptr, &fz);
   }
   // sweeps 2 .. n ping-pong between t and z so that the last lands in z
@@ -290,11 +301,14 @@ hipError_t launch_vcycle(fe_problem* p, int l, const T* r, T* z, CgState* st, in
                      C.g, t, C.nmask, rc, st, wsh_of(p));
   if ((e = hipGetLastError()) != hipSuccess) return e;
   if ((e = launch_vcycle<T>(p, l + 1, rc, zc, st, RZ_NONE, 0)) != hipSuccess) return e;
-  // post-smoothing, arranged so the last sweep writes z
+  // post-smoothing, arranged so the last sweep writes z; with one fused
+  // pre-smoothing sweep z was not stored and the prolongation forms it
   const int nu = p->mg_nu;
+  const bool z_implicit = nu == 1 && (!(l == 0 && p->mfma_l0) || (l == 0 && fold_rr > 0));
   T* a = (nu % 2) ? t : z;
   hipLaunchKernelGGL(prolong_add_kernel<T>, dim3(nblocks(L.g.nnode), p->bcount), dim3(FE_BLOCK), 0, p->stream,
-                     L.g, C.g, z, zc, L.nmask, a, st, wsh_of(p));
+                     L.g, C.g, z, zc, L.nmask, a, z_implicit ? r : nullptr, z_implicit ? lev_invd<T>(L) : nullptr,
+                     (T)p->mg_omega, st, wsh_of(p));
   if ((e = hipGetLastError()) != hipSuccess) return e;
   T* b = (a == t) ? z : t;
   for (int s = 0; s < nu; ++s) {
