@@ -848,6 +848,55 @@ extern "C" fe_status fe_filter(fe_problem* p, const double* in, double* out, int
   return FE_OK;
 }
 
+namespace {
+
+void drop_oc_graph(OcGraph& g) {
+  if (g.exec) (void)hipGraphExecDestroy(g.exec);
+  g.exec = nullptr;
+}
+
+// The OC update is some fifty short launches, most of which return at once
+// once the multiplier search has converged; replayed as one graph they cost
+// the host a single launch.  The graph bakes in the arrays and parameters, so
+// a call with others launches directly and the next call with those captures.
+hipError_t enqueue_oc(fe_problem* p, const double* x, const double* dcx, const double* dv, double volfrac,
+                      double move, double* x_new, double* change) {
+  OcGraph& g = p->ocg;
+  const void* key[5] = {x, dcx, dv, x_new, change};
+  const bool same = g.seen && std::equal(key, key + 5, g.key) && g.volfrac == volfrac && g.move == move;
+  if (!p->use_graphs || !p->cap_stream || !same) {
+    drop_oc_graph(g);
+    std::copy(key, key + 5, g.key);
+    g.volfrac = volfrac;
+    g.move = move;
+    g.seen = true;
+    return launch_oc(p, x, dcx, dv, volfrac, move, x_new, change);
+  }
+  if (!g.exec) {
+    hipStream_t saved = p->stream;
+    p->stream = p->cap_stream;
+    hipError_t e = hipStreamBeginCapture(p->cap_stream, hipStreamCaptureModeRelaxed);
+    hipGraph_t graph = nullptr;
+    if (e == hipSuccess) {
+      e = launch_oc(p, x, dcx, dv, volfrac, move, x_new, change);
+      const hipError_t e2 = hipStreamEndCapture(p->cap_stream, &graph);
+      if (e == hipSuccess) e = e2;
+    }
+    p->stream = saved;
+    if (e == hipSuccess && graph) e = hipGraphInstantiate(&g.exec, graph, nullptr, nullptr, 0);
+    if (graph) (void)hipGraphDestroy(graph);
+    if (e != hipSuccess || !g.exec) {
+      (void)hipGetLastError();
+      drop_oc_graph(g);
+      p->use_graphs = false;  // direct launches from now on
+      return launch_oc(p, x, dcx, dv, volfrac, move, x_new, change);
+    }
+  }
+  return hipGraphLaunch(g.exec, p->stream);
+}
+
+}  // namespace
+
 extern "C" fe_status oc_update(fe_problem* p, const double* x, const double* dcx, const double* dv,
                                double volfrac, double move, double* x_new, double* change) {
   CHECK_HANDLE(p);
@@ -859,7 +908,7 @@ extern "C" fe_status oc_update(fe_problem* p, const double* x, const double* dcx
     fe_set_error("volfrac must lie in (0, 1] and move must be > 0");
     return FE_EINVAL;
   }
-  HIP_TRY(launch_oc(p, x, dcx, dv, volfrac, move, x_new, change));
+  HIP_TRY(enqueue_oc(p, x, dcx, dv, volfrac, move, x_new, change));
   return FE_OK;
 }
 
@@ -947,6 +996,7 @@ extern "C" void fe_destroy(fe_problem* p) {
   if (p->stream) (void)hipStreamSynchronize(p->stream);
   drop_graph(p->chunk64);
   drop_graph(p->chunk32);
+  drop_oc_graph(p->ocg);
   for (hipEvent_t e : p->kst.ev) (void)hipEventDestroy(e);
   if (p->done_ev) (void)hipEventDestroy(p->done_ev);
   if (p->cap_stream) (void)hipStreamDestroy(p->cap_stream);

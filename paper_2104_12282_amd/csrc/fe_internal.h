@@ -93,6 +93,16 @@ struct GraphChunk {
   int iter0 = 0;                // completed CG iterations when the last replay was launched
 };
 
+// The OC update captured as one graph for the arrays and parameters of the
+// call it serves; a key met for the first time is launched directly and
+// recorded, its second call captures.
+struct OcGraph {
+  hipGraphExec_t exec = nullptr;
+  const void* key[5] = {};
+  double volfrac = 0.0, move = 0.0;
+  bool seen = false;
+};
+
 // Non-blocking solve: a host state machine advanced by fe_solve_step; every
 // stage ends with a copy of the few scalars it needs into pinned host memory
 // and an event.
@@ -157,6 +167,7 @@ struct fe_problem {
   hipEvent_t done_ev = nullptr;
   hipStream_t cap_stream = nullptr;
   GraphChunk chunk64, chunk32;
+  OcGraph ocg;
   GraphChunk* last_replay = nullptr;  // profiled graph replayed since the last harvest
   bool use_graphs = true;
   bool in_batch = false;  // a slot of an fe_batch: its CG chunks run in the batch's replays

@@ -586,62 +586,111 @@ __device__ inline double oc_candidate(const OcState* os, int c) {
   return lo + (hi - lo) * (double)(c + 1) / (double)(OC_NC + 1);
 }
 
+// One pass over the elements evaluates the volume at the OC_NC candidates.
+// Over the candidate range [s_0, s_last] an element is either pinned at lo or
+// at hi (contributing a constant), free (contributing w a s, linear in s), or
+// crosses a bound inside the range; only the last kind is evaluated candidate
+// by candidate.  Those elements are packed into LDS, where the lane of
+// candidate c in each wave sums them in element order.  Once the bracket is
+// narrow few elements cross a bound and a pass costs one read of x, dc, dv.
 __global__ void __launch_bounds__(FE_BLOCK) oc_pass_kernel(int64_t n, const double* __restrict__ x,
                                                            const double* __restrict__ dcx,
                                                            const double* __restrict__ dv, double move,
                                                            const OcState* os, double* partials) {
   if (os->done) return;
-  const int cand = threadIdx.x & (OC_NC - 1);
-  const int sub = threadIdx.x / OC_NC;  // 0..3
+  const int tid = threadIdx.x;
+  const int lane = tid & 63, wv = tid >> 6;
+  const int cand = tid & (OC_NC - 1);
+  const int sub = tid / OC_NC;  // 0..3
   const double sc = oc_candidate(os, cand);
+  const double s_first = oc_candidate(os, 0), s_last = oc_candidate(os, OC_NC - 1);
   __shared__ double sa[FE_BLOCK], slo[FE_BLOCK], shi[FE_BLOCK], sw[FE_BLOCK];
-  double vol = 0.0;
+  __shared__ int wcount[FE_BLOCK / 64];
+  double cst = 0.0, lin = 0.0, vol = 0.0;
   for (int64_t base = blockIdx.x * (int64_t)FE_BLOCK; base < n; base += (int64_t)gridDim.x * FE_BLOCK) {
-    const int64_t e = base + threadIdx.x;
+    const int64_t e = base + tid;
+    bool cross = false;
+    double a = 0.0, lo = 0.0, hi = 0.0, w = 0.0;
     if (e < n) {
-      double a, lo, hi, w;
       oc_elem(x, dcx, dv, e, move, a, lo, hi, w);
-      sa[threadIdx.x] = a;
-      slo[threadIdx.x] = lo;
-      shi[threadIdx.x] = hi;
-      sw[threadIdx.x] = w;
-    } else {
-      sa[threadIdx.x] = 0.0;
-      slo[threadIdx.x] = 0.0;
-      shi[threadIdx.x] = 0.0;
-      sw[threadIdx.x] = 0.0;
+      const double v0 = a * s_first, v1 = a * s_last;
+      if (v1 <= lo)
+        cst += w * fmin(lo, hi);
+      else if (v0 >= hi)
+        cst += w * hi;
+      else if (v0 >= lo && v1 <= hi)
+        lin += w * a;
+      else
+        cross = true;
+    }
+    const uint64_t m = __ballot(cross);
+    if (lane == 0) wcount[wv] = __popcll(m);
+    __syncthreads();
+    int off = 0, tot = 0;
+    for (int k = 0; k < FE_BLOCK / 64; ++k) {
+      const int c = wcount[k];
+      off += k < wv ? c : 0;
+      tot += c;
+    }
+    if (cross) {
+      const int pos = off + __popcll(m & ((1ull << lane) - 1ull));
+      sa[pos] = a;
+      slo[pos] = lo;
+      shi[pos] = hi;
+      sw[pos] = w;
     }
     __syncthreads();
-    for (int q = sub; q < FE_BLOCK; q += FE_BLOCK / OC_NC)
-      vol += sw[q] * fmin(fmax(sa[q] * sc, slo[q]), shi[q]);
+    for (int q = sub; q < tot; q += FE_BLOCK / OC_NC) vol += sw[q] * fmin(fmax(sa[q] * sc, slo[q]), shi[q]);
     __syncthreads();
   }
-  // combine the four sub-sums of each candidate in fixed order
-  __shared__ double part[FE_BLOCK];
-  part[threadIdx.x] = vol;
+  // block sums of the constant and linear parts (fixed tree), and of the four
+  // sub-sums of each candidate (fixed order)
+  __shared__ double part[FE_BLOCK], pc[FE_BLOCK], pl[FE_BLOCK];
+  part[tid] = vol;
+  pc[tid] = cst;
+  pl[tid] = lin;
   __syncthreads();
-  if (threadIdx.x < OC_NC) {
+  for (int h = FE_BLOCK / 2; h > 0; h >>= 1) {
+    if (tid < h) {
+      pc[tid] += pc[tid + h];
+      pl[tid] += pl[tid + h];
+    }
+    __syncthreads();
+  }
+  if (tid < OC_NC) {
     double s = 0.0;
-    for (int q = 0; q < FE_BLOCK / OC_NC; ++q) s += part[q * OC_NC + threadIdx.x];
-    partials[(size_t)threadIdx.x * gridDim.x + blockIdx.x] = s;
+    for (int q = 0; q < FE_BLOCK / OC_NC; ++q) s += part[q * OC_NC + tid];
+    partials[(size_t)blockIdx.x * OC_NC + tid] = (pc[0] + pl[0] * sc) + s;
   }
 }
 
-__global__ void __launch_bounds__(FE_BLOCK) oc_pass_finalize(int nb, const double* __restrict__ partials,
-                                                             OcState* os) {
+// Sums the per-workgroup partials of a pass: thread (c, q) adds those of
+// candidate c from every OC_FIN_Q-th workgroup starting at q, in workgroup
+// order, its loads issued OC_FIN_BATCH at a time; the OC_FIN_Q sums are then
+// added in q order (a fixed order throughout).
+#define OC_FIN_Q 16
+#define OC_FIN_BATCH 16
+__global__ void __launch_bounds__(OC_NC * OC_FIN_Q) oc_pass_finalize(int nb, const double* __restrict__ partials,
+                                                                    OcState* os) {
   if (os->done) return;
-  // thread (c, q): candidate c, every (FE_BLOCK / OC_NC)-th block from q;
-  // the quarter sums are then added in q order (fixed)
   const int c = threadIdx.x % OC_NC, q = threadIdx.x / OC_NC;
   double s = 0.0;
-  for (int b = q; b < nb; b += FE_BLOCK / OC_NC) s += partials[(size_t)c * nb + b];
-  __shared__ double part[FE_BLOCK];
+  int b = q;
+  for (; b + (OC_FIN_BATCH - 1) * OC_FIN_Q < nb; b += OC_FIN_BATCH * OC_FIN_Q) {
+    double v[OC_FIN_BATCH];
+#pragma unroll
+    for (int k = 0; k < OC_FIN_BATCH; ++k) v[k] = partials[(size_t)(b + k * OC_FIN_Q) * OC_NC + c];
+#pragma unroll
+    for (int k = 0; k < OC_FIN_BATCH; ++k) s += v[k];
+  }
+  for (; b < nb; b += OC_FIN_Q) s += partials[(size_t)b * OC_NC + c];
+  __shared__ double part[OC_NC * OC_FIN_Q];
   __shared__ double vols[OC_NC];
   part[threadIdx.x] = s;
   __syncthreads();
   if (threadIdx.x < OC_NC) {
     double v = 0.0;
-    for (int k = 0; k < FE_BLOCK / OC_NC; ++k) v += part[k * OC_NC + threadIdx.x];
+    for (int k = 0; k < OC_FIN_Q; ++k) v += part[k * OC_NC + threadIdx.x];
     vols[threadIdx.x] = v;
   }
   __syncthreads();
@@ -976,14 +1025,14 @@ hipError_t launch_oc(fe_problem* p, const double* x, const double* dcx, const do
   OcState* os = reinterpret_cast<OcState*>(p->oc);
   const double target = volfrac * (double)n;
   const int nb = red_grid(n);
-  // the candidate passes keep 64 partials per workgroup: fewer, fuller workgroups
-  const int nbp = nb < 512 ? nb : 512;
+  // the candidate passes keep 64 partials per workgroup: at most 1024 workgroups
+  const int nbp = nb < 1024 ? nb : 1024;
   hipLaunchKernelGGL(oc_prep_kernel, dim3(nb), dim3(FE_BLOCK), 0, p->stream, n, x, dcx, dv, move, p->partials);
   hipLaunchKernelGGL(oc_prep_finalize, dim3(1), dim3(FE_BLOCK), 0, p->stream, nb, p->partials, target, os);
   for (int pass = 0; pass < 24; ++pass) {  // passes after convergence return at once
     hipLaunchKernelGGL(oc_pass_kernel, dim3(nbp), dim3(FE_BLOCK), 0, p->stream, n, x, dcx, dv, move, os,
                        p->partials);
-    hipLaunchKernelGGL(oc_pass_finalize, dim3(1), dim3(FE_BLOCK), 0, p->stream, nbp, p->partials, os);
+    hipLaunchKernelGGL(oc_pass_finalize, dim3(1), dim3(OC_NC * OC_FIN_Q), 0, p->stream, nbp, p->partials, os);
   }
   hipLaunchKernelGGL(oc_final_kernel, dim3(nb), dim3(FE_BLOCK), 0, p->stream, n, x, dcx, dv, move, os, x_new,
                      p->partials);

@@ -114,3 +114,26 @@ def test_fullsize_filter_and_oc(grid):
     xn = N(xn)
     assert np.abs(xn - xn_ref).max() <= 1e-9
     assert abs(float(N(ch)[0]) - ch_ref) <= 1e-9
+
+
+def test_fullsize_oc_near_binary():
+    """A late design: most elements at a bound or a move limit over the whole
+    multiplier bracket, a few hundred crossing a bound inside it; repeated
+    calls give the same bits."""
+    nx, ny, nz = 96, 48, 48
+    ne = nx * ny * nz
+    rng = np.random.default_rng(6)
+    solid = rng.random(ne) < 0.2
+    x = np.where(solid, 1.0 - rng.uniform(0.0, 1e-3, ne), rng.uniform(1e-3, 2e-3, ne))
+    mid = rng.random(ne) < 0.01
+    x[mid] = rng.uniform(0.05, 0.95, mid.sum())
+    dcx = -np.where(solid | mid, rng.uniform(0.5, 2.0, ne), rng.uniform(1e-9, 1e-6, ne))
+    dv = O.filter_matrix(nx, ny, nz, 1.5).T @ np.ones(ne)
+    prob = fe.Problem(nx, ny, nz, T(synth.cantilever_edge_load(nx, ny, nz)), device=DEV)
+    for volfrac, move in ((0.21, 0.2), (0.2, 0.05)):
+        xn_ref, _, ch_ref = O.oc_update(x, dcx, dv, volfrac, move)
+        xn, ch = prob.oc_update(T(x), T(dcx), T(dv), volfrac, move)
+        xn2, _ = prob.oc_update(T(x), T(dcx), T(dv), volfrac, move)
+        assert torch.equal(xn, xn2)
+        assert np.abs(N(xn) - xn_ref).max() <= 1e-9
+        assert abs(float(N(ch)[0]) - ch_ref) <= 1e-9
