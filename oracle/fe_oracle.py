@@ -385,3 +385,33 @@ def oc_update(x, dcx, dv, volfrac, move, rel_tol=1e-12):
     lam = 0.5 * (l1 + l2)
     xn = x_of(lam)
     return xn, lam, float(np.max(np.abs(xn - x)))
+
+
+# ---------------------------------------------------------------------------
+# Coarse scale of the two-scale scheme (Sec. III-C, Sec. III-E; the
+# coarse-graining and coarse-solve steps of Alg. 1)
+# ---------------------------------------------------------------------------
+def block_mean(nx, ny, nz, z, nb) -> np.ndarray:
+    """z_C: each coarse element takes the mean of the design variables over
+    its nb x nb x nb block of fine elements (nb divides nx, ny, nz).  Coarse
+    element (I, J, K) holds fine elements i = nb I .. nb I + nb - 1 (and so on);
+    the coarse grid is numbered like the fine one."""
+    if nb < 1 or nx % nb or ny % nb or nz % nb:
+        raise ValueError("nb must be >= 1 and divide nx, ny, nz")
+    z = np.asarray(z, dtype=np.float64).reshape(nz // nb, nb, ny // nb, nb, nx // nb, nb)
+    return z.mean(axis=(1, 3, 5)).ravel()
+
+
+def coarse_scale_solve(nx, ny, nz, z, nb, f_c, nu=0.3, h=1.0, r=1.5, E0=1.0, Emin=1e-9, penal=3.0):
+    """u_C of K_C(z_C) u_C = f_C on the coarse mesh of (nx/nb, ny/nb, nz/nb)
+    elements of edge nb h, with the design-to-stiffness map of the fine
+    scale: z_C = block_mean(z), the density filter of the same physical
+    radius (r / nb coarse elements), SIMP, supports clamped at x = 0.  With
+    nb = 1 this is the fine-scale solve.  Returns (z_C, u_C, c_C)."""
+    ncx, ncy, ncz = nx // nb, ny // nb, nz // nb
+    zc = block_mean(nx, ny, nz, z, nb)
+    rho_c = filter_matrix(ncx, ncy, ncz, r / nb) @ zc
+    Ke = hex8_ke(nu, h=nb * h)
+    u = solve_direct(ncx, ncy, ncz, simp_modulus(rho_c, E0, Emin, penal), Ke, f_c,
+                     clamp_x0_fixed(ncx, ncy, ncz))
+    return zc, u, compliance(f_c, u)
