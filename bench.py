@@ -38,8 +38,10 @@ def parse():
     ap.add_argument("--precond", default="gmg", choices=["jacobi", "gmg"])
     ap.add_argument("--mg-levels", type=int, default=3)
     ap.add_argument("--mg-nu", type=int, default=1)
-    ap.add_argument("--mg-coarse", type=int, default=48)
-    ap.add_argument("--mg-coarse-ratio", type=float, default=5000.0)
+    ap.add_argument("--mg-coarse", type=int, default=0,
+                    help="coarsest-level Chebyshev degree (0: the library's default for the coarsest grid)")
+    ap.add_argument("--mg-coarse-ratio", type=float, default=0.0,
+                    help="coarsest-level Chebyshev interval ratio (0: the library's default)")
     ap.add_argument("--rtol", type=float, default=1e-6)
     ap.add_argument("--volfrac", type=float, default=0.12)
     ap.add_argument("--move", type=float, default=0.2)
@@ -48,6 +50,8 @@ def parse():
                     help="seeded smoothed densities of the precision study (0 = skip it)")
     ap.add_argument("--mg4", type=int, default=1,
                     help="also run the float64 loop with a 4-level hierarchy (context line)")
+    ap.add_argument("--two-scale", type=int, default=1,
+                    help="time the coarse-scale solves of the two-scale scheme beside the fine solve")
     ap.add_argument("--cpu-grid", type=str, default="80x40x20")
     ap.add_argument("--serving", type=int, default=256,
                     help="requests of the serving stream to run (0: skip)")
@@ -95,7 +99,18 @@ def profile_record(grid: str):
         return None
 
 
-def coarse_solve_record(nx, ny, nz, args):
+def apply_mg(prob, args):
+    """Multigrid settings of the command line on a problem; 0 keeps the
+    library's default for that problem's coarsest grid."""
+    if args.precond != "gmg" or prob.cfg.precond != 1:
+        return None
+    cur = prob.mg_params()
+    prob.set_mg_params(nu=args.mg_nu, coarse_sweeps=args.mg_coarse or cur["coarse_sweeps"], omega=cur["omega"],
+                       coarse_ratio=args.mg_coarse_ratio or cur["coarse_ratio"])
+    return prob.mg_params()
+
+
+def coarse_solve_record(nx, ny, nz, args, degree):
     """Roofline context of the coarsest-level Chebyshev launches (two steps
     each), the largest share of GPU time in the multigrid solve: algorithmic
     bytes per launch and rocprofv3's average duration from the stored
@@ -111,7 +126,7 @@ def coarse_solve_record(nx, ny, nz, args):
     nbytes = vb * (6 * 3 * nnode + cx * cy * cz + nnode) + nnode
     out = {"kernel": "cheb2_kernel<" + ("double" if args.precision == "fp64" else "float")
                      + ">: two coarsest-level Chebyshev steps per launch",
-           "coarse_grid": [cx, cy, cz], "launches_per_vcycle": args.mg_coarse // 2,
+           "coarse_grid": [cx, cy, cz], "launches_per_vcycle": (degree + 1) // 2,
            "algorithmic_bytes_per_launch": nbytes, "bound": "latency",
            "note": "about 4 MB per launch on a 22k-element grid: the launch is bound by its chain of "
                    "dependent memory round trips and march steps, not by HBM bandwidth"}
@@ -189,7 +204,7 @@ def precision_study(fe, synth, torch, nx, ny, nz, seeds, args):
     probs = {p: fe.Problem(nx, ny, nz, f, precision=p, **kw) for p in ("fp64",) + tuple(v for v, _ in PREC_VARIANTS)}
     if args.precond == "gmg":
         for pr in probs.values():
-            pr.set_mg_params(nu=args.mg_nu, coarse_sweeps=args.mg_coarse, coarse_ratio=args.mg_coarse_ratio)
+            apply_mg(pr, args)
     res = {p: {"c_rel_err": [], "dc_rel_err": [], "iters": [], "outer_iters": [], "rel_res": [], "ms": []}
            for p in probs}
     for seed in range(seeds):
@@ -234,6 +249,81 @@ def precision_study(fe, synth, torch, nx, ny, nz, seeds, args):
         pr.close()
     return out
 
+
+
+def two_scale_study(fe, synth, torch, nx, ny, nz, args, block_sizes=(2, 4, 5, 7, 8), steps=20):
+    """Cost of the coarse scale of the two-scale scheme, which solves the
+    coarse problem at every optimisation iteration: the loop of the main
+    benchmark (filter, warm-started solve, sensitivity, transpose filter, OC)
+    runs `steps` iterations, and after each, per block size nb dividing the
+    grid, the coarse step on the same design (block means, the coarse filter,
+    the coarse solve warm-started from the previous u_C).  Each part is timed
+    on its own (synchronised); the first iteration is left out of the means."""
+    dev = "cuda:0"
+    T = lambda a: torch.as_tensor(a, dtype=torch.float64, device=dev)
+    ne = nx * ny * nz
+    fine = fe.Problem(nx, ny, nz, T(synth.cantilever_edge_load(nx, ny, nz)), device=dev,
+                      precision=args.precision, precond=args.precond, mg_levels=args.mg_levels)
+    if args.precond == "gmg":
+        apply_mg(fine, args)
+    x = torch.full((ne,), args.volfrac, dtype=torch.float64, device=dev)
+    u = torch.zeros(fine.ndof, dtype=torch.float64, device=dev)
+    rho, dc, dcx = (torch.empty_like(x) for _ in range(3))
+    dv = fine.filter(torch.ones_like(x), transpose=True)
+    comp = torch.zeros(1, dtype=torch.float64, device=dev)
+    change = torch.zeros(1, dtype=torch.float64, device=dev)
+    coarse = {}
+    for nb in block_sizes:
+        if nx % nb or ny % nb or nz % nb:
+            continue
+        cx, cy, cz = nx // nb, ny // nb, nz // nb
+        pc = fine.coarse_problem(nb, T(synth.cantilever_edge_load(cx, cy, cz)))
+        apply_mg(pc, args)
+        zc = torch.empty(cx * cy * cz, dtype=torch.float64, device=dev)
+        coarse[nb] = {"prob": pc, "zc": zc, "rc": torch.empty_like(zc),
+                      "uc": torch.zeros(pc.ndof, dtype=torch.float64, device=dev), "ms": [], "iters": []}
+    fine_ms, fine_iters = [], []
+    for it in range(steps):
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        fine.filter(x, out=rho)
+        _, info = fine.solve(rho, u=u, rtol=args.rtol)
+        fine.sensitivity(rho, u, out=dc, compliance_out=comp)
+        fine.filter(dc, transpose=True, out=dcx)
+        torch.cuda.synchronize()
+        fine_ms.append(1e3 * (time.perf_counter() - t0))
+        fine_iters.append(info["iters"])
+        for nb, c in coarse.items():
+            torch.cuda.synchronize()
+            t0 = time.perf_counter()
+            fine.block_mean(x, nb, out=c["zc"])
+            c["prob"].filter(c["zc"], out=c["rc"])
+            _, ci = c["prob"].solve(c["rc"], u=c["uc"], rtol=args.rtol)
+            torch.cuda.synchronize()
+            c["ms"].append(1e3 * (time.perf_counter() - t0))
+            c["iters"].append(ci["iters"])
+        fine.oc_update(x, dcx, dv, args.volfrac, args.move, out=x, change_out=change)
+    mean = lambda v: float(np.mean(v[1:])) if len(v) > 1 else float(v[0])
+    f_ms = mean(fine_ms)
+    out = {"grid": [nx, ny, nz], "steps": steps, "rtol": args.rtol,
+           "fine_step": {"ms": f_ms, "iters_mean": mean(fine_iters), "dofs": fine.ndof,
+                         "parts": "filter, warm-started solve, sensitivity, transpose filter (OC not timed)"},
+           "coarse": {}}
+    print(f"bench[two-scale]: fine step {f_ms:.2f} ms, {mean(fine_iters):.1f} iterations", file=sys.stderr,
+          flush=True)
+    for nb, c in coarse.items():
+        pc = c["prob"]
+        precond = fe.PRECOND_NAME[pc.cfg.precond]
+        rec = {"grid": [pc.nx, pc.ny, pc.nz], "dofs": pc.ndof, "precond": precond,
+               "mg_levels": pc.cfg.mg_levels if precond == "gmg" else 0, "ms": mean(c["ms"]),
+               "iters_mean": mean(c["iters"]), "ratio_to_fine_step": mean(c["ms"]) / f_ms}
+        out["coarse"][str(nb)] = rec
+        print(f"bench[two-scale]: nb {nb} coarse {pc.nx}x{pc.ny}x{pc.nz} ({precond}) {rec['ms']:.2f} ms, "
+              f"{rec['iters_mean']:.1f} iterations, {rec['ratio_to_fine_step']:.3f} of the fine step",
+              file=sys.stderr, flush=True)
+        pc.close()
+    fine.close()
+    return out
 
 
 def serving_bench(n, torch, nslots=16):
@@ -286,7 +376,9 @@ def run_loop(fe, synth, torch, nx, ny, nz, precision, args, steps, warmup, profi
     prob = fe.Problem(nx, ny, nz, T(f), device=dev, precision=precision, precond=args.precond,
                       mg_levels=args.mg_levels)
     if args.precond == "gmg":
-        prob.set_mg_params(nu=args.mg_nu, coarse_sweeps=args.mg_coarse, coarse_ratio=args.mg_coarse_ratio)
+        rec_mg = apply_mg(prob, args)
+    else:
+        rec_mg = None
     x = torch.empty(ne, dtype=torch.float64, device=dev)
     u = torch.empty(prob.ndof, dtype=torch.float64, device=dev)
     rho = torch.empty_like(x)
@@ -295,7 +387,7 @@ def run_loop(fe, synth, torch, nx, ny, nz, precision, args, steps, warmup, profi
     dv = prob.filter(torch.ones_like(x), transpose=True)
     comp = torch.zeros(1, dtype=torch.float64, device=dev)
     change = torch.zeros(1, dtype=torch.float64, device=dev)
-    rec = {"iters": [], "compliance": []}
+    rec = {"iters": [], "compliance": [], "mg": rec_mg}
 
     def reset():
         x.fill_(args.volfrac)
@@ -383,8 +475,8 @@ def main():
                    "precision": args.precision, "precond": args.precond,
                    "mg_levels": args.mg_levels if args.precond == "gmg" else None,
                    "mg_smoothing_sweeps": args.mg_nu if args.precond == "gmg" else None,
-                   "mg_coarse_chebyshev_degree": args.mg_coarse if args.precond == "gmg" else None,
-                   "mg_coarse_chebyshev_ratio": args.mg_coarse_ratio if args.precond == "gmg" else None,
+                   "mg_coarse_chebyshev_degree": rec["mg"]["coarse_sweeps"] if rec["mg"] else None,
+                   "mg_coarse_chebyshev_ratio": rec["mg"]["coarse_ratio"] if rec["mg"] else None,
                    "rtol": args.rtol, "volfrac": args.volfrac, "filter_r": 1.5, "move": args.move,
                    "cg_iters_per_solve": float(np.mean(rec["iters"])),
                    "cg_iters_max": int(np.max(rec["iters"])),
@@ -412,7 +504,7 @@ def main():
         out["roofline"]["rocprofv3_time_shares"] = [
             {"kernel": t["kernel"], "share": round(t["share"], 4), "avg_us": round(t["avg_us"], 2)}
             for t in rec_prof["time_shares"][:8]]
-    coarse = coarse_solve_record(nx, ny, nz, args)
+    coarse = coarse_solve_record(nx, ny, nz, args, rec["mg"]["coarse_sweeps"]) if rec["mg"] else None
     if coarse:
         out["roofline"]["coarse_solve"] = coarse
     if probe:
@@ -435,6 +527,8 @@ def main():
                                "cg_iters_per_solve": float(np.mean(rec4["iters"]))}
     if args.precision_seeds > 0:
         out["precision_study"] = precision_study(fe, synth, torch, nx, ny, nz, args.precision_seeds, args)
+    if args.two_scale:
+        out["two_scale"] = two_scale_study(fe, synth, torch, nx, ny, nz, args)
     if args.serving > 0:
         out["serving"] = serving_bench(args.serving, torch, nslots=args.serving_slots)
     if not args.no_cpu_baseline:

@@ -160,6 +160,19 @@ FE_API fe_status fe_filter(fe_problem* p, const double* in, double* out, int32_t
 FE_API fe_status oc_update(fe_problem* p, const double* x, const double* dcx, const double* dv,
                     double volfrac, double move, double* x_new, double* change);
 
+/* Coarse-grained design variables of the two-scale scheme (Sec. III-C and
+ * III-E, the coarse-graining step of Alg. 1): zc[ec] is the mean of z over
+ * the nb x nb x nb block of fine elements of coarse element ec.  z is
+ * float64[nelem] in the fine element order; zc is float64[nelem / nb^3] in
+ * the element order of the (nx/nb) x (ny/nb) x (nz/nb) coarse grid, coarse
+ * element (I, J, K) holding fine elements i = nb I .. nb I + nb - 1 (and the
+ * same in y, z).  Both are device arrays owned by the caller and must not
+ * alias.  FE_EINVAL unless 1 <= nb and nb divides nx, ny and nz.  The coarse
+ * problem of the scheme is an fe_problem of that grid with element edge nb h
+ * and filter radius filter_r / nb (the same physical radius).
+ * Asynchronous. */
+FE_API fe_status fe_block_mean(fe_problem* p, const double* z, int32_t nb, double* zc);
+
 /* Multigrid parameters (used when precond = FE_PRECOND_GMG): nu damped
  * Jacobi sweeps (damping omega) before and after each coarse correction
  * (1..8), and the degree (1..10000) of the Jacobi-preconditioned Chebyshev
@@ -167,12 +180,20 @@ FE_API fe_status oc_update(fe_problem* p, const double* x, const double* dcx, co
  * [lambda_max / coarse_ratio, lambda_max] (2 <= coarse_ratio <= 1e12) with
  * lambda_max = largest eigenvalue of diag(Ke)^-1 Ke (5.32 for nu = 0.3),
  * which bounds that of D^-1 K for any density field.  Defaults: nu = 1,
- * degree 48, omega = 0.35, coarse_ratio 5000.  The V-cycle is linear and
+ * omega = 0.35, and for the coarsest grid's longest dimension n the degree
+ * 2 clamp(round(12 n / 28), 4, 24) and coarse_ratio
+ * max(50, 5000 min(1, (n / 56)^2)) (48 and 5000 at n = 56, the 224 x 112 x 56
+ * grid with 3 levels).  The V-cycle is linear and
  * symmetric, and positive definite while omega * lambda_max < 2 (checked:
  * FE_EINVAL otherwise; the Chebyshev residual polynomial stays in (0, 1)
  * below the interval for any ratio), so plain CG applies. */
 FE_API fe_status fe_set_mg_params(fe_problem* p, int32_t nu, int32_t coarse_sweeps, double omega,
                            double coarse_ratio);
+
+/* The multigrid parameters in effect (the defaults above or the last
+ * fe_set_mg_params); each output pointer is host memory and may be NULL. */
+FE_API fe_status fe_get_mg_params(const fe_problem* p, int32_t* nu, int32_t* coarse_sweeps, double* omega,
+                           double* coarse_ratio);
 
 /* Launches of the coarsest-level Chebyshev solve: steps_per_launch = 2
  * (default) runs pairs of steps in one launch, each workgroup recomputing

@@ -143,6 +143,19 @@ size_t layout(const fe_config* c, fe_problem* p, char* base) {
   double* zpad = (double*)take(8 * sizeof(double));
   if (p) {
     p->nlev = nl;
+    if (nl > 1) {
+      // default coarse Chebyshev for the coarsest grid's longest dimension
+      // n: the number of steps a Chebyshev solve needs grows like the square
+      // root of the condition number, i.e. like n, and the smallest
+      // eigenvalue worth resolving like n^-2 (degree 48 and ratio 5000 at
+      // n = 56, measured best there; degree ~ 6n/7 measured best from n = 8
+      // to 32)
+      const Grid& gc = p->L[nl - 1].g;
+      const int n = std::max(gc.nx, std::max(gc.ny, gc.nz));
+      p->mg_coarse_sweeps = 2 * std::max(4, std::min(24, (int)std::lround(n * 24.0 / 56.0)));
+      p->cheb_ratio = 5000.0 * std::min(1.0, (n / 56.0) * (n / 56.0));
+      p->cheb_ratio = std::max(p->cheb_ratio, 50.0);
+    }
     p->f = f;
     p->invW = invW;
     p->st_off = st_off;
@@ -912,6 +925,21 @@ extern "C" fe_status oc_update(fe_problem* p, const double* x, const double* dcx
   return FE_OK;
 }
 
+extern "C" fe_status fe_block_mean(fe_problem* p, const double* z, int32_t nb, double* zc) {
+  CHECK_HANDLE(p);
+  if (!z || !zc || z == zc) {
+    fe_set_error("z and zc must be distinct non-NULL arrays");
+    return FE_EINVAL;
+  }
+  const Grid& g = p->L[0].g;
+  if (nb < 1 || g.nx % nb || g.ny % nb || g.nz % nb) {
+    fe_set_error("nb must be >= 1 and divide nx, ny and nz");
+    return FE_EINVAL;
+  }
+  HIP_TRY(launch_block_mean(p, z, nb, zc));
+  return FE_OK;
+}
+
 extern "C" fe_status fe_set_mg_params(fe_problem* p, int32_t nu, int32_t coarse_sweeps, double omega,
                                       double coarse_ratio) {
   CHECK_HANDLE(p);
@@ -935,6 +963,16 @@ extern "C" fe_status fe_set_mg_params(fe_problem* p, int32_t nu, int32_t coarse_
   p->cheb_ratio = coarse_ratio;
   drop_graph(p->chunk64);  // the captured chunks bake these in
   drop_graph(p->chunk32);
+  return FE_OK;
+}
+
+extern "C" fe_status fe_get_mg_params(const fe_problem* p, int32_t* nu, int32_t* coarse_sweeps, double* omega,
+                                      double* coarse_ratio) {
+  CHECK_HANDLE(p);
+  if (nu) *nu = p->mg_nu;
+  if (coarse_sweeps) *coarse_sweeps = p->mg_coarse_sweeps;
+  if (omega) *omega = p->mg_omega;
+  if (coarse_ratio) *coarse_ratio = p->cheb_ratio;
   return FE_OK;
 }
 

@@ -737,6 +737,27 @@ __global__ void __launch_bounds__(FE_BLOCK) oc_final_finalize(int nb, const doub
   }
 }
 
+// ------------------------------------------------------------ two-scale
+// Block means of the design variables: one thread per coarse element sums
+// the nb^3 fine elements of its block (z level slowest, x fastest) and
+// divides by nb^3.
+__global__ void __launch_bounds__(FE_BLOCK) block_mean_kernel(int nx, int ny, int nb, int cx, int cy, int64_t nc,
+                                                              const double* __restrict__ z,
+                                                              double* __restrict__ zc) {
+  const double cnt = (double)nb * (double)nb * (double)nb;
+  for (int64_t ec = blockIdx.x * (int64_t)FE_BLOCK + threadIdx.x; ec < nc; ec += (int64_t)gridDim.x * FE_BLOCK) {
+    const int64_t I = ec % cx, t = ec / cx;
+    const int64_t J = t % cy, K = t / cy;
+    double s = 0.0;
+    for (int c = 0; c < nb; ++c)
+      for (int b = 0; b < nb; ++b) {
+        const double* row = z + nb * I + (int64_t)nx * (nb * J + b + (int64_t)ny * (nb * K + c));
+        for (int a = 0; a < nb; ++a) s += row[a];
+      }
+    zc[ec] = s / cnt;
+  }
+}
+
 }  // namespace
 
 // =================================================================== launchers
@@ -1016,6 +1037,15 @@ hipError_t launch_filter(fe_problem* p, const double* in, double* out, int trans
   else
     hipLaunchKernelGGL(filter_kernel<0>, dim3(red_grid(g.nelem) * 4), dim3(FE_BLOCK), 0, p->stream, g,
                        make_stencil(p), p->invW, in, out);
+  return hipGetLastError();
+}
+
+hipError_t launch_block_mean(fe_problem* p, const double* z, int nb, double* zc) {
+  const Grid g = G(p, 0);
+  const int cx = g.nx / nb, cy = g.ny / nb;
+  const int64_t nc = (int64_t)cx * cy * (g.nz / nb);
+  hipLaunchKernelGGL(block_mean_kernel, dim3(red_grid(nc) * 4), dim3(FE_BLOCK), 0, p->stream, g.nx, g.ny, nb, cx,
+                     cy, nc, z, zc);
   return hipGetLastError();
 }
 

@@ -18,13 +18,15 @@ LIB_PATH = os.environ.get("FE_HIP_LIB") or os.path.join(_PKG, "libfe_hip.so")
 FE_OK, FE_EINVAL, FE_ENOMEM, FE_EDEVICE, FE_ENOTCONV, FE_EBREAKDOWN = 0, -1, -2, -3, -4, -5
 PRECISION = {"fp64": 0, "fp32_ir": 1, "bf16_ir": 2, "bf16x3_ir": 3}
 PRECOND = {"jacobi": 0, "gmg": 1}
+PRECISION_NAME = {v: k for k, v in PRECISION.items()}
+PRECOND_NAME = {v: k for k, v in PRECOND.items()}
 STATUS_NAME = {0: "FE_OK", -1: "FE_EINVAL", -2: "FE_ENOMEM", -3: "FE_EDEVICE",
                -4: "FE_ENOTCONV", -5: "FE_EBREAKDOWN"}
 
 # Every entry point declared in include/fe_abi.h.
 ABI_SYMBOLS = ("fe_workspace_size", "fe_setup", "fe_apply_K", "fe_solve", "fe_solve_begin",
                "fe_solve_step", "fe_solve_end", "fe_sensitivity",
-               "fe_filter", "oc_update", "fe_set_mg_params", "fe_set_coarse_fusion", "fe_set_profiling",
+               "fe_filter", "oc_update", "fe_block_mean", "fe_set_mg_params", "fe_get_mg_params", "fe_set_coarse_fusion", "fe_set_profiling",
                "fe_kernel_stats", "fe_destroy", "fe_batch_workspace_size", "fe_batch_create", "fe_batch_setup_slot",
                "fe_batch_round_begin", "fe_batch_round_end", "fe_batch_destroy", "fe_last_error")
 
@@ -72,7 +74,9 @@ def load_library() -> C.CDLL:
     lib.fe_sensitivity.argtypes = [P, P, P, P, P]
     lib.fe_filter.argtypes = [P, P, P, I32]
     lib.oc_update.argtypes = [P, P, P, P, D, D, P, P]
+    lib.fe_block_mean.argtypes = [P, P, I32, P]
     lib.fe_set_mg_params.argtypes = [P, I32, I32, D, D]
+    lib.fe_get_mg_params.argtypes = [P, C.POINTER(I32), C.POINTER(I32), C.POINTER(D), C.POINTER(D)]
     lib.fe_set_coarse_fusion.argtypes = [P, I32]
     lib.fe_set_profiling.argtypes = [P, I32]
     lib.fe_kernel_stats.argtypes = [P, I32, C.POINTER(I64), C.POINTER(D), C.POINTER(D)]
@@ -235,8 +239,48 @@ class Problem:
                                         _ptr(xn), _ptr(ch)))
         return xn, ch
 
+    def block_mean(self, z, nb, out=None):
+        """Coarse-grained design variables of the two-scale scheme: the mean
+        of z over each nb x nb x nb block of elements (include/fe_abi.h,
+        fe_block_mean)."""
+        n = (self.nx // nb) * (self.ny // nb) * (self.nz // nb) if nb >= 1 else 0
+        zc = self._vec(max(1, n)) if out is None else out  # the library rejects a bad nb
+        _check(load_library().fe_block_mean(self._h, _ptr(z), nb, _ptr(zc)))
+        return zc
+
+    def coarse_problem(self, nb, f_c, fixed_c=None, **cfg_kw):
+        """The coarse problem of the two-scale scheme for block size nb: the
+        (nx/nb, ny/nb, nz/nb) grid with element edge nb h and the same
+        physical filter radius (filter_r / nb elements), the material of this
+        problem, load f_c.  Keyword arguments override the solver settings
+        (precision, precond, mg_levels); with multigrid the hierarchy keeps
+        as many of this problem's levels as the coarse grid's dimensions
+        admit, and Jacobi preconditioning replaces it when they admit none."""
+        if nb < 1 or self.nx % nb or self.ny % nb or self.nz % nb:
+            raise FEError(FE_EINVAL, "nb must be >= 1 and divide nx, ny and nz")
+        c = self.cfg
+        cx, cy, cz = self.nx // nb, self.ny // nb, self.nz // nb
+        kw = dict(h=c.h * nb, E0=c.E0, Emin=c.Emin, nu=c.nu, penal=c.penal, filter_r=c.filter_r / nb,
+                  precision=PRECISION_NAME[c.precision], precond=PRECOND_NAME[c.precond],
+                  mg_levels=max(2, c.mg_levels))
+        kw.update(cfg_kw)
+        if kw["precond"] == "gmg":
+            lv = kw["mg_levels"]
+            while lv >= 2 and any(n % (1 << (lv - 1)) for n in (cx, cy, cz)):
+                lv -= 1
+            if lv < 2:
+                kw["precond"] = "jacobi"
+            kw["mg_levels"] = max(lv, 2)
+        return Problem(cx, cy, cz, f_c, fixed_c, device=self.device, stream=self.stream, **kw)
+
     def set_mg_params(self, nu=1, coarse_sweeps=48, omega=0.35, coarse_ratio=5000.0):
         _check(load_library().fe_set_mg_params(self._h, nu, coarse_sweeps, omega, coarse_ratio))
+
+    def mg_params(self):
+        """The multigrid parameters in effect: nu, coarse_sweeps, omega, coarse_ratio."""
+        nu, deg, om, ra = C.c_int32(), C.c_int32(), C.c_double(), C.c_double()
+        _check(load_library().fe_get_mg_params(self._h, C.byref(nu), C.byref(deg), C.byref(om), C.byref(ra)))
+        return {"nu": nu.value, "coarse_sweeps": deg.value, "omega": om.value, "coarse_ratio": ra.value}
 
     def set_coarse_fusion(self, steps_per_launch=2):
         """Coarsest-level Chebyshev steps per launch (2: pairs fused, 1: one each)."""

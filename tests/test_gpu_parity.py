@@ -281,6 +281,24 @@ def test_gmg_params_validation():
     assert info["rel_res"] <= 1e-9
 
 
+def test_gmg_default_coarse_chebyshev_follows_the_coarsest_grid():
+    """Defaults: degree 2 clamp(round(12 n / 28), 4, 24) and interval ratio
+    max(50, 5000 min(1, (n / 56)^2)) for the coarsest grid's longest
+    dimension n; fe_set_mg_params overrides them and fe_get_mg_params reads
+    what is in effect."""
+    cases = {(224, 112, 56): (48, 5000.0), (32, 16, 16): (8, 5000.0 * (8 / 56) ** 2),
+             (96, 48, 48): (20, 5000.0 * (24 / 56) ** 2), (8, 4, 4): (8, 50.0)}
+    for (nx, ny, nz), (deg, ratio) in cases.items():
+        prob = fe.Problem(nx, ny, nz, T(synth.cantilever_edge_load(nx, ny, nz)), device=DEV, precond="gmg",
+                          mg_levels=3)
+        mg = prob.mg_params()
+        assert mg["coarse_sweeps"] == deg and abs(mg["coarse_ratio"] - ratio) <= 1e-9 * ratio
+        assert mg["nu"] == 1 and mg["omega"] == 0.35
+        prob.set_mg_params(nu=2, coarse_sweeps=13, omega=0.3, coarse_ratio=700.0)
+        assert prob.mg_params() == {"nu": 2, "coarse_sweeps": 13, "omega": 0.3, "coarse_ratio": 700.0}
+        prob.close()
+
+
 def test_oc_extreme_dynamic_range():
     """Late designs have void elements with x ~ 1e-50 and dc ~ 1e-80: the
     multiplier then lies hundreds of decades below the largest a-scale."""
