@@ -322,6 +322,26 @@ def sensitivity(nx, ny, nz, Ke, rho, u, E0=1.0, Emin=1e-9, penal=3.0):
     return -penal * np.asarray(rho) ** (penal - 1.0) * (E0 - Emin) * ee
 
 
+def adjoint_sensitivity(nx, ny, nz, Ke, rho, u, lam, E0=1.0, Emin=1e-9, penal=3.0):
+    """The state-equation term of the gradient (3) for r(rho, u) = K(rho) u - f:
+    -lam^T (dr/drho_e) = -p rho_e^(p-1) (E0 - Emin) lam_e^T Ke u_e, where lam
+    solves K^T lam = dJ/du (K is symmetric)."""
+    edof = element_dofs(nx, ny, nz)
+    return -penal * np.asarray(rho) ** (penal - 1.0) * (E0 - Emin) * np.einsum(
+        "ei,ij,ej->e", lam[edof], Ke, u[edof])
+
+
+def linear_objective_gradient(nx, ny, nz, Ke, rho, f, l, fixed, E0=1.0, Emin=1e-9, penal=3.0):
+    """dJ/drho of J = l^T u(rho) by the gradient (3): J has no explicit
+    dependence on rho and dJ/du = l, so u solves K u = f, lam solves
+    K lam = l (both with the fixed dofs eliminated) and the gradient is
+    adjoint_sensitivity(u, lam).  Returns (u, lam, gradient)."""
+    E = simp_modulus(rho, E0, Emin, penal)
+    u = solve_direct(nx, ny, nz, E, Ke, f, fixed)
+    lam = solve_direct(nx, ny, nz, E, Ke, l, fixed)
+    return u, lam, adjoint_sensitivity(nx, ny, nz, Ke, rho, u, lam, E0, Emin, penal)
+
+
 # ---------------------------------------------------------------------------
 # Density filter P (Eq. 4) and its transpose (gradient of the volume, Sec. III-D)
 # ---------------------------------------------------------------------------

@@ -270,6 +270,34 @@ def test_sensitivity_central_fd(Ke, grid):
     assert abs(np.sum(rho * dc) + penal * (c0 - Emin * ee.sum())) < 1e-10 * c0
 
 
+@pytest.mark.parametrize("grid", [(4, 2, 2), (6, 3, 3)])
+def test_adjoint_gradient_central_fd(Ke, grid):
+    """J = l^T u(rho) for a random l (not self-adjoint): the gradient (3)
+    against central finite differences; with l = f it is the compliance
+    sensitivity; swapping f and l leaves it unchanged (Betti)."""
+    nx, ny, nz = grid
+    rng = np.random.default_rng(11)
+    rho = rng.uniform(0.2, 1.0, nx * ny * nz)
+    _, f, fixed = _c1_problem(nx, ny, nz)
+    l = np.where(fixed, 0.0, rng.standard_normal(f.size))
+    u, lam, g = O.linear_objective_gradient(nx, ny, nz, Ke, rho, f, l, fixed)
+
+    def J(r):
+        return l @ O.solve_direct(nx, ny, nz, O.simp_modulus(r), Ke, f, fixed)
+
+    for e in rng.choice(rho.size, size=min(8, rho.size), replace=False):
+        step = 1e-6 * rho[e]
+        rp, rm = rho.copy(), rho.copy()
+        rp[e] += step
+        rm[e] -= step
+        fd = (J(rp) - J(rm)) / (2 * step)
+        assert abs(fd - g[e]) <= 1e-6 * np.abs(g).max(), (e, fd, g[e])
+    _, _, g_ff = O.linear_objective_gradient(nx, ny, nz, Ke, rho, f, f, fixed)
+    assert np.abs(g_ff - O.sensitivity(nx, ny, nz, Ke, rho, u)).max() <= 1e-12 * np.abs(g_ff).max()
+    _, _, g_sw = O.linear_objective_gradient(nx, ny, nz, Ke, rho, l, f, fixed)
+    assert np.abs(g_sw - g).max() <= 1e-10 * np.abs(g).max()
+
+
 # ----------------------------------------------------------------- filter
 def test_filter_closed_form_weights():
     P = O.filter_matrix(7, 7, 7, 1.5)
