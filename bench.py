@@ -52,6 +52,8 @@ def parse():
                     help="also run the float64 loop with a 4-level hierarchy (context line)")
     ap.add_argument("--two-scale", type=int, default=1,
                     help="time the coarse-scale solves of the two-scale scheme beside the fine solve")
+    ap.add_argument("--adjoint", type=int, default=1,
+                    help="time the adjoint gradient of a non-self-adjoint objective")
     ap.add_argument("--cpu-grid", type=str, default="80x40x20")
     ap.add_argument("--serving", type=int, default=256,
                     help="requests of the serving stream to run (0: skip)")
@@ -326,6 +328,77 @@ def two_scale_study(fe, synth, torch, nx, ny, nz, args, block_sizes=(2, 4, 5, 7,
     return out
 
 
+def adjoint_study(fe, synth, torch, nx, ny, nz, args, reps=5):
+    """The general adjoint gradient (Eq. 3) of a non-self-adjoint objective,
+    J = -u_z at the middle of the loaded edge, on one smoothed random design
+    (U(0.01,1) through 3 filter passes): the forward solve, the adjoint solve
+    (load swapped to dJ/du and restored), and the state-equation term
+    -lam^T dr/drho, against the compliance sensitivity kernel.  Medians of
+    reps after one untimed run; kernel times from events on the stream."""
+    dev = "cuda:0"
+    T = lambda a: torch.as_tensor(a, dtype=torch.float64, device=dev)
+    f = T(synth.cantilever_edge_load(nx, ny, nz))
+    prob = fe.Problem(nx, ny, nz, f, device=dev, precision=args.precision, precond=args.precond,
+                      mg_levels=args.mg_levels)
+    apply_mg(prob, args)
+    l = torch.zeros(prob.ndof, dtype=torch.float64, device=dev)
+    l[3 * (nx + (nx + 1) * (ny // 2)) + 2] = -1.0
+    rho = T(synth.density_uniform(nx, ny, nz, 0))
+    tmp = torch.empty_like(rho)
+    for _ in range(3):
+        prob.filter(rho, out=tmp)
+        rho, tmp = tmp, rho
+    g = torch.empty_like(rho)
+
+    def median_ms(fn):
+        fn()
+        ms = []
+        for _ in range(reps):
+            torch.cuda.synchronize()
+            t0 = time.perf_counter()
+            out = fn()
+            torch.cuda.synchronize()
+            ms.append(1e3 * (time.perf_counter() - t0))
+        return float(np.median(ms)), out
+
+    fwd_ms, (u, finfo) = median_ms(lambda: prob.solve(rho, rtol=args.rtol))
+
+    def adjoint_solve():
+        prob.set_load(l)
+        try:
+            return prob.solve(rho, rtol=args.rtol)
+        finally:
+            prob.set_load(f)
+
+    adj_ms, (lam, ainfo) = median_ms(adjoint_solve)
+
+    def kernel_us(fn, n=20):
+        fn()
+        a, b = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+        torch.cuda.synchronize()
+        a.record()
+        for _ in range(n):
+            fn()
+        b.record()
+        b.synchronize()
+        return a.elapsed_time(b) * 1e3 / n
+
+    dc = torch.empty_like(rho)
+    adj_us = kernel_us(lambda: prob.sensitivity_adjoint(rho, u, lam, out=g))
+    sens_us = kernel_us(lambda: prob.sensitivity(rho, u, out=dc))
+    nbytes = 8.0 * (2 * prob.ndof + 2 * prob.nelem)  # u, lam, rho read, g written
+    out = {"grid": [nx, ny, nz], "objective": "J = -u_z at node (nx, ny/2, 0)", "rtol": args.rtol,
+           "forward_solve_ms": fwd_ms, "forward_iters": finfo["iters"],
+           "adjoint_solve_ms": adj_ms, "adjoint_iters": ainfo["iters"],
+           "adjoint_term_us": adj_us, "adjoint_term_algorithmic_bytes": nbytes,
+           "adjoint_term_gbs": nbytes / (adj_us * 1e-6) / 1e9, "compliance_sensitivity_us": sens_us}
+    print(f"bench[adjoint]: forward {fwd_ms:.2f} ms ({finfo['iters']} it), adjoint {adj_ms:.2f} ms "
+          f"({ainfo['iters']} it), term {adj_us:.1f} us ({out['adjoint_term_gbs']:.0f} GB/s), "
+          f"compliance sensitivity {sens_us:.1f} us", file=sys.stderr, flush=True)
+    prob.close()
+    return out
+
+
 def serving_bench(n, torch, nslots=16):
     """Serving stream of n seeded requests over the five grid sizes: the same
     requests one at a time (blocking solves); through the batched engine
@@ -527,6 +600,8 @@ def main():
                                "cg_iters_per_solve": float(np.mean(rec4["iters"]))}
     if args.precision_seeds > 0:
         out["precision_study"] = precision_study(fe, synth, torch, nx, ny, nz, args.precision_seeds, args)
+    if args.adjoint:
+        out["adjoint"] = adjoint_study(fe, synth, torch, nx, ny, nz, args)
     if args.two_scale:
         out["two_scale"] = two_scale_study(fe, synth, torch, nx, ny, nz, args)
     if args.serving > 0:

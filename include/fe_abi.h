@@ -144,6 +144,25 @@ FE_API fe_status fe_solve_end(fe_problem* p, fe_solve_info* info);
 FE_API fe_status fe_sensitivity(fe_problem* p, const double* rho, const double* u,
                          double* dc, double* compliance);
 
+/* The state-equation term of the adjoint gradient (Sec. III-A, Eq. 3) for
+ * r(rho, u) = K(rho) u - f:
+ *   g[e] = -lam^T dr/drho_e = -penal rho_e^(penal-1) (E0 - Emin) lam_e^T Ke u_e,
+ * where u solves K u = f and lam solves K lam = dJ/du (K is symmetric: a
+ * second fe_solve after fe_set_load(p, dJ/du) gives lam).  The gradient of
+ * an objective J(rho, u) is its explicit dJ/drho (the caller's) plus g; for
+ * the compliance lam = u and g is fe_sensitivity's dc.  rho: float64[nelem],
+ * u and lam: float64[ndof], g: float64[nelem]; device arrays owned by the
+ * caller.  Asynchronous. */
+FE_API fe_status fe_sensitivity_adjoint(fe_problem* p, const double* rho, const double* u, const double* lam,
+                                 double* g);
+
+/* Replaces the problem's load by f (float64[ndof], device, caller-owned;
+ * entries at fixed dofs are ignored), e.g. by dJ/du for the adjoint solve of
+ * Eq. (3); the supports are unchanged.  Blocks until the new load's norm is
+ * known on the host.  FE_EINVAL while a solve is in progress or on a batch
+ * slot (fe_batch_setup_slot sets those). */
+FE_API fe_status fe_set_load(fe_problem* p, const double* f);
+
 /* Density filter of problem (4): out = P in (transpose = 0) or
  * out = P^T in (transpose = 1), with P_ij = w_ij / sum_j w_ij and
  * w_ij = max(0, r - |c_i - c_j|) over element centroids in element units.

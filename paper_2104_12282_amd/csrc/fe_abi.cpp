@@ -851,6 +851,39 @@ extern "C" fe_status fe_sensitivity(fe_problem* p, const double* rho, const doub
   return FE_OK;
 }
 
+extern "C" fe_status fe_sensitivity_adjoint(fe_problem* p, const double* rho, const double* u, const double* lam,
+                                            double* g) {
+  CHECK_HANDLE(p);
+  if (!rho || !u || !lam || !g) {
+    fe_set_error("rho, u, lam and g must not be NULL");
+    return FE_EINVAL;
+  }
+  HIP_TRY(launch_adjoint_sensitivity(p, rho, u, lam, g));
+  return FE_OK;
+}
+
+extern "C" fe_status fe_set_load(fe_problem* p, const double* f) {
+  CHECK_HANDLE(p);
+  if (!f) {
+    fe_set_error("f must not be NULL");
+    return FE_EINVAL;
+  }
+  if (p->in_batch) {
+    fe_set_error("a batch slot takes its load from fe_batch_setup_slot");
+    return FE_EINVAL;
+  }
+  if (p->sc.stage != ST_DONE) {
+    fe_set_error("a solve is still in progress on this problem");
+    return FE_EINVAL;
+  }
+  HIP_TRY(launch_mask_load(p, f));
+  HIP_TRY(launch_dot64(p, p->f, p->f, p->L[0].g.ndof, p->scal + 2 * SLOT_FF));
+  HIP_TRY(hipMemcpyAsync(p->h_scal, p->scal + 2 * SLOT_FF, sizeof(double), hipMemcpyDeviceToHost, p->stream));
+  HIP_TRY(hipStreamSynchronize(p->stream));
+  p->ff = p->h_scal[0];
+  return FE_OK;
+}
+
 extern "C" fe_status fe_filter(fe_problem* p, const double* in, double* out, int32_t transpose) {
   CHECK_HANDLE(p);
   if (!in || !out || in == out) {

@@ -337,6 +337,8 @@ hipError_t launch_dot64(fe_problem* p, const double* a, const double* b, int64_t
 hipError_t launch_sensitivity(fe_problem* p, const double* rho, const double* u, double* dc);
 hipError_t launch_filter(fe_problem* p, const double* in, double* out, int transpose);
 hipError_t launch_filter_rowsums(fe_problem* p);
+hipError_t launch_adjoint_sensitivity(fe_problem* p, const double* rho, const double* u, const double* lam,
+                                      double* out);
 hipError_t launch_block_mean(fe_problem* p, const double* z, int nb, double* zc);
 hipError_t launch_oc(fe_problem* p, const double* x, const double* dcx, const double* dv,
                      double volfrac, double move, double* x_new, double* change);

@@ -478,6 +478,59 @@ __global__ void __launch_bounds__(FE_BLOCK) sensitivity_kernel(Grid g, const dou
   }
 }
 
+// The state-equation term of the general adjoint gradient:
+// out_e = -p rho^(p-1) (E0 - Emin) lam_e^T Ke u_e, the symmetric bilinear form
+// of the factorised Ke (the quadratic form above with one operand from u and
+// one from lam, each cross term taken in both orders).
+__device__ inline void load_walsh(const Grid& g, const double* __restrict__ v, int i, int j, int k,
+                                  double (&t)[3][8]) {
+#pragma unroll
+  for (int a = 0; a < 8; ++a) {
+    const int64_t n = (i + c_cx[a]) + (int64_t)(g.nx + 1) * ((j + c_cy[a]) + (int64_t)(g.ny + 1) * (k + c_cz[a]));
+    t[0][a] = v[3 * n];
+    t[1][a] = v[3 * n + 1];
+    t[2][a] = v[3 * n + 2];
+  }
+  walsh8(t[0]);
+  walsh8(t[1]);
+  walsh8(t[2]);
+}
+
+__global__ void __launch_bounds__(FE_BLOCK) adjoint_sensitivity_kernel(Grid g, const double* __restrict__ rho,
+                                                                       const double* __restrict__ u,
+                                                                       const double* __restrict__ lam,
+                                                                       WalshK wk, double penal, double dE,
+                                                                       double* __restrict__ out) {
+  for (int64_t e = blockIdx.x * (int64_t)FE_BLOCK + threadIdx.x; e < g.nelem;
+       e += (int64_t)gridDim.x * FE_BLOCK) {
+    const int i = (int)(e % g.nx), j = (int)((e / g.nx) % g.ny), k = (int)(e / ((int64_t)g.nx * g.ny));
+    double t[3][8], s[3][8];
+    load_walsh(g, u, i, j, k, t);
+    load_walsh(g, lam, i, j, k, s);
+    enum { X = 0, Y = 1, Z = 2 };
+    double en = 0.0;
+    // linear modes, normal block
+    const double n1 = t[X][1], n2 = t[Y][3], n3 = t[Z][4];
+    const double m1 = s[X][1], m2 = s[Y][3], m3 = s[Z][4];
+    en += wk.A * (n1 * m1 + n2 * m2 + n3 * m3) +
+          wk.B * (n1 * m2 + n2 * m1 + n1 * m3 + n3 * m1 + n2 * m3 + n3 * m2);
+    // shear pairs (rank one)
+    en += wk.G * ((t[Y][1] + t[X][3]) * (s[Y][1] + s[X][3]) + (t[Z][1] + t[X][4]) * (s[Z][1] + s[X][4]) +
+                  (t[Z][3] + t[Y][4]) * (s[Z][3] + s[Y][4]));
+    // bilinear pairs
+    en += wk.C * (t[X][2] * s[X][2] + t[Z][7] * s[Z][7]) + wk.D * (t[X][2] * s[Z][7] + t[Z][7] * s[X][2]);
+    en += wk.C * (t[Y][2] * s[Y][2] + t[Z][5] * s[Z][5]) + wk.D * (t[Y][2] * s[Z][5] + t[Z][5] * s[Y][2]);
+    en += wk.C * (t[X][5] * s[X][5] + t[Y][7] * s[Y][7]) + wk.D * (t[X][5] * s[Y][7] + t[Y][7] * s[X][5]);
+    // bilinear triple
+    const double a3 = t[Z][2], b3 = t[Y][5], c3 = t[X][7];
+    const double a4 = s[Z][2], b4 = s[Y][5], c4 = s[X][7];
+    en += wk.F * (a3 * a4 + b3 * b4 + c3 * c4) + wk.H * (a3 * b4 + b3 * a4 + a3 * c4 + c3 * a4 + b3 * c4 + c3 * b4);
+    // trilinear mode
+    en += wk.J * (t[X][6] * s[X][6] + t[Y][6] * s[Y][6] + t[Z][6] * s[Z][6]);
+    out[e] = -penal * pow(rho[e], penal - 1.0) * dE * en;
+  }
+}
+
 // ------------------------------------------------------------ filter
 struct Stencil {
   int n;
@@ -1011,6 +1064,17 @@ hipError_t launch_sensitivity(fe_problem* p, const double* rho, const double* u,
   wk.A *= h; wk.B *= h; wk.G *= h; wk.C *= h; wk.D *= h; wk.F *= h; wk.H *= h; wk.J *= h;
   hipLaunchKernelGGL(sensitivity_kernel, dim3(red_grid(g.nelem) * 4), dim3(FE_BLOCK), 0, p->stream, g, rho,
                      u, wk, p->cfg.penal, p->cfg.E0 - p->cfg.Emin, dc);
+  return hipGetLastError();
+}
+
+hipError_t launch_adjoint_sensitivity(fe_problem* p, const double* rho, const double* u, const double* lam,
+                                      double* out) {
+  const Grid g = G(p, 0);
+  WalshK wk = p->wk;
+  const double h = p->L[0].h;
+  wk.A *= h; wk.B *= h; wk.G *= h; wk.C *= h; wk.D *= h; wk.F *= h; wk.H *= h; wk.J *= h;
+  hipLaunchKernelGGL(adjoint_sensitivity_kernel, dim3(red_grid(g.nelem) * 4), dim3(FE_BLOCK), 0, p->stream, g,
+                     rho, u, lam, wk, p->cfg.penal, p->cfg.E0 - p->cfg.Emin, out);
   return hipGetLastError();
 }
 

@@ -25,7 +25,7 @@ STATUS_NAME = {0: "FE_OK", -1: "FE_EINVAL", -2: "FE_ENOMEM", -3: "FE_EDEVICE",
 
 # Every entry point declared in include/fe_abi.h.
 ABI_SYMBOLS = ("fe_workspace_size", "fe_setup", "fe_apply_K", "fe_solve", "fe_solve_begin",
-               "fe_solve_step", "fe_solve_end", "fe_sensitivity",
+               "fe_solve_step", "fe_solve_end", "fe_sensitivity", "fe_sensitivity_adjoint", "fe_set_load",
                "fe_filter", "oc_update", "fe_block_mean", "fe_set_mg_params", "fe_get_mg_params", "fe_set_coarse_fusion", "fe_set_profiling",
                "fe_kernel_stats", "fe_destroy", "fe_batch_workspace_size", "fe_batch_create", "fe_batch_setup_slot",
                "fe_batch_round_begin", "fe_batch_round_end", "fe_batch_destroy", "fe_last_error")
@@ -72,6 +72,8 @@ def load_library() -> C.CDLL:
     lib.fe_solve_step.argtypes = [P, C.POINTER(I32)]
     lib.fe_solve_end.argtypes = [P, C.POINTER(fe_solve_info)]
     lib.fe_sensitivity.argtypes = [P, P, P, P, P]
+    lib.fe_sensitivity_adjoint.argtypes = [P, P, P, P, P]
+    lib.fe_set_load.argtypes = [P, P]
     lib.fe_filter.argtypes = [P, P, P, I32]
     lib.oc_update.argtypes = [P, P, P, P, D, D, P, P]
     lib.fe_block_mean.argtypes = [P, P, I32, P]
@@ -225,6 +227,33 @@ class Problem:
             else compliance_out
         _check(load_library().fe_sensitivity(self._h, _ptr(rho), _ptr(u), _ptr(dc), _ptr(c)))
         return dc, c
+
+    def sensitivity_adjoint(self, rho, u, lam, out=None):
+        """-lam^T dr/drho of the adjoint gradient (include/fe_abi.h, fe_sensitivity_adjoint)."""
+        g = self._vec(self.nelem) if out is None else out
+        _check(load_library().fe_sensitivity_adjoint(self._h, _ptr(rho), _ptr(u), _ptr(lam), _ptr(g)))
+        return g
+
+    def set_load(self, f):
+        """Replaces the load (fixed dofs ignored); blocks until its norm is known."""
+        f = f.to(self.device, torch.float64).contiguous()
+        _check(load_library().fe_set_load(self._h, _ptr(f)))
+        self.f = f
+
+    def linear_objective_gradient(self, rho, l, u=None, rtol=1e-8):
+        """Gradient of J = l^T u(rho) by the adjoint method (Eq. 3): u solves
+        K u = f (skipped when u is given), lam solves K lam = l (the load is
+        swapped to l for that solve and restored), g = -lam^T dr/drho.
+        Returns (g, u, lam)."""
+        if u is None:
+            u, _ = self.solve(rho, rtol=rtol)
+        f = self.f
+        self.set_load(l)
+        try:
+            lam, _ = self.solve(rho, rtol=rtol)
+        finally:
+            self.set_load(f)
+        return self.sensitivity_adjoint(rho, u, lam), u, lam
 
     def filter(self, x, transpose=False, out=None):
         y = self._vec(self.nelem) if out is None else out
