@@ -54,6 +54,8 @@ def parse():
                     help="time the coarse-scale solves of the two-scale scheme beside the fine solve")
     ap.add_argument("--adjoint", type=int, default=1,
                     help="time the adjoint gradient of a non-self-adjoint objective")
+    ap.add_argument("--paper-meshes", type=int, default=200,
+                    help="iterations of the runs on the paper's three cantilever meshes (0: skip)")
     ap.add_argument("--cpu-grid", type=str, default="80x40x20")
     ap.add_argument("--serving", type=int, default=256,
                     help="requests of the serving stream to run (0: skip)")
@@ -399,6 +401,68 @@ def adjoint_study(fe, synth, torch, nx, ny, nz, args, reps=5):
     return out
 
 
+# Final objectives of the paper's standard optimizer on its cantilever meshes
+# (Table II); its material constants are not stated, so they are context only.
+PAPER_TABLE2_STANDARD = {70: 370.11, 100: 379.54, 180: 383.51}
+
+
+def paper_mesh_study(fe, synth, torch, args, iters):
+    """The standard optimizer on the paper's cantilever meshes (Sec. IV):
+    the 2 x 1 x 1 domain in 70x35x35, 100x50x50 and 180x90x90 elements
+    (h = 2 / nx), filter radius R = 0.08 (2.8, 4 and 7.2 elements), volume
+    fraction 0.12, the edge load, `iters` iterations from the uniform design.
+    Multigrid keeps the levels the grid admits (Jacobi PCG when none)."""
+    dev = "cuda:0"
+    T = lambda a: torch.as_tensor(a, dtype=torch.float64, device=dev)
+    out = {"domain": [2.0, 1.0, 1.0], "filter_R": 0.08, "volfrac": 0.12, "move": args.move,
+           "rtol": args.rtol, "iterations": iters, "meshes": {}}
+    for nx in (70, 100, 180):
+        ny = nz = nx // 2
+        h = 2.0 / nx
+        levels = 1
+        while levels < args.mg_levels and all(n % (1 << levels) == 0 for n in (nx, ny, nz)):
+            levels += 1
+        precond = "gmg" if levels >= 2 and args.precond == "gmg" else "jacobi"
+        prob = fe.Problem(nx, ny, nz, T(synth.cantilever_edge_load(nx, ny, nz)), device=dev, h=h,
+                          filter_r=0.08 / h, precision=args.precision, precond=precond,
+                          mg_levels=max(levels, 2))
+        mg = apply_mg(prob, args)
+        ne = nx * ny * nz
+        x = torch.full((ne,), 0.12, dtype=torch.float64, device=dev)
+        u = torch.zeros(prob.ndof, dtype=torch.float64, device=dev)
+        rho, dc, dcx = (torch.empty_like(x) for _ in range(3))
+        dv = prob.filter(torch.ones_like(x), transpose=True)
+        comp = torch.zeros(1, dtype=torch.float64, device=dev)
+        change = torch.zeros(1, dtype=torch.float64, device=dev)
+        cs, its = [], []
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        for it in range(iters):
+            prob.filter(x, out=rho)
+            _, info = prob.solve(rho, u=u, rtol=args.rtol)
+            prob.sensitivity(rho, u, out=dc, compliance_out=comp)
+            prob.filter(dc, transpose=True, out=dcx)
+            prob.oc_update(x, dcx, dv, 0.12, args.move, out=x, change_out=change)
+            cs.append(info["compliance"])
+            its.append(info["iters"])
+        torch.cuda.synchronize()
+        dt = time.perf_counter() - t0
+        rec = {"grid": [nx, ny, nz], "elements": ne, "dofs": prob.ndof, "h": h, "filter_r_elements": 0.08 / h,
+               "precond": precond, "mg_levels": levels if precond == "gmg" else 0,
+               "mg_coarse_chebyshev_degree": mg["coarse_sweeps"] if mg else None,
+               "seconds": dt, "ms_per_iteration": 1e3 * dt / iters, "cg_iters_mean": float(np.mean(its)),
+               "objective_first": cs[0], "objective_final": cs[-1],
+               "objective_at": {str(k): cs[k - 1] for k in (10, 50, 100, 200) if k <= iters},
+               "paper_table2_standard_objective": PAPER_TABLE2_STANDARD[nx]}
+        out["meshes"][f"{nx}x{ny}x{nz}"] = rec
+        print(f"bench[paper-mesh]: {nx}x{ny}x{nz} ({precond}{'' if precond != 'gmg' else f', {levels} levels'}) "
+              f"{iters} iterations in {dt:.1f} s ({rec['ms_per_iteration']:.1f} ms each, "
+              f"{rec['cg_iters_mean']:.0f} CG iterations), objective {cs[0]:.4g} -> {cs[-1]:.4g} "
+              f"(paper, other constants: {PAPER_TABLE2_STANDARD[nx]})", file=sys.stderr, flush=True)
+        prob.close()
+    return out
+
+
 def serving_bench(n, torch, nslots=16):
     """Serving stream of n seeded requests over the five grid sizes: the same
     requests one at a time (blocking solves); through the batched engine
@@ -600,6 +664,8 @@ def main():
                                "cg_iters_per_solve": float(np.mean(rec4["iters"]))}
     if args.precision_seeds > 0:
         out["precision_study"] = precision_study(fe, synth, torch, nx, ny, nz, args.precision_seeds, args)
+    if args.paper_meshes > 0:
+        out["paper_meshes"] = paper_mesh_study(fe, synth, torch, args, args.paper_meshes)
     if args.adjoint:
         out["adjoint"] = adjoint_study(fe, synth, torch, nx, ny, nz, args)
     if args.two_scale:

@@ -44,7 +44,7 @@ extern "C" {
 typedef enum {
   FE_OK = 0,
   FE_EINVAL = -1,      /* bad argument: dims < 1, nu not in (-1, 0.5), Emin not in (0, E0),
-                          penal < 1, filter_r <= 0, NULL required pointer, ... */
+                          penal < 1, filter_r not in (0, 8], NULL required pointer, ... */
   FE_ENOMEM = -2,      /* workspace smaller than fe_workspace_size(cfg) */
   FE_EDEVICE = -3,     /* a HIP runtime call failed */
   FE_ENOTCONV = -4,    /* iteration limit reached; u holds the last iterate */
@@ -68,7 +68,7 @@ typedef struct fe_config {
   double E0, Emin;      /* SIMP moduli, 0 < Emin < E0 */
   double nu;            /* Poisson ratio, -1 < nu < 0.5 */
   double penal;         /* SIMP exponent p >= 1 */
-  double filter_r;      /* density-filter radius in element units (> 0) */
+  double filter_r;      /* density-filter radius in element units, 0 < filter_r <= 8 */
   int32_t precision;    /* FE_PREC_* */
   int32_t precond;      /* FE_PRECOND_* */
   int32_t mg_levels;    /* levels of the geometric multigrid (>= 2 when precond = GMG) */

@@ -5,6 +5,7 @@
 #include <algorithm>
 #include <cmath>
 #include <cstdio>
+#include <cstdlib>
 #include <cstring>
 #include <mutex>
 #include <new>
@@ -46,7 +47,7 @@ std::string validate(const fe_config* c) {
   if (!(c->E0 > 0.0) || !std::isfinite(c->E0)) return "E0 must be > 0";
   if (!(c->Emin > 0.0 && c->Emin < c->E0)) return "Emin must lie in (0, E0)";
   if (!(c->penal >= 1.0) || !std::isfinite(c->penal)) return "penal must be >= 1";
-  if (!(c->filter_r > 0.0) || c->filter_r > 7.0) return "filter_r must lie in (0, 7]";
+  if (!(c->filter_r > 0.0) || c->filter_r > 8.0) return "filter_r must lie in (0, 8]";
   if (c->precision < FE_PREC_FP64 || c->precision > FE_PREC_BF16X3_IR) return "unknown precision";
   if (c->precond != FE_PRECOND_JACOBI && c->precond != FE_PRECOND_GMG) return "unknown preconditioner";
   if (c->reserved != 0) return "reserved must be 0";
@@ -63,7 +64,7 @@ std::string validate(const fe_config* c) {
     for (int dj = -R; dj <= R; ++dj)
       for (int di = -R; di <= R; ++di)
         if (c->filter_r - std::sqrt((double)(di * di + dj * dj + dk * dk)) > 0.0) ++cnt;
-  if (cnt > 512) return "filter radius too large";
+  if (cnt > FE_MAX_STENCIL) return "filter radius too large";
   return "";
 }
 
@@ -111,8 +112,8 @@ size_t layout(const fe_config* c, fe_problem* p, char* base) {
   }
   double* f = (double*)take(g0.ndof * sizeof(double));
   double* invW = (double*)take(g0.nelem * sizeof(double));
-  int4* st_off = (int4*)take(512 * sizeof(int4));
-  double* st_w = (double*)take(512 * sizeof(double));
+  int* st_lin = (int*)take(FE_MAX_STENCIL * sizeof(int));
+  double* st_w = (double*)take(FE_MAX_STENCIL * sizeof(double));
   double* r64 = (double*)take(g0.ndof * sizeof(double));
   double* p64 = (double*)take(g0.ndof * sizeof(double));
   double* p64b = (double*)take(g0.ndof * sizeof(double));
@@ -158,7 +159,7 @@ size_t layout(const fe_config* c, fe_problem* p, char* base) {
     }
     p->f = f;
     p->invW = invW;
-    p->st_off = st_off;
+    p->st_lin = st_lin;
     p->st_w = st_w;
     p->r64 = r64;
     p->p64 = p64;
@@ -693,23 +694,33 @@ extern "C" fe_status fe_setup(const fe_config* cfg, const uint8_t* fixed, const 
   float ke32h[576];
   for (int i = 0; i < 576; ++i) ke32h[i] = (float)p->ke64_host[i];
 
-  // filter stencil: offsets with positive cone weight r - |d|
-  int4 off[512];
-  double w[512];
-  int n = 0;
+  // filter stencil: offsets d with positive cone weight r - |d| (z slowest),
+  // as offsets into the LDS tile of the filter kernel (8 x 8 x tz elements
+  // plus a halo of the stencil's reach H; tz = 2 when the halo is 7, so that
+  // the tile stays within 64 KB)
   const double r = cfg->filter_r;
   const int R = (int)std::ceil(r);
+  std::vector<int> soff;
+  std::vector<double> w;
+  int H = 0;
   for (int dk = -R; dk <= R; ++dk)
     for (int dj = -R; dj <= R; ++dj)
       for (int di = -R; di <= R; ++di) {
         const double wt = r - std::sqrt((double)(di * di + dj * dj + dk * dk));
         if (wt > 0.0) {
-          off[n] = make_int4(di, dj, dk, 0);
-          w[n] = wt;
-          ++n;
+          soff.insert(soff.end(), {di, dj, dk});
+          w.push_back(wt);
+          H = std::max(H, std::max(std::abs(di), std::max(std::abs(dj), std::abs(dk))));
         }
       }
+  const int n = (int)w.size();
+  const int tz = H <= 6 ? 4 : 2;
+  const int LX = 8 + 2 * H;
+  std::vector<int> lin(n);
+  for (int q = 0; q < n; ++q) lin[q] = (soff[3 * q + 2] * LX + soff[3 * q + 1]) * LX + soff[3 * q];
   p->nstencil = n;
+  p->st_halo = H;
+  p->st_tz = tz;
 
   auto fail = [&](hipError_t e, const char* what) {
     fe_set_error(std::string(what) + ": " + hipGetErrorString(e));
@@ -721,9 +732,9 @@ extern "C" fe_status fe_setup(const fe_config* cfg, const uint8_t* fixed, const 
     return fail(e, "copy Ke");
   if ((e = hipMemcpyAsync(p->ke32, ke32h, sizeof(ke32h), hipMemcpyHostToDevice, p->stream)))
     return fail(e, "copy Ke32");
-  if ((e = hipMemcpyAsync(p->st_off, off, n * sizeof(int4), hipMemcpyHostToDevice, p->stream)))
+  if ((e = hipMemcpyAsync(p->st_lin, lin.data(), n * sizeof(int), hipMemcpyHostToDevice, p->stream)))
     return fail(e, "copy stencil");
-  if ((e = hipMemcpyAsync(p->st_w, w, n * sizeof(double), hipMemcpyHostToDevice, p->stream)))
+  if ((e = hipMemcpyAsync(p->st_w, w.data(), n * sizeof(double), hipMemcpyHostToDevice, p->stream)))
     return fail(e, "copy stencil weights");
   if ((e = launch_fill<double>(p, p->scal, NSCAL, 0.0))) return fail(e, "clear scalars");
   if ((e = launch_fill<double>(p, p->zpad, 8, 0.0))) return fail(e, "clear zero pad");

@@ -13,6 +13,7 @@
 #define FE_BLOCK 256
 #define FE_MAX_LEVELS 6
 #define FE_RED_GRID 4096  // grid of the reduction kernels (partials per slot)
+#define FE_MAX_STENCIL 2304  // density-filter stencil entries (radius <= 8 elements)
 
 // Structured brick grid of one multigrid level.
 struct Grid {
@@ -140,9 +141,10 @@ struct fe_problem {
   double* f = nullptr;     // load, zero on fixed dofs
   double* invW = nullptr;  // 1 / filter row sums
   double* zpad = nullptr;  // 64 zero bytes: the source of loads outside the mesh
-  int nstencil = 0;        // filter stencil: offsets and cone weights
-  int4* st_off = nullptr;
+  int nstencil = 0;             // filter stencil: LDS offsets in the filter tile, cone weights
+  int* st_lin = nullptr;
   double* st_w = nullptr;
+  int st_halo = 0, st_tz = 4;  // the stencil's reach, the filter tile's depth
 
   // float64 CG vectors
   double *r64 = nullptr, *p64 = nullptr, *q64 = nullptr;

@@ -532,46 +532,60 @@ __global__ void __launch_bounds__(FE_BLOCK) adjoint_sensitivity_kernel(Grid g, c
 }
 
 // ------------------------------------------------------------ filter
-struct Stencil {
-  int n;
-  const int4* off;  // (di, dj, dk, unused)
-  const double* w;
+// Density filter by LDS tiles.  A workgroup of 8 x 8 x tz threads owns an
+// 8 x 8 x tz brick of elements; it copies the brick and a halo of H elements
+// (the stencil's reach; zero outside the mesh, which truncates the cone at
+// the boundary) into LDS, then each thread sums the stencil over LDS.  The
+// stencil is a table of LDS offsets and cone weights r - |d| (only d with
+// positive weight, z slowest), built on the host for the tile shape; entry q
+// goes to partial sum q mod 8 (eight LDS reads in flight), and the partial
+// sums are added pairwise in a fixed order.  Modes:
+//   0  out = P in:    out_i = invW_i sum_j w_ij in_j
+//   1  out = P^T in:  out_j = sum_i w_ij invW_i in_i
+//   2  out = invW:    1 / sum_j w_ij (row sums of the truncated cone)
+struct FilterTile {
+  int n;            // stencil entries
+  const int* lin;   // LDS offset of each entry
+  const double* w;  // its weight
+  int H, tz;        // halo, brick depth
+  int tbx, tby;     // bricks along x, y
 };
 
-__global__ void __launch_bounds__(FE_BLOCK) filter_rowsum_kernel(Grid g, Stencil s, double* __restrict__ invW) {
-  for (int64_t e = blockIdx.x * (int64_t)FE_BLOCK + threadIdx.x; e < g.nelem;
-       e += (int64_t)gridDim.x * FE_BLOCK) {
-    const int i = (int)(e % g.nx), j = (int)((e / g.nx) % g.ny), k = (int)(e / ((int64_t)g.nx * g.ny));
-    double W = 0.0;
-    for (int q = 0; q < s.n; ++q) {
-      const int4 o = s.off[q];
-      const int ii = i + o.x, jj = j + o.y, kk = k + o.z;
-      if (ii >= 0 && ii < g.nx && jj >= 0 && jj < g.ny && kk >= 0 && kk < g.nz) W += s.w[q];
-    }
-    invW[e] = 1.0 / W;
-  }
-}
-
-// out = P in (transpose = 0):  out_i = invW_i sum_j w_ij in_j
-// out = P^T in (transpose = 1): out_j = sum_i w_ij invW_i in_i
-template <int TRANSPOSE>
-__global__ void __launch_bounds__(FE_BLOCK) filter_kernel(Grid g, Stencil s, const double* __restrict__ invW,
+template <int MODE>
+__global__ void __launch_bounds__(256) filter_tile_kernel(Grid g, FilterTile ft, const double* __restrict__ invW,
                                                           const double* __restrict__ in,
                                                           double* __restrict__ out) {
-  for (int64_t e = blockIdx.x * (int64_t)FE_BLOCK + threadIdx.x; e < g.nelem;
-       e += (int64_t)gridDim.x * FE_BLOCK) {
-    const int i = (int)(e % g.nx), j = (int)((e / g.nx) % g.ny), k = (int)(e / ((int64_t)g.nx * g.ny));
-    double acc = 0.0;
-    for (int q = 0; q < s.n; ++q) {
-      const int4 o = s.off[q];
-      const int ii = i + o.x, jj = j + o.y, kk = k + o.z;
-      if (ii >= 0 && ii < g.nx && jj >= 0 && jj < g.ny && kk >= 0 && kk < g.nz) {
-        const int64_t f = ii + (int64_t)g.nx * (jj + (int64_t)g.ny * kk);
-        acc += TRANSPOSE ? s.w[q] * invW[f] * in[f] : s.w[q] * in[f];
-      }
+  extern __shared__ double tile[];
+  const int LX = 8 + 2 * ft.H, LY = LX, LZ = ft.tz + 2 * ft.H;
+  const int bx = blockIdx.x % ft.tbx, t1 = blockIdx.x / ft.tbx;
+  const int by = t1 % ft.tby, bz = t1 / ft.tby;
+  const int i0 = bx * 8 - ft.H, j0 = by * 8 - ft.H, k0 = bz * ft.tz - ft.H;
+  const int nthr = 64 * ft.tz;
+  const int tid = threadIdx.x + 8 * (threadIdx.y + 8 * threadIdx.z);
+  for (int t = tid; t < LX * LY * LZ; t += nthr) {
+    const int li = t % LX, lj = (t / LX) % LY, lk = t / (LX * LY);
+    const int i = i0 + li, j = j0 + lj, k = k0 + lk;
+    double v = 0.0;
+    if (i >= 0 && i < g.nx && j >= 0 && j < g.ny && k >= 0 && k < g.nz) {
+      const int64_t f = i + (int64_t)g.nx * (j + (int64_t)g.ny * k);
+      v = MODE == 0 ? in[f] : MODE == 1 ? invW[f] * in[f] : 1.0;
     }
-    out[e] = TRANSPOSE ? acc : acc * invW[e];
+    tile[t] = v;
   }
+  __syncthreads();
+  const int i = bx * 8 + (int)threadIdx.x, j = by * 8 + (int)threadIdx.y, k = bz * ft.tz + (int)threadIdx.z;
+  if (i >= g.nx || j >= g.ny || k >= g.nz) return;
+  const double* c = tile + ((threadIdx.z + ft.H) * LY + threadIdx.y + ft.H) * LX + threadIdx.x + ft.H;
+  double a[8] = {0.0, 0.0, 0.0, 0.0, 0.0, 0.0, 0.0, 0.0};
+  int q = 0;
+  for (; q + 8 <= ft.n; q += 8) {
+#pragma unroll
+    for (int m = 0; m < 8; ++m) a[m] += ft.w[q + m] * c[ft.lin[q + m]];
+  }
+  for (int m = 0; q < ft.n; ++q, ++m) a[m] += ft.w[q] * c[ft.lin[q]];
+  const double acc = ((a[0] + a[1]) + (a[2] + a[3])) + ((a[4] + a[5]) + (a[6] + a[7]));
+  const int64_t e = i + (int64_t)g.nx * (j + (int64_t)g.ny * k);
+  out[e] = MODE == 0 ? acc * invW[e] : MODE == 1 ? acc : 1.0 / acc;
 }
 
 // ------------------------------------------------------------------ OC
@@ -1078,30 +1092,29 @@ hipError_t launch_adjoint_sensitivity(fe_problem* p, const double* rho, const do
   return hipGetLastError();
 }
 
-static Stencil make_stencil(fe_problem* p) {
-  Stencil s;
-  s.n = p->nstencil;
-  s.off = p->st_off;
-  s.w = p->st_w;
-  return s;
-}
-
-hipError_t launch_filter_rowsums(fe_problem* p) {
+template <int MODE>
+static hipError_t launch_filter_tile(fe_problem* p, const double* in, double* out) {
   const Grid g = G(p, 0);
-  hipLaunchKernelGGL(filter_rowsum_kernel, dim3(red_grid(g.nelem) * 4), dim3(FE_BLOCK), 0, p->stream, g,
-                     make_stencil(p), p->invW);
+  FilterTile ft;
+  ft.n = p->nstencil;
+  ft.lin = p->st_lin;
+  ft.w = p->st_w;
+  ft.H = p->st_halo;
+  ft.tz = p->st_tz;
+  ft.tbx = (g.nx + 7) / 8;
+  ft.tby = (g.ny + 7) / 8;
+  const int tbz = (g.nz + ft.tz - 1) / ft.tz;
+  const int L = 8 + 2 * ft.H;
+  const size_t lds = (size_t)L * L * (ft.tz + 2 * ft.H) * sizeof(double);
+  hipLaunchKernelGGL(filter_tile_kernel<MODE>, dim3(ft.tbx * ft.tby * tbz), dim3(8, 8, ft.tz), lds, p->stream, g, ft,
+                     p->invW, in, out);
   return hipGetLastError();
 }
+
+hipError_t launch_filter_rowsums(fe_problem* p) { return launch_filter_tile<2>(p, nullptr, p->invW); }
 
 hipError_t launch_filter(fe_problem* p, const double* in, double* out, int transpose) {
-  const Grid g = G(p, 0);
-  if (transpose)
-    hipLaunchKernelGGL(filter_kernel<1>, dim3(red_grid(g.nelem) * 4), dim3(FE_BLOCK), 0, p->stream, g,
-                       make_stencil(p), p->invW, in, out);
-  else
-    hipLaunchKernelGGL(filter_kernel<0>, dim3(red_grid(g.nelem) * 4), dim3(FE_BLOCK), 0, p->stream, g,
-                       make_stencil(p), p->invW, in, out);
-  return hipGetLastError();
+  return transpose ? launch_filter_tile<1>(p, in, out) : launch_filter_tile<0>(p, in, out);
 }
 
 hipError_t launch_block_mean(fe_problem* p, const double* z, int nb, double* zc) {

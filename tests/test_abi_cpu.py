@@ -37,10 +37,11 @@ def test_workspace_size_validation():
     gmg = fe.make_config(24, 12, 12, precond="gmg", mg_levels=3)
     assert lib.fe_workspace_size(C.byref(gmg)) > n
     for kw in ({"nu": 0.5}, {"nu": -1.0}, {"Emin": 0.0}, {"Emin": 2.0}, {"penal": 0.5},
-               {"filter_r": 0.0}, {"h": -1.0}):
+               {"filter_r": 0.0}, {"filter_r": 8.01}, {"h": -1.0}):
         cfg = fe.make_config(24, 12, 12, **kw)
         assert lib.fe_workspace_size(C.byref(cfg)) == 0, kw
     assert lib.fe_workspace_size(C.byref(fe.make_config(0, 12, 12))) == 0
+    assert lib.fe_workspace_size(C.byref(fe.make_config(24, 12, 12, filter_r=8.0))) > 0
     # multigrid needs dims divisible by 2^(levels-1)
     assert lib.fe_workspace_size(C.byref(fe.make_config(25, 12, 12, precond="gmg"))) == 0
 

@@ -119,16 +119,24 @@ def test_sensitivity_kernel_given_u(Ke):
 
 
 @pytest.mark.parametrize("grid", GRIDS)
-@pytest.mark.parametrize("r", [1.5, 2.3])
+@pytest.mark.parametrize("r", [1.5, 2.3, 2.8, 4.0, 7.2, 8.0])
 def test_filter_parity(grid, r):
+    """Radii from the 19-point stencil to the paper's 0.08 on its finest mesh
+    (7.2 elements, 1,560 points) and the largest supported (8).  The kernel
+    sums in stencil order, the oracle in column order: n terms of at most
+    max |y| each, so 2e-16 n relative (at least 1e-14) bounds the difference."""
     nx, ny, nz = grid
     x = synth.density_uniform(nx, ny, nz, seed=2)
     prob = _problem(nx, ny, nz, filter_r=r)
     P = O.filter_matrix(nx, ny, nz, r)
+    R = int(np.ceil(r))
+    d = np.arange(-R, R + 1)
+    nst = int(np.sum(r - np.sqrt(d[:, None, None] ** 2 + d[None, :, None] ** 2 + d[None, None, :] ** 2) > 0))
+    tol = max(1e-14, 2e-16 * nst)
     for tr in (False, True):
         y = N(prob.filter(T(x), transpose=tr))
         y_ref = (P.T @ x) if tr else (P @ x)
-        assert np.abs(y - y_ref).max() <= 1e-14 * max(1.0, np.abs(y_ref).max())
+        assert np.abs(y - y_ref).max() <= tol * max(1.0, np.abs(y_ref).max())
 
 
 @pytest.mark.parametrize("grid", [(24, 12, 12), (37, 19, 11), (3, 2, 1)])
@@ -260,6 +268,32 @@ def test_gmg_solve_parity(Ke, grid, levels, precision):
     jac = _problem(nx, ny, nz, precision=precision)
     _, info_j = jac.solve(T(rho), rtol=1e-10)
     assert info["iters"] < info_j["iters"]
+
+
+@pytest.mark.parametrize("precond", ["jacobi", "gmg"])
+def test_paper_domain_step_parity(Ke, precond):
+    """The paper's cantilever geometry (2 x 1 x 1 domain, h = 2 / nx, filter
+    radius 0.08 = 1.12 elements here) on 28x14x14: one optimisation step's
+    filter, solve, compliance and sensitivity against the oracle with Ke of
+    edge h."""
+    nx, ny, nz = 28, 14, 14
+    h = 2.0 / nx
+    r = 0.08 / h
+    x = synth.density_uniform(nx, ny, nz, seed=8)
+    f = synth.cantilever_edge_load(nx, ny, nz)
+    prob = fe.Problem(nx, ny, nz, T(f), device=DEV, h=h, filter_r=r, precond=precond, mg_levels=2)
+    rho = prob.filter(T(x))
+    P = O.filter_matrix(nx, ny, nz, r)
+    rho_ref = P @ x
+    assert np.abs(N(rho) - rho_ref).max() <= 1e-14
+    u, info = prob.solve(rho, rtol=1e-10)
+    Keh = O.hex8_ke(NU, h=h)
+    u_ref = O.solve_direct(nx, ny, nz, O.simp_modulus(rho_ref), Keh, f, O.clamp_x0_fixed(nx, ny, nz))
+    c_ref = O.compliance(f, u_ref)
+    assert abs(info["compliance"] - c_ref) / c_ref <= 1e-6
+    dc, _ = prob.sensitivity(rho, u)
+    dc_ref = O.sensitivity(nx, ny, nz, Keh, rho_ref, u_ref)
+    assert np.abs(N(dc) - dc_ref).max() <= 1e-5 * np.abs(dc_ref).max()
 
 
 def test_gmg_params_validation():
