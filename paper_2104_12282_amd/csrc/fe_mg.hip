@@ -45,13 +45,17 @@ __global__ void __launch_bounds__(FE_BLOCK) jacobi0_kernel(int64_t ndof, const T
 template <typename T>
 __global__ void __launch_bounds__(FE_BLOCK) restrict_kernel(Grid fg, Grid cg, const T* __restrict__ tf,
                                                             const uint8_t* __restrict__ cmask,
-                                                            T* __restrict__ rc, const CgState* st, int64_t wsh) {
+                                                            T* __restrict__ rc, const CgState* st, int64_t wsh,
+                                                            const T* __restrict__ invd_c, T omega,
+                                                            T* __restrict__ d0) {
   if (wsh) {  // batched launch: this workgroup's problem
     const int64_t o = batch_offset(wsh);
     tf = wshift(tf, o);
     cmask = wshift(cmask, o);
     rc = wshift(rc, o);
     st = wshift(st, o);
+    invd_c = wshift(invd_c, o);
+    d0 = wshift(d0, o);
   }
   const int64_t n = blockIdx.x * (int64_t)FE_BLOCK + threadIdx.x;
   if (n >= cg.nnode) return;
@@ -95,9 +99,16 @@ __global__ void __launch_bounds__(FE_BLOCK) restrict_kernel(Grid fg, Grid cg, co
     acc[2] += w[q] * v[q][2];
   }
   const uint8_t m = cmask[n];
+  const T dn = d0 ? invd_c[n] : T(0);
   if (st && st->done) return;  // read after the loads: no round trip in front of them
 #pragma unroll
-  for (int q = 0; q < 3; ++q) rc[3 * n + q] = ((m >> q) & 1) ? T(0) : acc[q];
+  for (int q = 0; q < 3; ++q) {
+    const T v = ((m >> q) & 1) ? T(0) : acc[q];
+    rc[3 * n + q] = v;
+    // the coarsest level's first Chebyshev direction omega D^-1 r, formed as
+    // the separate first-direction launch forms it
+    if (d0) d0[3 * n + q] = omega * dn * v;
+  }
 }
 
 // out_f = z_f + P z_c (out may alias z: each thread touches only its own node).
@@ -234,6 +245,12 @@ hipError_t presmooth(fe_problem* p, int l, const T* r, T* z, T* t, int n, CgStat
   return launch_kxu_tile<T>(p, l, z, lev_E<T>(L), t, st, 4, nullptr, nullptr, r, nullptr, 0.0);
 }
 
+// Chebyshev interval [lam_max / ratio, 1.02 lam_max] of the coarsest level: its centre.
+static inline double cheb_theta(const fe_problem* p) {
+  const double b = 1.02 * p->lam_max, a = b / p->cheb_ratio;
+  return 0.5 * (b + a);
+}
+
 // Coarsest-level solve: `deg` steps of Jacobi-preconditioned Chebyshev
 // iteration from z = 0 on the interval [lam_max / ratio, lam_max], where
 // lam_max bounds the spectrum of D^-1 K from above.  The result is a fixed
@@ -242,14 +259,15 @@ hipError_t presmooth(fe_problem* p, int l, const T* r, T* z, T* t, int n, CgStat
 // below 1 in magnitude on it) positive definite.  r and the level's mg_q
 // buffer are overwritten (the residual of the iteration).
 template <typename T>
-hipError_t chebyshev_solve(fe_problem* p, int l, T* r, T* z, T* d0, T* d1, int deg, CgState* st) {
+hipError_t chebyshev_solve(fe_problem* p, int l, T* r, T* z, T* d0, T* d1, int deg, CgState* st, bool d0_ready) {
   const Level& L = p->L[l];
   const double b = 1.02 * p->lam_max, a = b / p->cheb_ratio;
-  const double theta = 0.5 * (b + a), delta = 0.5 * (b - a), sigma = theta / delta;
+  const double theta = cheb_theta(p), delta = 0.5 * (b - a), sigma = theta / delta;
   double rho = 1.0 / sigma;
-  // d0 = D^-1 r / theta
-  hipLaunchKernelGGL(jacobi0_kernel<T>, dim3(nblocks(L.g.ndof), p->bcount), dim3(FE_BLOCK), 0, p->stream,
-                     L.g.ndof, r, lev_invd<T>(L), (T)(1.0 / theta), d0, st, wsh_of(p));
+  // d0 = D^-1 r / theta (formed by the restriction when d0_ready)
+  if (!d0_ready)
+    hipLaunchKernelGGL(jacobi0_kernel<T>, dim3(nblocks(L.g.ndof), p->bcount), dim3(FE_BLOCK), 0, p->stream,
+                       L.g.ndof, r, lev_invd<T>(L), (T)(1.0 / theta), d0, st, wsh_of(p));
   hipError_t e = hipGetLastError();
   T* r_alt = static_cast<T*>(L.mg_q);
   for (int k = 0; k < deg && e == hipSuccess;) {
@@ -290,15 +308,19 @@ hipError_t launch_vcycle(fe_problem* p, int l, const T* r, T* z, CgState* st, in
   const Level& L = p->L[l];
   T* t = static_cast<T*>(L.mg_t);
   if (l == p->nlev - 1)  // r is this level's own restricted residual: free to overwrite
-    return chebyshev_solve<T>(p, l, const_cast<T*>(r), z, t, static_cast<T*>(L.mg_w), p->mg_coarse_sweeps, st);
+    return chebyshev_solve<T>(p, l, const_cast<T*>(r), z, t, static_cast<T*>(L.mg_w), p->mg_coarse_sweeps, st,
+                              l > 0);
   // z from the pre-smoothing sweeps, t = r - K z restricted to the next level
   hipError_t e = presmooth<T>(p, l, r, z, t, p->mg_nu, st, l == 0 ? fold_rr : 0);
   if (e != hipSuccess) return e;
   const Level& C = p->L[l + 1];
   T* rc = static_cast<T*>(C.mg_r);
   T* zc = static_cast<T*>(C.mg_z);
+  // the restriction to the coarsest level also forms its first Chebyshev direction
+  const bool last = l + 1 == p->nlev - 1;
   hipLaunchKernelGGL(restrict_kernel<T>, dim3(nblocks(C.g.nnode), p->bcount), dim3(FE_BLOCK), 0, p->stream, L.g,
-                     C.g, t, C.nmask, rc, st, wsh_of(p));
+                     C.g, t, C.nmask, rc, st, wsh_of(p), last ? lev_invd<T>(C) : nullptr,
+                     (T)(1.0 / cheb_theta(p)), last ? static_cast<T*>(C.mg_t) : nullptr);
   if ((e = hipGetLastError()) != hipSuccess) return e;
   if ((e = launch_vcycle<T>(p, l + 1, rc, zc, st, RZ_NONE, 0)) != hipSuccess) return e;
   // post-smoothing, arranged so the last sweep writes z; with one fused
