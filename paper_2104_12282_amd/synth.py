@@ -79,3 +79,21 @@ def serving_requests(n, seed=0, grids=SERVING_GRIDS):
     rng = np.random.default_rng(seed)
     idx = rng.integers(0, len(grids), n)
     return [{"id": i, "grid": tuple(grids[int(idx[i])]), "seed": 1000 + i} for i in range(n)]
+
+
+def mlp_init(sizes, seed):
+    """Initial parameters of a fully-connected network with layer sizes
+    `sizes`: per layer W (out x in, row-major) from the He-uniform
+    U(-sqrt(6/in), sqrt(6/in)), then a zero bias; float64, flat."""
+    rng = np.random.default_rng(seed)
+    parts = []
+    for i, o in zip(sizes[:-1], sizes[1:]):
+        lim = np.sqrt(6.0 / i)
+        parts.append(rng.uniform(-lim, lim, o * i))
+        parts.append(np.zeros(o))
+    return np.concatenate(parts)
+
+
+def minibatches(n_samples, steps, batch, seed):
+    """steps x batch sample indices drawn uniformly with replacement (int32)."""
+    return np.random.default_rng(seed).integers(0, n_samples, size=(steps, batch)).astype(np.int32)
