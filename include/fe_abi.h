@@ -286,6 +286,73 @@ FE_API fe_status fe_batch_round_end(fe_batch* b, int32_t* running);
 /* Releases the batch and its slots' handles (the workspace stays the caller's). */
 FE_API void fe_batch_destroy(fe_batch* b);
 
+/* ---- Online neural synthetic gradients (Sec. III-B/C/E, Alg. 1) --------
+ * A sample is one block of nb x nb x nb fine elements (the coarse elements
+ * of the two-scale scheme, in coarse element order): its input is the
+ * block's design variables z (x fastest, then y, then z) followed by the 24
+ * displacements u_C of its coarse element (corner order (0,0,0) (1,0,0)
+ * (1,1,0) (0,1,0) (0,0,1) (1,0,1) (1,1,1) (0,1,1), 3 dofs each) divided by
+ * s_u; its target is the exact gradient dJ/dz of the block's elements
+ * divided by s_g.  The network: nb^3 + 24 inputs, four hidden layers of
+ * `width` with ReLU, a linear output of nb^3; parameters per layer W
+ * (out x in, row-major) then b (out), all layers in one vector of
+ * fe_onsg_num_params(nb, width) values.  Float32 arithmetic; the dense
+ * products are rocBLAS GEMMs.  All pointers are device memory owned by the
+ * caller unless stated; calls are asynchronous on the stream of
+ * fe_onsg_create except where stated. */
+typedef struct fe_onsg fe_onsg;
+
+/* Parameter count of the network for block size nb and hidden width
+ * (0 if nb is not in [1, 16] or width not in [1, 8192]). */
+FE_API int64_t fe_onsg_num_params(int32_t nb, int32_t width);
+
+/* Bytes of device workspace for a model of the (nx, ny, nz) grid, block
+ * size nb (dividing nx, ny, nz; <= 16), hidden width (1..8192), at most
+ * max_samples stored samples and mini-batches of `batch` rows; 0 if an
+ * argument is invalid.  Pure host arithmetic. */
+FE_API size_t fe_onsg_workspace_size(int32_t nx, int32_t ny, int32_t nz, int32_t nb, int32_t width,
+                              int32_t max_samples, int32_t batch);
+
+/* Creates the model in ws (256-byte aligned, >= fe_onsg_workspace_size)
+ * with the initial parameters params (float64, rounded to float32), the
+ * scales s_u, s_g (> 0) and the stream (hipStream_t, NULL = default).  The
+ * rocBLAS handle it creates holds memory of its own until
+ * fe_onsg_destroy.  FE_EINVAL / FE_ENOMEM on bad arguments. */
+FE_API fe_status fe_onsg_create(int32_t nx, int32_t ny, int32_t nz, int32_t nb, int32_t width,
+                         int32_t max_samples, int32_t batch, double s_u, double s_g, const double* params,
+                         void* ws, size_t ws_bytes, void* stream, fe_onsg** out);
+
+/* Appends the samples of every block of one exact iteration (Alg. 1's
+ * training set grows by one iteration): z (nelem design variables), uc
+ * (coarse-mesh displacements, 3 (nx/nb + 1)(ny/nb + 1)(nz/nb + 1)), g
+ * (nelem exact gradients dJ/dz), float64.  FE_EINVAL when max_samples would
+ * be exceeded. */
+FE_API fe_status fe_onsg_add_samples(fe_onsg* m, const double* z, const double* uc, const double* g);
+
+/* Number of stored samples (host output, immediate). */
+FE_API fe_status fe_onsg_num_samples(const fe_onsg* m, int64_t* n);
+
+/* One model update: `steps` Adam steps (beta1 0.9, beta2 0.999, eps 1e-8,
+ * bias-corrected, moments restarted), step t on the mini-batch of samples
+ * idx[t * batch .. t * batch + batch - 1] (int32, device; an index outside
+ * [0, num_samples) is clamped into it), learning rate lr0 halved every
+ * halve_every steps, loss = mean squared error over the batch and outputs;
+ * losses (float32[steps], device, may be NULL) receives each step's batch
+ * loss before its update. */
+FE_API fe_status fe_onsg_train(fe_onsg* m, int32_t steps, const int32_t* idx, double lr0, int32_t halve_every,
+                        float* losses);
+
+/* Synthetic gradient of every element (float64 g[nelem], device) from the
+ * design z and the coarse displacements uc, as laid out above: the
+ * network's outputs times s_g. */
+FE_API fe_status fe_onsg_predict(fe_onsg* m, const double* z, const double* uc, double* g);
+
+/* The current parameters as float64 (device array of the parameter count). */
+FE_API fe_status fe_onsg_get_params(const fe_onsg* m, double* params);
+
+/* Waits for the model's stream and releases the handle (ws stays the caller's). */
+FE_API void fe_onsg_destroy(fe_onsg* m);
+
 /* Message of the last failure on this thread ("" if none). */
 FE_API const char* fe_last_error(void);
 

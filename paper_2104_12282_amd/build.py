@@ -14,7 +14,7 @@ OUT = os.path.join(PKG, "_build")
 LIB = os.path.join(PKG, "libfe_hip.so")
 HIPCC = os.environ.get("HIPCC", "/opt/rocm/bin/hipcc")
 
-SOURCES = ["fe_host.cpp", "fe_abi.cpp", "fe_kernels.hip", "fe_kxu.hip", "fe_mg.hip"]
+SOURCES = ["fe_host.cpp", "fe_abi.cpp", "fe_kernels.hip", "fe_kxu.hip", "fe_mg.hip", "fe_onsg.hip"]
 # Packed-FP32 instructions are switched off for every device pass.
 FLAGS = ["-O3", "-std=c++17", "--offload-arch=gfx950", "-fPIC", "-Wall",
          "-Wno-unused-function", "-fvisibility=hidden", "-Xclang", "-target-feature", "-Xclang", "-packed-fp32-ops",
@@ -52,7 +52,7 @@ def build(verbose: bool = False, out_lib: str = LIB, defines=()) -> str:
     with cf.ThreadPoolExecutor(max_workers=min(8, len(SOURCES))) as ex:
         objs = list(ex.map(lambda s: _compile(s, out_dir, defines), SOURCES))
     tmp = out_lib + ".tmp"
-    cmd = [HIPCC, "--offload-arch=gfx950", "-shared", "-fPIC", *objs, "-o", tmp]
+    cmd = [HIPCC, "--offload-arch=gfx950", "-shared", "-fPIC", *objs, "-L/opt/rocm/lib", "-lrocblas", "-o", tmp]
     r = subprocess.run(cmd, capture_output=True, text=True)
     if r.returncode != 0:
         raise RuntimeError(f"link failed:\n{r.stderr}")

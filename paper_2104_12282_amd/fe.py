@@ -28,7 +28,9 @@ ABI_SYMBOLS = ("fe_workspace_size", "fe_setup", "fe_apply_K", "fe_solve", "fe_so
                "fe_solve_step", "fe_solve_end", "fe_sensitivity", "fe_sensitivity_adjoint", "fe_set_load",
                "fe_filter", "oc_update", "fe_block_mean", "fe_set_mg_params", "fe_get_mg_params", "fe_set_coarse_fusion", "fe_set_profiling",
                "fe_kernel_stats", "fe_destroy", "fe_batch_workspace_size", "fe_batch_create", "fe_batch_setup_slot",
-               "fe_batch_round_begin", "fe_batch_round_end", "fe_batch_destroy", "fe_last_error")
+               "fe_batch_round_begin", "fe_batch_round_end", "fe_batch_destroy", "fe_onsg_num_params",
+               "fe_onsg_workspace_size", "fe_onsg_create", "fe_onsg_add_samples", "fe_onsg_num_samples",
+               "fe_onsg_train", "fe_onsg_predict", "fe_onsg_get_params", "fe_onsg_destroy", "fe_last_error")
 
 
 class FEError(RuntimeError):
@@ -92,6 +94,18 @@ def load_library() -> C.CDLL:
     lib.fe_batch_round_end.argtypes = [P, C.POINTER(I32)]
     lib.fe_batch_destroy.argtypes = [P]
     lib.fe_batch_destroy.restype = None
+    lib.fe_onsg_num_params.argtypes = [I32, I32]
+    lib.fe_onsg_num_params.restype = C.c_int64
+    lib.fe_onsg_workspace_size.argtypes = [I32] * 7
+    lib.fe_onsg_workspace_size.restype = C.c_size_t
+    lib.fe_onsg_create.argtypes = [I32] * 7 + [D, D, P, P, C.c_size_t, P, C.POINTER(P)]
+    lib.fe_onsg_add_samples.argtypes = [P, P, P, P]
+    lib.fe_onsg_num_samples.argtypes = [P, C.POINTER(I64)]
+    lib.fe_onsg_train.argtypes = [P, I32, P, D, I32, P]
+    lib.fe_onsg_predict.argtypes = [P, P, P, P]
+    lib.fe_onsg_get_params.argtypes = [P, P]
+    lib.fe_onsg_destroy.argtypes = [P]
+    lib.fe_onsg_destroy.restype = None
     lib.fe_last_error.argtypes = []
     lib.fe_last_error.restype = C.c_char_p
     for name in ("fe_setup", "fe_apply_K", "fe_solve", "fe_solve_begin", "fe_solve_step",
@@ -384,6 +398,72 @@ class Batch:
                     s._h = None
             load_library().fe_batch_destroy(self._b)
             self._b = None
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
+
+
+class SyntheticGradientModel:
+    """The network of the online synthetic gradients (include/fe_abi.h,
+    fe_onsg_*): samples of the blocks of nb^3 elements of an (nx, ny, nz)
+    grid, `width`-wide hidden layers, at most max_samples stored samples,
+    mini-batches of `batch` rows, input scale s_u of the coarse
+    displacements and output scale s_g of the gradients."""
+
+    def __init__(self, nx, ny, nz, nb, width, max_samples, batch, s_u, s_g, params, *, device="cuda:0",
+                 stream: torch.cuda.Stream | None = None):
+        lib = load_library()
+        self.nx, self.ny, self.nz, self.nb, self.batch = nx, ny, nz, nb, batch
+        self.n_params = int(lib.fe_onsg_num_params(nb, width))
+        self.device = torch.device(device)
+        self.stream = stream if stream is not None else torch.cuda.current_stream(self.device)
+        nbytes = int(lib.fe_onsg_workspace_size(nx, ny, nz, nb, width, max_samples, batch)) or 256
+        self.ws = torch.empty(nbytes, dtype=torch.uint8, device=self.device)
+        p = torch.as_tensor(params, dtype=torch.float64).to(self.device).contiguous()
+        h = C.c_void_p()
+        _check(lib.fe_onsg_create(nx, ny, nz, nb, width, max_samples, batch, s_u, s_g, _ptr(p),
+                                  _ptr(self.ws, torch.uint8), nbytes, C.c_void_p(self.stream.cuda_stream), C.byref(h)))
+        torch.cuda.synchronize(self.device)  # the initial parameters are read
+        self._h = h
+
+    def add_samples(self, z, uc, g):
+        _check(load_library().fe_onsg_add_samples(self._h, _ptr(z), _ptr(uc), _ptr(g)))
+
+    @property
+    def num_samples(self):
+        n = C.c_int64()
+        _check(load_library().fe_onsg_num_samples(self._h, C.byref(n)))
+        return n.value
+
+    def train(self, idx, lr0=5e-4, halve_every=500):
+        """idx: int32 (steps, batch) sample indices; returns each step's loss."""
+        idx = torch.as_tensor(idx, dtype=torch.int32).to(self.device).contiguous()
+        if idx.dim() != 2 or idx.shape[1] != self.batch:
+            raise ValueError(f"idx must be (steps, {self.batch})")
+        losses = torch.empty(idx.shape[0], dtype=torch.float32, device=self.device)
+        _check(load_library().fe_onsg_train(self._h, idx.shape[0], _ptr(idx, torch.int32), lr0, halve_every,
+                                            _ptr(losses, torch.float32)))
+        self._idx = idx  # alive until the stream has run the update
+        return losses
+
+    def predict(self, z, uc, out=None):
+        g = torch.empty(self.nx * self.ny * self.nz, dtype=torch.float64, device=self.device) if out is None \
+            else out
+        _check(load_library().fe_onsg_predict(self._h, _ptr(z), _ptr(uc), _ptr(g)))
+        return g
+
+    def params(self):
+        p = torch.empty(self.n_params, dtype=torch.float64, device=self.device)
+        _check(load_library().fe_onsg_get_params(self._h, _ptr(p)))
+        return p
+
+    def close(self):
+        if getattr(self, "_h", None):
+            load_library().fe_onsg_destroy(self._h)
+            self._h = None
 
     def __del__(self):
         try:
