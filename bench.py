@@ -56,6 +56,8 @@ def parse():
                     help="time the adjoint gradient of a non-self-adjoint objective")
     ap.add_argument("--paper-meshes", type=int, default=200,
                     help="iterations of the runs on the paper's three cantilever meshes (0: skip)")
+    ap.add_argument("--onsg-iters", type=int, default=40,
+                    help="iterations of the online synthetic-gradient loop on the paper's mesh 2 (0: skip)")
     ap.add_argument("--cpu-grid", type=str, default="80x40x20")
     ap.add_argument("--serving", type=int, default=256,
                     help="requests of the serving stream to run (0: skip)")
@@ -463,6 +465,131 @@ def paper_mesh_study(fe, synth, torch, args, iters):
     return out
 
 
+def onsg_study(fe, synth, torch, args, K, nb=5, width=1000, steps=2000, batch=256, lr0=5e-4, halve=500,
+               n_init=10, n_freq=10):
+    """Alg. 1 on the paper's cantilever mesh 2 (100x50x50, h = 0.02, R = 0.08)
+    with block size nb: every iteration coarse-grains the design and solves
+    the coarse problem; iterations k < n_init and k = 0 mod n_freq take the
+    exact gradient, add the blocks' samples and update the network (`steps`
+    Adam steps on mini-batches of `batch` drawn uniformly from all samples so
+    far), the others take the network's synthetic gradient; OC with either.
+    The standard optimizer runs the same K iterations for comparison; both
+    final designs are evaluated by one exact solve.  Scales: s_u = max |u_C|
+    and s_g = max |g| of iteration 0."""
+    dev = "cuda:0"
+    T = lambda a: torch.as_tensor(a, dtype=torch.float64, device=dev)
+    nx, ny, nz = 100, 50, 50
+    h = 2.0 / nx
+    ne = nx * ny * nz
+    cx, cy, cz = nx // nb, ny // nb, nz // nb
+
+    def make():
+        prob = fe.Problem(nx, ny, nz, T(synth.cantilever_edge_load(nx, ny, nz)), device=dev, h=h,
+                          filter_r=0.08 / h, precision=args.precision, precond="gmg", mg_levels=2)
+        return prob
+
+    def run(onsg):
+        prob = make()
+        coarse = prob.coarse_problem(nb, T(synth.cantilever_edge_load(cx, cy, cz)))
+        x = torch.full((ne,), 0.12, dtype=torch.float64, device=dev)
+        u = torch.zeros(prob.ndof, dtype=torch.float64, device=dev)
+        uc = torch.zeros(coarse.ndof, dtype=torch.float64, device=dev)
+        rho, dc, g = (torch.empty_like(x) for _ in range(3))
+        zc = torch.empty(cx * cy * cz, dtype=torch.float64, device=dev)
+        rc = torch.empty_like(zc)
+        dv = prob.filter(torch.ones_like(x), transpose=True)
+        change = torch.zeros(1, dtype=torch.float64, device=dev)
+        model = None
+        t = {"fine": 0.0, "coarse": 0.0, "train": 0.0, "predict": 0.0, "oc": 0.0}
+        exact_iters, objective, err, losses = 0, [], [], []
+        torch.cuda.synchronize()
+        t_all = time.perf_counter()
+
+        def clock(key, t0):
+            torch.cuda.synchronize()
+            t[key] += time.perf_counter() - t0
+
+        for k in range(K):
+            exact = (not onsg) or k < n_init or k % n_freq == 0
+            if onsg:
+                t0 = time.perf_counter()
+                prob.block_mean(x, nb, out=zc)
+                coarse.filter(zc, out=rc)
+                coarse.solve(rc, u=uc, rtol=args.rtol)
+                clock("coarse", t0)
+            if exact:
+                t0 = time.perf_counter()
+                prob.filter(x, out=rho)
+                _, info = prob.solve(rho, u=u, rtol=args.rtol)
+                prob.sensitivity(rho, u, out=dc)
+                prob.filter(dc, transpose=True, out=g)
+                clock("fine", t0)
+                objective.append(info["compliance"])
+                exact_iters += 1
+                if onsg:
+                    if model is not None:
+                        # the model's synthetic gradient for this design, before it sees it
+                        gs = model.predict(x, uc)
+                        err.append({"iteration": k, "rel_l2": float((gs - g).norm() / g.norm()),
+                                    "cosine": float(torch.dot(gs, g) / (gs.norm() * g.norm()))})
+                    t0 = time.perf_counter()
+                    if model is None:
+                        s_u = float(uc.abs().max())
+                        s_g = float(g.abs().max())
+                        sizes = [nb ** 3 + 24, width, width, width, width, nb ** 3]
+                        model = fe.SyntheticGradientModel(nx, ny, nz, nb, width, (n_init + K // n_freq + 1) * cx * cy * cz,
+                                                          batch, s_u, s_g, synth.mlp_init(sizes, 0), device=dev)
+                    model.add_samples(x, uc, g)
+                    ls = model.train(synth.minibatches(model.num_samples, steps, batch, seed=1000 + k), lr0, halve)
+                    clock("train", t0)
+                    losses.append({"iteration": k, "first": float(ls[0]), "last_50_mean": float(ls[-50:].mean())})
+            else:
+                t0 = time.perf_counter()
+                model.predict(x, uc, out=g)
+                clock("predict", t0)
+            t0 = time.perf_counter()
+            prob.oc_update(x, g, dv, 0.12, args.move, out=x, change_out=change)
+            clock("oc", t0)
+        torch.cuda.synchronize()
+        wall = time.perf_counter() - t_all
+        prob.filter(x, out=rho)
+        _, info = prob.solve(rho, u=u, rtol=args.rtol)
+        rec = {"seconds": wall, "exact_iterations": exact_iters, "final_objective": info["compliance"],
+               "objective_at_exact_iterations": objective, "seconds_by_part": t}
+        if onsg:
+            rec["synthetic_vs_exact"] = err
+            rec["training_loss"] = losses
+        if model is not None:
+            model.close()
+        coarse.close()
+        prob.close()
+        return rec
+
+    std = run(False)
+    ons = run(True)
+    flops = 6.0 * batch * sum(i * o for i, o in zip([nb ** 3 + 24] + [width] * 4, [width] * 4 + [nb ** 3]))
+    out = {"mesh": [nx, ny, nz], "h": h, "filter_r_elements": 0.08 / h, "nb": nb, "iterations": K,
+           "n_init": n_init, "n_freq": n_freq, "network": {"hidden": [width] * 4, "steps_per_update": steps,
+                                                          "batch": batch, "lr0": lr0, "halve_every": halve},
+           "standard": std, "onsg": ons,
+           "training_tflops": flops * steps * (ons["exact_iterations"]) / max(ons["seconds_by_part"]["train"], 1e-9)
+           / 1e12,
+           "final_objective_rel_diff": ons["final_objective"] / std["final_objective"] - 1.0,
+           "speedup": std["seconds"] / ons["seconds"]}
+    for e in ons["synthetic_vs_exact"]:
+        print(f"bench[onsg]: iteration {e['iteration']}: synthetic vs exact gradient rel. l2 error "
+              f"{e['rel_l2']:.3f}, cosine {e['cosine']:.3f}", file=sys.stderr, flush=True)
+    for e in ons["training_loss"]:
+        print(f"bench[onsg]: update at {e['iteration']}: loss {e['first']:.3g} -> {e['last_50_mean']:.3g}",
+              file=sys.stderr, flush=True)
+    print(f"bench[onsg]: {K} iterations on 100x50x50 (nb {nb}): standard {std['seconds']:.2f} s, objective "
+          f"{std['final_objective']:.4g}; ONSG {ons['seconds']:.2f} s ({ons['exact_iterations']} exact, "
+          f"train {ons['seconds_by_part']['train']:.2f} s at {out['training_tflops']:.1f} TFLOP/s, coarse "
+          f"{ons['seconds_by_part']['coarse']:.2f} s), objective {ons['final_objective']:.4g}",
+          file=sys.stderr, flush=True)
+    return out
+
+
 def serving_bench(n, torch, nslots=16):
     """Serving stream of n seeded requests over the five grid sizes: the same
     requests one at a time (blocking solves); through the batched engine
@@ -664,6 +791,8 @@ def main():
                                "cg_iters_per_solve": float(np.mean(rec4["iters"]))}
     if args.precision_seeds > 0:
         out["precision_study"] = precision_study(fe, synth, torch, nx, ny, nz, args.precision_seeds, args)
+    if args.onsg_iters > 0:
+        out["onsg"] = onsg_study(fe, synth, torch, args, args.onsg_iters)
     if args.paper_meshes > 0:
         out["paper_meshes"] = paper_mesh_study(fe, synth, torch, args, args.paper_meshes)
     if args.adjoint:
