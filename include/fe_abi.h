@@ -209,6 +209,15 @@ FE_API fe_status fe_block_mean(fe_problem* p, const double* z, int32_t nb, doubl
 FE_API fe_status fe_set_mg_params(fe_problem* p, int32_t nu, int32_t coarse_sweeps, double omega,
                            double coarse_ratio);
 
+/* Precision of the coarsest-level Chebyshev solve inside the multigrid
+ * preconditioner of FE_PREC_FP64 solves: 32 (default) runs it in float32 on
+ * the level's float32 moduli and inverse diagonal (the restriction rounds
+ * the float64 residual once, the prolongation widens the correction), 64 in
+ * float64.  The CG vectors, products, reductions and the returned residual
+ * stay float64 either way; the preconditioner remains a fixed linear map up
+ * to float32 rounding.  No effect on float32 inner solves. */
+FE_API fe_status fe_set_coarse_precision(fe_problem* p, int32_t bits);
+
 /* The multigrid parameters in effect (the defaults above or the last
  * fe_set_mg_params); each output pointer is host memory and may be NULL. */
 FE_API fe_status fe_get_mg_params(const fe_problem* p, int32_t* nu, int32_t* coarse_sweeps, double* omega,

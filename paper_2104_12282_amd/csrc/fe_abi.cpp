@@ -1010,6 +1010,22 @@ extern "C" fe_status fe_set_mg_params(fe_problem* p, int32_t nu, int32_t coarse_
   return FE_OK;
 }
 
+extern "C" fe_status fe_set_coarse_precision(fe_problem* p, int32_t bits) {
+  CHECK_HANDLE(p);
+  if (p->in_batch) {
+    fe_set_error("batch slots share the batch's multigrid parameters (the library defaults)");
+    return FE_EINVAL;
+  }
+  if (bits != 32 && bits != 64) {
+    fe_set_error("bits must be 32 or 64");
+    return FE_EINVAL;
+  }
+  p->coarse_f32 = bits == 32 ? 1 : 0;
+  drop_graph(p->chunk64);  // the captured chunks bake the path in
+  drop_graph(p->chunk32);
+  return FE_OK;
+}
+
 extern "C" fe_status fe_get_mg_params(const fe_problem* p, int32_t* nu, int32_t* coarse_sweeps, double* omega,
                                       double* coarse_ratio) {
   CHECK_HANDLE(p);

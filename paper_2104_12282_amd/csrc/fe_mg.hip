@@ -6,6 +6,7 @@
 // which keeps the V-cycle symmetric so it can precondition CG.
 #include <hip/hip_runtime.h>
 
+#include <type_traits>
 #include <utility>
 
 #include "fe_internal.h"
@@ -42,12 +43,14 @@ __global__ void __launch_bounds__(FE_BLOCK) jacobi0_kernel(int64_t ndof, const T
 
 // r_c = P^T t_f: coarse node (I,J,K) collects the fine nodes 2I+a, 2J+b, 2K+c
 // (a, b, c in {-1, 0, 1}) with weight prod (a == 0 ? 1 : 1/2).
-template <typename T>
+// The coarse level may hold a narrower type (TC) than the fine one (T): the
+// sum is formed in T and rounded once.
+template <typename T, typename TC = T>
 __global__ void __launch_bounds__(FE_BLOCK) restrict_kernel(Grid fg, Grid cg, const T* __restrict__ tf,
                                                             const uint8_t* __restrict__ cmask,
-                                                            T* __restrict__ rc, const CgState* st, int64_t wsh,
-                                                            const T* __restrict__ invd_c, T omega,
-                                                            T* __restrict__ d0) {
+                                                            TC* __restrict__ rc, const CgState* st, int64_t wsh,
+                                                            const TC* __restrict__ invd_c, TC omega,
+                                                            TC* __restrict__ d0) {
   if (wsh) {  // batched launch: this workgroup's problem
     const int64_t o = batch_offset(wsh);
     tf = wshift(tf, o);
@@ -99,11 +102,11 @@ __global__ void __launch_bounds__(FE_BLOCK) restrict_kernel(Grid fg, Grid cg, co
     acc[2] += w[q] * v[q][2];
   }
   const uint8_t m = cmask[n];
-  const T dn = d0 ? invd_c[n] : T(0);
+  const TC dn = d0 ? invd_c[n] : TC(0);
   if (st && st->done) return;  // read after the loads: no round trip in front of them
 #pragma unroll
   for (int q = 0; q < 3; ++q) {
-    const T v = ((m >> q) & 1) ? T(0) : acc[q];
+    const TC v = ((m >> q) & 1) ? TC(0) : (TC)acc[q];
     rc[3 * n + q] = v;
     // the coarsest level's first Chebyshev direction omega D^-1 r, formed as
     // the separate first-direction launch forms it
@@ -115,9 +118,9 @@ __global__ void __launch_bounds__(FE_BLOCK) restrict_kernel(Grid fg, Grid cg, co
 // With rf given, z_f is the first Jacobi sweep from zero, formed here as
 // (omega D^-1) r_f exactly as the launch that used it formed it, instead of
 // being stored there and read back.
-template <typename T>
+template <typename T, typename TC = T>
 __global__ void __launch_bounds__(FE_BLOCK) prolong_add_kernel(Grid fg, Grid cg, const T* zf,
-                                                               const T* __restrict__ zc,
+                                                               const TC* __restrict__ zc,
                                                                const uint8_t* __restrict__ fmask, T* out,
                                                                const T* __restrict__ rf, const T* __restrict__ invd,
                                                                T omega, const CgState* st, int64_t wsh) {
@@ -154,9 +157,9 @@ __global__ void __launch_bounds__(FE_BLOCK) prolong_add_kernel(Grid fg, Grid cg,
         const bool used = (c == 0 || (k & 1)) && (b == 0 || (j & 1)) && (a == 0 || (i & 1));
         const int64_t cq = ii[a] + csx * jj[b] + csxy * kk[c];
         wq[q] = used ? w : T(0);
-        v[q][0] = zc[3 * cq];
-        v[q][1] = zc[3 * cq + 1];
-        v[q][2] = zc[3 * cq + 2];
+        v[q][0] = (T)zc[3 * cq];
+        v[q][1] = (T)zc[3 * cq + 1];
+        v[q][2] = (T)zc[3 * cq + 2];
       }
   T acc[3] = {T(0), T(0), T(0)};
 #pragma unroll
@@ -318,19 +321,37 @@ hipError_t launch_vcycle(fe_problem* p, int l, const T* r, T* z, CgState* st, in
   T* zc = static_cast<T*>(C.mg_z);
   // the restriction to the coarsest level also forms its first Chebyshev direction
   const bool last = l + 1 == p->nlev - 1;
-  hipLaunchKernelGGL(restrict_kernel<T>, dim3(nblocks(C.g.nnode), p->bcount), dim3(FE_BLOCK), 0, p->stream, L.g,
-                     C.g, t, C.nmask, rc, st, wsh_of(p), last ? lev_invd<T>(C) : nullptr,
-                     (T)(1.0 / cheb_theta(p)), last ? static_cast<T*>(C.mg_t) : nullptr);
-  if ((e = hipGetLastError()) != hipSuccess) return e;
-  if ((e = launch_vcycle<T>(p, l + 1, rc, zc, st, RZ_NONE, 0)) != hipSuccess) return e;
-  // post-smoothing, arranged so the last sweep writes z; with one fused
-  // pre-smoothing sweep z was not stored and the prolongation forms it
+  // a float64 hierarchy may solve its coarsest level in float32 (the
+  // level's buffers are sized for float64 and hold the float32 values)
+  const bool narrow = last && std::is_same<T, double>::value && p->coarse_f32;
   const int nu = p->mg_nu;
   const bool z_implicit = nu == 1 && (!(l == 0 && p->mfma_l0) || (l == 0 && fold_rr > 0));
   T* a = (nu % 2) ? t : z;
-  hipLaunchKernelGGL(prolong_add_kernel<T>, dim3(nblocks(L.g.nnode), p->bcount), dim3(FE_BLOCK), 0, p->stream,
-                     L.g, C.g, z, zc, L.nmask, a, z_implicit ? r : nullptr, z_implicit ? lev_invd<T>(L) : nullptr,
-                     (T)p->mg_omega, st, wsh_of(p));
+  if (narrow) {
+    float* rcf = static_cast<float*>(C.mg_r);
+    float* zcf = static_cast<float*>(C.mg_z);
+    hipLaunchKernelGGL((restrict_kernel<T, float>), dim3(nblocks(C.g.nnode), p->bcount), dim3(FE_BLOCK), 0,
+                       p->stream, L.g, C.g, t, C.nmask, rcf, st, wsh_of(p), C.invd32, (float)(1.0 / cheb_theta(p)),
+                       static_cast<float*>(C.mg_t));
+    if ((e = hipGetLastError()) != hipSuccess) return e;
+    if ((e = chebyshev_solve<float>(p, l + 1, rcf, zcf, static_cast<float*>(C.mg_t), static_cast<float*>(C.mg_w),
+                                    p->mg_coarse_sweeps, st, true)) != hipSuccess)
+      return e;
+    hipLaunchKernelGGL((prolong_add_kernel<T, float>), dim3(nblocks(L.g.nnode), p->bcount), dim3(FE_BLOCK), 0,
+                       p->stream, L.g, C.g, z, zcf, L.nmask, a, z_implicit ? r : nullptr,
+                       z_implicit ? lev_invd<T>(L) : nullptr, (T)p->mg_omega, st, wsh_of(p));
+  } else {
+    hipLaunchKernelGGL(restrict_kernel<T>, dim3(nblocks(C.g.nnode), p->bcount), dim3(FE_BLOCK), 0, p->stream, L.g,
+                       C.g, t, C.nmask, rc, st, wsh_of(p), last ? lev_invd<T>(C) : nullptr,
+                       (T)(1.0 / cheb_theta(p)), last ? static_cast<T*>(C.mg_t) : nullptr);
+    if ((e = hipGetLastError()) != hipSuccess) return e;
+    if ((e = launch_vcycle<T>(p, l + 1, rc, zc, st, RZ_NONE, 0)) != hipSuccess) return e;
+    // post-smoothing, arranged so the last sweep writes z; with one fused
+    // pre-smoothing sweep z was not stored and the prolongation forms it
+    hipLaunchKernelGGL(prolong_add_kernel<T>, dim3(nblocks(L.g.nnode), p->bcount), dim3(FE_BLOCK), 0, p->stream,
+                       L.g, C.g, z, zc, L.nmask, a, z_implicit ? r : nullptr, z_implicit ? lev_invd<T>(L) : nullptr,
+                       (T)p->mg_omega, st, wsh_of(p));
+  }
   if ((e = hipGetLastError()) != hipSuccess) return e;
   T* b = (a == t) ? z : t;
   for (int s = 0; s < nu; ++s) {
