@@ -138,7 +138,7 @@ def coarse_solve_record(nx, ny, nz, args, degree):
                      + ">: two coarsest-level Chebyshev steps per launch",
            "coarse_grid": [cx, cy, cz], "launches_per_vcycle": (degree + 1) // 2,
            "algorithmic_bytes_per_launch": nbytes, "bound": "latency",
-           "note": "about 4 MB per launch on a 22k-element grid: the launch is bound by its chain of "
+           "note": "a few MB per launch on a 22k-element grid: the launch is bound by its chain of "
                    "dependent memory round trips and march steps, not by HBM bandwidth"}
     rec = profile_record(f"{nx}x{ny}x{nz}")
     if rec:
