@@ -40,8 +40,9 @@ def parse():
     ap.add_argument("--mg-nu", type=int, default=1)
     ap.add_argument("--mg-coarse", type=int, default=0,
                     help="coarsest-level Chebyshev degree (0: the library's default for the coarsest grid)")
-    ap.add_argument("--coarse-bits", type=int, default=32, choices=[32, 64],
-                    help="precision of the coarsest-level Chebyshev inside float64 multigrid solves")
+    ap.add_argument("--f32-from", type=int, default=0,
+                    help="first multigrid level run in float32 inside float64 solves (0: the library default, "
+                         "level 1; the number of levels: none)")
     ap.add_argument("--mg-coarse-ratio", type=float, default=0.0,
                     help="coarsest-level Chebyshev interval ratio (0: the library's default)")
     ap.add_argument("--rtol", type=float, default=1e-6)
@@ -112,7 +113,8 @@ def apply_mg(prob, args):
     library's default for that problem's coarsest grid."""
     if args.precond != "gmg" or prob.cfg.precond != 1:
         return None
-    prob.set_coarse_precision(args.coarse_bits)
+    if args.f32_from > 0:
+        prob.set_float32_levels(min(args.f32_from, prob.cfg.mg_levels))
     cur = prob.mg_params()
     prob.set_mg_params(nu=args.mg_nu, coarse_sweeps=args.mg_coarse or cur["coarse_sweeps"], omega=cur["omega"],
                        coarse_ratio=args.mg_coarse_ratio or cur["coarse_ratio"])
@@ -129,7 +131,7 @@ def coarse_solve_record(nx, ny, nz, args, degree):
     s = 2 ** (args.mg_levels - 1)
     cx, cy, cz = nx // s, ny // s, nz // s
     nnode = (cx + 1) * (cy + 1) * (cz + 1)
-    wide = args.precision == "fp64" and args.coarse_bits == 64
+    wide = args.precision == "fp64" and args.f32_from >= args.mg_levels  # the coarsest level in float64
     vb = 8.0 if wide else 4.0
     # d_k, r_k, acc read and r, acc, d_{k+2} written (3 dofs per node), moduli,
     # inverse diagonal, fixed-dof mask: each array once
@@ -745,7 +747,7 @@ def main():
                    "mg_smoothing_sweeps": args.mg_nu if args.precond == "gmg" else None,
                    "mg_coarse_chebyshev_degree": rec["mg"]["coarse_sweeps"] if rec["mg"] else None,
                    "mg_coarse_chebyshev_ratio": rec["mg"]["coarse_ratio"] if rec["mg"] else None,
-                   "mg_coarse_chebyshev_precision": (f"f{args.coarse_bits}" if args.precision == "fp64" else "f32")
+                   "mg_float32_from_level": ((args.f32_from or 1) if args.precision == "fp64" else 0)
                    if rec["mg"] else None,
                    "rtol": args.rtol, "volfrac": args.volfrac, "filter_r": 1.5, "move": args.move,
                    "cg_iters_per_solve": float(np.mean(rec["iters"])),

@@ -209,14 +209,16 @@ FE_API fe_status fe_block_mean(fe_problem* p, const double* z, int32_t nb, doubl
 FE_API fe_status fe_set_mg_params(fe_problem* p, int32_t nu, int32_t coarse_sweeps, double omega,
                            double coarse_ratio);
 
-/* Precision of the coarsest-level Chebyshev solve inside the multigrid
- * preconditioner of FE_PREC_FP64 solves: 32 (default) runs it in float32 on
- * the level's float32 moduli and inverse diagonal (the restriction rounds
- * the float64 residual once, the prolongation widens the correction), 64 in
- * float64.  The CG vectors, products, reductions and the returned residual
- * stay float64 either way; the preconditioner remains a fixed linear map up
- * to float32 rounding.  No effect on float32 inner solves. */
-FE_API fe_status fe_set_coarse_precision(fe_problem* p, int32_t bits);
+/* Levels first_level .. nlev-1 of the multigrid preconditioner of
+ * FE_PREC_FP64 solves run in float32 on their float32 moduli and inverse
+ * diagonals (the restriction into first_level sums in float64 and rounds
+ * once, the prolongation out of it widens the correction); first_level =
+ * nlev keeps the whole hierarchy in float64.  Default 1: every level below
+ * the finest in float32.  The CG vectors, products, reductions
+ * and the returned residual stay float64 either way; the preconditioner
+ * remains a fixed linear map up to float32 rounding.  No effect on float32
+ * inner solves.  FE_EINVAL unless 1 <= first_level <= nlev. */
+FE_API fe_status fe_set_float32_levels(fe_problem* p, int32_t first_level);
 
 /* The multigrid parameters in effect (the defaults above or the last
  * fe_set_mg_params); each output pointer is host memory and may be NULL. */

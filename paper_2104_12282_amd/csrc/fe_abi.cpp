@@ -144,6 +144,7 @@ size_t layout(const fe_config* c, fe_problem* p, char* base) {
   double* zpad = (double*)take(8 * sizeof(double));
   if (p) {
     p->nlev = nl;
+    p->f32_from = 1;  // every level below the finest in float32
     if (nl > 1) {
       // default coarse Chebyshev for the coarsest grid's longest dimension
       // n: the number of steps a Chebyshev solve needs grows like the square
@@ -1010,17 +1011,17 @@ extern "C" fe_status fe_set_mg_params(fe_problem* p, int32_t nu, int32_t coarse_
   return FE_OK;
 }
 
-extern "C" fe_status fe_set_coarse_precision(fe_problem* p, int32_t bits) {
+extern "C" fe_status fe_set_float32_levels(fe_problem* p, int32_t first_level) {
   CHECK_HANDLE(p);
   if (p->in_batch) {
     fe_set_error("batch slots share the batch's multigrid parameters (the library defaults)");
     return FE_EINVAL;
   }
-  if (bits != 32 && bits != 64) {
-    fe_set_error("bits must be 32 or 64");
+  if (first_level < 1 || first_level > p->nlev) {
+    fe_set_error("first_level must lie in [1, number of levels]");
     return FE_EINVAL;
   }
-  p->coarse_f32 = bits == 32 ? 1 : 0;
+  p->f32_from = first_level;
   drop_graph(p->chunk64);  // the captured chunks bake the path in
   drop_graph(p->chunk32);
   return FE_OK;

@@ -184,7 +184,7 @@ struct fe_problem {
   double lam_max = 0.0;        // lambda_max(diag(Ke)^-1 Ke): bounds that of D^-1 K on every level
   double cheb_ratio = 5000.0;  // coarse Chebyshev interval [lam_max / ratio, lam_max]
   int cheb_per_launch = 2;     // coarse Chebyshev steps per launch (2: pairs fused, 1: one each)
-  int coarse_f32 = 1;          // float64 solves run the coarsest level's Chebyshev in float32
+  int f32_from = 1 << 30;      // float64 solves run multigrid levels >= f32_from in float32
 
   KStats kst;
 

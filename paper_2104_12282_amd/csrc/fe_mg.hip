@@ -321,9 +321,9 @@ hipError_t launch_vcycle(fe_problem* p, int l, const T* r, T* z, CgState* st, in
   T* zc = static_cast<T*>(C.mg_z);
   // the restriction to the coarsest level also forms its first Chebyshev direction
   const bool last = l + 1 == p->nlev - 1;
-  // a float64 hierarchy may solve its coarsest level in float32 (the
-  // level's buffers are sized for float64 and hold the float32 values)
-  const bool narrow = last && std::is_same<T, double>::value && p->coarse_f32;
+  // a float64 hierarchy may run its levels from f32_from on in float32 (their
+  // buffers are sized for float64 and hold the float32 values)
+  const bool narrow = std::is_same<T, double>::value && l + 1 >= p->f32_from;
   const int nu = p->mg_nu;
   const bool z_implicit = nu == 1 && (!(l == 0 && p->mfma_l0) || (l == 0 && fold_rr > 0));
   T* a = (nu % 2) ? t : z;
@@ -331,12 +331,10 @@ hipError_t launch_vcycle(fe_problem* p, int l, const T* r, T* z, CgState* st, in
     float* rcf = static_cast<float*>(C.mg_r);
     float* zcf = static_cast<float*>(C.mg_z);
     hipLaunchKernelGGL((restrict_kernel<T, float>), dim3(nblocks(C.g.nnode), p->bcount), dim3(FE_BLOCK), 0,
-                       p->stream, L.g, C.g, t, C.nmask, rcf, st, wsh_of(p), C.invd32, (float)(1.0 / cheb_theta(p)),
-                       static_cast<float*>(C.mg_t));
+                       p->stream, L.g, C.g, t, C.nmask, rcf, st, wsh_of(p), last ? C.invd32 : nullptr,
+                       (float)(1.0 / cheb_theta(p)), last ? static_cast<float*>(C.mg_t) : nullptr);
     if ((e = hipGetLastError()) != hipSuccess) return e;
-    if ((e = chebyshev_solve<float>(p, l + 1, rcf, zcf, static_cast<float*>(C.mg_t), static_cast<float*>(C.mg_w),
-                                    p->mg_coarse_sweeps, st, true)) != hipSuccess)
-      return e;
+    if ((e = launch_vcycle<float>(p, l + 1, rcf, zcf, st, RZ_NONE, 0)) != hipSuccess) return e;
     hipLaunchKernelGGL((prolong_add_kernel<T, float>), dim3(nblocks(L.g.nnode), p->bcount), dim3(FE_BLOCK), 0,
                        p->stream, L.g, C.g, z, zcf, L.nmask, a, z_implicit ? r : nullptr,
                        z_implicit ? lev_invd<T>(L) : nullptr, (T)p->mg_omega, st, wsh_of(p));

@@ -26,7 +26,7 @@ STATUS_NAME = {0: "FE_OK", -1: "FE_EINVAL", -2: "FE_ENOMEM", -3: "FE_EDEVICE",
 # Every entry point declared in include/fe_abi.h.
 ABI_SYMBOLS = ("fe_workspace_size", "fe_setup", "fe_apply_K", "fe_solve", "fe_solve_begin",
                "fe_solve_step", "fe_solve_end", "fe_sensitivity", "fe_sensitivity_adjoint", "fe_set_load",
-               "fe_filter", "oc_update", "fe_block_mean", "fe_set_mg_params", "fe_get_mg_params", "fe_set_coarse_precision", "fe_set_coarse_fusion", "fe_set_profiling",
+               "fe_filter", "oc_update", "fe_block_mean", "fe_set_mg_params", "fe_get_mg_params", "fe_set_float32_levels", "fe_set_coarse_fusion", "fe_set_profiling",
                "fe_kernel_stats", "fe_destroy", "fe_batch_workspace_size", "fe_batch_create", "fe_batch_setup_slot",
                "fe_batch_round_begin", "fe_batch_round_end", "fe_batch_destroy", "fe_onsg_num_params",
                "fe_onsg_workspace_size", "fe_onsg_create", "fe_onsg_add_samples", "fe_onsg_num_samples",
@@ -80,7 +80,7 @@ def load_library() -> C.CDLL:
     lib.oc_update.argtypes = [P, P, P, P, D, D, P, P]
     lib.fe_block_mean.argtypes = [P, P, I32, P]
     lib.fe_set_mg_params.argtypes = [P, I32, I32, D, D]
-    lib.fe_set_coarse_precision.argtypes = [P, I32]
+    lib.fe_set_float32_levels.argtypes = [P, I32]
     lib.fe_get_mg_params.argtypes = [P, C.POINTER(I32), C.POINTER(I32), C.POINTER(D), C.POINTER(D)]
     lib.fe_set_coarse_fusion.argtypes = [P, I32]
     lib.fe_set_profiling.argtypes = [P, I32]
@@ -326,9 +326,10 @@ class Problem:
         _check(load_library().fe_get_mg_params(self._h, C.byref(nu), C.byref(deg), C.byref(om), C.byref(ra)))
         return {"nu": nu.value, "coarse_sweeps": deg.value, "omega": om.value, "coarse_ratio": ra.value}
 
-    def set_coarse_precision(self, bits=32):
-        """Coarsest-level Chebyshev of float64 solves in float32 (32) or float64 (64)."""
-        _check(load_library().fe_set_coarse_precision(self._h, bits))
+    def set_float32_levels(self, first_level):
+        """Multigrid levels >= first_level of float64 solves in float32
+        (first_level = number of levels: none)."""
+        _check(load_library().fe_set_float32_levels(self._h, first_level))
 
     def set_coarse_fusion(self, steps_per_launch=2):
         """Coarsest-level Chebyshev steps per launch (2: pairs fused, 1: one each)."""

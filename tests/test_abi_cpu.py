@@ -74,7 +74,7 @@ def test_calls_on_null_handle_fail_cleanly():
     assert lib.fe_sensitivity_adjoint(None, x, x, x, x) == fe.FE_EINVAL
     assert lib.fe_set_load(None, x) == fe.FE_EINVAL
     assert lib.fe_get_mg_params(None, None, None, None, None) == fe.FE_EINVAL
-    assert lib.fe_set_coarse_precision(None, 32) == fe.FE_EINVAL
+    assert lib.fe_set_float32_levels(None, 1) == fe.FE_EINVAL
     assert lib.fe_apply_K(None, x, x, x, 0) == fe.FE_EINVAL
     lib.fe_destroy(None)
 

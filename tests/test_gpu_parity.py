@@ -297,12 +297,12 @@ def test_paper_domain_step_parity(Ke, precond):
 
 
 @pytest.mark.parametrize("grid,levels", [((24, 12, 12), 3), ((32, 16, 16), 3), ((20, 10, 6), 2)])
-def test_float32_coarse_level_in_float64_solves(Ke, grid, levels):
-    """The float64 solve with its coarsest Chebyshev in float32 (default)
-    and in float64 reach the oracle's answer to the contract's tolerances;
-    float32 rounding in the preconditioner costs some iterations near a
-    tight tolerance (1e-10 here: up to a quarter more); 32 / 64 select the
-    path, other values are rejected."""
+def test_float32_levels_in_float64_solves(Ke, grid, levels):
+    """Float64 solves with their multigrid levels from k on in float32 (k =
+    1 is the default; k = levels keeps float64) reach the oracle's
+    answer to the contract's tolerances; float32 rounding in the
+    preconditioner costs some iterations near a tight tolerance (1e-10 here:
+    up to a quarter more); levels outside [1, levels] are rejected."""
     nx, ny, nz = grid
     rho = synth.density_uniform(nx, ny, nz, seed=3)
     f = synth.cantilever_edge_load(nx, ny, nz)
@@ -311,19 +311,25 @@ def test_float32_coarse_level_in_float64_solves(Ke, grid, levels):
     c_ref = O.compliance(f, u_ref)
     dc_ref = O.sensitivity(nx, ny, nz, Ke, rho, u_ref)
     its = {}
-    for bits in (32, 64):
+    for first in range(1, levels + 1):
         prob = _problem(nx, ny, nz, precond="gmg", mg_levels=levels)
-        prob.set_coarse_precision(bits)
+        prob.set_float32_levels(first)
         u, info = prob.solve(T(rho), rtol=1e-10)
         assert info["rel_res"] <= 1e-10
         assert abs(info["compliance"] - c_ref) / c_ref <= 1e-6
         dc, _ = prob.sensitivity(T(rho), u)
         assert np.abs(N(dc) - dc_ref).max() <= 1e-5 * np.abs(dc_ref).max()
-        its[bits] = info["iters"]
-        with pytest.raises(fe.FEError):
-            prob.set_coarse_precision(16)
+        its[first] = info["iters"]
+        for bad in (0, levels + 1):
+            with pytest.raises(fe.FEError):
+                prob.set_float32_levels(bad)
         prob.close()
-    assert its[32] <= 2 + 1.25 * its[64]
+    for first in range(1, levels):
+        assert its[first] <= 2 + 1.25 * its[levels]
+    # the default is every level below the finest
+    prob = _problem(nx, ny, nz, precond="gmg", mg_levels=levels)
+    u, info = prob.solve(T(rho), rtol=1e-10)
+    assert info["iters"] == its[1]
 
 
 def test_gmg_params_validation():
