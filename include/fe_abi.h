@@ -303,8 +303,10 @@ FE_API void fe_batch_destroy(fe_batch* b);
  * block's design variables z (x fastest, then y, then z) followed by the 24
  * displacements u_C of its coarse element (corner order (0,0,0) (1,0,0)
  * (1,1,0) (0,1,0) (0,0,1) (1,0,1) (1,1,1) (0,1,1), 3 dofs each) divided by
- * s_u; its target is the exact gradient dJ/dz of the block's elements
- * divided by s_g.  The network: nb^3 + 24 inputs, four hidden layers of
+ * max |u_C| of that iteration; its target is the exact gradient dJ/dz of
+ * the block's elements divided by max |dJ/dz| of that iteration.  A
+ * prediction is therefore a gradient up to a positive factor, which the OC
+ * update does not see (its multiplier absorbs it).  The network: nb^3 + 24 inputs, four hidden layers of
  * `width` with ReLU, a linear output of nb^3; parameters per layer W
  * (out x in, row-major) then b (out), all layers in one vector of
  * fe_onsg_num_params(nb, width) values.  Float32 arithmetic; the dense
@@ -325,12 +327,12 @@ FE_API size_t fe_onsg_workspace_size(int32_t nx, int32_t ny, int32_t nz, int32_t
                               int32_t max_samples, int32_t batch);
 
 /* Creates the model in ws (256-byte aligned, >= fe_onsg_workspace_size)
- * with the initial parameters params (float64, rounded to float32), the
- * scales s_u, s_g (> 0) and the stream (hipStream_t, NULL = default).  The
+ * with the initial parameters params (float64, rounded to float32) and the
+ * stream (hipStream_t, NULL = default).  The
  * rocBLAS handle it creates holds memory of its own until
  * fe_onsg_destroy.  FE_EINVAL / FE_ENOMEM on bad arguments. */
 FE_API fe_status fe_onsg_create(int32_t nx, int32_t ny, int32_t nz, int32_t nb, int32_t width,
-                         int32_t max_samples, int32_t batch, double s_u, double s_g, const double* params,
+                         int32_t max_samples, int32_t batch, const double* params,
                          void* ws, size_t ws_bytes, void* stream, fe_onsg** out);
 
 /* Appends the samples of every block of one exact iteration (Alg. 1's
@@ -355,7 +357,7 @@ FE_API fe_status fe_onsg_train(fe_onsg* m, int32_t steps, const int32_t* idx, do
 
 /* Synthetic gradient of every element (float64 g[nelem], device) from the
  * design z and the coarse displacements uc, as laid out above: the
- * network's outputs times s_g. */
+ * network's outputs, in units of the largest gradient of an iteration. */
 FE_API fe_status fe_onsg_predict(fe_onsg* m, const double* z, const double* uc, double* g);
 
 /* The current parameters as float64 (device array of the parameter count). */

@@ -11,9 +11,11 @@ Readings where the paper is silent (each listed in the design doc):
   * a sample is one block of nb^3 fine elements: its input is the block's
     design variables (local order x fastest, then y, then z) followed by the
     24 coarse displacements of its coarse element (local node order of
-    fe_oracle.LOCAL_NODES, 3 dofs each) divided by a fixed scale s_u; its
-    target is the exact gradient dJ/dz of the block's elements divided by a
-    fixed scale s_g;
+    fe_oracle.LOCAL_NODES, 3 dofs each) divided by a scale s_u; its target
+    is the exact gradient dJ/dz of the block's elements divided by a scale
+    s_g (the optimisation loop takes each iteration's max |u_C| and
+    max |dJ/dz|: the OC update is blind to a positive factor on the
+    gradient, its multiplier absorbs it);
   * the network has 4 hidden layers with ReLU and a linear output layer;
     parameters are stored per layer as W (out x in, row-major) then b (out);
   * the loss is the mean of the squared errors over the mini-batch and the

@@ -38,14 +38,33 @@ struct Blocks {
   int nx, ny, nb, cx, cy, nblk, nin, nout;  // fine grid, block size, coarse grid, sizes
 };
 
+// max |x| over n values into *out (one workgroup; the maximum does not
+// depend on the order)
+__global__ void __launch_bounds__(1024) absmax_kernel(int64_t n, const double* __restrict__ x,
+                                                      double* __restrict__ out) {
+  __shared__ double part[1024];
+  double m = 0.0;
+  for (int64_t t = threadIdx.x; t < n; t += 1024) m = fmax(m, fabs(x[t]));
+  part[threadIdx.x] = m;
+  __syncthreads();
+  for (int h = 512; h > 0; h >>= 1) {
+    if ((int)threadIdx.x < h) part[threadIdx.x] = fmax(part[threadIdx.x], part[threadIdx.x + h]);
+    __syncthreads();
+  }
+  if (threadIdx.x == 0) *out = part[0];
+}
+
 // Inputs (and with g, targets) of blocks blk0 .. blk0 + n - 1 into rows of X
 // (and Y): the block's design variables (x fastest, then y, then z), then
-// the 24 coarse displacements of its coarse element over s_u; targets are
-// the block's gradients over s_g (each computed in float64, then rounded).
+// the 24 coarse displacements of its coarse element over *s_u; targets are
+// the block's gradients over *s_g (each computed in float64, then rounded).
+// A zero scale leaves the values unscaled.
 __global__ void __launch_bounds__(TPB) samples_kernel(Blocks bk, int blk0, int n, const double* __restrict__ z,
                                                       const double* __restrict__ uc, const double* __restrict__ g,
-                                                      double s_u, double s_g, float* __restrict__ X,
+                                                      const double* __restrict__ scales, float* __restrict__ X,
                                                       float* __restrict__ Y) {
+  const double s_u = scales[0] > 0.0 ? scales[0] : 1.0;
+  const double s_g = (g && scales[1] > 0.0) ? scales[1] : 1.0;
   const int64_t total = (int64_t)n * bk.nin;
   for (int64_t t = blockIdx.x * (int64_t)TPB + threadIdx.x; t < total; t += (int64_t)gridDim.x * TPB) {
     const int r = (int)(t / bk.nin), f = (int)(t % bk.nin);
@@ -67,7 +86,7 @@ __global__ void __launch_bounds__(TPB) samples_kernel(Blocks bk, int blk0, int n
 
 // g of the fine elements of blocks blk0 .. blk0 + n - 1 from the output rows
 __global__ void __launch_bounds__(TPB) scatter_kernel(Blocks bk, int blk0, int n, const float* __restrict__ out,
-                                                      double s_g, double* __restrict__ g) {
+                                                      double* __restrict__ g) {
   const int64_t total = (int64_t)n * bk.nout;
   for (int64_t t = blockIdx.x * (int64_t)TPB + threadIdx.x; t < total; t += (int64_t)gridDim.x * TPB) {
     const int r = (int)(t / bk.nout), l = (int)(t % bk.nout);
@@ -75,7 +94,7 @@ __global__ void __launch_bounds__(TPB) scatter_kernel(Blocks bk, int blk0, int n
     const int I = blk % bk.cx, J = (blk / bk.cx) % bk.cy, K = blk / (bk.cx * bk.cy);
     const int a = l % bk.nb, b = (l / bk.nb) % bk.nb, c = l / (bk.nb * bk.nb);
     const int64_t e = (bk.nb * I + a) + (int64_t)bk.nx * ((bk.nb * J + b) + (int64_t)bk.ny * (bk.nb * K + c));
-    g[e] = (double)out[t] * s_g;
+    g[e] = (double)out[t];
   }
 }
 
@@ -197,7 +216,7 @@ struct fe_onsg {
   Blocks bk;
   Dims dm;
   int width = 0, batch = 0, max_samples = 0, n_samples = 0;
-  double s_u = 1.0, s_g = 1.0;
+  double* scales = nullptr;    // device: max |u_C| and max |g| of the current call
   hipStream_t stream = nullptr;
   rocblas_handle blas = nullptr;
   float *p = nullptr, *g = nullptr, *m = nullptr, *v = nullptr;  // parameters, gradient, Adam moments
@@ -233,6 +252,7 @@ size_t onsg_layout(const Blocks& bk, const Dims& dm, int max_samples, int batch,
   float* Yb = take((size_t)batch * bk.nout * 4);
   float* dZ = take((size_t)batch * wmax * 4);
   float* dA = take((size_t)batch * wmax * 4);
+  float* sc = take(2 * sizeof(double));
   if (o) {
     o->p = p;
     o->g = g;
@@ -244,6 +264,7 @@ size_t onsg_layout(const Blocks& bk, const Dims& dm, int max_samples, int batch,
     o->Yb = Yb;
     o->dZ = dZ;
     o->dA = dA;
+    o->scales = reinterpret_cast<double*>(sc);
   }
   return al(off);
 }
@@ -317,8 +338,7 @@ extern "C" size_t fe_onsg_workspace_size(int32_t nx, int32_t ny, int32_t nz, int
 }
 
 extern "C" fe_status fe_onsg_create(int32_t nx, int32_t ny, int32_t nz, int32_t nb, int32_t width,
-                                    int32_t max_samples, int32_t batch, double s_u, double s_g,
-                                    const double* params, void* ws, size_t ws_bytes, void* stream_ptr,
+                                    int32_t max_samples, int32_t batch, const double* params, void* ws, size_t ws_bytes, void* stream_ptr,
                                     fe_onsg** out) {
   hipStream_t stream = static_cast<hipStream_t>(stream_ptr);
   if (!out || !params || !ws) {
@@ -329,10 +349,6 @@ extern "C" fe_status fe_onsg_create(int32_t nx, int32_t ny, int32_t nz, int32_t 
   const std::string why = onsg_validate(nx, ny, nz, nb, width, max_samples, batch);
   if (!why.empty()) {
     fe_set_error(why);
-    return FE_EINVAL;
-  }
-  if (!(s_u > 0.0) || !(s_g > 0.0) || !std::isfinite(s_u) || !std::isfinite(s_g)) {
-    fe_set_error("s_u and s_g must be finite and > 0");
     return FE_EINVAL;
   }
   if (reinterpret_cast<uintptr_t>(ws) % kAl) {
@@ -351,8 +367,6 @@ extern "C" fe_status fe_onsg_create(int32_t nx, int32_t ny, int32_t nz, int32_t 
   o->width = width;
   o->batch = batch;
   o->max_samples = max_samples;
-  o->s_u = s_u;
-  o->s_g = s_g;
   o->stream = stream;
   onsg_layout(bk, dm, max_samples, batch, static_cast<char*>(ws), o);
   if (rocblas_create_handle(&o->blas) != rocblas_status_success ||
@@ -382,9 +396,12 @@ extern "C" fe_status fe_onsg_add_samples(fe_onsg* o, const double* z, const doub
     return FE_EINVAL;
   }
   const int64_t r0 = o->n_samples;
+  const int64_t nuc = 3 * (int64_t)(o->bk.cx + 1) * (o->bk.cy + 1) * (o->bk.nblk / (o->bk.cx * o->bk.cy) + 1);
+  const int64_t nel = (int64_t)o->bk.nblk * o->bk.nout;
+  hipLaunchKernelGGL(absmax_kernel, dim3(1), dim3(1024), 0, o->stream, nuc, uc, o->scales);
+  hipLaunchKernelGGL(absmax_kernel, dim3(1), dim3(1024), 0, o->stream, nel, g, o->scales + 1);
   hipLaunchKernelGGL(samples_kernel, dim3(blocks_for((int64_t)o->bk.nblk * o->bk.nin)), dim3(TPB), 0, o->stream,
-                     o->bk, 0, o->bk.nblk, z, uc, g, o->s_u, o->s_g, o->DX + r0 * o->bk.nin,
-                     o->DY + r0 * o->bk.nout);
+                     o->bk, 0, o->bk.nblk, z, uc, g, o->scales, o->DX + r0 * o->bk.nin, o->DY + r0 * o->bk.nout);
   ONSG_HIP(hipGetLastError());
   o->n_samples += o->bk.nblk;
   return FE_OK;
@@ -463,15 +480,17 @@ extern "C" fe_status fe_onsg_predict(fe_onsg* o, const double* z, const double* 
     return FE_EINVAL;
   }
   const int B = o->batch;
+  const int64_t nuc = 3 * (int64_t)(o->bk.cx + 1) * (o->bk.cy + 1) * (o->bk.nblk / (o->bk.cx * o->bk.cy) + 1);
+  hipLaunchKernelGGL(absmax_kernel, dim3(1), dim3(1024), 0, o->stream, nuc, uc, o->scales);
   for (int b0 = 0; b0 < o->bk.nblk; b0 += B) {
     const int n = o->bk.nblk - b0 < B ? o->bk.nblk - b0 : B;
     hipLaunchKernelGGL(samples_kernel, dim3(blocks_for((int64_t)n * o->bk.nin)), dim3(TPB), 0, o->stream, o->bk, b0,
-                       n, z, uc, nullptr, o->s_u, o->s_g, o->A[0], nullptr);
+                       n, z, uc, nullptr, o->scales, o->A[0], nullptr);
     ONSG_HIP(hipGetLastError());
     fe_status s = forward(o, n);
     if (s != FE_OK) return s;
     hipLaunchKernelGGL(scatter_kernel, dim3(blocks_for((int64_t)n * o->bk.nout)), dim3(TPB), 0, o->stream, o->bk,
-                       b0, n, o->A[NL], o->s_g, g);
+                       b0, n, o->A[NL], g);
     ONSG_HIP(hipGetLastError());
   }
   return FE_OK;

@@ -99,7 +99,7 @@ def load_library() -> C.CDLL:
     lib.fe_onsg_num_params.restype = C.c_int64
     lib.fe_onsg_workspace_size.argtypes = [I32] * 7
     lib.fe_onsg_workspace_size.restype = C.c_size_t
-    lib.fe_onsg_create.argtypes = [I32] * 7 + [D, D, P, P, C.c_size_t, P, C.POINTER(P)]
+    lib.fe_onsg_create.argtypes = [I32] * 7 + [P, P, C.c_size_t, P, C.POINTER(P)]
     lib.fe_onsg_add_samples.argtypes = [P, P, P, P]
     lib.fe_onsg_num_samples.argtypes = [P, C.POINTER(I64)]
     lib.fe_onsg_train.argtypes = [P, I32, P, D, I32, P]
@@ -416,10 +416,9 @@ class SyntheticGradientModel:
     """The network of the online synthetic gradients (include/fe_abi.h,
     fe_onsg_*): samples of the blocks of nb^3 elements of an (nx, ny, nz)
     grid, `width`-wide hidden layers, at most max_samples stored samples,
-    mini-batches of `batch` rows, input scale s_u of the coarse
-    displacements and output scale s_g of the gradients."""
+    mini-batches of `batch` rows."""
 
-    def __init__(self, nx, ny, nz, nb, width, max_samples, batch, s_u, s_g, params, *, device="cuda:0",
+    def __init__(self, nx, ny, nz, nb, width, max_samples, batch, params, *, device="cuda:0",
                  stream: torch.cuda.Stream | None = None):
         lib = load_library()
         self.nx, self.ny, self.nz, self.nb, self.batch = nx, ny, nz, nb, batch
@@ -430,7 +429,7 @@ class SyntheticGradientModel:
         self.ws = torch.empty(nbytes, dtype=torch.uint8, device=self.device)
         p = torch.as_tensor(params, dtype=torch.float64).to(self.device).contiguous()
         h = C.c_void_p()
-        _check(lib.fe_onsg_create(nx, ny, nz, nb, width, max_samples, batch, s_u, s_g, _ptr(p),
+        _check(lib.fe_onsg_create(nx, ny, nz, nb, width, max_samples, batch, _ptr(p),
                                   _ptr(self.ws, torch.uint8), nbytes, C.c_void_p(self.stream.cuda_stream), C.byref(h)))
         torch.cuda.synchronize(self.device)  # the initial parameters are read
         self._h = h

@@ -7,7 +7,9 @@ initial parameters and mini-batches.
 Tolerances: the GPU computes in float32, the oracle in float64; the first
 batch loss (forward only) agrees to float32 rounding (1e-5 relative); later
 steps differ by Adam's amplification of rounding in the updates, bounded
-here by 2% of the loss and 2% of the target scale for the predictions."""
+here by 2% of the loss and 2% of the target scale for the predictions.
+Inputs and targets of an iteration are scaled by that iteration's largest
+|u_C| and |dJ/dz|; predictions come in units of the latter."""
 import numpy as np
 import pytest
 import torch
@@ -52,15 +54,15 @@ def test_samples_layout_and_forward_exact(grid, nb):
     rng = np.random.default_rng(1)
     z = rng.uniform(0, 1, nx * ny * nz)
     uc = rng.standard_normal(3 * (cx + 1) * (cy + 1) * (cz + 1))
-    s_u, s_g = 0.37, 2.5
+    s_u = np.abs(uc).max()  # the library scales by the input's own maximum
     X, _ = S.block_samples(nx, ny, nz, nb, z, uc, s_u=s_u)
     Xf = X.astype(np.float32).astype(np.float64)
     nin = nb ** 3 + 24
     for pick in (list(range(nb ** 3)), [nb ** 3 + (k % 24) for k in range(nb ** 3)]):
         sizes, params = _copy_net(nb, pick)
-        m = fe.SyntheticGradientModel(nx, ny, nz, nb, sizes[1], 4, 16, s_u, s_g, params, device=DEV)
+        m = fe.SyntheticGradientModel(nx, ny, nz, nb, sizes[1], 4, 16, params, device=DEV)
         g = N(m.predict(T(z), T(uc)))
-        ref = S.scatter_blocks(nx, ny, nz, nb, Xf[:, pick], s_g=s_g)
+        ref = S.scatter_blocks(nx, ny, nz, nb, Xf[:, pick])
         assert np.array_equal(g, ref), (grid, nb, pick[:3])
         assert np.array_equal(N(m.params()), params.astype(np.float32).astype(np.float64))
         m.close()
@@ -73,15 +75,14 @@ def test_update_matches_oracle():
     sizes = S.layer_sizes(nb, width)
     p0 = synth.mlp_init(sizes, seed=5)
     rng = np.random.default_rng(6)
-    s_u, s_g = 3.0, 0.5
-    m = fe.SyntheticGradientModel(nx, ny, nz, nb, width, 64, batch, s_u, s_g, p0, device=DEV)
+    m = fe.SyntheticGradientModel(nx, ny, nz, nb, width, 64, batch, p0, device=DEV)
     DX, DY = [], []
-    for it in range(2):  # two exact iterations of samples
+    for it in range(2):  # two exact iterations of samples, each scaled by its own maxima
         z = rng.uniform(0, 1, nx * ny * nz)
-        uc = rng.standard_normal(3 * (cx + 1) * (cy + 1) * (cz + 1))
-        g = -np.abs(rng.standard_normal(nx * ny * nz)) * (1.0 + z)
+        uc = rng.standard_normal(3 * (cx + 1) * (cy + 1) * (cz + 1)) * (1 + 4 * it)
+        g = -np.abs(rng.standard_normal(nx * ny * nz)) * (1.0 + z) * (10.0 ** it)
         m.add_samples(T(z), T(uc), T(g))
-        X, Y = S.block_samples(nx, ny, nz, nb, z, uc, g, s_u=s_u, s_g=s_g)
+        X, Y = S.block_samples(nx, ny, nz, nb, z, uc, g, s_u=np.abs(uc).max(), s_g=np.abs(g).max())
         DX.append(X)
         DY.append(Y)
     assert m.num_samples == 2 * cx * cy * cz
@@ -95,9 +96,9 @@ def test_update_matches_oracle():
     assert losses_ref[-10:].mean() < losses_ref[0]
     # predictions of the trained networks on the last iteration's design
     pred = N(m.predict(T(z), T(uc)))
-    acts = S.forward(p_ref, sizes, S.block_samples(nx, ny, nz, nb, z, uc, s_u=s_u)[0])
-    pred_ref = S.scatter_blocks(nx, ny, nz, nb, acts[-1], s_g=s_g)
-    assert np.abs(pred - pred_ref).max() <= 0.02 * s_g * np.abs(DY).max()
+    acts = S.forward(p_ref, sizes, S.block_samples(nx, ny, nz, nb, z, uc, s_u=np.abs(uc).max())[0])
+    pred_ref = S.scatter_blocks(nx, ny, nz, nb, acts[-1])
+    assert np.abs(pred - pred_ref).max() <= 0.02 * np.abs(DY).max()
     m.close()
 
 
@@ -107,7 +108,7 @@ def test_bad_arguments():
     assert lib.fe_onsg_workspace_size(8, 4, 4, 2, 0, 10, 8) == 0       # width
     assert lib.fe_onsg_num_params(2, 16) == S.n_params(S.layer_sizes(2, 16))
     sizes = S.layer_sizes(2, 8)
-    m = fe.SyntheticGradientModel(8, 4, 4, 2, 8, 8, 4, 1.0, 1.0, synth.mlp_init(sizes, 0), device=DEV)
+    m = fe.SyntheticGradientModel(8, 4, 4, 2, 8, 8, 4, synth.mlp_init(sizes, 0), device=DEV)
     z = T(np.full(128, 0.5))
     uc = T(np.zeros(3 * 5 * 3 * 3))
     with pytest.raises(fe.FEError):  # 16 samples per iteration exceed max_samples = 8
