@@ -211,13 +211,16 @@ FE_API fe_status fe_set_mg_params(fe_problem* p, int32_t nu, int32_t coarse_swee
 
 /* Levels first_level .. nlev-1 of the multigrid preconditioner of
  * FE_PREC_FP64 solves run in float32 on their float32 moduli and inverse
- * diagonals (the restriction into first_level sums in float64 and rounds
- * once, the prolongation out of it widens the correction); first_level =
- * nlev keeps the whole hierarchy in float64.  Default 1: every level below
- * the finest in float32.  The CG vectors, products, reductions
- * and the returned residual stay float64 either way; the preconditioner
- * remains a fixed linear map up to float32 rounding.  No effect on float32
- * inner solves.  FE_EINVAL unless 1 <= first_level <= nlev. */
+ * diagonals.  first_level = 0 (default): the whole V-cycle, the finest
+ * level's smoothing included, reads a float32 copy of the residual that the
+ * CG update writes and its result is widened to float64; first_level >= 1:
+ * the restriction into first_level sums in float64 and rounds once, the
+ * prolongation out of it widens the correction; first_level = nlev keeps the
+ * preconditioner in float64.  The CG itself (the operator K p, its vectors,
+ * reductions and the returned residual) stays float64 either way, and the
+ * preconditioner remains a fixed linear map up to float32 rounding.  No
+ * effect on float32 inner solves.  FE_EINVAL unless 0 <= first_level <=
+ * nlev. */
 FE_API fe_status fe_set_float32_levels(fe_problem* p, int32_t first_level);
 
 /* The multigrid parameters in effect (the defaults above or the last

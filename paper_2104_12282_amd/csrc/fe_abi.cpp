@@ -144,7 +144,7 @@ size_t layout(const fe_config* c, fe_problem* p, char* base) {
   double* zpad = (double*)take(8 * sizeof(double));
   if (p) {
     p->nlev = nl;
-    p->f32_from = 1;  // every level below the finest in float32
+    p->f32_from = 0;  // the whole preconditioner in float32
     if (nl > 1) {
       // default coarse Chebyshev for the coarsest grid's longest dimension
       // n: the number of steps a Chebyshev solve needs grows like the square
@@ -275,14 +275,25 @@ hipError_t cg_iteration(fe_problem* p, T* x, T* r, T* pv, T* q, int it) {
     fz.xin = 2;
     fz.pold = pold;
     fz.xout = pnew;
+    // a float64 solve whose preconditioner runs the finest level in float32
+    // too: its V-cycle reads a float32 copy of r and leaves z in float32,
+    // widened for the direction kernel
+    const bool f32_l0 = std::is_same<T, double>::value && p->f32_from == 0;
     fz.fold = part_region(p, PART_RZ);
-    fz.nfold = kxu_rz_partials<T>(p, 0);
+    fz.nfold = f32_l0 ? kxu_rz_partials<float>(p, 0) : kxu_rz_partials<T>(p, 0);
     fz.part = part_region(p, PART_PQ);
     fz.no_finalize = true;
     fz.nblocks = &npq;
     if ((e = launch_kxu_tile<T>(p, 0, z, fine_E<T>(p), q, p->st, 1, nullptr, nullptr, nullptr, nullptr, 0.0,
                                 nullptr, &fz)) != hipSuccess)
       return e;
+    if (f32_l0) {
+      float* r32 = static_cast<float*>(p->L[0].mg_r);
+      float* z32 = static_cast<float*>(p->L[0].mg_w);
+      if ((e = launch_cg_update_mg<T>(p, x, r, pnew, q, p->st, npq, &nrr, r32)) != hipSuccess) return e;
+      if ((e = launch_vcycle<float>(p, 0, r32, z32, p->st, RZ_PARTIALS, nrr)) != hipSuccess) return e;
+      return launch_widen(p, z32, reinterpret_cast<double*>(z), p->st);
+    }
     if ((e = launch_cg_update_mg<T>(p, x, r, pnew, q, p->st, npq, &nrr)) != hipSuccess) return e;
     return launch_vcycle<T>(p, 0, r, z, p->st, RZ_PARTIALS, nrr);
   }
@@ -389,6 +400,13 @@ hipError_t enqueue_start(fe_problem* p, const T* b, const T* Kx, T* r, T* pv) {
   if (e != hipSuccess || !mg) return e;
   T* z = static_cast<T*>(p->L[0].mg_z);
   // folded: the first direction kernel forms p = z from the r^T z partials
+  if (folded_mg(p) && std::is_same<T, double>::value && p->f32_from == 0) {
+    float* r32 = static_cast<float*>(p->L[0].mg_r);
+    float* z32 = static_cast<float*>(p->L[0].mg_w);
+    if ((e = launch_narrow(p, reinterpret_cast<const double*>(r), r32)) != hipSuccess) return e;
+    if ((e = launch_vcycle<float>(p, 0, r32, z32, p->st, RZ_PARTIALS, 0)) != hipSuccess) return e;
+    return launch_widen(p, z32, reinterpret_cast<double*>(z), p->st);
+  }
   if (folded_mg(p)) return launch_vcycle<T>(p, 0, r, z, p->st, RZ_PARTIALS, 0);
   if ((e = launch_fill<T>(p, pv, p->L[0].g.ndof, T(0))) != hipSuccess) return e;
   if ((e = launch_vcycle<T>(p, 0, r, z, p->st, RZ_FINISH)) != hipSuccess) return e;
@@ -1017,8 +1035,8 @@ extern "C" fe_status fe_set_float32_levels(fe_problem* p, int32_t first_level) {
     fe_set_error("batch slots share the batch's multigrid parameters (the library defaults)");
     return FE_EINVAL;
   }
-  if (first_level < 1 || first_level > p->nlev) {
-    fe_set_error("first_level must lie in [1, number of levels]");
+  if (first_level < 0 || first_level > p->nlev) {
+    fe_set_error("first_level must lie in [0, number of levels]");
     return FE_EINVAL;
   }
   p->f32_from = first_level;

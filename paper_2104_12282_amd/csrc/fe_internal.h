@@ -318,9 +318,13 @@ hipError_t launch_cg_direction(fe_problem* p, const T* r, const T* z, T* pvec, C
 // Multigrid CG update: alpha = rz_new / p^T q from the npq partials in PART_PQ
 // (summed by every workgroup), x += alpha p, r -= alpha q, r^T r partials to
 // PART_RR; returns their count in *nrr.
+// With r32 given, the updated residual is also written there in float32.
 template <typename T>
 hipError_t launch_cg_update_mg(fe_problem* p, T* x, T* r, const T* pvec, const T* q, CgState* st, int npq,
-                               int* nrr);
+                               int* nrr, float* r32 = nullptr);
+// b = (double)a over the finest grid's dofs (skipped once CG stopped), and the converse
+hipError_t launch_widen(fe_problem* p, const float* a, double* b, CgState* st);
+hipError_t launch_narrow(fe_problem* p, const double* a, float* b);
 
 hipError_t launch_cg_state_init(fe_problem* p, CgState* st, double tol_rel, int max_iter);
 // One-workgroup scalar update after a kernel that left nb partials:

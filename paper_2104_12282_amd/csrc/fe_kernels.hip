@@ -229,7 +229,8 @@ __global__ void __launch_bounds__(FE_BLOCK) cg_update_mg_kernel(Grid g, T* __res
                                                                 const T* __restrict__ p,
                                                                 const T* __restrict__ q, CgState* st,
                                                                 const double* __restrict__ pq_part, int npq,
-                                                                double* partials, int64_t wsh) {
+                                                                double* partials, int64_t wsh,
+                                                                float* __restrict__ r32) {
   if (wsh) {  // batched launch: this workgroup's problem
     const int64_t o = batch_offset(wsh);
     x = wshift(x, o);
@@ -239,6 +240,7 @@ __global__ void __launch_bounds__(FE_BLOCK) cg_update_mg_kernel(Grid g, T* __res
     st = wshift(st, o);
     pq_part = wshift(pq_part, o);
     partials = wshift(partials, o);
+    r32 = wshift(r32, o);
   }
   if (st->done) return;
   __shared__ double sh[FE_BLOCK / 64];
@@ -275,9 +277,36 @@ __global__ void __launch_bounds__(FE_BLOCK) cg_update_mg_kernel(Grid g, T* __res
     x[d] += alpha * p[d];
     const T rv = r[d] - alpha * q[d];
     r[d] = rv;
+    if (r32) r32[d] = (float)rv;  // the residual a float32 preconditioner reads
     acc[0] += (double)rv * (double)rv;
   }
   block_partials<1>(acc, partials);
+}
+
+// b = (double)a, skipped once CG has stopped (st may be null)
+__global__ void __launch_bounds__(FE_BLOCK) widen_kernel(int64_t n, const float* __restrict__ a,
+                                                         double* __restrict__ b, const CgState* st, int64_t wsh) {
+  if (wsh) {
+    const int64_t o = batch_offset(wsh);
+    a = wshift(a, o);
+    b = wshift(b, o);
+    st = wshift(st, o);
+  }
+  if (st && st->done) return;
+  for (int64_t d = blockIdx.x * (int64_t)FE_BLOCK + threadIdx.x; d < n; d += (int64_t)gridDim.x * FE_BLOCK)
+    b[d] = (double)a[d];
+}
+
+// b = (float)a
+__global__ void __launch_bounds__(FE_BLOCK) narrow_kernel(int64_t n, const double* __restrict__ a,
+                                                          float* __restrict__ b, int64_t wsh) {
+  if (wsh) {
+    const int64_t o = batch_offset(wsh);
+    a = wshift(a, o);
+    b = wshift(b, o);
+  }
+  for (int64_t d = blockIdx.x * (int64_t)FE_BLOCK + threadIdx.x; d < n; d += (int64_t)gridDim.x * FE_BLOCK)
+    b[d] = (float)a[d];
 }
 
 // Scalar updates of CG, one workgroup, after the kernel that left nb partials.
@@ -998,20 +1027,34 @@ constexpr int kUpdateMgGrid = 1024;
 
 template <typename T>
 hipError_t launch_cg_update_mg(fe_problem* p, T* x, T* r, const T* pvec, const T* q, CgState* st, int npq,
-                               int* nrr) {
+                               int* nrr, float* r32) {
   const Grid g = G(p, 0);
   int nb = red_grid(g.ndof);
   if (nb > kUpdateMgGrid) nb = kUpdateMgGrid;
   hipLaunchKernelGGL(cg_update_mg_kernel<T>, dim3(nb, p->bcount), dim3(FE_BLOCK), 0, p->stream, g, x, r, pvec, q,
                      st, part_region(p, PART_PQ), npq, part_region(p, PART_RR),
-                     p->bcount > 1 ? p->bstride : (int64_t)0);
+                     p->bcount > 1 ? p->bstride : (int64_t)0, r32);
   *nrr = nb;
   return hipGetLastError();
 }
 template hipError_t launch_cg_update_mg<double>(fe_problem*, double*, double*, const double*, const double*,
-                                                CgState*, int, int*);
+                                                CgState*, int, int*, float*);
 template hipError_t launch_cg_update_mg<float>(fe_problem*, float*, float*, const float*, const float*,
-                                               CgState*, int, int*);
+                                               CgState*, int, int*, float*);
+
+hipError_t launch_widen(fe_problem* p, const float* a, double* b, CgState* st) {
+  const int64_t n = G(p, 0).ndof;
+  hipLaunchKernelGGL(widen_kernel, dim3(red_grid(n) * 2, p->bcount), dim3(FE_BLOCK), 0, p->stream, n, a, b, st,
+                     p->bcount > 1 ? p->bstride : (int64_t)0);
+  return hipGetLastError();
+}
+
+hipError_t launch_narrow(fe_problem* p, const double* a, float* b) {
+  const int64_t n = G(p, 0).ndof;
+  hipLaunchKernelGGL(narrow_kernel, dim3(red_grid(n) * 2, p->bcount), dim3(FE_BLOCK), 0, p->stream, n, a, b,
+                     p->bcount > 1 ? p->bstride : (int64_t)0);
+  return hipGetLastError();
+}
 
 template <typename T>
 hipError_t launch_cg_direction(fe_problem* p, const T* r, const T* z, T* pvec, CgState* st) {

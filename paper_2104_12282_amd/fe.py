@@ -328,7 +328,8 @@ class Problem:
 
     def set_float32_levels(self, first_level):
         """Multigrid levels >= first_level of float64 solves in float32
-        (first_level = number of levels: none)."""
+        (0: the whole preconditioner, the default; the number of levels:
+        none)."""
         _check(load_library().fe_set_float32_levels(self._h, first_level))
 
     def set_coarse_fusion(self, steps_per_launch=2):

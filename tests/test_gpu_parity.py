@@ -299,7 +299,8 @@ def test_paper_domain_step_parity(Ke, precond):
 @pytest.mark.parametrize("grid,levels", [((24, 12, 12), 3), ((32, 16, 16), 3), ((20, 10, 6), 2)])
 def test_float32_levels_in_float64_solves(Ke, grid, levels):
     """Float64 solves with their multigrid levels from k on in float32 (k =
-    1 is the default; k = levels keeps float64) reach the oracle's
+    0, the default, includes the finest level's smoothing; k = levels keeps
+    float64) reach the oracle's
     answer to the contract's tolerances; float32 rounding in the
     preconditioner costs some iterations near a tight tolerance (1e-10 here:
     up to a quarter more); levels outside [1, levels] are rejected."""
@@ -311,7 +312,7 @@ def test_float32_levels_in_float64_solves(Ke, grid, levels):
     c_ref = O.compliance(f, u_ref)
     dc_ref = O.sensitivity(nx, ny, nz, Ke, rho, u_ref)
     its = {}
-    for first in range(1, levels + 1):
+    for first in range(0, levels + 1):
         prob = _problem(nx, ny, nz, precond="gmg", mg_levels=levels)
         prob.set_float32_levels(first)
         u, info = prob.solve(T(rho), rtol=1e-10)
@@ -320,16 +321,16 @@ def test_float32_levels_in_float64_solves(Ke, grid, levels):
         dc, _ = prob.sensitivity(T(rho), u)
         assert np.abs(N(dc) - dc_ref).max() <= 1e-5 * np.abs(dc_ref).max()
         its[first] = info["iters"]
-        for bad in (0, levels + 1):
+        for bad in (-1, levels + 1):
             with pytest.raises(fe.FEError):
                 prob.set_float32_levels(bad)
         prob.close()
-    for first in range(1, levels):
+    for first in range(0, levels):
         assert its[first] <= 2 + 1.25 * its[levels]
-    # the default is every level below the finest
+    # the default is the whole preconditioner in float32
     prob = _problem(nx, ny, nz, precond="gmg", mg_levels=levels)
     u, info = prob.solve(T(rho), rtol=1e-10)
-    assert info["iters"] == its[1]
+    assert info["iters"] == its[0]
 
 
 def test_gmg_params_validation():
