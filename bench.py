@@ -71,6 +71,15 @@ def parse():
     return ap.parse_args()
 
 
+# Fused-operand form of the CG-product launch: 3 when a float64 solve's
+# preconditioner leaves z in float32 (the default), else 2; set by main().
+PRODUCT_XIN = {"fp64": 3}
+
+
+def product_xin(precision: str) -> int:
+    return PRODUCT_XIN.get(precision, 2)
+
+
 def traffic_from_profiles(precision: str, grid: str, field: str = "bytes"):
     """HBM bytes (fetched + written) of one CG-product launch of the tiled K*u
     kernel on this grid, from rocprofv3 FETCH_SIZE / WRITE_SIZE counters scaled
@@ -85,7 +94,7 @@ def traffic_from_profiles(precision: str, grid: str, field: str = "bytes"):
         from paper_2104_12282_amd.build import source_digest
         if rec.get("source_digest") != source_digest():
             return None
-        want = f"kxu_tile_kernel<{'double' if precision == 'fp64' else 'float'}, 1, 2>"
+        want = f"kxu_tile_kernel<{'double' if precision == 'fp64' else 'float'}, 1, {product_xin(precision)}>"
         for name, k in rec["kernels"].items():
             if want in name:
                 return k["fetch_bytes"] + k["write_bytes"] if field == "bytes" else k.get(field)
@@ -711,6 +720,7 @@ def main():
 
     nx, ny, nz = (int(v) for v in args.grid.split("x"))
     ne = nx * ny * nz
+    PRODUCT_XIN["fp64"] = 3 if args.precond == "gmg" and args.f32_from <= 0 else 2
     torch.cuda.set_device(0)
     probe = None
     if args.copy_probe:
@@ -761,8 +771,9 @@ def main():
                      "traffic": traffic_from_profiles(args.precision, f"{nx}x{ny}x{nz}"),
                      "traffic_of": "one CG-product launch (rocprofv3 counters, copy-scaled)",
                      "kernel": "kxu_tile_kernel<" + ("double" if args.precision == "fp64" else "float")
-                               + ", 1, 2>: CG product on the finest grid (direction p = z + beta p fused "
-                               "into the matrix-free K*u, p^T K p partials)",
+                               + f", 1, {product_xin(args.precision)}>: CG product on the finest grid "
+                               "(direction p = z + beta p fused into the matrix-free K*u, p^T K p partials"
+                               + ("; z read in float32" if product_xin(args.precision) == 3 else "") + ")",
                      "launches": ks["launches"], "avg_launch_us": avg_ms * 1e3,
                      "rocprofv3_avg_kernel_us": traffic_from_profiles(args.precision, f"{nx}x{ny}x{nz}",
                                                                       "trace_work_avg_us"),

@@ -277,22 +277,22 @@ hipError_t cg_iteration(fe_problem* p, T* x, T* r, T* pv, T* q, int it) {
     fz.xout = pnew;
     // a float64 solve whose preconditioner runs the finest level in float32
     // too: its V-cycle reads a float32 copy of r and leaves z in float32,
-    // widened for the direction kernel
+    // which the direction kernel reads as such
     const bool f32_l0 = std::is_same<T, double>::value && p->f32_from == 0;
+    float* z32 = static_cast<float*>(p->L[0].mg_w);
+    if (f32_l0) fz.xin = 3;
     fz.fold = part_region(p, PART_RZ);
     fz.nfold = f32_l0 ? kxu_rz_partials<float>(p, 0) : kxu_rz_partials<T>(p, 0);
     fz.part = part_region(p, PART_PQ);
     fz.no_finalize = true;
     fz.nblocks = &npq;
-    if ((e = launch_kxu_tile<T>(p, 0, z, fine_E<T>(p), q, p->st, 1, nullptr, nullptr, nullptr, nullptr, 0.0,
-                                nullptr, &fz)) != hipSuccess)
+    if ((e = launch_kxu_tile<T>(p, 0, f32_l0 ? reinterpret_cast<const T*>(z32) : z, fine_E<T>(p), q, p->st, 1,
+                                nullptr, nullptr, nullptr, nullptr, 0.0, nullptr, &fz)) != hipSuccess)
       return e;
     if (f32_l0) {
       float* r32 = static_cast<float*>(p->L[0].mg_r);
-      float* z32 = static_cast<float*>(p->L[0].mg_w);
       if ((e = launch_cg_update_mg<T>(p, x, r, pnew, q, p->st, npq, &nrr, r32)) != hipSuccess) return e;
-      if ((e = launch_vcycle<float>(p, 0, r32, z32, p->st, RZ_PARTIALS, nrr)) != hipSuccess) return e;
-      return launch_widen(p, z32, reinterpret_cast<double*>(z), p->st);
+      return launch_vcycle<float>(p, 0, r32, z32, p->st, RZ_PARTIALS, nrr);
     }
     if ((e = launch_cg_update_mg<T>(p, x, r, pnew, q, p->st, npq, &nrr)) != hipSuccess) return e;
     return launch_vcycle<T>(p, 0, r, z, p->st, RZ_PARTIALS, nrr);
@@ -404,8 +404,7 @@ hipError_t enqueue_start(fe_problem* p, const T* b, const T* Kx, T* r, T* pv) {
     float* r32 = static_cast<float*>(p->L[0].mg_r);
     float* z32 = static_cast<float*>(p->L[0].mg_w);
     if ((e = launch_narrow(p, reinterpret_cast<const double*>(r), r32)) != hipSuccess) return e;
-    if ((e = launch_vcycle<float>(p, 0, r32, z32, p->st, RZ_PARTIALS, 0)) != hipSuccess) return e;
-    return launch_widen(p, z32, reinterpret_cast<double*>(z), p->st);
+    return launch_vcycle<float>(p, 0, r32, z32, p->st, RZ_PARTIALS, 0);
   }
   if (folded_mg(p)) return launch_vcycle<T>(p, 0, r, z, p->st, RZ_PARTIALS, 0);
   if ((e = launch_fill<T>(p, pv, p->L[0].g.ndof, T(0))) != hipSuccess) return e;

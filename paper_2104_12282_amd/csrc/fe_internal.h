@@ -322,8 +322,7 @@ hipError_t launch_cg_direction(fe_problem* p, const T* r, const T* z, T* pvec, C
 template <typename T>
 hipError_t launch_cg_update_mg(fe_problem* p, T* x, T* r, const T* pvec, const T* q, CgState* st, int npq,
                                int* nrr, float* r32 = nullptr);
-// b = (double)a over the finest grid's dofs (skipped once CG stopped), and the converse
-hipError_t launch_widen(fe_problem* p, const float* a, double* b, CgState* st);
+// b = (float)a over the finest grid's dofs
 hipError_t launch_narrow(fe_problem* p, const double* a, float* b);
 
 hipError_t launch_cg_state_init(fe_problem* p, CgState* st, double tol_rel, int max_iter);

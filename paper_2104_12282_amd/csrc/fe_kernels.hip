@@ -283,20 +283,6 @@ __global__ void __launch_bounds__(FE_BLOCK) cg_update_mg_kernel(Grid g, T* __res
   block_partials<1>(acc, partials);
 }
 
-// b = (double)a, skipped once CG has stopped (st may be null)
-__global__ void __launch_bounds__(FE_BLOCK) widen_kernel(int64_t n, const float* __restrict__ a,
-                                                         double* __restrict__ b, const CgState* st, int64_t wsh) {
-  if (wsh) {
-    const int64_t o = batch_offset(wsh);
-    a = wshift(a, o);
-    b = wshift(b, o);
-    st = wshift(st, o);
-  }
-  if (st && st->done) return;
-  for (int64_t d = blockIdx.x * (int64_t)FE_BLOCK + threadIdx.x; d < n; d += (int64_t)gridDim.x * FE_BLOCK)
-    b[d] = (double)a[d];
-}
-
 // b = (float)a
 __global__ void __launch_bounds__(FE_BLOCK) narrow_kernel(int64_t n, const double* __restrict__ a,
                                                           float* __restrict__ b, int64_t wsh) {
@@ -1041,13 +1027,6 @@ template hipError_t launch_cg_update_mg<double>(fe_problem*, double*, double*, c
                                                 CgState*, int, int*, float*);
 template hipError_t launch_cg_update_mg<float>(fe_problem*, float*, float*, const float*, const float*,
                                                CgState*, int, int*, float*);
-
-hipError_t launch_widen(fe_problem* p, const float* a, double* b, CgState* st) {
-  const int64_t n = G(p, 0).ndof;
-  hipLaunchKernelGGL(widen_kernel, dim3(red_grid(n) * 2, p->bcount), dim3(FE_BLOCK), 0, p->stream, n, a, b, st,
-                     p->bcount > 1 ? p->bstride : (int64_t)0);
-  return hipGetLastError();
-}
 
 hipError_t launch_narrow(fe_problem* p, const double* a, float* b) {
   const int64_t n = G(p, 0).ndof;

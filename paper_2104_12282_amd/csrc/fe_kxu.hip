@@ -397,12 +397,15 @@ __global__ void __launch_bounds__(TX* TY, FE_KXU_MIN_WAVES) kxu_tile_kernel(Grid
   // loaded: [nlo, nhi]; brick layers: [elo, ehi].
   const int nlo = max(K0 - 1, 0), nhi = min(kend, g.nz), elo = max(K0 - 1, 0), ehi = min(kend - 1, g.nz - 1);
   const int64_t nlev = nhi - nlo + 1, nel = (int64_t)g.nx * g.ny;
+  // XIN 3: the operand x (the preconditioned residual) is float32
+  constexpr int64_t xsz = XIN == 3 ? 4 : (int64_t)sizeof(T);
   const int64_t vbytes = 3 * sxy * nlev * (int64_t)sizeof(T);
-  const __amdgpu_buffer_rsrc_t rx = load_range(x + 3 * sxy * nlo, vbytes);
+  const __amdgpu_buffer_rsrc_t rx =
+      load_range(reinterpret_cast<const char*>(x) + 3 * sxy * nlo * xsz, 3 * sxy * nlev * xsz);
   const __amdgpu_buffer_rsrc_t rxd =
       load_range(XIN == 1 ? (const void*)(xi.invd + sxy * nlo) : (const void*)x, XIN == 1 ? vbytes / 3 : 0);
   const __amdgpu_buffer_rsrc_t rxp =
-      load_range(XIN == 2 ? (const void*)(xi.pold + 3 * sxy * nlo) : (const void*)x, XIN == 2 ? vbytes : 0);
+      load_range(XIN >= 2 ? (const void*)(xi.pold + 3 * sxy * nlo) : (const void*)x, XIN >= 2 ? vbytes : 0);
   const __amdgpu_buffer_rsrc_t re =
       load_range(E + nel * elo, ehi >= elo ? nel * (ehi - elo + 1) * (int64_t)sizeof(T) : 0);
   const uint32_t o_own = off_part(ni >= 0 && ni <= g.nx && nj >= 0 && nj <= g.ny, ni + sx * nj);
@@ -416,9 +419,16 @@ __global__ void __launch_bounds__(TX* TY, FE_KXU_MIN_WAVES) kxu_tile_kernel(Grid
     T p_own[3], p_halo[3];  // XIN 2: previous direction
   };
   auto node_in = [&](uint32_t o, T (&v)[3], T& d, T (&pv)[3]) {
-    load3(rx, o * (uint32_t)(3 * sizeof(T)), v);
+    if constexpr (XIN == 3) {
+      float vf[3];
+      load3(rx, o * 12u, vf);
+#pragma unroll
+      for (int c = 0; c < 3; ++c) v[c] = (T)vf[c];
+    } else {
+      load3(rx, o * (uint32_t)(3 * sizeof(T)), v);
+    }
     if (XIN == 1) d = load1(rxd, o * (uint32_t)sizeof(T), T());
-    if (XIN == 2) load3(rxp, o * (uint32_t)(3 * sizeof(T)), pv);  // also on the first iteration (then unused)
+    if (XIN >= 2) load3(rxp, o * (uint32_t)(3 * sizeof(T)), pv);  // also on the first iteration (then unused)
   };
   auto load_level = [&](int k, LevelIn& L) {
     const uint32_t lk = lev_part(k, nlo, (int)nlev, sxy);  // k <= kend: nhi bounds it
@@ -429,7 +439,7 @@ __global__ void __launch_bounds__(TX* TY, FE_KXU_MIN_WAVES) kxu_tile_kernel(Grid
   // the operand value of a node from what was loaded for it
   auto operand = [&](const T (&v)[3], T d, const T (&pv)[3], int c) -> T {
     if (XIN == 1) return xi.s * d * v[c];
-    if (XIN == 2) return first_dir ? v[c] : v[c] + beta * pv[c];  // p_old is not set before the first
+    if (XIN >= 2) return first_dir ? v[c] : v[c] + beta * pv[c];  // p_old is not set before the first
     return v[c];
   };
   // stores a level into LDS; the loaded registers die here (this thread's
@@ -1404,7 +1414,8 @@ hipError_t launch_kxu_tile(fe_problem* p, int lev, const T* x, const T* E, T* y,
     if (mode == 3 || mode == 5 || mode == 6) bytes += vb * (double)g.nnode;
     if (mode == 6) bytes += vb * 3.0 * (double)g.ndof;  // res in/out, acc in/out (res read counted above)
     if (fz && fz->xin == 1) bytes += vb * (double)g.nnode;  // inverse diagonal of the fused first sweep
-    if (fz && fz->xin == 2) bytes += vb * (double)g.ndof;   // previous direction
+    if (fz && fz->xin >= 2) bytes += vb * (double)g.ndof;   // previous direction
+    if (fz && fz->xin == 3) bytes -= (vb - 4.0) * (double)g.ndof;  // the operand read in float32
     if (fz && fz->xin && fz->xout) bytes += vb * (double)g.ndof;  // the operand, stored
     slot = kstats_begin(p, bytes);
   }
@@ -1445,6 +1456,10 @@ hipError_t launch_kxu_tile(fe_problem* p, int lev, const T* x, const T* E, T* y,
     switch (mode * 4 + xin) {
       case 1 * 4: nb = FE_TILE(1, 0); break;
       case 1 * 4 + 2: nb = FE_TILE(1, 2); break;
+      case 1 * 4 + 3:
+        if (!std::is_same<T, double>::value) return hipErrorInvalidValue;
+        nb = FE_TILE(1, 3);
+        break;
       case 2 * 4: nb = FE_TILE(2, 0); break;
       case 3 * 4: nb = FE_TILE(3, 0); break;
       case 3 * 4 + 1: nb = FE_TILE(3, 1); break;

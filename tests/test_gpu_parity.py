@@ -504,12 +504,20 @@ def test_profiling_selector():
     # one CG-product launch per iteration, plus the unused tail of the last chunk
     assert info["iters"] <= ks["launches"] <= info["iters"] + 8
     nd, ne = prob.ndof, nx * ny * nz
-    # z and the previous direction read, q and the new direction written, E read
-    assert ks["bytes_per_launch"] == pytest.approx(8.0 * (4 * nd + ne), rel=1e-12)
+    # z read (float32: the preconditioner's result), the previous direction
+    # read, q and the new direction written, E read
+    assert ks["bytes_per_launch"] == pytest.approx(8.0 * (3 * nd + ne) + 4.0 * nd, rel=1e-12)
     prob.set_profiling(True)
     prob.solve(rho, rtol=1e-8)
     prob.set_profiling(False)
     assert prob.kernel_stats()["launches"] > ks["launches"]
+    # with the preconditioner in float64, z is read in float64
+    prob.kernel_stats(reset=True)
+    prob.set_float32_levels(3)
+    prob.set_profiling(True, mode=1)
+    prob.solve(rho, rtol=1e-8)
+    prob.set_profiling(False)
+    assert prob.kernel_stats()["bytes_per_launch"] == pytest.approx(8.0 * (4 * nd + ne), rel=1e-12)
 
 
 @pytest.mark.parametrize("deg", [1, 2, 3, 8])
