@@ -213,7 +213,8 @@ FE_API fe_status fe_set_mg_params(fe_problem* p, int32_t nu, int32_t coarse_swee
  * FE_PREC_FP64 solves run in float32 on their float32 moduli and inverse
  * diagonals.  first_level = 0 (default): the whole V-cycle, the finest
  * level's smoothing included, reads a float32 copy of the residual that the
- * CG update writes and its result is widened to float64; first_level >= 1:
+ * CG update writes, and the CG direction kernel reads its float32 result
+ * directly; first_level >= 1:
  * the restriction into first_level sums in float64 and rounds once, the
  * prolongation out of it widens the correction; first_level = nlev keeps the
  * preconditioner in float64.  The CG itself (the operator K p, its vectors,
