@@ -121,34 +121,65 @@ __global__ void __launch_bounds__(TPB) bias_act_kernel(int out, int B, const flo
 }
 
 // dZ = 2 (P - Y) / (B out); the batch's loss mean((P - Y)^2) is summed in a
-// fixed order by the single workgroup this kernel runs as.
-__global__ void __launch_bounds__(TPB) mse_kernel(int n, const float* __restrict__ P, const float* __restrict__ Y,
-                                                  float* __restrict__ dZ, float* __restrict__ loss) {
-  __shared__ double part[TPB];
+// fixed order by the single workgroup this kernel runs as (1024 threads,
+// four independent loads in flight per thread).
+__global__ void __launch_bounds__(1024) mse_kernel(int n, const float* __restrict__ P, const float* __restrict__ Y,
+                                                   float* __restrict__ dZ, float* __restrict__ loss) {
+  __shared__ double part[1024];
   double s = 0.0;
   const float sc = 2.0f / (float)n;
-  for (int t = threadIdx.x; t < n; t += TPB) {
+  int t = threadIdx.x;
+  for (; t + 3 * 1024 < n; t += 4 * 1024) {
+    float d[4];
+#pragma unroll
+    for (int k = 0; k < 4; ++k) d[k] = P[t + k * 1024] - Y[t + k * 1024];
+#pragma unroll
+    for (int k = 0; k < 4; ++k) {
+      dZ[t + k * 1024] = sc * d[k];
+      s += (double)d[k] * (double)d[k];
+    }
+  }
+  for (; t < n; t += 1024) {
     const float d = P[t] - Y[t];
     dZ[t] = sc * d;
     s += (double)d * (double)d;
   }
   part[threadIdx.x] = s;
   __syncthreads();
-  for (int h = TPB / 2; h > 0; h >>= 1) {
+  for (int h = 512; h > 0; h >>= 1) {
     if ((int)threadIdx.x < h) part[threadIdx.x] += part[threadIdx.x + h];
     __syncthreads();
   }
   if (threadIdx.x == 0 && loss) *loss = (float)(part[0] / n);
 }
 
-// db[o] = sum over the batch of dZ[o, b], b in order
-__global__ void __launch_bounds__(TPB) bias_grad_kernel(int out, int B, const float* __restrict__ dZ,
+// db[o] = sum over the batch of dZ[o, b]: a workgroup takes 16 outputs, its
+// 16 slices of threads each sum every 16th sample (b = q, q + 16, ...), and
+// the slices are added in q order (a fixed order throughout)
+__global__ void __launch_bounds__(256) bias_grad_kernel(int out, int B, const float* __restrict__ dZ,
                                                         float* __restrict__ db) {
-  const int o = blockIdx.x * TPB + threadIdx.x;
-  if (o >= out) return;
+  __shared__ float part[16][16];
+  const int ol = threadIdx.x % 16, q = threadIdx.x / 16;
+  const int o = blockIdx.x * 16 + ol;
   float s = 0.0f;
-  for (int b = 0; b < B; ++b) s += dZ[(int64_t)b * out + o];
-  db[o] = s;
+  if (o < out) {
+    int b = q;
+    for (; b + 3 * 16 < B; b += 4 * 16) {
+      float v[4];
+#pragma unroll
+      for (int k = 0; k < 4; ++k) v[k] = dZ[(int64_t)(b + 16 * k) * out + o];
+#pragma unroll
+      for (int k = 0; k < 4; ++k) s += v[k];
+    }
+    for (; b < B; b += 16) s += dZ[(int64_t)b * out + o];
+  }
+  part[q][ol] = s;
+  __syncthreads();
+  if (q == 0 && o < out) {
+    float t = 0.0f;
+    for (int k = 0; k < 16; ++k) t += part[k][ol];
+    db[o] = t;
+  }
 }
 
 // dZ = dA where the layer's output was positive, else 0
@@ -442,7 +473,7 @@ extern "C" fe_status fe_onsg_train(fe_onsg* o, int32_t steps, const int32_t* idx
     ONSG_HIP(hipGetLastError());
     fe_status s = forward(o, B);
     if (s != FE_OK) return s;
-    hipLaunchKernelGGL(mse_kernel, dim3(1), dim3(TPB), 0, o->stream, B * nout, o->A[NL], o->Yb, o->dZ,
+    hipLaunchKernelGGL(mse_kernel, dim3(1), dim3(1024), 0, o->stream, B * nout, o->A[NL], o->Yb, o->dZ,
                        losses ? losses + (t - 1) : nullptr);
     ONSG_HIP(hipGetLastError());
     for (int l = NL - 1; l >= 0; --l) {
@@ -450,7 +481,7 @@ extern "C" fe_status fe_onsg_train(fe_onsg* o, int32_t steps, const int32_t* idx
       // weight gradient (column-major in x out) = A_l dZ^T, bias gradient = row sums of dZ
       ONSG_BLAS(rocblas_sgemm(o->blas, rocblas_operation_none, rocblas_operation_transpose, in, out, B, &one,
                               o->A[l], in, o->dZ, out, &zero, o->g + o->dm.wofs[l], in));
-      hipLaunchKernelGGL(bias_grad_kernel, dim3((out + TPB - 1) / TPB), dim3(TPB), 0, o->stream, out, B, o->dZ,
+      hipLaunchKernelGGL(bias_grad_kernel, dim3((out + 15) / 16), dim3(256), 0, o->stream, out, B, o->dZ,
                          o->g + o->dm.bofs[l]);
       ONSG_HIP(hipGetLastError());
       if (l > 0) {
