@@ -2,6 +2,10 @@
 profiles/.
 
   python -m paper_2104_12282_amd.profile_summary stats <kernel_stats.csv> <out.md> "<command>"
+
+`stats` lists the kernels with the largest total time and, from the kernel
+trace next to the statistics file, how much of the traced span the GPU was
+busy and how long it sat between kernels.
   python -m paper_2104_12282_amd.profile_summary traffic <fetch_dir> <write_dir> <bench.json> <out.json> "<commands>" [<kernel_stats.csv>]
 
 `traffic` reads two counter runs (FETCH_SIZE, then WRITE_SIZE, in KiB per
@@ -42,8 +46,34 @@ def stats(csv_path, out_path, command):
         lines.append(f"| `{name}` | {r['Calls']} | {float(r['TotalDurationNs']) / 1e6:.3f} | "
                      f"{float(r['AverageNs']) / 1e3:.2f} | {float(r['MinNs']) / 1e3:.2f} | "
                      f"{float(r['MaxNs']) / 1e3:.2f} | {100 * float(r['TotalDurationNs']) / total:.1f} |")
+    lines += _timeline(os.path.dirname(csv_path))
     with open(out_path, "w") as fh:
         fh.write("\n".join(lines) + "\n")
+
+
+def _timeline(run_dir, short_ns=50_000):
+    """Busy time and idle gaps of the kernel trace next to the statistics:
+    a gap under `short_ns` between one kernel's end and the next one's start
+    is the dispatch of a queued kernel, a longer one is host work between
+    launches."""
+    traces = glob.glob(os.path.join(run_dir, "*kernel_trace.csv"))
+    if not traces:
+        return []
+    spans = sorted((int(r["Start_Timestamp"]), int(r["End_Timestamp"])) for r in _rows(traces[0]))
+    if len(spans) < 2:
+        return []
+    busy = sum(e - s for s, e in spans)
+    gaps = sorted(max(0, s - e0) for (_, e0), (s, _) in zip(spans, spans[1:]))
+    short = [g for g in gaps if g < short_ns]
+    long_ = [g for g in gaps if g >= short_ns]
+    span = spans[-1][1] - spans[0][0]
+    med = short[len(short) // 2] if short else 0
+    return ["", "Timeline of the kernel trace of the same run:", "",
+            f"* span {span / 1e6:.3f} ms, kernels busy {busy / 1e6:.3f} ms ({100 * busy / span:.1f}%)",
+            f"* {len(short)} gaps under {short_ns / 1e3:.0f} us between one kernel's end and the next "
+            f"one's start (dispatch of queued work, timed under the trace): median {med / 1e3:.2f} us, "
+            f"total {sum(short) / 1e6:.3f} ms",
+            f"* {len(long_)} longer gaps (host work between launches): total {sum(long_) / 1e6:.3f} ms"]
 
 
 def _counter_by_kernel(run_dir, counter):
