@@ -69,8 +69,12 @@ def test_samples_layout_and_forward_exact(grid, nb):
     assert nin == sizes[0]
 
 
-def test_update_matches_oracle():
-    nx, ny, nz, nb, width, batch, steps = 8, 4, 4, 2, 16, 8, 60
+# the second case has a batch and an output width that are not multiples of
+# the bias-gradient kernel's 16-wide slices or of its 4-row unrolling, and a
+# loss sum over more than 4096 values (the unrolled part of the loss kernel)
+@pytest.mark.parametrize("grid,nb,width,batch", [((8, 4, 4), 2, 16, 8), ((12, 9, 6), 3, 40, 200)])
+def test_update_matches_oracle(grid, nb, width, batch):
+    (nx, ny, nz), steps = grid, 60
     cx, cy, cz = nx // nb, ny // nb, nz // nb
     sizes = S.layer_sizes(nb, width)
     p0 = synth.mlp_init(sizes, seed=5)
