@@ -137,8 +137,9 @@ def coarse_solve_record(nx, ny, nz, args, degree):
     kernel-trace run of the same source."""
     if args.precond != "gmg":
         return None
-    s = 2 ** (args.mg_levels - 1)
-    cx, cy, cz = nx // s, ny // s, nz // s
+    cx, cy, cz = nx, ny, nz
+    for _ in range(args.mg_levels - 1):  # each level has ceil(n / 2) elements per axis
+        cx, cy, cz = (cx + 1) // 2, (cy + 1) // 2, (cz + 1) // 2
     nnode = (cx + 1) * (cy + 1) * (cz + 1)
     wide = args.precision == "fp64" and args.f32_from >= args.mg_levels  # the coarsest level in float64
     vb = 8.0 if wide else 4.0
@@ -428,7 +429,8 @@ def paper_mesh_study(fe, synth, torch, args, iters):
     the 2 x 1 x 1 domain in 70x35x35, 100x50x50 and 180x90x90 elements
     (h = 2 / nx), filter radius R = 0.08 (2.8, 4 and 7.2 elements), volume
     fraction 0.12, the edge load, `iters` iterations from the uniform design.
-    Multigrid keeps the levels the grid admits (Jacobi PCG when none)."""
+    Multigrid with the requested levels on every mesh (an odd axis coarsens
+    to ceil(n / 2) elements)."""
     dev = "cuda:0"
     T = lambda a: torch.as_tensor(a, dtype=torch.float64, device=dev)
     out = {"domain": [2.0, 1.0, 1.0], "filter_R": 0.08, "volfrac": 0.12, "move": args.move,
@@ -436,13 +438,11 @@ def paper_mesh_study(fe, synth, torch, args, iters):
     for nx in (70, 100, 180):
         ny = nz = nx // 2
         h = 2.0 / nx
-        levels = 1
-        while levels < args.mg_levels and all(n % (1 << levels) == 0 for n in (nx, ny, nz)):
-            levels += 1
-        precond = "gmg" if levels >= 2 and args.precond == "gmg" else "jacobi"
+        levels = args.mg_levels
+        precond = args.precond
         prob = fe.Problem(nx, ny, nz, T(synth.cantilever_edge_load(nx, ny, nz)), device=dev, h=h,
                           filter_r=0.08 / h, precision=args.precision, precond=precond,
-                          mg_levels=max(levels, 2))
+                          mg_levels=levels)
         mg = apply_mg(prob, args)
         ne = nx * ny * nz
         x = torch.full((ne,), 0.12, dtype=torch.float64, device=dev)
@@ -500,7 +500,7 @@ def onsg_study(fe, synth, torch, args, K, nb=5, width=1000, steps=2000, batch=25
 
     def make():
         prob = fe.Problem(nx, ny, nz, T(synth.cantilever_edge_load(nx, ny, nz)), device=dev, h=h,
-                          filter_r=0.08 / h, precision=args.precision, precond="gmg", mg_levels=2)
+                          filter_r=0.08 / h, precision=args.precision, precond="gmg", mg_levels=args.mg_levels)
         return prob
 
     def run(onsg):

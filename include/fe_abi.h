@@ -71,7 +71,11 @@ typedef struct fe_config {
   double filter_r;      /* density-filter radius in element units, 0 < filter_r <= 8 */
   int32_t precision;    /* FE_PREC_* */
   int32_t precond;      /* FE_PRECOND_* */
-  int32_t mg_levels;    /* levels of the geometric multigrid (>= 2 when precond = GMG) */
+  int32_t mg_levels;    /* levels of the geometric multigrid, 2..6 when precond = GMG;
+                           level l + 1 has ceil(n / 2) elements of twice the edge per
+                           axis of level l (any dimensions: an odd axis ends in a
+                           coarse element overhanging the mesh, its missing children
+                           counted as void) */
   int32_t reserved;     /* must be 0 */
 } fe_config;
 

@@ -53,9 +53,6 @@ std::string validate(const fe_config* c) {
   if (c->reserved != 0) return "reserved must be 0";
   if (c->precond == FE_PRECOND_GMG) {
     if (c->mg_levels < 2 || c->mg_levels > FE_MAX_LEVELS) return "mg_levels must lie in [2, 6]";
-    const int d = 1 << (c->mg_levels - 1);
-    if (c->nx % d || c->ny % d || c->nz % d)
-      return "grid dimensions must be divisible by 2^(mg_levels-1) for multigrid";
   }
   // the stencil table holds at most 512 offsets
   const int R = (int)std::ceil(c->filter_r);
@@ -105,9 +102,13 @@ size_t layout(const fe_config* c, fe_problem* p, char* base) {
     int64_t nb = (g.nnode + FE_BLOCK - 1) / FE_BLOCK;
     if (kxu_tile_blocks(g) > nb) nb = kxu_tile_blocks(g);
     if (nb > max_blocks) max_blocks = nb;
-    nx /= 2;
-    ny /= 2;
-    nz /= 2;
+    // the next level has ceil(n / 2) elements of twice the edge per axis: an
+    // odd axis ends in a coarse element that overhangs the mesh by one fine
+    // element (coarse node I sits on fine node 2I, the last one just past
+    // the mesh)
+    nx = (nx + 1) / 2;
+    ny = (ny + 1) / 2;
+    nz = (nz + 1) / 2;
     h *= 2.0;
   }
   double* f = (double*)take(g0.ndof * sizeof(double));

@@ -35,7 +35,11 @@ __global__ void __launch_bounds__(FE_BLOCK) simp_kernel(const double* __restrict
   }
 }
 
-// Coarse modulus: mean of the (up to) 8 fine children of each coarse element.
+// Coarse modulus: mean of the 8 fine children of each coarse element, a
+// child past the mesh (the overhanging last element of an odd axis) counting
+// as void: the rediscretised element then carries the stiffness of the part
+// of it that lies in the mesh, as the Galerkin product of the prolongation
+// would.
 __global__ void __launch_bounds__(FE_BLOCK) coarsen_modulus_kernel(Grid fg, Grid cg,
                                                                    const double* __restrict__ Ef,
                                                                    double* __restrict__ Ec64,
@@ -44,15 +48,11 @@ __global__ void __launch_bounds__(FE_BLOCK) coarsen_modulus_kernel(Grid fg, Grid
        e += (int64_t)gridDim.x * FE_BLOCK) {
     const int i = (int)(e % cg.nx), j = (int)((e / cg.nx) % cg.ny), k = (int)(e / ((int64_t)cg.nx * cg.ny));
     double s = 0.0;
-    int cnt = 0;
     for (int c = 0; c < 8; ++c) {
       const int fi = 2 * i + c_cx[c], fj = 2 * j + c_cy[c], fk = 2 * k + c_cz[c];
-      if (fi < fg.nx && fj < fg.ny && fk < fg.nz) {
-        s += Ef[fi + (int64_t)fg.nx * (fj + (int64_t)fg.ny * fk)];
-        ++cnt;
-      }
+      if (fi < fg.nx && fj < fg.ny && fk < fg.nz) s += Ef[fi + (int64_t)fg.nx * (fj + (int64_t)fg.ny * fk)];
     }
-    const double E = s / cnt;
+    const double E = s / 8.0;
     if (Ec64) Ec64[e] = E;
     if (Ec32) Ec32[e] = (float)E;
   }
@@ -73,7 +73,8 @@ __global__ void __launch_bounds__(FE_BLOCK) node_mask_kernel(Grid g, const uint8
   }
 }
 
-// A coarse node is fixed in component c when the fine node at the same place is.
+// A coarse node is fixed in component c when the fine node at the same place
+// is; a coarse node just past the mesh (odd axis) takes the last fine node's.
 __global__ void __launch_bounds__(FE_BLOCK) coarsen_mask_kernel(Grid fg, Grid cg,
                                                                 const uint8_t* __restrict__ fm,
                                                                 uint8_t* __restrict__ cm) {

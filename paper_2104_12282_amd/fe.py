@@ -297,9 +297,7 @@ class Problem:
         (nx/nb, ny/nb, nz/nb) grid with element edge nb h and the same
         physical filter radius (filter_r / nb elements), the material of this
         problem, load f_c.  Keyword arguments override the solver settings
-        (precision, precond, mg_levels); with multigrid the hierarchy keeps
-        as many of this problem's levels as the coarse grid's dimensions
-        admit, and Jacobi preconditioning replaces it when they admit none."""
+        (precision, precond, mg_levels)."""
         if nb < 1 or self.nx % nb or self.ny % nb or self.nz % nb:
             raise FEError(FE_EINVAL, "nb must be >= 1 and divide nx, ny and nz")
         c = self.cfg
@@ -308,13 +306,6 @@ class Problem:
                   precision=PRECISION_NAME[c.precision], precond=PRECOND_NAME[c.precond],
                   mg_levels=max(2, c.mg_levels))
         kw.update(cfg_kw)
-        if kw["precond"] == "gmg":
-            lv = kw["mg_levels"]
-            while lv >= 2 and any(n % (1 << (lv - 1)) for n in (cx, cy, cz)):
-                lv -= 1
-            if lv < 2:
-                kw["precond"] = "jacobi"
-            kw["mg_levels"] = max(lv, 2)
         return Problem(cx, cy, cz, f_c, fixed_c, device=self.device, stream=self.stream, **kw)
 
     def set_mg_params(self, nu=1, coarse_sweeps=48, omega=0.35, coarse_ratio=5000.0):

@@ -42,8 +42,12 @@ def test_workspace_size_validation():
         assert lib.fe_workspace_size(C.byref(cfg)) == 0, kw
     assert lib.fe_workspace_size(C.byref(fe.make_config(0, 12, 12))) == 0
     assert lib.fe_workspace_size(C.byref(fe.make_config(24, 12, 12, filter_r=8.0))) > 0
-    # multigrid needs dims divisible by 2^(levels-1)
-    assert lib.fe_workspace_size(C.byref(fe.make_config(25, 12, 12, precond="gmg"))) == 0
+    # multigrid takes any dimensions (levels of ceil(n / 2) elements per axis)
+    # and 2-6 levels
+    odd = fe.make_config(25, 13, 7, precond="gmg", mg_levels=3)
+    assert lib.fe_workspace_size(C.byref(odd)) > lib.fe_workspace_size(C.byref(fe.make_config(25, 13, 7)))
+    for lv in (1, 7):
+        assert lib.fe_workspace_size(C.byref(fe.make_config(24, 12, 12, precond="gmg", mg_levels=lv))) == 0
 
 
 def test_setup_rejects_bad_arguments_without_gpu():

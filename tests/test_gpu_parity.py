@@ -250,7 +250,8 @@ def test_breakdown_on_nan_density():
 
 
 @pytest.mark.parametrize("precision", ["fp64", "fp32_ir"])
-@pytest.mark.parametrize("grid,levels", [((24, 12, 12), 3), ((16, 8, 8), 2), ((32, 16, 8), 4)])
+@pytest.mark.parametrize("grid,levels", [((24, 12, 12), 3), ((16, 8, 8), 2), ((32, 16, 8), 4),
+                                         ((13, 7, 5), 3), ((25, 12, 9), 3), ((30, 15, 15), 3), ((21, 11, 7), 4)])
 def test_gmg_solve_parity(Ke, grid, levels, precision):
     nx, ny, nz = grid
     rho = synth.density_around(nx, ny, nz, 3)
@@ -270,18 +271,20 @@ def test_gmg_solve_parity(Ke, grid, levels, precision):
     assert info["iters"] < info_j["iters"]
 
 
+@pytest.mark.parametrize("grid,levels", [((28, 14, 14), 2), ((30, 15, 15), 3)])
 @pytest.mark.parametrize("precond", ["jacobi", "gmg"])
-def test_paper_domain_step_parity(Ke, precond):
+def test_paper_domain_step_parity(Ke, precond, grid, levels):
     """The paper's cantilever geometry (2 x 1 x 1 domain, h = 2 / nx, filter
-    radius 0.08 = 1.12 elements here) on 28x14x14: one optimisation step's
-    filter, solve, compliance and sensitivity against the oracle with Ke of
-    edge h."""
-    nx, ny, nz = 28, 14, 14
+    radius 0.08 = 1.12-1.2 elements here) on 28x14x14 and on 30x15x15 (odd
+    like the paper's 70x35x35 mesh: its coarse levels overhang the mesh):
+    one optimisation step's filter, solve, compliance and sensitivity
+    against the oracle with Ke of edge h."""
+    nx, ny, nz = grid
     h = 2.0 / nx
     r = 0.08 / h
     x = synth.density_uniform(nx, ny, nz, seed=8)
     f = synth.cantilever_edge_load(nx, ny, nz)
-    prob = fe.Problem(nx, ny, nz, T(f), device=DEV, h=h, filter_r=r, precond=precond, mg_levels=2)
+    prob = fe.Problem(nx, ny, nz, T(f), device=DEV, h=h, filter_r=r, precond=precond, mg_levels=levels)
     rho = prob.filter(T(x))
     P = O.filter_matrix(nx, ny, nz, r)
     rho_ref = P @ x
@@ -543,7 +546,8 @@ def test_coarse_chebyshev_degrees_parity(Ke, deg, precision):
 
 @pytest.mark.parametrize("grid,precond,levels", [((1, 1, 1), "jacobi", 1), ((5, 1, 1), "jacobi", 1),
                                                  ((2, 9, 3), "jacobi", 1), ((2, 2, 2), "gmg", 2),
-                                                 ((4, 2, 2), "gmg", 2), ((8, 4, 4), "gmg", 3)])
+                                                 ((4, 2, 2), "gmg", 2), ((8, 4, 4), "gmg", 3),
+                                                 ((3, 1, 1), "gmg", 2), ((5, 3, 1), "gmg", 3)])
 @pytest.mark.parametrize("precision", ["fp64", "fp32_ir"])
 def test_solve_degenerate_grids(Ke, grid, precond, levels, precision):
     """One-element-thick grids and multigrid hierarchies whose coarsest
@@ -568,7 +572,7 @@ def test_solve_degenerate_grids(Ke, grid, precond, levels, precision):
 
 @pytest.mark.parametrize("grid,levels,deg", [((32, 16, 16), 3, 40), ((60, 32, 28), 3, 7), ((8, 4, 4), 3, 4),
                                              ((26, 14, 2), 2, 5), ((80, 80, 40), 2, 6),
-                                             ((208, 208, 64), 2, 6)])
+                                             ((208, 208, 64), 2, 6), ((27, 13, 9), 3, 6)])
 @pytest.mark.parametrize("precision", ["fp64", "fp32_ir"])
 def test_coarse_fusion_bitwise(grid, levels, deg, precision):
     """Pairs of coarse Chebyshev steps in one launch (each workgroup

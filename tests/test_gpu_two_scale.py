@@ -105,8 +105,9 @@ def test_fullsize_block_means(nb):
 
 
 def test_fullsize_coarse_solves():
-    """224x112x56 design, block sizes 8 (28x14x7, Jacobi-PCG: checked against
-    the oracle's direct solve) and 4 (56x28x14, 3-level multigrid: float64
+    """224x112x56 design, block sizes 8 (28x14x7, 3-level multigrid whose
+    coarse levels overhang the odd axis: checked against the oracle's direct
+    solve) and 4 (56x28x14, 3-level multigrid: float64
     residual and the energy identity by the oracle)."""
     nx, ny, nz = 224, 112, 56
     P = O.filter_matrix(nx, ny, nz, 1.5)
