@@ -60,12 +60,14 @@ def test_served_design_matches_oracle():
     assert np.abs(r["dc"] - dc_ref).max() / np.abs(dc_ref).max() <= 1e-5
 
 
+@pytest.mark.parametrize("grid", [(16, 8, 8), (13, 7, 5)])
 @pytest.mark.parametrize("precision", ["fp32_ir", "fp64"])
-def test_batch_slots_match_lone_solves(precision):
+def test_batch_slots_match_lone_solves(precision, grid):
     """Designs sharing a batch's launches (one slot idle, slots reused)
-    give bitwise the result of the same design solved alone."""
+    give bitwise the result of the same design solved alone, also on an odd
+    grid whose coarse levels overhang the mesh."""
     from paper_2104_12282_amd import fe
-    nx, ny, nz = 16, 8, 8
+    nx, ny, nz = grid
     T = lambda a: torch.as_tensor(a, dtype=torch.float64, device=DEV)
     designs = [(synth.point_load(nx, ny, nz, s), synth.density_uniform(nx, ny, nz, s)) for s in (11, 12, 13, 14)]
     alone = []
