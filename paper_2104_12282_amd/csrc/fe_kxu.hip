@@ -411,22 +411,17 @@ __global__ void __launch_bounds__(TX* TY, FE_KXU_MIN_WAVES) kxu_tile_kernel(Grid
   const uint32_t o_own = off_part(ni >= 0 && ni <= g.nx && nj >= 0 && nj <= g.ny, ni + sx * nj);
   const uint32_t o_halo = off_part(hslot && hi >= 0 && hi <= g.nx && hj >= 0 && hj <= g.ny, hi + sx * hj);
   const uint32_t o_el = off_part(ecol, ni + (int64_t)g.nx * nj);
+  // the operand as loaded: float32 under XIN 3, widened when it goes to LDS
+  using XT = typename std::conditional<XIN == 3, float, T>::type;
   struct LevelIn {
-    T own[3];
-    T halo[3];
+    XT own[3];
+    XT halo[3];
     T Ee;  // modulus of the brick layer below this level
     T d_own, d_halo;       // XIN 1: inverse diagonal
     T p_own[3], p_halo[3];  // XIN 2: previous direction
   };
-  auto node_in = [&](uint32_t o, T (&v)[3], T& d, T (&pv)[3]) {
-    if constexpr (XIN == 3) {
-      float vf[3];
-      load3(rx, o * 12u, vf);
-#pragma unroll
-      for (int c = 0; c < 3; ++c) v[c] = (T)vf[c];
-    } else {
-      load3(rx, o * (uint32_t)(3 * sizeof(T)), v);
-    }
+  auto node_in = [&](uint32_t o, XT (&v)[3], T& d, T (&pv)[3]) {
+    load3(rx, o * (uint32_t)(3 * sizeof(XT)), v);
     if (XIN == 1) d = load1(rxd, o * (uint32_t)sizeof(T), T());
     if (XIN >= 2) load3(rxp, o * (uint32_t)(3 * sizeof(T)), pv);  // also on the first iteration (then unused)
   };
@@ -437,10 +432,11 @@ __global__ void __launch_bounds__(TX* TY, FE_KXU_MIN_WAVES) kxu_tile_kernel(Grid
     L.Ee = load1(re, (o_el + lev_part(k - 1, elo, ehi - elo + 1, nel)) * (uint32_t)sizeof(T), T());
   };
   // the operand value of a node from what was loaded for it
-  auto operand = [&](const T (&v)[3], T d, const T (&pv)[3], int c) -> T {
-    if (XIN == 1) return xi.s * d * v[c];
-    if (XIN >= 2) return first_dir ? v[c] : v[c] + beta * pv[c];  // p_old is not set before the first
-    return v[c];
+  auto operand = [&](const XT (&v)[3], T d, const T (&pv)[3], int c) -> T {
+    const T x = (T)v[c];
+    if (XIN == 1) return xi.s * d * x;
+    if (XIN >= 2) return first_dir ? x : x + beta * pv[c];  // p_old is not set before the first
+    return x;
   };
   // stores a level into LDS; the loaded registers die here (this thread's
   // own values are read back from LDS after the barrier), so the register
