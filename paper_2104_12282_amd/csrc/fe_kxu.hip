@@ -39,6 +39,14 @@ constexpr int TX = 16, TY = 16, OWN = 15;
 #define FE_KXU_MIN_WAVES 1  // no occupancy floor beyond what the registers give
 #endif
 
+// Occupancy floor per instance: the float32 last-sweep form (MODE 5) fits
+// 128 VGPRs without spills when asked to, four waves per SIMD instead of
+// three; every other instance keeps what its registers give.
+template <typename T, int MODE>
+constexpr int kxu_min_waves() {
+  return std::is_same<T, float>::value && MODE == 5 ? 4 : FE_KXU_MIN_WAVES;
+}
+
 template <typename T>
 struct WK {
   T A, B, G, C, D, F, H, J;
@@ -342,7 +350,7 @@ __device__ inline double block_sum_all(const double* __restrict__ part, int n) {
 // a buffer is rewritten only after every thread has passed the barrier that
 // follows its last read.
 template <typename T, int MODE, int XIN>
-__global__ void __launch_bounds__(TX* TY, FE_KXU_MIN_WAVES) kxu_tile_kernel(Grid g, TileMap tm, const T* __restrict__ x,
+__global__ void __launch_bounds__(TX* TY, (kxu_min_waves<T, MODE>())) kxu_tile_kernel(Grid g, TileMap tm, const T* __restrict__ x,
                                                          const T* __restrict__ E,
                                                          const uint8_t* __restrict__ nmask, WK<T> wk,
                                                          T* __restrict__ y, Epi<T> ep, CgState* st,
