@@ -214,6 +214,21 @@ def apply_K_rows(nx, ny, nz, E_elem, Ke, fixed, u, nodes):
     return out
 
 
+def apply_K_elementwise(nx, ny, nz, E_elem, Ke, fixed, u, edof=None):
+    """y = K_ff u_f on free dofs, 0 on fixed dofs, evaluated from the
+    definition K = sum_e E_e A_e^T Ke A_e without assembling K: gather each
+    brick's 24 values, multiply by E_e Ke, add the products back into the
+    global vector (np.bincount sums them in element order).  Memory grows
+    with the mesh, not with the nonzeros of K, so it serves grids whose
+    assembled K does not fit in host memory."""
+    if edof is None:
+        edof = element_dofs(nx, ny, nz)
+    uf = np.where(fixed, 0.0, u)
+    Y = (uf[edof] @ Ke) * np.asarray(E_elem, dtype=np.float64)[:, None]  # Ke symmetric
+    y = np.bincount(edof.ravel(), weights=Y.ravel(), minlength=u.size)
+    return np.where(fixed, 0.0, y)
+
+
 def apply_K_free(K: sp.csr_matrix, fixed: np.ndarray, u: np.ndarray) -> np.ndarray:
     """y = K_ff u_f on free dofs, 0 on fixed dofs (fixed entries of u are
     ignored)."""
@@ -261,17 +276,37 @@ def solve_direct(nx, ny, nz, E_elem, Ke, f, fixed) -> np.ndarray:
 
 
 def solve_pcg(nx, ny, nz, E_elem, Ke, f, fixed, rtol=1e-12, max_iters=100000,
-              u0=None):
+              u0=None, elementwise=False, progress=None):
     """Fallback for grids too large for the banded factor: Jacobi-preconditioned
-    CG on the assembled K_ff, stopped at ||f - K u|| <= rtol ||f|| over the free
-    dofs.  Returns (u, iterations, relative residual)."""
-    K = assemble_K(nx, ny, nz, E_elem, Ke)
+    CG on K_ff, stopped at ||f - K u|| <= rtol ||f|| over the free dofs.
+    K_ff is the assembled CSR matrix, or with elementwise=True the
+    element-by-element product apply_K_elementwise (the same K, for grids
+    whose assembled matrix does not fit in host memory); the Jacobi diagonal
+    is then sum_e E_e Ke_dd over the bricks that hold the dof.  progress, if
+    given, is called as progress(iteration, relative residual) every 100
+    iterations.  Returns (u, iterations, relative residual)."""
     free = ~fixed
-    Kff = K[free][:, free].tocsr()
+    if elementwise:
+        edof = element_dofs(nx, ny, nz)
+        E = np.asarray(E_elem, dtype=np.float64)
+        dfull = np.bincount(edof.ravel(), weights=(E[:, None] * np.diag(Ke)[None, :]).ravel(),
+                            minlength=f.size)
+
+        def matvec(v):
+            full = np.zeros(f.size)
+            full[free] = v
+            return apply_K_elementwise(nx, ny, nz, E, Ke, fixed, full, edof)[free]
+        d = dfull[free]
+    else:
+        K = assemble_K(nx, ny, nz, E_elem, Ke)
+        Kff = K[free][:, free].tocsr()
+        d = Kff.diagonal()
+
+        def matvec(v):
+            return Kff @ v
     b = f[free]
-    d = Kff.diagonal()
     x = np.zeros(b.size) if u0 is None else u0[free].copy()
-    r = b - Kff @ x
+    r = b - matvec(x)
     z = r / d
     p = z.copy()
     rz = r @ z
@@ -279,7 +314,7 @@ def solve_pcg(nx, ny, nz, E_elem, Ke, f, fixed, rtol=1e-12, max_iters=100000,
     it = 0
     rel = np.linalg.norm(r) / bnorm
     while rel > rtol and it < max_iters:
-        q = Kff @ p
+        q = matvec(p)
         alpha = rz / (p @ q)
         x += alpha * p
         r -= alpha * q
@@ -289,6 +324,8 @@ def solve_pcg(nx, ny, nz, E_elem, Ke, f, fixed, rtol=1e-12, max_iters=100000,
         rz = rz_new
         it += 1
         rel = np.linalg.norm(r) / bnorm
+        if progress is not None and it % 100 == 0:
+            progress(it, rel)
     u = np.zeros(f.size)
     u[free] = x
     return u, it, rel

@@ -83,3 +83,102 @@ def test_training_fits_a_smooth_target():
     Y = np.sin(X[:, :3].sum(axis=1, keepdims=True))
     p, losses = S.adam_train(synth.mlp_init(sizes, 0), sizes, X, Y, synth.minibatches(256, 400, 32, 2), 5e-3, 200)
     assert losses[-20:].mean() < 0.1 * losses[0]
+
+
+def _copy_net(nb, pick):
+    """Parameters (per layer W out x in row-major, then b) of a network whose
+    output k equals input pick[k]: relu(x) - relu(-x) = x through identity
+    hidden layers of width 2 nin."""
+    sizes = S.layer_sizes(nb, 2 * (nb ** 3 + 24))
+    nin, w = sizes[0], sizes[1]
+    eye = np.eye(nin)
+    parts = [np.vstack([eye, -eye]).ravel(), np.zeros(w)]
+    for _ in range(3):
+        parts += [np.eye(w).ravel(), np.zeros(w)]
+    Wo = np.zeros((nb ** 3, w))
+    for k, src in enumerate(pick):
+        Wo[k, src] = 1.0
+        Wo[k, nin + src] = -1.0
+    parts += [Wo.ravel(), np.zeros(nb ** 3)]
+    return sizes, np.concatenate(parts)
+
+
+@pytest.mark.parametrize("nb", [1, 2])
+def test_forward_copies_picked_inputs(nb):
+    """Signed inputs pass the copy network unchanged only if the hidden
+    layers (and not the output layer) apply ReLU and every W is read as
+    out x in, row-major, ahead of its bias."""
+    rng = np.random.default_rng(11)
+    nin = nb ** 3 + 24
+    X = rng.standard_normal((9, nin))
+    for pick in (list(range(nb ** 3)), [nin - 1 - (k % nin) for k in range(nb ** 3)]):
+        sizes, p = _copy_net(nb, pick)
+        assert p.size == S.n_params(sizes)
+        out = S.forward(p, sizes, X)[-1]
+        assert np.array_equal(out, X[:, pick])
+
+
+# a network of widths 2 -> 3 -> 2 worked by hand, biases nonzero:
+# z1 = W1 x + b1 = (1 - 4 + 0.5, 2 - 1, 3 - 2 + 2) = (-2.5, 1, 3); relu -> (0, 1, 3);
+# out = W2 a1 + b2 = (0 + 1 + 3 - 1, 0 + 0 - 3 + 0.25) = (3, -2.75), linear (no ReLU).
+HAND_X = np.array([[1.0, -2.0]])
+HAND_W1 = np.array([[1.0, 2.0], [0.0, -1.0], [3.0, 1.0]])
+HAND_B1 = np.array([0.5, -1.0, 2.0])
+HAND_W2 = np.array([[1.0, 1.0, 1.0], [2.0, 0.0, -1.0]])
+HAND_B2 = np.array([-1.0, 0.25])
+HAND_OUT = np.array([[3.0, -2.75]])
+
+
+def _hand_case_holds():
+    sizes = [2, 3, 2]
+    p = np.concatenate([HAND_W1.ravel(), HAND_B1, HAND_W2.ravel(), HAND_B2])
+    layers = S.unpack(p, sizes)
+    ok = (len(layers) == 2 and np.array_equal(layers[0][0], HAND_W1) and np.array_equal(layers[0][1], HAND_B1)
+          and np.array_equal(layers[1][0], HAND_W2) and np.array_equal(layers[1][1], HAND_B2))
+    return ok and np.array_equal(S.forward(p, sizes, HAND_X)[-1], HAND_OUT)
+
+
+def test_unpack_layout_and_hand_computed_forward():
+    assert _hand_case_holds()
+    # the hidden activation as worked by hand
+    sizes = [2, 3, 2]
+    p = np.concatenate([HAND_W1.ravel(), HAND_B1, HAND_W2.ravel(), HAND_B2])
+    assert np.array_equal(S.forward(p, sizes, HAND_X)[1], np.array([[0.0, 1.0, 3.0]]))
+
+
+def test_pins_catch_planted_network_mistakes(monkeypatch):
+    good_unpack, good_forward = S.unpack, S.forward
+
+    def bias_first(params, sizes):  # b ahead of W in the flat vector
+        out, k = [], 0
+        for i, o in zip(sizes[:-1], sizes[1:]):
+            b = params[k:k + o]
+            k += o
+            out.append((params[k:k + o * i].reshape(o, i), b))
+            k += o * i
+        return out
+
+    def transposed(params, sizes):  # W read in x out
+        return [(W.reshape(W.shape[1], W.shape[0]).T if W.shape[0] != W.shape[1] else W.T, b)
+                for W, b in good_unpack(params, sizes)]
+
+    def no_bias(params, sizes, X):
+        acts = [np.asarray(X, dtype=np.float64)]
+        layers = good_unpack(params, sizes)
+        for li, (W, _) in enumerate(layers):
+            z = acts[-1] @ W.T
+            acts.append(np.maximum(z, 0.0) if li < len(layers) - 1 else z)
+        return acts
+
+    def relu_on_output(params, sizes, X):
+        acts = good_forward(params, sizes, X)
+        acts[-1] = np.maximum(acts[-1], 0.0)
+        return acts
+
+    for name, fn in (("unpack", bias_first), ("unpack", transposed), ("forward", no_bias),
+                     ("forward", relu_on_output)):
+        monkeypatch.setattr(S, name, fn)
+        assert not _hand_case_holds(), fn.__name__
+        monkeypatch.setattr(S, "unpack", good_unpack)
+        monkeypatch.setattr(S, "forward", good_forward)
+    assert _hand_case_holds()

@@ -229,6 +229,33 @@ def test_cholesky_vs_pcg(Ke):
     K = O.assemble_K(nx, ny, nz, E, Ke)
     r = np.where(fixed, 0.0, f - K @ ud)
     assert np.linalg.norm(r) < 1e-10 * np.linalg.norm(f)
+    # the element-by-element operator (the paper-scale references) reaches the same u
+    ue, it_e, rel_e = O.solve_pcg(nx, ny, nz, E, Ke, f, fixed, rtol=1e-13, elementwise=True)
+    assert rel_e <= 1e-13
+    assert np.abs(ud - ue).max() < 1e-9 * np.abs(ud).max()
+
+
+def test_elementwise_operator(Ke):
+    """K u formed brick by brick equals the assembled K_ff u_f, annihilates
+    the rigid motions when nothing is fixed, and is symmetric."""
+    nx, ny, nz = 5, 4, 3
+    rng = np.random.default_rng(8)
+    E = rng.uniform(0.1, 1.0, nx * ny * nz)
+    u = rng.standard_normal(3 * (nx + 1) * (ny + 1) * (nz + 1))
+    fixed = O.clamp_x0_fixed(nx, ny, nz)
+    ref = O.apply_K_free(O.assemble_K(nx, ny, nz, E, Ke), fixed, u)
+    y = O.apply_K_elementwise(nx, ny, nz, E, Ke, fixed, u)
+    assert np.abs(y - ref).max() < 1e-13 * np.abs(ref).max()
+    none = np.zeros_like(fixed)
+    n = np.arange((nx + 1) * (ny + 1) * (nz + 1))
+    xyz = np.stack([n % (nx + 1), (n // (nx + 1)) % (ny + 1), n // ((nx + 1) * (ny + 1))], axis=1)
+    R = O.rigid_body_modes(xyz.astype(float))
+    for m in range(6):
+        assert np.abs(O.apply_K_elementwise(nx, ny, nz, E, Ke, none, R[:, m])).max() < 1e-12
+    v = rng.standard_normal(u.size)
+    a = v @ O.apply_K_elementwise(nx, ny, nz, E, Ke, fixed, u)
+    b = u @ O.apply_K_elementwise(nx, ny, nz, E, Ke, fixed, v)
+    assert abs(a - b) < 1e-12 * abs(a)
 
 
 # ----------------------------------------------------- compliance, dc
@@ -407,3 +434,13 @@ def test_row_and_element_samplers_agree_with_full_forms(Ke):
     el = np.array([0, 7, 33, 59])
     assert np.abs(O.sensitivity_elements(nx, ny, nz, Ke, rho, u, el)
                   - O.sensitivity(nx, ny, nz, Ke, rho, u)[el]).max() < 1e-13
+    lam = rng.standard_normal(u.size)
+    full = O.adjoint_sensitivity(nx, ny, nz, Ke, rho, u, lam)
+    part = O.adjoint_sensitivity_elements(nx, ny, nz, Ke, rho, u, lam, el)
+    assert np.abs(part - full[el]).max() < 1e-13 * np.abs(full).max()
+    # lam and u enter as lam_e^T Ke u_e: swapping them changes nothing (Ke symmetric),
+    # and lam = u is the compliance sensitivity
+    assert np.abs(O.adjoint_sensitivity_elements(nx, ny, nz, Ke, rho, lam, u, el) - part).max() \
+        < 1e-13 * np.abs(full).max()
+    assert np.abs(O.adjoint_sensitivity_elements(nx, ny, nz, Ke, rho, u, u, el)
+                  - O.sensitivity_elements(nx, ny, nz, Ke, rho, u, el)).max() < 1e-13
