@@ -15,9 +15,29 @@
  *   dof 3*n + c with c = x, y, z.
  *
  * Memory: every array argument is a DEVICE pointer owned by the caller, in
- * float64, unless stated otherwise.  The library owns only the opaque handle;
- * all of its device memory lives in the caller's workspace (no allocation on
- * any call after fe_setup, and none inside fe_setup either).
+ * float64, unless stated otherwise.  Every device array the library works on
+ * (vectors, moduli, multigrid levels, reduction partials, scalars) lives in
+ * the caller's workspace; the library makes no device-array allocation.
+ * What it does create, per handle, outside the workspace:
+ *   - fe_setup: the host handle (operator new), two small pinned host
+ *     buffers (hipHostMalloc: the CG state mirror and four scalars), one
+ *     event (hipEventCreateWithFlags) and one non-blocking capture stream
+ *     (hipStreamCreateWithFlags); fe_setup also synchronises the stream
+ *     once (its host-to-device copies read host stack arrays);
+ *   - the first solve of each vector type (and the first after a change of
+ *     multigrid parameters, precision path or profiling): one captured and
+ *     instantiated HIP graph of a chunk of CG iterations (hipGraphInstantiate
+ *     allocates the graph's own runtime memory); oc_update on the same
+ *     arrays a second time: one captured graph of the update;
+ *   - fe_batch_create: the host batch object and one handle per slot, each
+ *     created as by fe_setup (pinned buffers, event, capture stream), and
+ *     the batch's own captured graph on its first round;
+ *   - with profiling on: event pairs (hipEventCreate), reused;
+ *   - the synthetic-gradient model (fe_onsg_create): a rocBLAS handle.
+ * fe_destroy / fe_batch_destroy / fe_onsg_destroy release all of it.
+ * Blocking calls: fe_setup, fe_solve, fe_set_load, fe_kernel_stats (when
+ * events are pending), fe_batch_setup_slot and fe_batch_round_end wait for
+ * the handle's stream; everything else is asynchronous.
  *
  * Streams: every call is ordered on the stream given to fe_setup.  Calls that
  * return host scalars (fe_solve) synchronise that stream before returning;
@@ -255,6 +275,18 @@ FE_API fe_status fe_set_coarse_fusion(fe_problem* p, int32_t steps_per_launch);
 FE_API fe_status fe_set_profiling(fe_problem* p, int32_t on);
 FE_API fe_status fe_kernel_stats(fe_problem* p, int32_t reset, int64_t* launches,
                           double* total_ms, double* bytes_per_launch);
+
+/* Cold-cache timing of the profiled launches (measurement only): with buf
+ * set (device memory of `bytes` >= 512 MB, 16-byte aligned, owned by the
+ * caller and overwritten: every 32-bit word is incremented once per profiled
+ * launch), every launch that fe_set_profiling brackets with events is
+ * preceded by a kernel that streams once through buf, so the launch finds
+ * none of its operands in the 256 MB last-level cache or in the XCDs' L2
+ * caches and its timing is that of data coming from HBM.  The time of the
+ * streaming kernel itself is outside the event pair.  buf = NULL switches
+ * it off.  Captured CG chunks are re-captured on the next solve.
+ * FE_EINVAL for a smaller or misaligned buffer. */
+FE_API fe_status fe_set_cache_flush(fe_problem* p, void* buf, size_t bytes);
 
 /* Release the handle (the workspace stays the caller's). */
 FE_API void fe_destroy(fe_problem* p);

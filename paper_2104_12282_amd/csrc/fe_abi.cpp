@@ -1082,6 +1082,20 @@ extern "C" fe_status fe_set_profiling(fe_problem* p, int32_t on) {
   return FE_OK;
 }
 
+extern "C" fe_status fe_set_cache_flush(fe_problem* p, void* buf, size_t bytes) {
+  CHECK_HANDLE(p);
+  if (buf && (bytes < ((size_t)512 << 20) || ((uintptr_t)buf) % 16)) {
+    fe_set_error("the cold-cache buffer must be 16-byte aligned and at least 512 MB");
+    return FE_EINVAL;
+  }
+  p->kst.flush = buf ? static_cast<uint32_t*>(buf) : nullptr;
+  p->kst.flush_words = buf ? bytes / sizeof(uint32_t) : 0;
+  // captured chunks carry the flush launches only if captured with it
+  drop_graph(p->chunk64);
+  drop_graph(p->chunk32);
+  return FE_OK;
+}
+
 extern "C" fe_status fe_kernel_stats(fe_problem* p, int32_t reset, int64_t* launches, double* total_ms,
                                      double* bytes_per_launch) {
   CHECK_HANDLE(p);

@@ -79,6 +79,10 @@ struct KStats {
   int64_t launches = 0;
   double total_ms = 0.0;
   double total_bytes = 0.0;
+  // cold-cache timing: a caller buffer streamed through (read and written)
+  // before every profiled launch, larger than the last-level cache
+  uint32_t* flush = nullptr;
+  size_t flush_words = 0;
   // while a graph is being captured, event pairs go to the graph's own lists
   std::vector<hipEvent_t>* cap_ev = nullptr;
   std::vector<double>* cap_bytes = nullptr;

@@ -26,7 +26,7 @@ STATUS_NAME = {0: "FE_OK", -1: "FE_EINVAL", -2: "FE_ENOMEM", -3: "FE_EDEVICE",
 # Every entry point declared in include/fe_abi.h.
 ABI_SYMBOLS = ("fe_workspace_size", "fe_setup", "fe_apply_K", "fe_solve", "fe_solve_begin",
                "fe_solve_step", "fe_solve_end", "fe_sensitivity", "fe_sensitivity_adjoint", "fe_set_load",
-               "fe_filter", "oc_update", "fe_block_mean", "fe_set_mg_params", "fe_get_mg_params", "fe_set_float32_levels", "fe_set_coarse_fusion", "fe_set_profiling",
+               "fe_filter", "oc_update", "fe_block_mean", "fe_set_mg_params", "fe_get_mg_params", "fe_set_float32_levels", "fe_set_coarse_fusion", "fe_set_profiling", "fe_set_cache_flush",
                "fe_kernel_stats", "fe_destroy", "fe_batch_workspace_size", "fe_batch_create", "fe_batch_setup_slot",
                "fe_batch_round_begin", "fe_batch_round_end", "fe_batch_destroy", "fe_onsg_num_params",
                "fe_onsg_workspace_size", "fe_onsg_create", "fe_onsg_add_samples", "fe_onsg_num_samples",
@@ -84,6 +84,7 @@ def load_library() -> C.CDLL:
     lib.fe_get_mg_params.argtypes = [P, C.POINTER(I32), C.POINTER(I32), C.POINTER(D), C.POINTER(D)]
     lib.fe_set_coarse_fusion.argtypes = [P, I32]
     lib.fe_set_profiling.argtypes = [P, I32]
+    lib.fe_set_cache_flush.argtypes = [P, P, C.c_size_t]
     lib.fe_kernel_stats.argtypes = [P, I32, C.POINTER(I64), C.POINTER(D), C.POINTER(D)]
     lib.fe_destroy.argtypes = [P]
     lib.fe_destroy.restype = None
@@ -111,7 +112,7 @@ def load_library() -> C.CDLL:
     lib.fe_last_error.restype = C.c_char_p
     for name in ("fe_setup", "fe_apply_K", "fe_solve", "fe_solve_begin", "fe_solve_step",
                  "fe_solve_end", "fe_sensitivity", "fe_filter",
-                 "oc_update", "fe_set_mg_params", "fe_set_coarse_fusion", "fe_set_profiling", "fe_kernel_stats",
+                 "oc_update", "fe_set_mg_params", "fe_set_coarse_fusion", "fe_set_profiling", "fe_set_cache_flush", "fe_kernel_stats",
                  "fe_batch_create", "fe_batch_setup_slot", "fe_batch_round_begin", "fe_batch_round_end"):
         getattr(lib, name).restype = C.c_int
     _lib = lib
@@ -331,6 +332,17 @@ class Problem:
         """Times finest-grid K*u launches: all forms, or only form `mode`."""
         sel = 0 if not on else (1 if mode is None else 2 + int(mode))
         _check(load_library().fe_set_profiling(self._h, sel))
+
+    def set_cache_flush(self, buf: torch.Tensor | None):
+        """Cold-cache timing of profiled launches: `buf` (a device tensor of at
+        least 512 MB, overwritten) is streamed through before each one."""
+        if buf is None:
+            _check(load_library().fe_set_cache_flush(self._h, None, 0))
+            return
+        if not buf.is_cuda or not buf.is_contiguous():
+            raise ValueError("contiguous device tensor required")
+        _check(load_library().fe_set_cache_flush(self._h, C.c_void_p(buf.data_ptr()),
+                                                 buf.numel() * buf.element_size()))
 
     def kernel_stats(self, reset=False):
         n, ms, b = C.c_int64(), C.c_double(), C.c_double()

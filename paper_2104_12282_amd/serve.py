@@ -155,20 +155,30 @@ def run_engine(requests, arrivals=None, *, device="cuda:0", max_active=16, n_str
 
 
 def run_sequential(requests, *, device="cuda:0", rtol=1e-8, filter_passes=3, keep_outputs=False,
-                   cfg_kw=None):
+                   cfg_kw=None, reuse=True):
     """The same requests one at a time with the blocking fe_solve (no
-    overlap, no admission), for comparison."""
+    overlap, no admission), for comparison.  With reuse (the default) one
+    problem per grid size is set up once and kept: a request swaps in its
+    load (fe_set_load) and reuses the size's workspace and captured graphs,
+    as the batched engine reuses its slots; reuse=False sets up a fresh
+    problem per request."""
     cfg_kw = dict(cfg_kw or {"precision": "fp32_ir", "precond": "gmg", "mg_levels": 3})
     stream = torch.cuda.current_stream(device)
     results = {}
+    probs = {}
     t0 = time.perf_counter()
     for req in requests:
         ts = time.perf_counter() - t0
-        prob, rho, u, dc, comp = None, None, None, None, None
         nx, ny, nz = req["grid"]
         f, rho0 = prepare_inputs(req, device)
-        prob = fe.Problem(nx, ny, nz, torch.as_tensor(f, device=device), device=device,
-                          stream=stream, **cfg_kw)
+        ft = torch.as_tensor(f, device=device)
+        prob = probs.get(tuple(req["grid"])) if reuse else None
+        if prob is None:
+            prob = fe.Problem(nx, ny, nz, ft, device=device, stream=stream, **cfg_kw)
+            if reuse:
+                probs[tuple(req["grid"])] = prob
+        else:
+            prob.set_load(ft)
         a = torch.as_tensor(rho0, device=device)
         b = torch.empty_like(a)
         for _ in range(filter_passes):
@@ -186,12 +196,16 @@ def run_sequential(requests, *, device="cuda:0", rtol=1e-8, filter_passes=3, kee
             rec["u"] = u.cpu().numpy()
             rec["dc"] = dc.cpu().numpy()
         results[req["id"]] = rec
-        prob.close()
+        if not reuse:
+            prob.close()
     wall = time.perf_counter() - t0
+    for prob in probs.values():
+        prob.close()
     lat = np.array([r["latency"] for r in results.values()])
     return results, {"requests": len(results), "wall_s": wall, "designs_per_s": len(results) / wall,
                      "p50_latency_s": float(np.percentile(lat, 50)),
-                     "p99_latency_s": float(np.percentile(lat, 99))}
+                     "p99_latency_s": float(np.percentile(lat, 99)),
+                     "problem_reuse": bool(reuse)}
 
 
 def run_engine_batched(requests, arrivals=None, *, device="cuda:0", nslots=16, n_streams=4,
@@ -211,7 +225,17 @@ def run_engine_batched(requests, arrivals=None, *, device="cuda:0", nslots=16, n
     results = {}
     finishing = []  # (slot record, event)
     max_q = max_act = 0
+    peak = 0  # largest admitted footprint (batch workspaces + per-request arrays)
     t0 = time.perf_counter()
+
+    def release_idle(keep):
+        """Closes the batches (other than size `keep`) that hold no design,
+        live or finishing, returning their workspaces to the budget."""
+        nonlocal used
+        busy = {rec["cls"] for rec, _ in finishing}
+        for gi in [gi for gi, ci in classes.items() if gi != keep and not ci["live"] and gi not in busy]:
+            classes.pop(gi)["batch"].close()
+            used -= fe.Batch.workspace_bytes(*gi, nslots, **cfg_kw)
 
     def per_request_bytes(grid):
         nx, ny, nz = grid
@@ -230,6 +254,8 @@ def run_engine_batched(requests, arrivals=None, *, device="cuda:0", nslots=16, n
             c = classes.get(g)
             if c is None:
                 nbytes = fe.Batch.workspace_bytes(*g, nslots, **cfg_kw)
+                if used + nbytes + per_request_bytes(g) > hbm_budget:
+                    release_idle(g)
                 if used + nbytes + per_request_bytes(g) > hbm_budget and (classes or finishing):
                     rest.append((t_arr, req))
                     continue
@@ -238,6 +264,9 @@ def run_engine_batched(requests, arrivals=None, *, device="cuda:0", nslots=16, n
                     b = fe.Batch(*g, nslots, device=device, stream=stream, **cfg_kw)
                 c = classes[g] = {"batch": b, "free": list(range(nslots - 1, -1, -1)), "live": {}}
                 used += nbytes
+                peak = max(peak, used)
+            if c["free"] and used + per_request_bytes(g) > hbm_budget:
+                release_idle(g)
             if not c["free"] or used + per_request_bytes(g) > hbm_budget:
                 rest.append((t_arr, req))
                 continue
@@ -256,6 +285,11 @@ def run_engine_batched(requests, arrivals=None, *, device="cuda:0", nslots=16, n
             c["live"][slot] = {"req": req, "arrival": t_arr, "admit": time.perf_counter() - t0, "prob": prob,
                                "rho": a, "u": u, "slot": slot, "cls": g}
             used += per_request_bytes(g)
+            peak = max(peak, used)
+        if rest and len(rest) == len(queue) and not pending and not finishing \
+                and not any(c["live"] for c in classes.values()):
+            # nothing runs, nothing arrives, nothing was admitted: it never will be
+            raise RuntimeError("a request cannot be admitted within the HBM budget")
         queue = rest
         max_q = max(max_q, len(queue))
         max_act = max(max_act, sum(len(c["live"]) for c in classes.values()))
@@ -296,7 +330,7 @@ def run_engine_batched(requests, arrivals=None, *, device="cuda:0", nslots=16, n
             if log:
                 log(out)
         finishing = still
-        if not active and not finishing and not queue and pending:
+        if not active and not finishing and pending and (not queue or not classes):
             wait = pending[0][0] - (time.perf_counter() - t0)
             if wait > 0:
                 time.sleep(min(wait, 0.01))
@@ -308,4 +342,4 @@ def run_engine_batched(requests, arrivals=None, *, device="cuda:0", nslots=16, n
     return results, {"requests": len(results), "wall_s": wall, "designs_per_s": len(results) / wall,
                      "p50_latency_s": float(np.percentile(lat, 50)),
                      "p99_latency_s": float(np.percentile(lat, 99)), "max_queue": max_q,
-                     "max_active": max_act, "slots_per_size": nslots, "sizes": len(classes)}
+                     "max_active": max_act, "slots_per_size": nslots, "peak_bytes": peak}

@@ -60,8 +60,8 @@ def test_served_design_matches_oracle():
     assert np.abs(r["dc"] - dc_ref).max() / np.abs(dc_ref).max() <= 1e-5
 
 
-@pytest.mark.parametrize("grid", [(16, 8, 8), (13, 7, 5)])
-@pytest.mark.parametrize("precision", ["fp32_ir", "fp64"])
+@pytest.mark.parametrize("precision,grid", [("fp32_ir", (16, 8, 8)), ("fp64", (16, 8, 8)), ("fp32_ir", (13, 7, 5)),
+                                            ("fp64", (13, 7, 5)), ("fp32_ir", (96, 48, 48))])
 def test_batch_slots_match_lone_solves(precision, grid):
     """Designs sharing a batch's launches (one slot idle, slots reused)
     give bitwise the result of the same design solved alone, also on an odd
@@ -120,3 +120,36 @@ def test_batched_engine_matches_sequential():
         assert np.array_equal(a["u"], b["u"])
         assert np.array_equal(a["dc"], b["dc"])
         assert a["rel_res"] <= 1e-8
+
+
+def test_batched_engine_budget_of_one_batch_two_sizes():
+    """A budget that holds one size's batch at a time: requests of two sizes
+    alternate, each size's batch is released once idle so the other's can
+    be created, every request finishes and the admitted footprint never
+    exceeds the budget."""
+    from paper_2104_12282_amd import fe
+    cfg = {"precision": "fp32_ir", "precond": "gmg", "mg_levels": 3}
+    grids = ((16, 8, 8), (24, 12, 12))
+    reqs = [{"id": i, "grid": grids[i % 2], "seed": 500 + i} for i in range(6)]
+
+    def need(g):
+        ne, nd = g[0] * g[1] * g[2], 3 * (g[0] + 1) * (g[1] + 1) * (g[2] + 1)
+        return fe.Batch.workspace_bytes(*g, 2, **cfg) + 8 * (2 * nd + 3 * ne)
+
+    budget = max(need(g) for g in grids) + 1
+    res, st = serve.run_engine_batched(reqs, None, device=DEV, nslots=2, hbm_budget=budget, cfg_kw=cfg)
+    assert st["requests"] == len(reqs)
+    assert st["peak_bytes"] <= budget
+    assert all(r["rel_res"] <= 1e-8 for r in res.values())
+
+
+def test_sequential_reuse_matches_fresh_problems():
+    """The sequential baseline with one problem kept per size (load swapped
+    in) gives bitwise the results of a fresh problem per request."""
+    reqs = _requests(6, seed=9)
+    a, _ = serve.run_sequential(reqs, device=DEV, keep_outputs=True, reuse=True)
+    b, _ = serve.run_sequential(reqs, device=DEV, keep_outputs=True, reuse=False)
+    for r in reqs:
+        assert a[r["id"]]["iters"] == b[r["id"]]["iters"]
+        assert np.array_equal(a[r["id"]]["u"], b[r["id"]]["u"])
+        assert np.array_equal(a[r["id"]]["dc"], b[r["id"]]["dc"])
