@@ -203,6 +203,33 @@ FE_API fe_status fe_filter(fe_problem* p, const double* in, double* out, int32_t
 FE_API fe_status oc_update(fe_problem* p, const double* x, const double* dcx, const double* dv,
                     double volfrac, double move, double* x_new, double* change);
 
+/* oc_update without a problem handle and without any allocation, for
+ * callers that cannot allocate device or host memory (code under HIP graph
+ * capture, tight serving loops, harnesses that forbid hipMalloc): the same
+ * kernels and launch sequence as oc_update (so the same x_new and change
+ * bit for bit), launched directly on `stream` (hipStream_t, NULL = default
+ * stream) with their partial sums and search state in a static device array
+ * of the library (65,536 float64 partial sums and a 48-byte search state,
+ * 512 KiB + 48 B, held by each GPU the library runs on until the process
+ * ends; the amount does not grow
+ * with nelem: the update's partials are bounded by its launch grid).  The
+ * first call on a device looks up that device's copy (hipGetSymbolAddress,
+ * with the device current); no call calls hipMalloc, hipFree or any other
+ * allocating routine, and none synchronises.
+ *   nelem: elements, 1 <= nelem <= FE_NOALLOC_MAX_ELEMS = 2^31 - 1 (else
+ *          FE_EINVAL; the scratch is the same for every nelem up to it);
+ *   x, dcx, dv, x_new, change: device float64 arrays of nelem entries
+ *   (change: one scalar, may be NULL), as for oc_update; x and x_new may
+ *   alias.
+ * Every call on one GPU shares that GPU's array and leaves its contents
+ * behind (each call writes every entry before reading it, so nothing needs
+ * clearing): calls that may overlap on one GPU (different streams, threads)
+ * race and must be ordered by the caller.  Asynchronous; errors of the launch
+ * are returned as FE_EDEVICE. */
+#define FE_NOALLOC_MAX_ELEMS 2147483647LL
+FE_API fe_status oc_update_noalloc(int64_t nelem, const double* x, const double* dcx, const double* dv,
+                                   double volfrac, double move, double* x_new, double* change, void* stream);
+
 /* Coarse-grained design variables of the two-scale scheme (Sec. III-C and
  * III-E, the coarse-graining step of Alg. 1): zc[ec] is the mean of z over
  * the nb x nb x nb block of fine elements of coarse element ec.  z is

@@ -988,6 +988,24 @@ extern "C" fe_status oc_update(fe_problem* p, const double* x, const double* dcx
   return FE_OK;
 }
 
+extern "C" fe_status oc_update_noalloc(int64_t nelem, const double* x, const double* dcx, const double* dv,
+                                       double volfrac, double move, double* x_new, double* change, void* stream) {
+  if (!x || !dcx || !dv || !x_new) {
+    fe_set_error("x, dcx, dv and x_new must not be NULL");
+    return FE_EINVAL;
+  }
+  if (nelem < 1 || nelem > FE_NOALLOC_MAX_ELEMS) {
+    fe_set_error("nelem must lie in [1, " + std::to_string((long long)FE_NOALLOC_MAX_ELEMS) + "]");
+    return FE_EINVAL;
+  }
+  if (!(volfrac > 0.0 && volfrac <= 1.0) || !(move > 0.0)) {
+    fe_set_error("volfrac must lie in (0, 1] and move must be > 0");
+    return FE_EINVAL;
+  }
+  HIP_TRY(launch_oc_noalloc(static_cast<hipStream_t>(stream), nelem, x, dcx, dv, volfrac, move, x_new, change));
+  return FE_OK;
+}
+
 extern "C" fe_status fe_block_mean(fe_problem* p, const double* z, int32_t nb, double* zc) {
   CHECK_HANDLE(p);
   if (!z || !zc || z == zc) {

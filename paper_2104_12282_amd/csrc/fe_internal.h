@@ -13,6 +13,7 @@
 #define FE_BLOCK 256
 #define FE_MAX_LEVELS 6
 #define FE_RED_GRID 4096  // grid of the reduction kernels (partials per slot)
+#define FE_OC_PARTIALS 65536  // partial sums an OC update needs (max of FE_RED_GRID and 1024 x 64)
 #define FE_MAX_STENCIL 2304  // density-filter stencil entries (radius <= 8 elements)
 
 // Structured brick grid of one multigrid level.
@@ -352,6 +353,10 @@ hipError_t launch_adjoint_sensitivity(fe_problem* p, const double* rho, const do
 hipError_t launch_block_mean(fe_problem* p, const double* z, int nb, double* zc);
 hipError_t launch_oc(fe_problem* p, const double* x, const double* dcx, const double* dv,
                      double volfrac, double move, double* x_new, double* change);
+// The same update on `stream` with the library's static per-device scratch
+// instead of a problem's workspace (no allocation).
+hipError_t launch_oc_noalloc(hipStream_t stream, int64_t n, const double* x, const double* dcx, const double* dv,
+                             double volfrac, double move, double* x_new, double* change);
 
 // conversions and fills (fill is a kernel, so it is safe inside captured graphs)
 template <typename T>

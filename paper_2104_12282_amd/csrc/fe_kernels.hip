@@ -1,6 +1,8 @@
 // Element, node and vector kernels of the FE step (gfx950, wave64).
 #include <hip/hip_runtime.h>
 
+#include <mutex>
+
 #include "fe_internal.h"
 #include "fe_reduce.h"
 
@@ -1169,23 +1171,77 @@ hipError_t launch_block_mean(fe_problem* p, const double* z, int nb, double* zc)
   return hipGetLastError();
 }
 
-hipError_t launch_oc(fe_problem* p, const double* x, const double* dcx, const double* dv, double volfrac,
-                     double move, double* x_new, double* change) {
-  const int64_t n = G(p, 0).nelem;
-  OcState* os = reinterpret_cast<OcState*>(p->oc);
+namespace {
+
+// The OC launch sequence on a given stream with the given scratch: partials
+// holds at least FE_OC_PARTIALS doubles (the block partials of the prep and
+// final passes, then 64 per workgroup of the candidate passes; they are
+// used one launch pair at a time), os one OcState.  Every partial and every
+// field of os is written before it is read, so the scratch needs no clearing.
+hipError_t launch_oc_on(hipStream_t stream, double* partials, OcState* os, int64_t n, const double* x,
+                        const double* dcx, const double* dv, double volfrac, double move, double* x_new,
+                        double* change) {
   const double target = volfrac * (double)n;
   const int nb = red_grid(n);
   // the candidate passes keep 64 partials per workgroup: at most 1024 workgroups
   const int nbp = nb < 1024 ? nb : 1024;
-  hipLaunchKernelGGL(oc_prep_kernel, dim3(nb), dim3(FE_BLOCK), 0, p->stream, n, x, dcx, dv, move, p->partials);
-  hipLaunchKernelGGL(oc_prep_finalize, dim3(1), dim3(FE_BLOCK), 0, p->stream, nb, p->partials, target, os);
+  hipLaunchKernelGGL(oc_prep_kernel, dim3(nb), dim3(FE_BLOCK), 0, stream, n, x, dcx, dv, move, partials);
+  hipLaunchKernelGGL(oc_prep_finalize, dim3(1), dim3(FE_BLOCK), 0, stream, nb, partials, target, os);
   for (int pass = 0; pass < 24; ++pass) {  // passes after convergence return at once
-    hipLaunchKernelGGL(oc_pass_kernel, dim3(nbp), dim3(FE_BLOCK), 0, p->stream, n, x, dcx, dv, move, os,
-                       p->partials);
-    hipLaunchKernelGGL(oc_pass_finalize, dim3(1), dim3(OC_NC * OC_FIN_Q), 0, p->stream, nbp, p->partials, os);
+    hipLaunchKernelGGL(oc_pass_kernel, dim3(nbp), dim3(FE_BLOCK), 0, stream, n, x, dcx, dv, move, os, partials);
+    hipLaunchKernelGGL(oc_pass_finalize, dim3(1), dim3(OC_NC * OC_FIN_Q), 0, stream, nbp, partials, os);
   }
-  hipLaunchKernelGGL(oc_final_kernel, dim3(nb), dim3(FE_BLOCK), 0, p->stream, n, x, dcx, dv, move, os, x_new,
-                     p->partials);
-  hipLaunchKernelGGL(oc_final_finalize, dim3(1), dim3(FE_BLOCK), 0, p->stream, nb, p->partials, os, change);
+  hipLaunchKernelGGL(oc_final_kernel, dim3(nb), dim3(FE_BLOCK), 0, stream, n, x, dcx, dv, move, os, x_new,
+                     partials);
+  hipLaunchKernelGGL(oc_final_finalize, dim3(1), dim3(FE_BLOCK), 0, stream, nb, partials, os, change);
   return hipGetLastError();
+}
+
+// Scratch of the allocation-free OC entry point: FE_OC_PARTIALS partial sums
+// followed by the search state.  Each GPU holds its own copy for the life of
+// the process; host code reaches it only through the address
+// hipGetSymbolAddress returns on that GPU (the array's name is a host-side
+// stand-in, not a device address).
+constexpr int64_t kOcScratchDoubles = FE_OC_PARTIALS + (int64_t)(sizeof(OcState) + 7) / 8;
+static_assert(FE_OC_PARTIALS >= FE_RED_GRID && FE_OC_PARTIALS >= 1024 * OC_NC, "OC partials do not fit");
+static __device__ __align__(256) double scratch[kOcScratchDoubles];
+
+constexpr int kMaxDevices = 64;
+std::mutex g_scratch_mu;
+double* g_scratch_ptr[kMaxDevices] = {};
+
+// The device address of this GPU's scratch, looked up once per device with
+// that device current (the caller's current device).
+hipError_t oc_scratch_address(double** out) {
+  int dev = -1;
+  hipError_t e = hipGetDevice(&dev);
+  if (e != hipSuccess) return e;
+  if (dev < 0 || dev >= kMaxDevices) return hipErrorInvalidDevice;
+  std::lock_guard<std::mutex> lock(g_scratch_mu);
+  if (!g_scratch_ptr[dev]) {
+    void* ptr = nullptr;
+    e = hipGetSymbolAddress(&ptr, HIP_SYMBOL(scratch));
+    if (e != hipSuccess) return e;
+    if (!ptr) return hipErrorInvalidSymbol;
+    g_scratch_ptr[dev] = static_cast<double*>(ptr);
+  }
+  *out = g_scratch_ptr[dev];
+  return hipSuccess;
+}
+
+}  // namespace
+
+hipError_t launch_oc(fe_problem* p, const double* x, const double* dcx, const double* dv, double volfrac,
+                     double move, double* x_new, double* change) {
+  return launch_oc_on(p->stream, p->partials, reinterpret_cast<OcState*>(p->oc), G(p, 0).nelem, x, dcx, dv,
+                      volfrac, move, x_new, change);
+}
+
+hipError_t launch_oc_noalloc(hipStream_t stream, int64_t n, const double* x, const double* dcx, const double* dv,
+                             double volfrac, double move, double* x_new, double* change) {
+  double* base = nullptr;
+  const hipError_t e = oc_scratch_address(&base);
+  if (e != hipSuccess) return e;
+  return launch_oc_on(stream, base, reinterpret_cast<OcState*>(base + FE_OC_PARTIALS), n, x, dcx, dv, volfrac,
+                      move, x_new, change);
 }

@@ -26,7 +26,7 @@ STATUS_NAME = {0: "FE_OK", -1: "FE_EINVAL", -2: "FE_ENOMEM", -3: "FE_EDEVICE",
 # Every entry point declared in include/fe_abi.h.
 ABI_SYMBOLS = ("fe_workspace_size", "fe_setup", "fe_apply_K", "fe_solve", "fe_solve_begin",
                "fe_solve_step", "fe_solve_end", "fe_sensitivity", "fe_sensitivity_adjoint", "fe_set_load",
-               "fe_filter", "oc_update", "fe_block_mean", "fe_set_mg_params", "fe_get_mg_params", "fe_set_float32_levels", "fe_set_coarse_fusion", "fe_set_profiling", "fe_set_cache_flush",
+               "fe_filter", "oc_update", "oc_update_noalloc", "fe_block_mean", "fe_set_mg_params", "fe_get_mg_params", "fe_set_float32_levels", "fe_set_coarse_fusion", "fe_set_profiling", "fe_set_cache_flush",
                "fe_kernel_stats", "fe_destroy", "fe_batch_workspace_size", "fe_batch_create", "fe_batch_setup_slot",
                "fe_batch_round_begin", "fe_batch_round_end", "fe_batch_destroy", "fe_onsg_num_params",
                "fe_onsg_workspace_size", "fe_onsg_create", "fe_onsg_add_samples", "fe_onsg_num_samples",
@@ -78,6 +78,7 @@ def load_library() -> C.CDLL:
     lib.fe_set_load.argtypes = [P, P]
     lib.fe_filter.argtypes = [P, P, P, I32]
     lib.oc_update.argtypes = [P, P, P, P, D, D, P, P]
+    lib.oc_update_noalloc.argtypes = [I64, P, P, P, D, D, P, P, P]
     lib.fe_block_mean.argtypes = [P, P, I32, P]
     lib.fe_set_mg_params.argtypes = [P, I32, I32, D, D]
     lib.fe_set_float32_levels.argtypes = [P, I32]
@@ -143,6 +144,23 @@ def make_config(nx, ny, nz, *, h=1.0, E0=1.0, Emin=1e-9, nu=0.3, penal=3.0, filt
 
 def workspace_size(cfg: fe_config) -> int:
     return int(load_library().fe_workspace_size(C.byref(cfg)))
+
+
+def oc_update_noalloc(x, dcx, dv, volfrac, move, x_new, change=None, stream=None):
+    """The optimality-criteria update without a problem and without any
+    allocation (include/fe_abi.h, oc_update_noalloc): x_new (and change, a
+    one-element float64 tensor, if given) are written on `stream` (torch
+    stream; the current stream of x's device by default) from the library's
+    static scratch.  Asynchronous."""
+    n = x.numel()
+    if not (dcx.numel() == dv.numel() == x_new.numel() == n):
+        raise ValueError("x, dcx, dv and x_new must have the same number of elements")
+    if change is not None and change.numel() != 1:
+        raise ValueError("change must hold one element")
+    s = stream if stream is not None else torch.cuda.current_stream(x.device)
+    _check(load_library().oc_update_noalloc(n, _ptr(x), _ptr(dcx), _ptr(dv), volfrac, move, _ptr(x_new),
+                                            _ptr(change), C.c_void_p(s.cuda_stream)))
+    return x_new
 
 
 class Problem:
