@@ -45,6 +45,9 @@ def parse():
                          "0: all, the finest level's smoothing included; the number of levels: none)")
     ap.add_argument("--mg-coarse-ratio", type=float, default=0.0,
                     help="coarsest-level Chebyshev interval ratio (0: the library's default)")
+    ap.add_argument("--coarse-form", type=int, default=0,
+                    help="coarsest-level Chebyshev launch form (0: the library's automatic choice; 3: pairs of "
+                         "steps on 3D tiles, 2: pairs on z-marching tiles, 1: one step per launch)")
     ap.add_argument("--rtol", type=float, default=1e-6)
     ap.add_argument("--volfrac", type=float, default=0.12)
     ap.add_argument("--move", type=float, default=0.2)
@@ -127,6 +130,8 @@ def apply_mg(prob, args):
         return None
     if args.f32_from >= 0:
         prob.set_float32_levels(min(args.f32_from, prob.cfg.mg_levels))
+    if args.coarse_form:
+        prob.set_coarse_fusion(args.coarse_form)
     cur = prob.mg_params()
     prob.set_mg_params(nu=args.mg_nu, coarse_sweeps=args.mg_coarse or cur["coarse_sweeps"], omega=cur["omega"],
                        coarse_ratio=args.mg_coarse_ratio or cur["coarse_ratio"])
@@ -149,16 +154,25 @@ def coarse_solve_record(nx, ny, nz, args, degree):
     # d_k, r_k, acc read and r, acc, d_{k+2} written (3 dofs per node), moduli,
     # inverse diagonal, fixed-dof mask: each array once
     nbytes = vb * (6 * 3 * nnode + cx * cy * cz + nnode) + nnode
-    out = {"kernel": "cheb2_kernel<" + ("double" if wide else "float")
-                     + ">: two coarsest-level Chebyshev steps per launch",
+    form = args.coarse_form
+    if form == 0:  # the library's automatic choice: 3D tiles while they need at most one workgroup per CU
+        import torch
+        cus = torch.cuda.get_device_properties(0).multi_processor_count
+        cols = ((cx + 4) // 4) * ((cy + 4) // 4)
+        form = 3 if cols * ((cz + 4) // 4) <= cus else 4 if not wide and cols * ((cz + 8) // 8) <= cus else 2
+    oz = 8 if form == 4 and not wide else 4
+    name = f"cheb3d_kernel<{'double' if wide else 'float'}, {oz}>" if form >= 3 else \
+        f"cheb2_kernel<{'double' if wide else 'float'}>"
+    shape = f"3D tiles of 4 x 4 x {oz} nodes" if form >= 3 else "z-marching tiles"
+    out = {"kernel": f"{name}: two coarsest-level Chebyshev steps per launch on {shape}",
            "coarse_grid": [cx, cy, cz], "launches_per_vcycle": (degree + 1) // 2,
            "algorithmic_bytes_per_launch": nbytes, "bound": "latency",
            "note": "a few MB per launch on a 22k-element grid: the launch is bound by its chain of "
-                   "dependent memory round trips and march steps, not by HBM bandwidth"}
+                   "dependent memory round trips, LDS phases and barriers, not by HBM bandwidth"}
     rec = profile_record(f"{nx}x{ny}x{nz}")
     if rec:
         for t in rec.get("time_shares", []):
-            if "cheb2_kernel" in t["kernel"] and t.get("work_avg_us"):
+            if name.split("<")[0] in t["kernel"] and t.get("work_avg_us"):
                 out["rocprofv3_avg_kernel_us"] = t["work_avg_us"]
                 out["rocprofv3_share_of_gpu_time"] = t["share"]
                 out["achieved_GBs"] = nbytes / (t["work_avg_us"] * 1e-6) / 1e9
@@ -791,7 +805,7 @@ def run_loop(fe, synth, torch, nx, ny, nz, precision, args, steps, warmup, profi
     dv = prob.filter(torch.ones_like(x), transpose=True)
     comp = torch.zeros(1, dtype=torch.float64, device=dev)
     change = torch.zeros(1, dtype=torch.float64, device=dev)
-    rec = {"iters": [], "compliance": [], "mg": rec_mg}
+    rec = {"iters": [], "outer": [], "compliance": [], "mg": rec_mg}
 
     def reset():
         x.fill_(args.volfrac)
@@ -804,6 +818,7 @@ def run_loop(fe, synth, torch, nx, ny, nz, precision, args, steps, warmup, profi
         prob.filter(dc, transpose=True, out=dcx)
         prob.oc_update(x, dcx, dv, args.volfrac, args.move, out=x, change_out=change)
         rec["iters"].append(info["iters"])
+        rec["outer"].append(info["outer_iters"])
         rec["compliance"].append(info["compliance"])
         return info
 
@@ -814,6 +829,7 @@ def run_loop(fe, synth, torch, nx, ny, nz, precision, args, steps, warmup, profi
               file=sys.stderr, flush=True)
     reset()
     rec["iters"].clear()
+    rec["outer"].clear()
     rec["compliance"].clear()
     torch.cuda.synchronize()
     prob.kernel_stats(reset=True)
@@ -911,6 +927,7 @@ def main():
                    "rtol": args.rtol, "volfrac": args.volfrac, "filter_r": 1.5, "move": args.move,
                    "cg_iters_per_solve": float(np.mean(rec["iters"])),
                    "cg_iters_max": int(np.max(rec["iters"])),
+                   "refinement_steps_per_solve": float(np.mean(rec["outer"])),
                    "compliance_first": rec["compliance"][0], "compliance_last": rec["compliance"][-1]},
         "roofline": {"bound": "hbm", "achieved": achieved, "peak": HBM_PEAK_GBS, "unit": "GB/s",
                      "frac": achieved / HBM_PEAK_GBS,
@@ -952,6 +969,7 @@ def main():
         out["alt"] = {"precision": args.alt_precision, "value": args.steps / dt2,
                       "ms_per_step": 1e3 * dt2 / args.steps,
                       "cg_iters_per_solve": float(np.mean(rec2["iters"])),
+                      "refinement_steps_per_solve": float(np.mean(rec2["outer"])),
                       "compliance_max_rel_diff": float(np.max(np.abs(c2 - c1) / np.abs(c1)))}
     if args.precision == "fp64" and args.precond == "gmg" and args.alt_precision != "none":
         # context: the same loop with the preconditioner in float64 throughout

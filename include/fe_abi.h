@@ -280,12 +280,20 @@ FE_API fe_status fe_set_float32_levels(fe_problem* p, int32_t first_level);
 FE_API fe_status fe_get_mg_params(const fe_problem* p, int32_t* nu, int32_t* coarse_sweeps, double* omega,
                            double* coarse_ratio);
 
-/* Launches of the coarsest-level Chebyshev solve: steps_per_launch = 2
- * (default) runs pairs of steps in one launch, each workgroup recomputing
- * the ring of first-step values its second step needs (the solve on the
- * small coarse grid is bound by launch latency, not by arithmetic); 1 runs
- * one launch per step.  Both give bitwise the same result.  FE_EINVAL for
- * other values and for batch slots. */
+/* Launches of the coarsest-level Chebyshev solve (the solve on the small
+ * coarse grid is bound by launch and memory latency, not by arithmetic):
+ *   3, 4: pairs of steps in one launch on 3D tiles (a workgroup owns 4 x 4 x 4
+ *     nodes (3) or 4 x 4 x 8 (4; float32 levels only, float64 levels take
+ *     4 x 4 x 4), works on all their levels at once and recomputes the
+ *     two-node halo its second step needs);
+ *   2: pairs of steps in one launch on z-marching tiles (each workgroup
+ *     recomputing the ring of first-step values its second step needs);
+ *   1: one launch per step;
+ *   0 (default): 3 while the launch (every batch slot included) has at most
+ *     one workgroup per compute unit, else 4 while that holds for it, else 2.
+ * 1 and 2 give bitwise the same result; 3 and 4 the same polynomial with
+ * their node sums rounded in another order (each bitwise reproducible).
+ * FE_EINVAL for other values and for batch slots. */
 FE_API fe_status fe_set_coarse_fusion(fe_problem* p, int32_t steps_per_launch);
 
 /* Timing of the dominant kernel (matrix-free K*u on the finest grid): with

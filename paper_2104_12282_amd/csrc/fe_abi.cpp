@@ -488,8 +488,8 @@ fe_status advance(fe_problem* p) {
       }
       sc.prev_rel = rel;
       // inner tolerance: aim a little past the target, within float32 reach
-      double itol = 0.3 * sc.rtol / rel;
-      if (itol < 1e-5) itol = 1e-5;
+      double itol = FE_IR_FACTOR * sc.rtol / rel;
+      if (itol < FE_IR_FLOOR) itol = FE_IR_FLOOR;
       if (itol > 1e-1) itol = 1e-1;
       HIP_TRY(launch_to32_scaled(p, p->r64, p->r32, p->scal + 2 * SLOT_RR));
       HIP_TRY(launch_fill<float>(p, p->x32, p->L[0].g.ndof, 0.0f));
@@ -1079,8 +1079,8 @@ extern "C" fe_status fe_set_coarse_fusion(fe_problem* p, int32_t steps_per_launc
     fe_set_error("batch slots share the batch's multigrid parameters (the library defaults)");
     return FE_EINVAL;
   }
-  if (steps_per_launch != 1 && steps_per_launch != 2) {
-    fe_set_error("steps_per_launch must be 1 or 2");
+  if (steps_per_launch < 0 || steps_per_launch > 4) {
+    fe_set_error("the coarse launch form must be 0, 1, 2, 3 or 4");
     return FE_EINVAL;
   }
   p->cheb_per_launch = steps_per_launch;

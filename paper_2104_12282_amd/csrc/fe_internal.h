@@ -14,6 +14,15 @@
 #define FE_MAX_LEVELS 6
 #define FE_RED_GRID 4096  // grid of the reduction kernels (partials per slot)
 #define FE_OC_PARTIALS 65536  // partial sums an OC update needs (max of FE_RED_GRID and 1024 x 64)
+#ifndef FE_IR_FACTOR
+#define FE_IR_FACTOR 0.3  // refinement: the inner solve aims at FE_IR_FACTOR x the outer target
+#endif
+#ifndef FE_IR_FLOOR
+#define FE_IR_FLOOR 1e-5  // refinement: tightest relative tolerance asked of a float32 inner solve
+#endif
+#ifndef FE_CHEB_FORM
+#define FE_CHEB_FORM 0  // default launch form of the coarsest-level Chebyshev steps (0: automatic)
+#endif
 #define FE_MAX_STENCIL 2304  // density-filter stencil entries (radius <= 8 elements)
 
 // Structured brick grid of one multigrid level.
@@ -188,7 +197,9 @@ struct fe_problem {
   double mg_omega = 0.35;      // Jacobi damping: below 2 / lambda_max(D^-1 Ke) = 2 / 5.32
   double lam_max = 0.0;        // lambda_max(diag(Ke)^-1 Ke): bounds that of D^-1 K on every level
   double cheb_ratio = 5000.0;  // coarse Chebyshev interval [lam_max / ratio, lam_max]
-  int cheb_per_launch = 2;     // coarse Chebyshev steps per launch (2: pairs fused, 1: one each)
+  int cheb_per_launch = FE_CHEB_FORM;  // coarse Chebyshev launches: 3 / 4 pairs of steps on 3D tiles of
+                                      // 4 x 4 x 4 / 4 x 4 x 8 nodes, 2 pairs on z-marching tiles, 1 one
+                                      // step each, 0 chosen per launch
   int f32_from = 1 << 30;      // float64 solves run multigrid levels >= f32_from in float32
 
   KStats kst;

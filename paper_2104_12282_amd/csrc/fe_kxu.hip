@@ -52,6 +52,11 @@ struct WK {
   T A, B, G, C, D, F, H, J;
 };
 
+// Corner offsets of the brick in the fixed local order 000 100 110 010 001 101 111 011.
+constexpr int kCornerX[8] = {0, 1, 1, 0, 0, 1, 1, 0};
+constexpr int kCornerY[8] = {0, 0, 1, 1, 0, 0, 1, 1};
+constexpr int kCornerZ[8] = {0, 0, 0, 0, 1, 1, 1, 1};
+
 template <typename T>
 __device__ inline void bf(T& a, T& b) {
   const T s = a + b, d = a - b;
@@ -1034,6 +1039,256 @@ __global__ void __launch_bounds__(2 * TX * TY) cheb2_kernel(Grid g, TileMap tm, 
 }
 
 // ---------------------------------------------------------------------------
+// Two coarsest-level Chebyshev steps in one launch on 3D tiles.
+//
+// The z-march above finishes a level per march step, so a workgroup's time is
+// the length of its march; on the small coarsest grid (a few dozen levels in
+// all) that chain, not arithmetic or bytes, sets the launch time.  Here a
+// workgroup owns a 4 x 4 x OZ block of nodes (OZ = 4 or 8) and works on all
+// of its levels at once.  It loads d_k, r_k, D^-1 and the masks of the
+// 8 x 8 x (OZ + 4) nodes around the block (two-node halo; off the mesh: zero,
+// every dof fixed) and the moduli of the 7 x 7 x (OZ + 3) bricks between them
+// into LDS; then
+//   step k:     every brick of the box computes its 24 products E_e Ke d_e
+//               (one thread per brick, exact factorised operator) into LDS;
+//               every node one node inside the halo sums the products of its
+//               8 bricks (local corner order 0..7, a fixed order) and forms
+//               r_{k+1}, d_{k+1};
+//   step k + 1: the same on the 5 x 5 x (OZ + 1) bricks around the owned
+//               block, whose corners all lie one node inside the halo;
+// and the owned nodes store r_{k+2}, d_{k+2} and the iterate
+// acc + d_k + d_{k+1}.  Four barriers per launch; no atomics, so the result is
+// bitwise reproducible (its rounding differs from the march kernels', whose
+// node sums run in another order).  Workgroup b takes tile (b % 8) * per +
+// b / 8, so each XCD works on one contiguous run of tiles.
+constexpr int C3_OWN = 4;  // owned nodes along x and y
+constexpr int C3_IN = 8;   // input box nodes along x and y (two-node halo)
+
+template <int OZ>
+struct C3 {
+  static constexpr int IZ = OZ + 4;                  // input box nodes along z
+  static constexpr int NIN = C3_IN * C3_IN * IZ;     // input box nodes
+  static constexpr int B1X = C3_IN - 1, B1Z = IZ - 1;
+  static constexpr int NB1 = B1X * B1X * B1Z;        // step-k bricks
+  static constexpr int B2X = C3_OWN + 1, B2Z = OZ + 1;
+  static constexpr int NB2 = B2X * B2X * B2Z;        // step-(k+1) bricks
+  static constexpr int R1X = C3_OWN + 2, R1Z = OZ + 2;
+  static constexpr int NR1 = R1X * R1X * R1Z;        // nodes of step k kept
+  static constexpr int NOWN = C3_OWN * C3_OWN * OZ;  // owned nodes
+  static constexpr int THREADS = (NB1 + 63) / 64 * 64;
+};
+
+// E_e Ke u_e of one brick from its corner values u (local corner order),
+// in the same factorised form as brick_layer.
+template <typename T>
+__device__ inline void brick_full(T (&u)[3][8], T Ee, const WK<T>& wk, T (&yv)[3][8]) {
+#pragma unroll
+  for (int c = 0; c < 3; ++c) walsh8(u[c]);
+  WK<T> k = wk;
+  k.A *= Ee; k.B *= Ee; k.G *= Ee; k.C *= Ee; k.D *= Ee; k.F *= Ee; k.H *= Ee; k.J *= Ee;
+  T w[3][8];
+  apply_S(k, u, w);
+#pragma unroll
+  for (int c = 0; c < 3; ++c) {
+    T lo[4], up[4];
+#pragma unroll
+    for (int i = 0; i < 4; ++i) {
+      lo[i] = w[c][i] + w[c][i + 4];
+      up[i] = w[c][i] - w[c][i + 4];
+    }
+    face4(lo);
+    face4(up);
+#pragma unroll
+    for (int i = 0; i < 4; ++i) {
+      yv[c][i] = lo[i];
+      yv[c][i + 4] = up[i];
+    }
+  }
+}
+
+// Brick products of a box of BX x BX x BZ bricks whose lowest brick sits at
+// local node (lo, lo, lo) of the input box: thread e computes brick e.
+template <typename T, int OZ, int BX, int BZ>
+__device__ inline void c3_bricks(const T (*sd)[C3<OZ>::NIN], const T* sE, int lo, const WK<T>& wk,
+                                 T (*sbo)[C3<OZ>::NB1]) {
+  const int e = threadIdx.x;
+  if (e >= BX * BX * BZ) return;
+  const int bi = lo + e % BX, bj = lo + (e / BX) % BX, bk = lo + e / (BX * BX);
+  const int n0 = bi + C3_IN * (bj + C3_IN * bk);
+  T u[3][8];
+#pragma unroll
+  for (int a = 0; a < 8; ++a) {
+    const int n = n0 + kCornerX[a] + C3_IN * (kCornerY[a] + C3_IN * kCornerZ[a]);
+#pragma unroll
+    for (int c = 0; c < 3; ++c) u[c][a] = sd[c][n];
+  }
+  T yv[3][8];
+  brick_full(u, sE[bi + C3<OZ>::B1X * (bj + C3<OZ>::B1X * bk)], wk, yv);
+#pragma unroll
+  for (int c = 0; c < 3; ++c)
+#pragma unroll
+    for (int a = 0; a < 8; ++a) sbo[c * 8 + a][e] = yv[c][a];
+}
+
+// (K d)_c at local node (li, lj, lk) from the brick products of a box of
+// BX x BX x BZ bricks starting at local node lo: the 8 bricks holding the
+// node, in local corner order.
+template <typename T, int OZ, int BX>
+__device__ inline T c3_node_sum(const T (*sbo)[C3<OZ>::NB1], int c, int li, int lj, int lk, int lo) {
+  T v = T(0);
+#pragma unroll
+  for (int a = 0; a < 8; ++a) {
+    const int e = (li - lo - kCornerX[a]) + BX * ((lj - lo - kCornerY[a]) + BX * (lk - lo - kCornerZ[a]));
+    v = v + sbo[c * 8 + a][e];
+  }
+  return v;
+}
+
+template <typename T, int OZ>
+__global__ void __launch_bounds__(C3<OZ>::THREADS) cheb3d_kernel(Grid g, int gx, int gy, int nblk, int per,
+                                                                const T* __restrict__ dk,
+                                                                const T* __restrict__ E,
+                                                                const uint8_t* __restrict__ nmask, WK<T> wk,
+                                                                const T* __restrict__ invd,
+                                                                const T* __restrict__ rin, T* __restrict__ rout,
+                                                                T* __restrict__ acc, T* __restrict__ y,
+                                                                Cheb2<T> cf, CgState* st, int64_t wsh) {
+  using Q = C3<OZ>;
+  static_assert(Q::NIN <= 2 * Q::THREADS && Q::NR1 <= Q::THREADS && Q::NOWN <= Q::THREADS,
+                "one or two passes cover every phase");
+  static_assert(sizeof(T) * (10 * Q::NIN + 25 * Q::NB1) + Q::NIN <= 160 * 1024, "LDS of one workgroup");
+  if (wsh) {  // batched launch: this workgroup's problem
+    const int64_t o = batch_offset(wsh);
+    dk = wshift(dk, o);
+    E = wshift(E, o);
+    nmask = wshift(nmask, o);
+    invd = wshift(invd, o);
+    rin = wshift(rin, o);
+    rout = wshift(rout, o);
+    acc = wshift(acc, o);
+    y = wshift(y, o);
+    st = wshift(st, o);
+  }
+  const int tile = (int)(blockIdx.x % 8) * per + (int)(blockIdx.x / 8);
+  if (tile >= nblk) return;
+  __shared__ T sD0[3][Q::NIN], sD1[3][Q::NIN], sR[3][Q::NIN], sInv[Q::NIN], sE[Q::NB1];
+  __shared__ T sBO[24][Q::NB1];
+  __shared__ uint8_t sM[Q::NIN];
+  const int tx = tile % gx, t1 = tile / gx, ty = t1 % gy, tz = t1 / gy;
+  const int I0 = tx * C3_OWN - 2, J0 = ty * C3_OWN - 2, K0 = tz * OZ - 2;
+  const int64_t sx = g.nx + 1, sxy = sx * (g.ny + 1);
+  const int tid = threadIdx.x;
+  // the iterate at the owned node this thread finishes (threads 0 .. NOWN - 1)
+  int oi = 0, oj = 0, ok = 0;
+  bool own_in = false;
+  int64_t own_node = 0;
+  T a0[3] = {T(0), T(0), T(0)};
+  if (tid < Q::NOWN) {
+    oi = 2 + tid % C3_OWN;
+    oj = 2 + (tid / C3_OWN) % C3_OWN;
+    ok = 2 + tid / (C3_OWN * C3_OWN);
+    const int i = I0 + oi, j = J0 + oj, k = K0 + ok;
+    own_in = i <= g.nx && j <= g.ny && k <= g.nz;  // owned nodes are never below the mesh
+    own_node = i + sx * j + sxy * k;
+    if (own_in && !cf.first) {
+#pragma unroll
+      for (int c = 0; c < 3; ++c) a0[c] = acc[3 * own_node + c];
+    }
+  }
+  // every load of the launch is issued before the first wait: node tid and
+  // node tid + THREADS of the box, brick tid's modulus (one memory round
+  // trip for the whole prologue)
+  struct NodeIn {
+    T d[3], r[3], iv;
+    uint8_t m;
+  };
+  auto load_node = [&](int n, NodeIn& v) {
+    const int i = I0 + n % C3_IN, j = J0 + (n / C3_IN) % C3_IN, k = K0 + n / (C3_IN * C3_IN);
+    const bool in = n < Q::NIN && i >= 0 && i <= g.nx && j >= 0 && j <= g.ny && k >= 0 && k <= g.nz;
+#pragma unroll
+    for (int c = 0; c < 3; ++c) v.d[c] = v.r[c] = T(0);
+    v.iv = T(0);
+    v.m = 7;
+    if (in) {
+      const int64_t node = i + sx * j + sxy * k;
+#pragma unroll
+      for (int c = 0; c < 3; ++c) {
+        v.d[c] = dk[3 * node + c];
+        v.r[c] = rin[3 * node + c];
+      }
+      v.iv = invd[node];
+      v.m = nmask[node];
+    }
+  };
+  auto store_node = [&](int n, const NodeIn& v) {
+#pragma unroll
+    for (int c = 0; c < 3; ++c) {
+      sD0[c][n] = v.d[c];
+      sR[c][n] = v.r[c];
+    }
+    sInv[n] = v.iv;
+    sM[n] = v.m;
+  };
+  NodeIn v0, v1;
+  load_node(tid, v0);
+  load_node(tid + Q::THREADS, v1);
+  T Eb = T(0);
+  {
+    const int i = I0 + tid % Q::B1X, j = J0 + (tid / Q::B1X) % Q::B1X, k = K0 + tid / (Q::B1X * Q::B1X);
+    if (tid < Q::NB1 && i >= 0 && i < g.nx && j >= 0 && j < g.ny && k >= 0 && k < g.nz)
+      Eb = E[i + (int64_t)g.nx * (j + (int64_t)g.ny * k)];
+  }
+  // the CG stop flag is read while the loads are in flight
+  if (st && st->done) return;
+  if (tid < Q::NIN) store_node(tid, v0);
+  if (tid + Q::THREADS < Q::NIN) store_node(tid + Q::THREADS, v1);
+  if (tid < Q::NB1) sE[tid] = Eb;
+  __syncthreads();
+  // step k on the bricks of the box
+  c3_bricks<T, OZ, Q::B1X, Q::B1Z>(sD0, sE, 0, wk, sBO);
+  __syncthreads();
+  // r_{k+1}, d_{k+1} on the nodes one inside the halo
+  if (tid < Q::NR1) {
+    const int li = 1 + tid % Q::R1X, lj = 1 + (tid / Q::R1X) % Q::R1X, lk = 1 + tid / (Q::R1X * Q::R1X);
+    const int n = li + C3_IN * (lj + C3_IN * lk);
+    const uint8_t m = sM[n];
+#pragma unroll
+    for (int c = 0; c < 3; ++c) {
+      const bool fx = (m >> c) & 1;
+      T v = c3_node_sum<T, OZ, Q::B1X>(sBO, c, li, lj, lk, 0);
+      if (fx) v = T(0);
+      T rn, dn;
+      cheb_dof(fx, sR[c][n], v, sD0[c][n], sInv[n], cf.c1a, cf.c2a, rn, dn);
+      sR[c][n] = rn;
+      sD1[c][n] = dn;
+    }
+  }
+  __syncthreads();
+  // step k + 1 on the bricks around the owned block
+  c3_bricks<T, OZ, Q::B2X, Q::B2Z>(sD1, sE, 1, wk, sBO);
+  __syncthreads();
+  if (tid < Q::NOWN && own_in) {
+    const int n = oi + C3_IN * (oj + C3_IN * ok);
+    const uint8_t m = sM[n];
+    T rn[3], dn[3], an[3];
+#pragma unroll
+    for (int c = 0; c < 3; ++c) {
+      const bool fx = (m >> c) & 1;
+      T v = c3_node_sum<T, OZ, Q::B2X>(sBO, c, oi, oj, ok, 1);
+      if (fx) v = T(0);
+      cheb_dof(fx, sR[c][n], v, sD1[c][n], sInv[n], cf.c1b, cf.c2b, rn[c], dn[c]);
+      an[c] = (cf.first ? sD0[c][n] : a0[c] + sD0[c][n]) + sD1[c][n];
+    }
+#pragma unroll
+    for (int c = 0; c < 3; ++c) {
+      rout[3 * own_node + c] = rn[c];
+      acc[3 * own_node + c] = an[c];
+      y[3 * own_node + c] = dn[c];
+    }
+  }
+}
+
+// ---------------------------------------------------------------------------
 // The same operator with the brick contraction Ke u_e on bf16 matrix cores
 // (v_mfma_f32_16x16x32_bf16, float32 accumulation), float32 vectors.
 //
@@ -1270,6 +1525,22 @@ WK<T> scaled_wk(const WalshK& w, double h) {
 
 // Resident workgroups per compute unit of a kernel on the current device
 // (cached per device and kernel).
+// Compute units of the current device (cached per device).
+static int device_cus() {
+  static std::mutex mu;
+  static std::map<int, int> cache;
+  int dev = 0;
+  if (hipGetDevice(&dev) != hipSuccess) dev = 0;
+  std::lock_guard<std::mutex> lk(mu);
+  auto it = cache.find(dev);
+  if (it != cache.end()) return it->second;
+  int cus = 0;
+  if (hipDeviceGetAttribute(&cus, hipDeviceAttributeMultiprocessorCount, dev) != hipSuccess || cus < 1) cus = 1;
+  (void)hipGetLastError();
+  cache[dev] = cus;
+  return cus;
+}
+
 static int kxu_slots(const void* kernel, int threads = TX * TY) {
   static std::mutex mu;
   static std::map<std::pair<int, const void*>, int> cache;
@@ -1368,17 +1639,45 @@ template <typename T>
 hipError_t launch_cheb2(fe_problem* p, int lev, const T* dk, T* y, const T* E, const T* invd, const T* rin,
                         T* rout, T* acc, const double (&c)[4], int first, CgState* st) {
   const Grid g = p->L[lev].g;
-  const void* k = reinterpret_cast<const void*>(&cheb2_kernel<T>);
-  const TileMap tm = kxu_tile_map(g, kxu_slots(k, 2 * TX * TY), OWN2);
-  if (3 * (int64_t)(g.nx + 1) * (g.ny + 1) * tm.kc * (int64_t)sizeof(T) >= ((int64_t)1 << 31) ||
-      (int64_t)(g.nx + 1) * (g.ny + 1) * (tm.kc + 4) >= (int64_t)kOffIndex)
-    return hipErrorInvalidValue;  // the stores' 31-bit offsets, the load ranges' index bound
   Cheb2<T> cf;
   cf.c1a = (T)c[0];
   cf.c2a = (T)c[1];
   cf.c1b = (T)c[2];
   cf.c2b = (T)c[3];
   cf.first = first;
+  // 3D tiles of 4 x 4 x 4 or 4 x 4 x 8 owned nodes
+  const int gx = (g.nx + C3_OWN) / C3_OWN, gy = (g.ny + C3_OWN) / C3_OWN;
+  const int64_t n4 = (int64_t)gx * gy * ((g.nz + 4) / 4), n8 = (int64_t)gx * gy * ((g.nz + 8) / 8);
+  const int64_t cus = device_cus();
+  // automatic form: 3D tiles while every workgroup of the launch (all batch
+  // slots) gets a compute unit of its own, the shorter blocks first; beyond
+  // that workgroups share units and the z-marching tiles are faster
+  // (measured on the 56 x 28 x 14 coarsest grid of 224 x 112 x 56 with
+  // 4 x 4 x 4 blocks: 480 workgroups)
+  // (4 x 4 x 8 blocks only in float32: in float64 their LDS exceeds a workgroup's 160 KB)
+  constexpr bool tall = sizeof(T) == 4;
+  int form = p->cheb_per_launch;
+  if (form == 0) form = n4 * p->bcount <= cus ? 3 : (tall && n8 * p->bcount <= cus) ? 4 : 2;
+  if (form >= 3) {
+    const bool oz4 = form == 3 || !tall;
+    const int64_t nblk = oz4 ? n4 : n8, per = (nblk + 7) / 8;
+    if (8 * per > ((int64_t)1 << 31) - 1) return hipErrorInvalidValue;
+    const dim3 grid((unsigned)(8 * per), p->bcount);
+    const WK<T> wk = scaled_wk<T>(p->wk, p->L[lev].h);
+    const int64_t wsh = p->bcount > 1 ? p->bstride : (int64_t)0;
+    if (oz4)
+      hipLaunchKernelGGL((cheb3d_kernel<T, 4>), grid, dim3(C3<4>::THREADS), 0, p->stream, g, gx, gy, (int)nblk,
+                         (int)per, dk, E, p->L[lev].nmask, wk, invd, rin, rout, acc, y, cf, st, wsh);
+    else if constexpr (tall)
+      hipLaunchKernelGGL((cheb3d_kernel<T, 8>), grid, dim3(C3<8>::THREADS), 0, p->stream, g, gx, gy, (int)nblk,
+                         (int)per, dk, E, p->L[lev].nmask, wk, invd, rin, rout, acc, y, cf, st, wsh);
+    return hipGetLastError();
+  }
+  const void* k = reinterpret_cast<const void*>(&cheb2_kernel<T>);
+  const TileMap tm = kxu_tile_map(g, kxu_slots(k, 2 * TX * TY), OWN2);
+  if (3 * (int64_t)(g.nx + 1) * (g.ny + 1) * tm.kc * (int64_t)sizeof(T) >= ((int64_t)1 << 31) ||
+      (int64_t)(g.nx + 1) * (g.ny + 1) * (tm.kc + 4) >= (int64_t)kOffIndex)
+    return hipErrorInvalidValue;  // the stores' 31-bit offsets, the load ranges' index bound
   hipLaunchKernelGGL(cheb2_kernel<T>, dim3(tm.nblk, p->bcount), dim3(2 * TX * TY), 0, p->stream, g, tm, dk, E,
                      p->L[lev].nmask, scaled_wk<T>(p->wk, p->L[lev].h), invd, rin, rout, acc, y, cf, st,
                      reinterpret_cast<const T*>(p->zpad), p->bcount > 1 ? p->bstride : (int64_t)0);

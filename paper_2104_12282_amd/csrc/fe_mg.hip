@@ -275,7 +275,7 @@ hipError_t chebyshev_solve(fe_problem* p, int l, T* r, T* z, T* d0, T* d1, int d
   T* r_alt = static_cast<T*>(L.mg_q);
   for (int k = 0; k < deg && e == hipSuccess;) {
     const double rho1 = 1.0 / (2.0 * sigma - rho);
-    if (p->cheb_per_launch == 2 && k + 2 <= deg && r_alt) {
+    if (p->cheb_per_launch != 1 && k + 2 <= deg && r_alt) {
       // steps k and k + 1 in one launch; the residual moves to the other buffer
       const double rho2 = 1.0 / (2.0 * sigma - rho1);
       const double c[4] = {rho1 * rho, 2.0 * rho1 / delta, rho2 * rho1, 2.0 * rho2 / delta};

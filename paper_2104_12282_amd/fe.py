@@ -342,8 +342,10 @@ class Problem:
         none)."""
         _check(load_library().fe_set_float32_levels(self._h, first_level))
 
-    def set_coarse_fusion(self, steps_per_launch=2):
-        """Coarsest-level Chebyshev steps per launch (2: pairs fused, 1: one each)."""
+    def set_coarse_fusion(self, steps_per_launch=0):
+        """Launch form of the coarsest-level Chebyshev steps (0: chosen per
+        launch, the default; 3 / 4: pairs on 3D tiles of 4 x 4 x 4 / 4 x 4 x 8
+        nodes; 2: pairs on z-marching tiles; 1: one step each)."""
         _check(load_library().fe_set_coarse_fusion(self._h, steps_per_launch))
 
     def set_profiling(self, on, mode=None):

@@ -590,10 +590,46 @@ def test_coarse_fusion_bitwise(grid, levels, deg, precision):
         u, info = prob.solve(rho, rtol=1e-6)
         out.append((N(u), info))
         if per_launch == 2:
-            with pytest.raises(fe.FEError):
-                prob.set_coarse_fusion(3)
+            for bad in (-1, 5):
+                with pytest.raises(fe.FEError):
+                    prob.set_coarse_fusion(bad)
         prob.close()
     (u1, i1), (u2, i2) = out
     assert i1["rel_res"] <= 1e-6
     assert i1["iters"] == i2["iters"] and i1["outer_iters"] == i2["outer_iters"]
     assert np.array_equal(u1, u2)
+
+
+@pytest.mark.parametrize("grid,levels,deg", [((32, 16, 16), 3, 40), ((60, 32, 28), 3, 7), ((8, 4, 4), 3, 4),
+                                             ((26, 14, 2), 2, 5), ((80, 80, 40), 2, 6),
+                                             ((208, 208, 64), 2, 6), ((27, 13, 9), 3, 6), ((224, 112, 56), 3, 48)])
+@pytest.mark.parametrize("precision", ["fp64", "fp32_ir"])
+@pytest.mark.parametrize("form", [3, 4])
+def test_coarse_3d_tiles(grid, levels, deg, precision, form):
+    """Pairs of coarse Chebyshev steps on 3D tiles (the default launch form)
+    apply the same polynomial as one launch per step, up to the rounding of
+    their node sums (another order): to a tight tolerance both solves need
+    the same CG iterations (within two in float64, within 15% with float32
+    inner solves) and reach the same displacement;
+    two solves with 3D tiles agree bit for bit (no atomics).  Blocks of
+    4 x 4 x 4 and 4 x 4 x 8 nodes (float32 coarse levels; float64 ones take
+    the former), coarse grids of one tile and of many, one-element-thick
+    ones, odd degrees."""
+    nx, ny, nz = grid
+    rho = T(synth.density_around(nx, ny, nz, 4))
+    out = []
+    for per_launch in (1, form, form):
+        prob = _problem(nx, ny, nz, precision=precision, precond="gmg", mg_levels=levels)
+        prob.set_mg_params(coarse_sweeps=deg)
+        prob.set_coarse_fusion(per_launch)
+        u, info = prob.solve(rho, rtol=1e-9)
+        out.append((N(u), info))
+        prob.close()
+    (u1, i1), (u3, i3), (u3b, i3b) = out
+    assert i1["rel_res"] <= 1e-9 and i3["rel_res"] <= 1e-9
+    # float32 inner solves restart at each refinement step and feel the
+    # rounding of the preconditioner more: a looser iteration bound there
+    slack = 2 if precision == "fp64" else 2 + 0.15 * max(i1["iters"], i3["iters"])
+    assert abs(i1["iters"] - i3["iters"]) <= slack, (i1["iters"], i3["iters"])
+    assert np.abs(u3 - u1).max() <= 1e-6 * np.abs(u1).max()
+    assert np.array_equal(u3, u3b) and i3["iters"] == i3b["iters"]
