@@ -70,6 +70,8 @@ def parse():
                     help="run the 96x48x48 float64 Jacobi-PCG solve (to 1e-8) against the oracle")
     ap.add_argument("--serving", type=int, default=256,
                     help="requests of the serving stream to run (0: skip)")
+    ap.add_argument("--serving-streams", type=int, default=5,
+                    help="streams the serving engine's batches run on (one per grid size by default)")
     ap.add_argument("--serving-slots", type=int, default=16,
                     help="slots of each grid size's batch in the serving engine")
     ap.add_argument("--copy-probe", action="store_true",
@@ -86,11 +88,12 @@ def product_xin(precision: str) -> int:
     return PRODUCT_XIN.get(precision, 2)
 
 
-def traffic_from_profiles(precision: str, grid: str, field: str = "bytes"):
-    """HBM bytes (fetched + written) of one CG-product launch of the tiled K*u
-    kernel on this grid, from rocprofv3 FETCH_SIZE / WRITE_SIZE counters scaled
+def traffic_from_profiles(precision: str, grid: str, field: str = "bytes", want: str | None = None):
+    """HBM bytes (fetched + written) of one launch of a kernel on this grid
+    (`want`: a substring of its name; by default the CG-product launch of the
+    tiled K*u kernel), from rocprofv3 FETCH_SIZE / WRITE_SIZE counters scaled
     by a copy of known size (field "bytes"), or rocprofv3's average kernel
-    duration of that launch in us (field "trace_avg_us"), when the stored
+    duration of that launch in us (field "trace_work_avg_us"), when the stored
     figures were taken on the current kernel source; else None."""
     path = os.path.join(ROOT, "profiles", f"kxu_tile_{grid}_traffic.json")
     if not os.path.exists(path):
@@ -100,7 +103,7 @@ def traffic_from_profiles(precision: str, grid: str, field: str = "bytes"):
         from paper_2104_12282_amd.build import source_digest
         if rec.get("source_digest") != source_digest():
             return None
-        want = f"kxu_tile_kernel<{'double' if precision == 'fp64' else 'float'}, 1, {product_xin(precision)}>"
+        want = want or f"kxu_tile_kernel<{'double' if precision == 'fp64' else 'float'}, 1, {product_xin(precision)}>"
         for name, k in rec["kernels"].items():
             if want in name:
                 return k["fetch_bytes"] + k["write_bytes"] if field == "bytes" else k.get(field)
@@ -742,7 +745,7 @@ def onsg_study(fe, synth, torch, args, K, nb=5, width=1000, steps=2000, batch=25
     return out
 
 
-def serving_bench(n, torch, nslots=16):
+def serving_bench(n, torch, nslots=16, nstreams=5):
     """Serving stream of n seeded requests over the five grid sizes: the same
     requests one at a time (blocking solves); through the batched engine
     (one fe_batch of nslots per size, designs sharing launches) all at once
@@ -752,11 +755,11 @@ def serving_bench(n, torch, nslots=16):
     streams."""
     from paper_2104_12282_amd import serve, synth
     reqs = synth.serving_requests(n, seed=0)
-    serve.run_engine_batched(reqs[:8], None, nslots=nslots)  # warm-up: kernels, graphs, allocator
+    serve.run_engine_batched(reqs[:8], None, nslots=nslots, n_streams=nstreams)  # warm-up: kernels, graphs
     serve.run_engine(reqs[:8], None)
     _, seq = serve.run_sequential(reqs)
     print(f"bench[serving]: sequential {seq['designs_per_s']:.1f} designs/s", file=sys.stderr, flush=True)
-    _, sat = serve.run_engine_batched(reqs, None, nslots=nslots)
+    _, sat = serve.run_engine_batched(reqs, None, nslots=nslots, n_streams=nstreams)
     print(f"bench[serving]: batched engine {sat['designs_per_s']:.1f} designs/s", file=sys.stderr, flush=True)
     _, streams = serve.run_engine(reqs, None)
     print(f"bench[serving]: stream engine {streams['designs_per_s']:.1f} designs/s", file=sys.stderr, flush=True)
@@ -772,7 +775,7 @@ def serving_bench(n, torch, nslots=16):
                        ("2.0x_sequential_rate", 2.0 * seq["designs_per_s"]),
                        ("0.8x_batched_throughput", 0.8 * sat["designs_per_s"])):
         arr = synth.poisson_arrivals(n, rate, seed=1)
-        _, st = serve.run_engine_batched(reqs, arr, nslots=nslots)
+        _, st = serve.run_engine_batched(reqs, arr, nslots=nslots, n_streams=nstreams)
         st["arrival_rate_per_s"] = rate
         out["poisson"][name] = st
         print(f"bench[serving]: poisson {name}: {st['designs_per_s']:.1f} designs/s p50 "
@@ -782,10 +785,11 @@ def serving_bench(n, torch, nslots=16):
     return out
 
 
-def run_loop(fe, synth, torch, nx, ny, nz, precision, args, steps, warmup, profile, flush=None):
+def run_loop(fe, synth, torch, nx, ny, nz, precision, args, steps, warmup, profile, flush=None, prof_mode=1):
     """Warm-up steps, then `steps` timed optimisation steps from the start
     design (the timed steps are iterations 0 .. steps-1 of the loop).  With
-    profile, HIP event nodes bracket every CG-product launch; with flush as
+    profile, HIP event nodes bracket every CG-product launch (prof_mode 1)
+    or every coarsest-level Chebyshev pair launch (prof_mode 7); with flush as
     well, a pass over that buffer precedes each one (cold operands)."""
     ne = nx * ny * nz
     dev = "cuda:0"
@@ -835,7 +839,7 @@ def run_loop(fe, synth, torch, nx, ny, nz, precision, args, steps, warmup, profi
     prob.kernel_stats(reset=True)
     if flush is not None:
         prob.set_cache_flush(flush)
-    prob.set_profiling(profile, mode=1)  # the CG product: direction + K*u launch
+    prob.set_profiling(profile, mode=prof_mode)
     torch.cuda.synchronize()
     t0 = time.perf_counter()
     for i in range(steps):
@@ -879,7 +883,7 @@ def main():
     dt, rec, _, ndof = run_loop(fe, synth, torch, nx, ny, nz, args.precision, args, args.steps,
                                 args.warmup, profile=False)
     print(f"bench: {args.steps} steps in {dt:.3f} s ({args.steps / dt:.2f} solves/s)", file=sys.stderr, flush=True)
-    # the same steps again with event nodes around every CG-product launch (the roofline figure)
+    # the same steps again with event nodes around every CG-product launch
     dtp, recp, ks, _ = run_loop(fe, synth, torch, nx, ny, nz, args.precision, args, args.steps, 0,
                                 profile=True)
     avg_ms = ks["total_ms"] / max(1, ks["launches"])
@@ -899,6 +903,63 @@ def main():
                 "note": f"first {min(args.steps, 3)} steps of the loop; every timed launch follows a kernel that "
                         f"streams through a {args.cold} MB buffer, so its operands come from HBM"}
         cold["frac"] = cold["achieved"] / HBM_PEAK_GBS
+    product = {"bound": "hbm", "achieved": achieved, "peak": HBM_PEAK_GBS, "unit": "GB/s",
+               "frac": achieved / HBM_PEAK_GBS,
+               "measured_on": "a second pass over the same timed steps with event nodes (the headline "
+                              "pass runs without them); warm: the loop's own cache state",
+               "profiled_pass_solves_per_s": args.steps / dtp,
+               "cold": cold,
+               "traffic": traffic_from_profiles(args.precision, f"{nx}x{ny}x{nz}"),
+               "traffic_of": "one CG-product launch (rocprofv3 counters, copy-scaled)",
+               "kernel": "kxu_tile_kernel<" + ("double" if args.precision == "fp64" else "float")
+                         + f", 1, {product_xin(args.precision)}>: CG product on the finest grid "
+                         "(direction p = z + beta p fused into the matrix-free K*u, p^T K p partials"
+                         + ("; z read in float32" if product_xin(args.precision) == 3 else "") + ")",
+               "launches": ks["launches"], "avg_launch_us": avg_ms * 1e3,
+               "rocprofv3_avg_kernel_us": traffic_from_profiles(args.precision, f"{nx}x{ny}x{nz}",
+                                                                "trace_work_avg_us"),
+               "timing_note": "avg_launch_us brackets each launch with HIP event nodes inside the "
+                              "captured CG graph (includes the nodes' own dispatch time); "
+                              "rocprofv3_avg_kernel_us is the kernel-trace average of the same "
+                              "kernel in the profiled run of this command; both leave out the "
+                              "launches that met the CG stop flag (a converged solve's remaining "
+                              "iterations in its last chunk return at once)",
+               "algorithmic_bytes_per_launch": ks["bytes_per_launch"]}
+    roofline = product
+    coarse = coarse_solve_record(nx, ny, nz, args, rec["mg"]["coarse_sweeps"]) if rec["mg"] else None
+    if coarse:
+        # a multigrid solve spends most of its GPU time in the coarsest-level
+        # Chebyshev pairs: they are the dominant kernel of the roofline line
+        dtq, _, ksq, _ = run_loop(fe, synth, torch, nx, ny, nz, args.precision, args, args.steps, 0,
+                                  profile=True, prof_mode=7)
+        # one event pair brackets each coarse solve (its launches_per_vcycle
+        # launches back to back, the gaps between them included)
+        per = coarse["launches_per_vcycle"]
+        sms = ksq["total_ms"] / max(1, ksq["launches"])  # one coarse solve
+        qms = sms / per
+        qach = ksq["bytes_per_launch"] / (sms * 1e-3) / 1e9 if ksq["launches"] else 0.0
+        name = coarse["kernel"].split(":")[0]
+        roofline = {"bound": "hbm", "achieved": qach, "peak": HBM_PEAK_GBS, "unit": "GB/s",
+                    "frac": qach / HBM_PEAK_GBS,
+                    "limiter": "latency: a few MB per launch on the coarsest grid; the launch time is its chain "
+                               "of one memory round trip, four LDS phases and the stores, not HBM bandwidth",
+                    "measured_on": "a third pass over the same timed steps with event nodes around every "
+                                   "coarse pair launch (the headline pass runs without them); warm",
+                    "profiled_pass_solves_per_s": args.steps / dtq,
+                    "traffic": traffic_from_profiles(args.precision, f"{nx}x{ny}x{nz}", want=name.split("<")[0]),
+                    "traffic_of": "one coarse pair launch (rocprofv3 counters, copy-scaled)",
+                    "kernel": coarse["kernel"],
+                    "launches": ksq["launches"] * per, "avg_launch_us": qms * 1e3,
+                    "rocprofv3_avg_kernel_us": traffic_from_profiles(args.precision, f"{nx}x{ny}x{nz}",
+                                                                     "trace_work_avg_us",
+                                                                     want=name.split("<")[0]),
+                    "timing_note": "one HIP event pair inside the captured CG graph brackets each coarse solve "
+                                   f"({per} launches back to back); avg_launch_us is its time over {per}, so the "
+                                   "short gaps between the launches are included; rocprofv3_avg_kernel_us is the "
+                                   "kernel-trace average of the same kernel in the profiled run of this command; "
+                                   "both leave out the launches that met the CG stop flag",
+                    "algorithmic_bytes_per_launch": ksq["bytes_per_launch"] / per,
+                    "cg_product": product}
     out = {
         "metric": "FE solves/s at 1.4M elements (one optimisation step = one solve)",
         "value": args.steps / dt,
@@ -929,35 +990,13 @@ def main():
                    "cg_iters_max": int(np.max(rec["iters"])),
                    "refinement_steps_per_solve": float(np.mean(rec["outer"])),
                    "compliance_first": rec["compliance"][0], "compliance_last": rec["compliance"][-1]},
-        "roofline": {"bound": "hbm", "achieved": achieved, "peak": HBM_PEAK_GBS, "unit": "GB/s",
-                     "frac": achieved / HBM_PEAK_GBS,
-                     "measured_on": "a second pass over the same timed steps with event nodes (the headline "
-                                    "pass runs without them); warm: the loop's own cache state",
-                     "profiled_pass_solves_per_s": args.steps / dtp,
-                     "cold": cold,
-                     "traffic": traffic_from_profiles(args.precision, f"{nx}x{ny}x{nz}"),
-                     "traffic_of": "one CG-product launch (rocprofv3 counters, copy-scaled)",
-                     "kernel": "kxu_tile_kernel<" + ("double" if args.precision == "fp64" else "float")
-                               + f", 1, {product_xin(args.precision)}>: CG product on the finest grid "
-                               "(direction p = z + beta p fused into the matrix-free K*u, p^T K p partials"
-                               + ("; z read in float32" if product_xin(args.precision) == 3 else "") + ")",
-                     "launches": ks["launches"], "avg_launch_us": avg_ms * 1e3,
-                     "rocprofv3_avg_kernel_us": traffic_from_profiles(args.precision, f"{nx}x{ny}x{nz}",
-                                                                      "trace_work_avg_us"),
-                     "timing_note": "avg_launch_us brackets each launch with HIP event nodes inside the "
-                                    "captured CG graph (includes the nodes' own dispatch time); "
-                                    "rocprofv3_avg_kernel_us is the kernel-trace average of the same "
-                                    "kernel in the profiled run of this command; both leave out the "
-                                    "launches that met the CG stop flag (a converged solve's remaining "
-                                    "iterations in its last chunk return at once)",
-                     "algorithmic_bytes_per_launch": ks["bytes_per_launch"]},
+        "roofline": roofline,
     }
     rec_prof = profile_record(f"{nx}x{ny}x{nz}")
     if rec_prof and rec_prof.get("time_shares"):
         out["roofline"]["rocprofv3_time_shares"] = [
             {"kernel": t["kernel"], "share": round(t["share"], 4), "avg_us": round(t["avg_us"], 2)}
             for t in rec_prof["time_shares"][:8]]
-    coarse = coarse_solve_record(nx, ny, nz, args, rec["mg"]["coarse_sweeps"]) if rec["mg"] else None
     if coarse:
         out["roofline"]["coarse_solve"] = coarse
     if probe:
@@ -1000,7 +1039,7 @@ def main():
     if args.two_scale:
         out["two_scale"] = two_scale_study(fe, synth, torch, nx, ny, nz, args)
     if args.serving > 0:
-        out["serving"] = serving_bench(args.serving, torch, nslots=args.serving_slots)
+        out["serving"] = serving_bench(args.serving, torch, nslots=args.serving_slots, nstreams=args.serving_streams)
     if not args.no_cpu_baseline:
         out["cpu_baseline"] = cpu_baseline((nx, ny, nz), args.rtol)
         print(f"bench[cpu]: oracle {out['cpu_baseline']['seconds_sampled']:.1f} s sampled, "

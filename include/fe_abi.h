@@ -29,9 +29,10 @@
  *     instantiated HIP graph of a chunk of CG iterations (hipGraphInstantiate
  *     allocates the graph's own runtime memory); oc_update on the same
  *     arrays a second time: one captured graph of the update;
- *   - fe_batch_create: the host batch object and one handle per slot, each
- *     created as by fe_setup (pinned buffers, event, capture stream), and
- *     the batch's own captured graph on its first round;
+ *   - fe_batch_create: the host batch object, one event, a pinned array of
+ *     the slots' CG states and one handle per slot, each created as by
+ *     fe_setup (pinned buffers, event, capture stream), and the batch's own
+ *     captured graph on its first round;
  *   - with profiling on: event pairs (hipEventCreate), reused;
  *   - the synthetic-gradient model (fe_onsg_create): a rocBLAS handle.
  * fe_destroy / fe_batch_destroy / fe_onsg_destroy release all of it.
@@ -296,12 +297,16 @@ FE_API fe_status fe_get_mg_params(const fe_problem* p, int32_t* nu, int32_t* coa
  * FE_EINVAL for other values and for batch slots. */
 FE_API fe_status fe_set_coarse_fusion(fe_problem* p, int32_t steps_per_launch);
 
-/* Timing of the dominant kernel (matrix-free K*u on the finest grid): with
- * on = 1 every such launch, in all its forms (CG product, residual, smoothing
+/* Timing of the hot kernels: with on = 1 every launch of the matrix-free
+ * K*u on the finest grid, in all its forms (CG product, residual, smoothing
  * sweep), is bracketed by HIP events on the handle's stream; with on = 2 + m
  * only the launches of form m (1 = CG product, 3 = smoothing sweep,
  * 4 = residual, 5 = last smoothing sweep with r^T z, 6 = Chebyshev step,
- * 0 = plain product); on = 0 switches it off, other values are FE_EINVAL.
+ * 0 = plain product), and with m = 7 each coarsest-level Chebyshev solve
+ * (its launches of pairs of steps, the largest share of a multigrid solve's
+ * time, bracketed as one: a launch of a few microseconds is shorter than an
+ * event pair's own cost); on = 0 switches it off, other values are
+ * FE_EINVAL.
  * fe_kernel_stats returns the number of launches and their summed duration
  * in ms since the last reset, and the mean algorithmic bytes of one launch
  * (each array the kernel reads or writes counted once).  Launches that met
@@ -368,6 +373,12 @@ FE_API fe_status fe_batch_setup_slot(fe_batch* b, int32_t slot, const uint8_t* f
  * with its status in fe_solve_end; the first such status is also returned. */
 FE_API fe_status fe_batch_round_begin(fe_batch* b);
 FE_API fe_status fe_batch_round_end(fe_batch* b, int32_t* running);
+
+/* Whether the open round's work has completed on the device, without
+ * waiting (*ready = 1: fe_batch_round_end returns without blocking; also 1
+ * when no round is open), so that a serving loop can end and restart each
+ * batch's rounds as they complete instead of in lockstep. */
+FE_API fe_status fe_batch_round_ready(fe_batch* b, int32_t* ready);
 
 /* Releases the batch and its slots' handles (the workspace stays the caller's). */
 FE_API void fe_batch_destroy(fe_batch* b);

@@ -22,7 +22,8 @@ constexpr size_t kAlign = 256;
 inline size_t align_up(size_t x) { return (x + kAlign - 1) & ~(kAlign - 1); }
 
 // scal[] slots: value at 2*s, arrival counter of its reduction at 2*s + 1.
-enum { SLOT_FF = 0, SLOT_RR = 1, SLOT_C = 2, SLOT_TMP = 3, NSCAL = 128 };
+enum { SLOT_FF = 0, SLOT_RR = 1, SLOT_C = 2, SLOT_TMP = 3, SLOT_IRS = 4, NSCAL = 128 };
+// SLOT_IRS: ||r||^2 of the float64 residual the running float32 inner solve was scaled by
 
 Grid make_grid(int nx, int ny, int nz) {
   Grid g;
@@ -231,6 +232,7 @@ constexpr int kChunk = 24;    // Jacobi-PCG iterations per enqueued chunk
 constexpr int kChunkMG = 8;   // multigrid-PCG iterations per enqueued chunk (even: the folded
                               // iteration alternates two direction buffers)
 constexpr int kMaxOuter = 40; // float64 refinement steps
+constexpr bool kResumeInner = FE_IR_RESUME != 0;  // residual replacement instead of restarts
 
 enum { ST_DONE = 0, ST_CG64 = 1, ST_IR_RESID = 2, ST_IR_CG = 3, ST_FINISH = 4 };
 
@@ -487,33 +489,71 @@ fe_status advance(fe_problem* p) {
         return enqueue_finish(p, false);
       }
       sc.prev_rel = rel;
-      // inner tolerance: aim a little past the target, within float32 reach
+      if (sc.can_resume) {
+        // Residual replacement: the float32 CG goes on from its last
+        // direction with the float64 residual of the refined u in place of
+        // its recurrence (the Krylov space is kept; a restart would throw it
+        // away).  The system stays scaled by the norm it started with.
+        const CgState hs = *p->h_st;
+        const double scaled = std::sqrt(rr / sc.inner_rr);  // ||r|| in the inner system's units
+        double tol = FE_IR_FACTOR * sc.rtol * std::sqrt(p->ff / sc.inner_rr);
+        if (tol < FE_IR_PHASE * scaled) tol = FE_IR_PHASE * scaled;
+        HIP_TRY(launch_to32_scaled(p, p->r64, p->r32, p->scal + 2 * SLOT_IRS));
+        HIP_TRY(launch_fill<float>(p, p->x32, p->L[0].g.ndof, 0.0f));
+        // the chunk's first direction kernel reads the last direction from p32
+        const int j = hs.iter - sc.chunk_iter0 - 1;  // chunk position of the last iteration
+        if (j >= 0 && (j & 1) == 0)
+          HIP_TRY(hipMemcpyAsync(p->p32, p->p32b, p->L[0].g.ndof * sizeof(float), hipMemcpyDeviceToDevice,
+                                 p->stream));
+        HIP_TRY(launch_cg_state_resume(p, p->st, tol * tol, hs.iter + (sc.max_iters - sc.total)));
+        HIP_TRY(launch_vcycle<float>(p, 0, p->r32, static_cast<float*>(p->L[0].mg_z), p->st, RZ_PARTIALS, 0));
+        sc.inner_base = sc.total - hs.iter;
+        sc.chunk_iter0 = hs.iter;
+        sc.can_resume = false;
+        sc.stage = ST_IR_CG;
+        return copy_state(p);
+      }
+      // inner tolerance: aim a little past the target, within float32 reach;
+      // a float32 CG that will go on by residual replacement stops after a
+      // reduction of FE_IR_PHASE, while its recurrence still tracks the
+      // float64 residual to a small fraction
       double itol = FE_IR_FACTOR * sc.rtol / rel;
-      if (itol < FE_IR_FLOOR) itol = FE_IR_FLOOR;
+      const double floor = (kResumeInner && folded_mg(p)) ? FE_IR_PHASE : FE_IR_FLOOR;
+      if (itol < floor) itol = floor;
       if (itol > 1e-1) itol = 1e-1;
-      HIP_TRY(launch_to32_scaled(p, p->r64, p->r32, p->scal + 2 * SLOT_RR));
+      HIP_TRY(hipMemcpyAsync(p->scal + 2 * SLOT_IRS, p->scal + 2 * SLOT_RR, sizeof(double),
+                             hipMemcpyDeviceToDevice, p->stream));
+      sc.inner_rr = rr;
+      HIP_TRY(launch_to32_scaled(p, p->r64, p->r32, p->scal + 2 * SLOT_IRS));
       HIP_TRY(launch_fill<float>(p, p->x32, p->L[0].g.ndof, 0.0f));
       HIP_TRY(launch_cg_state_init(p, p->st, itol, sc.max_iters - sc.total));
       HIP_TRY(enqueue_start<float>(p, p->r32, nullptr, p->r32, p->p32));
+      sc.inner_base = sc.total;
+      sc.chunk_iter0 = 0;
       sc.stage = ST_IR_CG;
       return copy_state(p);
     }
     case ST_IR_CG: {
       const CgState hs = *p->h_st;
       if (!hs.done) {
+        sc.chunk_iter0 = hs.iter;  // the next chunk starts at this iteration
         if (p->in_batch) return FE_OK;  // the batch's next replay runs the chunk
         HIP_TRY(enqueue_chunk<float>(p, p->x32, p->r32, p->p32, p->q32));
         return copy_state(p);
       }
-      sc.total += hs.iter;
+      sc.total = sc.inner_base + hs.iter;
       sc.outer += 1;
       sc.info.iters = sc.total;
       sc.info.outer_iters = sc.outer;
-      if (hs.iter > 0) HIP_TRY(launch_axpy_from32(p, sc.u, p->x32, p->scal + 2 * SLOT_RR));
+      if (hs.iter > 0) HIP_TRY(launch_axpy_from32(p, sc.u, p->x32, p->scal + 2 * SLOT_IRS));
       if (hs.status == FE_EBREAKDOWN && hs.iter == 0) {
         sc.result = FE_EBREAKDOWN;
         return enqueue_finish(p, false);
       }
+      // the next refinement step may go on with this Krylov space: a folded
+      // multigrid CG that stopped at its tolerance after some iterations
+      sc.can_resume = kResumeInner && folded_mg(p) && hs.status == FE_OK && hs.iter > 0 &&
+                      hs.iter - sc.chunk_iter0 >= 1;
       return enqueue_ir_residual(p);
     }
     case ST_FINISH: {
@@ -1091,8 +1131,8 @@ extern "C" fe_status fe_set_coarse_fusion(fe_problem* p, int32_t steps_per_launc
 
 extern "C" fe_status fe_set_profiling(fe_problem* p, int32_t on) {
   CHECK_HANDLE(p);
-  if (on < 0 || on > 8) {
-    fe_set_error("profiling selector must be 0, 1 or 2 + form (form 0..6)");
+  if (on < 0 || on > 9) {
+    fe_set_error("profiling selector must be 0, 1 or 2 + form (form 0..7)");
     return FE_EINVAL;
   }
   p->kst.on = on != 0;
@@ -1172,7 +1212,9 @@ struct fe_batch {
   std::vector<fe_problem*> slot;
   hipGraphExec_t chunk = nullptr;
   hipEvent_t ev = nullptr;
-  bool open = false;  // a round was begun and not yet ended
+  CgState* h_states = nullptr;  // pinned: every slot's CG state after the round's replay (one copy)
+  bool open = false;      // a round was begun and not yet ended
+  bool replayed = false;  // the open round replayed the chunk (h_states is filled)
 };
 
 namespace {
@@ -1309,6 +1351,7 @@ extern "C" fe_status fe_batch_create(const fe_config* cfg, int32_t nslots, void*
   };
   hipError_t e = hipMemsetAsync(b->zero_f, 0, batch_zero_bytes(cfg), b->stream);
   if (e == hipSuccess) e = hipEventCreateWithFlags(&b->ev, hipEventDisableTiming);
+  if (e == hipSuccess) e = hipHostMalloc((void**)&b->h_states, (size_t)nslots * sizeof(CgState), hipHostMallocDefault);
   if (e != hipSuccess) {
     fe_set_error(std::string("batch setup: ") + hipGetErrorString(e));
     return fail(FE_EDEVICE);
@@ -1392,12 +1435,13 @@ extern "C" fe_status fe_batch_round_begin(fe_batch* b) {
       if (st != FE_OK) return st;
     }
     HIP_TRY(hipGraphLaunch(b->chunk, b->stream));
-    for (fe_problem* h : b->slot)
-      if (in_cg_stage(h))
-        HIP_TRY(hipMemcpyAsync(h->h_st, h->st, sizeof(CgState), hipMemcpyDeviceToHost, b->stream));
+    // every slot's state in one strided copy (the states sit stride bytes apart)
+    HIP_TRY(hipMemcpy2DAsync(b->h_states, sizeof(CgState), b->ws + b->st_off, b->stride, sizeof(CgState),
+                             (size_t)b->nslots, hipMemcpyDeviceToHost, b->stream));
   }
   HIP_TRY(hipEventRecord(b->ev, b->stream));
   b->open = true;
+  b->replayed = any;
   return FE_OK;
 }
 
@@ -1410,8 +1454,10 @@ extern "C" fe_status fe_batch_round_end(fe_batch* b, int32_t* running) {
   HIP_TRY(hipEventSynchronize(b->ev));
   fe_status first_err = FE_OK;
   int n = 0;
-  for (fe_problem* h : b->slot) {
+  for (int s = 0; s < b->nslots; ++s) {
+    fe_problem* h = b->slot[s];
     if (!h || h->sc.stage == ST_DONE) continue;
+    if (b->replayed && in_cg_stage(h)) *h->h_st = b->h_states[s];
     const fe_status st = advance(h);
     if (st != FE_OK) {
       h->sc.stage = ST_DONE;
@@ -1425,6 +1471,25 @@ extern "C" fe_status fe_batch_round_end(fe_batch* b, int32_t* running) {
   return first_err;
 }
 
+extern "C" fe_status fe_batch_round_ready(fe_batch* b, int32_t* ready) {
+  if (!b || !ready) {
+    fe_set_error("batch and ready must not be NULL");
+    return FE_EINVAL;
+  }
+  if (!b->open) {
+    *ready = 1;
+    return FE_OK;
+  }
+  const hipError_t q = hipEventQuery(b->ev);
+  if (q == hipErrorNotReady) {
+    *ready = 0;
+    return FE_OK;
+  }
+  HIP_TRY(q);
+  *ready = 1;
+  return FE_OK;
+}
+
 extern "C" void fe_batch_destroy(fe_batch* b) {
   if (!b) return;
   if (b->stream) (void)hipStreamSynchronize(b->stream);
@@ -1432,5 +1497,6 @@ extern "C" void fe_batch_destroy(fe_batch* b) {
     if (h) fe_destroy(h);
   if (b->chunk) (void)hipGraphExecDestroy(b->chunk);
   if (b->ev) (void)hipEventDestroy(b->ev);
+  if (b->h_states) (void)hipHostFree(b->h_states);
   delete b;
 }

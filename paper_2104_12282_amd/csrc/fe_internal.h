@@ -20,6 +20,12 @@
 #ifndef FE_IR_FLOOR
 #define FE_IR_FLOOR 1e-5  // refinement: tightest relative tolerance asked of a float32 inner solve
 #endif
+#ifndef FE_IR_PHASE
+#define FE_IR_PHASE 1e-2  // refinement with residual replacement: reduction of the residual per phase
+#endif
+#ifndef FE_IR_RESUME
+#define FE_IR_RESUME 1  // refinement: continue the float32 CG with the float64 residual (no restart)
+#endif
 #ifndef FE_CHEB_FORM
 #define FE_CHEB_FORM 0  // default launch form of the coarsest-level Chebyshev steps (0: automatic)
 #endif
@@ -129,6 +135,10 @@ struct SolveCtx {
   int total = 0, outer = 0;
   double prev_rel = 1e300;
   int fresh_inner = 0;          // the inner CG state was just initialised
+  bool can_resume = false;      // the next refinement step may continue the float32 CG
+  int inner_base = 0;           // refinement iterations before the running float32 CG
+  int chunk_iter0 = 0;          // CG iteration at which the last chunk started
+  double inner_rr = 0.0;        // ||r||^2 the running float32 CG is scaled by
   fe_status result = FE_OK;
   fe_solve_info info{};
 };
@@ -342,6 +352,10 @@ hipError_t launch_cg_update_mg(fe_problem* p, T* x, T* r, const T* pvec, const T
 hipError_t launch_narrow(fe_problem* p, const double* a, float* b);
 
 hipError_t launch_cg_state_init(fe_problem* p, CgState* st, double tol_rel, int max_iter);
+// Re-arms a stopped CG for residual replacement: not done, status FE_OK,
+// stop at ||r||^2 <= tol2 (absolute) or max_iter iterations; the iteration
+// count and the committed r^T z are kept.
+hipError_t launch_cg_state_resume(fe_problem* p, CgState* st, double tol2, int max_iter);
 // One-workgroup scalar update after a kernel that left nb partials:
 // op 0 alpha = rz / pq, 1 CG start, 2 CG update and convergence test,
 // 3 rz and beta, 4 out[0] = the sum.

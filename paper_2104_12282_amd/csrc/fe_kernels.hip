@@ -383,6 +383,15 @@ __global__ void __launch_bounds__(FE_BLOCK) cg_direction_kernel(Grid g, const T*
   }
 }
 
+__global__ void cg_state_resume_kernel(CgState* st, double tol2, int max_iter) {
+  if (threadIdx.x == 0 && blockIdx.x == 0) {
+    st->tol2 = tol2;
+    st->max_iter = max_iter;
+    st->done = 0;
+    st->status = FE_OK;
+  }
+}
+
 __global__ void cg_state_init_kernel(CgState* st, double tol_rel, int max_iter) {
   if (threadIdx.x == 0 && blockIdx.x == 0) {
     st->rz = st->alpha = st->beta = st->rr = st->bb = st->pq = 0.0;
@@ -1068,6 +1077,11 @@ hipError_t launch_cg_direction(fe_problem* p, const T* r, const T* z, T* pvec, C
 template hipError_t launch_cg_direction<double>(fe_problem*, const double*, const double*, double*,
                                                 CgState*);
 template hipError_t launch_cg_direction<float>(fe_problem*, const float*, const float*, float*, CgState*);
+
+hipError_t launch_cg_state_resume(fe_problem* p, CgState* st, double tol2, int max_iter) {
+  hipLaunchKernelGGL(cg_state_resume_kernel, dim3(1), dim3(64), 0, p->stream, st, tol2, max_iter);
+  return hipGetLastError();
+}
 
 hipError_t launch_cg_state_init(fe_problem* p, CgState* st, double tol_rel, int max_iter) {
   hipLaunchKernelGGL(cg_state_init_kernel, dim3(1), dim3(64), 0, p->stream, st, tol_rel, max_iter);

@@ -273,6 +273,16 @@ hipError_t chebyshev_solve(fe_problem* p, int l, T* r, T* z, T* d0, T* d1, int d
                        L.g.ndof, r, lev_invd<T>(L), (T)(1.0 / theta), d0, st, wsh_of(p));
   hipError_t e = hipGetLastError();
   T* r_alt = static_cast<T*>(L.mg_q);
+  // profiling form 7: one event pair around the solve's launches; the
+  // algorithmic bytes of each launch (one or two steps) read d_k, r_k, the
+  // iterate, D^-1, the fixed-dof mask and E and write the residual, the
+  // iterate and the next direction, each array once
+  int prof = -1;
+  if (p->kst.on && p->kst.mode == 7 && p->bcount == 1) {
+    const int launches = p->cheb_per_launch == 1 ? deg : (deg + 1) / 2;
+    prof = kstats_begin(p, (double)launches * ((double)sizeof(T) * (19.0 * (double)L.g.nnode + (double)L.g.nelem) +
+                                               (double)L.g.nnode));
+  }
   for (int k = 0; k < deg && e == hipSuccess;) {
     const double rho1 = 1.0 / (2.0 * sigma - rho);
     if (p->cheb_per_launch != 1 && k + 2 <= deg && r_alt) {
@@ -297,6 +307,7 @@ hipError_t chebyshev_solve(fe_problem* p, int l, T* r, T* z, T* d0, T* d1, int d
     }
     std::swap(d0, d1);
   }
+  kstats_end(p, prof);
   return e;
 }
 

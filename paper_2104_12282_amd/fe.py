@@ -28,7 +28,7 @@ ABI_SYMBOLS = ("fe_workspace_size", "fe_setup", "fe_apply_K", "fe_solve", "fe_so
                "fe_solve_step", "fe_solve_end", "fe_sensitivity", "fe_sensitivity_adjoint", "fe_set_load",
                "fe_filter", "oc_update", "oc_update_noalloc", "fe_block_mean", "fe_set_mg_params", "fe_get_mg_params", "fe_set_float32_levels", "fe_set_coarse_fusion", "fe_set_profiling", "fe_set_cache_flush",
                "fe_kernel_stats", "fe_destroy", "fe_batch_workspace_size", "fe_batch_create", "fe_batch_setup_slot",
-               "fe_batch_round_begin", "fe_batch_round_end", "fe_batch_destroy", "fe_onsg_num_params",
+               "fe_batch_round_begin", "fe_batch_round_end", "fe_batch_round_ready", "fe_batch_destroy", "fe_onsg_num_params",
                "fe_onsg_workspace_size", "fe_onsg_create", "fe_onsg_add_samples", "fe_onsg_num_samples",
                "fe_onsg_train", "fe_onsg_predict", "fe_onsg_get_params", "fe_onsg_destroy", "fe_last_error")
 
@@ -95,6 +95,7 @@ def load_library() -> C.CDLL:
     lib.fe_batch_setup_slot.argtypes = [P, I32, P, P, C.POINTER(P)]
     lib.fe_batch_round_begin.argtypes = [P]
     lib.fe_batch_round_end.argtypes = [P, C.POINTER(I32)]
+    lib.fe_batch_round_ready.argtypes = [P, C.POINTER(I32)]
     lib.fe_batch_destroy.argtypes = [P]
     lib.fe_batch_destroy.restype = None
     lib.fe_onsg_num_params.argtypes = [I32, I32]
@@ -349,7 +350,8 @@ class Problem:
         _check(load_library().fe_set_coarse_fusion(self._h, steps_per_launch))
 
     def set_profiling(self, on, mode=None):
-        """Times finest-grid K*u launches: all forms, or only form `mode`."""
+        """Times finest-grid K*u launches: all forms, or only form `mode`
+        (mode 7: the coarsest-level Chebyshev pair launches)."""
         sel = 0 if not on else (1 if mode is None else 2 + int(mode))
         _check(load_library().fe_set_profiling(self._h, sel))
 
@@ -420,6 +422,12 @@ class Batch:
         if st != FE_OK:
             raise FEError(st, load_library().fe_last_error().decode())
         return n.value
+
+    def round_ready(self) -> bool:
+        """Whether the open round has completed on the device (no wait)."""
+        n = C.c_int32()
+        _check(load_library().fe_batch_round_ready(self._b, C.byref(n)))
+        return bool(n.value)
 
     def close(self):
         if getattr(self, "_b", None):

@@ -12,7 +12,8 @@ busy and how long it sat between kernels.
 dispatch), scales each by what the same counter reads for the plain copy of
 known size that bench.py --copy-probe performs (hipMemcpy device-to-device,
 kernel __amd_rocclr_copyBuffer), and stores the bytes per launch of the tiled
-K*u kernel next to the digest of the sources it was measured on; given the
+K*u kernel and of the coarse Chebyshev pair kernels next to the digest of the
+sources it was measured on; given the
 kernel statistics of a --kernel-trace run of the same sources, it also
 stores each kernel's average duration there (all launches, and the launches
 that did their work: the kernel trace next to the statistics file gives the
@@ -106,12 +107,15 @@ def traffic(fetch_dir, write_dir, bench_json, out_path, command, stats_csv=None)
     rec = {"source_digest": source_digest(), "command": command,
            "copy_probe_bytes": probe["bytes"], "copy_fetch_kib": copy_f, "copy_write_kib": copy_w,
            "fetch_scale": f_scale, "write_scale": w_scale, "kernels": {}}
-    for mode_key in sorted({k for k in fetch if "kxu_tile_kernel" in k}):
+    for mode_key in sorted({k for k in fetch if any(n in k for n in ("kxu_tile_kernel", "cheb3d_kernel",
+                                                                    "cheb2_kernel"))}):
         fk = fetch[mode_key]
         wk = write.get(mode_key, [])
         if not wk:
             continue
-        # the finest grid's launches are the largest of each kernel variant
+        # the finest grid's launches are the largest of each K*u variant (the
+        # coarse Chebyshev pairs all run on the coarsest grid; launches that
+        # met the CG stop flag read almost nothing)
         fmax, wmax = max(fk), max(wk)
         rec["kernels"][mode_key] = {"fetch_bytes": fmax * 1024 * f_scale,
                                     "write_bytes": wmax * 1024 * w_scale,

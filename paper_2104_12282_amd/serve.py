@@ -262,12 +262,13 @@ def run_engine_batched(requests, arrivals=None, *, device="cuda:0", nslots=16, n
                 stream = streams[len(classes) % n_streams]
                 with torch.cuda.stream(stream):
                     b = fe.Batch(*g, nslots, device=device, stream=stream, **cfg_kw)
-                c = classes[g] = {"batch": b, "free": list(range(nslots - 1, -1, -1)), "live": {}}
+                c = classes[g] = {"batch": b, "free": list(range(nslots - 1, -1, -1)), "live": {}, "open": False}
                 used += nbytes
                 peak = max(peak, used)
             if c["free"] and used + per_request_bytes(g) > hbm_budget:
                 release_idle(g)
-            if not c["free"] or used + per_request_bytes(g) > hbm_budget:
+            # a slot is set up only between its batch's rounds
+            if c["open"] or not c["free"] or used + per_request_bytes(g) > hbm_budget:
                 rest.append((t_arr, req))
                 continue
             slot = c["free"].pop()
@@ -293,12 +294,16 @@ def run_engine_batched(requests, arrivals=None, *, device="cuda:0", nslots=16, n
         queue = rest
         max_q = max(max_q, len(queue))
         max_act = max(max_act, sum(len(c["live"]) for c in classes.values()))
-        # one round of every batch with running designs, overlapping
-        active = [c for c in classes.values() if c["live"]]
+        # every batch runs its rounds on its own stream: a batch whose round
+        # has completed is advanced and started again at once, without
+        # waiting for the rounds of the other sizes
+        active = [c for c in classes.values() if c["live"] or c["open"]]
         for c in active:
-            c["batch"].round_begin()
-        for c in active:
-            c["batch"].round_end()
+            if c["open"]:
+                if not c["batch"].round_ready():
+                    continue
+                c["batch"].round_end()
+                c["open"] = False
             for slot, rec in list(c["live"].items()):
                 if not rec["prob"].solve_step():
                     continue
@@ -311,6 +316,9 @@ def run_engine_batched(requests, arrivals=None, *, device="cuda:0", nslots=16, n
                 finishing.append((rec, ev))
                 del c["live"][slot]
                 c["free"].append(slot)  # stream order: the next design's setup follows the sensitivity
+            if c["live"]:
+                c["batch"].round_begin()
+                c["open"] = True
         still = []
         for rec, ev in finishing:
             if not ev.query():
