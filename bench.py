@@ -95,7 +95,7 @@ def traffic_from_profiles(precision: str, grid: str, field: str = "bytes", want:
     by a copy of known size (field "bytes"), or rocprofv3's average kernel
     duration of that launch in us (field "trace_work_avg_us"), when the stored
     figures were taken on the current kernel source; else None."""
-    path = os.path.join(ROOT, "profiles", f"kxu_tile_{grid}_traffic.json")
+    path = os.path.join(ROOT, "profiles", f"loop_kernels_{grid}_traffic.json")
     if not os.path.exists(path):
         return None
     try:
@@ -115,7 +115,7 @@ def traffic_from_profiles(precision: str, grid: str, field: str = "bytes", want:
 def profile_record(grid: str):
     """The stored rocprofv3 figures of this grid when they were taken on the
     current kernel source, else None."""
-    path = os.path.join(ROOT, "profiles", f"kxu_tile_{grid}_traffic.json")
+    path = os.path.join(ROOT, "profiles", f"loop_kernels_{grid}_traffic.json")
     if not os.path.exists(path):
         return None
     try:
