@@ -21,7 +21,7 @@
 #define FE_IR_FLOOR 1e-5  // refinement: tightest relative tolerance asked of a float32 inner solve
 #endif
 #ifndef FE_IR_PHASE
-#define FE_IR_PHASE 1e-2  // refinement with residual replacement: reduction of the residual per phase
+#define FE_IR_PHASE 3e-2  // refinement with residual replacement: reduction of the residual per phase
 #endif
 #ifndef FE_IR_RESUME
 #define FE_IR_RESUME 1  // refinement: continue the float32 CG with the float64 residual (no restart)
