@@ -517,8 +517,15 @@ fe_status advance(fe_problem* p) {
       // a float32 CG that will go on by residual replacement stops after a
       // reduction of FE_IR_PHASE, while its recurrence still tracks the
       // float64 residual to a small fraction
+      // With the bf16 contraction the inner operator itself is off by about
+      // a tenth of the residual it works on (8-bit operands, rounded after
+      // the brick's rigid motion is removed: a nonlinear perturbation of K),
+      // so a refinement step cannot cut the float64 residual by much more
+      // than 10: its inner solve stops there too
       double itol = FE_IR_FACTOR * sc.rtol / rel;
-      const double floor = (kResumeInner && folded_mg(p)) ? FE_IR_PHASE : FE_IR_FLOOR;
+      const double floor = p->cfg.precision == FE_PREC_BF16_IR          ? FE_IR_FLOOR_BF16
+                           : (kResumeInner && folded_mg(p)) ? FE_IR_PHASE
+                                                            : FE_IR_FLOOR;
       if (itol < floor) itol = floor;
       if (itol > 1e-1) itol = 1e-1;
       HIP_TRY(hipMemcpyAsync(p->scal + 2 * SLOT_IRS, p->scal + 2 * SLOT_RR, sizeof(double),

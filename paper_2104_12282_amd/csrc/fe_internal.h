@@ -20,6 +20,9 @@
 #ifndef FE_IR_FLOOR
 #define FE_IR_FLOOR 1e-5  // refinement: tightest relative tolerance asked of a float32 inner solve
 #endif
+#ifndef FE_IR_FLOOR_BF16
+#define FE_IR_FLOOR_BF16 1e-1  // refinement over the bf16 contraction: tightest inner tolerance
+#endif
 #ifndef FE_IR_PHASE
 #define FE_IR_PHASE 3e-2  // refinement with residual replacement: reduction of the residual per phase
 #endif

@@ -6,8 +6,13 @@ initial parameters and mini-batches.
 
 Tolerances: the GPU computes in float32, the oracle in float64; the first
 batch loss (forward only) agrees to float32 rounding (1e-5 relative); later
-steps differ by Adam's amplification of rounding in the updates, bounded
-here by 2% of the loss and 2% of the target scale for the predictions.
+steps differ by Adam's amplification of rounding in the updates (its
+per-parameter normalisation turns a rounding of a small gradient into a
+step of up to the learning rate).  Measured over these 60 steps: at most
+2.4e-6 of the first loss and 1.7e-6 of the target scale for the
+predictions; the bound is 1e-4 for both (a larger network, width 1000,
+drifts by tens of percent over 60 steps at this learning rate, which is
+why the cases stay small).
 Inputs and targets of an iteration are scaled by that iteration's largest
 |u_C| and |dJ/dz|; predictions come in units of the latter."""
 import numpy as np
@@ -96,13 +101,13 @@ def test_update_matches_oracle(grid, nb, width, batch):
     losses = N(m.train(idx, lr0=1e-2, halve_every=20))
     p_ref, losses_ref = S.adam_train(f32(p0), sizes, DX, DY, idx, 1e-2, 20)
     assert abs(losses[0] - losses_ref[0]) <= 1e-5 * losses_ref[0]
-    assert np.all(np.abs(losses - losses_ref) <= 0.02 * losses_ref[0])
+    assert np.all(np.abs(losses - losses_ref) <= 1e-4 * losses_ref[0])
     assert losses_ref[-10:].mean() < losses_ref[0]
     # predictions of the trained networks on the last iteration's design
     pred = N(m.predict(T(z), T(uc)))
     acts = S.forward(p_ref, sizes, S.block_samples(nx, ny, nz, nb, z, uc, s_u=np.abs(uc).max())[0])
     pred_ref = S.scatter_blocks(nx, ny, nz, nb, acts[-1])
-    assert np.abs(pred - pred_ref).max() <= 0.02 * np.abs(DY).max()
+    assert np.abs(pred - pred_ref).max() <= 1e-4 * np.abs(DY).max()
     m.close()
 
 
