@@ -307,11 +307,11 @@ hipError_t cg_iteration(fe_problem* p, T* x, T* r, T* pv, T* q, int it) {
 }
 
 template <typename T>
-GraphChunk& chunk_of(fe_problem* p);
+GraphChunk& chunk_of(fe_problem* p, int v);
 template <>
-GraphChunk& chunk_of<double>(fe_problem* p) { return p->chunk64; }
+GraphChunk& chunk_of<double>(fe_problem* p, int v) { return p->chunk64[v]; }
 template <>
-GraphChunk& chunk_of<float>(fe_problem* p) { return p->chunk32; }
+GraphChunk& chunk_of<float>(fe_problem* p, int v) { return p->chunk32[v]; }
 
 void drop_graph(GraphChunk& gc) {
   if (gc.exec) (void)hipGraphExecDestroy(gc.exec);
@@ -321,14 +321,59 @@ void drop_graph(GraphChunk& gc) {
   gc.bytes.clear();
 }
 
-// Enqueues a chunk of CG iterations on p->stream.  The chunk is captured once
-// per problem and vector type as a HIP graph (on a private stream, then
-// replayed on p->stream); with profiling on, the graph carries its own event
-// pairs around each fine-grid K*u launch.
+void drop_chunks(fe_problem* p) {
+  for (int v = 0; v < 4; ++v) {
+    drop_graph(p->chunk64[v]);
+    drop_graph(p->chunk32[v]);
+  }
+}
+
+// Full chunk length; chunk variant v (0..3) runs (v + 1) / 4 of it.  Every
+// length is even, so a chunk ends with the direction in the buffer it
+// started from.
+int full_chunk(const fe_problem* p) { return p->nlev > 1 ? kChunkMG : kChunk; }
+
+// Chunk plan at a chunk boundary of a running CG.  Iterations enqueued past
+// the stop run as early exits (tens of launches each, a few microseconds
+// apiece) and a chunk that ends short of the stop costs a host round trip,
+// so the iterations still needed -- from the residual's rate over the last
+// chunk, or the previous phase's rate at the start of one -- pick the
+// shortest chunk that covers them with one to spare; far from the stop two
+// full chunks go out back to back (one round trip for both).  Returns the
+// variant and sets *replays (1 or 2).
+int plan_chunk(fe_problem* p, const CgState& hs, int* replays) {
+  SolveCtx& sc = p->sc;
+  *replays = 1;
+  // at the first boundary after a residual replacement, hs.rr is still the
+  // recurrence's old value: the mark holds the replaced one
+  const bool fresh = hs.iter == sc.mark_iter;
+  const double rr = fresh ? sc.mark_rr : hs.rr;
+  if (!fresh && sc.mark_iter >= 0 && hs.iter > sc.mark_iter && sc.mark_rr > 0.0 && hs.rr > 0.0)
+    sc.rate = std::pow(hs.rr / sc.mark_rr, 1.0 / (double)(hs.iter - sc.mark_iter));
+  if (!fresh) {
+    sc.mark_rr = hs.rr;
+    sc.mark_iter = hs.iter;
+  }
+  const int full = full_chunk(p);
+  if (!(sc.rate > 0.0 && sc.rate < 1.0) || !(hs.tol2 > 0.0) || !(rr > hs.tol2)) return 3;
+  const double need = std::log(hs.tol2 / rr) / std::log(sc.rate) + 1.0;
+  if (need >= 2.5 * full && !p->kst.on) {  // profiled replays are harvested one at a time
+    *replays = 2;
+    return 3;
+  }
+  const int v = (int)std::ceil(need / (full / 4)) - 1;
+  return v < 0 ? 0 : v > 3 ? 3 : v;
+}
+
+// Enqueues a chunk of CG iterations (variant v: (v + 1) / 4 of the full
+// length) on p->stream.  The chunk is captured once per problem, vector type
+// and length as a HIP graph (on a private stream, then replayed on
+// p->stream); with profiling on, the graph carries its own event pairs
+// around each fine-grid K*u launch.
 template <typename T>
-hipError_t enqueue_chunk(fe_problem* p, T* x, T* r, T* pv, T* q) {
-  const int n = p->nlev > 1 ? kChunkMG : kChunk;
-  GraphChunk& gc = chunk_of<T>(p);
+hipError_t enqueue_chunk(fe_problem* p, T* x, T* r, T* pv, T* q, int v = 3) {
+  const int n = (v + 1) * (full_chunk(p) / 4);
+  GraphChunk& gc = chunk_of<T>(p, v);
   const bool prof = p->kst.on;
   if (p->use_graphs && p->cap_stream) {
     if (!gc.exec || gc.prof != prof) {
@@ -462,7 +507,9 @@ fe_status advance(fe_problem* p) {
       const CgState hs = *p->h_st;
       if (!hs.done) {
         if (p->in_batch) return FE_OK;  // the batch's next replay runs the chunk
-        HIP_TRY(enqueue_chunk<double>(p, p->x64, p->r64, p->p64, p->q64));
+        int reps = 1;
+        const int v = plan_chunk(p, hs, &reps);
+        for (int k = 0; k < reps; ++k) HIP_TRY(enqueue_chunk<double>(p, p->x64, p->r64, p->p64, p->q64, v));
         return copy_state(p);
       }
       sc.info.iters = hs.iter;
@@ -509,6 +556,8 @@ fe_status advance(fe_problem* p) {
         HIP_TRY(launch_vcycle<float>(p, 0, p->r32, static_cast<float*>(p->L[0].mg_z), p->st, RZ_PARTIALS, 0));
         sc.inner_base = sc.total - hs.iter;
         sc.chunk_iter0 = hs.iter;
+        sc.mark_rr = scaled * scaled;  // the replaced residual, in the inner system's units
+        sc.mark_iter = hs.iter;
         sc.can_resume = false;
         sc.stage = ST_IR_CG;
         return copy_state(p);
@@ -537,6 +586,7 @@ fe_status advance(fe_problem* p) {
       HIP_TRY(enqueue_start<float>(p, p->r32, nullptr, p->r32, p->p32));
       sc.inner_base = sc.total;
       sc.chunk_iter0 = 0;
+      sc.mark_iter = -1;
       sc.stage = ST_IR_CG;
       return copy_state(p);
     }
@@ -545,7 +595,9 @@ fe_status advance(fe_problem* p) {
       if (!hs.done) {
         sc.chunk_iter0 = hs.iter;  // the next chunk starts at this iteration
         if (p->in_batch) return FE_OK;  // the batch's next replay runs the chunk
-        HIP_TRY(enqueue_chunk<float>(p, p->x32, p->r32, p->p32, p->q32));
+        int reps = 1;
+        const int v = plan_chunk(p, hs, &reps);
+        for (int k = 0; k < reps; ++k) HIP_TRY(enqueue_chunk<float>(p, p->x32, p->r32, p->p32, p->q32, v));
         return copy_state(p);
       }
       sc.total = sc.inner_base + hs.iter;
@@ -1089,8 +1141,7 @@ extern "C" fe_status fe_set_mg_params(fe_problem* p, int32_t nu, int32_t coarse_
   p->mg_coarse_sweeps = coarse_sweeps;
   p->mg_omega = omega;
   p->cheb_ratio = coarse_ratio;
-  drop_graph(p->chunk64);  // the captured chunks bake these in
-  drop_graph(p->chunk32);
+  drop_chunks(p);  // the captured chunks bake these in
   return FE_OK;
 }
 
@@ -1105,8 +1156,7 @@ extern "C" fe_status fe_set_float32_levels(fe_problem* p, int32_t first_level) {
     return FE_EINVAL;
   }
   p->f32_from = first_level;
-  drop_graph(p->chunk64);  // the captured chunks bake the path in
-  drop_graph(p->chunk32);
+  drop_chunks(p);  // the captured chunks bake the path in
   return FE_OK;
 }
 
@@ -1131,8 +1181,7 @@ extern "C" fe_status fe_set_coarse_fusion(fe_problem* p, int32_t steps_per_launc
     return FE_EINVAL;
   }
   p->cheb_per_launch = steps_per_launch;
-  drop_graph(p->chunk64);
-  drop_graph(p->chunk32);
+  drop_chunks(p);
   return FE_OK;
 }
 
@@ -1156,8 +1205,7 @@ extern "C" fe_status fe_set_cache_flush(fe_problem* p, void* buf, size_t bytes) 
   p->kst.flush = buf ? static_cast<uint32_t*>(buf) : nullptr;
   p->kst.flush_words = buf ? bytes / sizeof(uint32_t) : 0;
   // captured chunks carry the flush launches only if captured with it
-  drop_graph(p->chunk64);
-  drop_graph(p->chunk32);
+  drop_chunks(p);
   return FE_OK;
 }
 
@@ -1190,8 +1238,7 @@ extern "C" fe_status fe_kernel_stats(fe_problem* p, int32_t reset, int64_t* laun
 extern "C" void fe_destroy(fe_problem* p) {
   if (!p) return;
   if (p->stream) (void)hipStreamSynchronize(p->stream);
-  drop_graph(p->chunk64);
-  drop_graph(p->chunk32);
+  drop_chunks(p);
   drop_oc_graph(p->ocg);
   for (hipEvent_t e : p->kst.ev) (void)hipEventDestroy(e);
   if (p->done_ev) (void)hipEventDestroy(p->done_ev);

@@ -142,6 +142,9 @@ struct SolveCtx {
   int inner_base = 0;           // refinement iterations before the running float32 CG
   int chunk_iter0 = 0;          // CG iteration at which the last chunk started
   double inner_rr = 0.0;        // ||r||^2 the running float32 CG is scaled by
+  double mark_rr = 0.0;         // ||r||^2 of the running CG at iteration mark_iter
+  int mark_iter = -1;           // (-1: none yet) -- its convergence rate sizes the next chunk
+  double rate = 0.0;            // ||r||^2 ratio per CG iteration last measured (0: none)
   fe_status result = FE_OK;
   fe_solve_info info{};
 };
@@ -195,7 +198,9 @@ struct fe_problem {
   double* h_scal = nullptr;     // pinned, 4 values
   hipEvent_t done_ev = nullptr;
   hipStream_t cap_stream = nullptr;
-  GraphChunk chunk64, chunk32;
+  // captured CG chunks per vector type, one per length: q, 2q, 3q, 4q
+  // iterations (q = a quarter of the full chunk, an even number)
+  GraphChunk chunk64[4], chunk32[4];
   OcGraph ocg;
   GraphChunk* last_replay = nullptr;  // profiled graph replayed since the last harvest
   bool use_graphs = true;
