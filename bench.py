@@ -36,7 +36,7 @@ def parse():
     ap.add_argument("--precision", default="fp64", choices=["fp64", "fp32_ir", "bf16_ir", "bf16x3_ir"])
     ap.add_argument("--alt-precision", default="fp32_ir", choices=["none", "fp64", "fp32_ir", "bf16_ir", "bf16x3_ir"])
     ap.add_argument("--precond", default="gmg", choices=["jacobi", "gmg"])
-    ap.add_argument("--mg-levels", type=int, default=3)
+    ap.add_argument("--mg-levels", type=int, default=4)
     ap.add_argument("--mg-nu", type=int, default=1)
     ap.add_argument("--mg-coarse", type=int, default=0,
                     help="coarsest-level Chebyshev degree (0: the library's default for the coarsest grid)")
@@ -45,6 +45,15 @@ def parse():
                          "0: all, the finest level's smoothing included; the number of levels: none)")
     ap.add_argument("--mg-coarse-ratio", type=float, default=0.0,
                     help="coarsest-level Chebyshev interval ratio (0: the library's default)")
+    ap.add_argument("--study-mg-levels", type=int, default=3,
+                    help="multigrid levels of the paper-mesh, synthetic-gradient and two-scale coarse solves "
+                         "(smaller grids: three levels)")
+    ap.add_argument("--mg-cheb-from", type=int, default=-1,
+                    help="first level smoothed by Chebyshev steps (-1: the library default; 0: damped Jacobi "
+                         "on every level)")
+    ap.add_argument("--mg-cheb-deg", type=int, default=6, help="Chebyshev smoothing steps (with --mg-cheb-from)")
+    ap.add_argument("--mg-cheb-ratio", type=float, default=30.0,
+                    help="Chebyshev smoothing interval ratio (with --mg-cheb-from)")
     ap.add_argument("--coarse-form", type=int, default=0,
                     help="coarsest-level Chebyshev launch form (0: the library's automatic choice; 3: pairs of "
                          "steps on 3D tiles, 2: pairs on z-marching tiles, 1: one step per launch)")
@@ -54,8 +63,9 @@ def parse():
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--precision-seeds", type=int, default=4,
                     help="seeded smoothed densities of the precision study (0 = skip it)")
-    ap.add_argument("--mg4", type=int, default=1,
-                    help="also run the float64 loop with a 4-level hierarchy (context line)")
+    ap.add_argument("--mg-context", type=int, default=1,
+                    help="also run the loop with the other hierarchy (3 levels with damped Jacobi smoothing "
+                         "when the headline runs 4, else 4) as a context line")
     ap.add_argument("--two-scale", type=int, default=1,
                     help="time the coarse-scale solves of the two-scale scheme beside the fine solve")
     ap.add_argument("--adjoint", type=int, default=1,
@@ -138,7 +148,9 @@ def apply_mg(prob, args):
     cur = prob.mg_params()
     prob.set_mg_params(nu=args.mg_nu, coarse_sweeps=args.mg_coarse or cur["coarse_sweeps"], omega=cur["omega"],
                        coarse_ratio=args.mg_coarse_ratio or cur["coarse_ratio"])
-    return prob.mg_params()
+    if args.mg_cheb_from == 0 or 1 <= args.mg_cheb_from <= prob.cfg.mg_levels - 2:
+        prob.set_mg_smoother(args.mg_cheb_from, args.mg_cheb_deg, args.mg_cheb_ratio)
+    return dict(prob.mg_params(), smoother=prob.mg_smoother())
 
 
 def coarse_solve_record(nx, ny, nz, args, degree):
@@ -438,7 +450,7 @@ def two_scale_study(fe, synth, torch, nx, ny, nz, args, block_sizes=(2, 4, 5, 7,
         if nx % nb or ny % nb or nz % nb:
             continue
         cx, cy, cz = nx // nb, ny // nb, nz // nb
-        pc = fine.coarse_problem(nb, T(synth.cantilever_edge_load(cx, cy, cz)))
+        pc = fine.coarse_problem(nb, T(synth.cantilever_edge_load(cx, cy, cz)), mg_levels=args.study_mg_levels)
         apply_mg(pc, args)
         zc = torch.empty(cx * cy * cz, dtype=torch.float64, device=dev)
         coarse[nb] = {"prob": pc, "zc": zc, "rc": torch.empty_like(zc),
@@ -577,7 +589,7 @@ def paper_mesh_study(fe, synth, torch, args, iters):
     for nx in (70, 100, 180):
         ny = nz = nx // 2
         h = 2.0 / nx
-        levels = args.mg_levels
+        levels = args.study_mg_levels
         precond = args.precond
         prob = fe.Problem(nx, ny, nz, T(synth.cantilever_edge_load(nx, ny, nz)), device=dev, h=h,
                           filter_r=0.08 / h, precision=args.precision, precond=precond,
@@ -639,7 +651,8 @@ def onsg_study(fe, synth, torch, args, K, nb=5, width=1000, steps=2000, batch=25
 
     def make():
         prob = fe.Problem(nx, ny, nz, T(synth.cantilever_edge_load(nx, ny, nz)), device=dev, h=h,
-                          filter_r=0.08 / h, precision=args.precision, precond="gmg", mg_levels=args.mg_levels)
+                          filter_r=0.08 / h, precision=args.precision, precond="gmg",
+                          mg_levels=args.study_mg_levels)
         return prob
 
     def run(onsg):
@@ -983,6 +996,7 @@ def main():
                    "mg_smoothing_sweeps": args.mg_nu if args.precond == "gmg" else None,
                    "mg_coarse_chebyshev_degree": rec["mg"]["coarse_sweeps"] if rec["mg"] else None,
                    "mg_coarse_chebyshev_ratio": rec["mg"]["coarse_ratio"] if rec["mg"] else None,
+                   "mg_chebyshev_smoothing": rec["mg"]["smoother"] if rec["mg"] else None,
                    "preconditioner_float32_from_level": ((args.f32_from if args.f32_from >= 0 else 0)
                                                          if args.precision == "fp64" else 0) if rec["mg"] else None,
                    "rtol": args.rtol, "volfrac": args.volfrac, "filter_r": 1.5, "move": args.move,
@@ -1017,14 +1031,15 @@ def main():
                                    profile=False)
         out["fp64_preconditioner_context"] = {"value": args.steps / dt6, "ms_per_step": 1e3 * dt6 / args.steps,
                                               "cg_iters_per_solve": float(np.mean(rec6["iters"]))}
-    if args.mg4 and args.precond == "gmg" and args.mg_levels != 4 and nx % 8 == 0 and ny % 8 == 0 \
-            and nz % 8 == 0:
-        a4 = argparse.Namespace(**{**vars(args), "mg_levels": 4})
+    if args.mg_context and args.precond == "gmg":
+        lv = 3 if args.mg_levels == 4 else 4
+        a4 = argparse.Namespace(**{**vars(args), "mg_levels": lv, "mg_coarse": 0, "mg_cheb_from": -1})
         dt4, rec4, _, _ = run_loop(fe, synth, torch, nx, ny, nz, args.precision, a4, args.steps, 1,
                                    profile=False)
-        out["gmg4_context"] = {"precision": args.precision, "mg_levels": 4, "value": args.steps / dt4,
-                               "ms_per_step": 1e3 * dt4 / args.steps,
-                               "cg_iters_per_solve": float(np.mean(rec4["iters"]))}
+        out[f"gmg{lv}_context"] = {"precision": args.precision, "mg_levels": lv, "value": args.steps / dt4,
+                                   "ms_per_step": 1e3 * dt4 / args.steps,
+                                   "cg_iters_per_solve": float(np.mean(rec4["iters"])),
+                                   "mg": rec4["mg"]}
     if args.c2:
         out["c2_jacobi"] = c2_study(fe, synth, torch, flush=flush)
     if args.precision_seeds > 0:

@@ -261,6 +261,27 @@ FE_API fe_status fe_block_mean(fe_problem* p, const double* z, int32_t nb, doubl
 FE_API fe_status fe_set_mg_params(fe_problem* p, int32_t nu, int32_t coarse_sweeps, double omega,
                            double coarse_ratio);
 
+/* Smoothing of the levels between the finest and the coarsest.  With
+ * cheb_from_level = k (1 <= k <= levels - 2), levels k .. levels - 2 are
+ * smoothed by `degree` steps of Jacobi-preconditioned Chebyshev iteration on
+ * [lambda_max / ratio, 1.02 lambda_max] (lambda_max as in fe_set_mg_params)
+ * instead of damped Jacobi sweeps: from zero before the coarse correction
+ * (the restricted residual is the iteration's own), and on the residual
+ * r - K z after it (the same polynomial in D^-1 K times D^-1, so the cycle
+ * stays symmetric; the Chebyshev residual polynomial stays below 1 in
+ * magnitude on the whole spectrum, so the smoother converges for any
+ * ratio).  The steps run in the launches the coarsest-level solve uses
+ * (fe_set_coarse_fusion).  cheb_from_level = 0: damped Jacobi on every
+ * level (degree and ratio ignored).  Default: level 2 on, degree 6, ratio
+ * 100, for hierarchies of four or more levels whose coarsest grid has 24 or
+ * more elements along its longest axis; off otherwise.  FE_EINVAL
+ * for other values and on batch slots.  fe_get_mg_smoother returns the
+ * setting in effect (0: off); its output pointers are host memory and may
+ * be NULL. */
+FE_API fe_status fe_set_mg_smoother(fe_problem* p, int32_t cheb_from_level, int32_t degree, double ratio);
+FE_API fe_status fe_get_mg_smoother(const fe_problem* p, int32_t* cheb_from_level, int32_t* degree,
+                             double* ratio);
+
 /* Levels first_level .. nlev-1 of the multigrid preconditioner of
  * FE_PREC_FP64 solves run in float32 on their float32 moduli and inverse
  * diagonals.  first_level = 0 (default): the whole V-cycle, the finest

@@ -23,6 +23,13 @@
 #ifndef FE_IR_FLOOR_BF16
 #define FE_IR_FLOOR_BF16 1e-1  // refinement over the bf16 contraction: tightest inner tolerance
 #endif
+#define FE_CS_OFF 99  // first multigrid level smoothed by Chebyshev steps: none
+#ifndef FE_CS_DEG
+#define FE_CS_DEG 6  // default Chebyshev smoothing steps
+#endif
+#ifndef FE_CS_RATIO
+#define FE_CS_RATIO 100.0  // default Chebyshev smoothing interval ratio
+#endif
 #ifndef FE_IR_PHASE
 #define FE_IR_PHASE 3e-2  // refinement with residual replacement: reduction of the residual per phase
 #endif
@@ -86,7 +93,8 @@ struct Level {
   void* mg_z = nullptr;
   void* mg_t = nullptr;
   void* mg_w = nullptr;
-  void* mg_q = nullptr;  // coarsest level only: second residual of the fused Chebyshev steps
+  void* mg_q = nullptr;  // levels below the finest: second residual of the fused Chebyshev steps
+  void* mg_s = nullptr;  // levels between the finest and the coarsest: third residual
 };
 
 struct KStats {
@@ -215,6 +223,11 @@ struct fe_problem {
   double mg_omega = 0.35;      // Jacobi damping: below 2 / lambda_max(D^-1 Ke) = 2 / 5.32
   double lam_max = 0.0;        // lambda_max(diag(Ke)^-1 Ke): bounds that of D^-1 K on every level
   double cheb_ratio = 5000.0;  // coarse Chebyshev interval [lam_max / ratio, lam_max]
+  // Chebyshev smoothing (instead of damped Jacobi) on levels cs_from .. nlev - 2:
+  // cs_deg steps before and after the coarse correction on [lam_max / cs_ratio, lam_max]
+  int cs_from = FE_CS_OFF;
+  int cs_deg = FE_CS_DEG;
+  double cs_ratio = FE_CS_RATIO;
   int cheb_per_launch = FE_CHEB_FORM;  // coarse Chebyshev launches: 3 / 4 pairs of steps on 3D tiles of
                                       // 4 x 4 x 4 / 4 x 4 x 8 nodes, 2 pairs on z-marching tiles, 1 one
                                       // step each, 0 chosen per launch
@@ -318,10 +331,15 @@ int64_t kxu_tile_blocks(const Grid& g);
 // direction dk, residual rin and iterate acc (in place) to the direction
 // y = d_{k+2} and residual rout (rin and rout must differ); c = c1, c2 of
 // step k, then of step k + 1; first: step k starts the iterate.  The result
-// is bitwise that of two mode-6 launches.
+// is bitwise that of two mode-6 launches.  dscale != 0: d_k is not read but
+// formed in the launch as dscale D^-1 r_k (the first direction; only the 3D
+// tile forms do, see cheb2_forms_first_direction; hipErrorInvalidValue
+// otherwise).
 template <typename T>
 hipError_t launch_cheb2(fe_problem* p, int lev, const T* dk, T* y, const T* E, const T* invd, const T* rin,
-                        T* rout, T* acc, const double (&c)[4], int first, CgState* st);
+                        T* rout, T* acc, const double (&c)[4], int first, CgState* st, double dscale = 0.0);
+template <typename T>
+bool cheb2_forms_first_direction(const fe_problem* p, int lev);
 // Number of r^T z partials the level's last smoothing sweep (mode 5) leaves.
 template <typename T>
 int kxu_rz_partials(const fe_problem* p, int lev);

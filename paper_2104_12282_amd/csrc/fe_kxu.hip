@@ -720,6 +720,7 @@ struct Cheb2 {
   T c1a, c2a;  // step k: d_{k+1} = c1a d_k + c2a D^-1 r_{k+1}
   T c1b, c2b;  // step k + 1
   int first;   // step k is the first (the iterate starts at zero)
+  T dscale;    // 3D tiles: nonzero = d_k is not read but formed as dscale D^-1 r_k (the first direction)
 };
 
 constexpr int OWN2 = 13;  // node columns per direction a fused workgroup finishes
@@ -1202,6 +1203,7 @@ __global__ void __launch_bounds__(C3<OZ>::THREADS) cheb3d_kernel(Grid g, int gx,
     T d[3], r[3], iv;
     uint8_t m;
   };
+  const bool form_d = cf.dscale != T(0);
   auto load_node = [&](int n, NodeIn& v) {
     const int i = I0 + n % C3_IN, j = J0 + (n / C3_IN) % C3_IN, k = K0 + n / (C3_IN * C3_IN);
     const bool in = n < Q::NIN && i >= 0 && i <= g.nx && j >= 0 && j <= g.ny && k >= 0 && k <= g.nz;
@@ -1213,17 +1215,18 @@ __global__ void __launch_bounds__(C3<OZ>::THREADS) cheb3d_kernel(Grid g, int gx,
       const int64_t node = i + sx * j + sxy * k;
 #pragma unroll
       for (int c = 0; c < 3; ++c) {
-        v.d[c] = dk[3 * node + c];
+        if (!form_d) v.d[c] = dk[3 * node + c];
         v.r[c] = rin[3 * node + c];
       }
       v.iv = invd[node];
       v.m = nmask[node];
     }
   };
+  // the formed first direction rounds as the separate first-direction launch does
   auto store_node = [&](int n, const NodeIn& v) {
 #pragma unroll
     for (int c = 0; c < 3; ++c) {
-      sD0[c][n] = v.d[c];
+      sD0[c][n] = form_d ? cf.dscale * v.iv * v.r[c] : v.d[c];
       sR[c][n] = v.r[c];
     }
     sInv[n] = v.iv;
@@ -1635,9 +1638,30 @@ int kxu_rz_partials(const fe_problem* p, int lev) {
 template int kxu_rz_partials<double>(const fe_problem*, int);
 template int kxu_rz_partials<float>(const fe_problem*, int);
 
+// Launch form of a pair of coarse Chebyshev steps on level lev (see fe_set_coarse_fusion).
+static int cheb2_form(const fe_problem* p, int lev, bool tall) {
+  const Grid g = p->L[lev].g;
+  const int gx = (g.nx + C3_OWN) / C3_OWN, gy = (g.ny + C3_OWN) / C3_OWN;
+  const int64_t n4 = (int64_t)gx * gy * ((g.nz + 4) / 4), n8 = (int64_t)gx * gy * ((g.nz + 8) / 8);
+  // automatic form: 3D tiles while every workgroup of the launch (all batch
+  // slots) gets a compute unit of its own, the shorter blocks first; beyond
+  // that workgroups share units and the z-marching tiles are faster
+  // (measured on the 56 x 28 x 14 coarsest grid of 224 x 112 x 56 with
+  // 4 x 4 x 4 blocks: 480 workgroups)
+  // (4 x 4 x 8 blocks only in float32: in float64 their LDS exceeds a workgroup's 160 KB)
+  if (p->cheb_per_launch != 0) return p->cheb_per_launch;
+  const int64_t cus = device_cus();
+  return n4 * p->bcount <= cus ? 3 : (tall && n8 * p->bcount <= cus) ? 4 : 2;
+}
+
+template <typename T>
+bool cheb2_forms_first_direction(const fe_problem* p, int lev) {
+  return cheb2_form(p, lev, sizeof(T) == 4) >= 3;
+}
+
 template <typename T>
 hipError_t launch_cheb2(fe_problem* p, int lev, const T* dk, T* y, const T* E, const T* invd, const T* rin,
-                        T* rout, T* acc, const double (&c)[4], int first, CgState* st) {
+                        T* rout, T* acc, const double (&c)[4], int first, CgState* st, double dscale) {
   const Grid g = p->L[lev].g;
   Cheb2<T> cf;
   cf.c1a = (T)c[0];
@@ -1645,19 +1669,13 @@ hipError_t launch_cheb2(fe_problem* p, int lev, const T* dk, T* y, const T* E, c
   cf.c1b = (T)c[2];
   cf.c2b = (T)c[3];
   cf.first = first;
+  cf.dscale = (T)dscale;
   // 3D tiles of 4 x 4 x 4 or 4 x 4 x 8 owned nodes
   const int gx = (g.nx + C3_OWN) / C3_OWN, gy = (g.ny + C3_OWN) / C3_OWN;
   const int64_t n4 = (int64_t)gx * gy * ((g.nz + 4) / 4), n8 = (int64_t)gx * gy * ((g.nz + 8) / 8);
-  const int64_t cus = device_cus();
-  // automatic form: 3D tiles while every workgroup of the launch (all batch
-  // slots) gets a compute unit of its own, the shorter blocks first; beyond
-  // that workgroups share units and the z-marching tiles are faster
-  // (measured on the 56 x 28 x 14 coarsest grid of 224 x 112 x 56 with
-  // 4 x 4 x 4 blocks: 480 workgroups)
-  // (4 x 4 x 8 blocks only in float32: in float64 their LDS exceeds a workgroup's 160 KB)
   constexpr bool tall = sizeof(T) == 4;
-  int form = p->cheb_per_launch;
-  if (form == 0) form = n4 * p->bcount <= cus ? 3 : (tall && n8 * p->bcount <= cus) ? 4 : 2;
+  const int form = cheb2_form(p, lev, tall);
+  if (dscale != 0.0 && form < 3) return hipErrorInvalidValue;  // only the 3D tiles form the first direction
   if (form >= 3) {
     const bool oz4 = form == 3 || !tall;
     const int64_t nblk = oz4 ? n4 : n8, per = (nblk + 7) / 8;
@@ -1684,9 +1702,12 @@ hipError_t launch_cheb2(fe_problem* p, int lev, const T* dk, T* y, const T* E, c
   return hipGetLastError();
 }
 template hipError_t launch_cheb2<double>(fe_problem*, int, const double*, double*, const double*, const double*,
-                                         const double*, double*, double*, const double (&)[4], int, CgState*);
+                                         const double*, double*, double*, const double (&)[4], int, CgState*,
+                                         double);
 template hipError_t launch_cheb2<float>(fe_problem*, int, const float*, float*, const float*, const float*,
-                                        const float*, float*, float*, const double (&)[4], int, CgState*);
+                                        const float*, float*, float*, const double (&)[4], int, CgState*, double);
+template bool cheb2_forms_first_direction<double>(const fe_problem*, int);
+template bool cheb2_forms_first_direction<float>(const fe_problem*, int);
 
 template <typename T>
 hipError_t launch_kxu_tile(fe_problem* p, int lev, const T* x, const T* E, T* y, CgState* st, int mode,

@@ -254,52 +254,71 @@ static inline double cheb_theta(const fe_problem* p) {
   return 0.5 * (b + a);
 }
 
-// Coarsest-level solve: `deg` steps of Jacobi-preconditioned Chebyshev
-// iteration from z = 0 on the interval [lam_max / ratio, lam_max], where
-// lam_max bounds the spectrum of D^-1 K from above.  The result is a fixed
-// polynomial in D^-1 K applied to D^-1 r: linear, symmetric and (since the
-// Chebyshev residual polynomial stays inside (0, 1) below the interval and
-// below 1 in magnitude on it) positive definite.  r and the level's mg_q
-// buffer are overwritten (the residual of the iteration).
+// `deg` steps of Jacobi-preconditioned Chebyshev iteration on the interval
+// [b / ratio, b], b = 1.02 lam_max (lam_max bounds the spectrum of D^-1 K
+// from above), for A z = r: from z = 0 (first) or adding to z.  The result
+// is a fixed polynomial in D^-1 K applied to D^-1 r: linear, symmetric and
+// (since the Chebyshev residual polynomial stays inside (0, 1) below the
+// interval and below 1 in magnitude on it) positive definite.  The
+// iteration's residual starts from r_src and moves between r_a and r_b
+// (the first launch reads r_src and writes r_a; r_src is overwritten only
+// if it is r_b); *r_end receives the buffer holding the final residual.
 template <typename T>
-hipError_t chebyshev_solve(fe_problem* p, int l, T* r, T* z, T* d0, T* d1, int deg, CgState* st, bool d0_ready) {
+hipError_t cheb_run(fe_problem* p, int l, T* r_src, T* r_a, T* r_b, T* z, T* d0, T* d1, int deg, double ratio,
+                    bool first, CgState* st, bool d0_ready, T** r_end) {
+  const bool keep_src = r_src != r_b;
   const Level& L = p->L[l];
-  const double b = 1.02 * p->lam_max, a = b / p->cheb_ratio;
-  const double theta = cheb_theta(p), delta = 0.5 * (b - a), sigma = theta / delta;
+  const double b = 1.02 * p->lam_max, a = b / ratio;
+  const double theta = 0.5 * (b + a), delta = 0.5 * (b - a), sigma = theta / delta;
   double rho = 1.0 / sigma;
-  // d0 = D^-1 r / theta (formed by the restriction when d0_ready)
-  if (!d0_ready)
+  // d0 = D^-1 r / theta: formed by the restriction when d0_ready, else by
+  // the first launch of pairs on 3D tiles, else by a launch of its own
+  const bool pairs = p->cheb_per_launch != 1 && deg >= 2;
+  double dscale = 0.0;
+  if (!d0_ready && pairs && cheb2_forms_first_direction<T>(p, l))
+    dscale = 1.0 / theta;
+  else if (!d0_ready)
     hipLaunchKernelGGL(jacobi0_kernel<T>, dim3(nblocks(L.g.ndof), p->bcount), dim3(FE_BLOCK), 0, p->stream,
-                       L.g.ndof, r, lev_invd<T>(L), (T)(1.0 / theta), d0, st, wsh_of(p));
+                       L.g.ndof, r_src, lev_invd<T>(L), (T)(1.0 / theta), d0, st, wsh_of(p));
   hipError_t e = hipGetLastError();
-  T* r_alt = static_cast<T*>(L.mg_q);
-  // profiling form 7: one event pair around the solve's launches; the
-  // algorithmic bytes of each launch (one or two steps) read d_k, r_k, the
-  // iterate, D^-1, the fixed-dof mask and E and write the residual, the
-  // iterate and the next direction, each array once
+  T* rin = r_src;
+  T* rout = r_a;
+  // profiling form 7: one event pair around a coarsest-level solve's
+  // launches; the algorithmic bytes of each launch (one or two steps) read
+  // d_k, r_k, the iterate, D^-1, the fixed-dof mask and E and write the
+  // residual, the iterate and the next direction, each array once
   int prof = -1;
-  if (p->kst.on && p->kst.mode == 7 && p->bcount == 1) {
+  if (p->kst.on && p->kst.mode == 7 && p->bcount == 1 && l == p->nlev - 1) {
     const int launches = p->cheb_per_launch == 1 ? deg : (deg + 1) / 2;
     prof = kstats_begin(p, (double)launches * ((double)sizeof(T) * (19.0 * (double)L.g.nnode + (double)L.g.nelem) +
                                                (double)L.g.nnode));
   }
   for (int k = 0; k < deg && e == hipSuccess;) {
     const double rho1 = 1.0 / (2.0 * sigma - rho);
-    if (p->cheb_per_launch != 1 && k + 2 <= deg && r_alt) {
+    if (p->cheb_per_launch != 1 && k + 2 <= deg && rout) {
       // steps k and k + 1 in one launch; the residual moves to the other buffer
       const double rho2 = 1.0 / (2.0 * sigma - rho1);
       const double c[4] = {rho1 * rho, 2.0 * rho1 / delta, rho2 * rho1, 2.0 * rho2 / delta};
-      e = launch_cheb2<T>(p, l, d0, d1, lev_E<T>(L), lev_invd<T>(L), r, r_alt, z, c, k == 0, st);
+      e = launch_cheb2<T>(p, l, d0, d1, lev_E<T>(L), lev_invd<T>(L), rin, rout, z, c, first && k == 0, st,
+                          k == 0 ? dscale : 0.0);
       rho = rho2;
-      std::swap(r, r_alt);
+      rin = rout;
+      rout = rin == r_a ? r_b : r_a;
       k += 2;
     } else {
+      // one step, its residual updated in place (a kept r_src is copied out first)
+      if (keep_src && rin == r_src) {
+        e = hipMemcpyAsync(rout, rin, L.g.ndof * sizeof(T), hipMemcpyDeviceToDevice, p->stream);
+        if (e != hipSuccess) break;
+        rin = rout;
+        rout = rin == r_a ? r_b : r_a;
+      }
       ChebStep<T> cs;
-      cs.res = r;
+      cs.res = rin;
       cs.acc = z;
       cs.c1 = rho1 * rho;
       cs.c2 = 2.0 * rho1 / delta;
-      cs.first = k == 0;
+      cs.first = first && k == 0;
       e = launch_kxu_tile<T>(p, l, d0, lev_E<T>(L), d1, st, 6, nullptr, nullptr, nullptr, lev_invd<T>(L), 0.0,
                              &cs);
       rho = rho1;
@@ -308,9 +327,69 @@ hipError_t chebyshev_solve(fe_problem* p, int l, T* r, T* z, T* d0, T* d1, int d
     std::swap(d0, d1);
   }
   kstats_end(p, prof);
+  if (r_end) *r_end = rin;
   return e;
 }
 
+// Coarsest-level solve: `deg` steps from z = 0 on [lam_max / cheb_ratio,
+// lam_max].  r and the level's mg_q buffer are overwritten.
+template <typename T>
+hipError_t chebyshev_solve(fe_problem* p, int l, T* r, T* z, T* d0, T* d1, int deg, CgState* st, bool d0_ready) {
+  return cheb_run<T>(p, l, r, static_cast<T*>(p->L[l].mg_q), r, z, d0, d1, deg, p->cheb_ratio, true, st, d0_ready,
+                     nullptr);
+}
+
+}  // namespace
+
+template <typename T>
+hipError_t launch_vcycle(fe_problem* p, int l, const T* r, T* z, CgState* st, int rz, int fold_rr);
+
+namespace {
+// V-cycle on a level between the finest and the coarsest with Chebyshev
+// smoothing: cs_deg steps from z = 0 (their residual is the one restricted),
+// the coarse correction, the residual r - K z, and cs_deg steps more on it
+// added to z.  Both smoothers are the same polynomial in D^-1 K applied to
+// D^-1 (symmetric), so the cycle stays symmetric.  r is kept.
+template <typename T>
+hipError_t cheb_smoothed_cycle(fe_problem* p, int l, const T* r, T* z, CgState* st) {
+  const Level& L = p->L[l];
+  T* t = static_cast<T*>(L.mg_t);
+  T* w = static_cast<T*>(L.mg_w);
+  T* q = static_cast<T*>(L.mg_q);
+  T* s = static_cast<T*>(L.mg_s);
+  T* res = nullptr;
+  hipError_t e = cheb_run<T>(p, l, const_cast<T*>(r), q, s, z, t, w, p->cs_deg, p->cs_ratio, true, st, false, &res);
+  if (e != hipSuccess) return e;
+  const Level& C = p->L[l + 1];
+  const bool last = l + 1 == p->nlev - 1;
+  // the next level may run in float32 under a float64 one (as in launch_vcycle)
+  using TC = typename std::conditional<std::is_same<T, double>::value, float, T>::type;
+  if (std::is_same<T, double>::value && l + 1 >= p->f32_from) {
+    TC* rc = static_cast<TC*>(C.mg_r);
+    TC* zc = static_cast<TC*>(C.mg_z);
+    hipLaunchKernelGGL((restrict_kernel<T, TC>), dim3(nblocks(C.g.nnode), p->bcount), dim3(FE_BLOCK), 0,
+                       p->stream, L.g, C.g, res, C.nmask, rc, st, wsh_of(p), last ? C.invd32 : nullptr,
+                       (TC)(1.0 / cheb_theta(p)), last ? static_cast<TC*>(C.mg_t) : nullptr);
+    if ((e = hipGetLastError()) != hipSuccess) return e;
+    if ((e = launch_vcycle<TC>(p, l + 1, rc, zc, st, RZ_NONE, 0)) != hipSuccess) return e;
+    hipLaunchKernelGGL((prolong_add_kernel<T, TC>), dim3(nblocks(L.g.nnode), p->bcount), dim3(FE_BLOCK), 0,
+                       p->stream, L.g, C.g, z, zc, L.nmask, z, nullptr, nullptr, (T)0, st, wsh_of(p));
+  } else {
+    T* rc = static_cast<T*>(C.mg_r);
+    T* zc = static_cast<T*>(C.mg_z);
+    hipLaunchKernelGGL(restrict_kernel<T>, dim3(nblocks(C.g.nnode), p->bcount), dim3(FE_BLOCK), 0, p->stream,
+                       L.g, C.g, res, C.nmask, rc, st, wsh_of(p), last ? lev_invd<T>(C) : nullptr,
+                       (T)(1.0 / cheb_theta(p)), last ? static_cast<T*>(C.mg_t) : nullptr);
+    if ((e = hipGetLastError()) != hipSuccess) return e;
+    if ((e = launch_vcycle<T>(p, l + 1, rc, zc, st, RZ_NONE, 0)) != hipSuccess) return e;
+    hipLaunchKernelGGL(prolong_add_kernel<T>, dim3(nblocks(L.g.nnode), p->bcount), dim3(FE_BLOCK), 0, p->stream,
+                       L.g, C.g, z, zc, L.nmask, z, nullptr, nullptr, (T)0, st, wsh_of(p));
+  }
+  if ((e = hipGetLastError()) != hipSuccess) return e;
+  if ((e = launch_kxu_tile<T>(p, l, z, lev_E<T>(L), q, st, 4, nullptr, nullptr, r, nullptr, 0.0)) != hipSuccess)
+    return e;
+  return cheb_run<T>(p, l, q, s, q, z, t, w, p->cs_deg, p->cs_ratio, false, st, false, nullptr);
+}
 }  // namespace
 
 // z = V(r): one symmetric V-cycle on levels l .. nlev-1 (pre- and
@@ -324,6 +403,7 @@ hipError_t launch_vcycle(fe_problem* p, int l, const T* r, T* z, CgState* st, in
   if (l == p->nlev - 1)  // r is this level's own restricted residual: free to overwrite
     return chebyshev_solve<T>(p, l, const_cast<T*>(r), z, t, static_cast<T*>(L.mg_w), p->mg_coarse_sweeps, st,
                               l > 0);
+  if (l > 0 && l >= p->cs_from) return cheb_smoothed_cycle<T>(p, l, r, z, st);
   // z from the pre-smoothing sweeps, t = r - K z restricted to the next level
   hipError_t e = presmooth<T>(p, l, r, z, t, p->mg_nu, st, l == 0 ? fold_rr : 0);
   if (e != hipSuccess) return e;

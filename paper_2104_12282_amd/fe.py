@@ -26,7 +26,7 @@ STATUS_NAME = {0: "FE_OK", -1: "FE_EINVAL", -2: "FE_ENOMEM", -3: "FE_EDEVICE",
 # Every entry point declared in include/fe_abi.h.
 ABI_SYMBOLS = ("fe_workspace_size", "fe_setup", "fe_apply_K", "fe_solve", "fe_solve_begin",
                "fe_solve_step", "fe_solve_end", "fe_sensitivity", "fe_sensitivity_adjoint", "fe_set_load",
-               "fe_filter", "oc_update", "oc_update_noalloc", "fe_block_mean", "fe_set_mg_params", "fe_get_mg_params", "fe_set_float32_levels", "fe_set_coarse_fusion", "fe_set_profiling", "fe_set_cache_flush",
+               "fe_filter", "oc_update", "oc_update_noalloc", "fe_block_mean", "fe_set_mg_params", "fe_get_mg_params", "fe_set_mg_smoother", "fe_get_mg_smoother", "fe_set_float32_levels", "fe_set_coarse_fusion", "fe_set_profiling", "fe_set_cache_flush",
                "fe_kernel_stats", "fe_destroy", "fe_batch_workspace_size", "fe_batch_create", "fe_batch_setup_slot",
                "fe_batch_round_begin", "fe_batch_round_end", "fe_batch_round_ready", "fe_batch_destroy", "fe_onsg_num_params",
                "fe_onsg_workspace_size", "fe_onsg_create", "fe_onsg_add_samples", "fe_onsg_num_samples",
@@ -82,6 +82,8 @@ def load_library() -> C.CDLL:
     lib.fe_block_mean.argtypes = [P, P, I32, P]
     lib.fe_set_mg_params.argtypes = [P, I32, I32, D, D]
     lib.fe_set_float32_levels.argtypes = [P, I32]
+    lib.fe_set_mg_smoother.argtypes = [P, I32, I32, D]
+    lib.fe_get_mg_smoother.argtypes = [P, C.POINTER(I32), C.POINTER(I32), C.POINTER(D)]
     lib.fe_get_mg_params.argtypes = [P, C.POINTER(I32), C.POINTER(I32), C.POINTER(D), C.POINTER(D)]
     lib.fe_set_coarse_fusion.argtypes = [P, I32]
     lib.fe_set_profiling.argtypes = [P, I32]
@@ -114,7 +116,7 @@ def load_library() -> C.CDLL:
     lib.fe_last_error.restype = C.c_char_p
     for name in ("fe_setup", "fe_apply_K", "fe_solve", "fe_solve_begin", "fe_solve_step",
                  "fe_solve_end", "fe_sensitivity", "fe_filter",
-                 "oc_update", "fe_set_mg_params", "fe_set_coarse_fusion", "fe_set_profiling", "fe_set_cache_flush", "fe_kernel_stats",
+                 "oc_update", "fe_set_mg_params", "fe_set_mg_smoother", "fe_get_mg_smoother", "fe_set_coarse_fusion", "fe_set_profiling", "fe_set_cache_flush", "fe_kernel_stats",
                  "fe_batch_create", "fe_batch_setup_slot", "fe_batch_round_begin", "fe_batch_round_end"):
         getattr(lib, name).restype = C.c_int
     _lib = lib
@@ -336,6 +338,18 @@ class Problem:
         nu, deg, om, ra = C.c_int32(), C.c_int32(), C.c_double(), C.c_double()
         _check(load_library().fe_get_mg_params(self._h, C.byref(nu), C.byref(deg), C.byref(om), C.byref(ra)))
         return {"nu": nu.value, "coarse_sweeps": deg.value, "omega": om.value, "coarse_ratio": ra.value}
+
+    def set_mg_smoother(self, cheb_from_level=0, degree=4, ratio=30.0):
+        """Chebyshev smoothing (degree steps on [lambda_max / ratio,
+        1.02 lambda_max]) on levels cheb_from_level .. levels - 2 instead of
+        damped Jacobi; 0: damped Jacobi on every level."""
+        _check(load_library().fe_set_mg_smoother(self._h, cheb_from_level, degree, ratio))
+
+    def mg_smoother(self):
+        """The smoothing in effect: cheb_from_level (0: damped Jacobi), degree, ratio."""
+        k, deg, ra = C.c_int32(), C.c_int32(), C.c_double()
+        _check(load_library().fe_get_mg_smoother(self._h, C.byref(k), C.byref(deg), C.byref(ra)))
+        return {"cheb_from_level": k.value, "degree": deg.value, "ratio": ra.value}
 
     def set_float32_levels(self, first_level):
         """Multigrid levels >= first_level of float64 solves in float32

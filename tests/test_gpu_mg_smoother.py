@@ -1,0 +1,162 @@
+"""Chebyshev smoothing of the multigrid levels between the finest and the
+coarsest (fe_set_mg_smoother): parity of the solves with the FP64 CPU
+oracle, the launch forms against each other, the setting's validation and
+defaults.
+
+Tolerances as in test_gpu_parity: compliance 1e-6, sensitivity 1e-5 (max
+norm) against the oracle's direct solve."""
+import numpy as np
+import pytest
+import torch
+
+from oracle import fe_oracle as O
+from paper_2104_12282_amd import fe, synth
+
+pytestmark = pytest.mark.gpu
+DEV = "cuda:0"
+NU = 0.3
+
+
+def T(a, dtype=torch.float64):
+    return torch.as_tensor(np.ascontiguousarray(a), dtype=dtype, device=DEV)
+
+
+def N(t):
+    torch.cuda.synchronize()
+    return t.detach().cpu().numpy()
+
+
+def _problem(nx, ny, nz, precision="fp64", levels=4):
+    f = synth.cantilever_edge_load(nx, ny, nz)
+    return fe.Problem(nx, ny, nz, T(f), device=DEV, precision=precision, nu=NU, precond="gmg",
+                      mg_levels=levels)
+
+
+@pytest.mark.parametrize("precision", ["fp64", "fp32_ir"])
+@pytest.mark.parametrize("grid,levels,cheb", [((32, 16, 16), 4, (2, 6, 100.0)), ((21, 11, 7), 4, (2, 6, 100.0)),
+                                              ((33, 17, 9), 4, (2, 5, 30.0)), ((48, 24, 24), 5, (2, 6, 100.0)),
+                                              ((48, 24, 24), 5, (3, 4, 300.0)), ((24, 12, 12), 3, (1, 2, 30.0))])
+def test_cheb_smoothed_solve_parity(grid, levels, cheb, precision):
+    """Solves with Chebyshev-smoothed middle levels (one or two of them, even
+    and odd degrees, odd grids) reach the oracle's compliance and
+    sensitivity; the V-cycle stays a symmetric positive definite
+    preconditioner (plain CG converges to 1e-10)."""
+    nx, ny, nz = grid
+    Ke = O.hex8_ke(NU)
+    rho = synth.density_around(nx, ny, nz, 3)
+    f = synth.cantilever_edge_load(nx, ny, nz)
+    u_ref = O.solve_direct(nx, ny, nz, O.simp_modulus(rho), Ke, f, O.clamp_x0_fixed(nx, ny, nz))
+    c_ref = O.compliance(f, u_ref)
+    dc_ref = O.sensitivity(nx, ny, nz, Ke, rho, u_ref)
+    prob = _problem(nx, ny, nz, precision, levels)
+    prob.set_mg_smoother(*cheb)
+    assert prob.mg_smoother() == {"cheb_from_level": cheb[0], "degree": cheb[1], "ratio": cheb[2]}
+    u, info = prob.solve(T(rho), rtol=1e-10)
+    dc, c = prob.sensitivity(T(rho), u)
+    assert info["status"] == 0 and info["rel_res"] <= 1e-10
+    assert abs(float(N(c)[0]) - c_ref) / c_ref <= 1e-6
+    assert np.abs(N(dc) - dc_ref).max() / np.abs(dc_ref).max() <= 1e-5
+
+
+@pytest.mark.parametrize("grid,levels,deg", [((32, 16, 16), 4, 6), ((40, 20, 12), 4, 5), ((48, 24, 24), 5, 4),
+                                             ((27, 13, 9), 4, 3)])
+@pytest.mark.parametrize("precision", ["fp64", "fp32_ir"])
+def test_cheb_smoothing_fusion_bitwise(grid, levels, deg, precision):
+    """Smoothing steps in pairs on z-marching tiles (with the first direction
+    from a launch of its own) give bitwise the solve of one launch per step,
+    for even and odd degrees."""
+    nx, ny, nz = grid
+    rho = T(synth.density_around(nx, ny, nz, 4))
+    out = []
+    for form in (1, 2):
+        prob = _problem(nx, ny, nz, precision, levels)
+        prob.set_mg_smoother(2, deg, 100.0)
+        prob.set_coarse_fusion(form)
+        u, info = prob.solve(rho, rtol=1e-6)
+        out.append((N(u), info))
+        prob.close()
+    (u1, i1), (u2, i2) = out
+    assert i1["rel_res"] <= 1e-6
+    assert i1["iters"] == i2["iters"] and i1["outer_iters"] == i2["outer_iters"]
+    assert np.array_equal(u1, u2)
+
+
+@pytest.mark.parametrize("grid,levels,deg", [((32, 16, 16), 4, 6), ((40, 20, 12), 4, 5), ((64, 32, 32), 4, 6),
+                                             ((48, 24, 24), 5, 4)])
+@pytest.mark.parametrize("precision", ["fp64_all", "fp64", "fp32_ir"])
+@pytest.mark.parametrize("form", [3, 4])
+def test_cheb_smoothing_3d_tiles(grid, levels, deg, precision, form):
+    """Pairs on 3D tiles, which form each first direction D^-1 r / theta in
+    the launch (rounded as the separate launch rounds it) and sum nodes in
+    another order: the same CG iterations as one launch per step (within one
+    with the whole preconditioner in float64; with its usual float32 levels,
+    whose rounding the tight tolerance feels, within 15%), the same
+    displacement to 1e-6, and bit-for-bit repeatable."""
+    nx, ny, nz = grid
+    rho = T(synth.density_around(nx, ny, nz, 4))
+    out = []
+    for f in (1, form, form):
+        prob = _problem(nx, ny, nz, "fp64" if precision == "fp64_all" else precision, levels)
+        if precision == "fp64_all":
+            prob.set_float32_levels(levels)
+        prob.set_mg_smoother(2, deg, 100.0)
+        prob.set_coarse_fusion(f)
+        u, info = prob.solve(rho, rtol=1e-9)
+        out.append((N(u), info))
+        prob.close()
+    (u1, i1), (u3, i3), (u3b, i3b) = out
+    assert i1["rel_res"] <= 1e-9 and i3["rel_res"] <= 1e-9
+    slack = 1 if precision == "fp64_all" else 2 + 0.15 * max(i1["iters"], i3["iters"])
+    assert abs(i1["iters"] - i3["iters"]) <= slack, (i1["iters"], i3["iters"])
+    assert np.abs(u3 - u1).max() <= 1e-6 * np.abs(u1).max()
+    assert np.array_equal(u3, u3b) and i3["iters"] == i3b["iters"]
+
+
+def test_cheb_smoother_defaults_and_validation():
+    """Default: on from level 2 (6 steps, ratio 100) for four or more levels
+    over a coarsest grid of 24 or more elements along its longest axis, off
+    otherwise; 0 switches it off; out-of-range settings are rejected and
+    leave the setting unchanged."""
+    big = _problem(224, 112, 56, levels=4)  # coarsest 28 x 14 x 7
+    assert big.mg_smoother() == {"cheb_from_level": 2, "degree": 6, "ratio": 100.0}
+    big.close()
+    # the threshold: coarsest grids of 24 x 2 x 2 and 23 x 2 x 2 elements
+    assert _problem(192, 16, 16, levels=4).mg_smoother()["cheb_from_level"] == 2
+    assert _problem(184, 16, 16, levels=4).mg_smoother()["cheb_from_level"] == 0
+    p4 = _problem(32, 16, 16, levels=4)
+    assert p4.mg_smoother()["cheb_from_level"] == 0
+    p4.set_mg_smoother(2, 6, 100.0)
+    p3 = _problem(32, 16, 16, levels=3)
+    assert p3.mg_smoother()["cheb_from_level"] == 0
+    for bad in [(3, 6, 100.0), (-1, 6, 100.0), (2, 0, 100.0), (2, 65, 100.0), (2, 6, 1.5), (2, 6, 2e6)]:
+        with pytest.raises(fe.FEError):
+            p4.set_mg_smoother(*bad)
+    assert p4.mg_smoother() == {"cheb_from_level": 2, "degree": 6, "ratio": 100.0}
+    with pytest.raises(fe.FEError):  # a three-level hierarchy has one middle level
+        p3.set_mg_smoother(2, 6, 100.0)
+    p4.set_mg_smoother(0)
+    assert p4.mg_smoother()["cheb_from_level"] == 0
+    p3.set_mg_smoother(1, 2, 30.0)
+    assert p3.mg_smoother() == {"cheb_from_level": 1, "degree": 2, "ratio": 30.0}
+
+
+def test_cheb_smoothing_beats_jacobi_at_four_levels():
+    """The reason for the default: on the 224 x 112 x 56 grid with four
+    levels, Chebyshev steps on level 2 leave CG fewer iterations than one
+    damped Jacobi sweep there (measured: 44 against 52 on a smooth random
+    design, 423 against 442 on a high-contrast one; 75 against 112 per solve
+    along the optimisation loop)."""
+    nx, ny, nz = 224, 112, 56
+    d = synth.density_around(nx, ny, nz, 2)
+    # high contrast, as the optimisation makes it: material where a smoothed
+    # random field is above its median, 0.05 elsewhere
+    for rho in (T(d), T(np.where(d > np.median(d), 1.0, 0.05))):
+        iters = {}
+        for cheb in (0, 2):
+            prob = _problem(nx, ny, nz, "fp64", 4)
+            prob.set_mg_smoother(cheb)
+            _, info = prob.solve(rho, rtol=1e-8)
+            assert info["rel_res"] <= 1e-8
+            iters[cheb] = info["iters"]
+            prob.close()
+        assert iters[2] < iters[0], iters
