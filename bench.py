@@ -154,10 +154,10 @@ def apply_mg(prob, args):
 
 
 def coarse_solve_record(nx, ny, nz, args, degree):
-    """Roofline context of the coarsest-level Chebyshev launches (two steps
-    each), the largest share of GPU time in the multigrid solve: algorithmic
-    bytes per launch and rocprofv3's average duration from the stored
-    kernel-trace run of the same source."""
+    """Roofline context of the coarsest-level Chebyshev launches (the largest
+    share of GPU time in the multigrid solve): the launch form the library
+    picks, algorithmic bytes per launch and rocprofv3's average duration
+    from the stored kernel-trace run of the same source."""
     if args.precond != "gmg":
         return None
     cx, cy, cz = nx, ny, nz
@@ -166,24 +166,32 @@ def coarse_solve_record(nx, ny, nz, args, degree):
     nnode = (cx + 1) * (cy + 1) * (cz + 1)
     wide = args.precision == "fp64" and args.f32_from >= args.mg_levels  # the coarsest level in float64
     vb = 8.0 if wide else 4.0
-    # d_k, r_k, acc read and r, acc, d_{k+2} written (3 dofs per node), moduli,
+    # d_k, r_k, acc read and r, acc, d_{k+s} written (3 dofs per node), moduli,
     # inverse diagonal, fixed-dof mask: each array once
     nbytes = vb * (6 * 3 * nnode + cx * cy * cz + nnode) + nnode
     form = args.coarse_form
-    if form == 0:  # the library's automatic choice: 3D tiles while they need at most one workgroup per CU
+    if form == 0:  # the library's automatic choice (fe_set_coarse_fusion)
         import torch
         cus = torch.cuda.get_device_properties(0).multi_processor_count
         cols = ((cx + 4) // 4) * ((cy + 4) // 4)
-        form = 3 if cols * ((cz + 4) // 4) <= cus else 4 if not wide and cols * ((cz + 8) // 8) <= cus else 2
-    oz = 8 if form == 4 and not wide else 4
-    name = f"cheb3d_kernel<{'double' if wide else 'float'}, {oz}>" if form >= 3 else \
-        f"cheb2_kernel<{'double' if wide else 'float'}>"
-    shape = f"3D tiles of 4 x 4 x {oz} nodes" if form >= 3 else "z-marching tiles"
-    out = {"kernel": f"{name}: two coarsest-level Chebyshev steps per launch on {shape}",
-           "coarse_grid": [cx, cy, cz], "launches_per_vcycle": (degree + 1) // 2,
+        form = 5 if cols * ((cz + 4) // 4) <= cus else 4 if not wide and cols * ((cz + 8) // 8) <= cus else 2
+    if form == 5 and wide:
+        form = 3
+    if form == 5:
+        name, steps, shape = "cheb3t_kernel", 3, "3D tiles of 4 x 4 x 4 nodes"
+        launches = 2 if degree == 4 else (degree + 2) // 3
+    else:
+        oz = 8 if form == 4 and not wide else 4
+        name = f"cheb3d_kernel<{'double' if wide else 'float'}, {oz}>" if form >= 3 else \
+            f"cheb2_kernel<{'double' if wide else 'float'}>"
+        steps, shape = 2, (f"3D tiles of 4 x 4 x {oz} nodes" if form >= 3 else "z-marching tiles")
+        launches = (degree + 1) // 2
+    word = {2: "two", 3: "three"}[steps]
+    out = {"kernel": f"{name}: {word} coarsest-level Chebyshev steps per launch on {shape}",
+           "coarse_grid": [cx, cy, cz], "launches_per_vcycle": launches,
            "algorithmic_bytes_per_launch": nbytes, "bound": "latency",
-           "note": "a few MB per launch on a 22k-element grid: the launch is bound by its chain of "
-                   "dependent memory round trips, LDS phases and barriers, not by HBM bandwidth"}
+           "note": "well under a MB per launch on a few-thousand-element grid: the launch is bound by its "
+                   "chain of dependent memory round trips, LDS phases and barriers, not by HBM bandwidth"}
     rec = profile_record(f"{nx}x{ny}x{nz}")
     if rec:
         for t in rec.get("time_shares", []):
@@ -941,8 +949,9 @@ def main():
     roofline = product
     coarse = coarse_solve_record(nx, ny, nz, args, rec["mg"]["coarse_sweeps"]) if rec["mg"] else None
     if coarse:
-        # a multigrid solve spends most of its GPU time in the coarsest-level
-        # Chebyshev pairs: they are the dominant kernel of the roofline line
+        # the coarsest-level Chebyshev launches take the largest share of a
+        # multigrid solve's GPU time: they are the dominant kernel of the
+        # roofline line
         dtq, _, ksq, _ = run_loop(fe, synth, torch, nx, ny, nz, args.precision, args, args.steps, 0,
                                   profile=True, prof_mode=7)
         # one event pair brackets each coarse solve (its launches_per_vcycle
@@ -954,13 +963,15 @@ def main():
         name = coarse["kernel"].split(":")[0]
         roofline = {"bound": "hbm", "achieved": qach, "peak": HBM_PEAK_GBS, "unit": "GB/s",
                     "frac": qach / HBM_PEAK_GBS,
-                    "limiter": "latency: a few MB per launch on the coarsest grid; the launch time is its chain "
-                               "of one memory round trip, four LDS phases and the stores, not HBM bandwidth",
+                    "limiter": "latency: a fraction of a MB per launch on the coarsest grid, one workgroup "
+                               "per tile on a quarter of the compute units; the launch time is its chain of one "
+                               "memory round trip, the brick and node phases in LDS (two per step) and the "
+                               "stores, not HBM bandwidth",
                     "measured_on": "a third pass over the same timed steps with event nodes around every "
-                                   "coarse pair launch (the headline pass runs without them); warm",
+                                   "coarse solve (the headline pass runs without them); warm",
                     "profiled_pass_solves_per_s": args.steps / dtq,
                     "traffic": traffic_from_profiles(args.precision, f"{nx}x{ny}x{nz}", want=name.split("<")[0]),
-                    "traffic_of": "one coarse pair launch (rocprofv3 counters, copy-scaled)",
+                    "traffic_of": "one coarse launch (rocprofv3 counters, copy-scaled)",
                     "kernel": coarse["kernel"],
                     "launches": ksq["launches"] * per, "avg_launch_us": qms * 1e3,
                     "rocprofv3_avg_kernel_us": traffic_from_profiles(args.precision, f"{nx}x{ny}x{nz}",

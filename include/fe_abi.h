@@ -302,8 +302,12 @@ FE_API fe_status fe_set_float32_levels(fe_problem* p, int32_t first_level);
 FE_API fe_status fe_get_mg_params(const fe_problem* p, int32_t* nu, int32_t* coarse_sweeps, double* omega,
                            double* coarse_ratio);
 
-/* Launches of the coarsest-level Chebyshev solve (the solve on the small
- * coarse grid is bound by launch and memory latency, not by arithmetic):
+/* Launches of the Chebyshev steps (the coarsest-level solve and the
+ * Chebyshev smoothing of middle levels; on small grids they are bound by
+ * launch and memory latency, not by arithmetic):
+ *   5: three steps in one launch on 3D tiles of 4 x 4 x 4 nodes with a
+ *     three-node halo (float32 levels; float64 ones take form 3), the
+ *     remainder in pairs (a single step for an odd remainder);
  *   3, 4: pairs of steps in one launch on 3D tiles (a workgroup owns 4 x 4 x 4
  *     nodes (3) or 4 x 4 x 8 (4; float32 levels only, float64 levels take
  *     4 x 4 x 4), works on all their levels at once and recomputes the
@@ -311,10 +315,12 @@ FE_API fe_status fe_get_mg_params(const fe_problem* p, int32_t* nu, int32_t* coa
  *   2: pairs of steps in one launch on z-marching tiles (each workgroup
  *     recomputing the ring of first-step values its second step needs);
  *   1: one launch per step;
- *   0 (default): 3 while the launch (every batch slot included) has at most
- *     one workgroup per compute unit, else 4 while that holds for it, else 2.
- * 1 and 2 give bitwise the same result; 3 and 4 the same polynomial with
- * their node sums rounded in another order (each bitwise reproducible).
+ *   0 (default), per level: 5 while a launch on 4 x 4 x 4 blocks (every
+ *     batch slot included) has at most one workgroup per compute unit,
+ *     else 4 while that holds for 4 x 4 x 8 blocks, else 2.
+ * 1 and 2 give bitwise the same result, and so do 3 and 5 for even
+ * degrees; 3, 4 and 5 apply the same polynomial with their node sums
+ * rounded in another order than 1 and 2 (each bitwise reproducible).
  * FE_EINVAL for other values and for batch slots. */
 FE_API fe_status fe_set_coarse_fusion(fe_problem* p, int32_t steps_per_launch);
 

@@ -1219,8 +1219,8 @@ extern "C" fe_status fe_set_coarse_fusion(fe_problem* p, int32_t steps_per_launc
     fe_set_error("batch slots share the batch's multigrid parameters (the library defaults)");
     return FE_EINVAL;
   }
-  if (steps_per_launch < 0 || steps_per_launch > 4) {
-    fe_set_error("the coarse launch form must be 0, 1, 2, 3 or 4");
+  if (steps_per_launch < 0 || steps_per_launch > 5) {
+    fe_set_error("the coarse launch form must be 0, 1, 2, 3, 4 or 5");
     return FE_EINVAL;
   }
   p->cheb_per_launch = steps_per_launch;

@@ -24,6 +24,9 @@
 #define FE_IR_FLOOR_BF16 1e-1  // refinement over the bf16 contraction: tightest inner tolerance
 #endif
 #define FE_CS_OFF 99  // first multigrid level smoothed by Chebyshev steps: none
+#ifndef FE_CHEB_TRIPLES
+#define FE_CHEB_TRIPLES 1  // automatic coarse form: three steps per launch where 4 x 4 x 4 blocks fit
+#endif
 #ifndef FE_CS_DEG
 #define FE_CS_DEG 6  // default Chebyshev smoothing steps
 #endif
@@ -340,6 +343,14 @@ hipError_t launch_cheb2(fe_problem* p, int lev, const T* dk, T* y, const T* E, c
                         T* rout, T* acc, const double (&c)[4], int first, CgState* st, double dscale = 0.0);
 template <typename T>
 bool cheb2_forms_first_direction(const fe_problem* p, int lev);
+// Three steps per launch (4 x 4 x 4 blocks with a three-node halo; float32
+// levels whose launch fits one workgroup per compute unit, or form 5 asked
+// for): c = c1, c2 of steps k, k + 1, k + 2; otherwise as launch_cheb2.
+template <typename T>
+bool cheb_triples(const fe_problem* p, int lev);
+template <typename T>
+hipError_t launch_cheb3(fe_problem* p, int lev, const T* dk, T* y, const T* E, const T* invd, const T* rin,
+                        T* rout, T* acc, const double (&c)[6], int first, CgState* st, double dscale = 0.0);
 // Number of r^T z partials the level's last smoothing sweep (mode 5) leaves.
 template <typename T>
 int kxu_rz_partials(const fe_problem* p, int lev);

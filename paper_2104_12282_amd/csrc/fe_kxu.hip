@@ -721,6 +721,7 @@ struct Cheb2 {
   T c1b, c2b;  // step k + 1
   int first;   // step k is the first (the iterate starts at zero)
   T dscale;    // 3D tiles: nonzero = d_k is not read but formed as dscale D^-1 r_k (the first direction)
+  T c1c, c2c;  // step k + 2 (three steps per launch)
 };
 
 constexpr int OWN2 = 13;  // node columns per direction a fused workgroup finishes
@@ -1067,6 +1068,7 @@ constexpr int C3_IN = 8;   // input box nodes along x and y (two-node halo)
 
 template <int OZ>
 struct C3 {
+  static constexpr int IN = C3_IN;                   // input box nodes along x and y
   static constexpr int IZ = OZ + 4;                  // input box nodes along z
   static constexpr int NIN = C3_IN * C3_IN * IZ;     // input box nodes
   static constexpr int B1X = C3_IN - 1, B1Z = IZ - 1;
@@ -1108,23 +1110,24 @@ __device__ inline void brick_full(T (&u)[3][8], T Ee, const WK<T>& wk, T (&yv)[3
 }
 
 // Brick products of a box of BX x BX x BZ bricks whose lowest brick sits at
-// local node (lo, lo, lo) of the input box: thread e computes brick e.
-template <typename T, int OZ, int BX, int BZ>
-__device__ inline void c3_bricks(const T (*sd)[C3<OZ>::NIN], const T* sE, int lo, const WK<T>& wk,
-                                 T (*sbo)[C3<OZ>::NB1]) {
+// local node (lo, lo, lo) of the input box (geometry G: G::IN nodes along x
+// and y, moduli of its G::B1X x G::B1X x G::B1Z bricks): thread e computes
+// brick e.
+template <typename T, class G, int BX, int BZ>
+__device__ inline void c3_bricks(const T (*sd)[G::NIN], const T* sE, int lo, const WK<T>& wk, T (*sbo)[G::NB1]) {
   const int e = threadIdx.x;
   if (e >= BX * BX * BZ) return;
   const int bi = lo + e % BX, bj = lo + (e / BX) % BX, bk = lo + e / (BX * BX);
-  const int n0 = bi + C3_IN * (bj + C3_IN * bk);
+  const int n0 = bi + G::IN * (bj + G::IN * bk);
   T u[3][8];
 #pragma unroll
   for (int a = 0; a < 8; ++a) {
-    const int n = n0 + kCornerX[a] + C3_IN * (kCornerY[a] + C3_IN * kCornerZ[a]);
+    const int n = n0 + kCornerX[a] + G::IN * (kCornerY[a] + G::IN * kCornerZ[a]);
 #pragma unroll
     for (int c = 0; c < 3; ++c) u[c][a] = sd[c][n];
   }
   T yv[3][8];
-  brick_full(u, sE[bi + C3<OZ>::B1X * (bj + C3<OZ>::B1X * bk)], wk, yv);
+  brick_full(u, sE[bi + G::B1X * (bj + G::B1X * bk)], wk, yv);
 #pragma unroll
   for (int c = 0; c < 3; ++c)
 #pragma unroll
@@ -1134,8 +1137,8 @@ __device__ inline void c3_bricks(const T (*sd)[C3<OZ>::NIN], const T* sE, int lo
 // (K d)_c at local node (li, lj, lk) from the brick products of a box of
 // BX x BX x BZ bricks starting at local node lo: the 8 bricks holding the
 // node, in local corner order.
-template <typename T, int OZ, int BX>
-__device__ inline T c3_node_sum(const T (*sbo)[C3<OZ>::NB1], int c, int li, int lj, int lk, int lo) {
+template <typename T, class G, int BX>
+__device__ inline T c3_node_sum(const T (*sbo)[G::NB1], int c, int li, int lj, int lk, int lo) {
   T v = T(0);
 #pragma unroll
   for (int a = 0; a < 8; ++a) {
@@ -1248,7 +1251,7 @@ __global__ void __launch_bounds__(C3<OZ>::THREADS) cheb3d_kernel(Grid g, int gx,
   if (tid < Q::NB1) sE[tid] = Eb;
   __syncthreads();
   // step k on the bricks of the box
-  c3_bricks<T, OZ, Q::B1X, Q::B1Z>(sD0, sE, 0, wk, sBO);
+  c3_bricks<T, Q, Q::B1X, Q::B1Z>(sD0, sE, 0, wk, sBO);
   __syncthreads();
   // r_{k+1}, d_{k+1} on the nodes one inside the halo
   if (tid < Q::NR1) {
@@ -1258,7 +1261,7 @@ __global__ void __launch_bounds__(C3<OZ>::THREADS) cheb3d_kernel(Grid g, int gx,
 #pragma unroll
     for (int c = 0; c < 3; ++c) {
       const bool fx = (m >> c) & 1;
-      T v = c3_node_sum<T, OZ, Q::B1X>(sBO, c, li, lj, lk, 0);
+      T v = c3_node_sum<T, Q, Q::B1X>(sBO, c, li, lj, lk, 0);
       if (fx) v = T(0);
       T rn, dn;
       cheb_dof(fx, sR[c][n], v, sD0[c][n], sInv[n], cf.c1a, cf.c2a, rn, dn);
@@ -1268,7 +1271,7 @@ __global__ void __launch_bounds__(C3<OZ>::THREADS) cheb3d_kernel(Grid g, int gx,
   }
   __syncthreads();
   // step k + 1 on the bricks around the owned block
-  c3_bricks<T, OZ, Q::B2X, Q::B2Z>(sD1, sE, 1, wk, sBO);
+  c3_bricks<T, Q, Q::B2X, Q::B2Z>(sD1, sE, 1, wk, sBO);
   __syncthreads();
   if (tid < Q::NOWN && own_in) {
     const int n = oi + C3_IN * (oj + C3_IN * ok);
@@ -1277,10 +1280,188 @@ __global__ void __launch_bounds__(C3<OZ>::THREADS) cheb3d_kernel(Grid g, int gx,
 #pragma unroll
     for (int c = 0; c < 3; ++c) {
       const bool fx = (m >> c) & 1;
-      T v = c3_node_sum<T, OZ, Q::B2X>(sBO, c, oi, oj, ok, 1);
+      T v = c3_node_sum<T, Q, Q::B2X>(sBO, c, oi, oj, ok, 1);
       if (fx) v = T(0);
       cheb_dof(fx, sR[c][n], v, sD1[c][n], sInv[n], cf.c1b, cf.c2b, rn[c], dn[c]);
       an[c] = (cf.first ? sD0[c][n] : a0[c] + sD0[c][n]) + sD1[c][n];
+    }
+#pragma unroll
+    for (int c = 0; c < 3; ++c) {
+      rout[3 * own_node + c] = rn[c];
+      acc[3 * own_node + c] = an[c];
+      y[3 * own_node + c] = dn[c];
+    }
+  }
+}
+
+// Three steps of the coarsest-level Chebyshev iteration in one launch, on
+// 4 x 4 x 4 owned nodes with a three-node halo (a 10 x 10 x 10 node box):
+// the bricks of step k on the 9^3 bricks of the box, the node updates on the
+// 8^3 nodes inside, step k + 1 on 7^3 bricks and 6^3 nodes, step k + 2 on
+// 5^3 bricks and the owned nodes.  Each phase is the pair kernel's (same
+// brick products, node sums in the same corner order, same per-dof update),
+// so three steps here are bitwise two launches of that kernel's steps plus
+// one, in any grouping.  float32 only (its brick products fill 70 KB of
+// LDS; float64 ones would not fit with the box).
+struct C3T {
+  static constexpr int IN = 10, IZ = 10;   // box nodes per axis (three-node halo around 4)
+  static constexpr int NIN = IN * IN * IZ;
+  static constexpr int B1X = IN - 1, B1Z = IZ - 1;
+  static constexpr int NB1 = B1X * B1X * B1Z;  // step-k bricks
+  static constexpr int THREADS = (NB1 + 63) / 64 * 64;
+  static constexpr int NOWN = C3_OWN * C3_OWN * C3_OWN;
+};
+
+__global__ void __launch_bounds__(C3T::THREADS) cheb3t_kernel(Grid g, int gx, int gy, int nblk, int per,
+                                                             const float* __restrict__ dk,
+                                                             const float* __restrict__ E,
+                                                             const uint8_t* __restrict__ nmask, WK<float> wk,
+                                                             const float* __restrict__ invd,
+                                                             const float* __restrict__ rin, float* __restrict__ rout,
+                                                             float* __restrict__ acc, float* __restrict__ y,
+                                                             Cheb2<float> cf, CgState* st, int64_t wsh) {
+  using Q = C3T;
+  using T = float;
+  static_assert(Q::NIN <= 2 * Q::THREADS, "two passes cover the box");
+  static_assert(sizeof(T) * (10 * Q::NIN + 25 * Q::NB1) + Q::NIN <= 160 * 1024, "LDS of one workgroup");
+  if (wsh) {  // batched launch: this workgroup's problem
+    const int64_t o = batch_offset(wsh);
+    dk = wshift(dk, o);
+    E = wshift(E, o);
+    nmask = wshift(nmask, o);
+    invd = wshift(invd, o);
+    rin = wshift(rin, o);
+    rout = wshift(rout, o);
+    acc = wshift(acc, o);
+    y = wshift(y, o);
+    st = wshift(st, o);
+  }
+  const int tile = (int)(blockIdx.x % 8) * per + (int)(blockIdx.x / 8);
+  if (tile >= nblk) return;
+  // sD0 holds d_k, then d_{k+2}; sD1 d_{k+1}; sR the running residual
+  __shared__ T sD0[3][Q::NIN], sD1[3][Q::NIN], sR[3][Q::NIN], sInv[Q::NIN], sE[Q::NB1];
+  __shared__ T sBO[24][Q::NB1];
+  __shared__ uint8_t sM[Q::NIN];
+  const int tx = tile % gx, t1 = tile / gx, ty = t1 % gy, tz = t1 / gy;
+  const int I0 = tx * C3_OWN - 3, J0 = ty * C3_OWN - 3, K0 = tz * C3_OWN - 3;
+  const int64_t sx = g.nx + 1, sxy = sx * (g.ny + 1);
+  const int tid = threadIdx.x;
+  int oi = 0, oj = 0, ok = 0;
+  bool own_in = false;
+  int64_t own_node = 0;
+  T a0[3] = {T(0), T(0), T(0)};
+  if (tid < Q::NOWN) {
+    oi = 3 + tid % C3_OWN;
+    oj = 3 + (tid / C3_OWN) % C3_OWN;
+    ok = 3 + tid / (C3_OWN * C3_OWN);
+    const int i = I0 + oi, j = J0 + oj, k = K0 + ok;
+    own_in = i <= g.nx && j <= g.ny && k <= g.nz;  // owned nodes are never below the mesh
+    own_node = i + sx * j + sxy * k;
+    if (own_in && !cf.first) {
+#pragma unroll
+      for (int c = 0; c < 3; ++c) a0[c] = acc[3 * own_node + c];
+    }
+  }
+  // every load is issued before the first wait (one memory round trip)
+  struct NodeIn {
+    T d[3], r[3], iv;
+    uint8_t m;
+  };
+  const bool form_d = cf.dscale != T(0);
+  auto load_node = [&](int n, NodeIn& v) {
+    const int i = I0 + n % Q::IN, j = J0 + (n / Q::IN) % Q::IN, k = K0 + n / (Q::IN * Q::IN);
+    const bool in = n < Q::NIN && i >= 0 && i <= g.nx && j >= 0 && j <= g.ny && k >= 0 && k <= g.nz;
+#pragma unroll
+    for (int c = 0; c < 3; ++c) v.d[c] = v.r[c] = T(0);
+    v.iv = T(0);
+    v.m = 7;
+    if (in) {
+      const int64_t node = i + sx * j + sxy * k;
+#pragma unroll
+      for (int c = 0; c < 3; ++c) {
+        if (!form_d) v.d[c] = dk[3 * node + c];
+        v.r[c] = rin[3 * node + c];
+      }
+      v.iv = invd[node];
+      v.m = nmask[node];
+    }
+  };
+  // the formed first direction rounds as the separate first-direction launch does
+  auto store_node = [&](int n, const NodeIn& v) {
+#pragma unroll
+    for (int c = 0; c < 3; ++c) {
+      sD0[c][n] = form_d ? cf.dscale * v.iv * v.r[c] : v.d[c];
+      sR[c][n] = v.r[c];
+    }
+    sInv[n] = v.iv;
+    sM[n] = v.m;
+  };
+  NodeIn v0, v1;
+  load_node(tid, v0);
+  load_node(tid + Q::THREADS, v1);
+  T Eb = T(0);
+  {
+    const int i = I0 + tid % Q::B1X, j = J0 + (tid / Q::B1X) % Q::B1X, k = K0 + tid / (Q::B1X * Q::B1X);
+    if (tid < Q::NB1 && i >= 0 && i < g.nx && j >= 0 && j < g.ny && k >= 0 && k < g.nz)
+      Eb = E[i + (int64_t)g.nx * (j + (int64_t)g.ny * k)];
+  }
+  // the CG stop flag is read while the loads are in flight
+  if (st && st->done) return;
+  if (tid < Q::NIN) store_node(tid, v0);
+  if (tid + Q::THREADS < Q::NIN) store_node(tid + Q::THREADS, v1);
+  if (tid < Q::NB1) sE[tid] = Eb;
+  __syncthreads();
+  // d_k at the owned node, before its buffer takes d_{k+2}
+  T d0own[3] = {T(0), T(0), T(0)};
+  if (tid < Q::NOWN) {
+    const int n = oi + Q::IN * (oj + Q::IN * ok);
+#pragma unroll
+    for (int c = 0; c < 3; ++c) d0own[c] = sD0[c][n];
+  }
+  // one step on the nodes of [lo + 1, lo + 1 + NX)^3: residual and direction
+  // from the bricks of [lo, lo + NX + 1)^3 (in sBO), d from din to dout
+  auto node_step = [&](auto nx_c, int lo, const T (*din)[Q::NIN], T (*dout)[Q::NIN], T c1, T c2) {
+    constexpr int NX = decltype(nx_c)::value;
+    if (tid < NX * NX * NX) {
+      const int li = lo + 1 + tid % NX, lj = lo + 1 + (tid / NX) % NX, lk = lo + 1 + tid / (NX * NX);
+      const int n = li + Q::IN * (lj + Q::IN * lk);
+      const uint8_t m = sM[n];
+#pragma unroll
+      for (int c = 0; c < 3; ++c) {
+        const bool fx = (m >> c) & 1;
+        T v = c3_node_sum<T, Q, NX + 1>(sBO, c, li, lj, lk, lo);
+        if (fx) v = T(0);
+        T rn, dn;
+        cheb_dof(fx, sR[c][n], v, din[c][n], sInv[n], c1, c2, rn, dn);
+        sR[c][n] = rn;
+        dout[c][n] = dn;
+      }
+    }
+  };
+  // step k: bricks of the box, nodes of [1, 9)^3
+  c3_bricks<T, Q, 9, 9>(sD0, sE, 0, wk, sBO);
+  __syncthreads();
+  node_step(std::integral_constant<int, 8>{}, 0, sD0, sD1, cf.c1a, cf.c2a);
+  __syncthreads();
+  // step k + 1: bricks of [1, 8)^3, nodes of [2, 8)^3 (d_{k+2} into sD0)
+  c3_bricks<T, Q, 7, 7>(sD1, sE, 1, wk, sBO);
+  __syncthreads();
+  node_step(std::integral_constant<int, 6>{}, 1, sD1, sD0, cf.c1b, cf.c2b);
+  __syncthreads();
+  // step k + 2: bricks of [2, 7)^3, the owned nodes
+  c3_bricks<T, Q, 5, 5>(sD0, sE, 2, wk, sBO);
+  __syncthreads();
+  if (tid < Q::NOWN && own_in) {
+    const int n = oi + Q::IN * (oj + Q::IN * ok);
+    const uint8_t m = sM[n];
+    T rn[3], dn[3], an[3];
+#pragma unroll
+    for (int c = 0; c < 3; ++c) {
+      const bool fx = (m >> c) & 1;
+      T v = c3_node_sum<T, Q, 5>(sBO, c, oi, oj, ok, 2);
+      if (fx) v = T(0);
+      cheb_dof(fx, sR[c][n], v, sD0[c][n], sInv[n], cf.c1c, cf.c2c, rn[c], dn[c]);
+      an[c] = ((cf.first ? d0own[c] : a0[c] + d0own[c]) + sD1[c][n]) + sD0[c][n];
     }
 #pragma unroll
     for (int c = 0; c < 3; ++c) {
@@ -1649,14 +1830,51 @@ static int cheb2_form(const fe_problem* p, int lev, bool tall) {
   // (measured on the 56 x 28 x 14 coarsest grid of 224 x 112 x 56 with
   // 4 x 4 x 4 blocks: 480 workgroups)
   // (4 x 4 x 8 blocks only in float32: in float64 their LDS exceeds a workgroup's 160 KB)
-  if (p->cheb_per_launch != 0) return p->cheb_per_launch;
-  const int64_t cus = device_cus();
-  return n4 * p->bcount <= cus ? 3 : (tall && n8 * p->bcount <= cus) ? 4 : 2;
+  // (three steps per launch on 4 x 4 x 4 blocks, float32 only, wherever
+  // 4 x 4 x 4 pairs would fit: one launch instead of 1.5)
+  int form = p->cheb_per_launch;
+  if (form == 0) {
+    const int64_t cus = device_cus();
+    form = n4 * p->bcount <= cus ? (FE_CHEB_TRIPLES ? 5 : 3) : (tall && n8 * p->bcount <= cus) ? 4 : 2;
+  }
+  return form == 5 && !tall ? 3 : form;
 }
 
 template <typename T>
 bool cheb2_forms_first_direction(const fe_problem* p, int lev) {
   return cheb2_form(p, lev, sizeof(T) == 4) >= 3;
+}
+
+template <typename T>
+bool cheb_triples(const fe_problem* p, int lev) {
+  return sizeof(T) == 4 && cheb2_form(p, lev, true) == 5;
+}
+
+template <typename T>
+hipError_t launch_cheb3(fe_problem* p, int lev, const T* dk, T* y, const T* E, const T* invd, const T* rin,
+                        T* rout, T* acc, const double (&c)[6], int first, CgState* st, double dscale) {
+  if constexpr (!std::is_same<T, float>::value) {
+    return hipErrorInvalidValue;
+  } else {
+    if (!cheb_triples<T>(p, lev)) return hipErrorInvalidValue;
+    const Grid g = p->L[lev].g;
+    Cheb2<T> cf;
+    cf.c1a = (T)c[0];
+    cf.c2a = (T)c[1];
+    cf.c1b = (T)c[2];
+    cf.c2b = (T)c[3];
+    cf.c1c = (T)c[4];
+    cf.c2c = (T)c[5];
+    cf.first = first;
+    cf.dscale = (T)dscale;
+    const int gx = (g.nx + C3_OWN) / C3_OWN, gy = (g.ny + C3_OWN) / C3_OWN;
+    const int64_t nblk = (int64_t)gx * gy * ((g.nz + C3_OWN) / C3_OWN), per = (nblk + 7) / 8;
+    if (8 * per > ((int64_t)1 << 31) - 1) return hipErrorInvalidValue;
+    hipLaunchKernelGGL(cheb3t_kernel, dim3((unsigned)(8 * per), p->bcount), dim3(C3T::THREADS), 0, p->stream, g,
+                       gx, gy, (int)nblk, (int)per, dk, E, p->L[lev].nmask, scaled_wk<T>(p->wk, p->L[lev].h), invd,
+                       rin, rout, acc, y, cf, st, p->bcount > 1 ? p->bstride : (int64_t)0);
+    return hipGetLastError();
+  }
 }
 
 template <typename T>
@@ -1677,7 +1895,7 @@ hipError_t launch_cheb2(fe_problem* p, int lev, const T* dk, T* y, const T* E, c
   const int form = cheb2_form(p, lev, tall);
   if (dscale != 0.0 && form < 3) return hipErrorInvalidValue;  // only the 3D tiles form the first direction
   if (form >= 3) {
-    const bool oz4 = form == 3 || !tall;
+    const bool oz4 = form == 3 || form == 5 || !tall;
     const int64_t nblk = oz4 ? n4 : n8, per = (nblk + 7) / 8;
     if (8 * per > ((int64_t)1 << 31) - 1) return hipErrorInvalidValue;
     const dim3 grid((unsigned)(8 * per), p->bcount);
@@ -1708,6 +1926,13 @@ template hipError_t launch_cheb2<float>(fe_problem*, int, const float*, float*, 
                                         const float*, float*, float*, const double (&)[4], int, CgState*, double);
 template bool cheb2_forms_first_direction<double>(const fe_problem*, int);
 template bool cheb2_forms_first_direction<float>(const fe_problem*, int);
+template bool cheb_triples<double>(const fe_problem*, int);
+template bool cheb_triples<float>(const fe_problem*, int);
+template hipError_t launch_cheb3<double>(fe_problem*, int, const double*, double*, const double*, const double*,
+                                         const double*, double*, double*, const double (&)[6], int, CgState*,
+                                         double);
+template hipError_t launch_cheb3<float>(fe_problem*, int, const float*, float*, const float*, const float*,
+                                        const float*, float*, float*, const double (&)[6], int, CgState*, double);
 
 template <typename T>
 hipError_t launch_kxu_tile(fe_problem* p, int lev, const T* x, const T* E, T* y, CgState* st, int mode,

@@ -289,13 +289,27 @@ hipError_t cheb_run(fe_problem* p, int l, T* r_src, T* r_a, T* r_b, T* z, T* d0,
   // residual, the iterate and the next direction, each array once
   int prof = -1;
   if (p->kst.on && p->kst.mode == 7 && p->bcount == 1 && l == p->nlev - 1) {
-    const int launches = p->cheb_per_launch == 1 ? deg : (deg + 1) / 2;
+    const int launches = p->cheb_per_launch == 1 ? deg : cheb_triples<T>(p, l) ? (deg == 4 ? 2 : (deg + 2) / 3)
+                                                                                : (deg + 1) / 2;
     prof = kstats_begin(p, (double)launches * ((double)sizeof(T) * (19.0 * (double)L.g.nnode + (double)L.g.nelem) +
                                                (double)L.g.nnode));
   }
+  const bool triples = cheb_triples<T>(p, l);
   for (int k = 0; k < deg && e == hipSuccess;) {
     const double rho1 = 1.0 / (2.0 * sigma - rho);
-    if (p->cheb_per_launch != 1 && k + 2 <= deg && rout) {
+    if (triples && k + 3 <= deg && deg - k != 4) {
+      // steps k .. k + 2 in one launch (four left: two pairs)
+      const double rho2 = 1.0 / (2.0 * sigma - rho1);
+      const double rho3 = 1.0 / (2.0 * sigma - rho2);
+      const double c[6] = {rho1 * rho,  2.0 * rho1 / delta, rho2 * rho1,
+                           2.0 * rho2 / delta, rho3 * rho2, 2.0 * rho3 / delta};
+      e = launch_cheb3<T>(p, l, d0, d1, lev_E<T>(L), lev_invd<T>(L), rin, rout, z, c, first && k == 0, st,
+                          k == 0 ? dscale : 0.0);
+      rho = rho3;
+      rin = rout;
+      rout = rin == r_a ? r_b : r_a;
+      k += 3;
+    } else if (p->cheb_per_launch != 1 && k + 2 <= deg && rout) {
       // steps k and k + 1 in one launch; the residual moves to the other buffer
       const double rho2 = 1.0 / (2.0 * sigma - rho1);
       const double c[4] = {rho1 * rho, 2.0 * rho1 / delta, rho2 * rho1, 2.0 * rho2 / delta};

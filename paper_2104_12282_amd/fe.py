@@ -358,9 +358,11 @@ class Problem:
         _check(load_library().fe_set_float32_levels(self._h, first_level))
 
     def set_coarse_fusion(self, steps_per_launch=0):
-        """Launch form of the coarsest-level Chebyshev steps (0: chosen per
-        launch, the default; 3 / 4: pairs on 3D tiles of 4 x 4 x 4 / 4 x 4 x 8
-        nodes; 2: pairs on z-marching tiles; 1: one step each)."""
+        """Launch form of the Chebyshev steps (coarsest-level solve and
+        middle-level smoothing; 0: chosen per level, the default; 5: three
+        steps per launch on 3D tiles of 4 x 4 x 4 nodes; 3 / 4: pairs on 3D
+        tiles of 4 x 4 x 4 / 4 x 4 x 8 nodes; 2: pairs on z-marching tiles;
+        1: one step each)."""
         _check(load_library().fe_set_coarse_fusion(self._h, steps_per_launch))
 
     def set_profiling(self, on, mode=None):

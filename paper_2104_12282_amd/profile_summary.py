@@ -108,14 +108,14 @@ def traffic(fetch_dir, write_dir, bench_json, out_path, command, stats_csv=None)
            "copy_probe_bytes": probe["bytes"], "copy_fetch_kib": copy_f, "copy_write_kib": copy_w,
            "fetch_scale": f_scale, "write_scale": w_scale, "kernels": {}}
     for mode_key in sorted({k for k in fetch if any(n in k for n in ("kxu_tile_kernel", "cheb3d_kernel",
-                                                                    "cheb2_kernel"))}):
+                                                                    "cheb3t_kernel", "cheb2_kernel"))}):
         fk = fetch[mode_key]
         wk = write.get(mode_key, [])
         if not wk:
             continue
-        # the finest grid's launches are the largest of each K*u variant (the
-        # coarse Chebyshev pairs all run on the coarsest grid; launches that
-        # met the CG stop flag read almost nothing)
+        # the finest grid's launches are the largest of each K*u variant (each
+        # Chebyshev launch form runs on one level of the hierarchy; launches
+        # that met the CG stop flag read almost nothing)
         fmax, wmax = max(fk), max(wk)
         rec["kernels"][mode_key] = {"fetch_bytes": fmax * 1024 * f_scale,
                                     "write_bytes": wmax * 1024 * w_scale,

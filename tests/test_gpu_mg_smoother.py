@@ -160,3 +160,29 @@ def test_cheb_smoothing_beats_jacobi_at_four_levels():
             iters[cheb] = info["iters"]
             prob.close()
         assert iters[2] < iters[0], iters
+
+
+@pytest.mark.parametrize("grid,levels,deg", [((56, 28, 14), 3, 24), ((32, 16, 16), 3, 6), ((40, 20, 12), 3, 8),
+                                             ((27, 13, 9), 3, 4), ((224, 112, 56), 4, 24), ((48, 24, 24), 4, 10)])
+@pytest.mark.parametrize("precision", ["fp64", "fp32_ir"])
+def test_cheb_triples_bitwise_pairs(grid, levels, deg, precision):
+    """Three Chebyshev steps per launch (4 x 4 x 4 blocks with a three-node
+    halo) compute every phase as the pair launches on 4 x 4 x 4 blocks do
+    (brick products, node sums in the same corner order, per-dof updates),
+    so for even degrees (no single step left over) the solves agree bit for
+    bit: coarsest levels and Chebyshev-smoothed middle levels, one and many
+    blocks per axis, ragged grids."""
+    nx, ny, nz = grid
+    rho = T(synth.density_around(nx, ny, nz, 4))
+    out = []
+    for form in (3, 5):
+        prob = _problem(nx, ny, nz, precision, levels)
+        prob.set_mg_params(coarse_sweeps=deg)
+        prob.set_coarse_fusion(form)
+        u, info = prob.solve(rho, rtol=1e-8)
+        out.append((N(u), info))
+        prob.close()
+    (u3, i3), (u5, i5) = out
+    assert i3["rel_res"] <= 1e-8
+    assert i3["iters"] == i5["iters"] and i3["outer_iters"] == i5["outer_iters"]
+    assert np.array_equal(u3, u5)

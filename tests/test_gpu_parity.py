@@ -600,7 +600,7 @@ def test_coarse_fusion_bitwise(grid, levels, deg, precision):
         u, info = prob.solve(rho, rtol=1e-6)
         out.append((N(u), info))
         if per_launch == 2:
-            for bad in (-1, 5):
+            for bad in (-1, 6):
                 with pytest.raises(fe.FEError):
                     prob.set_coarse_fusion(bad)
         prob.close()
@@ -614,7 +614,7 @@ def test_coarse_fusion_bitwise(grid, levels, deg, precision):
                                              ((26, 14, 2), 2, 5), ((80, 80, 40), 2, 6),
                                              ((208, 208, 64), 2, 6), ((27, 13, 9), 3, 6), ((224, 112, 56), 3, 48)])
 @pytest.mark.parametrize("precision", ["fp64", "fp32_ir"])
-@pytest.mark.parametrize("form", [3, 4])
+@pytest.mark.parametrize("form", [3, 4, 5])
 def test_coarse_3d_tiles(grid, levels, deg, precision, form):
     """Pairs of coarse Chebyshev steps on 3D tiles (the default launch form)
     apply the same polynomial as one launch per step, up to the rounding of
