@@ -500,16 +500,26 @@ def test_profiling_selector():
     rho = T(synth.density_around(nx, ny, nz, 0))
     with pytest.raises(fe.FEError):
         fe._check(fe.load_library().fe_set_profiling(prob._h, 10))
-    # form 7: each coarsest-level Chebyshev solve, its pair launches bracketed
-    # as one (coarsest grid 8 x 4 x 4, float32): one per V-cycle
+    # form 7: each coarsest-level Chebyshev solve, its launches bracketed as
+    # one (coarsest grid 8 x 4 x 4, float32: three steps per launch, the
+    # remainder in pairs, a last four as two pairs): one per V-cycle
     prob.set_profiling(True, mode=7)
     _, info = prob.solve(rho, rtol=1e-8)
     prob.set_profiling(False)
     ks = prob.kernel_stats(reset=True)
-    pairs = (prob.mg_params()["coarse_sweeps"] + 1) // 2
+    deg = prob.mg_params()["coarse_sweeps"]
+    launches = 2 if deg == 4 else (deg + 2) // 3
     assert info["iters"] + 1 <= ks["launches"] <= info["iters"] + 9
     cn, ce = 9 * 5 * 5, 8 * 4 * 4
-    assert ks["bytes_per_launch"] == pytest.approx(pairs * (4.0 * (19 * cn + ce) + cn), rel=1e-12)
+    assert ks["bytes_per_launch"] == pytest.approx(launches * (4.0 * (19 * cn + ce) + cn), rel=1e-12)
+    # pairs when asked for (one event pair still brackets the whole solve)
+    prob.set_coarse_fusion(3)
+    prob.set_profiling(True, mode=7)
+    prob.solve(rho, rtol=1e-8)
+    prob.set_profiling(False)
+    ks = prob.kernel_stats(reset=True)
+    assert ks["bytes_per_launch"] == pytest.approx((deg + 1) // 2 * (4.0 * (19 * cn + ce) + cn), rel=1e-12)
+    prob.set_coarse_fusion(0)
     prob.set_profiling(True, mode=1)
     _, info = prob.solve(rho, rtol=1e-8)
     prob.set_profiling(False)
