@@ -48,6 +48,7 @@ def stats(csv_path, out_path, command):
                      f"{float(r['AverageNs']) / 1e3:.2f} | {float(r['MinNs']) / 1e3:.2f} | "
                      f"{float(r['MaxNs']) / 1e3:.2f} | {100 * float(r['TotalDurationNs']) / total:.1f} |")
     lines += _timeline(os.path.dirname(csv_path))
+    lines += _by_shape(os.path.dirname(csv_path))
     with open(out_path, "w") as fh:
         fh.write("\n".join(lines) + "\n")
 
@@ -75,6 +76,30 @@ def _timeline(run_dir, short_ns=50_000):
             f"one's start (dispatch of queued work, timed under the trace): median {med / 1e3:.2f} us, "
             f"total {sum(short) / 1e6:.3f} ms",
             f"* {len(long_)} longer gaps (host work between launches): total {sum(long_) / 1e6:.3f} ms"]
+
+
+def _by_shape(run_dir, top=24):
+    """The kernels of the trace split by launch shape (grid size: one kernel
+    runs on several multigrid levels), largest total first, with the mean
+    and median durations of each."""
+    traces = glob.glob(os.path.join(run_dir, "*kernel_trace.csv"))
+    if not traces:
+        return []
+    groups = {}
+    for r in _rows(traces[0]):
+        name = r["Kernel_Name"].replace("void ", "").replace("(anonymous namespace)::", "").split("(")[0]
+        key = (name, int(r["Grid_Size_X"]) * int(r["Grid_Size_Y"]) * int(r["Grid_Size_Z"]),
+               int(r["Workgroup_Size_X"]) * int(r["Workgroup_Size_Y"]) * int(r["Workgroup_Size_Z"]))
+        groups.setdefault(key, []).append((int(r["End_Timestamp"]) - int(r["Start_Timestamp"])) / 1e3)
+    total = sum(sum(v) for v in groups.values())
+    lines = ["", "By launch shape (work-items of the grid, workgroup size):", "",
+             "| kernel | grid | workgroup | calls | total ms | mean us | median us | % |",
+             "|---|---:|---:|---:|---:|---:|---:|---:|"]
+    for (name, grid, wg), ds in sorted(groups.items(), key=lambda kv: -sum(kv[1]))[:top]:
+        ds = sorted(ds)
+        lines.append(f"| `{name[:60]}` | {grid} | {wg} | {len(ds)} | {sum(ds) / 1e3:.3f} | "
+                     f"{sum(ds) / len(ds):.2f} | {ds[len(ds) // 2]:.2f} | {100 * sum(ds) / total:.1f} |")
+    return lines
 
 
 def _counter_by_kernel(run_dir, counter):
