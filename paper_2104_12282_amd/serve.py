@@ -48,20 +48,62 @@ class _Slot:
 
 
 def prepare_inputs(req, device):
-    """Host-side seeded inputs of one request (load, raw density)."""
+    """Host-side seeded inputs of one request (load, raw density): its
+    payload when one is attached, else generated now."""
+    if "payload" in req:
+        return req["payload"]["f"], req["payload"]["rho0"]
     nx, ny, nz = req["grid"]
     f = synth.point_load(nx, ny, nz, req["seed"])
     rho0 = synth.density_uniform(nx, ny, nz, req["seed"])
     return f, rho0
 
 
+def attach_payloads(requests):
+    """Gives every request its inputs in pinned host memory (load, raw
+    density, and a pinned slot for the returned compliance), as a request
+    that arrives with its design carries them: the engines then copy them
+    to the device asynchronously on the design's stream and read the
+    compliance without a synchronising copy."""
+    for req in requests:
+        if "payload" in req:
+            continue
+        nx, ny, nz = req["grid"]
+        f = torch.from_numpy(synth.point_load(nx, ny, nz, req["seed"])).pin_memory()
+        rho0 = torch.from_numpy(synth.density_uniform(nx, ny, nz, req["seed"])).pin_memory()
+        req["payload"] = {"f": f, "rho0": rho0,
+                          "comp": torch.zeros(1, dtype=torch.float64).pin_memory()}
+    return requests
+
+
+def _dev(x, device):
+    """A request input on the device, copied on the current stream (pinned
+    payloads asynchronously)."""
+    if isinstance(x, torch.Tensor):
+        return x.to(device, non_blocking=True)
+    return torch.as_tensor(x, device=device)
+
+
+def _comp_out(req, comp):
+    """Queues the compliance's copy into the request's pinned slot on the
+    current stream (read after the stream's completion event); None without
+    a payload."""
+    if "payload" not in req:
+        return None
+    host = req["payload"]["comp"]
+    host.copy_(comp, non_blocking=True)
+    return host
+
+
+def _comp_value(host, comp):
+    return float(host[0]) if host is not None else float(comp.item())
+
+
 def _start(req, stream, device, cfg_kw, rtol, filter_passes):
     nx, ny, nz = req["grid"]
     f, rho0 = prepare_inputs(req, device)
     with torch.cuda.stream(stream):
-        prob = fe.Problem(nx, ny, nz, torch.as_tensor(f, device=device), device=device,
-                          stream=stream, **cfg_kw)
-        a = torch.as_tensor(rho0, device=device)
+        prob = fe.Problem(nx, ny, nz, _dev(f, device), device=device, stream=stream, **cfg_kw)
+        a = _dev(rho0, device)
         b = torch.empty_like(a)
         for _ in range(filter_passes):  # smoothed density, on the device
             prob.filter(a, out=b)
@@ -120,6 +162,7 @@ def run_engine(requests, arrivals=None, *, device="cuda:0", max_active=16, n_str
                     s.info = s.prob.solve_end()
                     with torch.cuda.stream(s.stream):
                         s.prob.sensitivity(s.rho, s.u, out=s.dc, compliance_out=s.comp)
+                        s.comp_host = _comp_out(s.req, s.comp)
                         s.event = torch.cuda.Event()
                         s.event.record(s.stream)
                 still.append(s)
@@ -128,7 +171,7 @@ def run_engine(requests, arrivals=None, *, device="cuda:0", max_active=16, n_str
                 rec = {"id": s.req["id"], "grid": s.req["grid"], "arrival": s.arrival,
                        "admit": s.admit_t, "finish": t_done, "latency": t_done - s.arrival,
                        "iters": s.info["iters"], "outer_iters": s.info["outer_iters"],
-                       "rel_res": s.info["rel_res"], "compliance": float(s.comp.item())}
+                       "rel_res": s.info["rel_res"], "compliance": _comp_value(s.comp_host, s.comp)}
                 if keep_outputs:
                     rec["u"] = s.u.cpu().numpy()
                     rec["dc"] = s.dc.cpu().numpy()
@@ -171,7 +214,7 @@ def run_sequential(requests, *, device="cuda:0", rtol=1e-8, filter_passes=3, kee
         ts = time.perf_counter() - t0
         nx, ny, nz = req["grid"]
         f, rho0 = prepare_inputs(req, device)
-        ft = torch.as_tensor(f, device=device)
+        ft = _dev(f, device)
         prob = probs.get(tuple(req["grid"])) if reuse else None
         if prob is None:
             prob = fe.Problem(nx, ny, nz, ft, device=device, stream=stream, **cfg_kw)
@@ -179,7 +222,7 @@ def run_sequential(requests, *, device="cuda:0", rtol=1e-8, filter_passes=3, kee
                 probs[tuple(req["grid"])] = prob
         else:
             prob.set_load(ft)
-        a = torch.as_tensor(rho0, device=device)
+        a = _dev(rho0, device)
         b = torch.empty_like(a)
         for _ in range(filter_passes):
             prob.filter(a, out=b)
@@ -275,8 +318,8 @@ def run_engine_batched(requests, arrivals=None, *, device="cuda:0", nslots=16, n
             b = c["batch"]
             f, rho0 = prepare_inputs(req, device)
             with torch.cuda.stream(b.stream):
-                prob = b.setup_slot(slot, torch.as_tensor(f, device=device))
-                a = torch.as_tensor(rho0, device=device)
+                prob = b.setup_slot(slot, _dev(f, device))
+                a = _dev(rho0, device)
                 tmp = torch.empty_like(a)
                 for _ in range(filter_passes):
                     prob.filter(a, out=tmp)
@@ -311,6 +354,7 @@ def run_engine_batched(requests, arrivals=None, *, device="cuda:0", nslots=16, n
                 rec["info"] = prob.solve_end()
                 with torch.cuda.stream(c["batch"].stream):
                     rec["dc"], rec["comp"] = prob.sensitivity(rec["rho"], rec["u"])
+                    rec["comp_host"] = _comp_out(rec["req"], rec["comp"])
                     ev = torch.cuda.Event()
                     ev.record(c["batch"].stream)
                 finishing.append((rec, ev))
@@ -329,7 +373,7 @@ def run_engine_batched(requests, arrivals=None, *, device="cuda:0", nslots=16, n
             out = {"id": rec["req"]["id"], "grid": rec["req"]["grid"], "arrival": rec["arrival"],
                    "admit": rec["admit"], "finish": t_done, "latency": t_done - rec["arrival"],
                    "iters": info["iters"], "outer_iters": info["outer_iters"], "rel_res": info["rel_res"],
-                   "compliance": float(rec["comp"].item()), "slot": rec["slot"]}
+                   "compliance": _comp_value(rec["comp_host"], rec["comp"]), "slot": rec["slot"]}
             if keep_outputs:
                 out["u"] = rec["u"].cpu().numpy()
                 out["dc"] = rec["dc"].cpu().numpy()

@@ -153,3 +153,24 @@ def test_sequential_reuse_matches_fresh_problems():
         assert a[r["id"]]["iters"] == b[r["id"]]["iters"]
         assert np.array_equal(a[r["id"]]["u"], b[r["id"]]["u"])
         assert np.array_equal(a[r["id"]]["dc"], b[r["id"]]["dc"])
+
+
+def test_pinned_payloads_match_generated_inputs():
+    """Requests that arrive with their inputs in pinned host memory (copied
+    to the device asynchronously on each design's stream, the compliance
+    read back through a pinned slot) give bitwise the results of inputs
+    generated and copied synchronously, in every engine."""
+    import copy
+    reqs = _requests(8, seed=11)
+    paid = serve.attach_payloads(copy.deepcopy(reqs))
+    base, _ = serve.run_sequential(reqs, device=DEV, keep_outputs=True)
+    for run in (lambda r: serve.run_sequential(r, device=DEV, keep_outputs=True),
+                lambda r: serve.run_engine(r, None, device=DEV, keep_outputs=True),
+                lambda r: serve.run_engine_batched(r, None, device=DEV, nslots=3, keep_outputs=True)):
+        got, _ = run(paid)
+        for r in reqs:
+            a, b = base[r["id"]], got[r["id"]]
+            assert a["iters"] == b["iters"]
+            assert a["compliance"] == b["compliance"]
+            assert np.array_equal(a["u"], b["u"])
+            assert np.array_equal(a["dc"], b["dc"])
