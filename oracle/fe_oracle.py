@@ -20,7 +20,7 @@ Conventions (structured hex8 voxel mesh, element size h):
   (0,0,0) (1,0,0) (1,1,0) (0,1,0) (0,0,1) (1,0,1) (1,1,1) (0,1,1);
   local dof = 3*a + c.
 
-Readings where the paper is silent (each listed in the design doc):
+Readings where the paper is silent:
   * the element is the trilinear 8-node brick with full 2x2x2 Gauss
     quadrature; the PDE is isotropic linear elasticity (Sec. III-D: K(z)u = f);
   * the stiffness interpolation is SIMP, E(rho) = Emin + rho^p (E0 - Emin);

@@ -7,7 +7,7 @@ TEST INFRASTRUCTURE ONLY.  Imported by ``tests/``;
 nothing in the product path imports, links or calls it, and it
 imports nothing from the product package.
 
-Readings where the paper is silent (each listed in the design doc):
+Readings where the paper is silent:
   * a sample is one block of nb^3 fine elements: its input is the block's
     design variables (local order x fastest, then y, then z) followed by the
     24 coarse displacements of its coarse element (local node order of
