@@ -178,7 +178,11 @@ def coarse_solve_record(nx, ny, nz, args, degree):
     if form == 5 and wide:
         form = 3
     if form == 5:
-        name, steps, shape = "cheb3t_kernel", 3, "3D tiles of 4 x 4 x 4 nodes"
+        import torch
+        cus = torch.cuda.get_device_properties(0).multi_processor_count
+        nblk = lambda ox, oy, oz: ((cx + ox) // ox) * ((cy + oy) // oy) * ((cz + oz) // oz)
+        ox, oy = (2, 2) if nblk(2, 2, 4) <= cus else (2, 4) if nblk(2, 4, 4) <= cus else (4, 4)
+        name, steps, shape = f"cheb3t_kernel<{ox}, {oy}, 4>", 3, f"3D tiles of {ox} x {oy} x 4 nodes"
         launches = 2 if degree == 4 else (degree + 2) // 3
     else:
         oz = 8 if form == 4 and not wide else 4

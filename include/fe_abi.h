@@ -305,9 +305,11 @@ FE_API fe_status fe_get_mg_params(const fe_problem* p, int32_t* nu, int32_t* coa
 /* Launches of the Chebyshev steps (the coarsest-level solve and the
  * Chebyshev smoothing of middle levels; on small grids they are bound by
  * launch and memory latency, not by arithmetic):
- *   5: three steps in one launch on 3D tiles of 4 x 4 x 4 nodes with a
- *     three-node halo (float32 levels; float64 ones take form 3), the
- *     remainder in pairs (a single step for an odd remainder);
+ *   5: three steps in one launch on 3D tiles with a three-node halo, of
+ *     2 x 2 x 4, 2 x 4 x 4 or 4 x 4 x 4 nodes (the smallest whose launch has
+ *     at most one workgroup per compute unit; float32 levels, float64 ones
+ *     take form 3), the remainder in pairs (a single step for an odd
+ *     remainder);
  *   3, 4: pairs of steps in one launch on 3D tiles (a workgroup owns 4 x 4 x 4
  *     nodes (3) or 4 x 4 x 8 (4; float32 levels only, float64 levels take
  *     4 x 4 x 4), works on all their levels at once and recomputes the

@@ -27,6 +27,9 @@
 #ifndef FE_CHEB_TRIPLES
 #define FE_CHEB_TRIPLES 1  // automatic coarse form: three steps per launch where 4 x 4 x 4 blocks fit
 #endif
+#ifndef FE_CHEB3_SHAPE
+#define FE_CHEB3_SHAPE 0  // blocks of the three-step launches: 0 automatic, 1: 4x4x4, 2: 2x4x4, 3: 2x2x4 nodes
+#endif
 #ifndef FE_CS_DEG
 #define FE_CS_DEG 6  // default Chebyshev smoothing steps
 #endif

@@ -1295,34 +1295,73 @@ __global__ void __launch_bounds__(C3<OZ>::THREADS) cheb3d_kernel(Grid g, int gx,
 }
 
 // Three steps of the coarsest-level Chebyshev iteration in one launch, on
-// 4 x 4 x 4 owned nodes with a three-node halo (a 10 x 10 x 10 node box):
-// the bricks of step k on the 9^3 bricks of the box, the node updates on the
-// 8^3 nodes inside, step k + 1 on 7^3 bricks and 6^3 nodes, step k + 2 on
-// 5^3 bricks and the owned nodes.  Each phase is the pair kernel's (same
-// brick products, node sums in the same corner order, same per-dof update),
-// so three steps here are bitwise two launches of that kernel's steps plus
-// one, in any grouping.  float32 only (its brick products fill 70 KB of
-// LDS; float64 ones would not fit with the box).
+// OX x OY x OZ owned nodes with a three-node halo (an (OX + 6) x (OY + 6) x
+// (OZ + 6) node box): the bricks of step k on all bricks of the box, the
+// node updates one node inside, step k + 1 on the bricks one inside and the
+// nodes two inside, step k + 2 on the bricks around the owned block and the
+// owned nodes.  Each phase is the pair kernel's (same brick products, node
+// sums in the same corner order, same per-dof update), so three steps here
+// are bitwise two launches of that kernel's steps plus one, in any
+// grouping, for any block shape.  float32 only (the brick products of a
+// 4 x 4 x 4 block fill 70 KB of LDS; float64 ones would not fit with the
+// box).
+template <int OX, int OY, int OZ>
 struct C3T {
-  static constexpr int IN = 10, IZ = 10;   // box nodes per axis (three-node halo around 4)
-  static constexpr int NIN = IN * IN * IZ;
-  static constexpr int B1X = IN - 1, B1Z = IZ - 1;
-  static constexpr int NB1 = B1X * B1X * B1Z;  // step-k bricks
+  static constexpr int IX = OX + 6, IY = OY + 6, IZ = OZ + 6;  // box nodes per axis
+  static constexpr int NIN = IX * IY * IZ;
+  static constexpr int B1X = IX - 1, B1Y = IY - 1, B1Z = IZ - 1;
+  static constexpr int NB1 = B1X * B1Y * B1Z;  // step-k bricks
   static constexpr int THREADS = (NB1 + 63) / 64 * 64;
-  static constexpr int NOWN = C3_OWN * C3_OWN * C3_OWN;
+  static constexpr int NOWN = OX * OY * OZ;
 };
 
-__global__ void __launch_bounds__(C3T::THREADS) cheb3t_kernel(Grid g, int gx, int gy, int nblk, int per,
-                                                             const float* __restrict__ dk,
-                                                             const float* __restrict__ E,
-                                                             const uint8_t* __restrict__ nmask, WK<float> wk,
-                                                             const float* __restrict__ invd,
-                                                             const float* __restrict__ rin, float* __restrict__ rout,
-                                                             float* __restrict__ acc, float* __restrict__ y,
-                                                             Cheb2<float> cf, CgState* st, int64_t wsh) {
-  using Q = C3T;
+// Brick products of the BX x BY x BZ bricks from local node (lo, lo, lo) of
+// a box of geometry G (moduli of its B1X x B1Y x B1Z bricks): thread e
+// computes brick e.
+template <typename T, class G, int BX, int BY, int BZ>
+__device__ inline void box_bricks(const T (*sd)[G::NIN], const T* sE, int lo, const WK<T>& wk, T (*sbo)[G::NB1]) {
+  const int e = threadIdx.x;
+  if (e >= BX * BY * BZ) return;
+  const int bi = lo + e % BX, bj = lo + (e / BX) % BY, bk = lo + e / (BX * BY);
+  const int n0 = bi + G::IX * (bj + G::IY * bk);
+  T u[3][8];
+#pragma unroll
+  for (int a = 0; a < 8; ++a) {
+    const int n = n0 + kCornerX[a] + G::IX * (kCornerY[a] + G::IY * kCornerZ[a]);
+#pragma unroll
+    for (int c = 0; c < 3; ++c) u[c][a] = sd[c][n];
+  }
+  T yv[3][8];
+  brick_full(u, sE[bi + G::B1X * (bj + G::B1Y * bk)], wk, yv);
+#pragma unroll
+  for (int c = 0; c < 3; ++c)
+#pragma unroll
+    for (int a = 0; a < 8; ++a) sbo[c * 8 + a][e] = yv[c][a];
+}
+
+// (K d)_c at local node (li, lj, lk) from the products of the BX x BY x ...
+// bricks starting at local node lo: its 8 bricks in local corner order.
+template <typename T, class G, int BX, int BY>
+__device__ inline T box_node_sum(const T (*sbo)[G::NB1], int c, int li, int lj, int lk, int lo) {
+  T v = T(0);
+#pragma unroll
+  for (int a = 0; a < 8; ++a) {
+    const int e = (li - lo - kCornerX[a]) + BX * ((lj - lo - kCornerY[a]) + BY * (lk - lo - kCornerZ[a]));
+    v = v + sbo[c * 8 + a][e];
+  }
+  return v;
+}
+
+template <int OX, int OY, int OZ>
+__global__ void __launch_bounds__((C3T<OX, OY, OZ>::THREADS)) cheb3t_kernel(
+    Grid g, int gx, int gy, int nblk, int per, const float* __restrict__ dk, const float* __restrict__ E,
+    const uint8_t* __restrict__ nmask, WK<float> wk, const float* __restrict__ invd, const float* __restrict__ rin,
+    float* __restrict__ rout, float* __restrict__ acc, float* __restrict__ y, Cheb2<float> cf, CgState* st,
+    int64_t wsh) {
+  using Q = C3T<OX, OY, OZ>;
   using T = float;
   static_assert(Q::NIN <= 2 * Q::THREADS, "two passes cover the box");
+  static_assert((Q::IX - 2) * (Q::IY - 2) * (Q::IZ - 2) <= Q::THREADS, "one pass covers the first node phase");
   static_assert(sizeof(T) * (10 * Q::NIN + 25 * Q::NB1) + Q::NIN <= 160 * 1024, "LDS of one workgroup");
   if (wsh) {  // batched launch: this workgroup's problem
     const int64_t o = batch_offset(wsh);
@@ -1343,7 +1382,7 @@ __global__ void __launch_bounds__(C3T::THREADS) cheb3t_kernel(Grid g, int gx, in
   __shared__ T sBO[24][Q::NB1];
   __shared__ uint8_t sM[Q::NIN];
   const int tx = tile % gx, t1 = tile / gx, ty = t1 % gy, tz = t1 / gy;
-  const int I0 = tx * C3_OWN - 3, J0 = ty * C3_OWN - 3, K0 = tz * C3_OWN - 3;
+  const int I0 = tx * OX - 3, J0 = ty * OY - 3, K0 = tz * OZ - 3;
   const int64_t sx = g.nx + 1, sxy = sx * (g.ny + 1);
   const int tid = threadIdx.x;
   int oi = 0, oj = 0, ok = 0;
@@ -1351,9 +1390,9 @@ __global__ void __launch_bounds__(C3T::THREADS) cheb3t_kernel(Grid g, int gx, in
   int64_t own_node = 0;
   T a0[3] = {T(0), T(0), T(0)};
   if (tid < Q::NOWN) {
-    oi = 3 + tid % C3_OWN;
-    oj = 3 + (tid / C3_OWN) % C3_OWN;
-    ok = 3 + tid / (C3_OWN * C3_OWN);
+    oi = 3 + tid % OX;
+    oj = 3 + (tid / OX) % OY;
+    ok = 3 + tid / (OX * OY);
     const int i = I0 + oi, j = J0 + oj, k = K0 + ok;
     own_in = i <= g.nx && j <= g.ny && k <= g.nz;  // owned nodes are never below the mesh
     own_node = i + sx * j + sxy * k;
@@ -1369,7 +1408,7 @@ __global__ void __launch_bounds__(C3T::THREADS) cheb3t_kernel(Grid g, int gx, in
   };
   const bool form_d = cf.dscale != T(0);
   auto load_node = [&](int n, NodeIn& v) {
-    const int i = I0 + n % Q::IN, j = J0 + (n / Q::IN) % Q::IN, k = K0 + n / (Q::IN * Q::IN);
+    const int i = I0 + n % Q::IX, j = J0 + (n / Q::IX) % Q::IY, k = K0 + n / (Q::IX * Q::IY);
     const bool in = n < Q::NIN && i >= 0 && i <= g.nx && j >= 0 && j <= g.ny && k >= 0 && k <= g.nz;
 #pragma unroll
     for (int c = 0; c < 3; ++c) v.d[c] = v.r[c] = T(0);
@@ -1401,7 +1440,7 @@ __global__ void __launch_bounds__(C3T::THREADS) cheb3t_kernel(Grid g, int gx, in
   load_node(tid + Q::THREADS, v1);
   T Eb = T(0);
   {
-    const int i = I0 + tid % Q::B1X, j = J0 + (tid / Q::B1X) % Q::B1X, k = K0 + tid / (Q::B1X * Q::B1X);
+    const int i = I0 + tid % Q::B1X, j = J0 + (tid / Q::B1X) % Q::B1Y, k = K0 + tid / (Q::B1X * Q::B1Y);
     if (tid < Q::NB1 && i >= 0 && i < g.nx && j >= 0 && j < g.ny && k >= 0 && k < g.nz)
       Eb = E[i + (int64_t)g.nx * (j + (int64_t)g.ny * k)];
   }
@@ -1414,22 +1453,24 @@ __global__ void __launch_bounds__(C3T::THREADS) cheb3t_kernel(Grid g, int gx, in
   // d_k at the owned node, before its buffer takes d_{k+2}
   T d0own[3] = {T(0), T(0), T(0)};
   if (tid < Q::NOWN) {
-    const int n = oi + Q::IN * (oj + Q::IN * ok);
+    const int n = oi + Q::IX * (oj + Q::IY * ok);
 #pragma unroll
     for (int c = 0; c < 3; ++c) d0own[c] = sD0[c][n];
   }
-  // one step on the nodes of [lo + 1, lo + 1 + NX)^3: residual and direction
-  // from the bricks of [lo, lo + NX + 1)^3 (in sBO), d from din to dout
-  auto node_step = [&](auto nx_c, int lo, const T (*din)[Q::NIN], T (*dout)[Q::NIN], T c1, T c2) {
-    constexpr int NX = decltype(nx_c)::value;
-    if (tid < NX * NX * NX) {
-      const int li = lo + 1 + tid % NX, lj = lo + 1 + (tid / NX) % NX, lk = lo + 1 + tid / (NX * NX);
-      const int n = li + Q::IN * (lj + Q::IN * lk);
+  // one step on the NX x NY x NZ nodes from local node lo + 1: residual and
+  // direction from the bricks of the box one larger from lo (in sBO), d from
+  // din to dout
+  auto node_step = [&](auto nx_c, auto ny_c, auto nz_c, int lo, const T (*din)[Q::NIN], T (*dout)[Q::NIN], T c1,
+                       T c2) {
+    constexpr int NX = decltype(nx_c)::value, NY = decltype(ny_c)::value, NZ = decltype(nz_c)::value;
+    if (tid < NX * NY * NZ) {
+      const int li = lo + 1 + tid % NX, lj = lo + 1 + (tid / NX) % NY, lk = lo + 1 + tid / (NX * NY);
+      const int n = li + Q::IX * (lj + Q::IY * lk);
       const uint8_t m = sM[n];
 #pragma unroll
       for (int c = 0; c < 3; ++c) {
         const bool fx = (m >> c) & 1;
-        T v = c3_node_sum<T, Q, NX + 1>(sBO, c, li, lj, lk, lo);
+        T v = box_node_sum<T, Q, NX + 1, NY + 1>(sBO, c, li, lj, lk, lo);
         if (fx) v = T(0);
         T rn, dn;
         cheb_dof(fx, sR[c][n], v, din[c][n], sInv[n], c1, c2, rn, dn);
@@ -1438,27 +1479,29 @@ __global__ void __launch_bounds__(C3T::THREADS) cheb3t_kernel(Grid g, int gx, in
       }
     }
   };
-  // step k: bricks of the box, nodes of [1, 9)^3
-  c3_bricks<T, Q, 9, 9>(sD0, sE, 0, wk, sBO);
+  // step k: bricks of the box, nodes one inside
+  box_bricks<T, Q, Q::B1X, Q::B1Y, Q::B1Z>(sD0, sE, 0, wk, sBO);
   __syncthreads();
-  node_step(std::integral_constant<int, 8>{}, 0, sD0, sD1, cf.c1a, cf.c2a);
+  node_step(std::integral_constant<int, OX + 4>{}, std::integral_constant<int, OY + 4>{},
+            std::integral_constant<int, OZ + 4>{}, 0, sD0, sD1, cf.c1a, cf.c2a);
   __syncthreads();
-  // step k + 1: bricks of [1, 8)^3, nodes of [2, 8)^3 (d_{k+2} into sD0)
-  c3_bricks<T, Q, 7, 7>(sD1, sE, 1, wk, sBO);
+  // step k + 1: bricks one inside, nodes two inside (d_{k+2} into sD0)
+  box_bricks<T, Q, OX + 3, OY + 3, OZ + 3>(sD1, sE, 1, wk, sBO);
   __syncthreads();
-  node_step(std::integral_constant<int, 6>{}, 1, sD1, sD0, cf.c1b, cf.c2b);
+  node_step(std::integral_constant<int, OX + 2>{}, std::integral_constant<int, OY + 2>{},
+            std::integral_constant<int, OZ + 2>{}, 1, sD1, sD0, cf.c1b, cf.c2b);
   __syncthreads();
-  // step k + 2: bricks of [2, 7)^3, the owned nodes
-  c3_bricks<T, Q, 5, 5>(sD0, sE, 2, wk, sBO);
+  // step k + 2: bricks around the owned block, the owned nodes
+  box_bricks<T, Q, OX + 1, OY + 1, OZ + 1>(sD0, sE, 2, wk, sBO);
   __syncthreads();
   if (tid < Q::NOWN && own_in) {
-    const int n = oi + Q::IN * (oj + Q::IN * ok);
+    const int n = oi + Q::IX * (oj + Q::IY * ok);
     const uint8_t m = sM[n];
     T rn[3], dn[3], an[3];
 #pragma unroll
     for (int c = 0; c < 3; ++c) {
       const bool fx = (m >> c) & 1;
-      T v = c3_node_sum<T, Q, 5>(sBO, c, oi, oj, ok, 2);
+      T v = box_node_sum<T, Q, OX + 1, OY + 1>(sBO, c, oi, oj, ok, 2);
       if (fx) v = T(0);
       cheb_dof(fx, sR[c][n], v, sD0[c][n], sInv[n], cf.c1c, cf.c2c, rn[c], dn[c]);
       an[c] = ((cf.first ? d0own[c] : a0[c] + d0own[c]) + sD1[c][n]) + sD0[c][n];
@@ -1867,12 +1910,34 @@ hipError_t launch_cheb3(fe_problem* p, int lev, const T* dk, T* y, const T* E, c
     cf.c2c = (T)c[5];
     cf.first = first;
     cf.dscale = (T)dscale;
-    const int gx = (g.nx + C3_OWN) / C3_OWN, gy = (g.ny + C3_OWN) / C3_OWN;
-    const int64_t nblk = (int64_t)gx * gy * ((g.nz + C3_OWN) / C3_OWN), per = (nblk + 7) / 8;
+    // block shape: the smallest of 2 x 2 x 4, 2 x 4 x 4 and 4 x 4 x 4 nodes
+    // whose launch (all batch slots) still has at most one workgroup per
+    // compute unit -- more units at work, each with a smaller first brick
+    // phase, for a larger share of recomputed halo (28 x 14 x 7 coarsest
+    // grid: 6.8 / 7.3 / 7.7 us per launch; 2 x 2 x 2 blocks, two workgroups
+    // per unit: 10.3 us)
+    const int64_t cus = device_cus();
+    auto blocks = [&](int ox, int oy, int oz) {
+      return (int64_t)((g.nx + ox) / ox) * ((g.ny + oy) / oy) * ((g.nz + oz) / oz);
+    };
+    int shape = FE_CHEB3_SHAPE;
+    if (shape == 0) shape = blocks(2, 2, 4) * p->bcount <= cus ? 3 : blocks(2, 4, 4) * p->bcount <= cus ? 2 : 1;
+    const int ox = shape == 1 ? 4 : 2, oy = shape == 3 ? 2 : 4, oz = 4;
+    const int gx = (g.nx + ox) / ox, gy = (g.ny + oy) / oy;
+    const int64_t nblk = blocks(ox, oy, oz), per = (nblk + 7) / 8;
     if (8 * per > ((int64_t)1 << 31) - 1) return hipErrorInvalidValue;
-    hipLaunchKernelGGL(cheb3t_kernel, dim3((unsigned)(8 * per), p->bcount), dim3(C3T::THREADS), 0, p->stream, g,
-                       gx, gy, (int)nblk, (int)per, dk, E, p->L[lev].nmask, scaled_wk<T>(p->wk, p->L[lev].h), invd,
-                       rin, rout, acc, y, cf, st, p->bcount > 1 ? p->bstride : (int64_t)0);
+    const dim3 grid((unsigned)(8 * per), p->bcount);
+    const WK<T> wk = scaled_wk<T>(p->wk, p->L[lev].h);
+    const int64_t wsh = p->bcount > 1 ? p->bstride : (int64_t)0;
+    if (shape == 3)
+      hipLaunchKernelGGL((cheb3t_kernel<2, 2, 4>), grid, dim3(C3T<2, 2, 4>::THREADS), 0, p->stream, g, gx, gy,
+                         (int)nblk, (int)per, dk, E, p->L[lev].nmask, wk, invd, rin, rout, acc, y, cf, st, wsh);
+    else if (shape == 2)
+      hipLaunchKernelGGL((cheb3t_kernel<2, 4, 4>), grid, dim3(C3T<2, 4, 4>::THREADS), 0, p->stream, g, gx, gy,
+                         (int)nblk, (int)per, dk, E, p->L[lev].nmask, wk, invd, rin, rout, acc, y, cf, st, wsh);
+    else
+      hipLaunchKernelGGL((cheb3t_kernel<4, 4, 4>), grid, dim3(C3T<4, 4, 4>::THREADS), 0, p->stream, g, gx, gy,
+                         (int)nblk, (int)per, dk, E, p->L[lev].nmask, wk, invd, rin, rout, acc, y, cf, st, wsh);
     return hipGetLastError();
   }
 }
