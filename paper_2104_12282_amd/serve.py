@@ -14,8 +14,11 @@ rho and multigrid hierarchy resident in its own workspace.  Two engines:
   ABI (fe_solve_begin / fe_solve_step / fe_solve_end) on a few streams so
   that the designs' launches overlap.
 
-A design's arithmetic is exactly that of a lone fe_solve in both, so its
-result does not depend on the mix.  Per request the engines record arrival,
+A design's arithmetic does not depend on the mix: in a batch the launch
+forms follow only the grid and the batch's slot count, and it is that of a
+lone fe_solve except where a large batch's coarse Chebyshev launches march
+while the lone solve takes 3D tiles (the same polynomial, node sums rounded
+in another order).  Per request the engines record arrival,
 admission and completion times (completion = sensitivity finished on the
 device, observed by the host); they report designs/s and p50/p99 latency.
 """

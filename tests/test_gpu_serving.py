@@ -60,23 +60,33 @@ def test_served_design_matches_oracle():
     assert np.abs(r["dc"] - dc_ref).max() / np.abs(dc_ref).max() <= 1e-5
 
 
-@pytest.mark.parametrize("precision,grid", [("fp32_ir", (16, 8, 8)), ("fp64", (16, 8, 8)), ("fp32_ir", (13, 7, 5)),
-                                            ("fp64", (13, 7, 5)), ("fp32_ir", (96, 48, 48))])
-def test_batch_slots_match_lone_solves(precision, grid):
+@pytest.mark.parametrize("precision,grid,levels", [("fp32_ir", (16, 8, 8), 3), ("fp64", (16, 8, 8), 3),
+                                                   ("fp32_ir", (13, 7, 5), 3), ("fp64", (13, 7, 5), 3),
+                                                   ("fp32_ir", (96, 48, 48), 3), ("fp32_ir", (128, 64, 64), 3),
+                                                   ("fp64", (192, 32, 32), 4), ("fp32_ir", (192, 32, 32), 4)])
+def test_batch_slots_match_lone_solves(precision, grid, levels):
     """Designs sharing a batch's launches (one slot idle, slots reused)
     give bitwise the result of the same design solved alone, also on an odd
-    grid whose coarse levels overhang the mesh."""
+    grid whose coarse levels overhang the mesh, and with four levels whose
+    level 2 is smoothed by Chebyshev steps (on by default over a coarsest
+    grid of 24 elements) -- as long as the batch's coarse Chebyshev launches
+    take the lone solve's form.  The forms follow the workgroups of a launch
+    (3D tiles while every slot's blocks get a compute unit each, else the
+    z-march), so on the largest serving grid the batch of three marches
+    where the lone solve takes 3D tiles: the same polynomial with its node
+    sums rounded in another order, hence the same iterations within a few
+    and the same displacement to 1e-6 of its largest entry."""
     from paper_2104_12282_amd import fe
     nx, ny, nz = grid
     T = lambda a: torch.as_tensor(a, dtype=torch.float64, device=DEV)
     designs = [(synth.point_load(nx, ny, nz, s), synth.density_uniform(nx, ny, nz, s)) for s in (11, 12, 13, 14)]
     alone = []
     for f, rho in designs:
-        p = fe.Problem(nx, ny, nz, T(f), device=DEV, precision=precision, precond="gmg", mg_levels=3)
+        p = fe.Problem(nx, ny, nz, T(f), device=DEV, precision=precision, precond="gmg", mg_levels=levels)
         u, info = p.solve(T(rho), rtol=1e-8)
         alone.append((u.cpu().numpy(), info))
         p.close()
-    b = fe.Batch(nx, ny, nz, 3, device=DEV, precision=precision, mg_levels=3)
+    b = fe.Batch(nx, ny, nz, 3, device=DEV, precision=precision, mg_levels=levels)
     got = {}
     todo = list(range(len(designs)))
     live = {}
@@ -100,12 +110,24 @@ def test_batch_slots_match_lone_solves(precision, grid):
                 del live[s]
                 free.append(s)
     b.close()
+    # the library's choice of coarse launch form (fe_set_coarse_fusion)
+    cus = torch.cuda.get_device_properties(0).multi_processor_count
+    cx, cy, cz = nx, ny, nz
+    for _ in range(levels - 1):
+        cx, cy, cz = (cx + 1) // 2, (cy + 1) // 2, (cz + 1) // 2
+    cols = ((cx + 4) // 4) * ((cy + 4) // 4)
+    n4, n8 = cols * ((cz + 4) // 4), cols * ((cz + 8) // 8)
+    same_form = (n4 <= cus) == (n4 * 3 <= cus or n8 * 3 <= cus)
     for d in range(len(designs)):
         ua, ia = alone[d]
         ub, ib = got[d]
-        assert ia["iters"] == ib["iters"] and ia["outer_iters"] == ib["outer_iters"]
-        assert np.array_equal(ua, ub)
         assert ib["rel_res"] <= 1e-8
+        if same_form:
+            assert ia["iters"] == ib["iters"] and ia["outer_iters"] == ib["outer_iters"]
+            assert np.array_equal(ua, ub)
+        else:
+            assert abs(ia["iters"] - ib["iters"]) <= 2 + 0.15 * ia["iters"]
+            assert np.abs(ua - ub).max() <= 1e-6 * np.abs(ua).max()
 
 
 def test_batched_engine_matches_sequential():
