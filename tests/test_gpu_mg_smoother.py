@@ -186,3 +186,27 @@ def test_cheb_triples_bitwise_pairs(grid, levels, deg, precision):
     assert i3["rel_res"] <= 1e-8
     assert i3["iters"] == i5["iters"] and i3["outer_iters"] == i5["outer_iters"]
     assert np.array_equal(u3, u5)
+
+
+@pytest.mark.parametrize("grid,levels", [((8, 4, 4), 4), ((9, 5, 3), 4), ((16, 8, 8), 5), ((3, 2, 1), 3),
+                                         ((12, 2, 2), 4)])
+@pytest.mark.parametrize("precision", ["fp64", "fp32_ir"])
+def test_cheb_smoothing_degenerate_grids(grid, levels, precision):
+    """Deep hierarchies on tiny and thin grids (coarsest levels of one or
+    two elements, odd axes overhanging the mesh, blocks of the three-step
+    launch mostly off the mesh) with Chebyshev smoothing from level 1 or 2:
+    the oracle's compliance and sensitivity."""
+    nx, ny, nz = grid
+    Ke = O.hex8_ke(NU)
+    rho = synth.density_around(nx, ny, nz, 5)
+    f = synth.cantilever_edge_load(nx, ny, nz)
+    u_ref = O.solve_direct(nx, ny, nz, O.simp_modulus(rho), Ke, f, O.clamp_x0_fixed(nx, ny, nz))
+    c_ref = O.compliance(f, u_ref)
+    dc_ref = O.sensitivity(nx, ny, nz, Ke, rho, u_ref)
+    prob = _problem(nx, ny, nz, precision, levels)
+    prob.set_mg_smoother(min(2, levels - 2), 6, 100.0)
+    u, info = prob.solve(T(rho), rtol=1e-10)
+    dc, c = prob.sensitivity(T(rho), u)
+    assert info["status"] == 0 and info["rel_res"] <= 1e-10
+    assert abs(float(N(c)[0]) - c_ref) / c_ref <= 1e-6
+    assert np.abs(N(dc) - dc_ref).max() / np.abs(dc_ref).max() <= 1e-5
