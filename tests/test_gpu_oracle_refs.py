@@ -48,14 +48,14 @@ def _density(case, seed):
     return rho
 
 
-def _check(case, seed, precision, precond, rtol=1e-8):
+def _check(case, seed, precision, precond, rtol=1e-8, levels=3):
     (nx, ny, nz), _ = CASES[case]
     c_ref, dc_ref, dc_max = _reference(case, seed)
     rho = _density(case, seed)
-    kw = {"mg_levels": 3} if precond == "gmg" else {}
+    kw = {"mg_levels": levels} if precond == "gmg" else {}
     prob = fe.Problem(nx, ny, nz, T(synth.cantilever_edge_load(nx, ny, nz)), device=DEV, precision=precision,
                       precond=precond, **kw)
-    print(f"oracle-ref: {case} seed {seed} {precision} {precond}", flush=True)
+    print(f"oracle-ref: {case} seed {seed} {precision} {precond} levels {levels}", flush=True)
     u, info = prob.solve(T(rho), rtol=rtol)
     dc, c = prob.sensitivity(T(rho), u)
     torch.cuda.synchronize()
@@ -79,9 +79,13 @@ def test_c2_multigrid(precision):
     _check("c2", 0, precision, "gmg")
 
 
+@pytest.mark.parametrize("levels", [3, 4])
 @pytest.mark.parametrize("precision", ["fp64", "fp32_ir", "bf16_ir", "bf16x3_ir"])
-def test_c4_seed0_every_precision(precision):
-    _check("c4", 0, precision, "gmg")
+def test_c4_seed0_every_precision(precision, levels):
+    """224x112x56 against the oracle's stored solution in every precision,
+    with three levels and with the loop's four (Chebyshev-smoothed level 2,
+    three-step coarse launches)."""
+    _check("c4", 0, precision, "gmg", levels=levels)
 
 
 @pytest.mark.parametrize("seed", [1, 2, 3])
