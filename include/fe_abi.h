@@ -332,7 +332,7 @@ FE_API fe_status fe_set_coarse_fusion(fe_problem* p, int32_t steps_per_launch);
  * only the launches of form m (1 = CG product, 3 = smoothing sweep,
  * 4 = residual, 5 = last smoothing sweep with r^T z, 6 = Chebyshev step,
  * 0 = plain product), and with m = 7 each coarsest-level Chebyshev solve
- * (its launches of pairs of steps, the largest share of a multigrid solve's
+ * (its launches of two or three steps, the largest share of a multigrid solve's
  * time, bracketed as one: a launch of a few microseconds is shorter than an
  * event pair's own cost); on = 0 switches it off, other values are
  * FE_EINVAL.

@@ -284,7 +284,7 @@ hipError_t cheb_run(fe_problem* p, int l, T* r_src, T* r_a, T* r_b, T* z, T* d0,
   T* rin = r_src;
   T* rout = r_a;
   // profiling form 7: one event pair around a coarsest-level solve's
-  // launches; the algorithmic bytes of each launch (one or two steps) read
+  // launches; the algorithmic bytes of each launch (one, two or three steps) read
   // d_k, r_k, the iterate, D^-1, the fixed-dof mask and E and write the
   // residual, the iterate and the next direction, each array once
   int prof = -1;

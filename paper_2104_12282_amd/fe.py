@@ -367,7 +367,7 @@ class Problem:
 
     def set_profiling(self, on, mode=None):
         """Times finest-grid K*u launches: all forms, or only form `mode`
-        (mode 7: the coarsest-level Chebyshev pair launches)."""
+        (mode 7: the coarsest-level Chebyshev launches, one event pair per solve)."""
         sel = 0 if not on else (1 if mode is None else 2 + int(mode))
         _check(load_library().fe_set_profiling(self._h, sel))
 
