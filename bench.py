@@ -794,7 +794,7 @@ def serving_bench(n, torch, nslots=16, nstreams=5):
     out = {"requests": n, "grids": [list(g) for g in synth.SERVING_GRIDS],
            "per_request": "load at a random node of x = nx (random direction), density U(0.01,1) "
                           "(both arriving with the request in pinned host memory, copied to the device "
-                          "asynchronously) through 3 filter passes, float32 CG with 3-level multigrid "
+                          "asynchronously) through 3 filter passes, float32 CG with 4-level multigrid "
                           "inside float64 refinement to 1e-8, then sensitivity",
            "engine": f"fe_batch per grid size, {nslots} slots each; CG chunks of all slots in shared "
                      "launches; designs admitted into free slots between replays",
