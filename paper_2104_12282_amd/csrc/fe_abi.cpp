@@ -264,7 +264,10 @@ const float* fine_E<float>(fe_problem* p) { return p->L[0].E32; }
 // them: three launch groups per iteration instead of seven.
 //   1. direction + product: p = z + beta p_old (beta from the r^T z partials
 //      of the last V-cycle), q = K p, p^T q partials;
-//   2. update: alpha, x += alpha p, r -= alpha q, r^T r partials;
+//   2. update: alpha, r -= alpha q, r^T r partials, and x += alpha p every
+//      second iteration for two steps (x += alpha_1 p_1 + alpha_2 p_2 while
+//      both directions are in their buffers; a stop after the deferring
+//      iteration applies the last step with cg_flush_x);
 //   3. V-cycle z = M r whose first kernel takes the convergence decision and
 //      whose last sweep leaves r^T z partials.
 // The direction alternates between two buffers (other workgroups still read
@@ -285,6 +288,10 @@ hipError_t cg_iteration(fe_problem* p, T* x, T* r, T* pv, T* q, int it) {
     T* pold = (it & 1) ? pb : pv;
     T* pnew = (it & 1) ? pv : pb;
     int npq = 0, nrr = 0;
+    // chunks have even lengths and start at even positions: an even
+    // iteration defers its x update to the odd one after it
+    T* xu = (it & 1) ? x : nullptr;
+    const T* xp = (it & 1) ? pold : nullptr;
     TileFuse<T> fz;
     fz.xin = 2;
     fz.pold = pold;
@@ -305,10 +312,10 @@ hipError_t cg_iteration(fe_problem* p, T* x, T* r, T* pv, T* q, int it) {
       return e;
     if (f32_l0) {
       float* r32 = static_cast<float*>(p->L[0].mg_r);
-      if ((e = launch_cg_update_mg<T>(p, x, r, pnew, q, p->st, npq, &nrr, r32)) != hipSuccess) return e;
+      if ((e = launch_cg_update_mg<T>(p, xu, r, pnew, q, p->st, npq, &nrr, r32, xp)) != hipSuccess) return e;
       return launch_vcycle<float>(p, 0, r32, z32, p->st, RZ_PARTIALS, nrr);
     }
-    if ((e = launch_cg_update_mg<T>(p, x, r, pnew, q, p->st, npq, &nrr)) != hipSuccess) return e;
+    if ((e = launch_cg_update_mg<T>(p, xu, r, pnew, q, p->st, npq, &nrr, nullptr, xp)) != hipSuccess) return e;
     return launch_vcycle<T>(p, 0, r, z, p->st, RZ_PARTIALS, nrr);
   }
   if ((e = launch_kxu<T>(p, 0, pv, q, p->st)) != hipSuccess) return e;
@@ -525,6 +532,8 @@ fe_status advance(fe_problem* p) {
       }
       sc.info.iters = hs.iter;
       sc.result = (fe_status)hs.status;
+      // an odd count: the last iteration deferred its x update
+      if (folded_mg(p) && (hs.iter & 1)) HIP_TRY(launch_cg_flush_x<double>(p, p->x64, p->st));
       HIP_TRY(hipMemcpyAsync(sc.u, p->x64, p->L[0].g.ndof * sizeof(double), hipMemcpyDeviceToDevice,
                              p->stream));
       return enqueue_finish(p, true);
@@ -615,6 +624,9 @@ fe_status advance(fe_problem* p) {
       sc.outer += 1;
       sc.info.iters = sc.total;
       sc.info.outer_iters = sc.outer;
+      // an odd count since the chunks' parity origin: the last iteration
+      // deferred its x update
+      if (folded_mg(p) && ((hs.iter - sc.chunk_iter0) & 1)) HIP_TRY(launch_cg_flush_x<float>(p, p->x32, p->st));
       if (hs.iter > 0) HIP_TRY(launch_axpy_from32(p, sc.u, p->x32, p->scal + 2 * SLOT_IRS));
       if (hs.status == FE_EBREAKDOWN && hs.iter == 0) {
         sc.result = FE_EBREAKDOWN;

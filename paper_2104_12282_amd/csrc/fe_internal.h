@@ -64,7 +64,7 @@ struct CgState {
   double bb;      // ||b||^2 (right-hand side)
   double tol2;    // stop when rr <= tol2
   double pq;      // p^T K p
-  double spare;
+  double x_alpha; // folded multigrid CG: step of a deferred x update (x += x_alpha x_dir)
   double rz_new;  // r^T z of the new preconditioned residual (multigrid CG, not yet committed)
   int32_t iter;   // iterations done
   int32_t max_iter;
@@ -72,6 +72,7 @@ struct CgState {
   int32_t status; // FE_OK, FE_ENOTCONV, FE_EBREAKDOWN
   int32_t iter_next;  // iteration count after the update in flight (multigrid CG)
   uint32_t counter[8];  // arrival counters of the last-block reductions
+  void* x_dir;    // the direction of the deferred x update (a vector of the solve's type)
 };
 
 // Constants of the element operator in the per-axis sum/difference basis.
@@ -387,7 +388,11 @@ hipError_t launch_cg_direction(fe_problem* p, const T* r, const T* z, T* pvec, C
 // With r32 given, the updated residual is also written there in float32.
 template <typename T>
 hipError_t launch_cg_update_mg(fe_problem* p, T* x, T* r, const T* pvec, const T* q, CgState* st, int npq,
-                               int* nrr, float* r32 = nullptr);
+                               int* nrr, float* r32 = nullptr, const T* pold = nullptr);
+// x += st->x_alpha st->x_dir: the x update a multigrid CG deferred when it
+// stopped after an iteration that defers it
+template <typename T>
+hipError_t launch_cg_flush_x(fe_problem* p, T* x, const CgState* st);
 // b = (float)a over the finest grid's dofs
 hipError_t launch_narrow(fe_problem* p, const double* a, float* b);
 

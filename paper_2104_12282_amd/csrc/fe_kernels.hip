@@ -225,20 +225,26 @@ __global__ void __launch_bounds__(FE_BLOCK) cg_update_kernel(Grid g, T* __restri
 
 // Multigrid CG update.  Every workgroup sums the p^T q partials the direction
 // kernel left (same order, same value), alpha = rz_new / p^T q; workgroup 0
-// commits rz and the step.  Then x += alpha p, r -= alpha q and r^T r
-// partials for the convergence test the next kernel takes.
+// commits rz and the step.  Then r -= alpha q with r^T r partials for the
+// convergence test the next kernel takes, and the iterate's update, made for
+// two iterations at once: with x null it is deferred (workgroup 0 records
+// alpha and p in st), with x given the deferred step is applied with this
+// one, x += x_alpha p_old + alpha p, while the previous direction p_old is
+// still in its buffer (x is read and written once per two iterations).
 template <typename T>
 __global__ void __launch_bounds__(FE_BLOCK) cg_update_mg_kernel(Grid g, T* __restrict__ x, T* __restrict__ r,
                                                                 const T* __restrict__ p,
                                                                 const T* __restrict__ q, CgState* st,
                                                                 const double* __restrict__ pq_part, int npq,
                                                                 double* partials, int64_t wsh,
-                                                                float* __restrict__ r32) {
+                                                                float* __restrict__ r32,
+                                                                const T* __restrict__ pold) {
   if (wsh) {  // batched launch: this workgroup's problem
     const int64_t o = batch_offset(wsh);
     x = wshift(x, o);
     r = wshift(r, o);
     p = wshift(p, o);
+    pold = wshift(pold, o);
     q = wshift(q, o);
     st = wshift(st, o);
     pq_part = wshift(pq_part, o);
@@ -261,8 +267,14 @@ __global__ void __launch_bounds__(FE_BLOCK) cg_update_mg_kernel(Grid g, T* __res
   __syncthreads();
   const double pq = tot, rz = st->rz_new;
   const bool bad = !(pq > 0.0) || !finite_d(pq);
+  // the deferred step (written by the previous update launch, not by this one)
+  const T xa = x ? (T)st->x_alpha : T(0);
   if (blockIdx.x == 0 && threadIdx.x == 0) {
     st->pq = pq;
+    if (!x && !bad) {
+      st->x_alpha = rz / pq;
+      st->x_dir = const_cast<T*>(p);
+    }
     if (bad) {
       st->status = FE_EBREAKDOWN;
       st->done = 1;
@@ -275,15 +287,30 @@ __global__ void __launch_bounds__(FE_BLOCK) cg_update_mg_kernel(Grid g, T* __res
   if (bad) return;
   const T alpha = (T)(rz / pq);
   double acc[1] = {0.0};
+  const bool upd_x = x != nullptr;
   for (int64_t d = blockIdx.x * (int64_t)FE_BLOCK + threadIdx.x; d < g.ndof;
        d += (int64_t)gridDim.x * FE_BLOCK) {
-    x[d] += alpha * p[d];
+    if (upd_x) {
+      T xv = x[d];
+      xv += xa * pold[d];
+      xv += alpha * p[d];
+      x[d] = xv;
+    }
     const T rv = r[d] - alpha * q[d];
     r[d] = rv;
     if (r32) r32[d] = (float)rv;  // the residual a float32 preconditioner reads
     acc[0] += (double)rv * (double)rv;
   }
   block_partials<1>(acc, partials);
+}
+
+// x += x_alpha x_dir (the update a multigrid CG deferred before it stopped)
+template <typename T>
+__global__ void __launch_bounds__(FE_BLOCK) cg_flush_x_kernel(int64_t n, T* __restrict__ x, const CgState* st) {
+  const T* __restrict__ p = static_cast<const T*>(st->x_dir);
+  const T alpha = (T)st->x_alpha;
+  for (int64_t d = blockIdx.x * (int64_t)FE_BLOCK + threadIdx.x; d < n; d += (int64_t)gridDim.x * FE_BLOCK)
+    x[d] += alpha * p[d];
 }
 
 // b = (float)a
@@ -1045,20 +1072,30 @@ constexpr int kUpdateMgGrid = 1024;
 
 template <typename T>
 hipError_t launch_cg_update_mg(fe_problem* p, T* x, T* r, const T* pvec, const T* q, CgState* st, int npq,
-                               int* nrr, float* r32) {
+                               int* nrr, float* r32, const T* pold) {
+  if (x && !pold) return hipErrorInvalidValue;  // applying the deferred step needs its direction
   const Grid g = G(p, 0);
   int nb = red_grid(g.ndof);
   if (nb > kUpdateMgGrid) nb = kUpdateMgGrid;
   hipLaunchKernelGGL(cg_update_mg_kernel<T>, dim3(nb, p->bcount), dim3(FE_BLOCK), 0, p->stream, g, x, r, pvec, q,
                      st, part_region(p, PART_PQ), npq, part_region(p, PART_RR),
-                     p->bcount > 1 ? p->bstride : (int64_t)0, r32);
+                     p->bcount > 1 ? p->bstride : (int64_t)0, r32, pold);
   *nrr = nb;
   return hipGetLastError();
 }
 template hipError_t launch_cg_update_mg<double>(fe_problem*, double*, double*, const double*, const double*,
-                                                CgState*, int, int*, float*);
+                                                CgState*, int, int*, float*, const double*);
 template hipError_t launch_cg_update_mg<float>(fe_problem*, float*, float*, const float*, const float*,
-                                               CgState*, int, int*, float*);
+                                               CgState*, int, int*, float*, const float*);
+
+template <typename T>
+hipError_t launch_cg_flush_x(fe_problem* p, T* x, const CgState* st) {
+  const int64_t n = G(p, 0).ndof;
+  hipLaunchKernelGGL(cg_flush_x_kernel<T>, dim3(red_grid(n) * 2), dim3(FE_BLOCK), 0, p->stream, n, x, st);
+  return hipGetLastError();
+}
+template hipError_t launch_cg_flush_x<double>(fe_problem*, double*, const CgState*);
+template hipError_t launch_cg_flush_x<float>(fe_problem*, float*, const CgState*);
 
 hipError_t launch_narrow(fe_problem* p, const double* a, float* b) {
   const int64_t n = G(p, 0).ndof;

@@ -239,6 +239,32 @@ def test_notconv_and_warm_start():
     assert info_warm["iters"] == 0
 
 
+@pytest.mark.parametrize("precision", ["fp64", "fp32_ir"])
+def test_every_iteration_count_moves_the_iterate(Ke, precision):
+    """Multigrid CG applies its x update every second iteration, for two
+    steps; a solve stopped after an iteration that deferred its step applies
+    it at the end.  CG minimises the energy 1/2 u^T K u - f^T u over growing
+    Krylov spaces, so after k = 1, 2, ... iterations (stopped by the cap) the
+    energy of the returned u (oracle K) falls strictly with k: a lost step
+    at an odd or even count would leave u where it was one iteration
+    earlier."""
+    nx, ny, nz = 16, 8, 8
+    rho = synth.density_around(nx, ny, nz, 2)
+    f = synth.cantilever_edge_load(nx, ny, nz)
+    fixed = O.clamp_x0_fixed(nx, ny, nz)
+    K = O.assemble_K(nx, ny, nz, O.simp_modulus(rho), Ke)
+    prob = _problem(nx, ny, nz, precision, precond="gmg", mg_levels=3)
+    energies = []
+    for k in range(1, 8):
+        u, info = prob.solve(T(rho), rtol=1e-14, max_iters=k, allow_notconv=True)
+        assert info["status"] == fe.FE_ENOTCONV and info["iters"] == k
+        un = N(u)
+        Ku = O.apply_K_free(K, fixed, un)
+        energies.append(0.5 * float(un @ Ku) - float(f @ un))
+    drops = -np.diff(energies)
+    assert (drops > 1e-9 * abs(energies[-1])).all(), energies
+
+
 def test_breakdown_on_nan_density():
     nx, ny, nz = 6, 3, 3
     rho = synth.density_around(nx, ny, nz, 1)
