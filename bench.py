@@ -888,8 +888,8 @@ def run_loop(fe, synth, torch, nx, ny, nz, precision, args, steps, warmup, profi
 
 def main():
     args = parse()
+    if args.gpus != 1:
         print(json.dumps({"error": "this benchmark measures one GPU: --gpus must be 1"}))
-        print(json.dumps({"error": "one GPU per run: --gpus must be 1 (the other GPUs serve other requests; see DESIGN.md, more than one GPU)"}))
         sys.exit(2)
     import torch
 
