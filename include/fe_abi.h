@@ -398,13 +398,18 @@ FE_API fe_status fe_batch_setup_slot(fe_batch* b, int32_t slot, const uint8_t* f
 /* One round, in two halves so that several batches (on different streams)
  * overlap: begin enqueues one replay of the batched CG chunk and the state
  * copies; end waits for them and advances every running slot by one stage,
- * returning the number of slots still running.  A slot that fails stops
- * with its status in fe_solve_end; the first such status is also returned. */
+ * returning the number of slots still running.  A slot whose new stage only
+ * waits for a short computation whose result the host needs (the float64
+ * residual of a refinement step, the final residual and compliance) is
+ * advanced again after one wait for the batch's stream, so that it rejoins
+ * the next replay, or finishes, within the same call instead of sitting a
+ * round out.  A slot that fails stops with its status in fe_solve_end; the
+ * first such status is also returned. */
 FE_API fe_status fe_batch_round_begin(fe_batch* b);
 FE_API fe_status fe_batch_round_end(fe_batch* b, int32_t* running);
 
 /* Whether the open round's work has completed on the device, without
- * waiting (*ready = 1: fe_batch_round_end returns without blocking; also 1
+ * waiting (*ready = 1: fe_batch_round_end does not wait for the replay; also 1
  * when no round is open), so that a serving loop can end and restart each
  * batch's rounds as they complete instead of in lockstep. */
 FE_API fe_status fe_batch_round_ready(fe_batch* b, int32_t* ready);

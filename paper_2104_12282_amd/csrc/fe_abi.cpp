@@ -1562,20 +1562,43 @@ extern "C" fe_status fe_batch_round_end(fe_batch* b, int32_t* running) {
   b->open = false;
   HIP_TRY(hipEventSynchronize(b->ev));
   fe_status first_err = FE_OK;
-  int n = 0;
-  for (int s = 0; s < b->nslots; ++s) {
-    fe_problem* h = b->slot[s];
-    if (!h || h->sc.stage == ST_DONE) continue;
-    if (b->replayed && in_cg_stage(h)) *h->h_st = b->h_states[s];
+  auto take = [&](fe_problem* h) {
     const fe_status st = advance(h);
     if (st != FE_OK) {
       h->sc.stage = ST_DONE;
       h->sc.result = st;
       if (first_err == FE_OK) first_err = st;
-      continue;
     }
-    if (h->sc.stage != ST_DONE) ++n;
+  };
+  // a stage that only waits for a short computation whose result the host
+  // needs (the float64 residual of a refinement step, the final residual and
+  // compliance)
+  auto waits_short = [](const fe_problem* h) {
+    return h && (h->sc.stage == ST_IR_RESID || h->sc.stage == ST_FINISH);
+  };
+  bool again = false;
+  for (int s = 0; s < b->nslots; ++s) {
+    fe_problem* h = b->slot[s];
+    if (!h || h->sc.stage == ST_DONE) continue;
+    if (b->replayed && in_cg_stage(h)) *h->h_st = b->h_states[s];
+    take(h);
+    again = again || waits_short(h);
   }
+  // such stages are taken now, after one wait for the stream, so the slot
+  // rejoins the next replay (or is free) instead of sitting a round out
+  for (int pass = 0; again && pass < 3; ++pass) {
+    HIP_TRY(hipStreamSynchronize(b->stream));
+    again = false;
+    for (int s = 0; s < b->nslots; ++s) {
+      fe_problem* h = b->slot[s];
+      if (!waits_short(h)) continue;
+      take(h);
+      again = again || waits_short(h);
+    }
+  }
+  int n = 0;
+  for (int s = 0; s < b->nslots; ++s)
+    if (b->slot[s] && b->slot[s]->sc.stage != ST_DONE) ++n;
   if (running) *running = n;
   return first_err;
 }
