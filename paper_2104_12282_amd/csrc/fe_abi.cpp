@@ -458,6 +458,33 @@ fe_status harvest_graph_events(fe_problem* p) {
   return FE_OK;
 }
 
+// The first V-cycle of a folded multigrid CG (its start, or the restart of a
+// refinement step): z = M r, leaving the r^T z partials that the chunk's
+// first direction kernel sums.  r and z follow the solve's form: a float64
+// solve runs it on the float32 copy of r (all levels float32) or on r
+// itself, a refinement's float32 CG on its scaled residual.  guard: the
+// state whose stop flag the launches honour.
+hipError_t launch_start_vcycle(fe_problem* p, CgState* guard) {
+  if (p->cfg.precision == FE_PREC_FP64) {
+    if (p->f32_from == 0)
+      return launch_vcycle<float>(p, 0, static_cast<float*>(p->L[0].mg_r), static_cast<float*>(p->L[0].mg_w),
+                                  guard, RZ_PARTIALS, 0);
+    return launch_vcycle<double>(p, 0, p->r64, static_cast<double*>(p->L[0].mg_z), guard, RZ_PARTIALS, 0);
+  }
+  return launch_vcycle<float>(p, 0, p->r32, static_cast<float*>(p->L[0].mg_z), guard, RZ_PARTIALS, 0);
+}
+
+// The first V-cycle now; for a batch slot, armed instead (its second state
+// is the guard, cleared) for the V-cycle that the batch runs for all its
+// starting slots at once before the next replay.
+hipError_t start_vcycle(fe_problem* p) {
+  if (p->in_batch) {
+    p->start_pending = true;
+    return launch_cg_guard(p, p->st + 1, 0);
+  }
+  return launch_start_vcycle(p, p->st);
+}
+
 // r = b - Kx (Kx null: x = 0) and the first preconditioned direction.
 template <typename T>
 hipError_t enqueue_start(fe_problem* p, const T* b, const T* Kx, T* r, T* pv) {
@@ -469,10 +496,11 @@ hipError_t enqueue_start(fe_problem* p, const T* b, const T* Kx, T* r, T* pv) {
   if (folded_mg(p) && std::is_same<T, double>::value && p->f32_from == 0) {
     float* r32 = static_cast<float*>(p->L[0].mg_r);
     float* z32 = static_cast<float*>(p->L[0].mg_w);
+    (void)z32;
     if ((e = launch_narrow(p, reinterpret_cast<const double*>(r), r32)) != hipSuccess) return e;
-    return launch_vcycle<float>(p, 0, r32, z32, p->st, RZ_PARTIALS, 0);
+    return start_vcycle(p);  // on r32, into z32
   }
-  if (folded_mg(p)) return launch_vcycle<T>(p, 0, r, z, p->st, RZ_PARTIALS, 0);
+  if (folded_mg(p)) return start_vcycle(p);  // on r, into z
   if ((e = launch_fill<T>(p, pv, p->L[0].g.ndof, T(0))) != hipSuccess) return e;
   if ((e = launch_vcycle<T>(p, 0, r, z, p->st, RZ_FINISH)) != hipSuccess) return e;
   return launch_cg_direction<T>(p, r, z, pv, p->st);
@@ -573,7 +601,7 @@ fe_status advance(fe_problem* p) {
           HIP_TRY(hipMemcpyAsync(p->p32, p->p32b, p->L[0].g.ndof * sizeof(float), hipMemcpyDeviceToDevice,
                                  p->stream));
         HIP_TRY(launch_cg_state_resume(p, p->st, tol * tol, hs.iter + (sc.max_iters - sc.total)));
-        HIP_TRY(launch_vcycle<float>(p, 0, p->r32, static_cast<float*>(p->L[0].mg_z), p->st, RZ_PARTIALS, 0));
+        HIP_TRY(start_vcycle(p));
         sc.inner_base = sc.total - hs.iter;
         sc.chunk_iter0 = hs.iter;
         sc.mark_rr = scaled * scaled;  // the replaced residual, in the inner system's units
@@ -1359,13 +1387,14 @@ size_t batch_zero_bytes(const fe_config* cfg) {
   return align_up((size_t)3 * (cfg->nx + 1) * (cfg->ny + 1) * (cfg->nz + 1) * sizeof(double));
 }
 
-// Stops the CG state at slot s (its workgroups exit at once in a replay).
+// Stops the CG state at slot s (its workgroups exit at once in a replay),
+// and its guard of the shared first V-cycle (the second state).
 fe_status batch_stop_slot(fe_batch* b, int s) {
-  CgState cs;
-  std::memset(&cs, 0, sizeof(cs));
-  cs.done = 1;
-  cs.status = FE_OK;
-  HIP_TRY(hipMemcpyAsync(b->ws + (size_t)s * b->stride + b->st_off, &cs, sizeof(cs), hipMemcpyHostToDevice,
+  CgState cs[2];
+  std::memset(cs, 0, sizeof(cs));
+  cs[0].done = cs[1].done = 1;
+  cs[0].status = cs[1].status = FE_OK;
+  HIP_TRY(hipMemcpyAsync(b->ws + (size_t)s * b->stride + b->st_off, cs, sizeof(cs), hipMemcpyHostToDevice,
                          b->stream));
   HIP_TRY(hipStreamSynchronize(b->stream));  // the source is on this stack
   return FE_OK;
@@ -1413,6 +1442,34 @@ fe_status batch_capture(fe_batch* b) {
 }
 
 bool in_cg_stage(const fe_problem* h) { return h && (h->sc.stage == ST_CG64 || h->sc.stage == ST_IR_CG); }
+
+// The slots that (re)started their CG since the last replay share one first
+// V-cycle before the next: every slot's launches run, those whose guard is
+// set leave at once; then every guard is set again.
+fe_status batch_start_vcycles(fe_batch* b) {
+  bool starting = false;
+  for (int s = 0; s < b->nslots; ++s)
+    if (b->slot[s] && b->slot[s]->start_pending) {
+      starting = true;
+      b->slot[s]->start_pending = false;
+    }
+  if (!starting) return FE_OK;
+  fe_problem* t = b->slot[0];
+  const bool prof = t->kst.on;
+  t->kst.on = false;
+  t->bcount = b->nslots;
+  t->bstride = (int64_t)b->stride;
+  hipError_t e = launch_start_vcycle(t, t->st + 1);
+  if (e == hipSuccess) e = launch_cg_guard(t, t->st + 1, 1);
+  t->bcount = 1;
+  t->bstride = 0;
+  t->kst.on = prof;
+  if (e != hipSuccess) {
+    fe_set_error(std::string("batched first V-cycle: ") + hipGetErrorString(e));
+    return FE_EDEVICE;
+  }
+  return FE_OK;
+}
 
 }  // namespace
 
@@ -1543,6 +1600,8 @@ extern "C" fe_status fe_batch_round_begin(fe_batch* b) {
       const fe_status st = b->cfg.precision == FE_PREC_FP64 ? batch_capture<double>(b) : batch_capture<float>(b);
       if (st != FE_OK) return st;
     }
+    const fe_status sv = batch_start_vcycles(b);
+    if (sv != FE_OK) return sv;
     HIP_TRY(hipGraphLaunch(b->chunk, b->stream));
     // every slot's state in one strided copy (the states sit stride bytes apart)
     HIP_TRY(hipMemcpy2DAsync(b->h_states, sizeof(CgState), b->ws + b->st_off, b->stride, sizeof(CgState),

@@ -220,6 +220,7 @@ struct fe_problem {
   GraphChunk* last_replay = nullptr;  // profiled graph replayed since the last harvest
   bool use_graphs = true;
   bool in_batch = false;  // a slot of an fe_batch: its CG chunks run in the batch's replays
+  bool start_pending = false;  // batch slot: its CG (re)start awaits the batch's shared first V-cycle
   int mfma_l0 = 0;  // finest-grid float32 K*u: 0 vector ALUs, 1 bf16, 2 split-bf16 matrix cores
   double* x64 = nullptr;        // float64 iterate of the solve (graphs need fixed pointers)
   double ff = 0.0;              // ||f||^2
@@ -401,6 +402,8 @@ hipError_t launch_cg_state_init(fe_problem* p, CgState* st, double tol_rel, int 
 // stop at ||r||^2 <= tol2 (absolute) or max_iter iterations; the iteration
 // count and the committed r^T z are kept.
 hipError_t launch_cg_state_resume(fe_problem* p, CgState* st, double tol2, int max_iter);
+// Sets g->done (a guard state; batched over p's slots while p->bcount > 1).
+hipError_t launch_cg_guard(fe_problem* p, CgState* g, int done);
 // One-workgroup scalar update after a kernel that left nb partials:
 // op 0 alpha = rz / pq, 1 CG start, 2 CG update and convergence test,
 // 3 rz and beta, 4 out[0] = the sum.

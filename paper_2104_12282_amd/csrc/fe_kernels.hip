@@ -419,6 +419,11 @@ __global__ void cg_state_resume_kernel(CgState* st, double tol2, int max_iter) {
   }
 }
 
+__global__ void cg_guard_kernel(CgState* g, int done, int64_t wsh) {
+  if (wsh) g = wshift(g, batch_offset(wsh));
+  if (threadIdx.x == 0) g->done = done;
+}
+
 __global__ void cg_state_init_kernel(CgState* st, double tol_rel, int max_iter) {
   if (threadIdx.x == 0 && blockIdx.x == 0) {
     st->rz = st->alpha = st->beta = st->rr = st->bb = st->pq = 0.0;
@@ -1117,6 +1122,12 @@ template hipError_t launch_cg_direction<float>(fe_problem*, const float*, const 
 
 hipError_t launch_cg_state_resume(fe_problem* p, CgState* st, double tol2, int max_iter) {
   hipLaunchKernelGGL(cg_state_resume_kernel, dim3(1), dim3(64), 0, p->stream, st, tol2, max_iter);
+  return hipGetLastError();
+}
+
+hipError_t launch_cg_guard(fe_problem* p, CgState* g, int done) {
+  hipLaunchKernelGGL(cg_guard_kernel, dim3(1, p->bcount), dim3(64), 0, p->stream, g, done,
+                     p->bcount > 1 ? p->bstride : (int64_t)0);
   return hipGetLastError();
 }
 
