@@ -495,10 +495,8 @@ hipError_t enqueue_start(fe_problem* p, const T* b, const T* Kx, T* r, T* pv) {
   // folded: the first direction kernel forms p = z from the r^T z partials
   if (folded_mg(p) && std::is_same<T, double>::value && p->f32_from == 0) {
     float* r32 = static_cast<float*>(p->L[0].mg_r);
-    float* z32 = static_cast<float*>(p->L[0].mg_w);
-    (void)z32;
     if ((e = launch_narrow(p, reinterpret_cast<const double*>(r), r32)) != hipSuccess) return e;
-    return start_vcycle(p);  // on r32, into z32
+    return start_vcycle(p);  // on r32, into the float32 z (mg_w)
   }
   if (folded_mg(p)) return start_vcycle(p);  // on r, into z
   if ((e = launch_fill<T>(p, pv, p->L[0].g.ndof, T(0))) != hipSuccess) return e;
