@@ -58,6 +58,9 @@ def parse():
                     help="coarsest-level Chebyshev launch form (0: the library's automatic choice; 3: pairs of "
                          "steps on 3D tiles, 2: pairs on z-marching tiles, 1: one step per launch)")
     ap.add_argument("--rtol", type=float, default=1e-6)
+    ap.add_argument("--extrapolate", type=float, default=1.0,
+                    help="initial guess of each loop solve: u + theta (u - u_prev) from the third "
+                         "iteration on (fe_extrapolate; 0: the last solution alone)")
     ap.add_argument("--volfrac", type=float, default=0.12)
     ap.add_argument("--move", type=float, default=0.2)
     ap.add_argument("--no-cpu-baseline", action="store_true")
@@ -134,6 +137,14 @@ def profile_record(grid: str):
         return rec if rec.get("source_digest") == source_digest() else None
     except Exception:
         return None
+
+
+def initial_guess_text(args):
+    """How each solve of an optimisation loop starts."""
+    if args.extrapolate:
+        return (f"u + {args.extrapolate:g} (u - u_prev) from the last two solutions, from the third solve on "
+                "(fe_extrapolate); the last solution before")
+    return "the last solution"
 
 
 def apply_mg(prob, args):
@@ -597,7 +608,7 @@ def paper_mesh_study(fe, synth, torch, args, iters):
     dev = "cuda:0"
     T = lambda a: torch.as_tensor(a, dtype=torch.float64, device=dev)
     out = {"domain": [2.0, 1.0, 1.0], "filter_R": 0.08, "volfrac": 0.12, "move": args.move,
-           "rtol": args.rtol, "iterations": iters, "meshes": {}}
+           "rtol": args.rtol, "initial_guess": initial_guess_text(args), "iterations": iters, "meshes": {}}
     for nx in (70, 100, 180):
         ny = nz = nx // 2
         h = 2.0 / nx
@@ -612,6 +623,7 @@ def paper_mesh_study(fe, synth, torch, args, iters):
         ne = nx * ny * nz
         x = torch.full((ne,), 0.12, dtype=torch.float64, device=dev)
         u = torch.zeros(prob.ndof, dtype=torch.float64, device=dev)
+        u_hist = torch.zeros_like(u)
         rho, dc, dcx = (torch.empty_like(x) for _ in range(3))
         dv = prob.filter(torch.ones_like(x), transpose=True)
         comp = torch.zeros(1, dtype=torch.float64, device=dev)
@@ -621,6 +633,7 @@ def paper_mesh_study(fe, synth, torch, args, iters):
         t0 = time.perf_counter()
         for it in range(iters):
             prob.filter(x, out=rho)
+            prob.extrapolate(u, u_hist, args.extrapolate if it >= 2 else 0.0)
             _, info = prob.solve(rho, u=u, rtol=args.rtol)
             prob.sensitivity(rho, u, out=dc, compliance_out=comp)
             prob.filter(dc, transpose=True, out=dcx)
@@ -834,6 +847,7 @@ def run_loop(fe, synth, torch, nx, ny, nz, precision, args, steps, warmup, profi
         rec_mg = None
     x = torch.empty(ne, dtype=torch.float64, device=dev)
     u = torch.empty(prob.ndof, dtype=torch.float64, device=dev)
+    u_hist = torch.empty_like(u)  # the solution before the last (initial-guess extrapolation)
     rho = torch.empty_like(x)
     dc = torch.empty_like(x)
     dcx = torch.empty_like(x)
@@ -845,9 +859,13 @@ def run_loop(fe, synth, torch, nx, ny, nz, precision, args, steps, warmup, profi
     def reset():
         x.fill_(args.volfrac)
         u.zero_()
+        rec["n"] = 0
 
     def step():
         prob.filter(x, out=rho)
+        # from the third solve on the guess extrapolates the last two solutions
+        prob.extrapolate(u, u_hist, args.extrapolate if rec["n"] >= 2 else 0.0)
+        rec["n"] += 1
         _, info = prob.solve(rho, u=u, rtol=args.rtol)
         prob.sensitivity(rho, u, out=dc, compliance_out=comp)
         prob.filter(dc, transpose=True, out=dcx)
@@ -1021,6 +1039,7 @@ def main():
                    "preconditioner_float32_from_level": ((args.f32_from if args.f32_from >= 0 else 0)
                                                          if args.precision == "fp64" else 0) if rec["mg"] else None,
                    "rtol": args.rtol, "volfrac": args.volfrac, "filter_r": 1.5, "move": args.move,
+                   "initial_guess": initial_guess_text(args),
                    "cg_iters_per_solve": float(np.mean(rec["iters"])),
                    "cg_iters_max": int(np.max(rec["iters"])),
                    "refinement_steps_per_solve": float(np.mean(rec["outer"])),

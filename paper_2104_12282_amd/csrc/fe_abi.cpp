@@ -1172,6 +1172,20 @@ extern "C" fe_status fe_block_mean(fe_problem* p, const double* z, int32_t nb, d
   return FE_OK;
 }
 
+extern "C" fe_status fe_extrapolate(fe_problem* p, double* u, double* u_hist, double theta) {
+  CHECK_HANDLE(p);
+  if (!u || !u_hist || u == u_hist) {
+    fe_set_error("u and u_hist must be distinct non-NULL arrays");
+    return FE_EINVAL;
+  }
+  if (!(theta >= 0.0 && theta <= 4.0)) {
+    fe_set_error("theta must be in [0, 4]");
+    return FE_EINVAL;
+  }
+  HIP_TRY(launch_extrapolate(p, u, u_hist, theta));
+  return FE_OK;
+}
+
 extern "C" fe_status fe_set_mg_params(fe_problem* p, int32_t nu, int32_t coarse_sweeps, double omega,
                                       double coarse_ratio) {
   CHECK_HANDLE(p);

@@ -424,6 +424,8 @@ hipError_t launch_filter_rowsums(fe_problem* p);
 hipError_t launch_adjoint_sensitivity(fe_problem* p, const double* rho, const double* u, const double* lam,
                                       double* out);
 hipError_t launch_block_mean(fe_problem* p, const double* z, int nb, double* zc);
+// u <- u + theta (u - hist), hist <- the old u (finest-grid dofs)
+hipError_t launch_extrapolate(fe_problem* p, double* u, double* hist, double theta);
 hipError_t launch_oc(fe_problem* p, const double* x, const double* dcx, const double* dv,
                      double volfrac, double move, double* x_new, double* change);
 // The same update on `stream` with the library's static per-device scratch

@@ -1224,6 +1224,22 @@ hipError_t launch_filter(fe_problem* p, const double* in, double* out, int trans
   return transpose ? launch_filter_tile<1>(p, in, out) : launch_filter_tile<0>(p, in, out);
 }
 
+// u <- u + theta (u - hist) and hist <- the old u, per dof
+__global__ void __launch_bounds__(FE_BLOCK) extrapolate_kernel(int64_t n, double* __restrict__ u,
+                                                               double* __restrict__ hist, double theta) {
+  for (int64_t d = blockIdx.x * (int64_t)FE_BLOCK + threadIdx.x; d < n; d += (int64_t)gridDim.x * FE_BLOCK) {
+    const double v = u[d];
+    u[d] = v + theta * (v - hist[d]);
+    hist[d] = v;
+  }
+}
+
+hipError_t launch_extrapolate(fe_problem* p, double* u, double* hist, double theta) {
+  const int64_t n = G(p, 0).ndof;
+  hipLaunchKernelGGL(extrapolate_kernel, dim3(red_grid(n) * 2), dim3(FE_BLOCK), 0, p->stream, n, u, hist, theta);
+  return hipGetLastError();
+}
+
 hipError_t launch_block_mean(fe_problem* p, const double* z, int nb, double* zc) {
   const Grid g = G(p, 0);
   const int cx = g.nx / nb, cy = g.ny / nb;

@@ -26,7 +26,7 @@ STATUS_NAME = {0: "FE_OK", -1: "FE_EINVAL", -2: "FE_ENOMEM", -3: "FE_EDEVICE",
 # Every entry point declared in include/fe_abi.h.
 ABI_SYMBOLS = ("fe_workspace_size", "fe_setup", "fe_apply_K", "fe_solve", "fe_solve_begin",
                "fe_solve_step", "fe_solve_end", "fe_sensitivity", "fe_sensitivity_adjoint", "fe_set_load",
-               "fe_filter", "oc_update", "oc_update_noalloc", "fe_block_mean", "fe_set_mg_params", "fe_get_mg_params", "fe_set_mg_smoother", "fe_get_mg_smoother", "fe_set_float32_levels", "fe_set_coarse_fusion", "fe_set_profiling", "fe_set_cache_flush",
+               "fe_filter", "oc_update", "oc_update_noalloc", "fe_block_mean", "fe_extrapolate", "fe_set_mg_params", "fe_get_mg_params", "fe_set_mg_smoother", "fe_get_mg_smoother", "fe_set_float32_levels", "fe_set_coarse_fusion", "fe_set_profiling", "fe_set_cache_flush",
                "fe_kernel_stats", "fe_destroy", "fe_batch_workspace_size", "fe_batch_create", "fe_batch_setup_slot",
                "fe_batch_round_begin", "fe_batch_round_end", "fe_batch_round_ready", "fe_batch_destroy", "fe_onsg_num_params",
                "fe_onsg_workspace_size", "fe_onsg_create", "fe_onsg_add_samples", "fe_onsg_num_samples",
@@ -80,6 +80,7 @@ def load_library() -> C.CDLL:
     lib.oc_update.argtypes = [P, P, P, P, D, D, P, P]
     lib.oc_update_noalloc.argtypes = [I64, P, P, P, D, D, P, P, P]
     lib.fe_block_mean.argtypes = [P, P, I32, P]
+    lib.fe_extrapolate.argtypes = [P, P, P, D]
     lib.fe_set_mg_params.argtypes = [P, I32, I32, D, D]
     lib.fe_set_float32_levels.argtypes = [P, I32]
     lib.fe_set_mg_smoother.argtypes = [P, I32, I32, D]
@@ -304,6 +305,12 @@ class Problem:
         _check(load_library().oc_update(self._h, _ptr(x), _ptr(dcx), _ptr(dv), volfrac, move,
                                         _ptr(xn), _ptr(ch)))
         return xn, ch
+
+    def extrapolate(self, u, u_hist, theta=1.0):
+        """Initial guess of the next solve from the last two solutions:
+        u <- u + theta (u - u_hist), u_hist <- the old u (include/fe_abi.h,
+        fe_extrapolate)."""
+        _check(load_library().fe_extrapolate(self._h, _ptr(u), _ptr(u_hist), float(theta)))
 
     def block_mean(self, z, nb, out=None):
         """Coarse-grained design variables of the two-scale scheme: the mean

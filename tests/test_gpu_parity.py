@@ -679,3 +679,25 @@ def test_coarse_3d_tiles(grid, levels, deg, precision, form):
     assert abs(i1["iters"] - i3["iters"]) <= slack, (i1["iters"], i3["iters"])
     assert np.abs(u3 - u1).max() <= 1e-6 * np.abs(u1).max()
     assert np.array_equal(u3, u3b) and i3["iters"] == i3b["iters"]
+
+
+def test_extrapolate():
+    """fe_extrapolate: u <- u + theta (u - u_hist), u_hist <- the old u,
+    exactly (one multiply-add per dof in float64); validation."""
+    nx, ny, nz = 9, 5, 4
+    prob = _problem(nx, ny, nz)
+    rng = np.random.default_rng(4)
+    u0 = rng.standard_normal(prob.ndof)
+    h0 = rng.standard_normal(prob.ndof)
+    for theta in (0.0, 1.0, 0.5):
+        u, h = T(u0), T(h0)
+        prob.extrapolate(u, h, theta)
+        want = u0 + theta * (u0 - h0)
+        assert np.array_equal(N(h), u0)
+        assert np.abs(N(u) - want).max() <= 1e-15 * np.abs(want).max()
+    u = T(u0)
+    for bad in (-0.1, 5.0, float("nan")):
+        with pytest.raises(fe.FEError):
+            prob.extrapolate(u, T(h0), bad)
+    with pytest.raises(fe.FEError):
+        prob.extrapolate(u, u, 1.0)
