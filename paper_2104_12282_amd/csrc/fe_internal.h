@@ -37,7 +37,7 @@
 #define FE_CS_RATIO 100.0  // default Chebyshev smoothing interval ratio
 #endif
 #ifndef FE_IR_PHASE
-#define FE_IR_PHASE 3e-2  // refinement with residual replacement: reduction of the residual per phase
+#define FE_IR_PHASE 5e-3  // refinement with residual replacement: reduction of the residual per phase
 #endif
 #ifndef FE_IR_RESUME
 #define FE_IR_RESUME 1  // refinement: continue the float32 CG with the float64 residual (no restart)
