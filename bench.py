@@ -38,6 +38,7 @@ def parse():
     ap.add_argument("--precond", default="gmg", choices=["jacobi", "gmg"])
     ap.add_argument("--mg-levels", type=int, default=4)
     ap.add_argument("--mg-nu", type=int, default=1)
+    ap.add_argument("--mg-omega", type=float, default=0.0, help="damped Jacobi weight (0: the library's default)")
     ap.add_argument("--mg-coarse", type=int, default=0,
                     help="coarsest-level Chebyshev degree (0: the library's default for the coarsest grid)")
     ap.add_argument("--f32-from", type=int, default=-1,
@@ -157,7 +158,8 @@ def apply_mg(prob, args):
     if args.coarse_form:
         prob.set_coarse_fusion(args.coarse_form)
     cur = prob.mg_params()
-    prob.set_mg_params(nu=args.mg_nu, coarse_sweeps=args.mg_coarse or cur["coarse_sweeps"], omega=cur["omega"],
+    prob.set_mg_params(nu=args.mg_nu, coarse_sweeps=args.mg_coarse or cur["coarse_sweeps"],
+                       omega=args.mg_omega or cur["omega"],
                        coarse_ratio=args.mg_coarse_ratio or cur["coarse_ratio"])
     if args.mg_cheb_from == 0 or 1 <= args.mg_cheb_from <= prob.cfg.mg_levels - 2:
         prob.set_mg_smoother(args.mg_cheb_from, args.mg_cheb_deg, args.mg_cheb_ratio)
