@@ -2,13 +2,15 @@
 
 A step is one iteration of the density-based optimisation loop on the
 paper-scale cantilever (224 x 112 x 56 bricks, 1,404,928 design variables):
-  rho = P x;  u = K(rho)^-1 f (CG with a 3-level geometric multigrid
-  preconditioner, warm-started, to 1e-6);  dc = dc/drho;  dcx = P^T dc;
+  rho = P x;  u = K(rho)^-1 f (CG with a 4-level geometric multigrid
+  preconditioner to 1e-6, each solve started from the extrapolation of the
+  last two solutions);  dc = dc/drho;  dcx = P^T dc;
   x = OC(x, dcx, dv)   (volume fraction 0.12, move limit 0.2).
 Warm-up steps run first; the design is then reset to the uniform start and
 the timed steps are the first `--steps` iterations of the loop (50 by
-default: the whole loop).  The same loop is then run untimed-for-roofline in
-the alternative precision and reported under "alt".  Prints one JSON line.
+default: the whole loop).  The same loop is then timed in the alternative
+precision (float32 CG inside float64 refinement) and reported under "alt",
+and profiled passes give the roofline records.  Prints one JSON line.
 """
 from __future__ import annotations
 
