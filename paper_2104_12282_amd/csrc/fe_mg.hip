@@ -20,6 +20,47 @@ inline int nblocks(int64_t n) {
   return (int)(g < 1 ? 1 : g);
 }
 
+// Division of a node index by a fixed divisor as a multiply and a shift
+// (Granlund and Montgomery, "Division by invariant integers using
+// multiplication", 1994, Thm. 4.2 with 31-bit numerators): with 2^l >= d and
+// m = floor(2^(31+l) / d) + 1 < 2^32, floor(n m / 2^(31+l)) = floor(n / d)
+// for every 0 <= n < 2^31.  Node indices qualify: the set-up rejects grids of
+// 2^31 / 3 nodes or more.  It replaces the 64-bit divisions (a long chain of
+// vector instructions in front of every load) of the node-indexed transfers.
+struct FastDiv {
+  uint32_t d, m, s;
+};
+struct NodeDiv {
+  FastDiv x, xy;  // by nx + 1 and (nx + 1) (ny + 1)
+};
+
+inline FastDiv make_fastdiv(uint32_t d) {
+  uint32_t l = 0;
+  while (((uint64_t)1 << l) < d) ++l;
+  FastDiv f;
+  f.d = d;
+  f.s = 31 + l;
+  f.m = (uint32_t)((((uint64_t)1 << (31 + l)) / d) + 1);
+  return f;
+}
+
+inline NodeDiv node_div(const Grid& g) {
+  NodeDiv nd;
+  nd.x = make_fastdiv((uint32_t)(g.nx + 1));
+  nd.xy = make_fastdiv((uint32_t)((g.nx + 1) * (g.ny + 1)));
+  return nd;
+}
+
+__device__ inline uint32_t fdiv(uint32_t n, const FastDiv& f) { return (uint32_t)(((uint64_t)n * f.m) >> f.s); }
+
+// (i, j, k) of node n < 2^31
+__device__ inline void node_ijk(uint32_t n, const NodeDiv& nd, int& i, int& j, int& k) {
+  const uint32_t kk = fdiv(n, nd.xy), rem = n - kk * nd.xy.d, jj = fdiv(rem, nd.x);
+  i = (int)(rem - jj * nd.x.d);
+  j = (int)jj;
+  k = (int)kk;
+}
+
 // z = omega D^-1 r (the first sweep from z = 0; fixed dofs have r = 0).
 // A non-null st guards every kernel of the cycle: nothing is stored once CG
 // stopped.
@@ -46,7 +87,8 @@ __global__ void __launch_bounds__(FE_BLOCK) jacobi0_kernel(int64_t ndof, const T
 // The coarse level may hold a narrower type (TC) than the fine one (T): the
 // sum is formed in T and rounded once.
 template <typename T, typename TC = T>
-__global__ void __launch_bounds__(FE_BLOCK) restrict_kernel(Grid fg, Grid cg, const T* __restrict__ tf,
+__global__ void __launch_bounds__(FE_BLOCK) restrict_kernel(Grid fg, Grid cg, NodeDiv cd,
+                                                            const T* __restrict__ tf,
                                                             const uint8_t* __restrict__ cmask,
                                                             TC* __restrict__ rc, const CgState* st, int64_t wsh,
                                                             const TC* __restrict__ invd_c, TC omega,
@@ -60,11 +102,14 @@ __global__ void __launch_bounds__(FE_BLOCK) restrict_kernel(Grid fg, Grid cg, co
     invd_c = wshift(invd_c, o);
     d0 = wshift(d0, o);
   }
-  const int64_t n = blockIdx.x * (int64_t)FE_BLOCK + threadIdx.x;
-  if (n >= cg.nnode) return;
-  const int I = (int)(n % (cg.nx + 1)), J = (int)((n / (cg.nx + 1)) % (cg.ny + 1)),
-            K = (int)(n / ((int64_t)(cg.nx + 1) * (cg.ny + 1)));
-  const int64_t fsx = fg.nx + 1, fsxy = (int64_t)(fg.nx + 1) * (fg.ny + 1);
+  const int64_t n64 = blockIdx.x * (int64_t)FE_BLOCK + threadIdx.x;
+  if (n64 >= cg.nnode) return;
+  // node and dof indices fit 31 bits; signed, so that the three components'
+  // loads of a node merge into one (no wrap-around between them)
+  const int n = (int)n64;
+  int I, J, K;
+  node_ijk((uint32_t)n, cd, I, J, K);
+  const int fsx = fg.nx + 1, fsxy = (fg.nx + 1) * (fg.ny + 1);
   // All 27 fine neighbours are loaded unconditionally (one off the mesh
   // reads a clamped node and gets weight 0), so the loads issue back to back
   // instead of one branch and one round trip each; a zero term leaves the
@@ -86,11 +131,11 @@ __global__ void __launch_bounds__(FE_BLOCK) restrict_kernel(Grid fg, Grid cg, co
         const bool in = kin && jin && i >= 0 && i <= fg.nx;
         const int ic = min(max(i, 0), fg.nx);
         const int q = 9 * (c + 1) + 3 * (b + 1) + (a + 1);
-        const int64_t f = ic + fsx * jc + fsxy * kc;
+        const int f = 3 * (ic + fsx * jc + fsxy * kc);
         w[q] = in ? (c ? T(0.5) : T(1)) * (b ? T(0.5) : T(1)) * (a ? T(0.5) : T(1)) : T(0);
-        v[q][0] = tf[3 * f];
-        v[q][1] = tf[3 * f + 1];
-        v[q][2] = tf[3 * f + 2];
+        v[q][0] = tf[f];
+        v[q][1] = tf[f + 1];
+        v[q][2] = tf[f + 2];
       }
     }
   }
@@ -119,7 +164,7 @@ __global__ void __launch_bounds__(FE_BLOCK) restrict_kernel(Grid fg, Grid cg, co
 // (omega D^-1) r_f exactly as the launch that used it formed it, instead of
 // being stored there and read back.
 template <typename T, typename TC = T>
-__global__ void __launch_bounds__(FE_BLOCK) prolong_add_kernel(Grid fg, Grid cg, const T* zf,
+__global__ void __launch_bounds__(FE_BLOCK) prolong_add_kernel(Grid fg, Grid cg, NodeDiv fd, const T* zf,
                                                                const TC* __restrict__ zc,
                                                                const uint8_t* __restrict__ fmask, T* out,
                                                                const T* __restrict__ rf, const T* __restrict__ invd,
@@ -134,14 +179,15 @@ __global__ void __launch_bounds__(FE_BLOCK) prolong_add_kernel(Grid fg, Grid cg,
     invd = wshift(invd, o);
     st = wshift(st, o);
   }
-  const int64_t n = blockIdx.x * (int64_t)FE_BLOCK + threadIdx.x;
-  if (n >= fg.nnode) return;
-  const int i = (int)(n % (fg.nx + 1)), j = (int)((n / (fg.nx + 1)) % (fg.ny + 1)),
-            k = (int)(n / ((int64_t)(fg.nx + 1) * (fg.ny + 1)));
+  const int64_t n64 = blockIdx.x * (int64_t)FE_BLOCK + threadIdx.x;
+  if (n64 >= fg.nnode) return;
+  const int n = (int)n64;  // node and dof indices fit 31 bits (signed: merged loads)
+  int i, j, k;
+  node_ijk((uint32_t)n, fd, i, j, k);
   // coarse neighbours along each axis: one (even index) or two (odd index)
   const int i0 = i >> 1, i1 = (i + 1) >> 1, j0 = j >> 1, j1 = (j + 1) >> 1, k0 = k >> 1, k1 = (k + 1) >> 1;
   const T wi = (i & 1) ? T(0.5) : T(1), wj = (j & 1) ? T(0.5) : T(1), wk = (k & 1) ? T(0.5) : T(1);
-  const int64_t csx = cg.nx + 1, csxy = (int64_t)(cg.nx + 1) * (cg.ny + 1);
+  const int csx = cg.nx + 1, csxy = (cg.nx + 1) * (cg.ny + 1);
   // the 8 corner loads are issued unconditionally: along an even axis the
   // second neighbour is the first one again, with weight 0
   const int ii[2] = {i0, i1}, jj[2] = {j0, j1}, kk[2] = {k0, k1};
@@ -155,11 +201,11 @@ __global__ void __launch_bounds__(FE_BLOCK) prolong_add_kernel(Grid fg, Grid cg,
       for (int a = 0; a < 2; ++a) {
         const int q = 4 * c + 2 * b + a;
         const bool used = (c == 0 || (k & 1)) && (b == 0 || (j & 1)) && (a == 0 || (i & 1));
-        const int64_t cq = ii[a] + csx * jj[b] + csxy * kk[c];
+        const int cq = 3 * (ii[a] + csx * jj[b] + csxy * kk[c]);
         wq[q] = used ? w : T(0);
-        v[q][0] = (T)zc[3 * cq];
-        v[q][1] = (T)zc[3 * cq + 1];
-        v[q][2] = (T)zc[3 * cq + 2];
+        v[q][0] = (T)zc[cq];
+        v[q][1] = (T)zc[cq + 1];
+        v[q][2] = (T)zc[cq + 2];
       }
   T acc[3] = {T(0), T(0), T(0)};
 #pragma unroll
@@ -382,22 +428,22 @@ hipError_t cheb_smoothed_cycle(fe_problem* p, int l, const T* r, T* z, CgState* 
     TC* rc = static_cast<TC*>(C.mg_r);
     TC* zc = static_cast<TC*>(C.mg_z);
     hipLaunchKernelGGL((restrict_kernel<T, TC>), dim3(nblocks(C.g.nnode), p->bcount), dim3(FE_BLOCK), 0,
-                       p->stream, L.g, C.g, res, C.nmask, rc, st, wsh_of(p), last ? C.invd32 : nullptr,
+                       p->stream, L.g, C.g, node_div(C.g), res, C.nmask, rc, st, wsh_of(p), last ? C.invd32 : nullptr,
                        (TC)(1.0 / cheb_theta(p)), last ? static_cast<TC*>(C.mg_t) : nullptr);
     if ((e = hipGetLastError()) != hipSuccess) return e;
     if ((e = launch_vcycle<TC>(p, l + 1, rc, zc, st, RZ_NONE, 0)) != hipSuccess) return e;
     hipLaunchKernelGGL((prolong_add_kernel<T, TC>), dim3(nblocks(L.g.nnode), p->bcount), dim3(FE_BLOCK), 0,
-                       p->stream, L.g, C.g, z, zc, L.nmask, z, nullptr, nullptr, (T)0, st, wsh_of(p));
+                       p->stream, L.g, C.g, node_div(L.g), z, zc, L.nmask, z, nullptr, nullptr, (T)0, st, wsh_of(p));
   } else {
     T* rc = static_cast<T*>(C.mg_r);
     T* zc = static_cast<T*>(C.mg_z);
     hipLaunchKernelGGL(restrict_kernel<T>, dim3(nblocks(C.g.nnode), p->bcount), dim3(FE_BLOCK), 0, p->stream,
-                       L.g, C.g, res, C.nmask, rc, st, wsh_of(p), last ? lev_invd<T>(C) : nullptr,
+                       L.g, C.g, node_div(C.g), res, C.nmask, rc, st, wsh_of(p), last ? lev_invd<T>(C) : nullptr,
                        (T)(1.0 / cheb_theta(p)), last ? static_cast<T*>(C.mg_t) : nullptr);
     if ((e = hipGetLastError()) != hipSuccess) return e;
     if ((e = launch_vcycle<T>(p, l + 1, rc, zc, st, RZ_NONE, 0)) != hipSuccess) return e;
     hipLaunchKernelGGL(prolong_add_kernel<T>, dim3(nblocks(L.g.nnode), p->bcount), dim3(FE_BLOCK), 0, p->stream,
-                       L.g, C.g, z, zc, L.nmask, z, nullptr, nullptr, (T)0, st, wsh_of(p));
+                       L.g, C.g, node_div(L.g), z, zc, L.nmask, z, nullptr, nullptr, (T)0, st, wsh_of(p));
   }
   if ((e = hipGetLastError()) != hipSuccess) return e;
   if ((e = launch_kxu_tile<T>(p, l, z, lev_E<T>(L), q, st, 4, nullptr, nullptr, r, nullptr, 0.0)) != hipSuccess)
@@ -436,24 +482,24 @@ hipError_t launch_vcycle(fe_problem* p, int l, const T* r, T* z, CgState* st, in
     float* rcf = static_cast<float*>(C.mg_r);
     float* zcf = static_cast<float*>(C.mg_z);
     hipLaunchKernelGGL((restrict_kernel<T, float>), dim3(nblocks(C.g.nnode), p->bcount), dim3(FE_BLOCK), 0,
-                       p->stream, L.g, C.g, t, C.nmask, rcf, st, wsh_of(p), last ? C.invd32 : nullptr,
+                       p->stream, L.g, C.g, node_div(C.g), t, C.nmask, rcf, st, wsh_of(p), last ? C.invd32 : nullptr,
                        (float)(1.0 / cheb_theta(p)), last ? static_cast<float*>(C.mg_t) : nullptr);
     if ((e = hipGetLastError()) != hipSuccess) return e;
     if ((e = launch_vcycle<float>(p, l + 1, rcf, zcf, st, RZ_NONE, 0)) != hipSuccess) return e;
     hipLaunchKernelGGL((prolong_add_kernel<T, float>), dim3(nblocks(L.g.nnode), p->bcount), dim3(FE_BLOCK), 0,
-                       p->stream, L.g, C.g, z, zcf, L.nmask, a, z_implicit ? r : nullptr,
+                       p->stream, L.g, C.g, node_div(L.g), z, zcf, L.nmask, a, z_implicit ? r : nullptr,
                        z_implicit ? lev_invd<T>(L) : nullptr, (T)p->mg_omega, st, wsh_of(p));
   } else {
     hipLaunchKernelGGL(restrict_kernel<T>, dim3(nblocks(C.g.nnode), p->bcount), dim3(FE_BLOCK), 0, p->stream, L.g,
-                       C.g, t, C.nmask, rc, st, wsh_of(p), last ? lev_invd<T>(C) : nullptr,
+                       C.g, node_div(C.g), t, C.nmask, rc, st, wsh_of(p), last ? lev_invd<T>(C) : nullptr,
                        (T)(1.0 / cheb_theta(p)), last ? static_cast<T*>(C.mg_t) : nullptr);
     if ((e = hipGetLastError()) != hipSuccess) return e;
     if ((e = launch_vcycle<T>(p, l + 1, rc, zc, st, RZ_NONE, 0)) != hipSuccess) return e;
     // post-smoothing, arranged so the last sweep writes z; with one fused
     // pre-smoothing sweep z was not stored and the prolongation forms it
     hipLaunchKernelGGL(prolong_add_kernel<T>, dim3(nblocks(L.g.nnode), p->bcount), dim3(FE_BLOCK), 0, p->stream,
-                       L.g, C.g, z, zc, L.nmask, a, z_implicit ? r : nullptr, z_implicit ? lev_invd<T>(L) : nullptr,
-                       (T)p->mg_omega, st, wsh_of(p));
+                       L.g, C.g, node_div(L.g), z, zc, L.nmask, a, z_implicit ? r : nullptr,
+                       z_implicit ? lev_invd<T>(L) : nullptr, (T)p->mg_omega, st, wsh_of(p));
   }
   if ((e = hipGetLastError()) != hipSuccess) return e;
   T* b = (a == t) ? z : t;
