@@ -64,8 +64,9 @@ extern "C" {
 
 typedef enum {
   FE_OK = 0,
-  FE_EINVAL = -1,      /* bad argument: dims < 1, nu not in (-1, 0.5), Emin not in (0, E0),
-                          penal < 1, filter_r not in (0, 8], NULL required pointer, ... */
+  FE_EINVAL = -1,      /* bad argument: dims < 1, 3 (nx+1)(ny+1)(nz+1) >= 2^31 (dof indices
+                          are 31-bit), nu not in (-1, 0.5), Emin not in (0, E0), penal < 1,
+                          filter_r not in (0, 8], NULL required pointer, ... */
   FE_ENOMEM = -2,      /* workspace smaller than fe_workspace_size(cfg) */
   FE_EDEVICE = -3,     /* a HIP runtime call failed */
   FE_ENOTCONV = -4,    /* iteration limit reached; u holds the last iterate */
